@@ -1,0 +1,274 @@
+/*
+ * FP64 CPU oracle for the tremor-HMM forward log-likelihood.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow, obviously correct
+ * reference that the GPU library is checked against.  Only the test suite, the
+ * smoke check and the benchmark's CPU-baseline leg may load it.  It shares no
+ * code, header, table or helper with the GPU library (nothing here is included
+ * by, or includes anything from, the package sources).
+ *
+ * Model (paper, section "An HMM for classifying nonvolcanic tremors"):
+ *   observations x_0..x_N, each either "no tremor" or a point in R^2;
+ *   K hidden states, state k has a tremor probability p_k and a bivariate
+ *   normal location law N(mu_k, Sigma_k).
+ *   Emission matrix, eq. (1): P(x) = diag(e_1..e_K) with
+ *       e_k = p_k * phi(x | mu_k, Sigma_k)   if x is a tremor location,
+ *       e_k = 1 - p_k                         if x is "no tremor".
+ *   Likelihood, eq. (2): L = delta^T Gamma P(x_0) Gamma P(x_1) ... Gamma P(x_N) 1.
+ *   The forward algorithm (Algorithm 1) evaluates eq. (2) left to right with a
+ *   row vector: v <- delta^T, then for every observation v <- v Gamma, v <- v P(x).
+ *
+ * Readings taken where the paper is silent (all also listed in the design notes):
+ *   - eq. (1) has lost its case labels; the first case is a tremor (flag 1),
+ *     the second is "no tremor" (flag 0); the location is ignored when flag=0.
+ *   - Gamma is applied before the first emission, exactly as eq. (2) and
+ *     Algorithm 1 write it; delta is used as given (not renormalised).
+ *   - phi keeps its full normalising constant (units of the inputs, km here).
+ *   - Sigma_k is a full symmetric 2x2 matrix given as (Sxx, Sxy, Syy).
+ *   - T = N+1 counts observations.  T = 0 gives log(sum_k delta_k) (the empty
+ *     chain of eq. (2) is delta^T 1).
+ *   - L = 0 gives -inf; invalid parameters or data give NaN (see oracle_valid).
+ *   - Underflow is avoided as the paper says (logarithm and scaling, section
+ *     "Step 3"); the scaling constant here is the per-step sum c_t, which is
+ *     mathematically exact and only changes rounding.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORACLE_LN_2PI 1.8378770664093454835606594728112
+
+/* Parameter and data validity shared by every oracle entry point.
+ * delta_k >= 0, 0 <= Gamma_ij <= 1, 0 <= p_k <= 1, mu finite,
+ * Sxx > 0, Syy > 0, Sxx*Syy - Sxy^2 > 0, all finite.  Returns 1 if valid. */
+static int oracle_params_valid(int K, const double *delta, const double *Gamma,
+                               const double *p, const double *mu, const double *Sigma)
+{
+    if (K < 1) return 0;
+    for (int k = 0; k < K; ++k) {
+        if (!isfinite(delta[k]) || delta[k] < 0.0) return 0;
+        for (int j = 0; j < K; ++j) {
+            double g = Gamma[(size_t)k * K + j];
+            if (!isfinite(g) || g < 0.0 || g > 1.0) return 0;
+        }
+        if (!isfinite(p[k]) || p[k] < 0.0 || p[k] > 1.0) return 0;
+        if (!isfinite(mu[2 * k]) || !isfinite(mu[2 * k + 1])) return 0;
+        double sxx = Sigma[3 * k], sxy = Sigma[3 * k + 1], syy = Sigma[3 * k + 2];
+        if (!isfinite(sxx) || !isfinite(sxy) || !isfinite(syy)) return 0;
+        if (!(sxx > 0.0) || !(syy > 0.0)) return 0;
+        if (!(sxx * syy - sxy * sxy > 0.0)) return 0;
+    }
+    return 1;
+}
+
+/* eq. (1) in natural-log form.  out[t*K + k] = ln e_{t,k}.
+ * ln e = ln p_k - ln(2 pi) - ln|Sigma_k|/2 - (x-mu_k)^T Sigma_k^{-1} (x-mu_k)/2  (tremor)
+ * ln e = ln(1 - p_k)                                                         (no tremor)
+ * Returns 0 on success, 1 if some data point is invalid (flag not 0/1, or a
+ * tremor with a non-finite location); out is then filled with NaN. */
+int oracle_log_emission(int K, const double *p, const double *mu, const double *Sigma,
+                        int64_t T, const uint8_t *flag, const double *xy, double *out)
+{
+    for (int64_t t = 0; t < T; ++t) {
+        int bad = 0;
+        if (flag[t] > 1) bad = 1;
+        if (flag[t] == 1 && (!isfinite(xy[2 * t]) || !isfinite(xy[2 * t + 1]))) bad = 1;
+        if (bad) {
+            for (int64_t i = 0; i < T * (int64_t)K; ++i) out[i] = NAN;
+            return 1;
+        }
+        for (int k = 0; k < K; ++k) {
+            double v;
+            if (flag[t] == 1) {
+                double sxx = Sigma[3 * k], sxy = Sigma[3 * k + 1], syy = Sigma[3 * k + 2];
+                double det = sxx * syy - sxy * sxy;
+                double d0 = xy[2 * t] - mu[2 * k];
+                double d1 = xy[2 * t + 1] - mu[2 * k + 1];
+                /* Sigma^{-1} = [[syy, -sxy], [-sxy, sxx]] / det */
+                double q = (syy * d0 * d0 - 2.0 * sxy * d0 * d1 + sxx * d1 * d1) / det;
+                v = log(p[k]) - ORACLE_LN_2PI - 0.5 * log(det) - 0.5 * q;
+            } else {
+                v = log1p(-p[k]);
+            }
+            out[(size_t)t * K + k] = v;
+        }
+    }
+    return 0;
+}
+
+/* Algorithm 1 with per-step normalisation, given ln e_{t,k} directly.
+ *   a <- delta^T Gamma
+ *   for t = 0..T-1:
+ *     if t > 0: a <- u Gamma
+ *     m_t = max_k ln e_{t,k};  b_k = a_k exp(ln e_{t,k} - m_t);  c_t = sum_k b_k
+ *     if c_t == 0: L = 0 -> return -inf
+ *     u <- b / c_t;  ll += ln c_t + m_t
+ *   return ll
+ * Summations run over ascending indices. */
+double oracle_forward_from_logemis(int K, const double *delta, const double *Gamma,
+                                   int64_t T, const double *logE)
+{
+    double *u = (double *)malloc(sizeof(double) * (size_t)K);
+    double *a = (double *)malloc(sizeof(double) * (size_t)K);
+    double ll = 0.0;
+    if (T == 0) {
+        double s = 0.0;
+        for (int k = 0; k < K; ++k) s += delta[k];
+        free(u); free(a);
+        return log(s);
+    }
+    for (int k = 0; k < K; ++k) u[k] = delta[k];
+    for (int64_t t = 0; t < T; ++t) {
+        /* a = u Gamma (for t = 0, u = delta: the Gamma before P(x_0) in eq. 2) */
+        for (int j = 0; j < K; ++j) {
+            double s = 0.0;
+            for (int i = 0; i < K; ++i) s += u[i] * Gamma[(size_t)i * K + j];
+            a[j] = s;
+        }
+        const double *le = logE + (size_t)t * K;
+        double m = -INFINITY;
+        for (int k = 0; k < K; ++k) if (le[k] > m) m = le[k];
+        if (isnan(m)) { free(u); free(a); return NAN; }
+        if (m == -INFINITY) { free(u); free(a); return -INFINITY; }
+        double c = 0.0;
+        for (int k = 0; k < K; ++k) {
+            u[k] = a[k] * exp(le[k] - m);
+            c += u[k];
+        }
+        if (c == 0.0) { free(u); free(a); return -INFINITY; }
+        for (int k = 0; k < K; ++k) u[k] /= c;
+        ll += log(c) + m;
+    }
+    free(u); free(a);
+    return ll;
+}
+
+/* Full likelihood: validity checks, eq. (1), then Algorithm 1 (natural log). */
+double oracle_loglik(int K, const double *delta, const double *Gamma, const double *p,
+                     const double *mu, const double *Sigma, int64_t T,
+                     const uint8_t *flag, const double *xy)
+{
+    if (!oracle_params_valid(K, delta, Gamma, p, mu, Sigma) || T < 0) return NAN;
+    double *logE = (double *)malloc(sizeof(double) * (size_t)(T > 0 ? T : 1) * (size_t)K);
+    if (!logE) return NAN;
+    if (oracle_log_emission(K, p, mu, Sigma, T, flag, xy, logE) != 0) { free(logE); return NAN; }
+    double ll = oracle_forward_from_logemis(K, delta, Gamma, T, logE);
+    free(logE);
+    return ll;
+}
+
+/* The same quantity in the order of the paper's parallel plan (section "The
+ * likelihood algorithm", steps 1-3): the chain Gamma P(x_0) ... Gamma P(x_N)
+ * is cut into segments of L factors, each segment's matrix product is formed
+ * on its own (with a scalar scale factor kept as a logarithm), and the
+ * segment products are then applied to delta^T left to right (the paper does
+ * this last part on the host).  Everything is FP64.  By associativity the
+ * result equals oracle_loglik up to rounding; the tests use this to pin that
+ * the block order is exact.  Each segment's running matrix is divided by its
+ * largest entry after every factor. */
+double oracle_loglik_blocked(int K, const double *delta, const double *Gamma, const double *p,
+                             const double *mu, const double *Sigma, int64_t T,
+                             const uint8_t *flag, const double *xy, int64_t L)
+{
+    if (!oracle_params_valid(K, delta, Gamma, p, mu, Sigma) || T < 0 || L < 1) return NAN;
+    if (T == 0) {
+        double s = 0.0;
+        for (int k = 0; k < K; ++k) s += delta[k];
+        return log(s);
+    }
+    size_t KK = (size_t)K * K;
+    double *logE = (double *)malloc(sizeof(double) * (size_t)T * K);
+    double *M = (double *)malloc(sizeof(double) * KK);
+    double *W = (double *)malloc(sizeof(double) * KK);
+    double *v = (double *)malloc(sizeof(double) * K);
+    double *w = (double *)malloc(sizeof(double) * K);
+    if (oracle_log_emission(K, p, mu, Sigma, T, flag, xy, logE) != 0) {
+        free(logE); free(M); free(W); free(v); free(w);
+        return NAN;
+    }
+    double ll = 0.0; /* accumulated log scale factors */
+    for (int k = 0; k < K; ++k) v[k] = delta[k];
+    for (int64_t s0 = 0; s0 < T; s0 += L) {
+        int64_t s1 = s0 + L < T ? s0 + L : T;
+        /* M <- identity */
+        for (size_t i = 0; i < KK; ++i) M[i] = 0.0;
+        for (int k = 0; k < K; ++k) M[(size_t)k * K + k] = 1.0;
+        double seg_log = 0.0;
+        for (int64_t t = s0; t < s1; ++t) {
+            const double *le = logE + (size_t)t * K;
+            double m = -INFINITY;
+            for (int k = 0; k < K; ++k) if (le[k] > m) m = le[k];
+            if (m == -INFINITY) { ll = -INFINITY; goto done; }
+            /* W = M Gamma diag(exp(le - m)) */
+            for (int i = 0; i < K; ++i)
+                for (int j = 0; j < K; ++j) {
+                    double s = 0.0;
+                    for (int r = 0; r < K; ++r) s += M[(size_t)i * K + r] * Gamma[(size_t)r * K + j];
+                    W[(size_t)i * K + j] = s * exp(le[j] - m);
+                }
+            double mx = 0.0;
+            for (size_t i = 0; i < KK; ++i) if (W[i] > mx) mx = W[i];
+            if (mx == 0.0) { ll = -INFINITY; goto done; }
+            for (size_t i = 0; i < KK; ++i) M[i] = W[i] / mx;
+            seg_log += m + log(mx);
+        }
+        /* v <- v M, normalised by its sum */
+        double c = 0.0;
+        for (int j = 0; j < K; ++j) {
+            double s = 0.0;
+            for (int i = 0; i < K; ++i) s += v[i] * M[(size_t)i * K + j];
+            w[j] = s;
+            c += s;
+        }
+        if (c == 0.0) { ll = -INFINITY; goto done; }
+        for (int j = 0; j < K; ++j) v[j] = w[j] / c;
+        ll += seg_log + log(c);
+    }
+done:
+    free(logE); free(M); free(W); free(v); free(w);
+    return ll;
+}
+
+/* Many independent sets at once, one set per call of oracle_loglik; used only
+ * to time the oracle on several host threads.  Sets are described by offsets
+ * into packed arrays exactly like the batched GPU entry point's inputs.
+ * Threads (if > 1) split the sets round-robin with pthreads. */
+#include <pthread.h>
+typedef struct {
+    int32_t n, nthreads, tid;
+    const int32_t *K; const int64_t *T; const int64_t *param_off; const double *params;
+    const int64_t *obs_off; const uint8_t *flag; const double *xy; double *out;
+} oracle_batch_job;
+
+static void *oracle_batch_worker(void *arg)
+{
+    oracle_batch_job *j = (oracle_batch_job *)arg;
+    for (int32_t s = j->tid; s < j->n; s += j->nthreads) {
+        int K = j->K[s];
+        const double *base = j->params + j->param_off[s];
+        /* packed parameter block: delta[K], Gamma[K*K], p[K], mu[2K], Sigma[3K] */
+        const double *delta = base, *Gamma = delta + K, *pp = Gamma + (size_t)K * K;
+        const double *mu = pp + K, *Sigma = mu + 2 * K;
+        int64_t o = j->obs_off[s];
+        j->out[s] = oracle_loglik(K, delta, Gamma, pp, mu, Sigma, j->T[s], j->flag + o, j->xy + 2 * o);
+    }
+    return NULL;
+}
+
+int oracle_loglik_batch(int32_t n, const int32_t *K, const int64_t *T, const int64_t *param_off,
+                        const double *params, const int64_t *obs_off, const uint8_t *flag,
+                        const double *xy, double *out, int32_t nthreads)
+{
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > 256) nthreads = 256;
+    pthread_t th[256];
+    oracle_batch_job jobs[256];
+    for (int32_t i = 0; i < nthreads; ++i) {
+        jobs[i] = (oracle_batch_job){n, nthreads, i, K, T, param_off, params, obs_off, flag, xy, out};
+        if (nthreads == 1) { oracle_batch_worker(&jobs[i]); return 0; }
+        pthread_create(&th[i], NULL, oracle_batch_worker, &jobs[i]);
+    }
+    for (int32_t i = 0; i < nthreads; ++i) pthread_join(th[i], NULL);
+    return 0;
+}

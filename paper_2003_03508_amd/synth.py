@@ -1,0 +1,152 @@
+"""Seeded synthetic tremor-HMM workloads.
+
+This module only draws random inputs; it contains none of the likelihood
+arithmetic, so both the GPU library's tests and the CPU oracle can be fed from
+it.  It stands in for the paper's Shikoku tremor catalogue (105,000 hourly
+points, section "Tremor dataset of the Shikoku region") and for the simulator
+the paper used to make synthetic data (section "OpenCL algorithm vs Forward
+algorithm"), neither of which is available: hourly binary tremor occurrence
+plus a 2-D location in km, generated from the HMM of the paper's model
+section.
+
+Recipe (one parameter set, ``numpy.random.default_rng(seed)``, draws in this
+order):
+  1. Gamma rows ~ Dirichlet(alpha), alpha = 1 off the diagonal, 50 on it.
+  2. delta = uniform 1/K (not drawn).
+  3. p_k ~ U(0.05, 0.9).
+  4. mu_k ~ U([0, 200]^2) km.
+  5. sigma_k ~ U(5, 30)^2 km (x then y), Sigma_k = diag(sigma_x^2, sigma_y^2),
+     stored as (Sxx, Sxy, Syy) with Sxy = 0.
+  6. s_{-1} ~ delta, then s_t ~ Gamma[s_{t-1}, :] for t = 0..T-1 (the state
+     before the first observation, as eq. (2) applies Gamma before P(x_0)).
+  7. f_t ~ Bernoulli(p_{s_t}); x_t ~ N(mu_{s_t}, Sigma_{s_t}) if f_t = 1,
+     else (NaN, NaN).
+Uniforms for steps 6-7 are drawn as whole arrays (u_state[T+1], u_flag[T],
+z[T, 2]) before the path is walked.
+"""
+import bisect
+import hashlib
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+@dataclass
+class HMMParams:
+    delta: np.ndarray   # (K,)
+    Gamma: np.ndarray   # (K, K) row-stochastic
+    p: np.ndarray       # (K,)
+    mu: np.ndarray      # (K, 2)
+    Sigma: np.ndarray   # (K, 3) as (Sxx, Sxy, Syy)
+
+    @property
+    def K(self):
+        return int(self.delta.shape[0])
+
+    def packed(self):
+        """delta | Gamma (row-major) | p | mu | Sigma as one float64 vector."""
+        return np.concatenate([self.delta.ravel(), self.Gamma.ravel(), self.p.ravel(),
+                               self.mu.ravel(), self.Sigma.ravel()]).astype(np.float64)
+
+
+@dataclass
+class Observations:
+    flag: np.ndarray    # (T,) uint8, 1 = tremor
+    xy: np.ndarray      # (T, 2) float64, NaN where flag = 0
+    states: np.ndarray = field(default=None)  # (T,) hidden states (for diagnostics)
+
+    @property
+    def T(self):
+        return int(self.flag.shape[0])
+
+    def digest(self):
+        h = hashlib.sha256()
+        h.update(np.ascontiguousarray(self.flag).tobytes())
+        h.update(np.ascontiguousarray(self.xy).tobytes())
+        return h.hexdigest()
+
+
+def draw_params(rng, K, diag_alpha=50.0, off_alpha=1.0):
+    alpha = np.full((K, K), off_alpha)
+    np.fill_diagonal(alpha, diag_alpha)
+    Gamma = np.stack([rng.dirichlet(alpha[i]) for i in range(K)])
+    delta = np.full(K, 1.0 / K)
+    p = rng.uniform(0.05, 0.9, size=K)
+    mu = rng.uniform(0.0, 200.0, size=(K, 2))
+    sig = rng.uniform(5.0, 30.0, size=(K, 2))
+    Sigma = np.stack([sig[:, 0] ** 2, np.zeros(K), sig[:, 1] ** 2], axis=1)
+    return HMMParams(delta, Gamma, p, mu, Sigma)
+
+
+def sample_path(rng, prm, T):
+    K = prm.K
+    u_state = rng.random(T + 1)
+    u_flag = rng.random(T)
+    z = rng.standard_normal((T, 2))
+    cum_delta = np.cumsum(prm.delta)
+    cum_delta[-1] = 1.0
+    rows = []
+    for i in range(K):
+        c = np.cumsum(prm.Gamma[i])
+        c[-1] = 1.0
+        rows.append(c.tolist())
+    s = min(bisect.bisect_right(cum_delta.tolist(), u_state[0]), K - 1)
+    states = np.empty(T, dtype=np.int32)
+    us = u_state.tolist()
+    for t in range(T):
+        s = bisect.bisect_right(rows[s], us[t + 1])
+        if s >= K:
+            s = K - 1
+        states[t] = s
+    flag = (u_flag < prm.p[states]).astype(np.uint8)
+    sd = np.sqrt(np.stack([prm.Sigma[:, 0], prm.Sigma[:, 2]], axis=1))
+    xy = prm.mu[states] + sd[states] * z
+    xy[flag == 0] = np.nan
+    return Observations(flag, np.ascontiguousarray(xy), states)
+
+
+def make(K, T, seed):
+    """One parameter set and one path with the recipe above."""
+    rng = np.random.default_rng(seed)
+    prm = draw_params(rng, K)
+    obs = sample_path(rng, prm, T)
+    return prm, obs
+
+
+# Workloads with the shapes the paper's method is benchmarked on.
+WORKLOADS = {
+    "k3_t1e4": dict(K=3, T=10_000, seed=0),
+    "k25_t1e6": dict(K=25, T=1_000_000, seed=1),
+    "k80_t4m": dict(K=80, T=4_194_304, seed=2),
+    "k20_t5e5": dict(K=20, T=500_000, seed=4),
+}
+
+
+def batch(n=256, K_lo=8, K_hi=64, T_lo=100_000, T_hi=1_000_000, seed=3, T_scale=1.0):
+    """n independent sets, K ~ U{K_lo..K_hi}, T ~ U[T_lo, T_hi] (scaled by T_scale),
+    each with its own seed derived from ``seed``.  Returns packed arrays in the
+    layout of the batched entry point plus the per-set objects."""
+    rng = np.random.default_rng(seed)
+    Ks = rng.integers(K_lo, K_hi + 1, size=n)
+    Ts = (rng.integers(T_lo, T_hi + 1, size=n) * T_scale).astype(np.int64)
+    seeds = rng.integers(0, 2**63 - 1, size=n)
+    sets = [make(int(Ks[i]), int(Ts[i]), int(seeds[i])) for i in range(n)]
+    return pack(sets), sets
+
+
+def pack(sets):
+    """Pack (params, obs) pairs: returns dict of K, T, param_off, params, obs_off, flag, xy."""
+    Ks = np.array([prm.K for prm, _ in sets], dtype=np.int32)
+    Ts = np.array([obs.T for _, obs in sets], dtype=np.int64)
+    blocks = [prm.packed() for prm, _ in sets]
+    param_off = np.zeros(len(sets), dtype=np.int64)
+    if len(sets) > 1:
+        param_off[1:] = np.cumsum([b.shape[0] for b in blocks])[:-1]
+    obs_off = np.zeros(len(sets), dtype=np.int64)
+    if len(sets) > 1:
+        obs_off[1:] = np.cumsum(Ts)[:-1]
+    params = np.concatenate(blocks) if blocks else np.zeros(0)
+    flag = np.concatenate([obs.flag for _, obs in sets]) if sets else np.zeros(0, np.uint8)
+    xy = np.concatenate([obs.xy for _, obs in sets]) if sets else np.zeros((0, 2))
+    return dict(K=Ks, T=Ts, param_off=param_off, params=params, obs_off=obs_off,
+                flag=flag, xy=xy)

@@ -1,0 +1,250 @@
+"""Pins for the CPU oracle, checked against things other than itself.
+
+Each test fixes a fact from the paper's definitions (eq. 1, eq. 2,
+Algorithm 1) or from mathematics: exact path enumeration, closed forms,
+invariants and a textbook density.  A dropped term, wrong sign, wrong index or
+transposed operand in the oracle fails at least one of them.
+"""
+import json
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+from scipy.special import logsumexp
+from scipy.stats import multivariate_normal
+
+from oracle import brute, logspace
+from paper_2003_03508_amd import synth
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def rel(a, b):
+    return abs(a - b) / max(abs(b), 1e-300)
+
+
+def rand_rational_stochastic(rng, K, den=97):
+    rows = []
+    for _ in range(K):
+        w = rng.integers(1, den, size=K)
+        s = int(w.sum())
+        rows.append([Fraction(int(x), s) for x in w])
+    return rows
+
+
+@pytest.mark.parametrize("K,T", [(1, 0), (1, 4), (2, 1), (2, 5), (3, 3), (3, 6)])
+def test_bruteforce_exact_rationals(oracle_mod, K, T):
+    """eq. (2) summed over all K^(T+1) paths in exact arithmetic vs both oracles."""
+    rng = np.random.default_rng(100 + 10 * K + T)
+    delta = [Fraction(int(x), 1000) for x in rng.integers(1, 1000, size=K)]
+    Gamma = rand_rational_stochastic(rng, K)
+    E = [[Fraction(int(a), int(b)) for a, b in zip(rng.integers(1, 50, size=K),
+                                                      rng.integers(50, 5000, size=K))]
+         for _ in range(T)]
+    exact = brute.log_fraction(brute.likelihood(delta, Gamma, E))
+    d = np.array([float(x) for x in delta])
+    G = np.array([[float(x) for x in r] for r in Gamma])
+    logE = np.array([[math.log(x.numerator) - math.log(x.denominator) for x in r] for r in E]
+                    ).reshape(T, K)
+    got = oracle_mod.forward_from_logemis(d, G, logE)
+    assert rel(got, exact) < 1e-13 or abs(got - exact) < 1e-13
+    got2 = logspace.forward_from_logemis(d, G, logE)
+    assert abs(got2 - exact) < 1e-12
+
+
+def test_hand_worked_golden(oracle_mod):
+    g = json.load(open(os.path.join(HERE, "golden", "hand_k2_t2.json")))
+    delta = [Fraction(x) for x in g["delta"]]
+    Gamma = [[Fraction(x) for x in r] for r in g["Gamma"]]
+    E = [[Fraction(x) for x in r] for r in g["E"]]
+    L = Fraction(g["L"])
+    assert brute.likelihood(delta, Gamma, E) == L
+    got = oracle_mod.forward_from_logemis(
+        np.array([float(x) for x in delta]), np.array([[float(x) for x in r] for r in Gamma]),
+        np.log(np.array([[float(x) for x in r] for r in E])))
+    assert abs(got - math.log(float(L))) < 1e-14
+
+
+def test_bruteforce_real_parameters(oracle_mod):
+    """Full path (eq. 1 emissions + eq. 2) on real parameters vs FP64 path enumeration
+    with emissions from SciPy's textbook bivariate normal."""
+    prm, obs = synth.make(3, 7, seed=11)
+    prm.Sigma[:, 1] = [3.0, -12.0, 0.5]  # correlated covariances
+    obs.flag[:] = [1, 0, 1, 1, 0, 1, 1]
+    rng = np.random.default_rng(5)
+    obs.xy[:] = rng.uniform(0, 200, size=(7, 2))
+    obs.xy[obs.flag == 0] = np.nan
+    E = []
+    for t in range(obs.T):
+        row = []
+        for k in range(prm.K):
+            if obs.flag[t]:
+                S = [[prm.Sigma[k, 0], prm.Sigma[k, 1]], [prm.Sigma[k, 1], prm.Sigma[k, 2]]]
+                row.append(prm.p[k] * multivariate_normal(prm.mu[k], S).pdf(obs.xy[t]))
+            else:
+                row.append(1 - prm.p[k])
+        E.append(row)
+    L = brute.likelihood(list(prm.delta), prm.Gamma.tolist(), E)
+    got = oracle_mod.loglik(prm.delta, prm.Gamma, prm.p, prm.mu, prm.Sigma, obs.flag, obs.xy)
+    assert rel(got, math.log(L)) < 1e-12
+
+
+def test_emission_vs_textbook_density(oracle_mod):
+    rng = np.random.default_rng(3)
+    K, T = 5, 200
+    p = rng.uniform(0.01, 0.99, K)
+    mu = rng.uniform(0, 200, (K, 2))
+    sx, sy = rng.uniform(5, 30, K), rng.uniform(5, 30, K)
+    rho = rng.uniform(-0.9, 0.9, K)
+    Sigma = np.stack([sx**2, rho * sx * sy, sy**2], axis=1)
+    flag = (rng.random(T) < 0.6).astype(np.uint8)
+    xy = rng.uniform(-50, 250, (T, 2))
+    xy[flag == 0] = np.nan
+    got = oracle_mod.log_emission(p, mu, Sigma, flag, xy)
+    for k in range(K):
+        S = [[Sigma[k, 0], Sigma[k, 1]], [Sigma[k, 1], Sigma[k, 2]]]
+        want = np.where(flag == 1,
+                        np.log(p[k]) + multivariate_normal(mu[k], S).logpdf(np.nan_to_num(xy)),
+                        np.log(1 - p[k]))
+        np.testing.assert_allclose(got[:, k], want, rtol=1e-13, atol=1e-12)
+
+
+def test_k1_closed_form(oracle_mod):
+    """K=1: Gamma = [1], so L = delta * prod_t e_t."""
+    prm, obs = synth.make(1, 3000, seed=7)
+    prm.delta[:] = 0.3
+    S = [[prm.Sigma[0, 0], 0], [0, prm.Sigma[0, 2]]]
+    f = obs.flag == 1
+    want = math.log(0.3) + f.sum() * math.log(prm.p[0]) \
+        + multivariate_normal(prm.mu[0], S).logpdf(obs.xy[f]).sum() \
+        + (~f).sum() * math.log1p(-prm.p[0])
+    got = oracle_mod.loglik(prm.delta, prm.Gamma, prm.p, prm.mu, prm.Sigma, obs.flag, obs.xy)
+    assert rel(got, want) < 1e-12
+
+
+def test_identical_states_closed_form(oracle_mod):
+    """Identical emissions in every state: L = (sum delta) * prod_t e_t for any
+    row-stochastic Gamma."""
+    prm, obs = synth.make(4, 2000, seed=8)
+    prm.p[:] = prm.p[0]
+    prm.mu[:] = prm.mu[0]
+    prm.Sigma[:] = prm.Sigma[0]
+    prm.delta[:] = [0.1, 0.2, 0.3, 0.15]
+    S = [[prm.Sigma[0, 0], 0], [0, prm.Sigma[0, 2]]]
+    f = obs.flag == 1
+    want = math.log(0.75) + f.sum() * math.log(prm.p[0]) \
+        + multivariate_normal(prm.mu[0], S).logpdf(obs.xy[f]).sum() \
+        + (~f).sum() * math.log1p(-prm.p[0])
+    got = oracle_mod.loglik(prm.delta, prm.Gamma, prm.p, prm.mu, prm.Sigma, obs.flag, obs.xy)
+    assert rel(got, want) < 1e-12
+
+
+def test_all_no_tremor_equal_p(oracle_mod):
+    prm, _ = synth.make(5, 1, seed=9)
+    prm.p[:] = 0.37
+    T = 12345
+    flag = np.zeros(T, np.uint8)
+    xy = np.full((T, 2), np.nan)
+    got = oracle_mod.loglik(prm.delta, prm.Gamma, prm.p, prm.mu, prm.Sigma, flag, xy)
+    assert rel(got, T * math.log(0.63)) < 1e-12
+
+
+def test_gamma_identity_closed_form(oracle_mod):
+    """Gamma = I: the chain never moves, L = sum_k delta_k prod_t e_{t,k}."""
+    prm, obs = synth.make(4, 300, seed=10)
+    prm.Gamma = np.eye(4)
+    prm.delta[:] = [0.4, 0.1, 0.3, 0.2]
+    lE = logspace.log_emission(prm.p, prm.mu, prm.Sigma, obs.flag, obs.xy)
+    want = logsumexp(np.log(prm.delta) + lE.sum(axis=0))
+    got = oracle_mod.loglik(prm.delta, prm.Gamma, prm.p, prm.mu, prm.Sigma, obs.flag, obs.xy)
+    assert rel(got, want) < 1e-12
+
+
+def test_gamma_rank_one_closed_form(oracle_mod):
+    """Gamma = 1 pi^T: every step forgets the past, L = (sum delta) prod_t pi^T e_t.
+    delta != pi, so applying Gamma before P(x_0) (eq. 2) matters."""
+    prm, obs = synth.make(5, 500, seed=12)
+    pi = np.array([0.05, 0.4, 0.25, 0.1, 0.2])
+    prm.Gamma = np.tile(pi, (5, 1))
+    prm.delta[:] = [0.6, 0.1, 0.1, 0.1, 0.1]
+    lE = logspace.log_emission(prm.p, prm.mu, prm.Sigma, obs.flag, obs.xy)
+    want = math.log(prm.delta.sum()) + logsumexp(np.log(pi)[None, :] + lE, axis=1).sum()
+    got = oracle_mod.loglik(prm.delta, prm.Gamma, prm.p, prm.mu, prm.Sigma, obs.flag, obs.xy)
+    assert rel(got, want) < 1e-12
+
+
+def test_state_permutation_invariance(oracle_mod):
+    prm, obs = synth.make(6, 3000, seed=13)
+    prm.delta = np.random.default_rng(1).dirichlet(np.ones(6))
+    base = oracle_mod.loglik(prm.delta, prm.Gamma, prm.p, prm.mu, prm.Sigma, obs.flag, obs.xy)
+    perm = np.array([3, 0, 5, 1, 4, 2])
+    got = oracle_mod.loglik(prm.delta[perm], prm.Gamma[np.ix_(perm, perm)], prm.p[perm],
+                            prm.mu[perm], prm.Sigma[perm], obs.flag, obs.xy)
+    assert rel(got, base) < 1e-12
+
+
+def test_linear_in_delta(oracle_mod):
+    prm, obs = synth.make(4, 2000, seed=14)
+    d1 = np.array([0.5, 0.0, 0.2, 0.0])
+    d2 = np.array([0.0, 0.3, 0.0, 0.4])
+    args = (prm.Gamma, prm.p, prm.mu, prm.Sigma, obs.flag, obs.xy)
+    l1 = oracle_mod.loglik(d1, *args)
+    l2 = oracle_mod.loglik(d2, *args)
+    l12 = oracle_mod.loglik(d1 + d2, *args)
+    assert rel(l12, np.logaddexp(l1, l2)) < 1e-12
+    assert rel(oracle_mod.loglik(0.25 * d1, *args), l1 + math.log(0.25)) < 1e-12
+
+
+@pytest.mark.parametrize("K,T,seed", [(3, 1000, 0), (7, 777, 3), (25, 400, 1)])
+def test_block_order_equals_serial_order(oracle_mod, K, T, seed):
+    """Associativity: the paper's segment-product order gives the same likelihood."""
+    prm, obs = synth.make(K, T, seed)
+    args = (prm.delta, prm.Gamma, prm.p, prm.mu, prm.Sigma, obs.flag, obs.xy)
+    serial = oracle_mod.loglik(*args)
+    for L in (1, 2, 3, 7, 64, T):
+        assert rel(oracle_mod.loglik_blocked(*args, L), serial) < 1e-12, L
+
+
+@pytest.mark.parametrize("K,T,seed", [(3, 2000, 0), (7, 600, 2), (25, 300, 1)])
+def test_two_oracles_agree(oracle_mod, K, T, seed):
+    prm, obs = synth.make(K, T, seed)
+    args = (prm.delta, prm.Gamma, prm.p, prm.mu, prm.Sigma, obs.flag, obs.xy)
+    assert rel(oracle_mod.loglik(*args), logspace.loglik(*args)) < 1e-12
+
+
+def test_edge_cases(oracle_mod):
+    prm, obs = synth.make(3, 50, seed=15)
+    args = [prm.delta, prm.Gamma, prm.p, prm.mu, prm.Sigma, obs.flag, obs.xy]
+    # empty chain: delta^T 1
+    e = oracle_mod.loglik(prm.delta * 0.5, prm.Gamma, prm.p, prm.mu, prm.Sigma,
+                          np.zeros(0, np.uint8), np.zeros((0, 2)))
+    assert abs(e - math.log(0.5)) < 1e-15
+    # impossible observation: no state can emit a tremor
+    p0 = np.zeros(3)
+    fl = obs.flag.copy()
+    fl[10] = 1
+    xy = obs.xy.copy()
+    xy[10] = (100.0, 100.0)
+    assert oracle_mod.loglik(prm.delta, prm.Gamma, p0, prm.mu, prm.Sigma, fl, xy) == -math.inf
+    # invalid parameters and data -> NaN
+    bad = [
+        ("delta<0", 0, np.array([-0.1, 0.6, 0.5])),
+        ("Gamma>1", 1, np.where(np.eye(3) > 0, 1.5, 0.0)),
+        ("p>1", 2, np.array([0.5, 1.2, 0.3])),
+        ("mu nan", 3, np.array([[1.0, np.nan], [2, 3], [4, 5]])),
+        ("Sigma not SPD", 4, np.array([[1.0, 2.0, 1.0]] * 3)),
+    ]
+    for name, i, val in bad:
+        a = list(args)
+        a[i] = val
+        assert math.isnan(oracle_mod.loglik(*a)), name
+    fl = obs.flag.copy()
+    fl[3] = 2
+    assert math.isnan(oracle_mod.loglik(*args[:5], fl, obs.xy))
+    fl = obs.flag.copy()
+    xy = obs.xy.copy()
+    fl[4] = 1
+    xy[4] = (np.nan, 1.0)
+    assert math.isnan(oracle_mod.loglik(*args[:5], fl, xy))
