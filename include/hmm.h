@@ -1,0 +1,129 @@
+/*
+ * hmm.h -- C ABI of the MI355X (gfx950) tremor-HMM likelihood library.
+ *
+ * The library evaluates the likelihood of the tremor hidden Markov model of
+ * Stoltz, Stoltz, Obara, Wang & Bryant, "A 1000-fold Acceleration of Hidden
+ * Markov Model Fitting using Graphical Processing Units" (arXiv 2003.03508):
+ *
+ *   eq. (1)  emission matrix P(x) = diag(e_1..e_K),
+ *            e_k = p_k * phi(x | mu_k, Sigma_k)  for a tremor at x in R^2,
+ *            e_k = 1 - p_k                        for "no tremor";
+ *            phi is the bivariate normal density (full normalising constant).
+ *   eq. (2)  L = delta^T Gamma P(x_0) Gamma P(x_1) ... Gamma P(x_N) 1,
+ *            Gamma applied before the first emission, as written there.
+ *
+ * and returns ln L in double precision.  Conventions shared by every entry
+ * point:
+ *
+ *   - All array arguments are DEVICE pointers (memory of the device the
+ *     context was created on), owned by the caller.  The library neither
+ *     frees nor keeps them past the call.
+ *   - Work is enqueued on `stream` (a hipStream_t; NULL = the legacy default
+ *     stream) and is asynchronous: results are valid once the caller has
+ *     synchronised that stream.  A context holds scratch memory that calls
+ *     reuse, so calls that share a context must be issued on one stream (or be
+ *     otherwise serialised); a context is not thread-safe.
+ *   - Layouts: delta[K]; Gamma[K*K] row-major with Gamma[i*K+j] the probability
+ *     of moving from state i to state j; p[K]; mu[2K] as (x, y) pairs in km;
+ *     Sigma[3K] as (Sxx, Sxy, Syy) triples in km^2; flag[T] uint8 (1 = tremor,
+ *     0 = none); xy[2T] as (x, y) pairs, read only where flag is 1.  T counts
+ *     observations (the paper's N+1).
+ *   - Errors the host can see (null pointers, K or T out of range, unknown
+ *     algorithm) are returned as an hmm_status and nothing is enqueued.
+ *     Problems only the device can see are reported in the result: NaN for
+ *     invalid parameters (delta_k < 0, Gamma_ij outside [0,1], p_k outside
+ *     [0,1], non-finite mu, Sigma not symmetric positive definite, any
+ *     non-finite parameter) or invalid data (a flag other than 0/1, a tremor
+ *     with a non-finite location); -inf when L = 0 with valid inputs.
+ *     T = 0 gives ln(sum_k delta_k), the empty chain of eq. (2).
+ *   - Numerics of the GPU paths: emissions are formed in FP32 (locations are
+ *     differenced from the means in FP64 first) relative to each step's
+ *     largest emission, whose power-of-two exponent is carried exactly as an
+ *     integer; products accumulate in FP32; only the final combination of
+ *     exponents and the logarithm are FP64.  A state whose emission falls
+ *     below 2^-149 of the step's largest one counts as zero.
+ */
+#ifndef HMM_MI355X_H
+#define HMM_MI355X_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HMM_OK = 0,
+    HMM_E_INVALID_ARG = -1,  /* null pointer, K/T/n out of range, bad option      */
+    HMM_E_UNSUPPORTED = -2,  /* valid request this build does not implement      */
+    HMM_E_DEVICE = -3,       /* a HIP call failed (launch, allocation of scratch) */
+    HMM_E_NOMEM = -4         /* scratch memory could not be allocated            */
+} hmm_status;
+
+typedef enum {
+    /* Algorithm 1 (the forward algorithm) on the GPU: one wavefront walks the
+     * T observations in order, v <- (v Gamma) P(x_t).  O(T K^2) work, T
+     * dependent steps.  K <= 128. */
+    HMM_SERIAL_F32 = 0,
+    /* The paper's parallel plan (section "The likelihood algorithm", steps
+     * 1-3): the chain Gamma P(x_0) ... Gamma P(x_N) is cut into segments whose
+     * products are formed independently on the matrix cores (FP32 MFMA) with
+     * the emissions computed in the same kernel, then the segment products are
+     * combined by a tree of matrix products on the GPU.  O(T K^3) work.
+     * K <= 80. */
+    HMM_BLOCKED_F32 = 1,
+    HMM_BLOCKED_BF16 = 2,   /* reserved: bf16 operands, FP32 accumulation */
+    HMM_BLOCKED_F16 = 3     /* reserved: fp16 operands, FP32 accumulation */
+} hmm_algo;
+
+typedef struct hmm_ctx hmm_ctx;
+
+/* Create a context on HIP device `device` (makes it current).  *out receives
+ * the context.  Returns HMM_E_DEVICE if the device cannot be used. */
+int hmm_ctx_create(hmm_ctx **out, int device);
+
+/* Release the context and its scratch memory (synchronises the device). */
+int hmm_ctx_destroy(hmm_ctx *ctx);
+
+/* ln L of eq. (2) for one parameter set and one observation sequence.
+ *   K      number of hidden states, 1 <= K <= 128 (K <= 80 for blocked algos)
+ *   delta, Gamma, p, mu, Sigma, flag, xy   device arrays as described above
+ *   T      number of observations, 0 <= T < 2^40
+ *   algo   an hmm_algo value
+ *   out    device pointer to one double, receives ln L
+ * Returns HMM_OK when the work was enqueued. */
+int hmm_loglik(hmm_ctx *ctx, int32_t K, const double *delta, const double *Gamma,
+               const double *p, const double *mu, const double *Sigma, int64_t T,
+               const uint8_t *flag, const double *xy, int32_t algo, void *stream,
+               double *out);
+
+/* The emission stage of the GPU paths (eq. 1) on its own, for inspection.
+ * For every observation t it writes the integer shift s_t (shift[t]) and the
+ * scaled emissions  e_hat[t*K + k] = e_{t,k} * 2^(-s_t)  in FP32, where s_t is
+ * floor(log2 max_k e_{t,k}) (so the largest scaled emission lies in [1, 2)).
+ * shift: device int32[T]; e_hat: device float[T*K].  status: device int32[1],
+ * receives a bit mask (1 = invalid parameters, 2 = invalid data). */
+int hmm_emission(hmm_ctx *ctx, int32_t K, const double *p, const double *mu,
+                 const double *Sigma, int64_t T, const uint8_t *flag, const double *xy,
+                 void *stream, int32_t *shift, float *e_hat, int32_t *status);
+
+/* Tuning knobs of the blocked path.  block_len: observations per segment
+ * (0 = automatic; otherwise >= 1).  fold: segment products folded per
+ * wavefront at each level of the combination tree (0 = automatic; otherwise
+ * 2..64).  They change the order of floating-point operations only. */
+int hmm_ctx_set_blocking(hmm_ctx *ctx, int64_t block_len, int32_t fold);
+
+/* Segment length and tree shape the blocked path would use for (K, T):
+ * *block_len, *n_blocks, *levels (reduction launches).  Host only; ctx may be
+ * NULL for the default knobs. */
+int hmm_blocked_plan(hmm_ctx *ctx, int32_t K, int64_t T, int64_t *block_len,
+                     int64_t *n_blocks, int32_t *levels);
+
+/* Human-readable name of a status code (static storage). */
+const char *hmm_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HMM_MI355X_H */

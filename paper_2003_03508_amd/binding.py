@@ -1,0 +1,158 @@
+"""Thin ctypes binding of the C ABI in include/hmm.h.
+
+Argument marshalling only: torch tensors are checked (device, dtype, layout)
+and their device pointers and the current HIP stream are handed to the
+library; every step of the computation runs in the library's kernels.  If the
+compiled library is missing the import fails -- there is no fallback.
+"""
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhmm.so")
+
+HMM_OK = 0
+HMM_E_INVALID_ARG = -1
+HMM_E_UNSUPPORTED = -2
+HMM_E_DEVICE = -3
+HMM_E_NOMEM = -4
+
+SERIAL_F32 = 0
+BLOCKED_F32 = 1
+BLOCKED_BF16 = 2
+BLOCKED_F16 = 3
+ALGOS = {"serial_f32": SERIAL_F32, "blocked_f32": BLOCKED_F32,
+         "blocked_bf16": BLOCKED_BF16, "blocked_f16": BLOCKED_F16}
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with "
+                      "`python -m paper_2003_03508_amd.build` (no CPU fallback exists)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+_vp = ctypes.c_void_p
+_i32, _i64 = ctypes.c_int32, ctypes.c_int64
+
+_lib.hmm_ctx_create.argtypes = [ctypes.POINTER(_vp), ctypes.c_int]
+_lib.hmm_ctx_destroy.argtypes = [_vp]
+_lib.hmm_loglik.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _i32, _vp, _vp]
+_lib.hmm_emission.argtypes = [_vp, _i32, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp]
+_lib.hmm_ctx_set_blocking.argtypes = [_vp, _i64, _i32]
+_lib.hmm_blocked_plan.argtypes = [_vp, _i32, _i64, ctypes.POINTER(_i64), ctypes.POINTER(_i64),
+                                  ctypes.POINTER(_i32)]
+_lib.hmm_status_string.restype = ctypes.c_char_p
+_lib.hmm_status_string.argtypes = [ctypes.c_int]
+for _f in ("hmm_ctx_create", "hmm_ctx_destroy", "hmm_loglik", "hmm_emission",
+           "hmm_ctx_set_blocking", "hmm_blocked_plan"):
+    getattr(_lib, _f).restype = ctypes.c_int
+
+
+class HMMError(RuntimeError):
+    def __init__(self, fn, code):
+        super().__init__(f"{fn}: {_lib.hmm_status_string(code).decode()} ({code})")
+        self.code = code
+
+
+def _check(fn, code):
+    if code != HMM_OK:
+        raise HMMError(fn, code)
+
+
+def lib():
+    return _lib
+
+
+def _dev(t, dtype, name, numel=None):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be on a GPU")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements, got {t.numel()}")
+    return t.data_ptr() if t.numel() else None
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+class Context:
+    """One library context (scratch memory, tuning) on one device."""
+
+    def __init__(self, device=0):
+        self.device = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
+        h = _vp()
+        _check("hmm_ctx_create", _lib.hmm_ctx_create(ctypes.byref(h), self.device.index or 0))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.hmm_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_blocking(self, block_len=0, fold=0):
+        _check("hmm_ctx_set_blocking", _lib.hmm_ctx_set_blocking(self._h, int(block_len), int(fold)))
+
+    def plan(self, K, T):
+        L, nb, lv = _i64(), _i64(), _i32()
+        _check("hmm_blocked_plan", _lib.hmm_blocked_plan(self._h, int(K), int(T), ctypes.byref(L),
+                                                         ctypes.byref(nb), ctypes.byref(lv)))
+        return dict(block_len=L.value, n_blocks=nb.value, levels=lv.value)
+
+    def loglik(self, delta, Gamma, p, mu, Sigma, flag, xy, algo="blocked_f32", out=None,
+               stream=None):
+        """ln L (eq. 2) into a device float64 tensor of one element (returned)."""
+        K = int(delta.numel())
+        T = int(flag.numel())
+        if out is None:
+            out = torch.empty(1, dtype=torch.float64, device=delta.device)
+        a = ALGOS[algo] if isinstance(algo, str) else int(algo)
+        rc = _lib.hmm_loglik(self._h, K, _dev(delta, torch.float64, "delta", K),
+                             _dev(Gamma, torch.float64, "Gamma", K * K),
+                             _dev(p, torch.float64, "p", K), _dev(mu, torch.float64, "mu", 2 * K),
+                             _dev(Sigma, torch.float64, "Sigma", 3 * K), T,
+                             _dev(flag, torch.uint8, "flag", T), _dev(xy, torch.float64, "xy", 2 * T),
+                             a, _stream(stream), _dev(out, torch.float64, "out", 1))
+        _check("hmm_loglik", rc)
+        return out
+
+    def emission(self, p, mu, Sigma, flag, xy, stream=None):
+        """(shift int32[T], e_hat float32[T, K], status int32[1]) of the emission stage."""
+        K = int(p.numel())
+        T = int(flag.numel())
+        shift = torch.empty(T, dtype=torch.int32, device=p.device)
+        e_hat = torch.empty((T, K), dtype=torch.float32, device=p.device)
+        status = torch.empty(1, dtype=torch.int32, device=p.device)
+        rc = _lib.hmm_emission(self._h, K, _dev(p, torch.float64, "p", K),
+                               _dev(mu, torch.float64, "mu", 2 * K),
+                               _dev(Sigma, torch.float64, "Sigma", 3 * K), T,
+                               _dev(flag, torch.uint8, "flag", T), _dev(xy, torch.float64, "xy", 2 * T),
+                               _stream(stream), _dev(shift, torch.int32, "shift"),
+                               _dev(e_hat, torch.float32, "e_hat"), _dev(status, torch.int32, "status"))
+        _check("hmm_emission", rc)
+        return shift, e_hat, status
+
+
+def to_device(prm, obs, device="cuda"):
+    """Move a synth (HMMParams, Observations) pair to device tensors."""
+    f64 = dict(dtype=torch.float64, device=device)
+    return dict(delta=torch.as_tensor(prm.delta, **f64).contiguous(),
+                Gamma=torch.as_tensor(prm.Gamma, **f64).contiguous(),
+                p=torch.as_tensor(prm.p, **f64).contiguous(),
+                mu=torch.as_tensor(prm.mu, **f64).contiguous(),
+                Sigma=torch.as_tensor(prm.Sigma, **f64).contiguous(),
+                flag=torch.as_tensor(obs.flag, dtype=torch.uint8, device=device).contiguous(),
+                xy=torch.as_tensor(obs.xy, **f64).contiguous())

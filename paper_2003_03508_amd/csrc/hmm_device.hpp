@@ -1,0 +1,213 @@
+// Device-side building blocks shared by the likelihood kernels (gfx950).
+//
+// Notation follows the paper: K hidden states, Gamma (K x K) transition
+// matrix, emission matrix P(x) = diag(e_1..e_K) of eq. (1), likelihood
+// L = delta^T Gamma P(x_0) ... Gamma P(x_N) 1 of eq. (2).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hmm {
+
+// Observations per emission chunk: one observation per lane in the per-step
+// passes, so the chunk equals the wavefront width.
+constexpr int kChunk = 64;
+constexpr int kWave = 64;
+
+// Per-state constants of eq. (1), prepared once per call from the FP64
+// parameters.  In log2 units:
+//   tremor:    log2 e = a1 + cxx*d0^2 + cxy*d0*d1 + cyy*d1^2,  d = x - mu
+//   no tremor: log2 e = a0
+// with a1 = log2 p - log2(2 pi) - log2|Sigma|/2, a0 = log2(1 - p) and
+// (cxx, cxy, cyy) = -log2(e)/2 * Sigma^{-1} (off-diagonal doubled).
+// Padding states (k >= K) carry a1 = a0 = -inf so their emission is zero.
+struct alignas(16) StateConst {
+    double mx, my;
+    float cxx, cxy, cyy, a1;
+    float a0, pad0, pad1, pad2;
+};
+
+// ---------------------------------------------------------------------------
+// MFMA tiles.  S = 16 uses v_mfma_f32_16x16x4_f32, S = 32 uses
+// v_mfma_f32_32x32x2_f32.  Lane l owns column c = l % S of every output tile
+// and belongs to lane group g = l / S.  Register r of a tile holds row
+// row_in_tile<S>(g, r).  The A operand of one instruction is A[i][g] on lane
+// (i = l % S, g), the B operand is B[g][c] on lane (c, g): the contraction
+// index is the lane group.
+// ---------------------------------------------------------------------------
+template <int S> struct Tile;
+template <> struct Tile<16> {
+    static constexpr int RS = 4;
+    typedef float acc_t __attribute__((ext_vector_type(4)));
+};
+template <> struct Tile<32> {
+    static constexpr int RS = 16;
+    typedef float acc_t __attribute__((ext_vector_type(16)));
+};
+
+template <int S>
+__device__ __forceinline__ constexpr int row_in_tile(int g, int r)
+{
+    return S == 16 ? 4 * g + r : 8 * (r >> 2) + 4 * g + (r & 3);
+}
+
+template <int S>
+__device__ __forceinline__ typename Tile<S>::acc_t mfma(float a, float b, typename Tile<S>::acc_t c)
+{
+    if constexpr (S == 16)
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    else
+        return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+}
+
+// ---------------------------------------------------------------------------
+// Cross-lane helpers.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float swap32_max(float x)
+{
+    auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+    return fmaxf(x, fmaxf(__uint_as_float(r[0]), __uint_as_float(r[1])));
+}
+
+__device__ __forceinline__ float swap16_max(float x)
+{
+    auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+    return fmaxf(x, fmaxf(__uint_as_float(r[0]), __uint_as_float(r[1])));
+}
+
+// Maximum over the lanes that share one output column (same l % S).
+template <int S>
+__device__ __forceinline__ float column_max(float x)
+{
+    x = swap32_max(x);
+    if constexpr (S == 16) x = swap16_max(x);
+    return x;
+}
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float x)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, true));
+}
+
+// Maximum over the whole wavefront, returned to every lane.
+__device__ __forceinline__ float wave_max(float x)
+{
+    x = fmaxf(x, dpp_f<0xB1>(x));   // quad_perm [1,0,3,2]
+    x = fmaxf(x, dpp_f<0x4E>(x));   // quad_perm [2,3,0,1]
+    x = fmaxf(x, dpp_f<0x141>(x));  // row_half_mirror
+    x = fmaxf(x, dpp_f<0x140>(x));  // row_mirror: every lane holds its row's max
+    const float a = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 0));
+    const float b = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 16));
+    const float c = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 32));
+    const float d = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 48));
+    return fmaxf(fmaxf(a, b), fmaxf(c, d));
+}
+
+__device__ __forceinline__ double wave_sum_f64(double x)
+{
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+    return x;
+}
+
+__device__ __forceinline__ long long wave_sum_i64(long long x)
+{
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+    return x;
+}
+
+__device__ __forceinline__ long long wave_max_i64(long long x)
+{
+    for (int o = 32; o > 0; o >>= 1) {
+        long long y = __shfl_xor(x, o);
+        x = y > x ? y : x;
+    }
+    return x;
+}
+
+// Exponent e with x = m * 2^e, m in [0.5, 1); 0 for x == 0.
+__device__ __forceinline__ int fexp(float x) { return __builtin_amdgcn_frexp_expf(x); }
+
+// ---------------------------------------------------------------------------
+// Fused emission stage (eq. 1) for one chunk of up to kChunk observations.
+//
+//  1. the chunk's flags and locations are read with coalesced loads (one
+//     observation per lane) and kept in LDS;
+//  2. lam[t][k] = log2 e_{t,k} for all (t, k) pairs of the chunk, FP32, after
+//     differencing the location from the mean in FP64;
+//  3. per observation, s_t = floor(max_k lam[t][k]) (an exact integer shift);
+//  4. E[t][k] = 2^(lam - s_t) in FP32, so max_k E[t][k] lies in [1, 2).
+//
+// E is [kChunk][KP] in LDS; padding states and observations past the chunk
+// end get E = 0.  `ssum` accumulates the shifts of the observations this lane
+// handled; `bad` is set for invalid data (flag not 0/1, tremor with a
+// non-finite location).
+// ---------------------------------------------------------------------------
+struct ChunkLds {
+    double ox[kChunk];
+    double oy[kChunk];
+    int of[kChunk];
+    int sh[kChunk];
+};
+
+template <int KP>
+__device__ __forceinline__ void stage_emissions(int K, int64_t tc, int nst,
+                                                const uint8_t *__restrict__ flag,
+                                                const double *__restrict__ xy,
+                                                const StateConst *__restrict__ sc,
+                                                float *E, ChunkLds &cl,
+                                                long long &ssum, int &bad)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    if (lane < nst) {
+        int f = flag[tc + lane];
+        double x = 0.0, y = 0.0;
+        if (f == 1) {
+            x = xy[2 * (tc + lane)];
+            y = xy[2 * (tc + lane) + 1];
+            if (!(isfinite(x) && isfinite(y))) bad = 1;
+        } else if (f != 0) {
+            bad = 1;
+        }
+        cl.ox[lane] = x;
+        cl.oy[lane] = y;
+        cl.of[lane] = f;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int pi = lane; pi < kChunk * KP; pi += kWave) {
+        const int tl = pi / KP, k = pi % KP;
+        float lam = -INFINITY;
+        if (tl < nst && k < K) {
+            const StateConst s = sc[k];
+            if (cl.of[tl] == 1) {
+                const float d0 = (float)(cl.ox[tl] - s.mx);
+                const float d1 = (float)(cl.oy[tl] - s.my);
+                lam = s.a1 + d0 * (s.cxx * d0 + s.cxy * d1) + s.cyy * (d1 * d1);
+            } else {
+                lam = s.a0;
+            }
+        }
+        E[pi] = lam;
+    }
+    __syncthreads();
+    if (lane < nst) {
+        float m = -INFINITY;
+        const float *row = E + lane * KP;
+        for (int k = 0; k < K; ++k) m = fmaxf(m, row[k]);
+        int s = 0;
+        if (m > -1.0e9f && m < 1.0e9f) s = (int)floorf(m);
+        cl.sh[lane] = s;
+        ssum += s;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int pi = lane; pi < kChunk * KP; pi += kWave) {
+        const int tl = pi / KP;
+        E[pi] = exp2f(E[pi] - (float)cl.sh[tl]);
+    }
+    __syncthreads();
+}
+
+}  // namespace hmm

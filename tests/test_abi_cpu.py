@@ -1,0 +1,101 @@
+"""The C ABI on a machine without a GPU: the library loads, exports every
+function include/hmm.h declares, and its host-side logic (argument checks,
+blocking plan, status strings) works without touching a device."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hmm.h")
+LIB = os.path.join(ROOT, "paper_2003_03508_amd", "libhmm.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^[A-Za-z_][\w\s\*]*?\b(hmm_\w+)\s*\(", text, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        from paper_2003_03508_amd import build
+        build.build()
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_the_entry_points():
+    names = declared_functions()
+    for want in ("hmm_ctx_create", "hmm_ctx_destroy", "hmm_loglik", "hmm_emission",
+                 "hmm_ctx_set_blocking", "hmm_blocked_plan", "hmm_status_string"):
+        assert want in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True).stdout
+    exported = set(l.split()[-1] for l in out.splitlines() if l.strip())
+    for name in declared_functions():
+        assert name in exported, name
+        assert hasattr(lib, name), name
+
+
+def test_library_carries_gfx950_code_object():
+    """The fat binary embedded in our own build targets gfx950 (and only gfx950)."""
+    data = open(LIB, "rb").read()
+    targets = set(re.findall(rb"amdgcn-amd-amdhsa--(gfx\w+)", data))
+    assert targets == {b"gfx950"}, targets
+
+
+def test_host_argument_checks(lib):
+    lib.hmm_loglik.restype = ctypes.c_int
+    lib.hmm_loglik.argtypes = [ctypes.c_void_p, ctypes.c_int32] + [ctypes.c_void_p] * 5 + [
+        ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+        ctypes.c_void_p]
+    # null context
+    assert lib.hmm_loglik(None, 3, 1, 1, 1, 1, 1, 10, 1, 1, 1, None, 1) == -1
+    lib.hmm_ctx_set_blocking.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32]
+    assert lib.hmm_ctx_set_blocking(None, 0, 0) == -1
+    lib.hmm_status_string.restype = ctypes.c_char_p
+    assert lib.hmm_status_string(0) == b"ok"
+    assert lib.hmm_status_string(-2) == b"unsupported"
+
+
+def test_blocked_plan_without_device(lib):
+    f = lib.hmm_blocked_plan
+    f.restype = ctypes.c_int
+    f.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64] + [ctypes.c_void_p] * 3
+    L, nb, lv = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32()
+    assert f(None, 25, 1_000_000, ctypes.byref(L), ctypes.byref(nb), ctypes.byref(lv)) == 0
+    assert L.value % 64 == 0 and nb.value == -(-1_000_000 // L.value)
+    assert nb.value >= 1024  # enough independent segments to fill 256 CUs
+    n, levels = nb.value, 1
+    while n > 8:
+        n, levels = -(-n // 8), levels + 1
+    assert lv.value == levels
+    assert f(None, 81, 1000, ctypes.byref(L), ctypes.byref(nb), ctypes.byref(lv)) == -2
+    assert f(None, 0, 1000, ctypes.byref(L), ctypes.byref(nb), ctypes.byref(lv)) == -1
+    assert f(None, 3, 0, ctypes.byref(L), ctypes.byref(nb), ctypes.byref(lv)) == 0 and nb.value == 0
+
+
+def test_context_needs_a_device(lib):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    lib.hmm_ctx_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int]
+    h = ctypes.c_void_p()
+    assert lib.hmm_ctx_create(ctypes.byref(h), 0) == -3
+
+
+def test_binding_fails_loudly_without_library(tmp_path):
+    """The binding has no CPU fallback: without libhmm.so its import raises."""
+    import shutil
+    pkg = tmp_path / "paper_2003_03508_amd"
+    pkg.mkdir()
+    for f in ("__init__.py", "binding.py"):
+        shutil.copy(os.path.join(ROOT, "paper_2003_03508_amd", f), pkg / f)
+    r = subprocess.run(["python", "-c", "import paper_2003_03508_amd.binding"], cwd=tmp_path,
+                       capture_output=True, text=True)
+    assert r.returncode != 0 and "libhmm.so" in r.stderr
