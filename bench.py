@@ -1,0 +1,152 @@
+"""Throughput of the HMM forward log-likelihood on one MI355X.
+
+Workload: K = 25 hidden states, T = 1,000,000 observations, one parameter set
+(synthetic tremor-shaped data, seed 1).  One step = one full evaluation of
+ln L (eq. 2) with the blocked FP32 MFMA path: parameter preparation, fused
+emission + segment products, and the combination tree down to ln L.  Inputs
+are resident in HBM before timing starts.
+
+Reported beside it: the plain forward recursion (Algorithm 1) on the GPU, the
+error of both against the FP64 CPU oracle, the roofline position of the
+dominant kernel (segment products; algorithmic flops 2*K^3 per observation,
+FP32 MFMA peak), and the oracle's own throughput on the host cores.
+
+    python bench.py [--gpus 1] [--steps 200] [--warmup 10]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_FP32_MFMA_TFLOPS = 157.3  # MI355X dense FP32 matrix peak
+PEAK_HBM_GBS = 8000.0
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--serial-steps", type=int, default=3)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="approximate wall time of the CPU-oracle sample")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle leg")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for {args.gpus}); this build has no "
+              "multi-GPU path.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2003_03508_amd import binding, synth
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+
+    wl = synth.WORKLOADS["k25_t1e6"]
+    K, T = wl["K"], wl["T"]
+    prm, obs = synth.make(**wl)
+    dev = torch.device("cuda:0")
+    d = binding.to_device(prm, obs, dev)
+    ctx = binding.Context(0)
+    plan = ctx.plan(K, T)
+    out = torch.empty(1, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+
+    # ---- blocked FP32 MFMA path: the measured step
+    for _ in range(args.warmup):
+        ctx.loglik(**d, algo="blocked_f32", out=out)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.loglik(**d, algo="blocked_f32", out=out)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    launches, kern_ms = ctx.profile_read()
+    ctx.profile(False)
+    ll_blocked = float(out.item())
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    evals_per_s = args.steps / (t1 - t0)
+    kern_avg_ms = kern_ms / max(launches, 1)
+
+    # ---- plain forward recursion on the GPU (the comparison path)
+    ctx.loglik(**d, algo="serial_f32", out=out)
+    torch.cuda.synchronize()
+    s0 = time.perf_counter()
+    for _ in range(args.serial_steps):
+        ctx.loglik(**d, algo="serial_f32", out=out)
+    torch.cuda.synchronize()
+    s1 = time.perf_counter()
+    ll_serial = float(out.item())
+    serial_evals_per_s = args.serial_steps / (s1 - s0)
+
+    # ---- roofline of the dominant kernel (segment products)
+    flops = 2.0 * T * K ** 3                 # algorithmic, unpadded
+    achieved_tflops = flops / (kern_avg_ms * 1e-3) / 1e12
+    roofline = {"bound": "mfma", "achieved": round(achieved_tflops, 3),
+                "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved_tflops / PEAK_FP32_MFMA_TFLOPS, 4), "traffic": None,
+                "kernel": "k_blocked<32,1>", "kernel_avg_ms": round(kern_avg_ms, 5),
+                "launches_timed": launches, "flops_per_launch": flops}
+
+    # ---- CPU oracle on the host (reference value and baseline throughput)
+    cpu = None
+    ll_oracle = None
+    if not args.no_cpu:
+        import oracle
+        oracle.build(force=False)
+        n = 0
+        c0 = time.perf_counter()
+        while True:
+            ll_oracle = oracle.loglik(prm.delta, prm.Gamma, prm.p, prm.mu, prm.Sigma, obs.flag, obs.xy)
+            n += 1
+            if time.perf_counter() - c0 >= args.cpu_seconds:
+                break
+        c1 = time.perf_counter()
+        cpu = {"value": round(n / (c1 - c0), 4), "unit": "evals/s", "cores": 1, "kind": "oracle",
+               "sample": f"{n} full evaluations of the same K=25, T=1e6 workload, single thread, "
+                         f"FP64 C oracle, {c1 - c0:.1f} s"}
+
+    def rel(x):
+        return None if ll_oracle is None else abs(x - ll_oracle) / abs(ll_oracle)
+
+    rec = {
+        "metric": "HMM log-lik evals/s at K=25,T=1e6 vs plain forward; MCMC ESS/s",
+        "value": round(evals_per_s, 3),
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "k25_t1e6: tremor HMM, K=25 states, T=1,000,000 observations, "
+                               "seed 1, one parameter set, blocked FP32 MFMA path",
+                   "K": K, "T": T, "algo": "blocked_f32", "block_len": plan["block_len"],
+                   "n_blocks": plan["n_blocks"], "fold_levels": plan["levels"]},
+        "plain_forward": {"value": round(serial_evals_per_s, 4), "unit": "evals/s",
+                          "steps": args.serial_steps, "algo": "serial_f32"},
+        "speedup_vs_plain_forward": round(evals_per_s / serial_evals_per_s, 2),
+        "loglik": ll_blocked,
+        "rel_err_vs_oracle": {"blocked_f32": rel(ll_blocked), "serial_f32": rel(ll_serial)},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    ctx.close()
+    print(json.dumps(rec))
+
+
+if __name__ == "__main__":
+    main()

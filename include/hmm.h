@@ -36,12 +36,13 @@
  *     non-finite parameter) or invalid data (a flag other than 0/1, a tremor
  *     with a non-finite location); -inf when L = 0 with valid inputs.
  *     T = 0 gives ln(sum_k delta_k), the empty chain of eq. (2).
- *   - Numerics of the GPU paths: emissions are formed in FP32 (locations are
- *     differenced from the means in FP64 first) relative to each step's
- *     largest emission, whose power-of-two exponent is carried exactly as an
- *     integer; products accumulate in FP32; only the final combination of
- *     exponents and the logarithm are FP64.  A state whose emission falls
- *     below 2^-149 of the step's largest one counts as zero.
+ *   - Numerics of the GPU paths: log2 e_{t,k} is evaluated in FP64, shifted
+ *     by the integer s_t = floor(max_k log2 e_{t,k}) (carried exactly), and
+ *     exponentiated as 2^n * 2^f with n an integer and only f in [0, 1)
+ *     rounded to FP32; products accumulate in FP32 with exact power-of-two
+ *     rescaling; the final combination of exponents and the logarithm are
+ *     FP64.  A state whose emission falls below 2^-149 of the step's largest
+ *     one counts as zero.
  */
 #ifndef HMM_MI355X_H
 #define HMM_MI355X_H
@@ -118,6 +119,15 @@ int hmm_ctx_set_blocking(hmm_ctx *ctx, int64_t block_len, int32_t fold);
  * NULL for the default knobs. */
 int hmm_blocked_plan(hmm_ctx *ctx, int32_t K, int64_t T, int64_t *block_len,
                      int64_t *n_blocks, int32_t *levels);
+
+/* Kernel timing for measurement.  While enabled (on != 0), every blocked
+ * call records a pair of HIP events on its stream around its segment-product
+ * kernel (the dominant kernel of HMM_BLOCKED_*).  hmm_ctx_profile_read waits
+ * for the recorded events, returns the number of timed launches and their
+ * summed duration in milliseconds, and forgets them.  At most 65536 launches
+ * are kept; later ones are not timed.  Enabling or disabling also forgets. */
+int hmm_ctx_profile(hmm_ctx *ctx, int32_t on);
+int hmm_ctx_profile_read(hmm_ctx *ctx, int64_t *launches, double *total_ms);
 
 /* Human-readable name of a status code (static storage). */
 const char *hmm_status_string(int status);

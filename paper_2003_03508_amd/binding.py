@@ -41,10 +41,12 @@ _lib.hmm_emission.argtypes = [_vp, _i32, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp
 _lib.hmm_ctx_set_blocking.argtypes = [_vp, _i64, _i32]
 _lib.hmm_blocked_plan.argtypes = [_vp, _i32, _i64, ctypes.POINTER(_i64), ctypes.POINTER(_i64),
                                   ctypes.POINTER(_i32)]
+_lib.hmm_ctx_profile.argtypes = [_vp, _i32]
+_lib.hmm_ctx_profile_read.argtypes = [_vp, ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_double)]
 _lib.hmm_status_string.restype = ctypes.c_char_p
 _lib.hmm_status_string.argtypes = [ctypes.c_int]
 for _f in ("hmm_ctx_create", "hmm_ctx_destroy", "hmm_loglik", "hmm_emission",
-           "hmm_ctx_set_blocking", "hmm_blocked_plan"):
+           "hmm_ctx_set_blocking", "hmm_blocked_plan", "hmm_ctx_profile", "hmm_ctx_profile_read"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 
@@ -111,6 +113,16 @@ class Context:
         _check("hmm_blocked_plan", _lib.hmm_blocked_plan(self._h, int(K), int(T), ctypes.byref(L),
                                                          ctypes.byref(nb), ctypes.byref(lv)))
         return dict(block_len=L.value, n_blocks=nb.value, levels=lv.value)
+
+    def profile(self, on=True):
+        """Time the segment-product kernel of blocked calls with HIP events."""
+        _check("hmm_ctx_profile", _lib.hmm_ctx_profile(self._h, 1 if on else 0))
+
+    def profile_read(self):
+        """(launches, total_ms) of the kernel timed since the last read."""
+        n, ms = _i64(), ctypes.c_double()
+        _check("hmm_ctx_profile_read", _lib.hmm_ctx_profile_read(self._h, ctypes.byref(n), ctypes.byref(ms)))
+        return n.value, ms.value
 
     def loglik(self, delta, Gamma, p, mu, Sigma, flag, xy, algo="blocked_f32", out=None,
                stream=None):

@@ -4,6 +4,8 @@
 #include <cstdint>
 #include <cstdlib>
 #include <new>
+#include <utility>
+#include <vector>
 
 #include <hip/hip_runtime.h>
 
@@ -18,12 +20,17 @@ struct hmm_ctx {
     size_t ws_bytes = 0;
     int64_t block_len = 0;  // 0 = automatic
     int32_t fold = 0;       // 0 = automatic
+    // measurement: event pairs around the segment-product kernel
+    bool profile = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+    size_t events_used = 0;
 };
 
 namespace {
 
 constexpr int64_t kMaxT = int64_t(1) << 40;
 constexpr size_t kAlign = 256;
+constexpr size_t kMaxTimed = 65536;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -162,11 +169,25 @@ int run_blocked(hmm_ctx *ctx, int K, const double *delta, int64_t T, const uint8
     int *status = at<int>(ws, ly.status);
     const StateConst *sc = at<StateConst>(ws, ly.sc);
     const float *gf = at<float>(ws, ly.gf);
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (ctx->profile && pl.nb > 0 && ctx->events_used < kMaxTimed) {
+        if (ctx->events_used == ctx->events.size()) {
+            hipEvent_t a, b;
+            if (hipEventCreate(&a) != hipSuccess) return HMM_E_DEVICE;
+            if (hipEventCreate(&b) != hipSuccess) return HMM_E_DEVICE;
+            ctx->events.emplace_back(a, b);
+        }
+        ev0 = ctx->events[ctx->events_used].first;
+        ev1 = ctx->events[ctx->events_used].second;
+        ++ctx->events_used;
+    }
+    if (ev0) (void)hipEventRecord(ev0, st);
     if (pl.nb > 0) {
         hipLaunchKernelGGL((k_blocked<S, MT>), dim3((unsigned)pl.nb), dim3(64), 0, st, K, T, pl.L, gf,
                            sc, flag, xy, at<float>(ws, ly.m0), at<long long>(ws, ly.e0),
                            at<long long>(ws, ly.s0), status);
     }
+    if (ev1) (void)hipEventRecord(ev1, st);
     // Fold levels: m0 -> m1 -> m2 -> m1 -> ... until one group remains.
     int64_t n = pl.nb;
     const float *mi = at<float>(ws, ly.m0);
@@ -235,9 +256,13 @@ int hmm_ctx_destroy(hmm_ctx *ctx)
     int rc = HMM_OK;
     {
         DeviceGuard dg(ctx->device);
-        if (ctx->ws) {
+        if (ctx->ws || !ctx->events.empty()) {
             if (hipDeviceSynchronize() != hipSuccess) rc = HMM_E_DEVICE;
-            (void)hipFree(ctx->ws);
+        }
+        if (ctx->ws) (void)hipFree(ctx->ws);
+        for (auto &e : ctx->events) {
+            (void)hipEventDestroy(e.first);
+            (void)hipEventDestroy(e.second);
         }
     }
     delete ctx;
@@ -351,6 +376,33 @@ int hmm_emission(hmm_ctx *ctx, int32_t K, const double *p, const double *mu, con
         }
     }
     return launch_status();
+}
+
+int hmm_ctx_profile(hmm_ctx *ctx, int32_t on)
+{
+    if (!ctx) return HMM_E_INVALID_ARG;
+    ctx->profile = on != 0;
+    ctx->events_used = 0;
+    return HMM_OK;
+}
+
+int hmm_ctx_profile_read(hmm_ctx *ctx, int64_t *launches, double *total_ms)
+{
+    if (!ctx || !launches || !total_ms) return HMM_E_INVALID_ARG;
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return HMM_E_DEVICE;
+    double sum = 0.0;
+    for (size_t i = 0; i < ctx->events_used; ++i) {
+        if (hipEventSynchronize(ctx->events[i].second) != hipSuccess) return HMM_E_DEVICE;
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, ctx->events[i].first, ctx->events[i].second) != hipSuccess)
+            return HMM_E_DEVICE;
+        sum += ms;
+    }
+    *launches = (int64_t)ctx->events_used;
+    *total_ms = sum;
+    ctx->events_used = 0;
+    return HMM_OK;
 }
 
 const char *hmm_status_string(int status)

@@ -23,9 +23,7 @@ constexpr int kWave = 64;
 // (cxx, cxy, cyy) = -log2(e)/2 * Sigma^{-1} (off-diagonal doubled).
 // Padding states (k >= K) carry a1 = a0 = -inf so their emission is zero.
 struct alignas(16) StateConst {
-    double mx, my;
-    float cxx, cxy, cyy, a1;
-    float a0, pad0, pad1, pad2;
+    double mx, my, cxx, cxy, cyy, a1, a0, pad;
 };
 
 // ---------------------------------------------------------------------------
@@ -134,10 +132,14 @@ __device__ __forceinline__ int fexp(float x) { return __builtin_amdgcn_frexp_exp
 //
 //  1. the chunk's flags and locations are read with coalesced loads (one
 //     observation per lane) and kept in LDS;
-//  2. lam[t][k] = log2 e_{t,k} for all (t, k) pairs of the chunk, FP32, after
-//     differencing the location from the mean in FP64;
-//  3. per observation, s_t = floor(max_k lam[t][k]) (an exact integer shift);
-//  4. E[t][k] = 2^(lam - s_t) in FP32, so max_k E[t][k] lies in [1, 2).
+//  2. lam[t][k] = log2 e_{t,k} for all (t, k) pairs of the chunk, evaluated in
+//     FP64 and kept in LDS rounded to FP32;
+//  3. per observation, s_t = floor(max_k lam[t][k]), an exact integer shift
+//     (any integer near the maximum keeps the scaled values in range);
+//  4. E[t][k] = e_{t,k} 2^(-s_t), recomputing lam in FP64 and splitting
+//     lam - s_t = n + f with n an integer and f in [0, 1):
+//     E = ldexp(exp2f(f), n).  Only f is rounded to FP32, so the relative
+//     error of E does not grow with |lam|.
 //
 // E is [kChunk][KP] in LDS; padding states and observations past the chunk
 // end get E = 0.  `ssum` accumulates the shifts of the observations this lane
@@ -150,6 +152,13 @@ struct ChunkLds {
     int of[kChunk];
     int sh[kChunk];
 };
+
+__device__ __forceinline__ double state_log2_emission(const StateConst &s, int f, double x, double y)
+{
+    if (f != 1) return s.a0;
+    const double d0 = x - s.mx, d1 = y - s.my;
+    return s.a1 + d0 * (s.cxx * d0 + s.cxy * d1) + s.cyy * (d1 * d1);
+}
 
 template <int KP>
 __device__ __forceinline__ void stage_emissions(int K, int64_t tc, int nst,
@@ -175,20 +184,11 @@ __device__ __forceinline__ void stage_emissions(int K, int64_t tc, int nst,
         cl.of[lane] = f;
     }
     __syncthreads();
-#pragma unroll 4
+#pragma unroll 2
     for (int pi = lane; pi < kChunk * KP; pi += kWave) {
         const int tl = pi / KP, k = pi % KP;
         float lam = -INFINITY;
-        if (tl < nst && k < K) {
-            const StateConst s = sc[k];
-            if (cl.of[tl] == 1) {
-                const float d0 = (float)(cl.ox[tl] - s.mx);
-                const float d1 = (float)(cl.oy[tl] - s.my);
-                lam = s.a1 + d0 * (s.cxx * d0 + s.cxy * d1) + s.cyy * (d1 * d1);
-            } else {
-                lam = s.a0;
-            }
-        }
+        if (tl < nst && k < K) lam = (float)state_log2_emission(sc[k], cl.of[tl], cl.ox[tl], cl.oy[tl]);
         E[pi] = lam;
     }
     __syncthreads();
@@ -202,10 +202,18 @@ __device__ __forceinline__ void stage_emissions(int K, int64_t tc, int nst,
         ssum += s;
     }
     __syncthreads();
-#pragma unroll 4
+#pragma unroll 2
     for (int pi = lane; pi < kChunk * KP; pi += kWave) {
-        const int tl = pi / KP;
-        E[pi] = exp2f(E[pi] - (float)cl.sh[tl]);
+        const int tl = pi / KP, k = pi % KP;
+        float e = 0.f;
+        if (tl < nst && k < K) {
+            const double r = state_log2_emission(sc[k], cl.of[tl], cl.ox[tl], cl.oy[tl]) - (double)cl.sh[tl];
+            if (r > -160.0) {
+                const double n = floor(r);
+                e = __builtin_amdgcn_ldexpf(exp2f((float)(r - n)), (int)n);
+            }
+        }
+        E[pi] = e;
     }
     __syncthreads();
 }

@@ -28,7 +28,7 @@ __device__ __forceinline__ int prepare_state(int k, int K, const double *__restr
 {
     int bad = 0;
     StateConst s;
-    s.pad0 = s.pad1 = s.pad2 = 0.f;
+    s.pad = 0.0;
     if (k < K) {
         const double pk = p[k], sxx = Sigma[3 * k], sxy = Sigma[3 * k + 1], syy = Sigma[3 * k + 2];
         const double mx = mu[2 * k], my = mu[2 * k + 1];
@@ -39,14 +39,14 @@ __device__ __forceinline__ int prepare_state(int k, int K, const double *__restr
             bad = 1;
         s.mx = mx;
         s.my = my;
-        s.cxx = (float)(-0.5 * kLog2E * syy / det);
-        s.cxy = (float)(kLog2E * sxy / det);
-        s.cyy = (float)(-0.5 * kLog2E * sxx / det);
-        s.a1 = (float)(log2(pk) - kLog2TwoPi - 0.5 * log2(det));
-        s.a0 = (float)(log1p(-pk) * kLog2E);
+        s.cxx = -0.5 * kLog2E * syy / det;
+        s.cxy = kLog2E * sxy / det;
+        s.cyy = -0.5 * kLog2E * sxx / det;
+        s.a1 = log2(pk) - kLog2TwoPi - 0.5 * log2(det);
+        s.a0 = log1p(-pk) * kLog2E;
     } else {
         s.mx = s.my = 0.0;
-        s.cxx = s.cxy = s.cyy = 0.f;
+        s.cxx = s.cxy = s.cyy = 0.0;
         s.a1 = s.a0 = -INFINITY;
     }
     sc[k] = s;

@@ -73,7 +73,8 @@ def test_emission_stage_matches_eq1(binding, ctx, K):
     live = rel_lam > -120
     got = np.log2(np.where(live, e_hat, 1.0))
     err = np.abs(got - rel_lam)[live]
-    tol = (4e-7 * (np.abs(lam) + 8.0))[live]
+    # only the fractional part of log2 e - s_t is rounded to FP32
+    tol = (3e-7 + 1e-14 * np.abs(lam))[live]
     assert np.all(err <= tol), float((err / tol).max())
     assert np.all(e_hat[rel_lam < -151] == 0.0)
 
