@@ -37,12 +37,14 @@
  *     with a non-finite location); -inf when L = 0 with valid inputs.
  *     T = 0 gives ln(sum_k delta_k), the empty chain of eq. (2).
  *   - Numerics of the GPU paths: log2 e_{t,k} is evaluated in FP64, shifted
- *     by the integer s_t = floor(max_k log2 e_{t,k}) (carried exactly), and
- *     exponentiated as 2^n * 2^f with n an integer and only f in [0, 1)
+ *     by the integer s_t = floor(max_k log2 e_{t,k}) - 96 (carried exactly),
+ *     and exponentiated as 2^n * 2^f with n an integer and only f in [0, 1)
  *     rounded to FP32; products accumulate in FP32 with exact power-of-two
  *     rescaling; the final combination of exponents and the logarithm are
- *     FP64.  A state whose emission falls below 2^-149 of the step's largest
- *     one counts as zero.
+ *     FP64.  An emission below 2^-222 of its step's largest one loses
+ *     precision (FP32 subnormal) and below 2^-245 counts as zero; the FP64
+ *     oracle's limit is 2^-1074.  With any transition matrix whose entries
+ *     are not tiny this cannot change ln L measurably.
  */
 #ifndef HMM_MI355X_H
 #define HMM_MI355X_H
@@ -100,8 +102,9 @@ int hmm_loglik(hmm_ctx *ctx, int32_t K, const double *delta, const double *Gamma
 
 /* The emission stage of the GPU paths (eq. 1) on its own, for inspection.
  * For every observation t it writes the integer shift s_t (shift[t]) and the
- * scaled emissions  e_hat[t*K + k] = e_{t,k} * 2^(-s_t)  in FP32, where s_t is
- * floor(log2 max_k e_{t,k}) (so the largest scaled emission lies in [1, 2)).
+ * scaled emissions  e_hat[t*K + k] = e_{t,k} * 2^(-s_t)  in FP32, where
+ * s_t = floor(log2 max_k e_{t,k}) - 96, so the largest scaled emission lies
+ * in [2^96, 2^97).
  * shift: device int32[T]; e_hat: device float[T*K].  status: device int32[1],
  * receives a bit mask (1 = invalid parameters, 2 = invalid data). */
 int hmm_emission(hmm_ctx *ctx, int32_t K, const double *p, const double *mu,

@@ -15,6 +15,12 @@ namespace hmm {
 constexpr int kChunk = 64;
 constexpr int kWave = 64;
 
+// Scaled emissions carry a bias of 2^kEmisBias: the largest one of a step lies
+// in [2^kEmisBias, 2^(kEmisBias+1)).  Emissions down to 2^-(126+kEmisBias) of
+// the step's largest stay normal FP32 numbers (full precision), and products
+// stay below 2^(kEmisBias+1) * 128 < 2^128.
+constexpr int kEmisBias = 96;
+
 // Per-state constants of eq. (1), prepared once per call from the FP64
 // parameters.  In log2 units:
 //   tremor:    log2 e = a1 + cxx*d0^2 + cxy*d0*d1 + cyy*d1^2,  d = x - mu
@@ -134,8 +140,9 @@ __device__ __forceinline__ int fexp(float x) { return __builtin_amdgcn_frexp_exp
 //     observation per lane) and kept in LDS;
 //  2. lam[t][k] = log2 e_{t,k} for all (t, k) pairs of the chunk, evaluated in
 //     FP64 and kept in LDS rounded to FP32;
-//  3. per observation, s_t = floor(max_k lam[t][k]), an exact integer shift
-//     (any integer near the maximum keeps the scaled values in range);
+//  3. per observation, s_t = floor(max_k lam[t][k]) - kEmisBias, an exact
+//     integer shift (any integer near that value keeps the scaled emissions
+//     in range);
 //  4. E[t][k] = e_{t,k} 2^(-s_t), recomputing lam in FP64 and splitting
 //     lam - s_t = n + f with n an integer and f in [0, 1):
 //     E = ldexp(exp2f(f), n).  Only f is rounded to FP32, so the relative
@@ -197,7 +204,7 @@ __device__ __forceinline__ void stage_emissions(int K, int64_t tc, int nst,
         const float *row = E + lane * KP;
         for (int k = 0; k < K; ++k) m = fmaxf(m, row[k]);
         int s = 0;
-        if (m > -1.0e9f && m < 1.0e9f) s = (int)floorf(m);
+        if (m > -1.0e9f && m < 1.0e9f) s = (int)floorf(m) - kEmisBias;
         cl.sh[lane] = s;
         ssum += s;
     }
