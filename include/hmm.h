@@ -112,9 +112,10 @@ int hmm_emission(hmm_ctx *ctx, int32_t K, const double *p, const double *mu,
                  void *stream, int32_t *shift, float *e_hat, int32_t *status);
 
 /* Tuning knobs of the blocked path.  block_len: observations per segment
- * (0 = automatic; otherwise >= 1).  fold: segment products folded per
- * wavefront at each level of the combination tree (0 = automatic; otherwise
- * 2..64).  They change the order of floating-point operations only. */
+ * (0 = automatic; otherwise >= 1).  fold: products a wavefront multiplies in
+ * sequence at each level of the combination tree before the workgroup's
+ * binary tree (0 = automatic; otherwise 1..64).  They change the order of
+ * floating-point operations only. */
 int hmm_ctx_set_blocking(hmm_ctx *ctx, int64_t block_len, int32_t fold);
 
 /* Segment length and tree shape the blocked path would use for (K, T):

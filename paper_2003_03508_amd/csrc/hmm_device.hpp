@@ -153,6 +153,16 @@ __device__ __forceinline__ int fexp(float x) { return __builtin_amdgcn_frexp_exp
 // handled; `bad` is set for invalid data (flag not 0/1, tremor with a
 // non-finite location).
 // ---------------------------------------------------------------------------
+// Wave-local LDS ordering (see stage_emissions): a wavefront's own LDS
+// writes become visible to all its lanes; no other wavefront takes part, so
+// wavefronts of one workgroup may run different numbers of chunks.
+__device__ __forceinline__ void wave_sync_lds()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
 struct ChunkLds {
     double ox[kChunk];
     double oy[kChunk];
@@ -190,7 +200,7 @@ __device__ __forceinline__ void stage_emissions(int K, int64_t tc, int nst,
         cl.oy[lane] = y;
         cl.of[lane] = f;
     }
-    __syncthreads();
+    wave_sync_lds();
 #pragma unroll 2
     for (int pi = lane; pi < kChunk * KP; pi += kWave) {
         const int tl = pi / KP, k = pi % KP;
@@ -198,7 +208,7 @@ __device__ __forceinline__ void stage_emissions(int K, int64_t tc, int nst,
         if (tl < nst && k < K) lam = (float)state_log2_emission(sc[k], cl.of[tl], cl.ox[tl], cl.oy[tl]);
         E[pi] = lam;
     }
-    __syncthreads();
+    wave_sync_lds();
     if (lane < nst) {
         float m = -INFINITY;
         const float *row = E + lane * KP;
@@ -208,7 +218,7 @@ __device__ __forceinline__ void stage_emissions(int K, int64_t tc, int nst,
         cl.sh[lane] = s;
         ssum += s;
     }
-    __syncthreads();
+    wave_sync_lds();
 #pragma unroll 2
     for (int pi = lane; pi < kChunk * KP; pi += kWave) {
         const int tl = pi / KP, k = pi % KP;
@@ -222,7 +232,7 @@ __device__ __forceinline__ void stage_emissions(int K, int64_t tc, int nst,
         }
         E[pi] = e;
     }
-    __syncthreads();
+    wave_sync_lds();
 }
 
 }  // namespace hmm

@@ -53,7 +53,7 @@ __device__ __forceinline__ int prepare_state(int k, int K, const double *__restr
     return bad;
 }
 
-__global__ __launch_bounds__(256) void k_prepare(int K, int KP, const double *__restrict__ delta,
+static __global__ __launch_bounds__(256) void k_prepare(int K, int KP, const double *__restrict__ delta,
                                                  const double *__restrict__ Gamma,
                                                  const double *__restrict__ p,
                                                  const double *__restrict__ mu,
@@ -85,7 +85,7 @@ __global__ __launch_bounds__(256) void k_prepare(int K, int KP, const double *__
 }
 
 // The state part of k_prepare alone (emission parameters only).
-__global__ __launch_bounds__(256) void k_prepare_states(int K, int KP, const double *__restrict__ p,
+static __global__ __launch_bounds__(256) void k_prepare_states(int K, int KP, const double *__restrict__ p,
                                                         const double *__restrict__ mu,
                                                         const double *__restrict__ Sigma,
                                                         StateConst *__restrict__ sc,
@@ -229,137 +229,140 @@ __global__ __launch_bounds__(64) void k_serial(int K, int64_t T, const double *_
     }
 }
 
-// ---------------------------------------------------------------------------
-// Segment products on the matrix cores (the paper's steps 1-3 with steps 1
-// and 2 fused into 3).  Workgroup b = one wavefront = observations
-// [b*L, min(T, (b+1)*L)).  It forms the segment product
-//     M_b = prod_t Gamma diag(e_t)
-// as its transpose N = M_b^T, N <- diag(e_hat_t) Gamma^T N, starting from the
-// identity.  Gamma^T is the fixed A operand, held in registers for the whole
-// segment; N lives in the accumulator layout, which is fed back as the next B
-// operand without leaving registers: the contraction order of every MFMA is
-// permuted so that lane group g contributes exactly the rows of N it holds
-// (register r of tile m is contraction row S*m + row_in_tile(g, r)), and A's
-// columns are loaded in the same permuted order.  After each step every
-// column of N (one start state) is divided by the power of two of its largest
-// entry; the exponents are kept per column.  Outputs:
-//   Mout[b][i][j] (KP x KP, row i = start state) = M~_b, the scaled product,
-//   Eout[b][i]    exponents, so M_b = 2^(Sout[b]) diag(2^Eout[b]) M~_b,
-//   Sout[b]       the segment's sum of per-observation shifts s_t.
-// ---------------------------------------------------------------------------
-template <int S, int MT>
-__global__ __launch_bounds__(64) void k_blocked(int K, int64_t T, int64_t L,
-                                                const float *__restrict__ GF,
-                                                const StateConst *__restrict__ sc,
-                                                const uint8_t *__restrict__ flag,
-                                                const double *__restrict__ xy,
-                                                float *__restrict__ Mout,
-                                                long long *__restrict__ Eout,
-                                                long long *__restrict__ Sout,
-                                                int *__restrict__ status)
+// ===========================================================================
+// Segment products and their combination (the paper's parallel plan).
+//
+// A running product is kept TRANSPOSED in accumulator layout: for tile
+// (m, n), register r of lane (c, g) holds
+//     N[S*m + row_in_tile(g, r)][S*n + c] = M[S*n + c][S*m + row_in_tile(g, r)],
+// i.e. lane (c, g) holds part of ROW S*n + c of the product M.  Each row of M
+// (one start state) carries its own power-of-two exponent ex[n] (the same on
+// the lanes that share the row), and a segment carries the exact sum of its
+// per-observation shifts s_t.  So a product stands for
+//     M = 2^ssum * diag(2^ex) * M~,   max_j M~[i][j] in [0.5, 1) (or row = 0).
+//
+// A step N <- X N on the matrix cores takes X as the A operand and N as the B
+// operand.  The contraction order of every MFMA is permuted so that lane
+// group g supplies exactly the rows of N it holds: "slot" j of the
+// contraction is tile row m_j = j / RS, register r_j = j % RS, and lane group
+// g supplies contraction index rho(j, g) = S*m_j + row_in_tile(g, r_j).  The
+// result of one step is therefore already in the layout the next step reads:
+// N never leaves registers.  Slots are ordered by their smallest row, so the
+// slots touching a real state form a prefix of NSL slots.
+// ===========================================================================
+template <int S>
+__host__ __device__ constexpr int rit(int g, int r)
 {
-    constexpr int KP = S * MT;
-    constexpr int RS = Tile<S>::RS;
-    constexpr int NSLOT = MT * RS;
+    return S == 16 ? 4 * g + r : 8 * (r >> 2) + 4 * g + (r & 3);
+}
+
+// Number of contraction slots (prefix) that touch one of the first K states.
+template <int S, int MT>
+__host__ __device__ constexpr int needed_slots(int K)
+{
+    constexpr int RS = S * S / 64;
+    int n = 0;
+    for (int j = 0; j < MT * RS; ++j)
+        if (S * (j / RS) + rit<S>(0, j % RS) < K) n = j + 1;
+    return n;
+}
+
+template <int S, int MT>
+struct Prod {
     typedef typename Tile<S>::acc_t acc_t;
-    __shared__ __attribute__((aligned(16))) float E[kChunk * KP];
-    __shared__ ChunkLds cl;
-
-    const int lane = threadIdx.x;
-    const int c = lane % S, g = lane / S;
-    const int64_t b = blockIdx.x;
-    const int64_t t0 = b * L;
-    const int64_t t1 = min(T, t0 + L);
-
-    // A operand: lane (i = c, g) of instruction (tile m, slot j) holds
-    // Gamma^T[S*m + i][rho(j, g)] = Gamma[rho(j, g)][S*m + i].
-    float A[MT][NSLOT];
-#pragma unroll
-    for (int m = 0; m < MT; ++m)
-#pragma unroll
-        for (int j = 0; j < NSLOT; ++j) {
-            const int rho = S * (j / RS) + row_in_tile<S>(g, j % RS);
-            A[m][j] = GF[rho * KP + S * m + c];
-        }
-
     acc_t B[MT][MT];
+    long long ex[MT];
+};
+
+template <int S, int MT>
+__device__ __forceinline__ void prod_identity(Prod<S, MT> &P)
+{
+    constexpr int RS = Tile<S>::RS;
+    const int lane = threadIdx.x & 63, c = lane % S, g = lane / S;
 #pragma unroll
     for (int m = 0; m < MT; ++m)
 #pragma unroll
         for (int n = 0; n < MT; ++n)
 #pragma unroll
-            for (int r = 0; r < RS; ++r)
-                B[m][n][r] = (S * m + row_in_tile<S>(g, r) == S * n + c) ? 1.f : 0.f;
-    int cexp[MT];
+            for (int r = 0; r < RS; ++r) P.B[m][n][r] = (S * m + rit<S>(g, r) == S * n + c) ? 1.f : 0.f;
 #pragma unroll
-    for (int n = 0; n < MT; ++n) cexp[n] = 0;
-    long long ssum = 0;
-    int bad = 0;
+    for (int n = 0; n < MT; ++n) P.ex[n] = 0;
+}
 
-    for (int64_t tc = t0; tc < t1; tc += kChunk) {
-        const int nst = (int)min((int64_t)kChunk, t1 - tc);
-        stage_emissions<KP>(K, tc, nst, flag, xy, sc, E, cl, ssum, bad);
-        for (int tl = 0; tl < nst; ++tl) {
-            float ev[MT][RS];
-#pragma unroll
-            for (int m = 0; m < MT; ++m)
-#pragma unroll
-                for (int r4 = 0; r4 < RS; r4 += 4) {
-                    const float4 q = *reinterpret_cast<const float4 *>(
-                        &E[tl * KP + S * m + row_in_tile<S>(g, r4)]);
-                    ev[m][r4 + 0] = q.x;
-                    ev[m][r4 + 1] = q.y;
-                    ev[m][r4 + 2] = q.z;
-                    ev[m][r4 + 3] = q.w;
-                }
-            acc_t C[MT][MT];
-#pragma unroll
-            for (int m = 0; m < MT; ++m) {
-                if (S * m >= K) continue;
-#pragma unroll
-                for (int n = 0; n < MT; ++n) {
-                    if (S * n >= K) continue;
-                    acc_t acc;
-#pragma unroll
-                    for (int r = 0; r < RS; ++r) acc[r] = 0.f;
-#pragma unroll
-                    for (int j = 0; j < NSLOT; ++j) {
-                        if (S * (j / RS) + row_in_tile<S>(0, j % RS) < K)
-                            acc = mfma<S>(A[m][j], B[j / RS][n][j % RS], acc);
-                    }
-                    C[m][n] = acc;
-                }
-            }
-#pragma unroll
-            for (int n = 0; n < MT; ++n) {
-                if (S * n >= K) continue;
-                float mx = 0.f;
-#pragma unroll
-                for (int m = 0; m < MT; ++m) {
-                    if (S * m >= K) continue;
-#pragma unroll
-                    for (int r = 0; r < RS; ++r) {
-                        const float v = C[m][n][r] * ev[m][r];
-                        C[m][n][r] = v;
-                        mx = fmaxf(mx, v);
-                    }
-                }
-                mx = column_max<S>(mx);
-                const int e = (mx > 0.f) ? fexp(mx) : 0;
-#pragma unroll
-                for (int m = 0; m < MT; ++m) {
-                    if (S * m >= K) continue;
-#pragma unroll
-                    for (int r = 0; r < RS; ++r) B[m][n][r] = __builtin_amdgcn_ldexpf(C[m][n][r], -e);
-                }
-                cexp[n] += e;
-            }
-        }
-        __syncthreads();
+// Maximum of a 64-bit value over the lanes sharing one output column.
+template <int S>
+__device__ __forceinline__ long long column_max_i64(long long x)
+{
+    long long o = __shfl_xor(x, 32);
+    x = o > x ? o : x;
+    if constexpr (S == 16) {
+        o = __shfl_xor(x, 16);
+        x = o > x ? o : x;
     }
+    return x;
+}
 
-    // Row (S*n + c) of M~_b is column (S*n + c) of N.
-    float *Mb = Mout + b * (int64_t)KP * KP;
+// Divide every column of C (times an optional per-row factor) by the power of
+// two of its largest entry and store it as the new product; exponents add up.
+template <int S, int MT, bool SCALE>
+__device__ __forceinline__ void renorm_columns(const typename Tile<S>::acc_t (&C)[MT][MT],
+                                               const float (&ev)[MT][Tile<S>::RS], Prod<S, MT> &P)
+{
+    constexpr int RS = Tile<S>::RS;
+#pragma unroll
+    for (int n = 0; n < MT; ++n) {
+        float v[MT][RS];
+        float mx = 0.f;
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+#pragma unroll
+            for (int r = 0; r < RS; ++r) {
+                v[m][r] = SCALE ? C[m][n][r] * ev[m][r] : C[m][n][r];
+                mx = fmaxf(mx, v[m][r]);
+            }
+        mx = column_max<S>(mx);
+        const int e = (mx > 0.f) ? fexp(mx) : 0;
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+#pragma unroll
+            for (int r = 0; r < RS; ++r) P.B[m][n][r] = __builtin_amdgcn_ldexpf(v[m][r], -e);
+        P.ex[n] += e;
+    }
+}
+
+// Per-wavefront LDS region: an emission chunk (or an exchanged product), the
+// exchanged product's row exponents and shift sum, and the chunk's data.
+__host__ __device__ constexpr int region_floats(int KP)
+{
+    return ((kChunk * KP > KP * KP) ? kChunk * KP : KP * KP) + 2 * KP + 4 + (int)(sizeof(ChunkLds) / 4);
+}
+__host__ __device__ constexpr int region_bytes(int KP) { return 4 * region_floats(KP); }
+
+// Wavefronts per workgroup: the segment kernel puts one segment on each SIMD
+// of a CU; the fold kernel uses as many as fit in 128 KiB of LDS (max 16).
+constexpr int kBlockedWaves = 4;
+__host__ __device__ constexpr int fold_waves(int KP)
+{
+    return (128 * 1024) / region_bytes(KP) > 16 ? 16 : (128 * 1024) / region_bytes(KP);
+}
+
+template <int KP>
+struct Region {
+    static constexpr int EF = (kChunk * KP > KP * KP) ? kChunk * KP : KP * KP;
+    static constexpr int floats = EF + 2 * KP + 4 + (int)(sizeof(ChunkLds) / 4);
+    __device__ static float *E(float *base) { return base; }
+    __device__ static long long *QE(float *base) { return reinterpret_cast<long long *>(base + EF); }
+    __device__ static long long *QS(float *base) { return reinterpret_cast<long long *>(base + EF + 2 * KP); }
+    __device__ static ChunkLds &CL(float *base) { return *reinterpret_cast<ChunkLds *>(base + EF + 2 * KP + 4); }
+};
+
+// Write P (row-major M~, row exponents, shift sum) into an LDS region.
+template <int S, int MT>
+__device__ __forceinline__ void prod_to_lds(const Prod<S, MT> &P, long long ssum, float *base)
+{
+    constexpr int KP = S * MT, RS = Tile<S>::RS;
+    const int lane = threadIdx.x & 63, c = lane % S, g = lane / S;
+    float *Q = Region<KP>::E(base);
 #pragma unroll
     for (int n = 0; n < MT; ++n) {
         const int row = S * n + c;
@@ -367,223 +370,292 @@ __global__ __launch_bounds__(64) void k_blocked(int K, int64_t T, int64_t L,
         for (int m = 0; m < MT; ++m)
 #pragma unroll
             for (int r4 = 0; r4 < RS; r4 += 4) {
-                float4 q;
-                const bool live = (S * m < K) && (S * n < K);
-                q.x = live ? B[m][n][r4 + 0] : 0.f;
-                q.y = live ? B[m][n][r4 + 1] : 0.f;
-                q.z = live ? B[m][n][r4 + 2] : 0.f;
-                q.w = live ? B[m][n][r4 + 3] : 0.f;
-                *reinterpret_cast<float4 *>(&Mb[row * KP + S * m + row_in_tile<S>(g, r4)]) = q;
+                const float4 q = {P.B[m][n][r4], P.B[m][n][r4 + 1], P.B[m][n][r4 + 2], P.B[m][n][r4 + 3]};
+                *reinterpret_cast<float4 *>(&Q[row * KP + S * m + rit<S>(g, r4)]) = q;
             }
-        if (g == 0) Eout[b * KP + row] = cexp[n];
+        if (g == 0) Region<KP>::QE(base)[row] = P.ex[n];
     }
-    const long long stot = wave_sum_i64(ssum);
-    if (lane == 0) Sout[b] = stot;
-    if (__any(bad) && lane == 0) atomicOr(status, kBadData);
+    if (lane == 0) *Region<KP>::QS(base) = ssum;
 }
 
-// ---------------------------------------------------------------------------
-// Combination of segment products, left to right within groups of G:
-// workgroup q folds inputs [q*G, min(n_in, (q+1)*G)) into
-//     P <- P * Q_next   (each with its exponent vectors),
-// on the matrix cores, as P^T <- Q^T P^T: P^T stays in accumulator layout
-// (lane (c, g) holds row c of P) and Q is staged through LDS and read as the
-// A operand.  Before each product, row c of P is rescaled so that
-//     P~[c][r] * 2^(eQ[r] - beta_c),  beta_c = max_r (eQ[r] + exponent(P~[c][r])),
-// which keeps the dominant term of every row in range whatever the exponent
-// spread; row c of P then gains 2^beta_c.  With `final_` set there is one
-// group and the workgroup finishes the likelihood:
-//     ln L = ln2 * (S + max) + ln( sum_c delta_c 2^(eP[c] - max) sum_j P~[c][j] ).
-// n_in == 0 (T = 0) folds nothing: P = I.
-// ---------------------------------------------------------------------------
+// Same, to global memory (row-major KP x KP, exponents, shift sum).
 template <int S, int MT>
-__global__ __launch_bounds__(64) void k_fold(int K, int n_in, int G,
-                                             const float *__restrict__ Min,
-                                             const long long *__restrict__ Ein,
-                                             const long long *__restrict__ Sin,
-                                             float *__restrict__ Mout,
-                                             long long *__restrict__ Eout,
-                                             long long *__restrict__ Sout, int final_,
-                                             const double *__restrict__ delta,
-                                             const int *__restrict__ status,
-                                             double *__restrict__ out)
+__device__ __forceinline__ void prod_to_global(const Prod<S, MT> &P, long long ssum, float *M,
+                                               long long *E, long long *Ssum)
 {
-    constexpr int KP = S * MT;
-    constexpr int RS = Tile<S>::RS;
-    constexpr int NSLOT = MT * RS;
-    typedef typename Tile<S>::acc_t acc_t;
-    __shared__ __attribute__((aligned(16))) float Q[KP * KP];
-    __shared__ long long QE[KP];
-
-    const int lane = threadIdx.x;
-    const int c = lane % S, g = lane / S;
-    const int g0 = blockIdx.x * G;
-    const int g1 = min(n_in, g0 + G);
-
-    acc_t B[MT][MT];
-    long long pexp[MT];
-    long long ssum = 0;
-    if (g1 > g0) {
-        const float *P0 = Min + (int64_t)g0 * KP * KP;
+    constexpr int KP = S * MT, RS = Tile<S>::RS;
+    const int lane = threadIdx.x & 63, c = lane % S, g = lane / S;
 #pragma unroll
-        for (int n = 0; n < MT; ++n) {
-            const int row = S * n + c;
-#pragma unroll
-            for (int m = 0; m < MT; ++m)
-#pragma unroll
-                for (int r4 = 0; r4 < RS; r4 += 4) {
-                    const float4 q = *reinterpret_cast<const float4 *>(
-                        &P0[row * KP + S * m + row_in_tile<S>(g, r4)]);
-                    B[m][n][r4 + 0] = q.x;
-                    B[m][n][r4 + 1] = q.y;
-                    B[m][n][r4 + 2] = q.z;
-                    B[m][n][r4 + 3] = q.w;
-                }
-            pexp[n] = Ein[(int64_t)g0 * KP + row];
-        }
-        ssum = Sin[g0];
-    } else {
+    for (int n = 0; n < MT; ++n) {
+        const int row = S * n + c;
 #pragma unroll
         for (int m = 0; m < MT; ++m)
 #pragma unroll
-            for (int n = 0; n < MT; ++n)
-#pragma unroll
-                for (int r = 0; r < RS; ++r)
-                    B[m][n][r] = (S * m + row_in_tile<S>(g, r) == S * n + c) ? 1.f : 0.f;
-#pragma unroll
-        for (int n = 0; n < MT; ++n) pexp[n] = 0;
+            for (int r4 = 0; r4 < RS; r4 += 4) {
+                const float4 q = {P.B[m][n][r4], P.B[m][n][r4 + 1], P.B[m][n][r4 + 2], P.B[m][n][r4 + 3]};
+                *reinterpret_cast<float4 *>(&M[row * KP + S * m + rit<S>(g, r4)]) = q;
+            }
+        if (g == 0) E[row] = P.ex[n];
     }
+    if (lane == 0) *Ssum = ssum;
+}
 
-    for (int q = g0 + 1; q < g1; ++q) {
-        __syncthreads();
-        const float4 *src = reinterpret_cast<const float4 *>(Min + (int64_t)q * KP * KP);
-        for (int idx = lane; idx < KP * KP / 4; idx += kWave) reinterpret_cast<float4 *>(Q)[idx] = src[idx];
-        for (int idx = lane; idx < KP; idx += kWave) QE[idx] = Ein[(int64_t)q * KP + idx];
-        ssum += Sin[q];
-        __syncthreads();
-
-        // Per-row rescaling of P against Q's row exponents.
+template <int S, int MT>
+__device__ __forceinline__ void prod_from_global(Prod<S, MT> &P, long long &ssum, const float *M,
+                                                 const long long *E, const long long *Ssum)
+{
+    constexpr int KP = S * MT, RS = Tile<S>::RS;
+    const int lane = threadIdx.x & 63, c = lane % S, g = lane / S;
 #pragma unroll
-        for (int n = 0; n < MT; ++n) {
-            if (S * n >= K) continue;
-            long long beta = LLONG_MIN;
+    for (int n = 0; n < MT; ++n) {
+        const int row = S * n + c;
 #pragma unroll
-            for (int m = 0; m < MT; ++m) {
-                if (S * m >= K) continue;
+        for (int m = 0; m < MT; ++m)
 #pragma unroll
-                for (int r = 0; r < RS; ++r) {
-                    const float v = B[m][n][r];
-                    const long long t = QE[S * m + row_in_tile<S>(g, r)] + fexp(v);
-                    if (v > 0.f && t > beta) beta = t;
-                }
+            for (int r4 = 0; r4 < RS; r4 += 4) {
+                const float4 q = *reinterpret_cast<const float4 *>(&M[row * KP + S * m + rit<S>(g, r4)]);
+                P.B[m][n][r4] = q.x;
+                P.B[m][n][r4 + 1] = q.y;
+                P.B[m][n][r4 + 2] = q.z;
+                P.B[m][n][r4 + 3] = q.w;
             }
-            {
-                long long o = __shfl_xor(beta, 32);
-                beta = o > beta ? o : beta;
-                if constexpr (S == 16) {
-                    o = __shfl_xor(beta, 16);
-                    beta = o > beta ? o : beta;
-                }
-            }
-            if (beta != LLONG_MIN) {
-#pragma unroll
-                for (int m = 0; m < MT; ++m) {
-                    if (S * m >= K) continue;
-#pragma unroll
-                    for (int r = 0; r < RS; ++r) {
-                        long long d = QE[S * m + row_in_tile<S>(g, r)] - beta;
-                        if (d < -400) d = -400;
-                        B[m][n][r] = __builtin_amdgcn_ldexpf(B[m][n][r], (int)d);
-                    }
-                }
-                pexp[n] += beta;
-            }
-        }
-
-        acc_t C[MT][MT];
-#pragma unroll
-        for (int m = 0; m < MT; ++m) {
-            if (S * m >= K) continue;
-#pragma unroll
-            for (int n = 0; n < MT; ++n) {
-                if (S * n >= K) continue;
-                acc_t acc;
-#pragma unroll
-                for (int r = 0; r < RS; ++r) acc[r] = 0.f;
-#pragma unroll
-                for (int j = 0; j < NSLOT; ++j) {
-                    if (S * (j / RS) + row_in_tile<S>(0, j % RS) < K) {
-                        const int rho = S * (j / RS) + row_in_tile<S>(g, j % RS);
-                        acc = mfma<S>(Q[rho * KP + S * m + c], B[j / RS][n][j % RS], acc);
-                    }
-                }
-                C[m][n] = acc;
-            }
-        }
-#pragma unroll
-        for (int n = 0; n < MT; ++n) {
-            if (S * n >= K) continue;
-            float mx = 0.f;
-#pragma unroll
-            for (int m = 0; m < MT; ++m) {
-                if (S * m >= K) continue;
-#pragma unroll
-                for (int r = 0; r < RS; ++r) mx = fmaxf(mx, C[m][n][r]);
-            }
-            mx = column_max<S>(mx);
-            const int e = (mx > 0.f) ? fexp(mx) : 0;
-#pragma unroll
-            for (int m = 0; m < MT; ++m) {
-                if (S * m >= K) continue;
-#pragma unroll
-                for (int r = 0; r < RS; ++r) B[m][n][r] = __builtin_amdgcn_ldexpf(C[m][n][r], -e);
-            }
-            pexp[n] += e;
-        }
+        P.ex[n] = E[row];
     }
+    ssum = *Ssum;
+}
 
-    if (!final_) {
-        float *Pb = Mout + (int64_t)blockIdx.x * KP * KP;
+// P <- P * Q with Q = 2^QS diag(2^QE) Q~ read from an LDS region.  Row c of
+// P is first rescaled against Q's row exponents,
+//     P~[c][r] <- P~[c][r] * 2^(QE[r] - beta_c),  beta_c = max_r (QE[r] + exponent(P~[c][r])),
+// so that the dominant term of every row stays in range whatever the spread
+// of exponents; then P^T <- Q~^T P^T on the matrix cores, and renormalise.
+template <int S, int MT, int NSL>
+__device__ __forceinline__ void combine_from_lds(Prod<S, MT> &P, long long &ssum, float *base)
+{
+    constexpr int KP = S * MT, RS = Tile<S>::RS;
+    typedef typename Tile<S>::acc_t acc_t;
+    const int lane = threadIdx.x & 63, c = lane % S, g = lane / S;
+    const float *Q = Region<KP>::E(base);
+    const long long *QE = Region<KP>::QE(base);
 #pragma unroll
-        for (int n = 0; n < MT; ++n) {
-            const int row = S * n + c;
+    for (int n = 0; n < MT; ++n) {
+        long long beta = LLONG_MIN;
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+#pragma unroll
+            for (int r = 0; r < RS; ++r) {
+                const float v = P.B[m][n][r];
+                const long long t = QE[S * m + rit<S>(g, r)] + fexp(v);
+                if (v > 0.f && t > beta) beta = t;
+            }
+        beta = column_max_i64<S>(beta);
+        if (beta != LLONG_MIN) {
 #pragma unroll
             for (int m = 0; m < MT; ++m)
 #pragma unroll
-                for (int r4 = 0; r4 < RS; r4 += 4) {
-                    float4 q;
-                    const bool live = (S * m < K) && (S * n < K);
-                    q.x = live ? B[m][n][r4 + 0] : 0.f;
-                    q.y = live ? B[m][n][r4 + 1] : 0.f;
-                    q.z = live ? B[m][n][r4 + 2] : 0.f;
-                    q.w = live ? B[m][n][r4 + 3] : 0.f;
-                    *reinterpret_cast<float4 *>(&Pb[row * KP + S * m + row_in_tile<S>(g, r4)]) = q;
+                for (int r = 0; r < RS; ++r) {
+                    long long d = QE[S * m + rit<S>(g, r)] - beta;
+                    if (d < -400) d = -400;
+                    P.B[m][n][r] = __builtin_amdgcn_ldexpf(P.B[m][n][r], (int)d);
                 }
-            if (g == 0) Eout[(int64_t)blockIdx.x * KP + row] = pexp[n];
+            P.ex[n] += beta;
         }
-        if (lane == 0) Sout[blockIdx.x] = ssum;
+    }
+    acc_t C[MT][MT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int n = 0; n < MT; ++n) {
+            acc_t acc;
+#pragma unroll
+            for (int r = 0; r < RS; ++r) acc[r] = 0.f;
+#pragma unroll
+            for (int j = 0; j < NSL; ++j) {
+                const int rho = S * (j / RS) + rit<S>(g, j % RS);
+                acc = mfma<S>(Q[rho * KP + S * m + c], P.B[j / RS][n][j % RS], acc);
+            }
+            C[m][n] = acc;
+        }
+    const float dummy[MT][RS] = {};
+    renorm_columns<S, MT, false>(C, dummy, P);
+    ssum += *Region<KP>::QS(base);
+}
+
+// Binary tree over the W wavefronts of a workgroup: wave w ends up holding
+// the ordered product of the waves [w, w + 2^k) after round k.  Every wave
+// takes part in every barrier.
+template <int S, int MT, int NSL>
+__device__ __forceinline__ void workgroup_tree(Prod<S, MT> &P, long long &ssum, float *smem, int region)
+{
+    const int W = blockDim.x >> 6, w = threadIdx.x >> 6;
+    for (int stride = 1; stride < W; stride <<= 1) {
+        const int pos = w % (2 * stride);
+        if (pos == stride) prod_to_lds<S, MT>(P, ssum, smem + w * region);
+        __syncthreads();
+        if (pos == 0 && w + stride < W) combine_from_lds<S, MT, NSL>(P, ssum, smem + (w + stride) * region);
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Segment products on the matrix cores, emissions fused (the paper's steps 1
+// to 3 in one kernel).  Wavefront w of workgroup q owns segment
+// b = q*W + w, observations [b*L, min(T, (b+1)*L)), and forms
+//     M_b = prod_t Gamma diag(e_t)
+// as N = M_b^T, N <- diag(e_hat_t) Gamma^T N from the identity.  Gamma^T is
+// the A operand, loaded once into registers in the permuted contraction
+// order; N is the B operand and never leaves registers.  After each step
+// every column of N (start state) is renormalised by a power of two.  At the
+// end the workgroup multiplies its W segment products in order (tree in LDS)
+// and writes one product: Mout[q] (KP x KP row-major), Eout[q][KP], Sout[q].
+// ---------------------------------------------------------------------------
+template <int S, int MT, int NSL>
+__global__ __launch_bounds__(64 * kBlockedWaves) void k_blocked(int K, int64_t T, int64_t L, int64_t nb,
+                                                 const float *__restrict__ GF,
+                                                 const StateConst *__restrict__ sc,
+                                                 const uint8_t *__restrict__ flag,
+                                                 const double *__restrict__ xy,
+                                                 float *__restrict__ Mout,
+                                                 long long *__restrict__ Eout,
+                                                 long long *__restrict__ Sout,
+                                                 int *__restrict__ status)
+{
+    constexpr int KP = S * MT, RS = Tile<S>::RS;
+    typedef typename Tile<S>::acc_t acc_t;
+    extern __shared__ __attribute__((aligned(16))) float smem[];
+    constexpr int region = Region<KP>::floats;
+
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int c = lane % S, g = lane / S;
+    const int W = blockDim.x >> 6;
+    const int64_t b = (int64_t)blockIdx.x * W + w;
+    float *base = smem + w * region;
+    float *E = Region<KP>::E(base);
+    ChunkLds &cl = Region<KP>::CL(base);
+
+    Prod<S, MT> P;
+    prod_identity<S, MT>(P);
+    long long ssum = 0;
+    int bad = 0;
+
+    if (b < nb) {
+        const int64_t t0 = b * L;
+        const int64_t t1 = min(T, t0 + L);
+        float A[MT][NSL];
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+#pragma unroll
+            for (int j = 0; j < NSL; ++j) {
+                const int rho = S * (j / RS) + rit<S>(g, j % RS);
+                A[m][j] = GF[rho * KP + S * m + c];
+            }
+        for (int64_t tc = t0; tc < t1; tc += kChunk) {
+            const int nst = (int)min((int64_t)kChunk, t1 - tc);
+            stage_emissions<KP>(K, tc, nst, flag, xy, sc, E, cl, ssum, bad);
+            for (int tl = 0; tl < nst; ++tl) {
+                float ev[MT][RS];
+#pragma unroll
+                for (int m = 0; m < MT; ++m)
+#pragma unroll
+                    for (int r4 = 0; r4 < RS; r4 += 4) {
+                        const float4 q = *reinterpret_cast<const float4 *>(&E[tl * KP + S * m + rit<S>(g, r4)]);
+                        ev[m][r4] = q.x;
+                        ev[m][r4 + 1] = q.y;
+                        ev[m][r4 + 2] = q.z;
+                        ev[m][r4 + 3] = q.w;
+                    }
+                acc_t C[MT][MT];
+#pragma unroll
+                for (int m = 0; m < MT; ++m)
+#pragma unroll
+                    for (int n = 0; n < MT; ++n) {
+                        acc_t acc;
+#pragma unroll
+                        for (int r = 0; r < RS; ++r) acc[r] = 0.f;
+#pragma unroll
+                        for (int j = 0; j < NSL; ++j) acc = mfma<S>(A[m][j], P.B[j / RS][n][j % RS], acc);
+                        C[m][n] = acc;
+                    }
+                renorm_columns<S, MT, true>(C, ev, P);
+            }
+            wave_sync_lds();
+        }
+    }
+    if (__any(bad) && lane == 0) atomicOr(status, kBadData);
+    workgroup_tree<S, MT, NSL>(P, ssum, smem, region);
+    if (w == 0)
+        prod_to_global<S, MT>(P, ssum, Mout + (int64_t)blockIdx.x * KP * KP,
+                              Eout + (int64_t)blockIdx.x * KP, Sout + blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// Combination of products: workgroup q of W wavefronts takes inputs
+// [q*F*W, (q+1)*F*W); wave w folds its F consecutive inputs left to right
+// (each next input staged through its LDS region), then the workgroup tree
+// multiplies the W partial products in order.  Missing inputs are identities.
+// With final_ set there is a single workgroup and wave 0 finishes
+//     ln L = ln2*(ssum + e_max) + ln( sum_c delta_c 2^(ex_c - e_max) sum_j M~[c][j] ).
+// ---------------------------------------------------------------------------
+template <int S, int MT, int NSL>
+__global__ __launch_bounds__(64 * fold_waves(S * MT)) void k_fold(int K, int64_t n_in, int F,
+                                               const float *__restrict__ Min,
+                                               const long long *__restrict__ Ein,
+                                               const long long *__restrict__ Sin,
+                                               float *__restrict__ Mout,
+                                               long long *__restrict__ Eout,
+                                               long long *__restrict__ Sout, int final_,
+                                               const double *__restrict__ delta,
+                                               const int *__restrict__ status,
+                                               double *__restrict__ out)
+{
+    constexpr int KP = S * MT, RS = Tile<S>::RS;
+    extern __shared__ __attribute__((aligned(16))) float smem[];
+    constexpr int region = Region<KP>::floats;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int c = lane % S, g = lane / S;
+    const int W = blockDim.x >> 6;
+    float *base = smem + w * region;
+
+    Prod<S, MT> P;
+    long long ssum = 0;
+    const int64_t i0 = ((int64_t)blockIdx.x * W + w) * F;
+    const int64_t i1 = min(n_in, i0 + F);
+    if (i0 < i1) {
+        prod_from_global<S, MT>(P, ssum, Min + i0 * KP * KP, Ein + i0 * KP, Sin + i0);
+        for (int64_t i = i0 + 1; i < i1; ++i) {
+            const float4 *src = reinterpret_cast<const float4 *>(Min + i * KP * KP);
+            float4 *dst = reinterpret_cast<float4 *>(Region<KP>::E(base));
+            for (int idx = lane; idx < KP * KP / 4; idx += 64) dst[idx] = src[idx];
+            for (int idx = lane; idx < KP; idx += 64) Region<KP>::QE(base)[idx] = Ein[i * KP + idx];
+            if (lane == 0) *Region<KP>::QS(base) = Sin[i];
+            wave_sync_lds();
+            combine_from_lds<S, MT, NSL>(P, ssum, base);
+            wave_sync_lds();
+        }
+    } else {
+        prod_identity<S, MT>(P);
+    }
+    workgroup_tree<S, MT, NSL>(P, ssum, smem, region);
+    if (w != 0) return;
+    if (!final_) {
+        prod_to_global<S, MT>(P, ssum, Mout + (int64_t)blockIdx.x * KP * KP, Eout + (int64_t)blockIdx.x * KP,
+                              Sout + blockIdx.x);
         return;
     }
-
-    // Final: L = sum_c delta_c 2^(pexp_c) rowsum_c(P~) * 2^ssum.
     double term[MT];
     long long emax = LLONG_MIN;
 #pragma unroll
     for (int n = 0; n < MT; ++n) {
         double rs = 0.0;
-        if (S * n < K) {
 #pragma unroll
-            for (int m = 0; m < MT; ++m) {
-                if (S * m >= K) continue;
+        for (int m = 0; m < MT; ++m)
 #pragma unroll
-                for (int r = 0; r < RS; ++r) rs += (double)B[m][n][r];
-            }
-        }
+            for (int r = 0; r < RS; ++r) rs += (double)P.B[m][n][r];
         rs += __shfl_xor(rs, 32);
         if constexpr (S == 16) rs += __shfl_xor(rs, 16);
         const int row = S * n + c;
         term[n] = (row < K && g == 0) ? delta[row] * rs : 0.0;
-        if (term[n] > 0.0 && pexp[n] > emax) emax = pexp[n];
+        if (term[n] > 0.0 && P.ex[n] > emax) emax = P.ex[n];
     }
     emax = wave_max_i64(emax);
     double part = 0.0;
@@ -591,7 +663,7 @@ __global__ __launch_bounds__(64) void k_fold(int K, int n_in, int G,
 #pragma unroll
         for (int n = 0; n < MT; ++n) {
             if (term[n] > 0.0) {
-                long long d = pexp[n] - emax;
+                long long d = P.ex[n] - emax;
                 if (d < -2000) d = -2000;
                 part += ldexp(term[n], (int)d);
             }
