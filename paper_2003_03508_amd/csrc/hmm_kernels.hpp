@@ -582,6 +582,8 @@ __global__ __launch_bounds__(64 * kBlockedWaves) void k_blocked(int K, int64_t T
         }
     }
     if (__any(bad) && lane == 0) atomicOr(status, kBadData);
+    // each lane summed the shifts of the observations it staged
+    ssum = wave_sum_i64(ssum);
     workgroup_tree<S, MT, NSL>(P, ssum, smem, region);
     if (w == 0)
         prod_to_global<S, MT>(P, ssum, Mout + (int64_t)blockIdx.x * KP * KP,
