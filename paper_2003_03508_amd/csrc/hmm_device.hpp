@@ -135,27 +135,29 @@ __device__ __forceinline__ int fexp(float x) { return __builtin_amdgcn_frexp_exp
 
 // ---------------------------------------------------------------------------
 // Fused emission stage (eq. 1) for one chunk of up to kChunk observations.
+// Lane t of the wavefront owns observation tc + t:
 //
-//  1. the chunk's flags and locations are read with coalesced loads (one
-//     observation per lane) and kept in LDS;
-//  2. lam[t][k] = log2 e_{t,k} for all (t, k) pairs of the chunk, evaluated in
-//     FP64 and kept in LDS rounded to FP32;
-//  3. per observation, s_t = floor(max_k lam[t][k]) - kEmisBias, an exact
-//     integer shift (any integer near that value keeps the scaled emissions
-//     in range);
-//  4. E[t][k] = e_{t,k} 2^(-s_t), recomputing lam in FP64 and splitting
-//     lam - s_t = n + f with n an integer and f in [0, 1):
-//     E = ldexp(exp2f(f), n).  Only f is rounded to FP32, so the relative
-//     error of E does not grow with |lam|.
+//  1. its flag and location are read with coalesced loads (one observation
+//     per lane: 1 byte and 16 bytes);
+//  2. lam_k = log2 e_{t,k} is evaluated in FP64 for every state k; the
+//     state constants are wave-uniform (scalar loads), and the lane keeps
+//     the running maximum;
+//  3. s_t = floor(max_k lam_k) - kEmisBias, an exact integer shift (any
+//     integer near that value keeps the scaled emissions in range);
+//  4. lam_k is evaluated again and split as lam_k - s_t = n + f, n an
+//     integer and f in [0, 1): Et[k][t] = ldexp(exp2f(f), n).  Only f is
+//     rounded to FP32, so the relative error of the scaled emission does not
+//     grow with |lam|.
 //
-// E is [kChunk][KP] in LDS; padding states and observations past the chunk
-// end get E = 0.  `ssum` accumulates the shifts of the observations this lane
-// handled; `bad` is set for invalid data (flag not 0/1, tremor with a
-// non-finite location).
+// Et is stored transposed, row k (state) of stride ES >= kChunk floats, so
+// that the writes of one state are contiguous across lanes.  Rows k >= K
+// are not written (the caller keeps them zero).  The shift of the lane's
+// observation is returned in `shift` and added to `ssum`; `bad` is set for
+// invalid data (flag not 0/1, tremor with a non-finite location).
 // ---------------------------------------------------------------------------
-// Wave-local LDS ordering (see stage_emissions): a wavefront's own LDS
-// writes become visible to all its lanes; no other wavefront takes part, so
-// wavefronts of one workgroup may run different numbers of chunks.
+// Wave-local LDS ordering: a wavefront's own LDS writes become visible to
+// all its lanes; no other wavefront takes part, so wavefronts of one
+// workgroup may run different numbers of chunks.
 __device__ __forceinline__ void wave_sync_lds()
 {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
@@ -163,74 +165,50 @@ __device__ __forceinline__ void wave_sync_lds()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
-struct ChunkLds {
-    double ox[kChunk];
-    double oy[kChunk];
-    int of[kChunk];
-    int sh[kChunk];
-};
-
-__device__ __forceinline__ double state_log2_emission(const StateConst &s, int f, double x, double y)
+__device__ __forceinline__ double state_log2_emission(const StateConst &s, bool tremor, double x, double y)
 {
-    if (f != 1) return s.a0;
     const double d0 = x - s.mx, d1 = y - s.my;
-    return s.a1 + d0 * (s.cxx * d0 + s.cxy * d1) + s.cyy * (d1 * d1);
+    const double q = s.a1 + d0 * (s.cxx * d0 + s.cxy * d1) + s.cyy * (d1 * d1);
+    return tremor ? q : s.a0;
 }
 
-template <int KP>
+template <int ES>
 __device__ __forceinline__ void stage_emissions(int K, int64_t tc, int nst,
                                                 const uint8_t *__restrict__ flag,
                                                 const double *__restrict__ xy,
                                                 const StateConst *__restrict__ sc,
-                                                float *E, ChunkLds &cl,
-                                                long long &ssum, int &bad)
+                                                float *Et, long long &ssum, int &bad, int &shift)
 {
     const int lane = threadIdx.x & (kWave - 1);
-    if (lane < nst) {
-        int f = flag[tc + lane];
-        double x = 0.0, y = 0.0;
+    const bool live = lane < nst;
+    int f = 0;
+    double x = 0.0, y = 0.0;
+    if (live) {
+        f = flag[tc + lane];
         if (f == 1) {
-            x = xy[2 * (tc + lane)];
-            y = xy[2 * (tc + lane) + 1];
+            const double2 p = reinterpret_cast<const double2 *>(xy)[tc + lane];
+            x = p.x;
+            y = p.y;
             if (!(isfinite(x) && isfinite(y))) bad = 1;
         } else if (f != 0) {
             bad = 1;
         }
-        cl.ox[lane] = x;
-        cl.oy[lane] = y;
-        cl.of[lane] = f;
     }
-    wave_sync_lds();
-#pragma unroll 2
-    for (int pi = lane; pi < kChunk * KP; pi += kWave) {
-        const int tl = pi / KP, k = pi % KP;
-        float lam = -INFINITY;
-        if (tl < nst && k < K) lam = (float)state_log2_emission(sc[k], cl.of[tl], cl.ox[tl], cl.oy[tl]);
-        E[pi] = lam;
-    }
-    wave_sync_lds();
-    if (lane < nst) {
-        float m = -INFINITY;
-        const float *row = E + lane * KP;
-        for (int k = 0; k < K; ++k) m = fmaxf(m, row[k]);
-        int s = 0;
-        if (m > -1.0e9f && m < 1.0e9f) s = (int)floorf(m) - kEmisBias;
-        cl.sh[lane] = s;
-        ssum += s;
-    }
-    wave_sync_lds();
-#pragma unroll 2
-    for (int pi = lane; pi < kChunk * KP; pi += kWave) {
-        const int tl = pi / KP, k = pi % KP;
+    const bool tremor = (f == 1);
+    double m = -INFINITY;
+    for (int k = 0; k < K; ++k) m = fmax(m, state_log2_emission(sc[k], tremor, x, y));
+    int sh = 0;
+    if (m > -1.0e9 && m < 1.0e9) sh = (int)floor(m) - kEmisBias;
+    if (live) ssum += sh;
+    shift = sh;
+    for (int k = 0; k < K; ++k) {
+        const double r = state_log2_emission(sc[k], tremor, x, y) - (double)sh;
         float e = 0.f;
-        if (tl < nst && k < K) {
-            const double r = state_log2_emission(sc[k], cl.of[tl], cl.ox[tl], cl.oy[tl]) - (double)cl.sh[tl];
-            if (r > -160.0) {
-                const double n = floor(r);
-                e = __builtin_amdgcn_ldexpf(exp2f((float)(r - n)), (int)n);
-            }
+        if (live && r > -160.0) {
+            const double n = floor(r);
+            e = __builtin_amdgcn_ldexpf(exp2f((float)(r - n)), (int)n);
         }
-        E[pi] = e;
+        Et[k * ES + lane] = e;
     }
     wave_sync_lds();
 }

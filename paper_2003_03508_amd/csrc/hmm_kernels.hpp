@@ -112,18 +112,17 @@ __global__ __launch_bounds__(64) void k_emission(int K, int64_t T, const StateCo
                                                  int32_t *__restrict__ shift,
                                                  float *__restrict__ e_hat, int *__restrict__ status)
 {
-    __shared__ __attribute__((aligned(16))) float E[kChunk * KP];
-    __shared__ ChunkLds cl;
+    __shared__ __attribute__((aligned(16))) float Et[KP * kChunk];
     const int lane = threadIdx.x;
     const int64_t tc = (int64_t)blockIdx.x * kChunk;
     const int nst = (int)min((int64_t)kChunk, T - tc);
     long long ssum = 0;
-    int bad = 0;
-    stage_emissions<KP>(K, tc, nst, flag, xy, sc, E, cl, ssum, bad);
-    if (lane < nst) shift[tc + lane] = cl.sh[lane];
+    int bad = 0, sh = 0;
+    stage_emissions<kChunk>(K, tc, nst, flag, xy, sc, Et, ssum, bad, sh);
+    if (lane < nst) shift[tc + lane] = sh;
     for (int idx = lane; idx < nst * K; idx += kWave) {
         const int tl = idx / K, k = idx % K;
-        e_hat[(tc + tl) * K + k] = E[tl * KP + k];
+        e_hat[(tc + tl) * K + k] = Et[k * kChunk + tl];
     }
     if (__any(bad) && lane == 0) atomicOr(status, kBadData);
 }
@@ -146,8 +145,8 @@ __global__ __launch_bounds__(64) void k_serial(int K, int64_t T, const double *_
                                                int *__restrict__ status, double *__restrict__ out)
 {
     constexpr int SPL = (KP + kWave - 1) / kWave;
-    __shared__ __attribute__((aligned(16))) float E[kChunk * KP];
-    __shared__ ChunkLds cl;
+    constexpr int ES = kChunk + 1;  // odd stride: lane j reads row j without bank conflicts
+    __shared__ float Et[KP * ES];
     __shared__ float4 U4[KP / 4];
     float *U = reinterpret_cast<float *>(U4);
     const int lane = threadIdx.x;
@@ -172,12 +171,13 @@ __global__ __launch_bounds__(64) void k_serial(int K, int64_t T, const double *_
     }
     long long uexp = e0;
     long long ssum = 0;
-    int bad = 0;
+    int bad = 0, sh = 0;
     const int K4 = (K + 3) & ~3;
+    for (int i = lane; i < KP * ES; i += kWave) Et[i] = 0.f;
 
     for (int64_t tc = 0; tc < T; tc += kChunk) {
         const int nst = (int)min((int64_t)kChunk, T - tc);
-        stage_emissions<KP>(K, tc, nst, flag, xy, sc, E, cl, ssum, bad);
+        stage_emissions<ES>(K, tc, nst, flag, xy, sc, Et, ssum, bad, sh);
         for (int tl = 0; tl < nst; ++tl) {
 #pragma unroll
             for (int s = 0; s < SPL; ++s) {
@@ -201,7 +201,7 @@ __global__ __launch_bounds__(64) void k_serial(int K, int64_t T, const double *_
                     }
                 }
                 const int j = lane + kWave * s;
-                const float ej = (j < KP) ? E[tl * KP + j] : 0.f;
+                const float ej = (j < KP) ? Et[j * ES + tl] : 0.f;
                 b[s] = ((acc0 + acc1) + (acc2 + acc3)) * ej;
                 bmax = fmaxf(bmax, b[s]);
             }
@@ -334,9 +334,14 @@ __device__ __forceinline__ void renorm_columns(const typename Tile<S>::acc_t (&C
 // exchanged product's row exponents and shift sum, and the chunk's data.
 __host__ __device__ constexpr int region_floats(int KP)
 {
-    return ((kChunk * KP > KP * KP) ? kChunk * KP : KP * KP) + 2 * KP + 4 + (int)(sizeof(ChunkLds) / 4);
+    return ((kChunk * KP > KP * KP) ? kChunk * KP : KP * KP) + 2 * KP + 4;
 }
 __host__ __device__ constexpr int region_bytes(int KP) { return 4 * region_floats(KP); }
+
+// Steps whose scaled emissions a lane reads with one LDS access in the
+// segment kernel (4 while registers allow).
+template <int S, int MT>
+constexpr int kUnroll = (MT * Tile<S>::RS <= 16) ? 4 : 2;
 
 // Wavefronts per workgroup: the segment kernel puts one segment on each SIMD
 // of a CU; the fold kernel uses as many as fit in 128 KiB of LDS (max 16).
@@ -349,11 +354,10 @@ __host__ __device__ constexpr int fold_waves(int KP)
 template <int KP>
 struct Region {
     static constexpr int EF = (kChunk * KP > KP * KP) ? kChunk * KP : KP * KP;
-    static constexpr int floats = EF + 2 * KP + 4 + (int)(sizeof(ChunkLds) / 4);
+    static constexpr int floats = EF + 2 * KP + 4;
     __device__ static float *E(float *base) { return base; }
     __device__ static long long *QE(float *base) { return reinterpret_cast<long long *>(base + EF); }
     __device__ static long long *QS(float *base) { return reinterpret_cast<long long *>(base + EF + 2 * KP); }
-    __device__ static ChunkLds &CL(float *base) { return *reinterpret_cast<ChunkLds *>(base + EF + 2 * KP + 4); }
 };
 
 // Write P (row-major M~, row exponents, shift sum) into an LDS region.
@@ -530,13 +534,12 @@ __global__ __launch_bounds__(64 * kBlockedWaves) void k_blocked(int K, int64_t T
     const int W = blockDim.x >> 6;
     const int64_t b = (int64_t)blockIdx.x * W + w;
     float *base = smem + w * region;
-    float *E = Region<KP>::E(base);
-    ChunkLds &cl = Region<KP>::CL(base);
+    float *Et = Region<KP>::E(base);  // Et[k][t], row stride kChunk
 
     Prod<S, MT> P;
     prod_identity<S, MT>(P);
     long long ssum = 0;
-    int bad = 0;
+    int bad = 0, sh = 0;
 
     if (b < nb) {
         const int64_t t0 = b * L;
@@ -549,34 +552,52 @@ __global__ __launch_bounds__(64 * kBlockedWaves) void k_blocked(int K, int64_t T
                 const int rho = S * (j / RS) + rit<S>(g, j % RS);
                 A[m][j] = GF[rho * KP + S * m + c];
             }
+        for (int i = lane; i < KP * kChunk; i += kWave) Et[i] = 0.f;  // rows >= K stay zero
         for (int64_t tc = t0; tc < t1; tc += kChunk) {
             const int nst = (int)min((int64_t)kChunk, t1 - tc);
-            stage_emissions<KP>(K, tc, nst, flag, xy, sc, E, cl, ssum, bad);
-            for (int tl = 0; tl < nst; ++tl) {
-                float ev[MT][RS];
+            stage_emissions<kChunk>(K, tc, nst, flag, xy, sc, Et, ssum, bad, sh);
+            for (int tl = 0; tl < nst; tl += kUnroll<S, MT>) {
+                // scaled emissions of the rows this lane holds, kUnroll steps at once
+                float evu[MT][RS][kUnroll<S, MT>];
 #pragma unroll
                 for (int m = 0; m < MT; ++m)
 #pragma unroll
-                    for (int r4 = 0; r4 < RS; r4 += 4) {
-                        const float4 q = *reinterpret_cast<const float4 *>(&E[tl * KP + S * m + rit<S>(g, r4)]);
-                        ev[m][r4] = q.x;
-                        ev[m][r4 + 1] = q.y;
-                        ev[m][r4 + 2] = q.z;
-                        ev[m][r4 + 3] = q.w;
+                    for (int r = 0; r < RS; ++r) {
+                        const float *src = &Et[(S * m + rit<S>(g, r)) * kChunk + tl];
+                        if constexpr (kUnroll<S, MT> == 4) {
+                            const float4 q = *reinterpret_cast<const float4 *>(src);
+                            evu[m][r][0] = q.x;
+                            evu[m][r][1] = q.y;
+                            evu[m][r][2] = q.z;
+                            evu[m][r][3] = q.w;
+                        } else {
+                            const float2 q = *reinterpret_cast<const float2 *>(src);
+                            evu[m][r][0] = q.x;
+                            evu[m][r][1] = q.y;
+                        }
                     }
-                acc_t C[MT][MT];
 #pragma unroll
-                for (int m = 0; m < MT; ++m)
+                for (int u = 0; u < kUnroll<S, MT>; ++u) {
+                    if (tl + u >= nst) break;
+                    float ev[MT][RS];
 #pragma unroll
-                    for (int n = 0; n < MT; ++n) {
-                        acc_t acc;
+                    for (int m = 0; m < MT; ++m)
 #pragma unroll
-                        for (int r = 0; r < RS; ++r) acc[r] = 0.f;
+                        for (int r = 0; r < RS; ++r) ev[m][r] = evu[m][r][u];
+                    acc_t C[MT][MT];
 #pragma unroll
-                        for (int j = 0; j < NSL; ++j) acc = mfma<S>(A[m][j], P.B[j / RS][n][j % RS], acc);
-                        C[m][n] = acc;
-                    }
-                renorm_columns<S, MT, true>(C, ev, P);
+                    for (int m = 0; m < MT; ++m)
+#pragma unroll
+                        for (int n = 0; n < MT; ++n) {
+                            acc_t acc;
+#pragma unroll
+                            for (int r = 0; r < RS; ++r) acc[r] = 0.f;
+#pragma unroll
+                            for (int j = 0; j < NSL; ++j) acc = mfma<S>(A[m][j], P.B[j / RS][n][j % RS], acc);
+                            C[m][n] = acc;
+                        }
+                    renorm_columns<S, MT, true>(C, ev, P);
+                }
             }
             wave_sync_lds();
         }
