@@ -107,20 +107,20 @@ struct Plan {
 inline Plan make_plan(const hmm_ctx *ctx, int KP, int64_t T)
 {
     Plan p;
-    // Two segments per SIMD (1024 SIMDs) while they fit in registers, one otherwise.
-    const int64_t waves = KP <= 32 ? 2048 : 1024;
+    p.W = group_waves(KP);
+    p.W2 = group_waves(KP);
+    // One workgroup of W segments per CU (256 CUs), segments of at least 32
+    // observations.
     if (ctx->block_len > 0) {
         p.L = ctx->block_len;
     } else {
-        int64_t per = (T + waves - 1) / waves;
-        p.L = ((per + kChunk - 1) / kChunk) * kChunk;
-        if (p.L < kChunk) p.L = kChunk;
+        const int64_t target = 256 * (int64_t)p.W;
+        p.L = (T + target - 1) / target;
+        if (p.L < 32) p.L = 32;
     }
     p.nb = T > 0 ? (T + p.L - 1) / p.L : 0;
-    p.W = kBlockedWaves;
     p.n1 = (p.nb + p.W - 1) / p.W;
-    p.W2 = fold_waves(KP);
-    p.F = ctx->fold > 0 ? ctx->fold : 4;
+    p.F = ctx->fold > 0 ? ctx->fold : 1;
     const int64_t per_wg = (int64_t)p.F * p.W2;
     int64_t n = p.n1;
     p.levels = 1;

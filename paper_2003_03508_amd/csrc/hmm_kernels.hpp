@@ -343,12 +343,12 @@ __host__ __device__ constexpr int region_bytes(int KP) { return 4 * region_float
 template <int S, int MT>
 constexpr int kUnroll = (MT * Tile<S>::RS <= 16) ? 4 : 2;
 
-// Wavefronts per workgroup: the segment kernel puts one segment on each SIMD
-// of a CU; the fold kernel uses as many as fit in 128 KiB of LDS (max 16).
-constexpr int kBlockedWaves = 4;
-__host__ __device__ constexpr int fold_waves(int KP)
+// Wavefronts per workgroup of the segment and fold kernels, by tile side:
+// as many as one CU holds given registers and LDS (160 KiB), so that one
+// workgroup per CU runs and most of the combination tree happens inside it.
+__host__ __device__ constexpr int group_waves(int KP)
 {
-    return (128 * 1024) / region_bytes(KP) > 16 ? 16 : (128 * 1024) / region_bytes(KP);
+    return KP <= 32 ? 16 : (KP <= 48 ? 12 : (KP <= 64 ? 8 : 4));
 }
 
 template <int KP>
@@ -514,7 +514,7 @@ __device__ __forceinline__ void workgroup_tree(Prod<S, MT> &P, long long &ssum, 
 // and writes one product: Mout[q] (KP x KP row-major), Eout[q][KP], Sout[q].
 // ---------------------------------------------------------------------------
 template <int S, int MT, int NSL>
-__global__ __launch_bounds__(64 * kBlockedWaves) void k_blocked(int K, int64_t T, int64_t L, int64_t nb,
+__global__ __launch_bounds__(64 * group_waves(S * MT)) void k_blocked(int K, int64_t T, int64_t L, int64_t nb,
                                                  const float *__restrict__ GF,
                                                  const StateConst *__restrict__ sc,
                                                  const uint8_t *__restrict__ flag,
@@ -620,7 +620,7 @@ __global__ __launch_bounds__(64 * kBlockedWaves) void k_blocked(int K, int64_t T
 //     ln L = ln2*(ssum + e_max) + ln( sum_c delta_c 2^(ex_c - e_max) sum_j M~[c][j] ).
 // ---------------------------------------------------------------------------
 template <int S, int MT, int NSL>
-__global__ __launch_bounds__(64 * fold_waves(S * MT)) void k_fold(int K, int64_t n_in, int F,
+__global__ __launch_bounds__(64 * group_waves(S * MT)) void k_fold(int K, int64_t n_in, int F,
                                                const float *__restrict__ Min,
                                                const long long *__restrict__ Ein,
                                                const long long *__restrict__ Sin,
