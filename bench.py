@@ -37,6 +37,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="approximate wall time of the CPU-oracle sample")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle leg")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="also run one plain device-to-device copy of BYTES (untimed), so that "
+                         "a counter profile of this command holds a copy of known size")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); this build has no "
@@ -60,6 +63,13 @@ def main():
     out = torch.empty(1, dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream()
 
+    if args.copy_probe > 0:
+        src = torch.ones(args.copy_probe // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     # ---- blocked FP32 MFMA path: the measured step
     for _ in range(args.warmup):
         ctx.loglik(**d, algo="blocked_f32", out=out)
@@ -79,15 +89,17 @@ def main():
     kern_avg_ms = kern_ms / max(launches, 1)
 
     # ---- plain forward recursion on the GPU (the comparison path)
-    ctx.loglik(**d, algo="serial_f32", out=out)
-    torch.cuda.synchronize()
-    s0 = time.perf_counter()
-    for _ in range(args.serial_steps):
+    ll_serial, serial_evals_per_s = None, None
+    if args.serial_steps > 0:
         ctx.loglik(**d, algo="serial_f32", out=out)
-    torch.cuda.synchronize()
-    s1 = time.perf_counter()
-    ll_serial = float(out.item())
-    serial_evals_per_s = args.serial_steps / (s1 - s0)
+        torch.cuda.synchronize()
+        s0 = time.perf_counter()
+        for _ in range(args.serial_steps):
+            ctx.loglik(**d, algo="serial_f32", out=out)
+        torch.cuda.synchronize()
+        s1 = time.perf_counter()
+        ll_serial = float(out.item())
+        serial_evals_per_s = args.serial_steps / (s1 - s0)
 
     # ---- roofline of the dominant kernel (segment products)
     flops = 2.0 * T * K ** 3                 # algorithmic, unpadded
@@ -117,7 +129,7 @@ def main():
                          f"FP64 C oracle, {c1 - c0:.1f} s"}
 
     def rel(x):
-        return None if ll_oracle is None else abs(x - ll_oracle) / abs(ll_oracle)
+        return None if (ll_oracle is None or x is None) else abs(x - ll_oracle) / abs(ll_oracle)
 
     rec = {
         "metric": "HMM log-lik evals/s at K=25,T=1e6 vs plain forward; MCMC ESS/s",
@@ -136,9 +148,11 @@ def main():
                                "seed 1, one parameter set, blocked FP32 MFMA path",
                    "K": K, "T": T, "algo": "blocked_f32", "block_len": plan["block_len"],
                    "n_blocks": plan["n_blocks"], "fold_levels": plan["levels"]},
-        "plain_forward": {"value": round(serial_evals_per_s, 4), "unit": "evals/s",
-                          "steps": args.serial_steps, "algo": "serial_f32"},
-        "speedup_vs_plain_forward": round(evals_per_s / serial_evals_per_s, 2),
+        "plain_forward": None if serial_evals_per_s is None else {
+            "value": round(serial_evals_per_s, 4), "unit": "evals/s", "steps": args.serial_steps,
+            "algo": "serial_f32"},
+        "speedup_vs_plain_forward": None if serial_evals_per_s is None else round(
+            evals_per_s / serial_evals_per_s, 2),
         "loglik": ll_blocked,
         "rel_err_vs_oracle": {"blocked_f32": rel(ll_blocked), "serial_f32": rel(ll_serial)},
         "roofline": roofline,
