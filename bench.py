@@ -26,6 +26,37 @@ if ROOT not in sys.path:
 
 PEAK_FP32_MFMA_TFLOPS = 157.3  # MI355X dense FP32 matrix peak
 PEAK_HBM_GBS = 8000.0
+COUNTERS = os.path.join(ROOT, "profiles", "k_blocked_k25_t1e6_counters.txt")
+
+
+def kernel_sources_sha256():
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2003_03508_amd", "csrc", "*"))):
+        if f.endswith((".hpp", ".hip")):
+            h.update(open(f, "rb").read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch of the segment kernel from the committed counter
+    profile (FETCH_SIZE and WRITE_SIZE, each scaled by the same counter's
+    reading for a device copy of known size); None when the kernel sources
+    have changed since the counters were taken."""
+    if not os.path.exists(COUNTERS):
+        return None
+    kv = {}
+    for line in open(COUNTERS):
+        if "=" in line and not line.lstrip().startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_sources_sha256") != kernel_sources_sha256():
+        return None
+    probe = float(kv["copy_probe_bytes"])
+    fetch = float(kv["fetch_kib_per_dispatch"]) * 1024 * probe / (float(kv["copy_fetch_kib"]) * 1024)
+    write = float(kv["write_kib_per_dispatch"]) * 1024 * probe / (float(kv["copy_write_kib"]) * 1024)
+    return int(round(fetch + write))
 
 
 def main():
@@ -106,7 +137,9 @@ def main():
     achieved_tflops = flops / (kern_avg_ms * 1e-3) / 1e12
     roofline = {"bound": "mfma", "achieved": round(achieved_tflops, 3),
                 "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved_tflops / PEAK_FP32_MFMA_TFLOPS, 4), "traffic": None,
+                "frac": round(achieved_tflops / PEAK_FP32_MFMA_TFLOPS, 4),
+                "traffic": measured_traffic(), "traffic_unit": "bytes/launch",
+                "algorithmic_bytes": 17 * T,
                 "kernel": "k_blocked<32,1>", "kernel_avg_ms": round(kern_avg_ms, 5),
                 "launches_timed": launches, "flops_per_launch": flops}
 
