@@ -51,6 +51,21 @@ int run_blocked_small(const Shape &sh, int K, hmm_ctx *ctx, const double *delta,
     }
 }
 
+int run_blocked_lp_small(int MT, bool f16, int K, hmm_ctx *ctx, const double *delta, int64_t T,
+                         const uint8_t *flag, const double *xy, hipStream_t st, double *out, const Plan &pl,
+                         const Layout &ly)
+{
+    switch (MT * 2 + (f16 ? 1 : 0)) {
+    case 2: return dispatch_lp<1, false, 1, 4>(needed_slots<16, 1>(K), ctx, K, delta, T, flag, xy, st, out, pl, ly);
+    case 3: return dispatch_lp<1, true, 1, 4>(needed_slots<16, 1>(K), ctx, K, delta, T, flag, xy, st, out, pl, ly);
+    case 4: return dispatch_lp<2, false, 5, 8>(needed_slots<16, 2>(K), ctx, K, delta, T, flag, xy, st, out, pl, ly);
+    case 5: return dispatch_lp<2, true, 5, 8>(needed_slots<16, 2>(K), ctx, K, delta, T, flag, xy, st, out, pl, ly);
+    case 6: return dispatch_lp<3, false, 9, 12>(needed_slots<16, 3>(K), ctx, K, delta, T, flag, xy, st, out, pl, ly);
+    case 7: return dispatch_lp<3, true, 9, 12>(needed_slots<16, 3>(K), ctx, K, delta, T, flag, xy, st, out, pl, ly);
+    default: return HMM_E_UNSUPPORTED;
+    }
+}
+
 }  // namespace hmmh
 
 extern "C" {
@@ -120,10 +135,9 @@ int hmm_loglik(hmm_ctx *ctx, int32_t K, const double *delta, const double *Gamma
     int rc = check_common(ctx, K, p, mu, Sigma, T, flag, xy);
     if (rc != HMM_OK) return rc;
     if (!delta || !Gamma || !out) return HMM_E_INVALID_ARG;
-    if (algo != HMM_SERIAL_F32 && algo != HMM_BLOCKED_F32) {
-        if (algo == HMM_BLOCKED_BF16 || algo == HMM_BLOCKED_F16) return HMM_E_UNSUPPORTED;
+    if (algo != HMM_SERIAL_F32 && algo != HMM_BLOCKED_F32 && algo != HMM_BLOCKED_BF16 &&
+        algo != HMM_BLOCKED_F16)
         return HMM_E_INVALID_ARG;
-    }
     DeviceGuard dg(ctx->device);
     if (!dg.ok) return HMM_E_DEVICE;
     hipStream_t st = static_cast<hipStream_t>(stream);
@@ -150,6 +164,8 @@ int hmm_loglik(hmm_ctx *ctx, int32_t K, const double *delta, const double *Gamma
 
     Shape sh;
     if (!blocked_shape(K, &sh)) return HMM_E_UNSUPPORTED;
+    const bool lp = (algo == HMM_BLOCKED_BF16 || algo == HMM_BLOCKED_F16);
+    if (lp) sh = Shape{16, (K + 15) / 16};  // 16-bit operands always use 16x16 tiles
     const int KP = sh.KP();
     Plan pl = make_plan(ctx, KP, T);
     if (pl.n1 > INT_MAX) return HMM_E_UNSUPPORTED;
@@ -159,6 +175,13 @@ int hmm_loglik(hmm_ctx *ctx, int32_t K, const double *delta, const double *Gamma
     hipLaunchKernelGGL(k_prepare, dim3(1), dim3(256), 0, st, K, KP, delta, Gamma, p, mu, Sigma,
                        at<StateConst>(ctx->ws, ly.sc), at<float>(ctx->ws, ly.gf),
                        at<int>(ctx->ws, ly.status));
+    if (lp) {
+        const bool f16 = (algo == HMM_BLOCKED_F16);
+        rc = (sh.MT <= 3) ? run_blocked_lp_small(sh.MT, f16, K, ctx, delta, T, flag, xy, st, out, pl, ly)
+                          : run_blocked_lp_large(sh.MT, f16, K, ctx, delta, T, flag, xy, st, out, pl, ly);
+        if (rc != HMM_OK) return rc;
+        return launch_status();
+    }
     rc = (KP <= 48) ? run_blocked_small(sh, K, ctx, delta, T, flag, xy, st, out, pl, ly)
                     : run_blocked_large(sh, K, ctx, delta, T, flag, xy, st, out, pl, ly);
     if (rc != HMM_OK) return rc;

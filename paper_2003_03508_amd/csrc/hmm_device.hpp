@@ -68,16 +68,24 @@ __device__ __forceinline__ typename Tile<S>::acc_t mfma(float a, float b, typena
 // ---------------------------------------------------------------------------
 // Cross-lane helpers.
 // ---------------------------------------------------------------------------
+// The maxima below are taken on IEEE bit patterns as unsigned integers, which
+// orders non-negative floats exactly like their values (all quantities
+// reduced here are non-negative) and avoids NaN canonicalisation.
+__device__ __forceinline__ float umax_f(float a, float b)
+{
+    return __uint_as_float(max(__float_as_uint(a), __float_as_uint(b)));
+}
+
 __device__ __forceinline__ float swap32_max(float x)
 {
     auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false, false);
-    return fmaxf(x, fmaxf(__uint_as_float(r[0]), __uint_as_float(r[1])));
+    return __uint_as_float(max(__float_as_uint(x), max((unsigned)r[0], (unsigned)r[1])));
 }
 
 __device__ __forceinline__ float swap16_max(float x)
 {
     auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(x), false, false);
-    return fmaxf(x, fmaxf(__uint_as_float(r[0]), __uint_as_float(r[1])));
+    return __uint_as_float(max(__float_as_uint(x), max((unsigned)r[0], (unsigned)r[1])));
 }
 
 // Maximum over the lanes that share one output column (same l % S).
@@ -90,23 +98,24 @@ __device__ __forceinline__ float column_max(float x)
 }
 
 template <int CTRL>
-__device__ __forceinline__ float dpp_f(float x)
+__device__ __forceinline__ unsigned dpp_u(unsigned x)
 {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, true));
+    return (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, 0xF, 0xF, true);
 }
 
-// Maximum over the whole wavefront, returned to every lane.
-__device__ __forceinline__ float wave_max(float x)
+// Maximum over the whole wavefront of a non-negative value, returned to every lane.
+__device__ __forceinline__ float wave_max(float xf)
 {
-    x = fmaxf(x, dpp_f<0xB1>(x));   // quad_perm [1,0,3,2]
-    x = fmaxf(x, dpp_f<0x4E>(x));   // quad_perm [2,3,0,1]
-    x = fmaxf(x, dpp_f<0x141>(x));  // row_half_mirror
-    x = fmaxf(x, dpp_f<0x140>(x));  // row_mirror: every lane holds its row's max
-    const float a = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 0));
-    const float b = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 16));
-    const float c = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 32));
-    const float d = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 48));
-    return fmaxf(fmaxf(a, b), fmaxf(c, d));
+    unsigned x = __float_as_uint(xf);
+    x = max(x, dpp_u<0xB1>(x));   // quad_perm [1,0,3,2]
+    x = max(x, dpp_u<0x4E>(x));   // quad_perm [2,3,0,1]
+    x = max(x, dpp_u<0x141>(x));  // row_half_mirror
+    x = max(x, dpp_u<0x140>(x));  // row_mirror: every lane holds its row's max
+    const unsigned a = (unsigned)__builtin_amdgcn_readlane((int)x, 0);
+    const unsigned b = (unsigned)__builtin_amdgcn_readlane((int)x, 16);
+    const unsigned c = (unsigned)__builtin_amdgcn_readlane((int)x, 32);
+    const unsigned d = (unsigned)__builtin_amdgcn_readlane((int)x, 48);
+    return __uint_as_float(max(max(a, b), max(c, d)));
 }
 
 __device__ __forceinline__ double wave_sum_f64(double x)

@@ -182,9 +182,12 @@ inline int allow_lds(const void *fn, size_t bytes)
     return HMM_OK;
 }
 
-template <int S, int MT, int NSL>
-int run_blocked(hmm_ctx *ctx, int K, const double *delta, int64_t T, const uint8_t *flag,
-                const double *xy, hipStream_t st, double *out, const Plan &pl, const Layout &ly)
+// Launch sequence of the blocked path: parameter preparation is done by the
+// caller; here the segment kernel (FP32 or 16-bit operands) and the fold tree.
+template <int S, int MT, int NSL, typename SegKernel>
+int run_blocked_with(SegKernel seg, hmm_ctx *ctx, int K, const double *delta, int64_t T,
+                     const uint8_t *flag, const double *xy, hipStream_t st, double *out, const Plan &pl,
+                     const Layout &ly, int &lds_ok)
 {
     constexpr int KP = S * MT;
     void *ws = ctx->ws;
@@ -192,9 +195,8 @@ int run_blocked(hmm_ctx *ctx, int K, const double *delta, int64_t T, const uint8
     const StateConst *sc = at<StateConst>(ws, ly.sc);
     const float *gf = at<float>(ws, ly.gf);
     const size_t rb = (size_t)region_bytes(KP);
-    static int lds_ok = -1;
     if (lds_ok < 0) {
-        lds_ok = (allow_lds(reinterpret_cast<const void *>(&k_blocked<S, MT, NSL>), rb * pl.W) == HMM_OK &&
+        lds_ok = (allow_lds(reinterpret_cast<const void *>(seg), rb * pl.W) == HMM_OK &&
                   allow_lds(reinterpret_cast<const void *>(&k_fold<S, MT, NSL>), rb * pl.W2) == HMM_OK)
                      ? 1
                      : 0;
@@ -215,9 +217,9 @@ int run_blocked(hmm_ctx *ctx, int K, const double *delta, int64_t T, const uint8
     }
     if (ev0) (void)hipEventRecord(ev0, st);
     if (pl.nb > 0) {
-        hipLaunchKernelGGL((k_blocked<S, MT, NSL>), dim3((unsigned)pl.n1), dim3(64 * pl.W), rb * pl.W, st,
-                           K, T, pl.L, pl.nb, gf, sc, flag, xy, at<float>(ws, ly.m0),
-                           at<long long>(ws, ly.e0), at<long long>(ws, ly.s0), status);
+        hipLaunchKernelGGL(seg, dim3((unsigned)pl.n1), dim3(64 * pl.W), rb * pl.W, st, K, T, pl.L, pl.nb, gf,
+                           sc, flag, xy, at<float>(ws, ly.m0), at<long long>(ws, ly.e0),
+                           at<long long>(ws, ly.s0), status);
     }
     if (ev1) (void)hipEventRecord(ev1, st);
     // Fold levels: m0 -> m1 -> m2 -> m1 -> ... until one workgroup remains.
@@ -245,6 +247,24 @@ int run_blocked(hmm_ctx *ctx, int K, const double *delta, int64_t T, const uint8
     return HMM_OK;
 }
 
+template <int S, int MT, int NSL>
+int run_blocked(hmm_ctx *ctx, int K, const double *delta, int64_t T, const uint8_t *flag,
+                const double *xy, hipStream_t st, double *out, const Plan &pl, const Layout &ly)
+{
+    static int lds_ok = -1;
+    return run_blocked_with<S, MT, NSL>(&k_blocked<S, MT, NSL>, ctx, K, delta, T, flag, xy, st, out, pl, ly,
+                                        lds_ok);
+}
+
+template <int MT, bool F16, int NSL>
+int run_blocked_lp(hmm_ctx *ctx, int K, const double *delta, int64_t T, const uint8_t *flag,
+                   const double *xy, hipStream_t st, double *out, const Plan &pl, const Layout &ly)
+{
+    static int lds_ok = -1;
+    return run_blocked_with<16, MT, NSL>(&k_blocked_lp<MT, F16, NSL>, ctx, K, delta, T, flag, xy, st, out, pl,
+                                         ly, lds_ok);
+}
+
 // Runtime number of live contraction slots -> compile-time instantiation.
 template <int S, int MT, int LO, int HI>
 int dispatch_nsl(int nsl, hmm_ctx *ctx, int K, const double *delta, int64_t T, const uint8_t *flag,
@@ -258,6 +278,19 @@ int dispatch_nsl(int nsl, hmm_ctx *ctx, int K, const double *delta, int64_t T, c
     }
 }
 
+// 16-bit operands: 16x16 tiles, MT = ceil(K/16); nsl only selects the FP32 fold.
+template <int MT, bool F16, int LO, int HI>
+int dispatch_lp(int nsl, hmm_ctx *ctx, int K, const double *delta, int64_t T, const uint8_t *flag,
+                const double *xy, hipStream_t st, double *out, const Plan &pl, const Layout &ly)
+{
+    if constexpr (LO > HI) {
+        return HMM_E_UNSUPPORTED;
+    } else {
+        if (nsl == LO) return run_blocked_lp<MT, F16, LO>(ctx, K, delta, T, flag, xy, st, out, pl, ly);
+        return dispatch_lp<MT, F16, LO + 1, HI>(nsl, ctx, K, delta, T, flag, xy, st, out, pl, ly);
+    }
+}
+
 // Shapes with KP <= 48 (hmm_api.hip, accumulators in VGPRs) and KP >= 64
 // (hmm_large.hip, accumulators in AGPRs: these kernels need more than 256
 // registers per lane).
@@ -267,5 +300,12 @@ int run_blocked_small(const Shape &sh, int K, hmm_ctx *ctx, const double *delta,
 int run_blocked_large(const Shape &sh, int K, hmm_ctx *ctx, const double *delta, int64_t T,
                       const uint8_t *flag, const double *xy, hipStream_t st, double *out, const Plan &pl,
                       const Layout &ly);
+// 16-bit operand paths: MT <= 3 in hmm_api.hip, MT 4..5 in hmm_large.hip.
+int run_blocked_lp_small(int MT, bool f16, int K, hmm_ctx *ctx, const double *delta, int64_t T,
+                         const uint8_t *flag, const double *xy, hipStream_t st, double *out, const Plan &pl,
+                         const Layout &ly);
+int run_blocked_lp_large(int MT, bool f16, int K, hmm_ctx *ctx, const double *delta, int64_t T,
+                         const uint8_t *flag, const double *xy, hipStream_t st, double *out, const Plan &pl,
+                         const Layout &ly);
 
 }  // namespace hmmh

@@ -172,38 +172,36 @@ __global__ __launch_bounds__(64) void k_serial(int K, int64_t T, const double *_
     long long uexp = e0;
     long long ssum = 0;
     int bad = 0, sh = 0;
-    const int K4 = (K + 3) & ~3;
     for (int i = lane; i < KP * ES; i += kWave) Et[i] = 0.f;
 
     for (int64_t tc = 0; tc < T; tc += kChunk) {
         const int nst = (int)min((int64_t)kChunk, T - tc);
         stage_emissions<ES>(K, tc, nst, flag, xy, sc, Et, ssum, bad, sh);
         for (int tl = 0; tl < nst; ++tl) {
+            float ej[SPL];
 #pragma unroll
             for (int s = 0; s < SPL; ++s) {
                 const int j = lane + kWave * s;
                 if (j < KP) U[j] = u[s];
+                ej[s] = (j < KP) ? Et[j * ES + tl] : 0.f;
             }
             __syncthreads();
             float bmax = 0.f;
             float b[SPL];
 #pragma unroll
             for (int s = 0; s < SPL; ++s) {
+                // padding entries of U and G are zero, so all KP/4 groups are summed
                 float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f, acc3 = 0.f;
 #pragma unroll
                 for (int i4 = 0; i4 < KP / 4; ++i4) {
-                    if (4 * i4 < K4) {
-                        const float4 uu = U4[i4];
-                        acc0 = fmaf(uu.x, G[s][4 * i4 + 0], acc0);
-                        acc1 = fmaf(uu.y, G[s][4 * i4 + 1], acc1);
-                        acc2 = fmaf(uu.z, G[s][4 * i4 + 2], acc2);
-                        acc3 = fmaf(uu.w, G[s][4 * i4 + 3], acc3);
-                    }
+                    const float4 uu = U4[i4];
+                    acc0 = fmaf(uu.x, G[s][4 * i4 + 0], acc0);
+                    acc1 = fmaf(uu.y, G[s][4 * i4 + 1], acc1);
+                    acc2 = fmaf(uu.z, G[s][4 * i4 + 2], acc2);
+                    acc3 = fmaf(uu.w, G[s][4 * i4 + 3], acc3);
                 }
-                const int j = lane + kWave * s;
-                const float ej = (j < KP) ? Et[j * ES + tl] : 0.f;
-                b[s] = ((acc0 + acc1) + (acc2 + acc3)) * ej;
-                bmax = fmaxf(bmax, b[s]);
+                b[s] = ((acc0 + acc1) + (acc2 + acc3)) * ej[s];
+                bmax = umax_f(bmax, b[s]);
             }
             const float mx = wave_max(bmax);
             const int e = (mx > 0.f) ? fexp(mx) : 0;
@@ -604,6 +602,165 @@ __global__ __launch_bounds__(64 * group_waves(S * MT)) void k_blocked(int K, int
     }
     if (__any(bad) && lane == 0) atomicOr(status, kBadData);
     // each lane summed the shifts of the observations it staged
+    ssum = wave_sum_i64(ssum);
+    workgroup_tree<S, MT, NSL>(P, ssum, smem, region);
+    if (w == 0)
+        prod_to_global<S, MT>(P, ssum, Mout + (int64_t)blockIdx.x * KP * KP,
+                              Eout + (int64_t)blockIdx.x * KP, Sout + blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// Segment products with BF16 or FP16 MFMA operands and FP32 accumulation.
+// Same structure as k_blocked with 16x16 tiles: the running product N is kept
+// and renormalised in FP32 (accumulator layout); each step packs it to 16-bit
+// as the B operand.  v_mfma_f32_16x16x32_{bf16,f16} contracts 32 rows: lane
+// group g supplies 8 of them, the rows it holds of two row tiles (2p, 2p+1):
+// element e of its operand is contraction row 16*(2p + e/4) + 4g + e%4.  An
+// odd last row tile uses v_mfma_f32_16x16x16_{bf16,f16} (4 rows per group).
+// Gamma^T is converted once per segment; for FP16 it is pre-scaled by
+// 2^kF16GammaShift to keep small transition probabilities out of FP16's
+// subnormal range, and each step's extra factor is removed from the shift
+// sum exactly.
+// ---------------------------------------------------------------------------
+constexpr int kF16GammaShift = 8;
+
+template <bool F16> struct Lp;
+template <> struct Lp<false> {
+    typedef __bf16 e_t;
+    typedef __bf16 v8 __attribute__((ext_vector_type(8)));
+    typedef __bf16 v4 __attribute__((ext_vector_type(4)));
+    static constexpr int shift = 0;
+    __device__ static Tile<16>::acc_t mma32(v8 a, v8 b, Tile<16>::acc_t c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+    }
+    __device__ static Tile<16>::acc_t mma16(v4 a, v4 b, Tile<16>::acc_t c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+    }
+};
+template <> struct Lp<true> {
+    typedef _Float16 e_t;
+    typedef _Float16 v8 __attribute__((ext_vector_type(8)));
+    typedef _Float16 v4 __attribute__((ext_vector_type(4)));
+    static constexpr int shift = kF16GammaShift;
+    __device__ static Tile<16>::acc_t mma32(v8 a, v8 b, Tile<16>::acc_t c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+    }
+    __device__ static Tile<16>::acc_t mma16(v4 a, v4 b, Tile<16>::acc_t c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
+    }
+};
+
+template <int MT, bool F16, int NSL>
+__global__ __launch_bounds__(64 * group_waves(16 * MT)) void k_blocked_lp(
+    int K, int64_t T, int64_t L, int64_t nb, const float *__restrict__ GF,
+    const StateConst *__restrict__ sc, const uint8_t *__restrict__ flag,
+    const double *__restrict__ xy, float *__restrict__ Mout, long long *__restrict__ Eout,
+    long long *__restrict__ Sout, int *__restrict__ status)
+{
+    constexpr int S = 16, KP = 16 * MT, RS = 4, NP = MT / 2, ODD = MT % 2;
+    typedef typename Tile<S>::acc_t acc_t;
+    typedef Lp<F16> lp;
+    typedef typename lp::e_t e_t;
+    typedef typename lp::v8 v8;
+    typedef typename lp::v4 v4;
+    extern __shared__ __attribute__((aligned(16))) float smem[];
+    constexpr int region = Region<KP>::floats;
+
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int c = lane % S, g = lane / S;
+    const int W = blockDim.x >> 6;
+    const int64_t b = (int64_t)blockIdx.x * W + w;
+    float *base = smem + w * region;
+    float *Et = Region<KP>::E(base);
+
+    Prod<S, MT> P;
+    prod_identity<S, MT>(P);
+    long long ssum = 0;
+    int bad = 0, sh = 0;
+
+    if (b < nb) {
+        const int64_t t0 = b * L;
+        const int64_t t1 = min(T, t0 + L);
+        const float gscale = (float)(1 << lp::shift);
+        v8 Ap[MT][NP > 0 ? NP : 1];
+        v4 Ao[MT];
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+#pragma unroll
+            for (int p2 = 0; p2 < NP; ++p2)
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const int rho = 16 * (2 * p2 + e / 4) + 4 * g + (e % 4);
+                    Ap[m][p2][e] = (e_t)(GF[rho * KP + 16 * m + c] * gscale);
+                }
+            if constexpr (ODD) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int rho = 16 * (MT - 1) + 4 * g + e;
+                    Ao[m][e] = (e_t)(GF[rho * KP + 16 * m + c] * gscale);
+                }
+            }
+        }
+        for (int i = lane; i < KP * kChunk; i += kWave) Et[i] = 0.f;
+        for (int64_t tc = t0; tc < t1; tc += kChunk) {
+            const int nst = (int)min((int64_t)kChunk, t1 - tc);
+            stage_emissions<kChunk>(K, tc, nst, flag, xy, sc, Et, ssum, bad, sh);
+            for (int tl = 0; tl < nst; tl += 2) {
+                float evu[MT][RS][2];
+#pragma unroll
+                for (int m = 0; m < MT; ++m)
+#pragma unroll
+                    for (int r = 0; r < RS; ++r) {
+                        const float2 q = *reinterpret_cast<const float2 *>(&Et[(S * m + rit<S>(g, r)) * kChunk + tl]);
+                        evu[m][r][0] = q.x;
+                        evu[m][r][1] = q.y;
+                    }
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    if (tl + u >= nst) break;
+                    float ev[MT][RS];
+#pragma unroll
+                    for (int m = 0; m < MT; ++m)
+#pragma unroll
+                        for (int r = 0; r < RS; ++r) ev[m][r] = evu[m][r][u];
+                    // pack N (columns of every tile) to 16-bit B operands
+                    v8 Bp[NP > 0 ? NP : 1][MT];
+                    v4 Bo[MT];
+#pragma unroll
+                    for (int n = 0; n < MT; ++n) {
+#pragma unroll
+                        for (int p2 = 0; p2 < NP; ++p2)
+#pragma unroll
+                            for (int e = 0; e < 8; ++e) Bp[p2][n][e] = (e_t)P.B[2 * p2 + e / 4][n][e % 4];
+                        if constexpr (ODD) {
+#pragma unroll
+                            for (int e = 0; e < 4; ++e) Bo[n][e] = (e_t)P.B[MT - 1][n][e];
+                        }
+                    }
+                    acc_t C[MT][MT];
+#pragma unroll
+                    for (int m = 0; m < MT; ++m)
+#pragma unroll
+                        for (int n = 0; n < MT; ++n) {
+                            acc_t acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                            for (int p2 = 0; p2 < NP; ++p2) acc = lp::mma32(Ap[m][p2], Bp[p2][n], acc);
+                            if constexpr (ODD) acc = lp::mma16(Ao[m], Bo[n], acc);
+                            C[m][n] = acc;
+                        }
+                    renorm_columns<S, MT, true>(C, ev, P);
+                }
+            }
+            wave_sync_lds();
+        }
+        // remove the Gamma pre-scale: one factor 2^shift per observation
+        if (lane == 0) ssum -= (long long)lp::shift * (t1 - t0);
+    }
+    if (__any(bad) && lane == 0) atomicOr(status, kBadData);
     ssum = wave_sum_i64(ssum);
     workgroup_tree<S, MT, NSL>(P, ssum, smem, region);
     if (w == 0)

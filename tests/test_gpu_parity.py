@@ -187,8 +187,8 @@ def test_host_errors(binding, ctx):
     prm, obs = synth.make(3, 100, seed=34)
     d = binding.to_device(prm, obs)
     with pytest.raises(binding.HMMError) as e:
-        ctx.loglik(**d, algo="blocked_bf16")
-    assert e.value.code == binding.HMM_E_UNSUPPORTED
+        ctx.loglik(**d, algo=7)
+    assert e.value.code == binding.HMM_E_INVALID_ARG
     d2 = dict(d)
     d2["xy"] = d["xy"].float()
     with pytest.raises(TypeError):
@@ -196,3 +196,55 @@ def test_host_errors(binding, ctx):
     prm, obs = synth.make(81, 100, seed=35)
     with pytest.raises(binding.HMMError):
         ctx.loglik(**binding.to_device(prm, obs), algo="blocked_f32")
+
+
+# ---------------------------------------------------------------- 16-bit operands
+U_OP = {"blocked_bf16": 2.0 ** -8, "blocked_f16": 2.0 ** -11}
+
+
+def lowp_bound(algo, K, T):
+    """A-priori |d ln L| bound for 16-bit operands with FP32 accumulation: all
+    factors are nonnegative, so each step adds at most 2*u_op (operand rounding
+    of Gamma and N) + (K+1)*2^-24 (FP32 accumulation) relative error, plus
+    K*2^-24 for FP16 subnormal flushes of N's small entries."""
+    eta = 2 * U_OP[algo] + (K + 1) * 2.0 ** -24
+    if algo == "blocked_f16":
+        eta += K * 2.0 ** -24
+    return T * eta
+
+
+@pytest.mark.parametrize("algo", ["blocked_bf16", "blocked_f16"])
+@pytest.mark.parametrize("K", [3, 16, 25, 40, 64, 80])
+def test_blocked_16bit_within_bound(binding, ctx, algo, K):
+    T = 4000 + 37 * K
+    prm, obs = synth.make(K, T, seed=200 + K)
+    want = ref(prm, obs)
+    bound = lowp_bound(algo, K, T)
+    for L in (0, 100):
+        got = gpu(binding, ctx, prm, obs, algo, L, 0)
+        err = abs(got - want)
+        print(f"{algo} K={K} T={T} L={L}: |d ln L| = {err:.3e} nats (bound {bound:.3e}), "
+              f"rel {err / abs(want):.2e}")
+        assert err <= bound, (algo, K, L, err, bound)
+
+
+# ---------------------------------------------------------------- full-size K=80 workload
+def golden(name):
+    import json
+    import os
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "oracle_values.json")))[name]
+    prm, obs = synth.make(K=g["K"], T=g["T"], seed=g["seed"])
+    assert obs.digest() == g["inputs_sha256"], "generator output changed: rerun make_oracle_values.py"
+    return prm, obs, g["loglik"]
+
+
+def test_full_size_k80_t4m_all_precisions(binding, ctx):
+    prm, obs, want = golden("k80_t4m")
+    got = gpu(binding, ctx, prm, obs, "blocked_f32")
+    assert_close(got, want, "blocked_f32 k80_t4m")
+    for algo in ("blocked_bf16", "blocked_f16"):
+        got = gpu(binding, ctx, prm, obs, algo)
+        err = abs(got - want)
+        bound = lowp_bound(algo, 80, obs.T)
+        print(f"{algo} k80_t4m: |d ln L| = {err:.3e} nats, rel {err / abs(want):.2e} (bound {bound:.3e})")
+        assert err <= bound

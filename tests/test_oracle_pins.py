@@ -248,3 +248,13 @@ def test_edge_cases(oracle_mod):
     fl[4] = 1
     xy[4] = (np.nan, 1.0)
     assert math.isnan(oracle_mod.loglik(*args[:5], fl, xy))
+
+
+def test_stored_oracle_values_are_current(oracle_mod):
+    """The stored oracle value for the benchmark workload matches a live run
+    (the larger ones are checked the same way by make_oracle_values.py)."""
+    g = json.load(open(os.path.join(HERE, "golden", "oracle_values.json")))["k25_t1e6"]
+    prm, obs = synth.make(K=g["K"], T=g["T"], seed=g["seed"])
+    assert obs.digest() == g["inputs_sha256"]
+    got = oracle_mod.loglik(prm.delta, prm.Gamma, prm.p, prm.mu, prm.Sigma, obs.flag, obs.xy)
+    assert got == g["loglik"]
