@@ -616,7 +616,9 @@ __global__ __launch_bounds__(64 * group_waves(S * MT)) void k_blocked(int K, int
 // as the B operand.  v_mfma_f32_16x16x32_{bf16,f16} contracts 32 rows: lane
 // group g supplies 8 of them, the rows it holds of two row tiles (2p, 2p+1):
 // element e of its operand is contraction row 16*(2p + e/4) + 4g + e%4.  An
-// odd last row tile uses v_mfma_f32_16x16x16_{bf16,f16} (4 rows per group).
+// odd last row tile uses the same instruction with elements 4..7 zero, so
+// that every accumulation chain uses one opcode (a 16x16x32 result fed as
+// the accumulator of a 16x16x16 instruction gave wrong sums on gfx950).
 // Gamma^T is converted once per segment; for FP16 it is pre-scaled by
 // 2^kF16GammaShift to keep small transition probabilities out of FP16's
 // subnormal range, and each step's extra factor is removed from the shift
@@ -628,29 +630,19 @@ template <bool F16> struct Lp;
 template <> struct Lp<false> {
     typedef __bf16 e_t;
     typedef __bf16 v8 __attribute__((ext_vector_type(8)));
-    typedef __bf16 v4 __attribute__((ext_vector_type(4)));
     static constexpr int shift = 0;
     __device__ static Tile<16>::acc_t mma32(v8 a, v8 b, Tile<16>::acc_t c)
     {
         return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
     }
-    __device__ static Tile<16>::acc_t mma16(v4 a, v4 b, Tile<16>::acc_t c)
-    {
-        return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
-    }
 };
 template <> struct Lp<true> {
     typedef _Float16 e_t;
     typedef _Float16 v8 __attribute__((ext_vector_type(8)));
-    typedef _Float16 v4 __attribute__((ext_vector_type(4)));
     static constexpr int shift = kF16GammaShift;
     __device__ static Tile<16>::acc_t mma32(v8 a, v8 b, Tile<16>::acc_t c)
     {
         return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
-    }
-    __device__ static Tile<16>::acc_t mma16(v4 a, v4 b, Tile<16>::acc_t c)
-    {
-        return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
     }
 };
 
@@ -666,7 +658,6 @@ __global__ __launch_bounds__(64 * group_waves(16 * MT)) void k_blocked_lp(
     typedef Lp<F16> lp;
     typedef typename lp::e_t e_t;
     typedef typename lp::v8 v8;
-    typedef typename lp::v4 v4;
     extern __shared__ __attribute__((aligned(16))) float smem[];
     constexpr int region = Region<KP>::floats;
 
@@ -687,7 +678,7 @@ __global__ __launch_bounds__(64 * group_waves(16 * MT)) void k_blocked_lp(
         const int64_t t1 = min(T, t0 + L);
         const float gscale = (float)(1 << lp::shift);
         v8 Ap[MT][NP > 0 ? NP : 1];
-        v4 Ao[MT];
+        v8 Ao[MT];
 #pragma unroll
         for (int m = 0; m < MT; ++m) {
 #pragma unroll
@@ -699,9 +690,9 @@ __global__ __launch_bounds__(64 * group_waves(16 * MT)) void k_blocked_lp(
                 }
             if constexpr (ODD) {
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
+                for (int e = 0; e < 8; ++e) {
                     const int rho = 16 * (MT - 1) + 4 * g + e;
-                    Ao[m][e] = (e_t)(GF[rho * KP + 16 * m + c] * gscale);
+                    Ao[m][e] = (e < 4) ? (e_t)(GF[rho * KP + 16 * m + c] * gscale) : (e_t)0.f;
                 }
             }
         }
@@ -729,7 +720,7 @@ __global__ __launch_bounds__(64 * group_waves(16 * MT)) void k_blocked_lp(
                         for (int r = 0; r < RS; ++r) ev[m][r] = evu[m][r][u];
                     // pack N (columns of every tile) to 16-bit B operands
                     v8 Bp[NP > 0 ? NP : 1][MT];
-                    v4 Bo[MT];
+                    v8 Bo[MT];
 #pragma unroll
                     for (int n = 0; n < MT; ++n) {
 #pragma unroll
@@ -738,7 +729,7 @@ __global__ __launch_bounds__(64 * group_waves(16 * MT)) void k_blocked_lp(
                             for (int e = 0; e < 8; ++e) Bp[p2][n][e] = (e_t)P.B[2 * p2 + e / 4][n][e % 4];
                         if constexpr (ODD) {
 #pragma unroll
-                            for (int e = 0; e < 4; ++e) Bo[n][e] = (e_t)P.B[MT - 1][n][e];
+                            for (int e = 0; e < 8; ++e) Bo[n][e] = (e < 4) ? (e_t)P.B[MT - 1][n][e] : (e_t)0.f;
                         }
                     }
                     acc_t C[MT][MT];
@@ -749,7 +740,7 @@ __global__ __launch_bounds__(64 * group_waves(16 * MT)) void k_blocked_lp(
                             acc_t acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                             for (int p2 = 0; p2 < NP; ++p2) acc = lp::mma32(Ap[m][p2], Bp[p2][n], acc);
-                            if constexpr (ODD) acc = lp::mma16(Ao[m], Bo[n], acc);
+                            if constexpr (ODD) acc = lp::mma32(Ao[m], Bo[n], acc);
                             C[m][n] = acc;
                         }
                     renorm_columns<S, MT, true>(C, ev, P);
