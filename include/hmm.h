@@ -100,6 +100,46 @@ int hmm_loglik(hmm_ctx *ctx, int32_t K, const double *delta, const double *Gamma
                const uint8_t *flag, const double *xy, int32_t algo, void *stream,
                double *out);
 
+/* ln L of eq. (2) for n independent parameter sets, each with its own K and
+ * observation sequence, in one launch sequence (batched evaluation of MCMC
+ * chains or proposals).  The descriptor arrays are HOST arrays of n entries:
+ *   K[s]          states of set s, 1 <= K[s] <= 80
+ *   T[s]          observations of set s, 0 <= T[s] < 2^40
+ *   param_off[s]  offset (in doubles) of set s's parameter block in `params`
+ *   obs_off[s]    offset (in observations) of set s's sequence in flag / xy
+ * Device arrays: `params` (params_len doubles) holds for every set the block
+ *   delta[K] | Gamma[K*K] (row-major) | p[K] | mu[2K] | Sigma[3K]
+ * flag (obs_len entries) / xy (2*obs_len) as in hmm_loglik; sets may share
+ * observations (equal obs_off).  Every block and sequence must lie inside
+ * its array (checked on the host: HMM_E_INVALID_ARG otherwise);
+ * out[n] receives ln L of every set, with hmm_loglik's conventions (NaN for
+ * invalid parameters or data of that set, -inf for L = 0).
+ * algo: HMM_BLOCKED_F32 / _BF16 / _F16.  The context builds a plan (job
+ * tables, per-set scratch) for these descriptors and device pointers and, by
+ * default, captures the launch sequence in a HIP graph; a later call with
+ * identical descriptors and pointers (the parameter VALUES may change)
+ * replays the graph.  The plan depends on the segment lengths tuned by
+ * hmm_autotune_batched. */
+int hmm_loglik_batched(hmm_ctx *ctx, int32_t n, const int32_t *K, const int64_t *T,
+                       const int64_t *param_off, const double *params, int64_t params_len,
+                       const int64_t *obs_off, const uint8_t *flag, const double *xy,
+                       int64_t obs_len, int32_t algo, void *stream, double *out);
+
+/* Use (on != 0, default) or bypass HIP graph capture for batched calls. */
+int hmm_ctx_set_batch_graph(hmm_ctx *ctx, int32_t on);
+
+/* Segment-length autotuner of the batched path: for every class of sets that
+ * share a kernel, times the class's launches (reps repetitions after one
+ * warm-up) for segment lengths 256..4096 on the caller's own inputs and keeps
+ * the fastest in the context (used by later batched calls).  Synchronous;
+ * writes out[] as a side effect.  chosen_L (host, n entries, may be NULL)
+ * receives the length chosen for each set. */
+int hmm_autotune_batched(hmm_ctx *ctx, int32_t n, const int32_t *K, const int64_t *T,
+                         const int64_t *param_off, const double *params, int64_t params_len,
+                         const int64_t *obs_off, const uint8_t *flag, const double *xy,
+                         int64_t obs_len, int32_t algo, double *out, int32_t reps,
+                         int64_t *chosen_L);
+
 /* The emission stage of the GPU paths (eq. 1) on its own, for inspection.
  * For every observation t it writes the integer shift s_t (shift[t]) and the
  * scaled emissions  e_hat[t*K + k] = e_{t,k} * 2^(-s_t)  in FP32, where

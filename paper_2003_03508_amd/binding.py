@@ -43,10 +43,15 @@ _lib.hmm_blocked_plan.argtypes = [_vp, _i32, _i64, ctypes.POINTER(_i64), ctypes.
                                   ctypes.POINTER(_i32)]
 _lib.hmm_ctx_profile.argtypes = [_vp, _i32]
 _lib.hmm_ctx_profile_read.argtypes = [_vp, ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_double)]
+_lib.hmm_loglik_batched.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _i64, _i32, _vp, _vp]
+_lib.hmm_ctx_set_batch_graph.argtypes = [_vp, _i32]
+_lib.hmm_autotune_batched.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _i64, _i32, _vp,
+                                      _i32, _vp]
 _lib.hmm_status_string.restype = ctypes.c_char_p
 _lib.hmm_status_string.argtypes = [ctypes.c_int]
 for _f in ("hmm_ctx_create", "hmm_ctx_destroy", "hmm_loglik", "hmm_emission",
-           "hmm_ctx_set_blocking", "hmm_blocked_plan", "hmm_ctx_profile", "hmm_ctx_profile_read"):
+           "hmm_ctx_set_blocking", "hmm_blocked_plan", "hmm_ctx_profile", "hmm_ctx_profile_read",
+           "hmm_loglik_batched", "hmm_ctx_set_batch_graph", "hmm_autotune_batched"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 
@@ -141,6 +146,57 @@ class Context:
         _check("hmm_loglik", rc)
         return out
 
+    def batch_graph(self, on=True):
+        _check("hmm_ctx_set_batch_graph", _lib.hmm_ctx_set_batch_graph(self._h, 1 if on else 0))
+
+    @staticmethod
+    def _desc(K, T, param_off, obs_off):
+        import numpy as np
+        K = np.ascontiguousarray(K, dtype=np.int32)
+        T = np.ascontiguousarray(T, dtype=np.int64)
+        param_off = np.ascontiguousarray(param_off, dtype=np.int64)
+        obs_off = np.ascontiguousarray(obs_off, dtype=np.int64)
+        n = K.shape[0]
+        if not (T.shape[0] == param_off.shape[0] == obs_off.shape[0] == n):
+            raise ValueError("descriptor arrays must have the same length")
+        return n, K, T, param_off, obs_off
+
+    def loglik_batched(self, K, T, param_off, params, obs_off, flag, xy, algo="blocked_f32",
+                       out=None, stream=None):
+        """ln L of n packed sets (host descriptors K, T, param_off, obs_off; device params,
+        flag, xy).  Returns the device float64[n] result."""
+        n, K, T, param_off, obs_off = self._desc(K, T, param_off, obs_off)
+        if out is None:
+            out = torch.empty(n, dtype=torch.float64, device=params.device)
+        a = ALGOS[algo] if isinstance(algo, str) else int(algo)
+        if xy.numel() != 2 * flag.numel():
+            raise ValueError("xy must hold two coordinates per observation")
+        rc = _lib.hmm_loglik_batched(self._h, n, K.ctypes.data, T.ctypes.data, param_off.ctypes.data,
+                                     _dev(params, torch.float64, "params"), params.numel(),
+                                     obs_off.ctypes.data, _dev(flag, torch.uint8, "flag"),
+                                     _dev(xy, torch.float64, "xy"), flag.numel(), a, _stream(stream),
+                                     _dev(out, torch.float64, "out", n))
+        _check("hmm_loglik_batched", rc)
+        return out
+
+    def autotune_batched(self, K, T, param_off, params, obs_off, flag, xy, algo="blocked_f32",
+                         reps=3):
+        """Tune the batched path's segment lengths on these inputs; returns the chosen L per set."""
+        import numpy as np
+        n, K, T, param_off, obs_off = self._desc(K, T, param_off, obs_off)
+        out = torch.empty(n, dtype=torch.float64, device=params.device)
+        chosen = np.zeros(n, dtype=np.int64)
+        a = ALGOS[algo] if isinstance(algo, str) else int(algo)
+        if xy.numel() != 2 * flag.numel():
+            raise ValueError("xy must hold two coordinates per observation")
+        rc = _lib.hmm_autotune_batched(self._h, n, K.ctypes.data, T.ctypes.data, param_off.ctypes.data,
+                                       _dev(params, torch.float64, "params"), params.numel(),
+                                       obs_off.ctypes.data, _dev(flag, torch.uint8, "flag"),
+                                       _dev(xy, torch.float64, "xy"), flag.numel(), a,
+                                       _dev(out, torch.float64, "out", n), int(reps), chosen.ctypes.data)
+        _check("hmm_autotune_batched", rc)
+        return chosen
+
     def emission(self, p, mu, Sigma, flag, xy, stream=None):
         """(shift int32[T], e_hat float32[T, K], status int32[1]) of the emission stage."""
         K = int(p.numel())
@@ -156,6 +212,14 @@ class Context:
                                _dev(e_hat, torch.float32, "e_hat"), _dev(status, torch.int32, "status"))
         _check("hmm_emission", rc)
         return shift, e_hat, status
+
+
+def batch_to_device(packed, device="cuda"):
+    """Device tensors for a packed batch (synth.pack / synth.batch)."""
+    return dict(K=packed["K"], T=packed["T"], param_off=packed["param_off"], obs_off=packed["obs_off"],
+                params=torch.as_tensor(packed["params"], dtype=torch.float64, device=device).contiguous(),
+                flag=torch.as_tensor(packed["flag"], dtype=torch.uint8, device=device).contiguous(),
+                xy=torch.as_tensor(packed["xy"], dtype=torch.float64, device=device).contiguous())
 
 
 def to_device(prm, obs, device="cuda"):

@@ -1,4 +1,9 @@
-// Host runtime of the C ABI declared in include/hmm.h.
+// Host runtime of the C ABI declared in include/hmm.h: contexts, the
+// single-set likelihood, the emission stage, timing and the blocked plan.
+// This unit also holds the blocked kernels with small tiles (FP32 tiles of
+// side <= 48, 16-bit kernels with <= 3 row tiles); it is compiled with MFMA
+// results kept in ordinary VGPRs, because those kernels read their
+// accumulators with vector ALU code after every step.
 #include <climits>
 #include <cstddef>
 #include <cstdint>
@@ -12,6 +17,58 @@
 #include "hmm_host.hpp"
 
 using namespace hmmh;
+
+namespace hmmh {
+
+namespace {
+
+template <int S, int MT, int LO, int HI>
+bool pick_f32(int nsl, KernelSet *ks)
+{
+    if constexpr (LO > HI) {
+        return false;
+    } else {
+        if (nsl == LO) {
+            *ks = kernel_set_f32<S, MT, LO>();
+            return true;
+        }
+        return pick_f32<S, MT, LO + 1, HI>(nsl, ks);
+    }
+}
+
+template <int MT, bool F16, int LO, int HI>
+bool pick_lp(int nsl, KernelSet *ks)
+{
+    if constexpr (LO > HI) {
+        return false;
+    } else {
+        if (nsl == LO) {
+            *ks = kernel_set_lp<MT, F16, LO>();
+            return true;
+        }
+        return pick_lp<MT, F16, LO + 1, HI>(nsl, ks);
+    }
+}
+
+}  // namespace
+
+bool kernels_small(int algo, int S, int MT, int NSL, KernelSet *ks)
+{
+    if (algo == HMM_BLOCKED_F32) {
+        if (S == 16 && MT == 1) return pick_f32<16, 1, 1, 4>(NSL, ks);
+        if (S == 32 && MT == 1) return pick_f32<32, 1, 9, 16>(NSL, ks);
+        if (S == 16 && MT == 3) return pick_f32<16, 3, 9, 12>(NSL, ks);
+        return false;
+    }
+    const bool f16 = (algo == HMM_BLOCKED_F16);
+    if (S != 16) return false;
+    if (MT == 1) return f16 ? pick_lp<1, true, 1, 4>(NSL, ks) : pick_lp<1, false, 1, 4>(NSL, ks);
+    if (MT == 2) return f16 ? pick_lp<2, true, 5, 8>(NSL, ks) : pick_lp<2, false, 5, 8>(NSL, ks);
+    if (MT == 3) return f16 ? pick_lp<3, true, 9, 12>(NSL, ks) : pick_lp<3, false, 9, 12>(NSL, ks);
+    return false;
+}
+
+}  // namespace hmmh
 
 namespace {
 
@@ -32,41 +89,6 @@ int launch_status(void)
 }
 
 }  // namespace
-
-namespace hmmh {
-
-int run_blocked_small(const Shape &sh, int K, hmm_ctx *ctx, const double *delta, int64_t T,
-                      const uint8_t *flag, const double *xy, hipStream_t st, double *out, const Plan &pl,
-                      const Layout &ly)
-{
-    switch (sh.S * 100 + sh.MT) {
-    case 1601:
-        return dispatch_nsl<16, 1, 1, 4>(needed_slots<16, 1>(K), ctx, K, delta, T, flag, xy, st, out, pl, ly);
-    case 3201:
-        return dispatch_nsl<32, 1, 9, 16>(needed_slots<32, 1>(K), ctx, K, delta, T, flag, xy, st, out, pl, ly);
-    case 1603:
-        return dispatch_nsl<16, 3, 9, 12>(needed_slots<16, 3>(K), ctx, K, delta, T, flag, xy, st, out, pl, ly);
-    default:
-        return HMM_E_UNSUPPORTED;
-    }
-}
-
-int run_blocked_lp_small(int MT, bool f16, int K, hmm_ctx *ctx, const double *delta, int64_t T,
-                         const uint8_t *flag, const double *xy, hipStream_t st, double *out, const Plan &pl,
-                         const Layout &ly)
-{
-    switch (MT * 2 + (f16 ? 1 : 0)) {
-    case 2: return dispatch_lp<1, false, 1, 4>(needed_slots<16, 1>(K), ctx, K, delta, T, flag, xy, st, out, pl, ly);
-    case 3: return dispatch_lp<1, true, 1, 4>(needed_slots<16, 1>(K), ctx, K, delta, T, flag, xy, st, out, pl, ly);
-    case 4: return dispatch_lp<2, false, 5, 8>(needed_slots<16, 2>(K), ctx, K, delta, T, flag, xy, st, out, pl, ly);
-    case 5: return dispatch_lp<2, true, 5, 8>(needed_slots<16, 2>(K), ctx, K, delta, T, flag, xy, st, out, pl, ly);
-    case 6: return dispatch_lp<3, false, 9, 12>(needed_slots<16, 3>(K), ctx, K, delta, T, flag, xy, st, out, pl, ly);
-    case 7: return dispatch_lp<3, true, 9, 12>(needed_slots<16, 3>(K), ctx, K, delta, T, flag, xy, st, out, pl, ly);
-    default: return HMM_E_UNSUPPORTED;
-    }
-}
-
-}  // namespace hmmh
 
 extern "C" {
 
@@ -93,14 +115,14 @@ int hmm_ctx_destroy(hmm_ctx *ctx)
     int rc = HMM_OK;
     {
         DeviceGuard dg(ctx->device);
-        if (ctx->ws || !ctx->events.empty()) {
-            if (hipDeviceSynchronize() != hipSuccess) rc = HMM_E_DEVICE;
-        }
+        if (hipDeviceSynchronize() != hipSuccess) rc = HMM_E_DEVICE;
         if (ctx->ws) (void)hipFree(ctx->ws);
         for (auto &e : ctx->events) {
             (void)hipEventDestroy(e.first);
             (void)hipEventDestroy(e.second);
         }
+        batch_plan_free(ctx->batch);
+        ctx->batch = nullptr;
     }
     delete ctx;
     return rc;
@@ -162,28 +184,32 @@ int hmm_loglik(hmm_ctx *ctx, int32_t K, const double *delta, const double *Gamma
         return launch_status();
     }
 
-    Shape sh;
-    if (!blocked_shape(K, &sh)) return HMM_E_UNSUPPORTED;
-    const bool lp = (algo == HMM_BLOCKED_BF16 || algo == HMM_BLOCKED_F16);
-    if (lp) sh = Shape{16, (K + 15) / 16};  // 16-bit operands always use 16x16 tiles
-    const int KP = sh.KP();
+    KernelSet ks;
+    if (!select_kernels(algo, K, &ks)) return HMM_E_UNSUPPORTED;
+    const int KP = ks.KP();
     Plan pl = make_plan(ctx, KP, T);
     if (pl.n1 > INT_MAX) return HMM_E_UNSUPPORTED;
     Layout ly = make_layout(KP, pl);
     rc = ensure_ws(ctx, ly.total);
     if (rc != HMM_OK) return rc;
-    hipLaunchKernelGGL(k_prepare, dim3(1), dim3(256), 0, st, K, KP, delta, Gamma, p, mu, Sigma,
-                       at<StateConst>(ctx->ws, ly.sc), at<float>(ctx->ws, ly.gf),
-                       at<int>(ctx->ws, ly.status));
-    if (lp) {
-        const bool f16 = (algo == HMM_BLOCKED_F16);
-        rc = (sh.MT <= 3) ? run_blocked_lp_small(sh.MT, f16, K, ctx, delta, T, flag, xy, st, out, pl, ly)
-                          : run_blocked_lp_large(sh.MT, f16, K, ctx, delta, T, flag, xy, st, out, pl, ly);
-        if (rc != HMM_OK) return rc;
-        return launch_status();
-    }
-    rc = (KP <= 48) ? run_blocked_small(sh, K, ctx, delta, T, flag, xy, st, out, pl, ly)
-                    : run_blocked_large(sh, K, ctx, delta, T, flag, xy, st, out, pl, ly);
+    int *status = at<int>(ctx->ws, ly.status);
+    StateConst *sc = at<StateConst>(ctx->ws, ly.sc);
+    float *gf = at<float>(ctx->ws, ly.gf);
+    hipLaunchKernelGGL(k_prepare, dim3(1), dim3(256), 0, st, K, KP, delta, Gamma, p, mu, Sigma, sc, gf,
+                       status);
+    SetDesc d;
+    d.flag = flag;
+    d.xy = xy;
+    d.sc = sc;
+    d.GF = gf;
+    d.delta = delta;
+    d.status = status;
+    d.out = out;
+    d.T = T;
+    d.L = pl.L;
+    d.K = K;
+    d.pad = 0;
+    rc = run_single(ctx, ks, d, pl, ly, st);
     if (rc != HMM_OK) return rc;
     return launch_status();
 }

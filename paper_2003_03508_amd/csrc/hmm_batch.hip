@@ -1,0 +1,441 @@
+// Batched likelihood: many parameter sets (MCMC chains or proposals) with
+// uneven K and T evaluated by one captured launch sequence, and the segment
+// length autotuner.
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <numeric>
+
+#include "hmm_host.hpp"
+
+namespace hmmh {
+
+// Sets that share one kernel instantiation (operand precision, tile shape,
+// live contraction slots) form a class: one segment launch and one fold
+// launch per class.
+struct BatchClass {
+    KernelSet ks;
+    int W = 1, W2 = 1;
+    int64_t L = 0;
+    std::vector<int> sets;
+    size_t job0 = 0, njobs = 0;   // WgJob table range
+    size_t fjob0 = 0, nfjobs = 0; // FoldJob table range (one per set)
+    float *M = nullptr;
+    long long *E = nullptr, *S = nullptr;
+};
+
+struct BatchPlan {
+    // what the plan was built for
+    int n = 0, algo = 0;
+    std::vector<int32_t> K;
+    std::vector<int64_t> T, param_off, obs_off;
+    const double *params = nullptr;
+    const uint8_t *flag = nullptr;
+    const double *xy = nullptr;
+    double *out = nullptr;
+    std::map<std::pair<int, int>, int64_t> tuned;
+    // device memory
+    void *mem = nullptr;
+    SetDesc *sets = nullptr;
+    PrepJob *prep = nullptr;
+    WgJob *jobs = nullptr;
+    FoldJob *fjobs = nullptr;
+    std::vector<BatchClass> classes;
+    // captured launch sequence
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+void batch_plan_free(BatchPlan *bp)
+{
+    if (!bp) return;
+    if (bp->exec) (void)hipGraphExecDestroy(bp->exec);
+    if (bp->graph) (void)hipGraphDestroy(bp->graph);
+    if (bp->cap) (void)hipStreamDestroy(bp->cap);
+    if (bp->mem) (void)hipFree(bp->mem);
+    delete bp;
+}
+
+namespace {
+
+// Segment length of a class: long segments keep the combination tree small;
+// at least ~4 workgroups per CU keep the GPU busy.  A tuned value wins.
+int64_t class_L(const hmm_ctx *ctx, const BatchPlan &bp, const BatchClass &c, int algo, int W)
+{
+    for (int s : c.sets) {
+        auto it = ctx->tuned_L.find({bp.K[s], algo});
+        if (it != ctx->tuned_L.end() && it->second > 0) return it->second;
+    }
+    if (ctx->block_len > 0) return ctx->block_len;
+    int64_t tot = 0;
+    for (int s : c.sets) tot += bp.T[s];
+    int64_t L = tot / (256LL * 4 * W);
+    L = (L / kChunk) * kChunk;
+    return std::max<int64_t>(128, std::min<int64_t>(2048, L));
+}
+
+int build(hmm_ctx *ctx, BatchPlan &bp)
+{
+    const int n = bp.n;
+    // classes
+    std::vector<KernelSet> kss(n);
+    for (int s = 0; s < n; ++s)
+        if (!select_kernels(bp.algo, bp.K[s], &kss[s])) return HMM_E_UNSUPPORTED;
+    for (int s = 0; s < n; ++s) {
+        auto it = std::find_if(bp.classes.begin(), bp.classes.end(),
+                               [&](const BatchClass &c) { return c.ks.seg1 == kss[s].seg1; });
+        if (it == bp.classes.end()) {
+            BatchClass c;
+            c.ks = kss[s];
+            c.W = group_waves(c.ks.KP());
+            c.W2 = c.W;
+            bp.classes.push_back(c);
+            it = bp.classes.end() - 1;
+        }
+        it->sets.push_back(s);
+    }
+    // job tables (host)
+    std::vector<WgJob> jobs;
+    std::vector<FoldJob> fjobs;
+    std::vector<size_t> prods(bp.classes.size(), 0);
+    for (size_t ci = 0; ci < bp.classes.size(); ++ci) {
+        BatchClass &c = bp.classes[ci];
+        c.L = class_L(ctx, bp, c, bp.algo, c.W);
+        c.job0 = jobs.size();
+        c.fjob0 = fjobs.size();
+        int64_t base = 0;
+        for (int s : c.sets) {
+            const int64_t nb = bp.T[s] > 0 ? (bp.T[s] + c.L - 1) / c.L : 0;
+            const int64_t n1 = (nb + c.W - 1) / c.W;
+            for (int64_t q = 0; q < n1; ++q) {
+                WgJob j;
+                j.seg0 = q * c.W;
+                j.out = base + q;
+                j.set = s;
+                j.nseg = (int)std::min<int64_t>(c.W, nb - q * c.W);
+                jobs.push_back(j);
+            }
+            FoldJob f;
+            f.in0 = base;
+            f.n_in = n1;
+            f.out = 0;
+            f.set = s;
+            f.F = (int)std::max<int64_t>(1, (n1 + c.W2 - 1) / c.W2);
+            f.final_ = 1;
+            f.pad = 0;
+            fjobs.push_back(f);
+            base += n1;
+        }
+        c.njobs = jobs.size() - c.job0;
+        c.nfjobs = fjobs.size() - c.fjob0;
+        prods[ci] = (size_t)std::max<int64_t>(base, 1);
+    }
+    // device memory: tables, per-set slots, per-class products
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align_up(off + bytes);
+        return o;
+    };
+    const size_t o_sets = take(sizeof(SetDesc) * n), o_prep = take(sizeof(PrepJob) * n);
+    const size_t o_jobs = take(sizeof(WgJob) * std::max<size_t>(jobs.size(), 1));
+    const size_t o_fjobs = take(sizeof(FoldJob) * std::max<size_t>(fjobs.size(), 1));
+    const size_t o_status = take(sizeof(int) * n);
+    std::vector<size_t> o_sc(n), o_gf(n);
+    for (int s = 0; s < n; ++s) {
+        const int KP = kss[s].KP();
+        o_sc[s] = take(sizeof(StateConst) * KP);
+        o_gf[s] = take(sizeof(float) * KP * KP);
+    }
+    std::vector<size_t> o_m(bp.classes.size()), o_e(bp.classes.size()), o_s(bp.classes.size());
+    for (size_t ci = 0; ci < bp.classes.size(); ++ci) {
+        const int KP = bp.classes[ci].ks.KP();
+        o_m[ci] = take(sizeof(float) * KP * KP * prods[ci]);
+        o_e[ci] = take(sizeof(long long) * KP * prods[ci]);
+        o_s[ci] = take(sizeof(long long) * prods[ci]);
+    }
+    if (hipMalloc(&bp.mem, off) != hipSuccess) {
+        (void)hipGetLastError();
+        bp.mem = nullptr;
+        return HMM_E_NOMEM;
+    }
+    char *base = static_cast<char *>(bp.mem);
+    bp.sets = reinterpret_cast<SetDesc *>(base + o_sets);
+    bp.prep = reinterpret_cast<PrepJob *>(base + o_prep);
+    bp.jobs = reinterpret_cast<WgJob *>(base + o_jobs);
+    bp.fjobs = reinterpret_cast<FoldJob *>(base + o_fjobs);
+    int *status = reinterpret_cast<int *>(base + o_status);
+    for (size_t ci = 0; ci < bp.classes.size(); ++ci) {
+        bp.classes[ci].M = reinterpret_cast<float *>(base + o_m[ci]);
+        bp.classes[ci].E = reinterpret_cast<long long *>(base + o_e[ci]);
+        bp.classes[ci].S = reinterpret_cast<long long *>(base + o_s[ci]);
+    }
+    std::vector<SetDesc> hs(n);
+    std::vector<PrepJob> hp(n);
+    for (int s = 0; s < n; ++s) {
+        const BatchClass *c = nullptr;
+        for (const auto &cc : bp.classes)
+            if (cc.ks.seg1 == kss[s].seg1) c = &cc;
+        SetDesc &d = hs[s];
+        d.flag = bp.flag + bp.obs_off[s];
+        d.xy = bp.xy + 2 * bp.obs_off[s];
+        d.sc = reinterpret_cast<const StateConst *>(base + o_sc[s]);
+        d.GF = reinterpret_cast<const float *>(base + o_gf[s]);
+        d.delta = bp.params + bp.param_off[s];
+        d.status = status + s;
+        d.out = bp.out + s;
+        d.T = bp.T[s];
+        d.L = c->L;
+        d.K = bp.K[s];
+        d.pad = 0;
+        PrepJob &pj = hp[s];
+        pj.params = bp.params + bp.param_off[s];
+        pj.sc = reinterpret_cast<StateConst *>(base + o_sc[s]);
+        pj.GF = reinterpret_cast<float *>(base + o_gf[s]);
+        pj.status = status + s;
+        pj.K = bp.K[s];
+        pj.KP = kss[s].KP();
+    }
+    if (hipMemcpy(bp.sets, hs.data(), sizeof(SetDesc) * n, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(bp.prep, hp.data(), sizeof(PrepJob) * n, hipMemcpyHostToDevice) != hipSuccess ||
+        (!jobs.empty() &&
+         hipMemcpy(bp.jobs, jobs.data(), sizeof(WgJob) * jobs.size(), hipMemcpyHostToDevice) != hipSuccess) ||
+        hipMemcpy(bp.fjobs, fjobs.data(), sizeof(FoldJob) * fjobs.size(), hipMemcpyHostToDevice) != hipSuccess)
+        return HMM_E_DEVICE;
+    for (const auto &c : bp.classes) {
+        const size_t rb = (size_t)region_bytes(c.ks.KP());
+        if (allow_lds(c.ks.segB, rb * c.W) != HMM_OK || allow_lds(c.ks.foldB, rb * c.W2) != HMM_OK)
+            return HMM_E_DEVICE;
+    }
+    return HMM_OK;
+}
+
+// The launch sequence of a plan on one stream (also what the graph records).
+int enqueue(const BatchPlan &bp, hipStream_t st, const BatchClass *only = nullptr)
+{
+    if (!only) hipLaunchKernelGGL(k_prepare_batch, dim3(bp.n), dim3(256), 0, st, bp.prep);
+    SetDesc none;
+    std::memset(&none, 0, sizeof(none));
+    for (const auto &c : bp.classes) {
+        if (only && &c != only) continue;
+        const size_t rb = (size_t)region_bytes(c.ks.KP());
+        if (c.njobs > 0 &&
+            launch_seg(c.ks.segB, (unsigned)c.njobs, c.W, rb * c.W, st, none, bp.sets, bp.jobs + c.job0, 0, c.M,
+                       c.E, c.S) != hipSuccess)
+            return HMM_E_DEVICE;
+        if (launch_fold(c.ks.foldB, (unsigned)c.nfjobs, c.W2, rb * c.W2, st, none, bp.sets, bp.fjobs + c.fjob0, 0,
+                        1, 1, c.M, c.E, c.S, nullptr, nullptr, nullptr) != hipSuccess)
+            return HMM_E_DEVICE;
+    }
+    return HMM_OK;
+}
+
+int capture(BatchPlan &bp)
+{
+    if (hipStreamCreateWithFlags(&bp.cap, hipStreamNonBlocking) != hipSuccess) return HMM_E_DEVICE;
+    if (hipStreamBeginCapture(bp.cap, hipStreamCaptureModeThreadLocal) != hipSuccess) return HMM_E_DEVICE;
+    int rc = enqueue(bp, bp.cap);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(bp.cap, &g);
+    if (rc != HMM_OK || e != hipSuccess || !g) {
+        if (g) (void)hipGraphDestroy(g);
+        (void)hipGetLastError();
+        return HMM_E_DEVICE;
+    }
+    bp.graph = g;
+    if (hipGraphInstantiate(&bp.exec, bp.graph, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        bp.exec = nullptr;
+        return HMM_E_DEVICE;
+    }
+    return HMM_OK;
+}
+
+bool same_plan(const BatchPlan &bp, const hmm_ctx *ctx, int n, const int32_t *K, const int64_t *T,
+               const int64_t *param_off, const double *params, const int64_t *obs_off, const uint8_t *flag,
+               const double *xy, int algo, double *out)
+{
+    if (bp.n != n || bp.algo != algo || bp.params != params || bp.flag != flag || bp.xy != xy || bp.out != out)
+        return false;
+    if (bp.tuned != ctx->tuned_L) return false;
+    return std::equal(K, K + n, bp.K.begin()) && std::equal(T, T + n, bp.T.begin()) &&
+           std::equal(param_off, param_off + n, bp.param_off.begin()) &&
+           std::equal(obs_off, obs_off + n, bp.obs_off.begin());
+}
+
+int get_plan(hmm_ctx *ctx, int n, const int32_t *K, const int64_t *T, const int64_t *param_off,
+             const double *params, const int64_t *obs_off, const uint8_t *flag, const double *xy, int algo,
+             double *out, BatchPlan **res)
+{
+    if (ctx->batch && same_plan(*ctx->batch, ctx, n, K, T, param_off, params, obs_off, flag, xy, algo, out)) {
+        *res = ctx->batch;
+        return HMM_OK;
+    }
+    if (ctx->batch) {
+        if (hipDeviceSynchronize() != hipSuccess) return HMM_E_DEVICE;
+        batch_plan_free(ctx->batch);
+        ctx->batch = nullptr;
+    }
+    BatchPlan *bp = new BatchPlan;
+    bp->n = n;
+    bp->algo = algo;
+    bp->K.assign(K, K + n);
+    bp->T.assign(T, T + n);
+    bp->param_off.assign(param_off, param_off + n);
+    bp->obs_off.assign(obs_off, obs_off + n);
+    bp->params = params;
+    bp->flag = flag;
+    bp->xy = xy;
+    bp->out = out;
+    bp->tuned = ctx->tuned_L;
+    int rc = build(ctx, *bp);
+    if (rc == HMM_OK && ctx->batch_graph) rc = capture(*bp);
+    if (rc != HMM_OK) {
+        batch_plan_free(bp);
+        return rc;
+    }
+    ctx->batch = bp;
+    *res = bp;
+    return HMM_OK;
+}
+
+int check_batch(hmm_ctx *ctx, int32_t n, const int32_t *K, const int64_t *T, const int64_t *param_off,
+                const double *params, int64_t params_len, const int64_t *obs_off, const uint8_t *flag,
+                const double *xy, int64_t obs_len, int32_t algo, double *out)
+{
+    if (!ctx || n < 1 || !K || !T || !param_off || !params || !obs_off || !out) return HMM_E_INVALID_ARG;
+    if (algo != HMM_BLOCKED_F32 && algo != HMM_BLOCKED_BF16 && algo != HMM_BLOCKED_F16) {
+        if (algo == HMM_SERIAL_F32) return HMM_E_UNSUPPORTED;
+        return HMM_E_INVALID_ARG;
+    }
+    bool any_obs = false;
+    for (int s = 0; s < n; ++s) {
+        if (K[s] < 1 || K[s] > 80 || T[s] < 0 || T[s] >= kMaxT || param_off[s] < 0 || obs_off[s] < 0)
+            return HMM_E_INVALID_ARG;
+        const int64_t blk = (int64_t)K[s] * (K[s] + 7);  // delta, Gamma, p, mu, Sigma
+        if (param_off[s] > params_len - blk || obs_off[s] > obs_len - T[s]) return HMM_E_INVALID_ARG;
+        any_obs |= T[s] > 0;
+    }
+    if (any_obs && (!flag || !xy)) return HMM_E_INVALID_ARG;
+    return HMM_OK;
+}
+
+}  // namespace
+
+}  // namespace hmmh
+
+using namespace hmmh;
+
+extern "C" {
+
+int hmm_loglik_batched(hmm_ctx *ctx, int32_t n, const int32_t *K, const int64_t *T, const int64_t *param_off,
+                       const double *params, int64_t params_len, const int64_t *obs_off, const uint8_t *flag,
+                       const double *xy, int64_t obs_len, int32_t algo, void *stream, double *out)
+{
+    int rc = check_batch(ctx, n, K, T, param_off, params, params_len, obs_off, flag, xy, obs_len, algo, out);
+    if (rc != HMM_OK) return rc;
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return HMM_E_DEVICE;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    BatchPlan *bp = nullptr;
+    rc = get_plan(ctx, n, K, T, param_off, params, obs_off, flag, xy, algo, out, &bp);
+    if (rc != HMM_OK) return rc;
+    if (bp->exec) {
+        if (hipGraphLaunch(bp->exec, st) != hipSuccess) {
+            (void)hipGetLastError();
+            return HMM_E_DEVICE;
+        }
+        return HMM_OK;
+    }
+    rc = enqueue(*bp, st);
+    if (rc != HMM_OK) return rc;
+    return hipGetLastError() == hipSuccess ? HMM_OK : HMM_E_DEVICE;
+}
+
+int hmm_ctx_set_batch_graph(hmm_ctx *ctx, int32_t on)
+{
+    if (!ctx) return HMM_E_INVALID_ARG;
+    ctx->batch_graph = on != 0;
+    if (ctx->batch) {
+        DeviceGuard dg(ctx->device);
+        if (hipDeviceSynchronize() != hipSuccess) return HMM_E_DEVICE;
+        batch_plan_free(ctx->batch);
+        ctx->batch = nullptr;
+    }
+    return HMM_OK;
+}
+
+int hmm_autotune_batched(hmm_ctx *ctx, int32_t n, const int32_t *K, const int64_t *T, const int64_t *param_off,
+                         const double *params, int64_t params_len, const int64_t *obs_off, const uint8_t *flag,
+                         const double *xy, int64_t obs_len, int32_t algo, double *out, int32_t reps,
+                         int64_t *chosen_L)
+{
+    int rc = check_batch(ctx, n, K, T, param_off, params, params_len, obs_off, flag, xy, obs_len, algo, out);
+    if (rc != HMM_OK) return rc;
+    if (reps < 1) reps = 3;
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return HMM_E_DEVICE;
+    const int64_t cands[] = {256, 512, 1024, 2048, 4096};
+    // distinct K values of the batch, tuned one class at a time
+    std::vector<int> ks(K, K + n);
+    std::sort(ks.begin(), ks.end());
+    ks.erase(std::unique(ks.begin(), ks.end()), ks.end());
+    hipStream_t st = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return HMM_E_DEVICE;
+    hipEvent_t e0, e1;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    const bool graph_was = ctx->batch_graph;
+    ctx->batch_graph = false;
+    for (int k : ks) ctx->tuned_L.erase({k, algo});
+    // classes are independent: time each class's launches under each candidate
+    std::map<const void *, std::pair<double, int64_t>> best;  // class seg kernel -> (ms, L)
+    for (int64_t L : cands) {
+        for (int k : ks) ctx->tuned_L[{k, algo}] = L;
+        BatchPlan *bp = nullptr;
+        rc = get_plan(ctx, n, K, T, param_off, params, obs_off, flag, xy, algo, out, &bp);
+        if (rc != HMM_OK) break;
+        hipLaunchKernelGGL(k_prepare_batch, dim3(bp->n), dim3(256), 0, st, bp->prep);
+        for (const auto &c : bp->classes) {
+            float tot = 0.f;
+            for (int r = 0; r <= reps; ++r) {
+                (void)hipEventRecord(e0, st);
+                rc = enqueue(*bp, st, &c);
+                (void)hipEventRecord(e1, st);
+                if (rc != HMM_OK) break;
+                (void)hipEventSynchronize(e1);
+                float ms = 0.f;
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                if (r > 0) tot += ms;  // first run warms up
+            }
+            const double avg = tot / reps;
+            auto it = best.find(c.ks.seg1);
+            if (it == best.end() || avg < it->second.first) best[c.ks.seg1] = {avg, L};
+        }
+        if (rc != HMM_OK) break;
+    }
+    // record the winner for every K of each class
+    if (rc == HMM_OK) {
+        for (int k : ks) {
+            KernelSet kset;
+            if (!select_kernels(algo, k, &kset)) continue;
+            auto it = best.find(kset.seg1);
+            ctx->tuned_L[{k, algo}] = (it != best.end()) ? it->second.second : 0;
+        }
+        if (chosen_L)
+            for (int s = 0; s < n; ++s) chosen_L[s] = ctx->tuned_L[{K[s], algo}];
+    }
+    ctx->batch_graph = graph_was;
+    (void)hipStreamSynchronize(st);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipStreamDestroy(st);
+    if (ctx->batch) {
+        batch_plan_free(ctx->batch);
+        ctx->batch = nullptr;
+    }
+    return rc;
+}
+
+}  // extern "C"

@@ -5,6 +5,9 @@
 #include <climits>
 #include <cstddef>
 #include <cstdint>
+#include <map>
+#include <memory>
+#include <mutex>
 #include <utility>
 #include <vector>
 
@@ -12,6 +15,11 @@
 
 #include "../../include/hmm.h"
 #include "hmm_kernels.hpp"
+
+namespace hmmh {
+struct BatchPlan;                  // hmm_batch.hip
+void batch_plan_free(BatchPlan *);
+}  // namespace hmmh
 
 struct hmm_ctx {
     int device = 0;
@@ -23,6 +31,11 @@ struct hmm_ctx {
     bool profile = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
     size_t events_used = 0;
+    // batched path: the last plan (descriptor tables, scratch, captured graph)
+    hmmh::BatchPlan *batch = nullptr;
+    bool batch_graph = true;
+    // tuned segment length per (K, algo) for the batched path (0 = heuristic)
+    std::map<std::pair<int, int>, int64_t> tuned_L;
 };
 
 namespace hmmh {
@@ -171,38 +184,114 @@ T *at(void *base, size_t off)
     return reinterpret_cast<T *>(static_cast<char *>(base) + off);
 }
 
-// Allow `bytes` of dynamic LDS for kernel `fn` (needed above 64 KiB).
+// Allow `bytes` of dynamic LDS for kernel `fn` (needed above 64 KiB); the
+// attribute is set once per kernel.
 inline int allow_lds(const void *fn, size_t bytes)
 {
-    if (bytes <= 64 * 1024) return HMM_OK;
-    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) {
+    static std::mutex mu;
+    static std::map<const void *, size_t> done;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = done.find(fn);
+    if (it != done.end() && it->second >= bytes) return HMM_OK;
+    if (bytes > 64 * 1024 &&
+        hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) {
         (void)hipGetLastError();
         return HMM_E_DEVICE;
     }
+    done[fn] = bytes;
     return HMM_OK;
 }
 
-// Launch sequence of the blocked path: parameter preparation is done by the
-// caller; here the segment kernel (FP32 or 16-bit operands) and the fold tree.
-template <int S, int MT, int NSL, typename SegKernel>
-int run_blocked_with(SegKernel seg, hmm_ctx *ctx, int K, const double *delta, int64_t T,
-                     const uint8_t *flag, const double *xy, hipStream_t st, double *out, const Plan &pl,
-                     const Layout &ly, int &lds_ok)
-{
-    constexpr int KP = S * MT;
-    void *ws = ctx->ws;
-    int *status = at<int>(ws, ly.status);
-    const StateConst *sc = at<StateConst>(ws, ly.sc);
-    const float *gf = at<float>(ws, ly.gf);
-    const size_t rb = (size_t)region_bytes(KP);
-    if (lds_ok < 0) {
-        lds_ok = (allow_lds(reinterpret_cast<const void *>(seg), rb * pl.W) == HMM_OK &&
-                  allow_lds(reinterpret_cast<const void *>(&k_fold<S, MT, NSL>), rb * pl.W2) == HMM_OK)
-                     ? 1
-                     : 0;
-    }
-    if (!lds_ok) return HMM_E_DEVICE;
+// The kernels of one blocked configuration (operand precision, tile shape,
+// live contraction slots): single-set and batched segment and fold kernels.
+struct KernelSet {
+    const void *seg1 = nullptr, *segB = nullptr, *fold1 = nullptr, *foldB = nullptr;
+    int S = 0, MT = 0, NSL = 0;
+    int KP() const { return S * MT; }
+};
 
+template <int S, int MT, int NSL>
+KernelSet kernel_set_f32()
+{
+    KernelSet k;
+    k.seg1 = reinterpret_cast<const void *>(&k_blocked<S, MT, NSL, false>);
+    k.segB = reinterpret_cast<const void *>(&k_blocked<S, MT, NSL, true>);
+    k.fold1 = reinterpret_cast<const void *>(&k_fold<S, MT, NSL, false>);
+    k.foldB = reinterpret_cast<const void *>(&k_fold<S, MT, NSL, true>);
+    k.S = S;
+    k.MT = MT;
+    k.NSL = NSL;
+    return k;
+}
+
+template <int MT, bool F16, int NSL>
+KernelSet kernel_set_lp()
+{
+    KernelSet k;
+    k.seg1 = reinterpret_cast<const void *>(&k_blocked_lp<MT, F16, NSL, false>);
+    k.segB = reinterpret_cast<const void *>(&k_blocked_lp<MT, F16, NSL, true>);
+    k.fold1 = reinterpret_cast<const void *>(&k_fold<16, MT, NSL, false>);
+    k.foldB = reinterpret_cast<const void *>(&k_fold<16, MT, NSL, true>);
+    k.S = 16;
+    k.MT = MT;
+    k.NSL = NSL;
+    return k;
+}
+
+// Runtime number of live contraction slots (same rule as needed_slots<S, MT>).
+inline int live_slots(int S, int MT, int K)
+{
+    const int RS = S * S / 64;
+    int n = 0;
+    for (int j = 0; j < MT * RS; ++j) {
+        const int r = j % RS;
+        const int row = S * (j / RS) + (S == 16 ? r : 8 * (r >> 2) + (r & 3));
+        if (row < K) n = j + 1;
+    }
+    return n;
+}
+
+// Kernel sets compiled in hmm_api.hip (FP32 tiles with KP <= 48, 16-bit with
+// MT <= 3) and hmm_large.hip (the rest).  Return false if not there.
+bool kernels_small(int algo, int S, int MT, int NSL, KernelSet *ks);
+bool kernels_large(int algo, int S, int MT, int NSL, KernelSet *ks);
+
+inline bool select_kernels(int algo, int K, KernelSet *ks)
+{
+    Shape sh;
+    if (!blocked_shape(K, &sh)) return false;
+    if (algo == HMM_BLOCKED_BF16 || algo == HMM_BLOCKED_F16) sh = Shape{16, (K + 15) / 16};
+    const int nsl = live_slots(sh.S, sh.MT, K);
+    return kernels_small(algo, sh.S, sh.MT, nsl, ks) || kernels_large(algo, sh.S, sh.MT, nsl, ks);
+}
+
+inline hipError_t launch_seg(const void *fn, unsigned grid, int W, size_t lds, hipStream_t st, SetDesc one,
+                             const SetDesc *sets, const WgJob *jobs, int64_t nb, float *M, long long *E,
+                             long long *Ssum)
+{
+    void *args[] = {&one, &sets, &jobs, &nb, &M, &E, &Ssum};
+    return hipLaunchKernel(fn, dim3(grid), dim3(64 * W), args, lds, st);
+}
+
+inline hipError_t launch_fold(const void *fn, unsigned grid, int W2, size_t lds, hipStream_t st, SetDesc one,
+                              const SetDesc *sets, const FoldJob *jobs, int64_t n_in, int F, int final_,
+                              const float *Min, const long long *Ein, const long long *Sin, float *Mout,
+                              long long *Eout, long long *Sout)
+{
+    void *args[] = {&one, &sets, &jobs, &n_in, &F, &final_, &Min, &Ein, &Sin, &Mout, &Eout, &Sout};
+    return hipLaunchKernel(fn, dim3(grid), dim3(64 * W2), args, lds, st);
+}
+
+// Single-set blocked path after parameter preparation: segment kernel, then
+// fold levels (m0 -> m1 -> m2 -> m1 -> ...) until one workgroup finishes ln L.
+inline int run_single(hmm_ctx *ctx, const KernelSet &ks, SetDesc d, const Plan &pl, const Layout &ly,
+                      hipStream_t st)
+{
+    const int KP = ks.KP();
+    void *ws = ctx->ws;
+    const size_t rb = (size_t)region_bytes(KP);
+    if (allow_lds(ks.seg1, rb * pl.W) != HMM_OK || allow_lds(ks.fold1, rb * pl.W2) != HMM_OK)
+        return HMM_E_DEVICE;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     if (ctx->profile && pl.nb > 0 && ctx->events_used < kMaxTimed) {
         if (ctx->events_used == ctx->events.size()) {
@@ -216,13 +305,11 @@ int run_blocked_with(SegKernel seg, hmm_ctx *ctx, int K, const double *delta, in
         ++ctx->events_used;
     }
     if (ev0) (void)hipEventRecord(ev0, st);
-    if (pl.nb > 0) {
-        hipLaunchKernelGGL(seg, dim3((unsigned)pl.n1), dim3(64 * pl.W), rb * pl.W, st, K, T, pl.L, pl.nb, gf,
-                           sc, flag, xy, at<float>(ws, ly.m0), at<long long>(ws, ly.e0),
-                           at<long long>(ws, ly.s0), status);
-    }
+    if (pl.nb > 0 &&
+        launch_seg(ks.seg1, (unsigned)pl.n1, pl.W, rb * pl.W, st, d, nullptr, nullptr, pl.nb,
+                   at<float>(ws, ly.m0), at<long long>(ws, ly.e0), at<long long>(ws, ly.s0)) != hipSuccess)
+        return HMM_E_DEVICE;
     if (ev1) (void)hipEventRecord(ev1, st);
-    // Fold levels: m0 -> m1 -> m2 -> m1 -> ... until one workgroup remains.
     int64_t n = pl.n1;
     const float *mi = at<float>(ws, ly.m0);
     const long long *ei = at<long long>(ws, ly.e0), *si = at<long long>(ws, ly.s0);
@@ -233,79 +320,19 @@ int run_blocked_with(SegKernel seg, hmm_ctx *ctx, int K, const double *delta, in
         float *mo = at<float>(ws, which == 1 ? ly.m1 : ly.m2);
         long long *eo = at<long long>(ws, which == 1 ? ly.e1 : ly.e2);
         long long *so = at<long long>(ws, which == 1 ? ly.s1 : ly.s2);
-        hipLaunchKernelGGL((k_fold<S, MT, NSL>), dim3((unsigned)nout), dim3(64 * pl.W2), rb * pl.W2, st, K,
-                           n, pl.F, mi, ei, si, mo, eo, so, 0, delta, status, out);
+        if (launch_fold(ks.fold1, (unsigned)nout, pl.W2, rb * pl.W2, st, d, nullptr, nullptr, n, pl.F, 0, mi,
+                        ei, si, mo, eo, so) != hipSuccess)
+            return HMM_E_DEVICE;
         mi = mo;
         ei = eo;
         si = so;
         n = nout;
         which = 3 - which;
     }
-    hipLaunchKernelGGL((k_fold<S, MT, NSL>), dim3(1), dim3(64 * pl.W2), rb * pl.W2, st, K, n, pl.F, mi, ei,
-                       si, (float *)nullptr, (long long *)nullptr, (long long *)nullptr, 1, delta, status,
-                       out);
+    if (launch_fold(ks.fold1, 1, pl.W2, rb * pl.W2, st, d, nullptr, nullptr, n, pl.F, 1, mi, ei, si, nullptr,
+                    nullptr, nullptr) != hipSuccess)
+        return HMM_E_DEVICE;
     return HMM_OK;
 }
-
-template <int S, int MT, int NSL>
-int run_blocked(hmm_ctx *ctx, int K, const double *delta, int64_t T, const uint8_t *flag,
-                const double *xy, hipStream_t st, double *out, const Plan &pl, const Layout &ly)
-{
-    static int lds_ok = -1;
-    return run_blocked_with<S, MT, NSL>(&k_blocked<S, MT, NSL>, ctx, K, delta, T, flag, xy, st, out, pl, ly,
-                                        lds_ok);
-}
-
-template <int MT, bool F16, int NSL>
-int run_blocked_lp(hmm_ctx *ctx, int K, const double *delta, int64_t T, const uint8_t *flag,
-                   const double *xy, hipStream_t st, double *out, const Plan &pl, const Layout &ly)
-{
-    static int lds_ok = -1;
-    return run_blocked_with<16, MT, NSL>(&k_blocked_lp<MT, F16, NSL>, ctx, K, delta, T, flag, xy, st, out, pl,
-                                         ly, lds_ok);
-}
-
-// Runtime number of live contraction slots -> compile-time instantiation.
-template <int S, int MT, int LO, int HI>
-int dispatch_nsl(int nsl, hmm_ctx *ctx, int K, const double *delta, int64_t T, const uint8_t *flag,
-                 const double *xy, hipStream_t st, double *out, const Plan &pl, const Layout &ly)
-{
-    if constexpr (LO > HI) {
-        return HMM_E_UNSUPPORTED;
-    } else {
-        if (nsl == LO) return run_blocked<S, MT, LO>(ctx, K, delta, T, flag, xy, st, out, pl, ly);
-        return dispatch_nsl<S, MT, LO + 1, HI>(nsl, ctx, K, delta, T, flag, xy, st, out, pl, ly);
-    }
-}
-
-// 16-bit operands: 16x16 tiles, MT = ceil(K/16); nsl only selects the FP32 fold.
-template <int MT, bool F16, int LO, int HI>
-int dispatch_lp(int nsl, hmm_ctx *ctx, int K, const double *delta, int64_t T, const uint8_t *flag,
-                const double *xy, hipStream_t st, double *out, const Plan &pl, const Layout &ly)
-{
-    if constexpr (LO > HI) {
-        return HMM_E_UNSUPPORTED;
-    } else {
-        if (nsl == LO) return run_blocked_lp<MT, F16, LO>(ctx, K, delta, T, flag, xy, st, out, pl, ly);
-        return dispatch_lp<MT, F16, LO + 1, HI>(nsl, ctx, K, delta, T, flag, xy, st, out, pl, ly);
-    }
-}
-
-// Shapes with KP <= 48 (hmm_api.hip, accumulators in VGPRs) and KP >= 64
-// (hmm_large.hip, accumulators in AGPRs: these kernels need more than 256
-// registers per lane).
-int run_blocked_small(const Shape &sh, int K, hmm_ctx *ctx, const double *delta, int64_t T,
-                      const uint8_t *flag, const double *xy, hipStream_t st, double *out, const Plan &pl,
-                      const Layout &ly);
-int run_blocked_large(const Shape &sh, int K, hmm_ctx *ctx, const double *delta, int64_t T,
-                      const uint8_t *flag, const double *xy, hipStream_t st, double *out, const Plan &pl,
-                      const Layout &ly);
-// 16-bit operand paths: MT <= 3 in hmm_api.hip, MT 4..5 in hmm_large.hip.
-int run_blocked_lp_small(int MT, bool f16, int K, hmm_ctx *ctx, const double *delta, int64_t T,
-                         const uint8_t *flag, const double *xy, hipStream_t st, double *out, const Plan &pl,
-                         const Layout &ly);
-int run_blocked_lp_large(int MT, bool f16, int K, hmm_ctx *ctx, const double *delta, int64_t T,
-                         const uint8_t *flag, const double *xy, hipStream_t st, double *out, const Plan &pl,
-                         const Layout &ly);
 
 }  // namespace hmmh

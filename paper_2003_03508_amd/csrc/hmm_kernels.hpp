@@ -84,6 +84,45 @@ static __global__ __launch_bounds__(256) void k_prepare(int K, int KP, const dou
     if (threadIdx.x == 0) *status = bad ? kBadParams : 0;
 }
 
+// Batched preparation: workgroup s prepares set s from its packed FP64
+// parameter block  delta[K] | Gamma[K*K] | p[K] | mu[2K] | Sigma[3K].
+struct PrepJob {
+    const double *params;
+    StateConst *sc;
+    float *GF;
+    int *status;
+    int K, KP;
+};
+
+static __global__ __launch_bounds__(256) void k_prepare_batch(const PrepJob *__restrict__ jobs)
+{
+    const PrepJob j = jobs[blockIdx.x];
+    const int K = j.K, KP = j.KP;
+    const double *delta = j.params, *Gamma = delta + K, *p = Gamma + (int64_t)K * K, *mu = p + K,
+                 *Sigma = mu + 2 * K;
+    __shared__ int bad;
+    if (threadIdx.x == 0) bad = 0;
+    __syncthreads();
+    int mybad = 0;
+    for (int k = threadIdx.x; k < KP; k += blockDim.x) {
+        mybad |= prepare_state(k, K, p, mu, Sigma, j.sc);
+        if (k < K && !(isfinite(delta[k]) && delta[k] >= 0.0)) mybad = 1;
+    }
+    for (int idx = threadIdx.x; idx < KP * KP; idx += blockDim.x) {
+        const int i = idx / KP, jj = idx % KP;
+        float v = 0.f;
+        if (i < K && jj < K) {
+            const double gij = Gamma[(int64_t)i * K + jj];
+            if (!(isfinite(gij) && gij >= 0.0 && gij <= 1.0)) mybad = 1;
+            v = (float)gij;
+        }
+        j.GF[idx] = v;
+    }
+    if (mybad) atomicOr(&bad, 1);
+    __syncthreads();
+    if (threadIdx.x == 0) *j.status = bad ? kBadParams : 0;
+}
+
 // The state part of k_prepare alone (emission parameters only).
 static __global__ __launch_bounds__(256) void k_prepare_states(int K, int KP, const double *__restrict__ p,
                                                         const double *__restrict__ mu,
@@ -248,6 +287,32 @@ __global__ __launch_bounds__(64) void k_serial(int K, int64_t T, const double *_
 // N never leaves registers.  Slots are ordered by their smallest row, so the
 // slots touching a real state form a prefix of NSL slots.
 // ===========================================================================
+// One parameter set with its observation sequence, as the segment and fold
+// kernels see it (prepared constants, output and status of that set).
+struct SetDesc {
+    const uint8_t *flag;     // the set's observations
+    const double *xy;
+    const StateConst *sc;    // prepared per-state constants (KP entries)
+    const float *GF;         // Gamma in FP32, KP x KP, zero-padded
+    const double *delta;     // initial distribution (FP64)
+    int *status;             // the set's status word
+    double *out;             // the set's ln L
+    int64_t T, L;            // observations, segment length
+    int K, pad;
+};
+// Segment-kernel work item of a batch: segments [seg0, seg0 + nseg) of one set,
+// product written to slot `out`.
+struct WgJob {
+    int64_t seg0, out;
+    int set, nseg;
+};
+// Fold work item of a batch: products [in0, in0 + n_in) of one set, F per
+// wavefront; final_ finishes ln L of the set, otherwise writes slot `out`.
+struct FoldJob {
+    int64_t in0, n_in, out;
+    int set, F, final_, pad;
+};
+
 template <int S>
 __host__ __device__ constexpr int rit(int g, int r)
 {
@@ -511,16 +576,13 @@ __device__ __forceinline__ void workgroup_tree(Prod<S, MT> &P, long long &ssum, 
 // end the workgroup multiplies its W segment products in order (tree in LDS)
 // and writes one product: Mout[q] (KP x KP row-major), Eout[q][KP], Sout[q].
 // ---------------------------------------------------------------------------
-template <int S, int MT, int NSL>
-__global__ __launch_bounds__(64 * group_waves(S * MT)) void k_blocked(int K, int64_t T, int64_t L, int64_t nb,
-                                                 const float *__restrict__ GF,
-                                                 const StateConst *__restrict__ sc,
-                                                 const uint8_t *__restrict__ flag,
-                                                 const double *__restrict__ xy,
-                                                 float *__restrict__ Mout,
-                                                 long long *__restrict__ Eout,
-                                                 long long *__restrict__ Sout,
-                                                 int *__restrict__ status)
+template <int S, int MT, int NSL, bool BATCH>
+__global__ __launch_bounds__(64 * group_waves(S * MT)) void k_blocked(SetDesc one,
+                                                                      const SetDesc *__restrict__ sets,
+                                                                      const WgJob *__restrict__ jobs,
+                                                                      int64_t nb, float *__restrict__ Mout,
+                                                                      long long *__restrict__ Eout,
+                                                                      long long *__restrict__ Sout)
 {
     constexpr int KP = S * MT, RS = Tile<S>::RS;
     typedef typename Tile<S>::acc_t acc_t;
@@ -530,7 +592,25 @@ __global__ __launch_bounds__(64 * group_waves(S * MT)) void k_blocked(int K, int
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int c = lane % S, g = lane / S;
     const int W = blockDim.x >> 6;
-    const int64_t b = (int64_t)blockIdx.x * W + w;
+    WgJob job;
+    SetDesc d;
+    if constexpr (BATCH) {
+        job = jobs[blockIdx.x];
+        d = sets[job.set];
+    } else {
+        d = one;
+        job.seg0 = (int64_t)blockIdx.x * W;
+        job.nseg = (int)min((int64_t)W, nb - job.seg0);
+        job.out = blockIdx.x;
+        job.set = 0;
+    }
+    const int K = d.K;
+    const int64_t T = d.T, L = d.L;
+    const float *__restrict__ GF = d.GF;
+    const StateConst *__restrict__ sc = d.sc;
+    const uint8_t *__restrict__ flag = d.flag;
+    const double *__restrict__ xy = d.xy;
+    const int64_t b = job.seg0 + w;
     float *base = smem + w * region;
     float *Et = Region<KP>::E(base);  // Et[k][t], row stride kChunk
 
@@ -539,7 +619,7 @@ __global__ __launch_bounds__(64 * group_waves(S * MT)) void k_blocked(int K, int
     long long ssum = 0;
     int bad = 0, sh = 0;
 
-    if (b < nb) {
+    if (w < job.nseg) {
         const int64_t t0 = b * L;
         const int64_t t1 = min(T, t0 + L);
         float A[MT][NSL];
@@ -600,13 +680,12 @@ __global__ __launch_bounds__(64 * group_waves(S * MT)) void k_blocked(int K, int
             wave_sync_lds();
         }
     }
-    if (__any(bad) && lane == 0) atomicOr(status, kBadData);
+    if (__any(bad) && lane == 0) atomicOr(d.status, kBadData);
     // each lane summed the shifts of the observations it staged
     ssum = wave_sum_i64(ssum);
     workgroup_tree<S, MT, NSL>(P, ssum, smem, region);
     if (w == 0)
-        prod_to_global<S, MT>(P, ssum, Mout + (int64_t)blockIdx.x * KP * KP,
-                              Eout + (int64_t)blockIdx.x * KP, Sout + blockIdx.x);
+        prod_to_global<S, MT>(P, ssum, Mout + job.out * KP * KP, Eout + job.out * KP, Sout + job.out);
 }
 
 // ---------------------------------------------------------------------------
@@ -646,12 +725,13 @@ template <> struct Lp<true> {
     }
 };
 
-template <int MT, bool F16, int NSL>
-__global__ __launch_bounds__(64 * group_waves(16 * MT)) void k_blocked_lp(
-    int K, int64_t T, int64_t L, int64_t nb, const float *__restrict__ GF,
-    const StateConst *__restrict__ sc, const uint8_t *__restrict__ flag,
-    const double *__restrict__ xy, float *__restrict__ Mout, long long *__restrict__ Eout,
-    long long *__restrict__ Sout, int *__restrict__ status)
+template <int MT, bool F16, int NSL, bool BATCH>
+__global__ __launch_bounds__(64 * group_waves(16 * MT)) void k_blocked_lp(SetDesc one,
+                                                                          const SetDesc *__restrict__ sets,
+                                                                          const WgJob *__restrict__ jobs,
+                                                                          int64_t nb, float *__restrict__ Mout,
+                                                                          long long *__restrict__ Eout,
+                                                                          long long *__restrict__ Sout)
 {
     constexpr int S = 16, KP = 16 * MT, RS = 4, NP = MT / 2, ODD = MT % 2;
     typedef typename Tile<S>::acc_t acc_t;
@@ -664,7 +744,25 @@ __global__ __launch_bounds__(64 * group_waves(16 * MT)) void k_blocked_lp(
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int c = lane % S, g = lane / S;
     const int W = blockDim.x >> 6;
-    const int64_t b = (int64_t)blockIdx.x * W + w;
+    WgJob job;
+    SetDesc d;
+    if constexpr (BATCH) {
+        job = jobs[blockIdx.x];
+        d = sets[job.set];
+    } else {
+        d = one;
+        job.seg0 = (int64_t)blockIdx.x * W;
+        job.nseg = (int)min((int64_t)W, nb - job.seg0);
+        job.out = blockIdx.x;
+        job.set = 0;
+    }
+    const int K = d.K;
+    const int64_t T = d.T, L = d.L;
+    const float *__restrict__ GF = d.GF;
+    const StateConst *__restrict__ sc = d.sc;
+    const uint8_t *__restrict__ flag = d.flag;
+    const double *__restrict__ xy = d.xy;
+    const int64_t b = job.seg0 + w;
     float *base = smem + w * region;
     float *Et = Region<KP>::E(base);
 
@@ -673,7 +771,7 @@ __global__ __launch_bounds__(64 * group_waves(16 * MT)) void k_blocked_lp(
     long long ssum = 0;
     int bad = 0, sh = 0;
 
-    if (b < nb) {
+    if (w < job.nseg) {
         const int64_t t0 = b * L;
         const int64_t t1 = min(T, t0 + L);
         const float gscale = (float)(1 << lp::shift);
@@ -751,12 +849,11 @@ __global__ __launch_bounds__(64 * group_waves(16 * MT)) void k_blocked_lp(
         // remove the Gamma pre-scale: one factor 2^shift per observation
         if (lane == 0) ssum -= (long long)lp::shift * (t1 - t0);
     }
-    if (__any(bad) && lane == 0) atomicOr(status, kBadData);
+    if (__any(bad) && lane == 0) atomicOr(d.status, kBadData);
     ssum = wave_sum_i64(ssum);
     workgroup_tree<S, MT, NSL>(P, ssum, smem, region);
     if (w == 0)
-        prod_to_global<S, MT>(P, ssum, Mout + (int64_t)blockIdx.x * KP * KP,
-                              Eout + (int64_t)blockIdx.x * KP, Sout + blockIdx.x);
+        prod_to_global<S, MT>(P, ssum, Mout + job.out * KP * KP, Eout + job.out * KP, Sout + job.out);
 }
 
 // ---------------------------------------------------------------------------
@@ -767,17 +864,16 @@ __global__ __launch_bounds__(64 * group_waves(16 * MT)) void k_blocked_lp(
 // With final_ set there is a single workgroup and wave 0 finishes
 //     ln L = ln2*(ssum + e_max) + ln( sum_c delta_c 2^(ex_c - e_max) sum_j M~[c][j] ).
 // ---------------------------------------------------------------------------
-template <int S, int MT, int NSL>
-__global__ __launch_bounds__(64 * group_waves(S * MT)) void k_fold(int K, int64_t n_in, int F,
-                                               const float *__restrict__ Min,
-                                               const long long *__restrict__ Ein,
-                                               const long long *__restrict__ Sin,
-                                               float *__restrict__ Mout,
-                                               long long *__restrict__ Eout,
-                                               long long *__restrict__ Sout, int final_,
-                                               const double *__restrict__ delta,
-                                               const int *__restrict__ status,
-                                               double *__restrict__ out)
+template <int S, int MT, int NSL, bool BATCH>
+__global__ __launch_bounds__(64 * group_waves(S * MT)) void k_fold(SetDesc one, const SetDesc *__restrict__ sets,
+                                                                   const FoldJob *__restrict__ jobs,
+                                                                   int64_t n_in, int F, int final_,
+                                                                   const float *__restrict__ Min,
+                                                                   const long long *__restrict__ Ein,
+                                                                   const long long *__restrict__ Sin,
+                                                                   float *__restrict__ Mout,
+                                                                   long long *__restrict__ Eout,
+                                                                   long long *__restrict__ Sout)
 {
     constexpr int KP = S * MT, RS = Tile<S>::RS;
     extern __shared__ __attribute__((aligned(16))) float smem[];
@@ -786,11 +882,26 @@ __global__ __launch_bounds__(64 * group_waves(S * MT)) void k_fold(int K, int64_
     const int c = lane % S, g = lane / S;
     const int W = blockDim.x >> 6;
     float *base = smem + w * region;
+    FoldJob job;
+    SetDesc d;
+    if constexpr (BATCH) {
+        job = jobs[blockIdx.x];
+        d = sets[job.set];
+    } else {
+        d = one;
+        job.in0 = (int64_t)blockIdx.x * W * F;
+        job.n_in = min((int64_t)W * F, n_in - job.in0);
+        job.out = blockIdx.x;
+        job.F = F;
+        job.final_ = final_;
+        job.set = 0;
+    }
+    const int K = d.K;
 
     Prod<S, MT> P;
     long long ssum = 0;
-    const int64_t i0 = ((int64_t)blockIdx.x * W + w) * F;
-    const int64_t i1 = min(n_in, i0 + F);
+    const int64_t i0 = job.in0 + (int64_t)w * job.F;
+    const int64_t i1 = min(job.in0 + job.n_in, i0 + job.F);
     if (i0 < i1) {
         prod_from_global<S, MT>(P, ssum, Min + i0 * KP * KP, Ein + i0 * KP, Sin + i0);
         for (int64_t i = i0 + 1; i < i1; ++i) {
@@ -808,11 +919,11 @@ __global__ __launch_bounds__(64 * group_waves(S * MT)) void k_fold(int K, int64_
     }
     workgroup_tree<S, MT, NSL>(P, ssum, smem, region);
     if (w != 0) return;
-    if (!final_) {
-        prod_to_global<S, MT>(P, ssum, Mout + (int64_t)blockIdx.x * KP * KP, Eout + (int64_t)blockIdx.x * KP,
-                              Sout + blockIdx.x);
+    if (!job.final_) {
+        prod_to_global<S, MT>(P, ssum, Mout + job.out * KP * KP, Eout + job.out * KP, Sout + job.out);
         return;
     }
+    const double *__restrict__ delta = d.delta;
     double term[MT];
     long long emax = LLONG_MIN;
 #pragma unroll
@@ -842,12 +953,12 @@ __global__ __launch_bounds__(64 * group_waves(S * MT)) void k_fold(int K, int64_
     }
     const double sum = wave_sum_f64(part);
     if (lane == 0) {
-        const int st = *status;
+        const int st = *d.status;
         double ll;
         if (st) ll = __builtin_nan("");
         else if (!(sum > 0.0)) ll = -INFINITY;
         else ll = kLn2 * (double)(ssum + emax) + log(sum);
-        *out = ll;
+        *d.out = ll;
     }
 }
 

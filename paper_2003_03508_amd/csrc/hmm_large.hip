@@ -1,36 +1,54 @@
-// Blocked-path kernels for 48 < K <= 80 (tile sides 64 and 80).  Compiled
-// separately from hmm_api.hip so that their MFMA accumulators may live in
-// AGPRs (these kernels hold more than 256 values per lane).
+// Blocked-path kernels compiled with their MFMA accumulators allowed in
+// AGPRs: FP32 tiles of side 64 and 80 (more than 256 values per lane) and the
+// 16-bit-operand kernels with 4 or 5 row tiles.
 #include "hmm_host.hpp"
 
 namespace hmmh {
 
-int run_blocked_large(const Shape &sh, int K, hmm_ctx *ctx, const double *delta, int64_t T,
-                      const uint8_t *flag, const double *xy, hipStream_t st, double *out, const Plan &pl,
-                      const Layout &ly)
+namespace {
+
+template <int S, int MT, int LO, int HI>
+bool pick_f32(int nsl, KernelSet *ks)
 {
-    switch (sh.S * 100 + sh.MT) {
-    case 3202:
-        return dispatch_nsl<32, 2, 25, 32>(needed_slots<32, 2>(K), ctx, K, delta, T, flag, xy, st, out, pl, ly);
-    case 1605:
-        return dispatch_nsl<16, 5, 17, 20>(needed_slots<16, 5>(K), ctx, K, delta, T, flag, xy, st, out, pl, ly);
-    default:
-        return HMM_E_UNSUPPORTED;
+    if constexpr (LO > HI) {
+        return false;
+    } else {
+        if (nsl == LO) {
+            *ks = kernel_set_f32<S, MT, LO>();
+            return true;
+        }
+        return pick_f32<S, MT, LO + 1, HI>(nsl, ks);
     }
 }
 
-int run_blocked_lp_large(int MT, bool f16, int K, hmm_ctx *ctx, const double *delta, int64_t T,
-                         const uint8_t *flag, const double *xy, hipStream_t st, double *out, const Plan &pl,
-                         const Layout &ly)
+template <int MT, bool F16, int LO, int HI>
+bool pick_lp(int nsl, KernelSet *ks)
 {
-    const int nsl = (MT == 4) ? needed_slots<16, 4>(K) : needed_slots<16, 5>(K);
-    switch (MT * 2 + (f16 ? 1 : 0)) {
-    case 8: return dispatch_lp<4, false, 13, 16>(nsl, ctx, K, delta, T, flag, xy, st, out, pl, ly);
-    case 9: return dispatch_lp<4, true, 13, 16>(nsl, ctx, K, delta, T, flag, xy, st, out, pl, ly);
-    case 10: return dispatch_lp<5, false, 17, 20>(nsl, ctx, K, delta, T, flag, xy, st, out, pl, ly);
-    case 11: return dispatch_lp<5, true, 17, 20>(nsl, ctx, K, delta, T, flag, xy, st, out, pl, ly);
-    default: return HMM_E_UNSUPPORTED;
+    if constexpr (LO > HI) {
+        return false;
+    } else {
+        if (nsl == LO) {
+            *ks = kernel_set_lp<MT, F16, LO>();
+            return true;
+        }
+        return pick_lp<MT, F16, LO + 1, HI>(nsl, ks);
     }
+}
+
+}  // namespace
+
+bool kernels_large(int algo, int S, int MT, int NSL, KernelSet *ks)
+{
+    if (algo == HMM_BLOCKED_F32) {
+        if (S == 32 && MT == 2) return pick_f32<32, 2, 25, 32>(NSL, ks);
+        if (S == 16 && MT == 5) return pick_f32<16, 5, 17, 20>(NSL, ks);
+        return false;
+    }
+    const bool f16 = (algo == HMM_BLOCKED_F16);
+    if (S != 16) return false;
+    if (MT == 4) return f16 ? pick_lp<4, true, 13, 16>(NSL, ks) : pick_lp<4, false, 13, 16>(NSL, ks);
+    if (MT == 5) return f16 ? pick_lp<5, true, 17, 20>(NSL, ks) : pick_lp<5, false, 17, 20>(NSL, ks);
+    return false;
 }
 
 }  // namespace hmmh

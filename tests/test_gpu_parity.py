@@ -248,3 +248,87 @@ def test_full_size_k80_t4m_all_precisions(binding, ctx):
         bound = lowp_bound(algo, 80, obs.T)
         print(f"{algo} k80_t4m: |d ln L| = {err:.3e} nats, rel {err / abs(want):.2e} (bound {bound:.3e})")
         assert err <= bound
+
+
+# ---------------------------------------------------------------- batched evaluation
+def test_batched_matches_oracle_uneven_sets(binding, ctx):
+    """Sets with uneven K (every tile class 1..80) and T (incl. 0 and 1), some
+    sharing observations; every result vs the oracle, graph replay included."""
+    sets = []
+    Ks = [1, 3, 8, 16, 17, 20, 25, 32, 33, 40, 48, 49, 57, 64, 65, 72, 80, 25, 25, 7]
+    Ts = [5000, 1, 3000, 0, 4321, 2500, 6000, 3333, 2000, 1500, 1000, 1200, 900, 800, 700, 600, 500,
+          4000, 4000, 10]
+    for i, (K, T) in enumerate(zip(Ks, Ts)):
+        sets.append(synth.make(K, T, seed=300 + i))
+    # the last three share the observations of the 18th set (different parameters)
+    packed = synth.pack(sets)
+    packed["obs_off"][18] = packed["obs_off"][17]
+    packed["T"][18] = packed["T"][17]
+    want = []
+    for i, (prm, obs) in enumerate(sets):
+        o = sets[17][1] if i == 18 else obs
+        want.append(ref(prm, o))
+    d = binding.batch_to_device(packed)
+    for rep in range(3):  # first call builds + captures, later calls replay the graph
+        out = ctx.loglik_batched(**d, algo="blocked_f32")
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()
+        for i in range(len(sets)):
+            assert_close(float(got[i]), want[i], f"batched set {i} K={Ks[i]} T={packed['T'][i]} rep {rep}")
+    # parameters change in place: the replayed graph must read the new values
+    prm0, obs0 = sets[6]
+    p2 = synth.HMMParams(prm0.delta, prm0.Gamma, prm0.p * 0.5, prm0.mu, prm0.Sigma)
+    off = int(packed["param_off"][6])
+    blk = torch.as_tensor(p2.packed(), dtype=torch.float64, device="cuda")
+    d["params"][off:off + blk.numel()].copy_(blk)
+    out = ctx.loglik_batched(**d, algo="blocked_f32")
+    torch.cuda.synchronize()
+    assert_close(float(out[6].item()), ref(p2, obs0), "batched after in-place parameter update")
+
+
+@pytest.mark.parametrize("algo", ["blocked_bf16", "blocked_f16"])
+def test_batched_16bit(binding, ctx, algo):
+    sets = [synth.make(K, T, seed=400 + K) for K, T in [(3, 2000), (25, 3000), (40, 2500), (64, 1500), (80, 1200)]]
+    packed = synth.pack(sets)
+    d = binding.batch_to_device(packed)
+    out = ctx.loglik_batched(**d, algo=algo).cpu().numpy()
+    for i, (prm, obs) in enumerate(sets):
+        err = abs(out[i] - ref(prm, obs))
+        assert err <= lowp_bound(algo, prm.K, obs.T), (algo, i, err)
+
+
+def test_batched_invalid_set_is_isolated(binding, ctx):
+    sets = [synth.make(5, 1000, seed=500 + i) for i in range(3)]
+    sets[1][0].p[2] = 1.5  # invalid parameter in set 1 only
+    packed = synth.pack(sets)
+    out = ctx.loglik_batched(**binding.batch_to_device(packed)).cpu().numpy()
+    assert math.isnan(out[1])
+    for i in (0, 2):
+        assert_close(float(out[i]), ref(*sets[i]), f"set {i} next to an invalid one")
+
+
+def test_autotune_batched(binding, ctx):
+    sets = [synth.make(K, 20_000, seed=600 + K) for K in (12, 25, 25, 40)]
+    packed = synth.pack(sets)
+    d = binding.batch_to_device(packed)
+    chosen = ctx.autotune_batched(**d, reps=1)
+    assert all(L in (256, 512, 1024, 2048, 4096) for L in chosen)
+    assert chosen[1] == chosen[2]  # same class, same choice
+    out = ctx.loglik_batched(**d).cpu().numpy()
+    for i, (prm, obs) in enumerate(sets):
+        assert_close(float(out[i]), ref(prm, obs), f"tuned set {i}")
+
+
+def test_batched_rejects_out_of_range_descriptors(binding, ctx):
+    sets = [synth.make(5, 100, seed=700 + i) for i in range(2)]
+    packed = synth.pack(sets)
+    d = binding.batch_to_device(packed)
+    bad = dict(d)
+    bad["obs_off"] = packed["obs_off"] + 50  # second sequence runs past the end
+    with pytest.raises(binding.HMMError) as e:
+        ctx.loglik_batched(**bad)
+    assert e.value.code == binding.HMM_E_INVALID_ARG
+    bad = dict(d)
+    bad["param_off"] = packed["param_off"] + 1
+    with pytest.raises(binding.HMMError):
+        ctx.loglik_batched(**bad)
