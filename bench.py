@@ -12,6 +12,10 @@ dominant kernel (segment products; algorithmic flops 2*K^3 per observation,
 FP32 MFMA peak), and the oracle's own throughput on the host cores.
 
     python bench.py [--gpus 1] [--steps 200] [--warmup 10]
+
+Other workloads (one JSON line each, not the headline):
+    python bench.py --workload k80_t4m    # K=80, T=4,194,304: FP32, BF16, FP16 operands
+    python bench.py --workload batch256   # 256 sets, K in 8..64, T in 1e5..1e6, batched
 """
 import argparse
 import json
@@ -25,6 +29,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_FP32_MFMA_TFLOPS = 157.3  # MI355X dense FP32 matrix peak
+PEAK_16BIT_MFMA_TFLOPS = 2500.0  # MI355X dense BF16 / FP16 matrix peak
 PEAK_HBM_GBS = 8000.0
 COUNTERS = os.path.join(ROOT, "profiles", "k_blocked_k25_t1e6_counters.txt")
 
@@ -62,6 +67,7 @@ def measured_traffic():
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--workload", default="k25_t1e6", choices=["k25_t1e6", "k80_t4m", "batch256"])
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--serial-steps", type=int, default=3)
@@ -83,6 +89,10 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "k80_t4m":
+        return bench_k80(args)
+    if args.workload == "batch256":
+        return bench_batch(args)
 
     wl = synth.WORKLOADS["k25_t1e6"]
     K, T = wl["K"], wl["T"]
@@ -193,6 +203,115 @@ def main():
     }
     ctx.close()
     print(json.dumps(rec))
+
+
+def _timed(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def _stored_oracle(name, obs):
+    import json
+    path = os.path.join(ROOT, "tests", "golden", "oracle_values.json")
+    if os.path.exists(path):
+        g = json.load(open(path)).get(name)
+        if g and g["inputs_sha256"] == obs.digest():
+            return g["loglik"]
+    return None
+
+
+def bench_k80(args):
+    """K=80, T=4,194,304: the blocked path with FP32, BF16 and FP16 operands."""
+    import torch
+    from paper_2003_03508_amd import binding, synth
+    wl = synth.WORKLOADS["k80_t4m"]
+    K, T = wl["K"], wl["T"]
+    prm, obs = synth.make(**wl)
+    want = _stored_oracle("k80_t4m", obs)
+    if want is None:
+        import oracle
+        want = oracle.loglik(prm.delta, prm.Gamma, prm.p, prm.mu, prm.Sigma, obs.flag, obs.xy)
+    ctx = binding.Context(0)
+    d = binding.to_device(prm, obs)
+    out = torch.empty(1, dtype=torch.float64, device="cuda")
+    flops = 2.0 * T * K ** 3
+    res = {}
+    for algo, peak in (("blocked_f32", PEAK_FP32_MFMA_TFLOPS), ("blocked_bf16", PEAK_16BIT_MFMA_TFLOPS),
+                       ("blocked_f16", PEAK_16BIT_MFMA_TFLOPS)):
+        steps = max(3, args.steps // 20)
+        ctx.profile(True)
+        sec = _timed(lambda: ctx.loglik(**d, algo=algo, out=out), steps, 2)
+        n, ms = ctx.profile_read()
+        ctx.profile(False)
+        kern = ms / max(n, 1) * 1e-3
+        ll = float(out.item())
+        res[algo] = {"evals_per_s": round(1.0 / sec, 3), "ms_per_eval": round(sec * 1e3, 3),
+                     "segment_kernel_ms": round(kern * 1e3, 3),
+                     "achieved_tflops": round(flops / kern / 1e12, 2), "peak_tflops": peak,
+                     "frac": round(flops / kern / 1e12 / peak, 4),
+                     "abs_err_nats": abs(ll - want), "rel_err": abs(ll - want) / abs(want)}
+    ctx.close()
+    print(json.dumps({"workload": "k80_t4m: tremor HMM, K=80, T=4,194,304, seed 2", "unit": "evals/s",
+                      "oracle_loglik": want, "results": res}))
+
+
+def bench_batch(args):
+    """256 sets, K in 8..64, T in 1e5..1e6: one batched (graph-replayed) call
+    vs 256 sequential single-set calls of the same blocked path."""
+    import numpy as np
+    import torch
+    from paper_2003_03508_amd import binding, synth
+    packed, sets = synth.batch()
+    n = len(sets)
+    ctx = binding.Context(0)
+    d = binding.batch_to_device(packed)
+    flops = float(sum(2.0 * obs.T * prm.K ** 3 for prm, obs in sets))
+    obs_total = int(packed["T"].sum())
+    chosen = ctx.autotune_batched(**d, reps=1)
+    out = ctx.loglik_batched(**d)
+    torch.cuda.synchronize()
+    steps = max(3, args.steps // 40)
+    sec_b = _timed(lambda: ctx.loglik_batched(**d, out=out), steps, 1)
+    res_b = out.cpu().numpy()
+    # 256 sequential single-set calls (same inputs, device-resident)
+    singles = [binding.to_device(prm, obs) for prm, obs in sets]
+    outs = torch.empty(n, dtype=torch.float64, device="cuda")
+
+    def seq():
+        for i in range(n):
+            ctx.loglik(**singles[i], out=outs[i:i + 1])
+    sec_s = _timed(seq, max(2, steps // 2), 1)
+    res_s = outs.cpu().numpy()
+    # oracle on a sample of sets (host, one thread per set)
+    import oracle
+    oracle.build(force=False)
+    sample = list(range(0, n, max(1, n // 8)))[:8]
+    c0 = time.perf_counter()
+    sub = synth.pack([sets[i] for i in sample])
+    want = oracle.loglik_batch(sub["K"], sub["T"], sub["param_off"], sub["params"], sub["obs_off"],
+                               sub["flag"], sub["xy"], nthreads=len(sample))
+    c1 = time.perf_counter()
+    rel = [abs(res_b[i] - w) / abs(w) for i, w in zip(sample, want)]
+    ctx.close()
+    print(json.dumps({
+        "workload": "batch256: 256 tremor-HMM sets, K~U{8..64}, T~U[1e5,1e6], seed 3",
+        "unit": "sets/s", "n_sets": n, "observations": obs_total,
+        "batched": {"sets_per_s": round(n / sec_b, 2), "ms_per_batch": round(sec_b * 1e3, 3),
+                    "tflops": round(flops / sec_b / 1e12, 2), "graph": True,
+                    "tuned_L": sorted(set(int(x) for x in chosen))},
+        "sequential_single_calls": {"sets_per_s": round(n / sec_s, 2), "ms_per_batch": round(sec_s * 1e3, 3)},
+        "speedup_batched_vs_sequential": round(sec_s / sec_b, 3),
+        "max_rel_err_vs_oracle_sample": max(rel), "oracle_sample_sets": len(sample),
+        "oracle_sample_seconds": round(c1 - c0, 2),
+        "batched_vs_single_max_rel_diff": float(np.max(np.abs(res_b - res_s) / np.abs(res_s))),
+    }))
 
 
 if __name__ == "__main__":

@@ -25,10 +25,61 @@ Uniforms for steps 6-7 are drawn as whole arrays (u_state[T+1], u_flag[T],
 z[T, 2]) before the path is walked.
 """
 import bisect
+import ctypes
 import hashlib
+import os
+import subprocess
 from dataclasses import dataclass, field
 
 import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_WALK_SRC = os.path.join(_HERE, "synth_walk.c")
+_WALK_LIB = os.path.join(_HERE, "libsynth_walk.so")
+_walk = None
+
+
+def build_walker():
+    """Compile the C path walker (gcc); the generator uses it when present."""
+    subprocess.run(["gcc", "-O2", "-fPIC", "-shared", "-o", _WALK_LIB + ".tmp", _WALK_SRC], check=True)
+    os.replace(_WALK_LIB + ".tmp", _WALK_LIB)
+
+
+def _walker():
+    global _walk
+    if _walk is None:
+        if not os.path.exists(_WALK_LIB) or os.path.getmtime(_WALK_LIB) < os.path.getmtime(_WALK_SRC):
+            try:
+                build_walker()
+            except (OSError, subprocess.CalledProcessError):
+                _walk = False
+                return _walk
+        lib = ctypes.CDLL(_WALK_LIB)
+        lib.synth_walk.restype = None
+        lib.synth_walk.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
+                                   ctypes.c_void_p, ctypes.c_void_p]
+        _walk = lib
+    return _walk
+
+
+def _walk_path(rows, s0, u):
+    """state_t = bisect_right(rows[state_{t-1}], u[t]) clamped to K-1."""
+    K, T = len(rows), u.shape[0]
+    out = np.empty(T, dtype=np.int32)
+    lib = _walker()
+    if lib:
+        cum = np.ascontiguousarray(np.array(rows, dtype=np.float64))
+        u = np.ascontiguousarray(u, dtype=np.float64)
+        lib.synth_walk(K, cum.ctypes.data, int(s0), T, u.ctypes.data, out.ctypes.data)
+        return out
+    s = s0
+    us = u.tolist()
+    for t in range(T):
+        s = bisect.bisect_right(rows[s], us[t])
+        if s >= K:
+            s = K - 1
+        out[t] = s
+    return out
 
 
 @dataclass
@@ -91,13 +142,7 @@ def sample_path(rng, prm, T):
         c[-1] = 1.0
         rows.append(c.tolist())
     s = min(bisect.bisect_right(cum_delta.tolist(), u_state[0]), K - 1)
-    states = np.empty(T, dtype=np.int32)
-    us = u_state.tolist()
-    for t in range(T):
-        s = bisect.bisect_right(rows[s], us[t + 1])
-        if s >= K:
-            s = K - 1
-        states[t] = s
+    states = _walk_path(rows, s, u_state[1:])
     flag = (u_flag < prm.p[states]).astype(np.uint8)
     sd = np.sqrt(np.stack([prm.Sigma[:, 0], prm.Sigma[:, 2]], axis=1))
     xy = prm.mu[states] + sd[states] * z
@@ -123,13 +168,14 @@ WORKLOADS = {
 
 
 def batch(n=256, K_lo=8, K_hi=64, T_lo=100_000, T_hi=1_000_000, seed=3, T_scale=1.0):
-    """n independent sets, K ~ U{K_lo..K_hi}, T ~ U[T_lo, T_hi] (scaled by T_scale),
-    each with its own seed derived from ``seed``.  Returns packed arrays in the
-    layout of the batched entry point plus the per-set objects."""
+    """n independent sets, K ~ U{K_lo..K_hi}, T ~ U[T_lo, T_hi] (times T_scale),
+    each drawn by ``make`` with its own seed.  Draw order: from
+    default_rng(seed): K[n], T[n], per-set seeds[n].  Returns (packed arrays,
+    list of (params, observations))."""
     rng = np.random.default_rng(seed)
     Ks = rng.integers(K_lo, K_hi + 1, size=n)
     Ts = (rng.integers(T_lo, T_hi + 1, size=n) * T_scale).astype(np.int64)
-    seeds = rng.integers(0, 2**63 - 1, size=n)
+    seeds = rng.integers(0, 2**62, size=n)
     sets = [make(int(Ks[i]), int(Ts[i]), int(seeds[i])) for i in range(n)]
     return pack(sets), sets
 
