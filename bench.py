@@ -289,6 +289,9 @@ def bench_batch(args):
             ctx.loglik(**singles[i], out=outs[i:i + 1])
     sec_s = _timed(seq, max(2, steps // 2), 1)
     res_s = outs.cpu().numpy()
+    # plain forward recursion for all sets at once (one wavefront per set)
+    out_p = torch.empty(n, dtype=torch.float64, device="cuda")
+    sec_p = _timed(lambda: ctx.loglik_batched(**d, algo="serial_f32", out=out_p), 1, 1)
     # oracle on a sample of sets (host, one thread per set)
     import oracle
     oracle.build(force=False)
@@ -308,6 +311,10 @@ def bench_batch(args):
                     "tuned_L": sorted(set(int(x) for x in chosen))},
         "sequential_single_calls": {"sets_per_s": round(n / sec_s, 2), "ms_per_batch": round(sec_s * 1e3, 3)},
         "speedup_batched_vs_sequential": round(sec_s / sec_b, 3),
+        "batched_plain_forward": {"sets_per_s": round(n / sec_p, 2), "ms_per_batch": round(sec_p * 1e3, 3),
+                                  "max_rel_diff_vs_blocked": float(np.max(np.abs(out_p.cpu().numpy() - res_b)
+                                                                          / np.abs(res_b)))},
+        "speedup_batched_vs_plain_forward": round(sec_p / sec_b, 3),
         "max_rel_err_vs_oracle_sample": max(rel), "oracle_sample_sets": len(sample),
         "oracle_sample_seconds": round(c1 - c0, 2),
         "batched_vs_single_max_rel_diff": float(np.max(np.abs(res_b - res_s) / np.abs(res_s))),

@@ -14,7 +14,10 @@ namespace hmmh {
 // live contraction slots) form a class: one segment launch and one fold
 // launch per class.
 struct BatchClass {
-    KernelSet ks;
+    KernelSet ks;          // blocked paths
+    const void *serial = nullptr;  // plain-forward path: k_serial_batch<KP>
+    int KP = 0;
+    int *ids = nullptr;    // plain-forward path: the class's set ids (device)
     int W = 1, W2 = 1;
     int64_t L = 0;
     std::vector<int> sets;
@@ -41,8 +44,11 @@ struct BatchPlan {
     WgJob *jobs = nullptr;
     FoldJob *fjobs = nullptr;
     std::vector<BatchClass> classes;
-    // captured launch sequence
+    // captured launch sequence (classes forked onto parallel branches)
+    static constexpr int kBranches = 4;
     hipStream_t cap = nullptr;
+    hipStream_t aux[kBranches] = {};
+    hipEvent_t fork = nullptr, join[kBranches] = {};
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
@@ -53,6 +59,11 @@ void batch_plan_free(BatchPlan *bp)
     if (bp->exec) (void)hipGraphExecDestroy(bp->exec);
     if (bp->graph) (void)hipGraphDestroy(bp->graph);
     if (bp->cap) (void)hipStreamDestroy(bp->cap);
+    for (int i = 0; i < BatchPlan::kBranches; ++i) {
+        if (bp->aux[i]) (void)hipStreamDestroy(bp->aux[i]);
+        if (bp->join[i]) (void)hipEventDestroy(bp->join[i]);
+    }
+    if (bp->fork) (void)hipEventDestroy(bp->fork);
     if (bp->mem) (void)hipFree(bp->mem);
     delete bp;
 }
@@ -75,20 +86,42 @@ int64_t class_L(const hmm_ctx *ctx, const BatchPlan &bp, const BatchClass &c, in
     return std::max<int64_t>(128, std::min<int64_t>(2048, L));
 }
 
+const void *serial_kernel(int KP)
+{
+    switch (KP) {
+    case 16: return reinterpret_cast<const void *>(&k_serial_batch<16>);
+    case 32: return reinterpret_cast<const void *>(&k_serial_batch<32>);
+    case 64: return reinterpret_cast<const void *>(&k_serial_batch<64>);
+    case 96: return reinterpret_cast<const void *>(&k_serial_batch<96>);
+    default: return reinterpret_cast<const void *>(&k_serial_batch<128>);
+    }
+}
+
 int build(hmm_ctx *ctx, BatchPlan &bp)
 {
     const int n = bp.n;
-    // classes
+    const bool serial = (bp.algo == HMM_SERIAL_F32);
+    // classes: sets sharing one kernel instantiation
     std::vector<KernelSet> kss(n);
-    for (int s = 0; s < n; ++s)
-        if (!select_kernels(bp.algo, bp.K[s], &kss[s])) return HMM_E_UNSUPPORTED;
+    std::vector<int> kp(n);
+    for (int s = 0; s < n; ++s) {
+        if (serial) {
+            kp[s] = serial_kp(bp.K[s]);
+            kss[s].seg1 = serial_kernel(kp[s]);
+        } else {
+            if (!select_kernels(bp.algo, bp.K[s], &kss[s])) return HMM_E_UNSUPPORTED;
+            kp[s] = kss[s].KP();
+        }
+    }
     for (int s = 0; s < n; ++s) {
         auto it = std::find_if(bp.classes.begin(), bp.classes.end(),
                                [&](const BatchClass &c) { return c.ks.seg1 == kss[s].seg1; });
         if (it == bp.classes.end()) {
             BatchClass c;
             c.ks = kss[s];
-            c.W = group_waves(c.ks.KP());
+            c.KP = kp[s];
+            if (serial) c.serial = kss[s].seg1;
+            c.W = group_waves(c.KP);
             c.W2 = c.W;
             bp.classes.push_back(c);
             it = bp.classes.end() - 1;
@@ -101,6 +134,7 @@ int build(hmm_ctx *ctx, BatchPlan &bp)
     std::vector<size_t> prods(bp.classes.size(), 0);
     for (size_t ci = 0; ci < bp.classes.size(); ++ci) {
         BatchClass &c = bp.classes[ci];
+        if (c.serial) continue;
         c.L = class_L(ctx, bp, c, bp.algo, c.W);
         c.job0 = jobs.size();
         c.fjob0 = fjobs.size();
@@ -142,15 +176,17 @@ int build(hmm_ctx *ctx, BatchPlan &bp)
     const size_t o_jobs = take(sizeof(WgJob) * std::max<size_t>(jobs.size(), 1));
     const size_t o_fjobs = take(sizeof(FoldJob) * std::max<size_t>(fjobs.size(), 1));
     const size_t o_status = take(sizeof(int) * n);
+    const size_t o_ids = take(sizeof(int) * n);
     std::vector<size_t> o_sc(n), o_gf(n);
     for (int s = 0; s < n; ++s) {
-        const int KP = kss[s].KP();
+        const int KP = kp[s];
         o_sc[s] = take(sizeof(StateConst) * KP);
         o_gf[s] = take(sizeof(float) * KP * KP);
     }
     std::vector<size_t> o_m(bp.classes.size()), o_e(bp.classes.size()), o_s(bp.classes.size());
     for (size_t ci = 0; ci < bp.classes.size(); ++ci) {
-        const int KP = bp.classes[ci].ks.KP();
+        const int KP = bp.classes[ci].KP;
+        if (bp.classes[ci].serial) continue;
         o_m[ci] = take(sizeof(float) * KP * KP * prods[ci]);
         o_e[ci] = take(sizeof(long long) * KP * prods[ci]);
         o_s[ci] = take(sizeof(long long) * prods[ci]);
@@ -166,10 +202,17 @@ int build(hmm_ctx *ctx, BatchPlan &bp)
     bp.jobs = reinterpret_cast<WgJob *>(base + o_jobs);
     bp.fjobs = reinterpret_cast<FoldJob *>(base + o_fjobs);
     int *status = reinterpret_cast<int *>(base + o_status);
+    std::vector<int> ids;
     for (size_t ci = 0; ci < bp.classes.size(); ++ci) {
-        bp.classes[ci].M = reinterpret_cast<float *>(base + o_m[ci]);
-        bp.classes[ci].E = reinterpret_cast<long long *>(base + o_e[ci]);
-        bp.classes[ci].S = reinterpret_cast<long long *>(base + o_s[ci]);
+        BatchClass &c = bp.classes[ci];
+        if (c.serial) {
+            c.ids = reinterpret_cast<int *>(base + o_ids) + ids.size();
+            ids.insert(ids.end(), c.sets.begin(), c.sets.end());
+            continue;
+        }
+        c.M = reinterpret_cast<float *>(base + o_m[ci]);
+        c.E = reinterpret_cast<long long *>(base + o_e[ci]);
+        c.S = reinterpret_cast<long long *>(base + o_s[ci]);
     }
     std::vector<SetDesc> hs(n);
     std::vector<PrepJob> hp(n);
@@ -186,7 +229,7 @@ int build(hmm_ctx *ctx, BatchPlan &bp)
         d.status = status + s;
         d.out = bp.out + s;
         d.T = bp.T[s];
-        d.L = c->L;
+        d.L = c->serial ? 0 : c->L;
         d.K = bp.K[s];
         d.pad = 0;
         PrepJob &pj = hp[s];
@@ -195,15 +238,20 @@ int build(hmm_ctx *ctx, BatchPlan &bp)
         pj.GF = reinterpret_cast<float *>(base + o_gf[s]);
         pj.status = status + s;
         pj.K = bp.K[s];
-        pj.KP = kss[s].KP();
+        pj.KP = kp[s];
     }
     if (hipMemcpy(bp.sets, hs.data(), sizeof(SetDesc) * n, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(bp.prep, hp.data(), sizeof(PrepJob) * n, hipMemcpyHostToDevice) != hipSuccess ||
         (!jobs.empty() &&
          hipMemcpy(bp.jobs, jobs.data(), sizeof(WgJob) * jobs.size(), hipMemcpyHostToDevice) != hipSuccess) ||
-        hipMemcpy(bp.fjobs, fjobs.data(), sizeof(FoldJob) * fjobs.size(), hipMemcpyHostToDevice) != hipSuccess)
+        (!fjobs.empty() &&
+         hipMemcpy(bp.fjobs, fjobs.data(), sizeof(FoldJob) * fjobs.size(), hipMemcpyHostToDevice) != hipSuccess) ||
+        (!ids.empty() &&
+         hipMemcpy(reinterpret_cast<int *>(base + o_ids), ids.data(), sizeof(int) * ids.size(),
+                   hipMemcpyHostToDevice) != hipSuccess))
         return HMM_E_DEVICE;
     for (const auto &c : bp.classes) {
+        if (c.serial) continue;
         const size_t rb = (size_t)region_bytes(c.ks.KP());
         if (allow_lds(c.ks.segB, rb * c.W) != HMM_OK || allow_lds(c.ks.foldB, rb * c.W2) != HMM_OK)
             return HMM_E_DEVICE;
@@ -211,22 +259,55 @@ int build(hmm_ctx *ctx, BatchPlan &bp)
     return HMM_OK;
 }
 
-// The launch sequence of a plan on one stream (also what the graph records).
-int enqueue(const BatchPlan &bp, hipStream_t st, const BatchClass *only = nullptr)
+int enqueue_class(const BatchPlan &bp, const BatchClass &c, hipStream_t st)
 {
-    if (!only) hipLaunchKernelGGL(k_prepare_batch, dim3(bp.n), dim3(256), 0, st, bp.prep);
+    if (c.serial) {
+        void *args[] = {(void *)&bp.sets, (void *)&c.ids};
+        return hipLaunchKernel(c.serial, dim3((unsigned)c.sets.size()), dim3(64), args, 0, st) == hipSuccess
+                   ? HMM_OK
+                   : HMM_E_DEVICE;
+    }
     SetDesc none;
     std::memset(&none, 0, sizeof(none));
-    for (const auto &c : bp.classes) {
-        if (only && &c != only) continue;
-        const size_t rb = (size_t)region_bytes(c.ks.KP());
-        if (c.njobs > 0 &&
-            launch_seg(c.ks.segB, (unsigned)c.njobs, c.W, rb * c.W, st, none, bp.sets, bp.jobs + c.job0, 0, c.M,
-                       c.E, c.S) != hipSuccess)
-            return HMM_E_DEVICE;
-        if (launch_fold(c.ks.foldB, (unsigned)c.nfjobs, c.W2, rb * c.W2, st, none, bp.sets, bp.fjobs + c.fjob0, 0,
-                        1, 1, c.M, c.E, c.S, nullptr, nullptr, nullptr) != hipSuccess)
-            return HMM_E_DEVICE;
+    const size_t rb = (size_t)region_bytes(c.ks.KP());
+    if (c.njobs > 0 &&
+        launch_seg(c.ks.segB, (unsigned)c.njobs, c.W, rb * c.W, st, none, bp.sets, bp.jobs + c.job0, 0, c.M, c.E,
+                   c.S) != hipSuccess)
+        return HMM_E_DEVICE;
+    if (launch_fold(c.ks.foldB, (unsigned)c.nfjobs, c.W2, rb * c.W2, st, none, bp.sets, bp.fjobs + c.fjob0, 0, 1,
+                    1, c.M, c.E, c.S, nullptr, nullptr, nullptr) != hipSuccess)
+        return HMM_E_DEVICE;
+    return HMM_OK;
+}
+
+// The launch sequence of a plan: preparation, then every class.  With
+// branches, class i runs on aux[i % kBranches] after the preparation and
+// the main stream waits for all of them (parallel graph branches when
+// captured), so that one class's tail overlaps the next class.
+int enqueue(const BatchPlan &bp, hipStream_t st, const BatchClass *only = nullptr, bool branches = false)
+{
+    if (!only) hipLaunchKernelGGL(k_prepare_batch, dim3(bp.n), dim3(256), 0, st, bp.prep);
+    if (!branches) {
+        for (const auto &c : bp.classes) {
+            if (only && &c != only) continue;
+            const int rc = enqueue_class(bp, c, st);
+            if (rc != HMM_OK) return rc;
+        }
+        return HMM_OK;
+    }
+    if (hipEventRecord(bp.fork, st) != hipSuccess) return HMM_E_DEVICE;
+    bool used[BatchPlan::kBranches] = {};
+    for (size_t i = 0; i < bp.classes.size(); ++i) {
+        const int b = (int)(i % BatchPlan::kBranches);
+        if (!used[b] && hipStreamWaitEvent(bp.aux[b], bp.fork, 0) != hipSuccess) return HMM_E_DEVICE;
+        used[b] = true;
+        const int rc = enqueue_class(bp, bp.classes[i], bp.aux[b]);
+        if (rc != HMM_OK) return rc;
+    }
+    for (int b = 0; b < BatchPlan::kBranches; ++b) {
+        if (!used[b]) continue;
+        if (hipEventRecord(bp.join[b], bp.aux[b]) != hipSuccess) return HMM_E_DEVICE;
+        if (hipStreamWaitEvent(st, bp.join[b], 0) != hipSuccess) return HMM_E_DEVICE;
     }
     return HMM_OK;
 }
@@ -234,8 +315,13 @@ int enqueue(const BatchPlan &bp, hipStream_t st, const BatchClass *only = nullpt
 int capture(BatchPlan &bp)
 {
     if (hipStreamCreateWithFlags(&bp.cap, hipStreamNonBlocking) != hipSuccess) return HMM_E_DEVICE;
+    for (int b = 0; b < BatchPlan::kBranches; ++b) {
+        if (hipStreamCreateWithFlags(&bp.aux[b], hipStreamNonBlocking) != hipSuccess) return HMM_E_DEVICE;
+        if (hipEventCreateWithFlags(&bp.join[b], hipEventDisableTiming) != hipSuccess) return HMM_E_DEVICE;
+    }
+    if (hipEventCreateWithFlags(&bp.fork, hipEventDisableTiming) != hipSuccess) return HMM_E_DEVICE;
     if (hipStreamBeginCapture(bp.cap, hipStreamCaptureModeThreadLocal) != hipSuccess) return HMM_E_DEVICE;
-    int rc = enqueue(bp, bp.cap);
+    int rc = enqueue(bp, bp.cap, nullptr, bp.classes.size() > 1);
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(bp.cap, &g);
     if (rc != HMM_OK || e != hipSuccess || !g) {
@@ -305,13 +391,12 @@ int check_batch(hmm_ctx *ctx, int32_t n, const int32_t *K, const int64_t *T, con
                 const double *xy, int64_t obs_len, int32_t algo, double *out)
 {
     if (!ctx || n < 1 || !K || !T || !param_off || !params || !obs_off || !out) return HMM_E_INVALID_ARG;
-    if (algo != HMM_BLOCKED_F32 && algo != HMM_BLOCKED_BF16 && algo != HMM_BLOCKED_F16) {
-        if (algo == HMM_SERIAL_F32) return HMM_E_UNSUPPORTED;
+    if (algo != HMM_SERIAL_F32 && algo != HMM_BLOCKED_F32 && algo != HMM_BLOCKED_BF16 && algo != HMM_BLOCKED_F16)
         return HMM_E_INVALID_ARG;
-    }
+    const int kmax = (algo == HMM_SERIAL_F32) ? 128 : 80;
     bool any_obs = false;
     for (int s = 0; s < n; ++s) {
-        if (K[s] < 1 || K[s] > 80 || T[s] < 0 || T[s] >= kMaxT || param_off[s] < 0 || obs_off[s] < 0)
+        if (K[s] < 1 || K[s] > kmax || T[s] < 0 || T[s] >= kMaxT || param_off[s] < 0 || obs_off[s] < 0)
             return HMM_E_INVALID_ARG;
         const int64_t blk = (int64_t)K[s] * (K[s] + 7);  // delta, Gamma, p, mu, Sigma
         if (param_off[s] > params_len - blk || obs_off[s] > obs_len - T[s]) return HMM_E_INVALID_ARG;
@@ -373,6 +458,7 @@ int hmm_autotune_batched(hmm_ctx *ctx, int32_t n, const int32_t *K, const int64_
 {
     int rc = check_batch(ctx, n, K, T, param_off, params, params_len, obs_off, flag, xy, obs_len, algo, out);
     if (rc != HMM_OK) return rc;
+    if (algo == HMM_SERIAL_F32) return HMM_E_UNSUPPORTED;
     if (reps < 1) reps = 3;
     DeviceGuard dg(ctx->device);
     if (!dg.ok) return HMM_E_DEVICE;
@@ -398,6 +484,7 @@ int hmm_autotune_batched(hmm_ctx *ctx, int32_t n, const int32_t *K, const int64_
         if (rc != HMM_OK) break;
         hipLaunchKernelGGL(k_prepare_batch, dim3(bp->n), dim3(256), 0, st, bp->prep);
         for (const auto &c : bp->classes) {
+            if (c.serial) continue;
             float tot = 0.f;
             for (int r = 0; r <= reps; ++r) {
                 (void)hipEventRecord(e0, st);

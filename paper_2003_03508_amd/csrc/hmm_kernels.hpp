@@ -176,12 +176,12 @@ __global__ __launch_bounds__(64) void k_emission(int K, int64_t T, const StateCo
 // The final ln L = ln2 * (sum of exponents + sum of shifts) + ln(sum_j u_j).
 // ---------------------------------------------------------------------------
 template <int KP>
-__global__ __launch_bounds__(64) void k_serial(int K, int64_t T, const double *__restrict__ delta,
+__device__ __forceinline__ void serial_forward(int K, int64_t T, const double *__restrict__ delta,
                                                const float *__restrict__ GF,
                                                const StateConst *__restrict__ sc,
                                                const uint8_t *__restrict__ flag,
-                                               const double *__restrict__ xy,
-                                               int *__restrict__ status, double *__restrict__ out)
+                                               const double *__restrict__ xy, int *__restrict__ status,
+                                               double *__restrict__ out)
 {
     constexpr int SPL = (KP + kWave - 1) / kWave;
     constexpr int ES = kChunk + 1;  // odd stride: lane j reads row j without bank conflicts
@@ -264,6 +264,17 @@ __global__ __launch_bounds__(64) void k_serial(int K, int64_t T, const double *_
         else ll = kLn2 * (double)(uexp + stot) + log(sum);
         *out = ll;
     }
+}
+
+template <int KP>
+__global__ __launch_bounds__(64) void k_serial(int K, int64_t T, const double *__restrict__ delta,
+                                               const float *__restrict__ GF,
+                                               const StateConst *__restrict__ sc,
+                                               const uint8_t *__restrict__ flag,
+                                               const double *__restrict__ xy,
+                                               int *__restrict__ status, double *__restrict__ out)
+{
+    serial_forward<KP>(K, T, delta, GF, sc, flag, xy, status, out);
 }
 
 // ===========================================================================
@@ -960,6 +971,15 @@ __global__ __launch_bounds__(64 * group_waves(S * MT)) void k_fold(SetDesc one, 
         else ll = kLn2 * (double)(ssum + emax) + log(sum);
         *d.out = ll;
     }
+}
+
+// Plain forward recursion for a batch: workgroup q walks set ids[q] (one
+// wavefront per set, all sets of one padding class in one launch).
+template <int KP>
+__global__ __launch_bounds__(64) void k_serial_batch(const SetDesc *__restrict__ sets, const int *__restrict__ ids)
+{
+    const SetDesc d = sets[ids[blockIdx.x]];
+    serial_forward<KP>(d.K, d.T, d.delta, d.GF, d.sc, d.flag, d.xy, d.status, d.out);
 }
 
 }  // namespace hmm

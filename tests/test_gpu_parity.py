@@ -332,3 +332,23 @@ def test_batched_rejects_out_of_range_descriptors(binding, ctx):
     bad["param_off"] = packed["param_off"] + 1
     with pytest.raises(binding.HMMError):
         ctx.loglik_batched(**bad)
+
+
+def test_batched_serial_and_graph_modes(binding, ctx):
+    sets = [synth.make(K, T, seed=800 + K) for K, T in [(3, 3000), (25, 2500), (40, 2000), (64, 1000),
+                                                        (90, 700), (128, 300), (25, 0)]]
+    packed = synth.pack(sets)
+    d = binding.batch_to_device(packed)
+    out = ctx.loglik_batched(**d, algo="serial_f32").cpu().numpy()
+    for i, (prm, obs) in enumerate(sets):
+        assert_close(float(out[i]), ref(prm, obs), f"batched serial set {i} K={prm.K}")
+    blocked = [s for s in sets if s[0].K <= 80]
+    pk = synth.pack(blocked)
+    db = binding.batch_to_device(pk)
+    g1 = ctx.loglik_batched(**db).cpu().numpy()
+    ctx.batch_graph(False)
+    try:
+        g0 = ctx.loglik_batched(**db).cpu().numpy()
+    finally:
+        ctx.batch_graph(True)
+    assert (g0 == g1).all()  # same kernels, same order: identical with or without the graph
