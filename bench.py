@@ -13,9 +13,13 @@ FP32 MFMA peak), and the oracle's own throughput on the host cores.
 
     python bench.py [--gpus 1] [--steps 200] [--warmup 10]
 
+The default line also carries the MCMC leg ("mcmc": ESS/s of random-walk MH
+vs the learned proposal on the K=20, T=500,000 posterior; --no-mcmc skips it).
+
 Other workloads (one JSON line each, not the headline):
     python bench.py --workload k80_t4m    # K=80, T=4,194,304: FP32, BF16, FP16 operands
     python bench.py --workload batch256   # 256 sets, K in 8..64, T in 1e5..1e6, batched
+    python bench.py --workload mcmc_k20   # the MCMC leg on its own
 """
 import argparse
 import json
@@ -67,7 +71,11 @@ def measured_traffic():
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", default="k25_t1e6", choices=["k25_t1e6", "k80_t4m", "batch256"])
+    ap.add_argument("--workload", default="k25_t1e6", choices=["k25_t1e6", "k80_t4m", "batch256", "mcmc_k20"])
+    ap.add_argument("--no-mcmc", action="store_true", help="skip the MCMC leg of the default run")
+    ap.add_argument("--mcmc-iterations", type=int, default=2000)
+    ap.add_argument("--mcmc-chains", type=int, default=16)
+    ap.add_argument("--mcmc-lag", type=int, default=20)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--serial-steps", type=int, default=3)
@@ -93,6 +101,10 @@ def main():
         return bench_k80(args)
     if args.workload == "batch256":
         return bench_batch(args)
+    if args.workload == "mcmc_k20":
+        print(json.dumps(run_mcmc(C=args.mcmc_chains, n_iter=args.mcmc_iterations, lag=args.mcmc_lag,
+                                  log=True)))
+        return
 
     wl = synth.WORKLOADS["k25_t1e6"]
     K, T = wl["K"], wl["T"]
@@ -202,6 +214,8 @@ def main():
         "cpu_baseline": cpu,
     }
     ctx.close()
+    if not args.no_mcmc:
+        rec["mcmc"] = run_mcmc(C=args.mcmc_chains, n_iter=args.mcmc_iterations, lag=args.mcmc_lag)
     print(json.dumps(rec))
 
 
@@ -319,6 +333,127 @@ def bench_batch(args):
         "oracle_sample_seconds": round(c1 - c0, 2),
         "batched_vs_single_max_rel_diff": float(np.max(np.abs(res_b - res_s) / np.abs(res_s))),
     }))
+
+
+def run_mcmc(C=16, burn=300, adapt_rounds=3, n_iter=2000, lag=20, train_steps=1500, batch=256, lr=1e-3,
+             eps=0.1, seed=1, log=None):
+    """MCMC leg: posterior over all parameters of the K=20 model given the
+    T=500,000 path simulated with seed 4, random-walk MH vs the learned
+    proposal, C chains each, exact FP32 likelihood in every MH step.
+
+    1. Burn-in from the generating parameters with a diagonal random walk,
+       adapted for `adapt_rounds` rounds of `burn` iterations (per-coordinate
+       scale 2.38/sqrt(D) times the chain spread, times a factor steering the
+       acceptance toward 0.234).  Both methods start from its end state and
+       use its random-walk scale.
+    2. The proposal network is trained on the burn-in history (lagged pairs),
+       timed, and frozen.
+    3. n_iter iterations of each method from the same states.  ESS per
+       coordinate (multi-chain, Geyer), ESS/s = ESS / wall time, the learned
+       method's time including its training.
+    Equal posterior accuracy: the two runs' posterior means agree within
+    their Monte Carlo standard errors (z-scores reported).
+    """
+    import numpy as np
+    import torch
+    from paper_2003_03508_amd import binding, synth
+    from paper_2003_03508_amd import ess as E
+    from paper_2003_03508_amd import mcmc as hm
+
+    def say(*a):
+        if log:
+            print(*a, file=sys.stderr, flush=True)
+
+    wl = synth.WORKLOADS["k20_t5e5"]
+    K, T = wl["K"], wl["T"]
+    prm, obs = synth.make(**wl)
+    box = hm.box_of(obs.flag, obs.xy)
+    d = binding.to_device(prm, obs)
+    ctx = binding.Context(0)
+    D = hm.dim(K)
+    H = max(burn * adapt_rounds, n_iter)
+    f64 = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+    # initial random-walk scale: posterior standard deviations guessed from counts
+    sl = hm.block_slices(K)
+    nk = T / K
+    rw = np.empty(D)
+    rw[sl["gamma"]] = 0.1
+    rw[sl["p"]] = 1.0 / np.sqrt(nk * prm.p * (1 - prm.p))
+    rw[sl["mu"]] = (np.sqrt(prm.Sigma[:, [0, 2]]) / np.sqrt(nk * prm.p)[:, None]).ravel()
+    rw[sl["logsigma"]] = np.repeat(np.sqrt(2.0 / (nk * prm.p)), 2)
+    rw *= 2.38 / math.sqrt(D)
+    th0 = hm.theta_from_params(prm.Gamma, prm.p, prm.mu, prm.Sigma)
+    ch = binding.Chains(ctx, K, C, d["flag"], d["xy"], box, seed=seed, history=H)
+    ch.set_state(f64(np.tile(th0, (C, 1))), f64(rw))
+
+    def window(n):
+        hist, _, it = ch.history()
+        hist = hist.cpu().numpy()
+        return hist[[(it - n + i) % H for i in range(n)]].transpose(1, 0, 2).astype(np.float64)
+
+    def run(n, proposal):
+        a0 = int(ch.state()["accepts"].sum())
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ch.step(n, proposal=proposal, eps=eps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        return dt, (int(ch.state()["accepts"].sum()) - a0) / (n * C)
+
+    scale = 1.0
+    t_burn = 0.0
+    for r in range(adapt_rounds):
+        dt, acc = run(burn, binding.MCMC_RANDOM_WALK)
+        t_burn += dt
+        spread = window(burn)[:, burn // 3:].reshape(-1, D).std(axis=0)
+        scale *= 0.7 if acc < 0.15 else (1.3 if acc > 0.35 else 1.0)
+        rw = scale * 2.38 / math.sqrt(D) * np.maximum(spread, 1e-12)
+        ch.set_rw_scale(f64(rw))
+        say(f"burn-in round {r}: acceptance {acc:.3f}, {dt / burn * 1e3:.2f} ms/iteration")
+    start = ch.state()["theta"].clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses = ch.train(train_steps, batch=batch, lag=lag, lr=lr, window=burn * adapt_rounds)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    losses = losses.cpu().numpy()
+    say(f"training: {train_steps} steps in {t_train:.2f} s, loss {losses[:50].mean():.3f} -> "
+        f"{losses[-50:].mean():.3f}")
+
+    res = {}
+    for name, prop in (("random_walk", binding.MCMC_RANDOM_WALK), ("learned", binding.MCMC_LEARNED)):
+        ch.set_state(start, f64(rw))
+        dt, acc = run(n_iter, prop)
+        w = window(n_iter)
+        ess = E.ess_columns(w)
+        cost = dt + (t_train if prop == binding.MCMC_LEARNED else 0.0)
+        res[name] = dict(seconds=round(dt, 3), ms_per_iteration=round(dt / n_iter * 1e3, 3),
+                         acceptance=round(acc, 4), ess_min=round(float(ess.min()), 2),
+                         ess_median=round(float(np.median(ess)), 2),
+                         ess_per_s_min=round(float(ess.min()) / cost, 3),
+                         ess_per_s_median=round(float(np.median(ess)) / cost, 3),
+                         means=w.reshape(-1, D).mean(axis=0),
+                         mcse=np.array([E.mcse_mean(w[:, :, j]) for j in range(D)]))
+        say(f"{name}: acceptance {acc:.3f}, ESS min {ess.min():.1f} median {np.median(ess):.1f}, "
+            f"{dt:.2f} s")
+    ch.close()
+    ctx.close()
+    a, b = res["random_walk"], res["learned"]
+    z = np.abs(a["means"] - b["means"]) / np.sqrt(a["mcse"] ** 2 + b["mcse"] ** 2)
+    for r in (a, b):
+        del r["means"], r["mcse"]
+    return {
+        "workload": "k20_t5e5: posterior over all parameters (D=480) of a K=20 tremor HMM given "
+                    "T=500,000 observations simulated with seed 4",
+        "chains": C, "iterations": n_iter, "burn_in": burn * adapt_rounds,
+        "burn_in_seconds": round(t_burn, 3), "train_seconds": round(t_train, 3),
+        "train_steps": train_steps, "lag": lag, "mixture_eps": eps,
+        "random_walk": a, "learned": b,
+        "ess_per_s_gain_median": round(b["ess_per_s_median"] / a["ess_per_s_median"], 3),
+        "ess_per_s_gain_min": round(b["ess_per_s_min"] / a["ess_per_s_min"], 3),
+        "mean_agreement_z_max": round(float(z.max()), 3),
+        "mean_agreement_z_frac_below_3": round(float((z < 3).mean()), 4),
+    }
 
 
 if __name__ == "__main__":

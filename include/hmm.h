@@ -75,8 +75,13 @@ typedef enum {
      * combined by a tree of matrix products on the GPU.  O(T K^3) work.
      * K <= 80. */
     HMM_BLOCKED_F32 = 1,
-    HMM_BLOCKED_BF16 = 2,   /* reserved: bf16 operands, FP32 accumulation */
-    HMM_BLOCKED_F16 = 3     /* reserved: fp16 operands, FP32 accumulation */
+    /* The same plan with the segment products on 16-bit MFMA: the running
+     * product and the emission-scaled transition matrix are rounded to bf16
+     * (resp. fp16) operands, accumulation stays FP32, rescaling by powers of
+     * two.  Error grows with T (about T * 2^-8 resp. T * 2^-11 relative per
+     * step at worst); the FP32 path is the reference.  K <= 80. */
+    HMM_BLOCKED_BF16 = 2,
+    HMM_BLOCKED_F16 = 3
 } hmm_algo;
 
 typedef struct hmm_ctx hmm_ctx;
@@ -172,6 +177,137 @@ int hmm_blocked_plan(hmm_ctx *ctx, int32_t K, int64_t T, int64_t *block_len,
  * are kept; later ones are not timed.  Enabling or disabling also forgets. */
 int hmm_ctx_profile(hmm_ctx *ctx, int32_t on);
 int hmm_ctx_profile_read(hmm_ctx *ctx, int64_t *launches, double *total_ms);
+
+/* ------------------------------------------------------------------------
+ * Metropolis-Hastings over the model parameters (section "Monte Carlo Markov
+ * Chains"; prior densities of Appendix A), many chains in parallel, each
+ * iteration one batched exact likelihood evaluation of all chains' proposals.
+ *
+ * Parameter vector theta (unconstrained, FP64) of D = K*K + 4K entries:
+ *   [0, K(K-1))    row i of Gamma as log(Gamma_ij / Gamma_ii), j != i ascending
+ *   [.., +K)       logit p_k
+ *   [.., +2K)      mu_k as (x, y) pairs, km
+ *   [.., +2K)      log of Sigma_k's diagonal (xx, yy); Sigma_xy = 0
+ * delta is fixed to the uniform distribution.  Log prior (additive constants
+ * dropped, Jacobians of the transforms included):
+ *   Gamma rows ~ Dirichlet(0.01, ..., 0.01)        -> 0.01 * sum_ij ln Gamma_ij
+ *   p_k ~ Gamma(10, rate 100) for k < K/2 (mean 0.1), Gamma(810, rate 900)
+ *     otherwise (mean 0.9), variance 0.001, truncated to (0, 1)
+ *                                                  -> a ln p - b p + ln(1 - p)
+ *   mu_k uniform on box = {x0, x1, y0, y1} (km)    -> 0 inside, -inf outside
+ *   Sigma_k ~ inverse Wishart(nu = K, I_2) restricted to diagonal matrices
+ *                                  -> -(K+1)/2 (w_x + w_y) - (e^-w_x + e^-w_y)/2
+ *   with w = ln Sigma_diag.
+ * Random numbers: Philox4x32-10 (Salmon et al., SC 2011) with key = seed and
+ * counter (index, chain, iteration, purpose); uniforms are
+ * ((64-bit word >> 11) + 1/2) * 2^-53 of words (0,1) and (2,3); normals are
+ * Box-Muller pairs (r cos 2 pi u1, r sin 2 pi u1), r = sqrt(-2 ln u0).
+ * Purposes: 1 proposal normals (index = coordinate pair), 2 mixture choice,
+ * 3 acceptance uniform, 4 training minibatch rows, 5 weight initialisation.
+ * ------------------------------------------------------------------------ */
+typedef enum { MCMC_RANDOM_WALK = 0, MCMC_LEARNED = 1 } mcmc_proposal;
+
+typedef struct mcmc_chains mcmc_chains;
+
+/* Device buffers and sizes of a sampler (filled by mcmc_view_get; the
+ * pointers stay valid until mcmc_destroy).  C = n_chains, D = dim,
+ * H = history_len. */
+typedef struct {
+    int32_t K, n_chains, dim;
+    int64_t iterations;        /* MH iterations run so far                       */
+    int64_t history_len;       /* iterations kept in the history ring            */
+    double *theta;             /* [C*D] current states                           */
+    double *loglik, *logprior; /* [C] of the current states                      */
+    double *theta_prop;        /* [C*D] last proposals                           */
+    double *loglik_prop, *logprior_prop, *logq_fwd; /* [C] of the last proposals */
+    long long *accepts;        /* [C] accepted moves                             */
+    float *history;            /* [H*C*D] states after iteration t at slot t % H  */
+    double *history_logpost;   /* [H*C] loglik + logprior after iteration t      */
+    float *net_weights;        /* [net_count] proposal network, layout below     */
+    int64_t net_count;
+    int32_t net_hidden;        /* width of both hidden layers (256)              */
+    double *center, *in_scale, *out_scale; /* [D] network standardisation        */
+    int32_t lag, trained;
+} mcmc_view;
+
+/* Create n_chains chains for a K-state model over the observations
+ * (flag, xy, T) -- device arrays that must stay valid while the sampler is
+ * used.  box: HOST double[4] {x0, x1, y0, y1}.  history: iterations kept in
+ * the ring that training reads (>= 2).  All chains start at theta = 0 with
+ * ln L unset: call mcmc_set_state before mcmc_step.  1 <= K <= 80. */
+int mcmc_create(hmm_ctx *ctx, int32_t K, int32_t n_chains, int64_t T, const uint8_t *flag,
+                const double *xy, const double *box, uint64_t seed, int64_t history,
+                mcmc_chains **out);
+int mcmc_destroy(mcmc_chains *chains);
+
+/* Set every chain's state (theta: device [C*D]) and the random-walk scales
+ * (rw_scale: device [D], > 0), and evaluate ln L and the log prior there. */
+int mcmc_set_state(mcmc_chains *chains, const double *theta, const double *rw_scale,
+                   void *stream);
+int mcmc_set_rw_scale(mcmc_chains *chains, const double *rw_scale, void *stream);
+
+/* n_iter Metropolis-Hastings iterations of every chain.  Iteration t of
+ * chain c:
+ *   proposal MCMC_RANDOM_WALK:  theta' = theta + rw_scale .* z
+ *   proposal MCMC_LEARNED: with probability 1 - eps (uniform of purpose 2)
+ *     theta'_d = theta_d + out_scale_d (o_d + exp(o_{D+d}) z_d), o the network
+ *     output at X = (theta - center) / in_scale; otherwise the random walk.
+ *     Needs a trained (or loaded) network; 0 < eps < 1.
+ *   z: normals of purpose 1.  theta' is mapped to model parameters, ln L of
+ *   all chains' proposals is computed by the batched FP32 blocked path, and
+ *   theta' is accepted when ln u < ln L' + ln prior' - ln L - ln prior +
+ *   ln q(theta | theta') - ln q(theta' | theta), u of purpose 3 (q is the
+ *   mixture density; the q terms are zero for the random walk).
+ * The state after the iteration is written to the history ring.  Enqueued
+ * on `stream`. */
+int mcmc_step(mcmc_chains *chains, int32_t n_iter, int32_t proposal, double eps, void *stream);
+
+int mcmc_view_get(mcmc_chains *chains, mcmc_view *view);
+
+/* Train the learned proposal on lagged pairs (theta_t, theta_{t+lag}) of the
+ * last `window` iterations of history (0 = the whole ring): `steps` Adam steps
+ * (beta 0.9 / 0.999, eps 1e-8, learning rate lr) on minibatches of `batch`
+ * pairs (time and chain drawn with purpose 4) of the Gaussian negative
+ * log-likelihood of the move.  The first call fixes the standardisation from
+ * the window (center and in_scale: mean and standard deviation of theta;
+ * out_scale: standard deviation of the lag-`lag` move; scales floored at
+ * 0.1 * rw_scale) and the lag.  loss_out: device float[steps] or NULL,
+ * receives each step's minibatch loss.
+ * Network: X (D) -> tanh(X W1 + b1) (256) -> tanh(. W2 + b2) (256)
+ *          -> . W3 + b3 (2D);  weights flat, FP32, in the order
+ *          W1 [D][256], b1, W2 [256][256], b2, W3 [256][2D], b3, each W
+ *          row-major with the input index first. */
+int mcmc_train_proposal(mcmc_chains *chains, int32_t steps, int32_t batch, int32_t lag,
+                        double lr, int64_t window, void *stream, float *loss_out);
+
+/* The proposal network on its own (for checks): network outputs out[n*2D]
+ * for inputs X[n*D] (device, FP32). */
+int mlp_forward(mcmc_chains *chains, int32_t n, const float *X, float *out, void *stream);
+
+/* Loss terms row_loss[B] (each with the 1/B factor) and the gradient
+ * grad[net_count] (same layout as the weights) of the training loss for a
+ * given minibatch: inputs X[B*D] and targets R[B*D] (moves in units of
+ * out_scale), device FP32.  No update. */
+int mlp_loss_grad(mcmc_chains *chains, int32_t B, const float *X, const float *R,
+                  float *row_loss, float *grad, void *stream);
+
+/* Install network weights and standardisation (device arrays) as if trained
+ * with this lag. */
+int mlp_set_weights(mcmc_chains *chains, const float *weights, const double *center,
+                    const double *in_scale, const double *out_scale, int32_t lag, void *stream);
+
+/* The parameter transform of the sampler on its own: for n vectors theta
+ * (device [n*D]) writes the likelihood blocks params[n * K(K+7)] in the
+ * layout of hmm_loglik_batched and the log priors logprior[n].  box: HOST
+ * double[4].  1 <= K <= 128. */
+int hmm_theta_to_params(hmm_ctx *ctx, int32_t K, int32_t n, const double *theta,
+                        const double *box, double *params, double *logprior, void *stream);
+
+/* Philox draws of the sampler's streams: for i < n, out[2i], out[2i+1] are
+ * the two uniforms (normal = 0) or Box-Muller normals (normal = 1) of counter
+ * (i, chain, iter, purpose).  out: device double[2n] (may be NULL when n = 0). */
+int hmm_philox(hmm_ctx *ctx, uint64_t seed, uint32_t purpose, uint32_t iter, uint32_t chain,
+               int64_t n, int32_t normal, double *out, void *stream);
 
 /* Human-readable name of a status code (static storage). */
 const char *hmm_status_string(int status);

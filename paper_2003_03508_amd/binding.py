@@ -47,11 +47,41 @@ _lib.hmm_loglik_batched.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp, _i64, _vp, _v
 _lib.hmm_ctx_set_batch_graph.argtypes = [_vp, _i32]
 _lib.hmm_autotune_batched.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _i64, _i32, _vp,
                                       _i32, _vp]
+_lib.hmm_theta_to_params.argtypes = [_vp, _i32, _i32, _vp, _vp, _vp, _vp, _vp]
+_lib.hmm_philox.argtypes = [_vp, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, _i64,
+                            _i32, _vp, _vp]
+_lib.mcmc_create.argtypes = [_vp, _i32, _i32, _i64, _vp, _vp, _vp, ctypes.c_uint64, _i64, ctypes.POINTER(_vp)]
+_lib.mcmc_destroy.argtypes = [_vp]
+_lib.mcmc_set_state.argtypes = [_vp, _vp, _vp, _vp]
+_lib.mcmc_set_rw_scale.argtypes = [_vp, _vp, _vp]
+_lib.mcmc_step.argtypes = [_vp, _i32, _i32, ctypes.c_double, _vp]
+_lib.mcmc_train_proposal.argtypes = [_vp, _i32, _i32, _i32, ctypes.c_double, _i64, _vp, _vp]
+_lib.mlp_forward.argtypes = [_vp, _i32, _vp, _vp, _vp]
+_lib.mlp_loss_grad.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp, _vp]
+_lib.mlp_set_weights.argtypes = [_vp, _vp, _vp, _vp, _vp, _i32, _vp]
+
+
+class McmcView(ctypes.Structure):
+    """Mirror of mcmc_view in include/hmm.h."""
+    _fields_ = [("K", _i32), ("n_chains", _i32), ("dim", _i32),
+                ("iterations", _i64), ("history_len", _i64),
+                ("theta", _vp), ("loglik", _vp), ("logprior", _vp),
+                ("theta_prop", _vp), ("loglik_prop", _vp), ("logprior_prop", _vp), ("logq_fwd", _vp),
+                ("accepts", _vp), ("history", _vp), ("history_logpost", _vp),
+                ("net_weights", _vp), ("net_count", _i64), ("net_hidden", _i32),
+                ("center", _vp), ("in_scale", _vp), ("out_scale", _vp),
+                ("lag", _i32), ("trained", _i32)]
+
+
+_lib.mcmc_view_get.argtypes = [_vp, ctypes.POINTER(McmcView)]
 _lib.hmm_status_string.restype = ctypes.c_char_p
 _lib.hmm_status_string.argtypes = [ctypes.c_int]
 for _f in ("hmm_ctx_create", "hmm_ctx_destroy", "hmm_loglik", "hmm_emission",
            "hmm_ctx_set_blocking", "hmm_blocked_plan", "hmm_ctx_profile", "hmm_ctx_profile_read",
-           "hmm_loglik_batched", "hmm_ctx_set_batch_graph", "hmm_autotune_batched"):
+           "hmm_loglik_batched", "hmm_ctx_set_batch_graph", "hmm_autotune_batched",
+           "hmm_theta_to_params", "hmm_philox", "mcmc_create", "mcmc_destroy", "mcmc_set_state",
+           "mcmc_set_rw_scale", "mcmc_step", "mcmc_train_proposal", "mcmc_view_get", "mlp_forward",
+           "mlp_loss_grad", "mlp_set_weights"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 
@@ -212,6 +242,173 @@ class Context:
                                _dev(e_hat, torch.float32, "e_hat"), _dev(status, torch.int32, "status"))
         _check("hmm_emission", rc)
         return shift, e_hat, status
+
+
+    def theta_to_params(self, K, theta, box, stream=None):
+        """(params [n, K(K+7)], logprior [n]) of unconstrained vectors theta [n, K*K+4K]."""
+        D = K * K + 4 * K
+        n = theta.numel() // D
+        if n * D != theta.numel() or n < 1:
+            raise ValueError("theta must hold whole vectors of K*K+4K entries")
+        params = torch.empty((n, K * (K + 7)), dtype=torch.float64, device=theta.device)
+        lp = torch.empty(n, dtype=torch.float64, device=theta.device)
+        b = (ctypes.c_double * 4)(*[float(v) for v in box])
+        _check("hmm_theta_to_params",
+               _lib.hmm_theta_to_params(self._h, int(K), n, _dev(theta, torch.float64, "theta"), b,
+                                        _dev(params, torch.float64, "params"), _dev(lp, torch.float64, "lp"),
+                                        _stream(stream)))
+        return params, lp
+
+    def philox(self, seed, purpose, it, chain, n, normal=False, stream=None):
+        """2n draws of Philox counter stream (i, chain, it, purpose), i < n (device float64)."""
+        out = torch.empty(2 * max(n, 0), dtype=torch.float64, device=self.device)
+        _check("hmm_philox", _lib.hmm_philox(self._h, int(seed), int(purpose), int(it), int(chain), int(n),
+                                             1 if normal else 0, _dev(out, torch.float64, "out"),
+                                             _stream(stream)))
+        return out
+
+
+MCMC_RANDOM_WALK = 0
+MCMC_LEARNED = 1
+
+
+class Chains:
+    """Parallel Metropolis-Hastings chains over the parameters of a K-state model."""
+
+    def __init__(self, ctx, K, n_chains, flag, xy, box, seed=0, history=1024):
+        self.ctx = ctx
+        self.K, self.C = int(K), int(n_chains)
+        self.D = self.K * self.K + 4 * self.K
+        T = int(flag.numel())
+        if xy.numel() != 2 * T:
+            raise ValueError("xy must hold two coordinates per observation")
+        self._obs = (flag, xy)          # keep the observations alive
+        b = (ctypes.c_double * 4)(*[float(v) for v in box])
+        h = _vp()
+        _check("mcmc_create", _lib.mcmc_create(ctx._h, self.K, self.C, T, _dev(flag, torch.uint8, "flag"),
+                                               _dev(xy, torch.float64, "xy"), b, int(seed), int(history),
+                                               ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.mcmc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def view(self):
+        v = McmcView()
+        _check("mcmc_view_get", _lib.mcmc_view_get(self._h, ctypes.byref(v)))
+        return v
+
+    def _tensor(self, ptr, shape, dtype):
+        """Copy of a library-owned device buffer as a torch tensor (synchronous)."""
+        n = 1
+        for s in shape:
+            n *= s
+        out = torch.empty(shape, dtype=dtype, device=self.ctx.device)
+        if n:
+            torch.cuda.synchronize(self.ctx.device)
+            rc = _hip().hipMemcpy(out.data_ptr(), ptr, n * out.element_size(), 3)  # device to device
+            if rc != 0:
+                raise HMMError("hipMemcpy", HMM_E_DEVICE)
+        return out
+
+    def state(self):
+        """dict of copies: theta [C, D], loglik [C], logprior [C], accepts [C], iterations."""
+        v = self.view()
+        return dict(theta=self._tensor(v.theta, (self.C, self.D), torch.float64),
+                    loglik=self._tensor(v.loglik, (self.C,), torch.float64),
+                    logprior=self._tensor(v.logprior, (self.C,), torch.float64),
+                    accepts=self._tensor(v.accepts, (self.C,), torch.int64),
+                    iterations=v.iterations)
+
+    def proposal(self):
+        """Copies of the last proposals: theta_prop, loglik_prop, logprior_prop, logq_fwd."""
+        v = self.view()
+        return dict(theta=self._tensor(v.theta_prop, (self.C, self.D), torch.float64),
+                    loglik=self._tensor(v.loglik_prop, (self.C,), torch.float64),
+                    logprior=self._tensor(v.logprior_prop, (self.C,), torch.float64),
+                    logq_fwd=self._tensor(v.logq_fwd, (self.C,), torch.float64))
+
+    def history(self):
+        """(states [H, C, D] float32, logpost [H, C] float64, iterations); slot t % H holds iteration t."""
+        v = self.view()
+        return (self._tensor(v.history, (v.history_len, self.C, self.D), torch.float32),
+                self._tensor(v.history_logpost, (v.history_len, self.C), torch.float64), v.iterations)
+
+    def network(self):
+        """dict of copies: weights (flat float32), center, in_scale, out_scale, lag, hidden, trained."""
+        v = self.view()
+        return dict(weights=self._tensor(v.net_weights, (v.net_count,), torch.float32),
+                    center=self._tensor(v.center, (self.D,), torch.float64),
+                    in_scale=self._tensor(v.in_scale, (self.D,), torch.float64),
+                    out_scale=self._tensor(v.out_scale, (self.D,), torch.float64),
+                    lag=v.lag, hidden=v.net_hidden, trained=bool(v.trained))
+
+    def set_state(self, theta, rw_scale, stream=None):
+        theta = theta.reshape(-1)
+        _check("mcmc_set_state", _lib.mcmc_set_state(self._h, _dev(theta, torch.float64, "theta", self.C * self.D),
+                                                     _dev(rw_scale, torch.float64, "rw_scale", self.D),
+                                                     _stream(stream)))
+
+    def set_rw_scale(self, rw_scale, stream=None):
+        _check("mcmc_set_rw_scale", _lib.mcmc_set_rw_scale(
+            self._h, _dev(rw_scale, torch.float64, "rw_scale", self.D), _stream(stream)))
+
+    def step(self, n_iter=1, proposal=MCMC_RANDOM_WALK, eps=0.1, stream=None):
+        _check("mcmc_step", _lib.mcmc_step(self._h, int(n_iter), int(proposal), float(eps), _stream(stream)))
+
+    def train(self, steps, batch=256, lag=1, lr=1e-3, window=0, stream=None, losses=True):
+        """Adam steps on lagged pairs of the history; returns the per-step losses (device) or None."""
+        out = torch.empty(max(steps, 1), dtype=torch.float32, device=self.ctx.device) if losses else None
+        _check("mcmc_train_proposal", _lib.mcmc_train_proposal(
+            self._h, int(steps), int(batch), int(lag), float(lr), int(window), _stream(stream),
+            _dev(out, torch.float32, "loss") if losses else None))
+        return out[:steps] if losses else None
+
+    def mlp_forward(self, X, stream=None):
+        n = X.numel() // self.D
+        out = torch.empty((n, 2 * self.D), dtype=torch.float32, device=X.device)
+        _check("mlp_forward", _lib.mlp_forward(self._h, n, _dev(X, torch.float32, "X", n * self.D),
+                                               _dev(out, torch.float32, "out"), _stream(stream)))
+        return out
+
+    def mlp_loss_grad(self, X, R, stream=None):
+        n = X.numel() // self.D
+        v = self.view()
+        rows = torch.empty(n, dtype=torch.float32, device=X.device)
+        grad = torch.empty(v.net_count, dtype=torch.float32, device=X.device)
+        _check("mlp_loss_grad", _lib.mlp_loss_grad(self._h, n, _dev(X, torch.float32, "X", n * self.D),
+                                                   _dev(R, torch.float32, "R", n * self.D),
+                                                   _dev(rows, torch.float32, "row_loss"),
+                                                   _dev(grad, torch.float32, "grad"), _stream(stream)))
+        return rows, grad
+
+    def set_network(self, weights, center, in_scale, out_scale, lag, stream=None):
+        v = self.view()
+        _check("mlp_set_weights", _lib.mlp_set_weights(
+            self._h, _dev(weights, torch.float32, "weights", v.net_count),
+            _dev(center, torch.float64, "center", self.D), _dev(in_scale, torch.float64, "in_scale", self.D),
+            _dev(out_scale, torch.float64, "out_scale", self.D), int(lag), _stream(stream)))
+
+
+_hip_lib = None
+
+
+def _hip():
+    """The HIP runtime, for copies out of library-owned buffers."""
+    global _hip_lib
+    if _hip_lib is None:
+        _hip_lib = ctypes.CDLL("libamdhip64.so")
+        _hip_lib.hipMemcpy.argtypes = [_vp, _vp, ctypes.c_size_t, ctypes.c_int]
+        _hip_lib.hipMemcpy.restype = ctypes.c_int
+    return _hip_lib
 
 
 def batch_to_device(packed, device="cuda"):

@@ -16,7 +16,7 @@ LIB = os.path.join(ROOT, "paper_2003_03508_amd", "libhmm.so")
 def declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"^[A-Za-z_][\w\s\*]*?\b(hmm_\w+)\s*\(", text, flags=re.M)))
+    return sorted(set(re.findall(r"^[A-Za-z_][\w\s\*]*?\b((?:hmm|mcmc|mlp)_\w+)\s*\(", text, flags=re.M)))
 
 
 @pytest.fixture(scope="module")
@@ -30,7 +30,10 @@ def lib():
 def test_header_declares_the_entry_points():
     names = declared_functions()
     for want in ("hmm_ctx_create", "hmm_ctx_destroy", "hmm_loglik", "hmm_emission",
-                 "hmm_ctx_set_blocking", "hmm_blocked_plan", "hmm_status_string"):
+                 "hmm_ctx_set_blocking", "hmm_blocked_plan", "hmm_status_string",
+                 "hmm_loglik_batched", "hmm_autotune_batched", "mcmc_create", "mcmc_step",
+                 "mcmc_train_proposal", "mlp_forward", "mlp_loss_grad", "hmm_philox",
+                 "hmm_theta_to_params"):
         assert want in names
 
 
@@ -96,3 +99,36 @@ def test_binding_fails_loudly_without_library(tmp_path):
     r = subprocess.run(["python", "-c", "import paper_2003_03508_amd.binding"], cwd=tmp_path,
                        capture_output=True, text=True)
     assert r.returncode != 0 and "libhmm.so" in r.stderr
+
+
+def test_mcmc_host_argument_checks(lib):
+    vp = ctypes.c_void_p
+    lib.mcmc_create.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, vp, vp, vp,
+                                ctypes.c_uint64, ctypes.c_int64, ctypes.POINTER(vp)]
+    box = (ctypes.c_double * 4)(0, 1, 0, 1)
+    h = vp()
+    assert lib.mcmc_create(None, 3, 4, 10, 1, 1, box, 0, 8, ctypes.byref(h)) == -1
+    lib.mcmc_step.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, vp]
+    assert lib.mcmc_step(None, 1, 0, 0.1, None) == -1
+    lib.mcmc_train_proposal.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                        ctypes.c_int64, vp, vp]
+    assert lib.mcmc_train_proposal(None, 1, 1, 1, 1e-3, 0, None, None) == -1
+    lib.hmm_philox.argtypes = [vp, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                               ctypes.c_int64, ctypes.c_int32, vp, vp]
+    assert lib.hmm_philox(None, 0, 1, 0, 0, 4, 0, 1, None) == -1
+
+
+def test_mcmc_view_layout_matches_binding(tmp_path):
+    """The ctypes mirror of mcmc_view has the C struct's field offsets."""
+    from paper_2003_03508_amd import binding  # needs only the library file, not a GPU
+    fields = [f[0] for f in binding.McmcView._fields_]
+    src = tmp_path / "off.c"
+    body = "\n".join(f'printf("%s %zu\\n", "{f}", offsetof(mcmc_view, {f}));' for f in fields)
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "hmm.h"\nint main(void){'
+                   + body + 'printf("size %zu\\n", sizeof(mcmc_view));return 0;}\n')
+    exe = tmp_path / "off"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)], check=True)
+    out = dict(l.split() for l in subprocess.run([str(exe)], capture_output=True, text=True).stdout.splitlines())
+    for f in fields:
+        assert int(out[f]) == getattr(binding.McmcView, f).offset, f
+    assert int(out["size"]) == ctypes.sizeof(binding.McmcView)
