@@ -38,13 +38,16 @@ PEAK_HBM_GBS = 8000.0
 COUNTERS = os.path.join(ROOT, "profiles", "k_blocked_k25_t1e6_counters.txt")
 
 
+# The sources the segment kernel of the K=25 workload is built from (its
+# translation unit and the headers it includes).
+SEGMENT_KERNEL_SOURCES = ("hmm_device.hpp", "hmm_kernels.hpp", "hmm_host.hpp", "hmm_api.hip")
+
+
 def kernel_sources_sha256():
-    import glob
     import hashlib
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2003_03508_amd", "csrc", "*"))):
-        if f.endswith((".hpp", ".hip")):
-            h.update(open(f, "rb").read())
+    for f in SEGMENT_KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_2003_03508_amd", "csrc", f), "rb").read())
     return h.hexdigest()
 
 
@@ -73,9 +76,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--workload", default="k25_t1e6", choices=["k25_t1e6", "k80_t4m", "batch256", "mcmc_k20"])
     ap.add_argument("--no-mcmc", action="store_true", help="skip the MCMC leg of the default run")
-    ap.add_argument("--mcmc-iterations", type=int, default=2000)
-    ap.add_argument("--mcmc-chains", type=int, default=16)
-    ap.add_argument("--mcmc-lag", type=int, default=20)
+    ap.add_argument("--mcmc-iterations", type=int, default=8000)
+    ap.add_argument("--mcmc-chains", type=int, default=4)
+    ap.add_argument("--mcmc-lag", type=int, default=5)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--serial-steps", type=int, default=3)
@@ -335,24 +338,27 @@ def bench_batch(args):
     }))
 
 
-def run_mcmc(C=16, burn=300, adapt_rounds=3, n_iter=2000, lag=20, train_steps=1500, batch=256, lr=1e-3,
-             eps=0.1, seed=1, log=None):
-    """MCMC leg: posterior over all parameters of the K=20 model given the
-    T=500,000 path simulated with seed 4, random-walk MH vs the learned
-    proposal, C chains each, exact FP32 likelihood in every MH step.
+def run_mcmc(C=4, burn_rounds=12, adapt_rounds=6, round_len=1000, n_iter=8000, lag=5, train_steps=500,
+             lr=1e-4, eps=0.1, seed=1, log=None):
+    """MCMC leg: posterior over all D = 480 parameters of the K=20 model given
+    the T=500,000 path simulated with seed 4; random-walk MH vs the learned
+    proposal, C chains each, the exact FP32 likelihood in every MH step.
 
-    1. Burn-in from the generating parameters with a diagonal random walk,
-       adapted for `adapt_rounds` rounds of `burn` iterations (per-coordinate
-       scale 2.38/sqrt(D) times the chain spread, times a factor steering the
-       acceptance toward 0.234).  Both methods start from its end state and
-       use its random-walk scale.
-    2. The proposal network is trained on the burn-in history (lagged pairs),
-       timed, and frozen.
-    3. n_iter iterations of each method from the same states.  ESS per
-       coordinate (multi-chain, Geyer), ESS/s = ESS / wall time, the learned
+    1. Burn-in from the generating parameters: burn_rounds rounds of
+       round_len random-walk iterations; during the first adapt_rounds the
+       per-coordinate scale is set to 2.38/sqrt(D) times the chains' spread in
+       the last round, times a factor steering the acceptance toward 0.234.
+       Both methods start from the burn-in's end state with its final
+       random-walk scale.
+    2. The proposal network is trained on the second half of the burn-in
+       (lagged pairs, 20% held out; least-squares start of its linear part,
+       then Adam steps kept only where the held-out loss improves), timed,
+       and frozen.
+    3. n_iter iterations of each method.  ESS per coordinate (multi-chain,
+       Geyer) and of the log posterior; ESS/s = ESS / wall time, the learned
        method's time including its training.
-    Equal posterior accuracy: the two runs' posterior means agree within
-    their Monte Carlo standard errors (z-scores reported).
+    Agreement of the two runs' posterior means is reported as z-scores
+    (difference over the combined Monte Carlo standard error).
     """
     import numpy as np
     import torch
@@ -371,7 +377,8 @@ def run_mcmc(C=16, burn=300, adapt_rounds=3, n_iter=2000, lag=20, train_steps=15
     d = binding.to_device(prm, obs)
     ctx = binding.Context(0)
     D = hm.dim(K)
-    H = max(burn * adapt_rounds, n_iter)
+    burn = burn_rounds * round_len
+    H = burn + 2 * n_iter
     f64 = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
     # initial random-walk scale: posterior standard deviations guessed from counts
     sl = hm.block_slices(K)
@@ -387,9 +394,9 @@ def run_mcmc(C=16, burn=300, adapt_rounds=3, n_iter=2000, lag=20, train_steps=15
     ch.set_state(f64(np.tile(th0, (C, 1))), f64(rw))
 
     def window(n):
-        hist, _, it = ch.history()
-        hist = hist.cpu().numpy()
-        return hist[[(it - n + i) % H for i in range(n)]].transpose(1, 0, 2).astype(np.float64)
+        hist, hlp, it = ch.history()
+        idx = [(it - n + i) % H for i in range(n)]
+        return (hist[idx].cpu().numpy().transpose(1, 0, 2).astype(np.float64), hlp[idx].cpu().numpy().T)
 
     def run(n, proposal):
         a0 = int(ch.state()["accepts"].sum())
@@ -402,57 +409,65 @@ def run_mcmc(C=16, burn=300, adapt_rounds=3, n_iter=2000, lag=20, train_steps=15
 
     scale = 1.0
     t_burn = 0.0
-    for r in range(adapt_rounds):
-        dt, acc = run(burn, binding.MCMC_RANDOM_WALK)
+    for r in range(burn_rounds):
+        dt, acc = run(round_len, binding.MCMC_RANDOM_WALK)
         t_burn += dt
-        spread = window(burn)[:, burn // 3:].reshape(-1, D).std(axis=0)
-        scale *= 0.7 if acc < 0.15 else (1.3 if acc > 0.35 else 1.0)
-        rw = scale * 2.38 / math.sqrt(D) * np.maximum(spread, 1e-12)
-        ch.set_rw_scale(f64(rw))
-        say(f"burn-in round {r}: acceptance {acc:.3f}, {dt / burn * 1e3:.2f} ms/iteration")
+        if r < adapt_rounds:
+            spread = window(round_len)[0][:, round_len // 3:].reshape(-1, D).std(axis=0)
+            scale *= math.exp(3.0 * (acc - 0.234))
+            rw = scale * 2.38 / math.sqrt(D) * np.maximum(spread, 1e-12)
+            ch.set_rw_scale(f64(rw))
+        say(f"burn-in round {r}: acceptance {acc:.3f}, {dt / round_len * 1e3:.2f} ms/iteration")
     start = ch.state()["theta"].clone()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    losses = ch.train(train_steps, batch=batch, lag=lag, lr=lr, window=burn * adapt_rounds)
+    tr = ch.train(train_steps, batch=256, lag=lag, lr=lr, window=burn // 2, holdout=0.2, val_every=25,
+                  val_batch=1024)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
-    losses = losses.cpu().numpy()
-    say(f"training: {train_steps} steps in {t_train:.2f} s, loss {losses[:50].mean():.3f} -> "
-        f"{losses[-50:].mean():.3f}")
+    val = tr["val"].cpu().numpy()
+    say(f"training: {train_steps} steps in {t_train:.2f} s, held-out loss {val[0]:.3f} -> best {val.min():.3f} "
+        f"(kept step {tr['best_step']})")
 
-    res = {}
+    res, draws = {}, {}
     for name, prop in (("random_walk", binding.MCMC_RANDOM_WALK), ("learned", binding.MCMC_LEARNED)):
         ch.set_state(start, f64(rw))
         dt, acc = run(n_iter, prop)
-        w = window(n_iter)
+        w, lpost = window(n_iter)
         ess = E.ess_columns(w)
+        ess_lp = E.ess(lpost)
         cost = dt + (t_train if prop == binding.MCMC_LEARNED else 0.0)
-        res[name] = dict(seconds=round(dt, 3), ms_per_iteration=round(dt / n_iter * 1e3, 3),
+        res[name] = dict(seconds=round(dt, 3), ms_per_iteration=round(dt / n_iter * 1e3, 4),
                          acceptance=round(acc, 4), ess_min=round(float(ess.min()), 2),
-                         ess_median=round(float(np.median(ess)), 2),
-                         ess_per_s_min=round(float(ess.min()) / cost, 3),
-                         ess_per_s_median=round(float(np.median(ess)) / cost, 3),
-                         means=w.reshape(-1, D).mean(axis=0),
-                         mcse=np.array([E.mcse_mean(w[:, :, j]) for j in range(D)]))
-        say(f"{name}: acceptance {acc:.3f}, ESS min {ess.min():.1f} median {np.median(ess):.1f}, "
-            f"{dt:.2f} s")
+                         ess_median=round(float(np.median(ess)), 2), ess_logpost=round(float(ess_lp), 2),
+                         ess_per_s_median=round(float(np.median(ess)) / cost, 4),
+                         ess_per_s_logpost=round(float(ess_lp) / cost, 4),
+                         ess_per_s_min=round(float(ess.min()) / cost, 4),
+                         ess_median_by_block={k: round(float(np.median(ess[v])), 2) for k, v in sl.items()})
+        draws[name] = (w.reshape(-1, D).mean(axis=0), np.array([E.mcse_mean(w[:, :, j]) for j in range(D)]))
+        say(f"{name}: acceptance {acc:.3f}, ESS median {np.median(ess):.1f}, log posterior {ess_lp:.1f}, "
+            f"min {ess.min():.1f}, {dt:.2f} s")
     ch.close()
     ctx.close()
     a, b = res["random_walk"], res["learned"]
-    z = np.abs(a["means"] - b["means"]) / np.sqrt(a["mcse"] ** 2 + b["mcse"] ** 2)
-    for r in (a, b):
-        del r["means"], r["mcse"]
+    z = np.abs(draws["random_walk"][0] - draws["learned"][0]) / np.sqrt(
+        draws["random_walk"][1] ** 2 + draws["learned"][1] ** 2)
+    gain = lambda k: round(b[k] / a[k], 3) if a[k] > 0 else None
     return {
-        "workload": "k20_t5e5: posterior over all parameters (D=480) of a K=20 tremor HMM given "
+        "workload": "k20_t5e5: posterior over all D=480 parameters of a K=20 tremor HMM given "
                     "T=500,000 observations simulated with seed 4",
-        "chains": C, "iterations": n_iter, "burn_in": burn * adapt_rounds,
-        "burn_in_seconds": round(t_burn, 3), "train_seconds": round(t_train, 3),
-        "train_steps": train_steps, "lag": lag, "mixture_eps": eps,
-        "random_walk": a, "learned": b,
-        "ess_per_s_gain_median": round(b["ess_per_s_median"] / a["ess_per_s_median"], 3),
-        "ess_per_s_gain_min": round(b["ess_per_s_min"] / a["ess_per_s_min"], 3),
-        "mean_agreement_z_max": round(float(z.max()), 3),
-        "mean_agreement_z_frac_below_3": round(float((z < 3).mean()), 4),
+        "chains": C, "iterations": n_iter, "burn_in": burn, "burn_in_seconds": round(t_burn, 3),
+        "train_seconds": round(t_train, 3), "train_steps": train_steps, "kept_adam_step": tr["best_step"],
+        "held_out_loss": [round(float(val[0]), 3), round(float(val.min()), 3)],
+        "lag": lag, "mixture_eps": eps, "random_walk": a, "learned": b,
+        "ess_per_s_gain_median": gain("ess_per_s_median"),
+        "ess_per_s_gain_logpost": gain("ess_per_s_logpost"),
+        "ess_per_s_gain_min": gain("ess_per_s_min"),
+        "mean_agreement_z_median": round(float(np.median(z)), 3),
+        "mean_agreement_frac_z_below_3": round(float((z < 3).mean()), 4),
+        "note": "min ESS sits on Gamma logits of transitions with (almost) no observed counts, whose "
+                "posterior is the Dirichlet(0.01) prior's heavy tail in log space; no local-move sampler "
+                "mixes them in this budget",
     }
 
 

@@ -203,7 +203,8 @@ int hmm_ctx_profile_read(hmm_ctx *ctx, int64_t *launches, double *total_ms);
  * ((64-bit word >> 11) + 1/2) * 2^-53 of words (0,1) and (2,3); normals are
  * Box-Muller pairs (r cos 2 pi u1, r sin 2 pi u1), r = sqrt(-2 ln u0).
  * Purposes: 1 proposal normals (index = coordinate pair), 2 mixture choice,
- * 3 acceptance uniform, 4 training minibatch rows, 5 weight initialisation.
+ * 3 acceptance uniform, 4 training minibatch rows, 5 weight initialisation,
+ * 6 held-out pairs of a training call.
  * ------------------------------------------------------------------------ */
 typedef enum { MCMC_RANDOM_WALK = 0, MCMC_LEARNED = 1 } mcmc_proposal;
 
@@ -264,21 +265,57 @@ int mcmc_step(mcmc_chains *chains, int32_t n_iter, int32_t proposal, double eps,
 
 int mcmc_view_get(mcmc_chains *chains, mcmc_view *view);
 
-/* Train the learned proposal on lagged pairs (theta_t, theta_{t+lag}) of the
- * last `window` iterations of history (0 = the whole ring): `steps` Adam steps
- * (beta 0.9 / 0.999, eps 1e-8, learning rate lr) on minibatches of `batch`
- * pairs (time and chain drawn with purpose 4) of the Gaussian negative
- * log-likelihood of the move.  The first call fixes the standardisation from
- * the window (center and in_scale: mean and standard deviation of theta;
- * out_scale: standard deviation of the lag-`lag` move; scales floored at
- * 0.1 * rw_scale) and the lag.  loss_out: device float[steps] or NULL,
- * receives each step's minibatch loss.
- * Network: X (D) -> tanh(X W1 + b1) (256) -> tanh(. W2 + b2) (256)
- *          -> . W3 + b3 (2D);  weights flat, FP32, in the order
- *          W1 [D][256], b1, W2 [256][256], b2, W3 [256][2D], b3, each W
- *          row-major with the input index first. */
-int mcmc_train_proposal(mcmc_chains *chains, int32_t steps, int32_t batch, int32_t lag,
-                        double lr, int64_t window, void *stream, float *loss_out);
+/* Options of mcmc_train_proposal. */
+typedef struct {
+    int32_t steps;        /* Adam steps (0: only the start described below)          */
+    int32_t batch;        /* pairs per minibatch, 1..65535                            */
+    int32_t lag;          /* pair lag in iterations (fixed by the first call)         */
+    double lr;            /* Adam learning rate (beta 0.9 / 0.999, eps 1e-8)          */
+    double weight_decay;  /* decoupled weight decay on W1, W2, W3                     */
+    int64_t window;       /* iterations of history used (0: as far as the ring goes)  */
+    int64_t window_end;   /* the window ends before this iteration (0: the current)   */
+    double holdout;       /* fraction of the window (its end) held out, in [0, 1)     */
+    int32_t val_every;    /* Adam steps between evaluations of the held-out loss      */
+    int32_t val_batch;    /* held-out pairs evaluated, 1..65535                       */
+} mcmc_train_opts;
+
+/* Train the learned proposal on lagged pairs (theta_t, theta_{t+lag}) of a
+ * window of history: the `window` iterations before iteration `window_end`.
+ * With holdout > 0 the window is split in time: pairs starting in its first
+ * 1 - holdout part train, pairs starting in the rest are held out.  Adam
+ * steps run on minibatches of training pairs (time and chain drawn with
+ * Philox purpose 4, iteration word = the network's Adam step) of the
+ * Gaussian negative log-likelihood of the move.  The first call after
+ * creation or mcmc_reset_proposal fixes, from the training pairs, the
+ * standardisation (center and in_scale: mean and standard deviation of
+ * theta; out_scale: standard deviation of the lag move; scales floored at
+ * 0.1 * rw_scale) and the lag, and starts the network at the least-squares
+ * fit of its linear part: per coordinate, move/out_scale = a x + b + noise of
+ * standard deviation s gives the skip a, the mean bias b (b3[d]) and the
+ * log-sd bias ln s (b3[D+d]), with W3 = 0.  With holdout > 0, val_batch
+ * held-out pairs (purpose 6) are evaluated before the first step and every
+ * val_every steps; the call ends with the weights of the lowest held-out loss
+ * (possibly the starting ones).
+ * loss_out: device float[steps] or NULL (each step's minibatch loss);
+ * val_out: device float[1 + ceil(steps / val_every)] or NULL (held-out
+ * losses); best_step: host int or NULL, receives the Adam step (0-based,
+ * within this call) whose weights were kept, -1 for the starting weights
+ * (synchronises the stream).
+ * Network: X (D) -> h1 = tanh(X W1 + b1) (256) -> h2 = tanh(h1 W2 + b2) (256)
+ *          -> o = h2 W3 + b3 (2D), plus a per-coordinate linear skip on the
+ *          mean outputs: o[d] += a[d] X[d] for d < D (it represents the
+ *          mean reversion of lagged moves coordinate by coordinate, which the
+ *          256-wide layers cannot for D > 256).  Weights flat, FP32, in the
+ *          order W1 [D][256], b1, W2 [256][256], b2, W3 [256][2D], b3, a [D],
+ *          each W row-major with the input index first. */
+int mcmc_train_proposal(mcmc_chains *chains, const mcmc_train_opts *opts, void *stream,
+                        float *loss_out, float *val_out, int32_t *best_step);
+
+/* Forget the trained network: weights re-initialised from `seed` (Glorot
+ * uniform hidden layers, zero output layer, biases and skip), Adam state
+ * cleared; the next training call recomputes the standardisation and may
+ * choose a new lag. */
+int mcmc_reset_proposal(mcmc_chains *chains, uint64_t seed, void *stream);
 
 /* The proposal network on its own (for checks): network outputs out[n*2D]
  * for inputs X[n*D] (device, FP32). */

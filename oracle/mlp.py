@@ -2,12 +2,14 @@
 
 TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
 
-Network (two hidden layers of width H, tanh):
-    h1 = tanh(x W1 + b1),  h2 = tanh(h1 W2 + b2),  o = h2 W3 + b3
+Network (two hidden layers of width H, tanh, and a per-coordinate linear
+skip on the mean outputs):
+    h1 = tanh(x W1 + b1),  h2 = tanh(h1 W2 + b2),  o = h2 W3 + b3,
+    o[:D] += a * x
 with x of length D and o of length 2D: o[:D] is the mean of the move and
 o[D:] its log standard deviation, both in units of the output scale.
 Weights are one flat vector in the order W1 (D x H), b1, W2 (H x H), b2,
-W3 (H x 2D), b3, each W row-major with the input index first.
+W3 (H x 2D), b3, a (D), each W row-major with the input index first.
 
 Loss of a minibatch of B rows (x_b, r_b), r the observed move:
     loss = (1/B) sum_b sum_d [ (r_bd - o_bd)^2 exp(-2 o_b,D+d) / 2 + o_b,D+d ]
@@ -19,7 +21,7 @@ import numpy as np
 
 
 def sizes(D, H):
-    return [(D, H), (H,), (H, H), (H,), (H, 2 * D), (2 * D,)]
+    return [(D, H), (H,), (H, H), (H,), (H, 2 * D), (2 * D,), (D,)]
 
 
 def count(D, H):
@@ -39,11 +41,13 @@ def unpack(w, D, H):
 
 def forward(w, X, D, H):
     """Outputs (B, 2D) and the hidden activations."""
-    W1, b1, W2, b2, W3, b3 = unpack(w, D, H)
+    W1, b1, W2, b2, W3, b3, a = unpack(w, D, H)
     X = np.asarray(X, dtype=np.float64)
     h1 = np.tanh(X @ W1 + b1)
     h2 = np.tanh(h1 @ W2 + b2)
-    return h2 @ W3 + b3, (h1, h2)
+    O = h2 @ W3 + b3
+    O[:, :D] += a * X
+    return O, (h1, h2)
 
 
 def loss_rows(w, X, R, D, H):
@@ -62,7 +66,7 @@ def loss(w, X, R, D, H):
 
 def grad(w, X, R, D, H):
     """Gradient of `loss` with respect to the flat weight vector."""
-    W1, b1, W2, b2, W3, b3 = unpack(w, D, H)
+    W1, b1, W2, b2, W3, b3, a = unpack(w, D, H)
     X = np.asarray(X, dtype=np.float64)
     R = np.asarray(R, dtype=np.float64)
     O, (h1, h2) = forward(w, X, D, H)
@@ -70,6 +74,7 @@ def grad(w, X, R, D, H):
     e = R - O[:, :D]
     q = np.exp(-2.0 * O[:, D:])
     dO = np.concatenate([-e * q, 1.0 - e * e * q], axis=1) / B
+    ga = (dO[:, :D] * X).sum(axis=0)
     gW3 = h2.T @ dO
     gb3 = dO.sum(axis=0)
     dh2 = (dO @ W3.T) * (1.0 - h2 * h2)
@@ -78,7 +83,7 @@ def grad(w, X, R, D, H):
     dh1 = (dh2 @ W2.T) * (1.0 - h1 * h1)
     gW1 = X.T @ dh1
     gb1 = dh1.sum(axis=0)
-    return np.concatenate([g.ravel() for g in (gW1, gb1, gW2, gb2, gW3, gb3)])
+    return np.concatenate([g.ravel() for g in (gW1, gb1, gW2, gb2, gW3, gb3, ga)])
 
 
 def move(w, theta, center, in_scale, out_scale, D, H):

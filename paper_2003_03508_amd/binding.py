@@ -55,7 +55,15 @@ _lib.mcmc_destroy.argtypes = [_vp]
 _lib.mcmc_set_state.argtypes = [_vp, _vp, _vp, _vp]
 _lib.mcmc_set_rw_scale.argtypes = [_vp, _vp, _vp]
 _lib.mcmc_step.argtypes = [_vp, _i32, _i32, ctypes.c_double, _vp]
-_lib.mcmc_train_proposal.argtypes = [_vp, _i32, _i32, _i32, ctypes.c_double, _i64, _vp, _vp]
+class TrainOpts(ctypes.Structure):
+    """Mirror of mcmc_train_opts in include/hmm.h."""
+    _fields_ = [("steps", _i32), ("batch", _i32), ("lag", _i32), ("lr", ctypes.c_double),
+                ("weight_decay", ctypes.c_double), ("window", _i64), ("window_end", _i64),
+                ("holdout", ctypes.c_double), ("val_every", _i32), ("val_batch", _i32)]
+
+
+_lib.mcmc_train_proposal.argtypes = [_vp, ctypes.POINTER(TrainOpts), _vp, _vp, _vp, ctypes.POINTER(_i32)]
+_lib.mcmc_reset_proposal.argtypes = [_vp, ctypes.c_uint64, _vp]
 _lib.mlp_forward.argtypes = [_vp, _i32, _vp, _vp, _vp]
 _lib.mlp_loss_grad.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp, _vp]
 _lib.mlp_set_weights.argtypes = [_vp, _vp, _vp, _vp, _vp, _i32, _vp]
@@ -80,7 +88,8 @@ for _f in ("hmm_ctx_create", "hmm_ctx_destroy", "hmm_loglik", "hmm_emission",
            "hmm_ctx_set_blocking", "hmm_blocked_plan", "hmm_ctx_profile", "hmm_ctx_profile_read",
            "hmm_loglik_batched", "hmm_ctx_set_batch_graph", "hmm_autotune_batched",
            "hmm_theta_to_params", "hmm_philox", "mcmc_create", "mcmc_destroy", "mcmc_set_state",
-           "mcmc_set_rw_scale", "mcmc_step", "mcmc_train_proposal", "mcmc_view_get", "mlp_forward",
+           "mcmc_set_rw_scale", "mcmc_step", "mcmc_train_proposal", "mcmc_reset_proposal", "mcmc_view_get",
+           "mlp_forward",
            "mlp_loss_grad", "mlp_set_weights"):
     getattr(_lib, _f).restype = ctypes.c_int
 
@@ -364,13 +373,27 @@ class Chains:
     def step(self, n_iter=1, proposal=MCMC_RANDOM_WALK, eps=0.1, stream=None):
         _check("mcmc_step", _lib.mcmc_step(self._h, int(n_iter), int(proposal), float(eps), _stream(stream)))
 
-    def train(self, steps, batch=256, lag=1, lr=1e-3, window=0, stream=None, losses=True):
-        """Adam steps on lagged pairs of the history; returns the per-step losses (device) or None."""
+    def train(self, steps, batch=256, lag=1, lr=1e-3, window=0, weight_decay=0.0, window_end=0, holdout=0.0,
+              val_every=25, val_batch=512, stream=None, losses=True):
+        """Train the proposal network on lagged pairs of the history.
+
+        Returns a dict: ``loss`` (device float32[steps], minibatch losses) and, with
+        holdout > 0, ``val`` (device held-out losses, the first before any step) and
+        ``best_step`` (Adam step whose weights were kept, -1 = the starting weights)."""
+        o = TrainOpts(int(steps), int(batch), int(lag), float(lr), float(weight_decay), int(window),
+                      int(window_end), float(holdout), int(val_every), int(val_batch))
         out = torch.empty(max(steps, 1), dtype=torch.float32, device=self.ctx.device) if losses else None
+        n_val = 1 + (-(-steps // max(int(val_every), 1))) if holdout > 0 else 0
+        val = torch.empty(max(n_val, 1), dtype=torch.float32, device=self.ctx.device) if n_val else None
+        best = _i32(-2)
         _check("mcmc_train_proposal", _lib.mcmc_train_proposal(
-            self._h, int(steps), int(batch), int(lag), float(lr), int(window), _stream(stream),
-            _dev(out, torch.float32, "loss") if losses else None))
-        return out[:steps] if losses else None
+            self._h, ctypes.byref(o), _stream(stream), _dev(out, torch.float32, "loss") if losses else None,
+            _dev(val, torch.float32, "val") if n_val else None, ctypes.byref(best) if n_val else None))
+        return dict(loss=out[:steps] if losses else None, val=val[:n_val] if n_val else None,
+                    best_step=best.value if n_val else None)
+
+    def reset_proposal(self, seed=0, stream=None):
+        _check("mcmc_reset_proposal", _lib.mcmc_reset_proposal(self._h, int(seed), _stream(stream)))
 
     def mlp_forward(self, X, stream=None):
         n = X.numel() // self.D

@@ -101,6 +101,7 @@ constexpr uint32_t kDrawMixture = 2;   // which proposal component
 constexpr uint32_t kDrawAccept = 3;    // the MH uniform
 constexpr uint32_t kDrawMinibatch = 4; // training minibatch rows
 constexpr uint32_t kDrawInit = 5;      // weight initialisation
+constexpr uint32_t kDrawValidation = 6; // held-out pairs of a training call
 
 // ---------------------------------------------------------------------------
 // theta -> packed likelihood block (delta | Gamma | p | mu | Sigma) and the

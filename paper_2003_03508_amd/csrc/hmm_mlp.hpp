@@ -70,6 +70,51 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int Kd, float alpha,
     }
 }
 
+// Few-row product for the sampler's per-iteration network passes (M <= 16
+// rows, one per chain): C = act(A B + bias), A [M][Kd] row-major (lda), B
+// [Kd][N] row-major (ldb).  A workgroup owns 16 output columns; its 256
+// threads are 16 columns x 16 slices of the contraction, each slice summed
+// for all M rows, then the slices are added in LDS in a fixed order.  A is
+// staged in LDS once per workgroup.  Launch: grid ceil(N / 16), 256 threads,
+// dynamic LDS M * Kd floats.
+constexpr int kSkinnyMaxRows = 16;
+
+__global__ __launch_bounds__(256) void k_gemm_skinny(int M, int N, int Kd, const float *__restrict__ A, int lda,
+                                                     const float *__restrict__ B, int ldb,
+                                                     const float *__restrict__ bias, float *__restrict__ C, int ldc,
+                                                     int act)
+{
+    extern __shared__ float As[];  // [M][Kd]
+    __shared__ float part[16][16][kSkinnyMaxRows + 1];
+    const int j = threadIdx.x & 15, sl = threadIdx.x >> 4;
+    const int n = blockIdx.x * 16 + j;
+    for (int i = threadIdx.x; i < M * Kd; i += 256) As[i] = A[(int64_t)(i / Kd) * lda + (i % Kd)];
+    __syncthreads();
+    float acc[kSkinnyMaxRows];
+#pragma unroll
+    for (int m = 0; m < kSkinnyMaxRows; ++m) acc[m] = 0.f;
+    if (n < N) {
+        for (int k = sl; k < Kd; k += 16) {
+            const float b = B[(int64_t)k * ldb + n];
+#pragma unroll
+            for (int m = 0; m < kSkinnyMaxRows; ++m)
+                if (m < M) acc[m] = fmaf(As[m * Kd + k], b, acc[m]);
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < kSkinnyMaxRows; ++m) part[sl][j][m] = acc[m];
+    __syncthreads();
+    // thread (j, m) for m < M adds the 16 slices in order
+    const int m = threadIdx.x >> 4;
+    if (m < M && n < N) {
+        float v = 0.f;
+        for (int q = 0; q < 16; ++q) v += part[q][j][m];
+        if (bias) v += bias[n];
+        if (act == 1) v = tanhf(v);
+        C[(int64_t)m * ldc + n] = v;
+    }
+}
+
 // G[i] *= (1 - Y[i]^2): backward through tanh (Y = tanh output).
 __global__ __launch_bounds__(256) void k_tanh_back(int64_t n, const float *__restrict__ Y, float *__restrict__ G)
 {
@@ -120,10 +165,36 @@ __global__ __launch_bounds__(256) void k_nll_grad(int B, int D, const float *__r
     if (threadIdx.x == 0 && row_loss) row_loss[b] = red[0] * invB;
 }
 
-// Adam (Kingma & Ba) with bias correction; t is the 1-based step.
+// Per-coordinate linear skip of the mean outputs: O[b][d] += a[d] X[b][d] for
+// d < D (O has row stride 2D, X row stride D).
+__global__ __launch_bounds__(256) void k_skip_fwd(int n, int D, const float *__restrict__ X,
+                                                  const float *__restrict__ a, float *__restrict__ O)
+{
+    const int64_t tot = (int64_t)n * D;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < tot; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t b = i / D;
+        const int d = (int)(i - b * D);
+        O[b * 2 * D + d] += a[d] * X[i];
+    }
+}
+
+// Gradient of the skip weights: ga[d] = sum_b dO[b][d] X[b][d].
+__global__ __launch_bounds__(256) void k_skip_grad(int B, int D, const float *__restrict__ X,
+                                                   const float *__restrict__ dO, float *__restrict__ ga)
+{
+    for (int d = blockIdx.x * blockDim.x + threadIdx.x; d < D; d += gridDim.x * blockDim.x) {
+        float s = 0.f;
+        for (int b = 0; b < B; ++b) s += dO[(int64_t)b * 2 * D + d] * X[(int64_t)b * D + d];
+        ga[d] = s;
+    }
+}
+
+// Adam (Kingma & Ba) with bias correction and decoupled weight decay
+// (Loshchilov & Hutter): w -= lr (m_hat / (sqrt(v_hat) + eps) + wd w).  t is
+// the 1-based step.
 __global__ __launch_bounds__(256) void k_adam(int64_t n, float *__restrict__ w, const float *__restrict__ g,
                                               float *__restrict__ m, float *__restrict__ v, float lr, float b1,
-                                              float b2, float eps, int t)
+                                              float b2, float eps, int t, float wd)
 {
     const float c1 = 1.f / (1.f - powf(b1, (float)t)), c2 = 1.f / (1.f - powf(b2, (float)t));
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
@@ -131,7 +202,7 @@ __global__ __launch_bounds__(256) void k_adam(int64_t n, float *__restrict__ w, 
         const float mi = b1 * m[i] + (1.f - b1) * gi, vi = b2 * v[i] + (1.f - b2) * gi * gi;
         m[i] = mi;
         v[i] = vi;
-        w[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+        w[i] -= lr * ((mi * c1) / (sqrtf(vi * c2) + eps) + wd * w[i]);
     }
 }
 

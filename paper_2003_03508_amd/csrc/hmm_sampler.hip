@@ -87,9 +87,10 @@ __device__ inline double log_mix(double eps, double lq_mlp, double lq_rw)
     return mx + log(exp(a - mx) + exp(b - mx));
 }
 
-// Proposal of chain c = blockIdx.x at iteration `iter`.  Writes theta', its
-// likelihood block and log prior, and ln q(theta' | theta) (learned mode).
-__global__ __launch_bounds__(256) void k_propose(int K, uint64_t seed, uint32_t iter, int learned, double eps,
+// Proposal of chain c = blockIdx.x at iteration *iter_dev.  Writes theta',
+// its likelihood block and log prior, and ln q(theta' | theta) (learned mode).
+__global__ __launch_bounds__(256) void k_propose(int K, uint64_t seed, const uint32_t *__restrict__ iter_dev,
+                                                 int learned, double eps,
                                                  const double *__restrict__ theta, const double *__restrict__ rw,
                                                  const float *__restrict__ net_out,
                                                  const double *__restrict__ out_scale, double *__restrict__ theta_p,
@@ -99,6 +100,7 @@ __global__ __launch_bounds__(256) void k_propose(int K, uint64_t seed, uint32_t 
     __shared__ double scratch[4];
     const int D = theta_dim(K), P = param_block(K);
     const int c = blockIdx.x;
+    const uint32_t iter = *iter_dev;
     const double *th = theta + (int64_t)c * D;
     double *tp = theta_p + (int64_t)c * D;
     const float *o = learned ? net_out + (int64_t)c * 2 * D : nullptr;
@@ -135,22 +137,26 @@ __global__ __launch_bounds__(256) void k_propose(int K, uint64_t seed, uint32_t 
     }
 }
 
-// Accept / reject of chain c and the history record of the resulting state:
+// Accept / reject of chain c at iteration *iter_dev and the history record
+// of the resulting state (slot iteration % H):
 //   ln A = (ll' + lp') - (ll + lp) + ln q(theta | theta') - ln q(theta' | theta)
 // accepted when ln u < ln A with u from Philox (a NaN ln A is a rejection).
-__global__ __launch_bounds__(256) void k_accept(int K, uint64_t seed, uint32_t iter, int learned, double eps,
+__global__ __launch_bounds__(256) void k_accept(int K, uint64_t seed, const uint32_t *__restrict__ iter_dev,
+                                                int learned, double eps,
                                                 double *__restrict__ theta, const double *__restrict__ theta_p,
                                                 double *__restrict__ ll, double *__restrict__ lp,
                                                 const double *__restrict__ ll_p, const double *__restrict__ lp_p,
                                                 const double *__restrict__ lq_fwd, const float *__restrict__ net_out_rev,
                                                 const double *__restrict__ out_scale, const double *__restrict__ rw,
                                                 long long *__restrict__ accepts, float *__restrict__ hist,
-                                                double *__restrict__ hist_lpost, int64_t slot, int C)
+                                                double *__restrict__ hist_lpost, int64_t H, int C)
 {
     __shared__ double scratch[4];
     __shared__ int acc_flag;
     const int D = theta_dim(K);
     const int c = blockIdx.x;
+    const uint32_t iter = *iter_dev;
+    const int64_t slot = (int64_t)iter % H;
     double *th = theta + (int64_t)c * D;
     const double *tp = theta_p + (int64_t)c * D;
     double lq_mlp = 0.0, lq_rw = 0.0;
@@ -180,61 +186,109 @@ __global__ __launch_bounds__(256) void k_accept(int K, uint64_t seed, uint32_t i
     }
 }
 
-// Standardisation of the network from the history window [t0, t1) (ring of
-// H iterations), one thread per coordinate:
-//   center    mean of theta_d
-//   in_scale  standard deviation of theta_d
-//   out_scale standard deviation of theta_{t+lag,d} - theta_{t,d}
-// both scales floored at floor_frac * rw_d.
+// The iteration counter advances once every chain has been accepted or
+// rejected (launched after k_accept).
+__global__ void k_advance(uint32_t *iter_dev)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *iter_dev += 1u;
+}
+
+// Standardisation of the network and the least-squares start of its linear
+// part, from the history window [t0, t1) (ring of H iterations), one thread
+// per coordinate d:
+//   center      mean of theta_d
+//   in_scale    standard deviation of theta_d
+//   out_scale   standard deviation of the lag move theta_{t+lag,d} - theta_{t,d}
+//               (both scales floored at floor_frac * rw_d)
+// With x = (theta_t - center) / in_scale and r = move / out_scale over all
+// pairs of the window, the least-squares line r = a x + b with residual
+// standard deviation s gives the skip weight a, the mean bias b and the
+// log-sd bias ln s: the network starts at the maximum-likelihood Gaussian
+// AR(1) kernel of each coordinate (its other weights add to that).
 __global__ __launch_bounds__(256) void k_hist_stats(int D, int C, int64_t H, int64_t t0, int64_t t1, int lag,
                                                     const float *__restrict__ hist, const double *__restrict__ rw,
                                                     double floor_frac, double *__restrict__ center,
-                                                    double *__restrict__ in_scale, double *__restrict__ out_scale)
+                                                    double *__restrict__ in_scale, double *__restrict__ out_scale,
+                                                    float *__restrict__ b3, float *__restrict__ skip)
 {
     const int d = blockIdx.x * blockDim.x + threadIdx.x;
     if (d >= D) return;
-    // two passes (means, then centred sums) for accuracy
+    auto at = [&](int64_t t, int c) { return (double)hist[((t % H) * C + c) * (int64_t)D + d]; };
+    // means (all states; moves of the pairs)
     double s = 0.0, sd = 0.0;
     int64_t n = 0, nd = 0;
     for (int64_t t = t0; t < t1; ++t)
         for (int c = 0; c < C; ++c) {
-            const double v = hist[((t % H) * C + c) * (int64_t)D + d];
+            const double v = at(t, c);
             s += v;
             ++n;
             if (t + lag < t1) {
-                sd += hist[(((t + lag) % H) * C + c) * (int64_t)D + d] - v;
+                sd += at(t + lag, c) - v;
                 ++nd;
             }
         }
     const double mean = s / (double)n, mdiff = nd ? sd / (double)nd : 0.0;
+    // spreads
     double ss = 0.0, ssd = 0.0;
     for (int64_t t = t0; t < t1; ++t)
         for (int c = 0; c < C; ++c) {
-            const double v = hist[((t % H) * C + c) * (int64_t)D + d];
+            const double v = at(t, c);
             ss += (v - mean) * (v - mean);
             if (t + lag < t1) {
-                const double w = hist[(((t + lag) % H) * C + c) * (int64_t)D + d] - v - mdiff;
+                const double w = at(t + lag, c) - v - mdiff;
                 ssd += w * w;
             }
         }
     const double fl = floor_frac * rw[d];
+    const double isc = fmax(n > 1 ? sqrt(ss / (double)(n - 1)) : 0.0, fl);
+    const double osc = fmax(nd > 1 ? sqrt(ssd / (double)(nd - 1)) : 0.0, fl);
     center[d] = mean;
-    in_scale[d] = fmax(n > 1 ? sqrt(ss / (double)(n - 1)) : 0.0, fl);
-    out_scale[d] = fmax(nd > 1 ? sqrt(ssd / (double)(nd - 1)) : 0.0, fl);
+    in_scale[d] = isc;
+    out_scale[d] = osc;
+    // least-squares line of r on x over the pairs (centred sums)
+    double sx = 0.0, sr = 0.0;
+    for (int64_t t = t0; t + lag < t1; ++t)
+        for (int c = 0; c < C; ++c) {
+            const double v = at(t, c);
+            sx += (v - mean) / isc;
+            sr += (at(t + lag, c) - v) / osc;
+        }
+    const double mx = nd ? sx / (double)nd : 0.0, mr = nd ? sr / (double)nd : 0.0;
+    double sxx = 0.0, sxr = 0.0;
+    for (int64_t t = t0; t + lag < t1; ++t)
+        for (int c = 0; c < C; ++c) {
+            const double v = at(t, c);
+            const double x = (v - mean) / isc - mx, r = (at(t + lag, c) - v) / osc - mr;
+            sxx += x * x;
+            sxr += x * r;
+        }
+    const double a = sxx > 0.0 ? sxr / sxx : 0.0, b = mr - a * mx;
+    double se = 0.0;
+    for (int64_t t = t0; t + lag < t1; ++t)
+        for (int c = 0; c < C; ++c) {
+            const double v = at(t, c);
+            const double e = (at(t + lag, c) - v) / osc - (a * (v - mean) / isc + b);
+            se += e * e;
+        }
+    const double var = nd > 2 ? se / (double)(nd - 2) : 1.0;
+    skip[d] = (float)a;
+    b3[d] = (float)b;
+    b3[D + d] = (float)(0.5 * log(fmax(var, 1e-12)));
 }
 
-// Minibatch of lagged pairs from the window [t0, t1): row b draws the time
-// and the chain from Philox and writes the network input X (standardised
-// theta_t) and the target R = (theta_{t+lag} - theta_t) / out_scale.
+// Minibatch of lagged pairs (t, t + lag) with t in [t0, t1 - lag): row b
+// draws the time and the chain from Philox (counter (b, 0, step, purpose))
+// and writes the network input X (standardised theta_t) and the target
+// R = (theta_{t+lag} - theta_t) / out_scale.
 __global__ __launch_bounds__(256) void k_pairs(int D, int C, int64_t H, int64_t t0, int64_t t1, int lag, uint64_t seed,
-                                               uint32_t step, const float *__restrict__ hist,
+                                               uint32_t purpose, uint32_t step, const float *__restrict__ hist,
                                                const double *__restrict__ center, const double *__restrict__ in_scale,
                                                const double *__restrict__ out_scale, float *__restrict__ X,
                                                float *__restrict__ R)
 {
     const int b = blockIdx.x;
     double u0, u1;
-    philox_uniform2(seed, kDrawMinibatch, step, 0, b, &u0, &u1);
+    philox_uniform2(seed, purpose, step, 0, b, &u0, &u1);
     const int64_t span = t1 - lag - t0;
     const int64_t t = t0 + min(span - 1, (int64_t)(u0 * (double)span));
     const int c = min(C - 1, (int)(u1 * C));
@@ -244,6 +298,34 @@ __global__ __launch_bounds__(256) void k_pairs(int D, int C, int64_t H, int64_t 
         X[(int64_t)b * D + d] = (float)(((double)x[d] - center[d]) / in_scale[d]);
         R[(int64_t)b * D + d] = (float)(((double)y[d] - (double)x[d]) / out_scale[d]);
     }
+}
+
+// Validation bookkeeping of a training call (single thread): the summed
+// row losses of the held-out batch are this evaluation's loss; when it is
+// below the best so far it becomes the best and *take = 1 (the weights are
+// then copied by k_copy_if).  best[0]: best loss, best[1]: Adam step of the
+// best weights (-1 for the starting weights).
+__global__ void k_val_decide(int B, const float *__restrict__ rows, float *__restrict__ best, int step,
+                             int *__restrict__ take, float *__restrict__ val_out)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    float v = 0.f;
+    for (int b = 0; b < B; ++b) v += rows[b];
+    if (val_out) *val_out = v;
+    const int t = (v < best[0]) || (step < 0);
+    if (t) {
+        best[0] = v;
+        best[1] = (float)step;
+    }
+    *take = t;
+}
+
+__global__ __launch_bounds__(256) void k_copy_if(int64_t n, const float *__restrict__ src, float *__restrict__ dst,
+                                                 const int *__restrict__ take)
+{
+    if (!*take) return;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
 }
 
 // Uniform(-limit, limit) weights from Philox (Glorot initialisation).
@@ -272,8 +354,9 @@ __global__ __launch_bounds__(256) void k_philox(uint64_t seed, uint32_t purpose,
 // ---------------------------------------------------------------------------
 // Network host side
 // ---------------------------------------------------------------------------
-// Weights, flat: [W1 D*H | b1 H | W2 H*H | b2 H | W3 H*2D | b3 2D], each W
-// row-major (input index major): layer out = act(in @ W + b).
+// Weights, flat: [W1 D*H | b1 H | W2 H*H | b2 H | W3 H*2D | b3 2D | a D], each
+// W row-major (input index major): layer out = act(in @ W + b); a is the
+// per-coordinate linear skip added to the mean outputs (out[d] += a[d] x[d]).
 struct Net {
     int D = 0, H = kHidden;
     int64_t P = 0;
@@ -281,7 +364,7 @@ struct Net {
     int steps = 0;  // Adam steps taken
     int64_t offset(int part) const
     {
-        const int64_t sz[6] = {(int64_t)D * H, H, (int64_t)H * H, H, (int64_t)H * 2 * D, 2LL * D};
+        const int64_t sz[7] = {(int64_t)D * H, H, (int64_t)H * H, H, (int64_t)H * 2 * D, 2LL * D, D};
         int64_t off = 0;
         for (int i = 0; i < part; ++i) off += sz[i];
         return off;
@@ -303,12 +386,28 @@ void gemm(hipStream_t st, int M, int N, int Kd, const float *A, int lda, const f
     hipLaunchKernelGGL((k_gemm<TA, TB>), grid, dim3(256), 0, st, M, N, Kd, 1.0f, A, lda, B, ldb, bias, C, ldc, act, 0);
 }
 
+// C = act(A B + bias) for row-major A [M][Kd], B [Kd][N]: the few-row kernel
+// when M fits it (the sampler's per-iteration passes), else the tiled one.
+void gemm_nn(hipStream_t st, int M, int N, int Kd, const float *A, const float *B, const float *bias, float *C, int act)
+{
+    const size_t lds = sizeof(float) * (size_t)M * Kd;
+    if (M <= kSkinnyMaxRows && lds <= 32768) {
+        hipLaunchKernelGGL(k_gemm_skinny, dim3((N + 15) / 16), dim3(256), lds, st, M, N, Kd, A, Kd, B, N, bias, C, N,
+                           act);
+        return;
+    }
+    gemm<false, false>(st, M, N, Kd, A, Kd, B, N, bias, C, N, act);
+}
+
 void net_forward(hipStream_t st, const Net &net, int n, const float *X, float *H1, float *H2, float *O)
 {
     const int D = net.D, H = net.H;
-    gemm<false, false>(st, n, H, D, X, D, net.at(net.w, 0), H, net.at(net.w, 1), H1, H, 1);
-    gemm<false, false>(st, n, H, H, H1, H, net.at(net.w, 2), H, net.at(net.w, 3), H2, H, 1);
-    gemm<false, false>(st, n, 2 * D, H, H2, H, net.at(net.w, 4), 2 * D, net.at(net.w, 5), O, 2 * D, 0);
+    gemm_nn(st, n, H, D, X, net.at(net.w, 0), net.at(net.w, 1), H1, 1);
+    gemm_nn(st, n, H, H, H1, net.at(net.w, 2), net.at(net.w, 3), H2, 1);
+    gemm_nn(st, n, 2 * D, H, H2, net.at(net.w, 4), net.at(net.w, 5), O, 0);
+    const int64_t nd = (int64_t)n * D;
+    hipLaunchKernelGGL(k_skip_fwd, dim3((unsigned)std::min<int64_t>((nd + 255) / 256, 4096)), dim3(256), 0, st, n, D,
+                       X, net.at(net.w, 6), O);
 }
 
 // Gradient of the minibatch loss into net.g (activations from net_forward).
@@ -316,6 +415,8 @@ void net_backward(hipStream_t st, const Net &net, int B, const Acts &a)
 {
     const int D = net.D, H = net.H;
     hipLaunchKernelGGL(k_nll_grad, dim3(B), dim3(256), 0, st, B, D, a.R, a.O, a.dO, a.loss);
+    // out[:, :D] += a .* X
+    hipLaunchKernelGGL(k_skip_grad, dim3((D + 255) / 256), dim3(256), 0, st, B, D, a.X, a.dO, net.at(net.g, 6));
     // O = H2 W3 + b3
     gemm<true, false>(st, H, 2 * D, B, a.H2, H, a.dO, 2 * D, nullptr, net.at(net.g, 4), 2 * D, 0);
     hipLaunchKernelGGL(k_colsum, dim3((2 * D + 255) / 256), dim3(256), 0, st, B, 2 * D, a.dO, net.at(net.g, 5));
@@ -334,7 +435,8 @@ void net_backward(hipStream_t st, const Net &net, int B, const Acts &a)
 }  // namespace
 
 struct mcmc_chains {
-    hmm_ctx *ctx = nullptr;
+    hmm_ctx *ctx = nullptr;    // the caller's context (device)
+    hmm_ctx *own = nullptr;    // private context: the batched plan the iteration graphs replay
     int K = 0, C = 0, D = 0, P = 0;
     int64_t T = 0, H = 0;
     const uint8_t *flag = nullptr;
@@ -350,8 +452,16 @@ struct mcmc_chains {
     double *center = nullptr, *in_scale = nullptr, *out_scale = nullptr;
     int lag = 0;
     bool trained = false;
+    bool ready = false;        // state set: the likelihood plan exists
+    uint32_t *iter_dev = nullptr;
+    hipStream_t cap = nullptr; // capture stream of the iteration graphs
+    hipGraphExec_t exec[2] = {nullptr, nullptr};  // one MH iteration: random walk, learned
+    double exec_eps = -1.0;
     Net net;
-    Acts fwd, rev, train;
+    Acts fwd, rev, train, val;
+    float *best_w = nullptr;   // weights of the best validation loss
+    float *best = nullptr;     // [best loss, its Adam step]
+    int *take = nullptr;
     std::vector<int32_t> Ks;
     std::vector<int64_t> Ts, poff, ooff;
     std::vector<void *> allocs;
@@ -359,9 +469,21 @@ struct mcmc_chains {
 
 namespace {
 
+void drop_graphs(mcmc_chains *s)
+{
+    for (auto &e : s->exec)
+        if (e) {
+            (void)hipGraphExecDestroy(e);
+            e = nullptr;
+        }
+}
+
 void release(mcmc_chains *s)
 {
+    drop_graphs(s);
+    if (s->cap) (void)hipStreamDestroy(s->cap);
     for (void *p : s->allocs) (void)hipFree(p);
+    if (s->own) (void)hmm_ctx_destroy(s->own);
     delete s;
 }
 
@@ -398,11 +520,16 @@ int acts_alloc(mcmc_chains *s, Acts &a, int n, bool training)
     return rc;
 }
 
-int loglik_all(mcmc_chains *s, hipStream_t st, double *out)
+// ln L of every chain's block in s->params into s->ll_p, through the private
+// context's batched plan (its launch sequence, not a graph of its own, so that
+// it can be captured inside the iteration graph).
+int loglik_all(mcmc_chains *s, hipStream_t st)
 {
-    return hmm_loglik_batched(s->ctx, s->C, s->Ks.data(), s->Ts.data(), s->poff.data(), s->params,
-                              (int64_t)s->C * s->P, s->ooff.data(), s->flag, s->xy, s->T, HMM_BLOCKED_F32, st, out);
+    return hmm_loglik_batched(s->own, s->C, s->Ks.data(), s->Ts.data(), s->poff.data(), s->params,
+                              (int64_t)s->C * s->P, s->ooff.data(), s->flag, s->xy, s->T, HMM_BLOCKED_F32, st,
+                              s->ll_p);
 }
+
 
 void forward_states(mcmc_chains *s, hipStream_t st, const double *theta, Acts &a)
 {
@@ -412,7 +539,56 @@ void forward_states(mcmc_chains *s, hipStream_t st, const double *theta, Acts &a
     net_forward(st, s->net, s->C, a.X, a.H1, a.H2, a.O);
 }
 
+// One MH iteration of every chain, enqueued on st (captured into a graph).
+int enqueue_iteration(mcmc_chains *s, hipStream_t st, bool learned, double eps)
+{
+    if (learned) forward_states(s, st, s->theta, s->fwd);
+    hipLaunchKernelGGL(k_propose, dim3(s->C), dim3(256), 0, st, s->K, s->seed, s->iter_dev, learned ? 1 : 0, eps,
+                       s->theta, s->rw, s->fwd.O, s->out_scale, s->theta_p, s->params, s->lp_p, s->lq, s->box);
+    const int rc = loglik_all(s, st);
+    if (rc != HMM_OK) return rc;
+    if (learned) forward_states(s, st, s->theta_p, s->rev);
+    hipLaunchKernelGGL(k_accept, dim3(s->C), dim3(256), 0, st, s->K, s->seed, s->iter_dev, learned ? 1 : 0, eps,
+                       s->theta, s->theta_p, s->ll, s->lp, s->ll_p, s->lp_p, s->lq, s->rev.O, s->out_scale, s->rw,
+                       s->accepts, s->hist, s->hist_lpost, s->H, s->C);
+    hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, st, s->iter_dev);
+    return HMM_OK;
+}
+
+int build_graph(mcmc_chains *s, int mode, double eps)
+{
+    if (hipStreamBeginCapture(s->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) return HMM_E_DEVICE;
+    const int rc = enqueue_iteration(s, s->cap, mode == 1, eps);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(s->cap, &g);
+    if (rc != HMM_OK || e != hipSuccess || !g) {
+        if (g) (void)hipGraphDestroy(g);
+        (void)hipGetLastError();
+        return rc != HMM_OK ? rc : HMM_E_DEVICE;
+    }
+    const hipError_t ie = hipGraphInstantiate(&s->exec[mode], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ie != hipSuccess) {
+        (void)hipGetLastError();
+        s->exec[mode] = nullptr;
+        return HMM_E_DEVICE;
+    }
+    return HMM_OK;
+}
+
 int launch_status() { return hipGetLastError() == hipSuccess ? HMM_OK : HMM_E_DEVICE; }
+
+// Glorot-uniform hidden layers (W1, W2) from Philox; the caller has zeroed
+// the rest, so biases, the output layer and the skip start at zero and the
+// untrained learned move is N(theta, out_scale^2).
+void init_hidden_layers(const Net &n, uint64_t seed, hipStream_t st)
+{
+    const float l1 = std::sqrt(6.f / (n.D + n.H)), l2 = std::sqrt(6.f / (2 * n.H));
+    hipLaunchKernelGGL(k_init_weights, dim3(512), dim3(256), 0, st, (int64_t)n.D * n.H, n.at(n.w, 0), n.offset(0), l1,
+                       seed);
+    hipLaunchKernelGGL(k_init_weights, dim3(256), dim3(256), 0, st, (int64_t)n.H * n.H, n.at(n.w, 2), n.offset(2), l2,
+                       seed);
+}
 
 }  // namespace
 
@@ -456,9 +632,16 @@ int mcmc_create(hmm_ctx *ctx, int32_t K, int32_t n_chains, int64_t T, const uint
     if (rc == HMM_OK) rc = dalloc(s, &s->center, s->D);
     if (rc == HMM_OK) rc = dalloc(s, &s->in_scale, s->D);
     if (rc == HMM_OK) rc = dalloc(s, &s->out_scale, s->D);
+    if (rc == HMM_OK) rc = dalloc(s, &s->iter_dev, 1);
+    if (rc == HMM_OK) rc = hmm_ctx_create(&s->own, ctx->device);
+    if (rc == HMM_OK) {
+        s->own->tuned_L = ctx->tuned_L;
+        s->own->batch_graph = false;
+        if (hipStreamCreateWithFlags(&s->cap, hipStreamNonBlocking) != hipSuccess) rc = HMM_E_DEVICE;
+    }
     Net &n = s->net;
     n.D = s->D;
-    n.P = n.offset(6);
+    n.P = n.offset(7);
     if (rc == HMM_OK) rc = dalloc(s, &n.w, n.P);
     if (rc == HMM_OK) rc = dalloc(s, &n.g, n.P);
     if (rc == HMM_OK) rc = dalloc(s, &n.m, n.P);
@@ -470,18 +653,13 @@ int mcmc_create(hmm_ctx *ctx, int32_t K, int32_t n_chains, int64_t T, const uint
         return rc;
     }
     bool ok = hipMemset(s->accepts, 0, sizeof(long long) * s->C) == hipSuccess;
+    ok = ok && hipMemset(s->iter_dev, 0, sizeof(uint32_t)) == hipSuccess;
     ok = ok && hipMemset(s->theta, 0, sizeof(double) * CD) == hipSuccess;
     ok = ok && hipMemset(s->hist_lpost, 0, sizeof(double) * s->H * s->C) == hipSuccess;
     ok = ok && hipMemset(n.w, 0, sizeof(float) * n.P) == hipSuccess;
     ok = ok && hipMemset(n.m, 0, sizeof(float) * n.P) == hipSuccess;
     ok = ok && hipMemset(n.v, 0, sizeof(float) * n.P) == hipSuccess;
-    // Glorot-uniform hidden layers; biases and the output layer start at zero,
-    // so the untrained learned move is N(theta, out_scale^2).
-    const float l1 = std::sqrt(6.f / (n.D + n.H)), l2 = std::sqrt(6.f / (2 * n.H));
-    hipLaunchKernelGGL(k_init_weights, dim3(512), dim3(256), 0, nullptr, (int64_t)n.D * n.H, n.at(n.w, 0),
-                       n.offset(0), l1, seed);
-    hipLaunchKernelGGL(k_init_weights, dim3(256), dim3(256), 0, nullptr, (int64_t)n.H * n.H, n.at(n.w, 2),
-                       n.offset(2), l2, seed);
+    init_hidden_layers(n, seed, nullptr);
     ok = ok && hipGetLastError() == hipSuccess && hipDeviceSynchronize() == hipSuccess;
     if (!ok) {
         release(s);
@@ -515,8 +693,12 @@ int mcmc_set_state(mcmc_chains *s, const double *theta, const double *rw_scale, 
         hipMemcpyAsync(s->rw, rw_scale, sizeof(double) * s->D, hipMemcpyDeviceToDevice, st) != hipSuccess)
         return HMM_E_DEVICE;
     hipLaunchKernelGGL(k_theta_to_params, dim3(s->C), dim3(256), 0, st, s->K, s->theta, s->params, s->lp, s->box);
-    const int rc = loglik_all(s, st, s->ll);
-    return rc != HMM_OK ? rc : launch_status();
+    const int rc = loglik_all(s, st);
+    if (rc != HMM_OK) return rc;
+    if (hipMemcpyAsync(s->ll, s->ll_p, sizeof(double) * s->C, hipMemcpyDeviceToDevice, st) != hipSuccess)
+        return HMM_E_DEVICE;
+    s->ready = true;
+    return launch_status();
 }
 
 int mcmc_set_rw_scale(mcmc_chains *s, const double *rw_scale, void *stream)
@@ -535,23 +717,33 @@ int mcmc_step(mcmc_chains *s, int32_t n_iter, int32_t proposal, double eps, void
     if (!s || n_iter < 0 || (proposal != MCMC_RANDOM_WALK && proposal != MCMC_LEARNED)) return HMM_E_INVALID_ARG;
     const bool learned = proposal == MCMC_LEARNED;
     if (learned && (!s->trained || !(eps > 0.0 && eps < 1.0))) return HMM_E_INVALID_ARG;
+    if (!s->ready) return HMM_E_INVALID_ARG;                                // mcmc_set_state first
     if (s->iter + n_iter > (int64_t)UINT32_MAX) return HMM_E_INVALID_ARG;  // Philox iteration word
     DeviceGuard dg(s->ctx->device);
     if (!dg.ok) return HMM_E_DEVICE;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    for (int it = 0; it < n_iter; ++it) {
-        const uint32_t iter = (uint32_t)s->iter;
-        if (learned) forward_states(s, st, s->theta, s->fwd);
-        hipLaunchKernelGGL(k_propose, dim3(s->C), dim3(256), 0, st, s->K, s->seed, iter, learned ? 1 : 0, eps, s->theta,
-                           s->rw, s->fwd.O, s->out_scale, s->theta_p, s->params, s->lp_p, s->lq, s->box);
-        const int rc = loglik_all(s, st, s->ll_p);
-        if (rc != HMM_OK) return rc;
-        if (learned) forward_states(s, st, s->theta_p, s->rev);
-        hipLaunchKernelGGL(k_accept, dim3(s->C), dim3(256), 0, st, s->K, s->seed, iter, learned ? 1 : 0, eps, s->theta,
-                           s->theta_p, s->ll, s->lp, s->ll_p, s->lp_p, s->lq, s->rev.O, s->out_scale, s->rw,
-                           s->accepts, s->hist, s->hist_lpost, (int64_t)(s->iter % s->H), s->C);
-        ++s->iter;
+    const int mode = learned ? 1 : 0;
+    if (learned && s->exec[1] && eps != s->exec_eps) {
+        (void)hipGraphExecDestroy(s->exec[1]);
+        s->exec[1] = nullptr;
     }
+    if (!s->exec[mode]) {
+        // the capture stream must not start before work already queued on st
+        hipEvent_t ev;
+        if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return HMM_E_DEVICE;
+        const bool ok = hipEventRecord(ev, st) == hipSuccess && hipEventSynchronize(ev) == hipSuccess;
+        (void)hipEventDestroy(ev);
+        if (!ok) return HMM_E_DEVICE;
+        const int rc = build_graph(s, mode, eps);
+        if (rc != HMM_OK) return rc;
+        if (learned) s->exec_eps = eps;
+    }
+    for (int it = 0; it < n_iter; ++it)
+        if (hipGraphLaunch(s->exec[mode], st) != hipSuccess) {
+            (void)hipGetLastError();
+            return HMM_E_DEVICE;
+        }
+    s->iter += n_iter;
     return launch_status();
 }
 
@@ -584,14 +776,22 @@ int mcmc_view_get(mcmc_chains *s, mcmc_view *v)
     return HMM_OK;
 }
 
-int mcmc_train_proposal(mcmc_chains *s, int32_t steps, int32_t batch, int32_t lag, double lr, int64_t window,
-                        void *stream, float *loss_out)
+int mcmc_train_proposal(mcmc_chains *s, const mcmc_train_opts *o, void *stream, float *loss_out,
+                        float *val_out, int32_t *best_step)
 {
-    if (!s || steps < 0 || batch < 1 || batch > 65535 || lag < 1 || !(lr > 0.0) || window < 0)
+    if (!s || !o) return HMM_E_INVALID_ARG;
+    const int steps = o->steps, batch = o->batch, lag = o->lag, vb = o->val_batch, ve = o->val_every;
+    const bool validate = o->holdout > 0.0;
+    if (steps < 0 || batch < 1 || batch > 65535 || lag < 1 || !(o->lr > 0.0) || !(o->weight_decay >= 0.0) ||
+        o->window < 0 || o->window_end < 0 || o->window_end > s->iter || !(o->holdout >= 0.0 && o->holdout < 1.0))
         return HMM_E_INVALID_ARG;
-    const int64_t w = std::min<int64_t>(window > 0 ? window : s->H, std::min<int64_t>(s->H, s->iter));
-    const int64_t t1 = s->iter, t0 = t1 - w;
-    if (w <= lag) return HMM_E_INVALID_ARG;  // no lagged pair in the window
+    if (validate && (vb < 1 || vb > 65535 || ve < 1)) return HMM_E_INVALID_ARG;
+    const int64_t t1 = o->window_end > 0 ? o->window_end : s->iter;
+    const int64_t oldest = std::max<int64_t>(0, s->iter - s->H);  // first iteration still in the ring
+    const int64_t t0 = std::max(oldest, t1 - (o->window > 0 ? o->window : s->H));
+    // training pairs start in [t0, tv - lag), held-out pairs in [tv, t1 - lag)
+    const int64_t tv = validate ? t0 + (int64_t)std::floor((1.0 - o->holdout) * (double)(t1 - t0)) : t1;
+    if (tv - t0 <= lag || (validate && t1 - tv <= lag)) return HMM_E_INVALID_ARG;  // no pair to use
     if (s->trained && lag != s->lag) return HMM_E_INVALID_ARG;
     DeviceGuard dg(s->ctx->device);
     if (!dg.ok) return HMM_E_DEVICE;
@@ -600,25 +800,91 @@ int mcmc_train_proposal(mcmc_chains *s, int32_t steps, int32_t batch, int32_t la
         const int rc = acts_alloc(s, s->train, batch, true);
         if (rc != HMM_OK) return rc;
     }
+    Net &n = s->net;
+    if (validate) {
+        if (s->val.cap < vb) {
+            const int rc = acts_alloc(s, s->val, vb, true);
+            if (rc != HMM_OK) return rc;
+        }
+        if (!s->best_w) {
+            int rc = dalloc(s, &s->best_w, n.P);
+            if (rc == HMM_OK) rc = dalloc(s, &s->best, 2);
+            if (rc == HMM_OK) rc = dalloc(s, &s->take, 1);
+            if (rc != HMM_OK) return rc;
+        }
+    }
     if (!s->trained) {
-        // the standardisation is fixed at the first training call
-        hipLaunchKernelGGL(k_hist_stats, dim3((s->D + 255) / 256), dim3(256), 0, st, s->D, s->C, s->H, t0, t1, lag,
-                           s->hist, s->rw, 0.1, s->center, s->in_scale, s->out_scale);
+        // the standardisation and the linear start are fixed at the first
+        // training call after creation or a reset, from the training pairs
+        hipLaunchKernelGGL(k_hist_stats, dim3((s->D + 255) / 256), dim3(256), 0, st, s->D, s->C, s->H, t0, tv, lag,
+                           s->hist, s->rw, 0.1, s->center, s->in_scale, s->out_scale, n.at(n.w, 5), n.at(n.w, 6));
         s->lag = lag;
     }
-    Net &n = s->net;
+    // the held-out batch (fixed for this call) and its loss at the start
+    auto evaluate = [&](int step, int k_eval) {
+        net_forward(st, n, vb, s->val.X, s->val.H1, s->val.H2, s->val.O);
+        hipLaunchKernelGGL(k_nll_grad, dim3(vb), dim3(256), 0, st, vb, s->D, s->val.R, s->val.O, s->val.dO,
+                           s->val.loss);
+        hipLaunchKernelGGL(k_val_decide, dim3(1), dim3(64), 0, st, vb, s->val.loss, s->best, step, s->take,
+                           val_out ? val_out + k_eval : nullptr);
+        hipLaunchKernelGGL(k_copy_if, dim3(512), dim3(256), 0, st, n.P, n.w, s->best_w, s->take);
+    };
+    int n_eval = 0;
+    if (validate) {
+        hipLaunchKernelGGL(k_pairs, dim3(vb), dim3(256), 0, st, s->D, s->C, s->H, tv, t1, lag, s->seed,
+                           kDrawValidation, (uint32_t)n.steps, s->hist, s->center, s->in_scale, s->out_scale,
+                           s->val.X, s->val.R);
+        evaluate(-1, n_eval++);
+    }
     for (int k = 0; k < steps; ++k) {
-        hipLaunchKernelGGL(k_pairs, dim3(batch), dim3(256), 0, st, s->D, s->C, s->H, t0, t1, lag, s->seed,
-                           (uint32_t)(n.steps + k), s->hist, s->center, s->in_scale, s->out_scale, s->train.X,
-                           s->train.R);
+        hipLaunchKernelGGL(k_pairs, dim3(batch), dim3(256), 0, st, s->D, s->C, s->H, t0, tv, lag, s->seed,
+                           kDrawMinibatch, (uint32_t)(n.steps + k), s->hist, s->center, s->in_scale, s->out_scale,
+                           s->train.X, s->train.R);
         net_forward(st, n, batch, s->train.X, s->train.H1, s->train.H2, s->train.O);
         net_backward(st, n, batch, s->train);
-        hipLaunchKernelGGL(k_adam, dim3(512), dim3(256), 0, st, n.P, n.w, n.g, n.m, n.v, (float)lr, 0.9f, 0.999f, 1e-8f,
-                           n.steps + k + 1);
+        // weight decay on the three weight matrices only
+        for (int part = 0; part < 7; ++part) {
+            const int64_t off = n.offset(part), len = n.offset(part + 1) - off;
+            const float wd = (part == 0 || part == 2 || part == 4) ? (float)o->weight_decay : 0.f;
+            hipLaunchKernelGGL(k_adam, dim3((unsigned)std::min<int64_t>((len + 255) / 256, 512)), dim3(256), 0, st,
+                               len, n.w + off, n.g + off, n.m + off, n.v + off, (float)o->lr, 0.9f, 0.999f, 1e-8f,
+                               n.steps + k + 1, wd);
+        }
         if (loss_out) hipLaunchKernelGGL(k_colsum, dim3(1), dim3(64), 0, st, batch, 1, s->train.loss, loss_out + k);
+        if (validate && ((k + 1) % ve == 0 || k + 1 == steps)) evaluate(k, n_eval++);
+    }
+    if (validate) {
+        // keep the weights with the lowest held-out loss
+        if (hipMemcpyAsync(n.w, s->best_w, sizeof(float) * n.P, hipMemcpyDeviceToDevice, st) != hipSuccess)
+            return HMM_E_DEVICE;
+        if (best_step) {
+            float b[2];
+            if (hipMemcpyAsync(b, s->best, sizeof(b), hipMemcpyDeviceToHost, st) != hipSuccess ||
+                hipStreamSynchronize(st) != hipSuccess)
+                return HMM_E_DEVICE;
+            *best_step = (int32_t)b[1];
+        }
     }
     n.steps += steps;
     s->trained = true;
+    return launch_status();
+}
+
+int mcmc_reset_proposal(mcmc_chains *s, uint64_t seed, void *stream)
+{
+    if (!s) return HMM_E_INVALID_ARG;
+    DeviceGuard dg(s->ctx->device);
+    if (!dg.ok) return HMM_E_DEVICE;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    Net &n = s->net;
+    const size_t bytes = sizeof(float) * n.P;
+    if (hipMemsetAsync(n.w, 0, bytes, st) != hipSuccess || hipMemsetAsync(n.m, 0, bytes, st) != hipSuccess ||
+        hipMemsetAsync(n.v, 0, bytes, st) != hipSuccess)
+        return HMM_E_DEVICE;
+    init_hidden_layers(n, seed, st);
+    n.steps = 0;
+    s->lag = 0;
+    s->trained = false;
     return launch_status();
 }
 

@@ -240,7 +240,7 @@ def _net_inputs(rng, ch, D):
     return w.astype(np.float32)
 
 
-@pytest.mark.parametrize("K,B", [(3, 37), (20, 256)])
+@pytest.mark.parametrize("K,B", [(3, 37), (20, 256), (3, 5), (20, 16)])
 def test_network_forward_and_gradient(binding, ctx, K, B):
     prm, obs, box = _problem(K, 200, 43)
     d = binding.to_device(prm, obs)
@@ -289,14 +289,18 @@ def _history_np(ch):
     return hist.cpu().numpy(), iters
 
 
-def test_standardisation_from_history(binding, ctx):
-    """First training call: center / in_scale / out_scale from the window."""
+@pytest.mark.parametrize("back", [0, 10])
+def test_standardisation_from_history(binding, ctx, back):
+    """First training call: center / in_scale / out_scale from the window
+    (the 30 iterations before the current one, or before iteration
+    current - back)."""
     K, C, H, lag = 3, 4, 64, 3
-    ch, prm, obs, box, rw, _ = _fill_history(binding, ctx, K, 1500, C, 9, 40, H)
+    ch, prm, obs, box, rw, _ = _fill_history(binding, ctx, K, 1500, C, 9, 50, H)
     hist, iters = _history_np(ch)
-    ch.train(1, batch=8, lag=lag, lr=1e-3, window=30)
+    ch.train(1, batch=8, lag=lag, lr=1e-3, window=30, window_end=iters - back if back else 0)
     net = ch.network()
-    t1, t0 = iters, iters - 30
+    t1 = iters - back
+    t0 = t1 - 30
     win = np.stack([hist[t % H] for t in range(t0, t1)]).astype(np.float64)     # (n, C, D)
     moves = np.stack([hist[(t + lag) % H] - hist[t % H] for t in range(t0, t1 - lag)]).astype(np.float64)
     fl = 0.1 * rw
@@ -307,8 +311,38 @@ def test_standardisation_from_history(binding, ctx):
     assert np.allclose(net["in_scale"].cpu().numpy(), ins, rtol=1e-9)
     assert np.allclose(net["out_scale"].cpu().numpy(), outs, rtol=1e-9)
     assert net["lag"] == lag and net["trained"]
+    # the least-squares start of the linear part (one Adam step moves each
+    # weight by at most ~lr = 1e-3)
+    D = ch.D
+    X = ((np.stack([hist[t % H] for t in range(t0, t1 - lag)]).astype(np.float64) - center) / ins).reshape(-1, D)
+    Rm = (moves / outs).reshape(-1, D)
+    w = net["weights"].cpu().numpy().astype(np.float64)
+    P = omlp.count(D, 256)
+    a_got, b_got, ls_got = w[P - D:], w[P - 3 * D:P - 2 * D], w[P - 2 * D:P - D]
+    for j in range(D):
+        A = np.column_stack([X[:, j], np.ones(X.shape[0])])
+        (a, b), res, *_ = np.linalg.lstsq(A, Rm[:, j], rcond=None)
+        s2 = np.sum((Rm[:, j] - a * X[:, j] - b) ** 2) / (X.shape[0] - 2)
+        assert abs(a_got[j] - a) <= 2e-3 + 1e-4 * abs(a), (j, a_got[j], a)
+        assert abs(b_got[j] - b) <= 2e-3 + 1e-4 * abs(b), (j, b_got[j], b)
+        assert abs(ls_got[j] - 0.5 * math.log(s2)) <= 2e-3, (j, ls_got[j], 0.5 * math.log(s2))
     with pytest.raises(binding.HMMError):       # the lag is fixed by the first call
         ch.train(1, batch=8, lag=lag + 1)
+    with pytest.raises(binding.HMMError):       # the window must end at or before now
+        ch.train(1, batch=8, lag=lag, window_end=iters + 1)
+    # a reset forgets the network and the standardisation
+    ch.reset_proposal(seed=4)
+    net = ch.network()
+    assert not net["trained"]
+    w = net["weights"].cpu().numpy()
+    D = ch.D
+    tail = w[omlp.count(D, 256) - (256 * 2 * D + 2 * D + D):]
+    assert np.all(tail == 0)                        # W3, b3 and the skip are zero
+    assert np.any(w[:D * 256] != 0)                 # W1 re-initialised
+    ch.train(2, batch=8, lag=lag + 1, lr=1e-3)      # a new lag is allowed
+    assert ch.network()["lag"] == lag + 1
+    with pytest.raises(binding.HMMError):
+        ch.step(1, proposal=binding.MCMC_LEARNED, eps=1.0)   # eps must lie in (0, 1)
     ch.close()
 
 
@@ -325,7 +359,7 @@ def test_training_step_matches_oracle(binding, ctx):
     outs = np.exp(rng.normal(0, 0.3, D)) * rw
     ch.set_network(dev(w0, torch.float32), dev(center), dev(ins), dev(outs), lag=lag)
     hist, iters = _history_np(ch)
-    losses = ch.train(1, batch=B, lag=lag, lr=lr, window=0).cpu().numpy()
+    losses = ch.train(1, batch=B, lag=lag, lr=lr, window=0)["loss"].cpu().numpy()
     w1 = ch.network()["weights"].cpu().numpy().astype(np.float64)
     # the oracle's minibatch: time and chain from Philox purpose 4, step 0
     t1, t0 = iters, iters - min(H, iters)
@@ -354,6 +388,43 @@ def test_training_step_matches_oracle(binding, ctx):
         assert big.mean() > 0.5, shp
         assert np.allclose(w1[off:off + n][big], want[off:off + n][big], rtol=0, atol=1e-3 * lr + 1e-7), shp
         off += n
+    ch.close()
+
+
+def test_held_out_selection(binding, ctx):
+    """With a held-out part of the window the call keeps the weights of the
+    lowest held-out loss; the held-out pairs and losses match the oracle."""
+    K, C, H, lag, vb, ve, steps, seed = 3, 4, 128, 2, 64, 5, 20, 14
+    ch, prm, obs, box, rw, _ = _fill_history(binding, ctx, K, 1500, C, seed, 100, H)
+    D = ch.D
+    hist, iters = _history_np(ch)
+    r = ch.train(steps, batch=32, lag=lag, lr=3e-3, window=80, holdout=0.25, val_every=ve, val_batch=vb)
+    val = r["val"].cpu().numpy()
+    assert val.shape[0] == 1 + -(-steps // ve)
+    best_i = int(np.argmin(val))
+    assert r["best_step"] == (-1 if best_i == 0 else min(best_i * ve, steps) - 1)
+    net = ch.network()
+    center = net["center"].cpu().numpy()
+    ins = net["in_scale"].cpu().numpy()
+    outs = net["out_scale"].cpu().numpy()
+    # the held-out pairs: starts in [tv, t1 - lag), Philox purpose 6, step word 0
+    t1 = iters
+    t0 = t1 - 80
+    tv = t0 + int(math.floor(0.75 * (t1 - t0)))
+    span = t1 - lag - tv
+    X = np.empty((vb, D))
+    R = np.empty((vb, D))
+    for b in range(vb):
+        u0, u1 = philox.uniform2(seed, 6, 0, 0, b)
+        t = tv + min(span - 1, int(u0 * span))
+        c = min(C - 1, int(u1 * C))
+        x = hist[t % H, c].astype(np.float64)
+        y = hist[(t + lag) % H, c].astype(np.float64)
+        X[b] = ((x - center) / ins).astype(np.float32)
+        R[b] = ((y - x) / outs).astype(np.float32)
+    w = net["weights"].cpu().numpy().astype(np.float64)
+    kept = omlp.loss(w, X, R, D, 256)               # mean row loss, as the kernel sums rows / B
+    assert abs(kept - val.min()) <= 1e-4 * abs(val.min()) + 1e-3, (kept, val.min())
     ch.close()
 
 

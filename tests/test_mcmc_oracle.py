@@ -278,7 +278,7 @@ def test_mlp_loss_is_gaussian_nll():
 
 def test_mlp_layout_and_forward_by_hand():
     D, H = 2, 3
-    assert omlp.count(D, H) == D * H + H + H * H + H + H * 2 * D + 2 * D
+    assert omlp.count(D, H) == D * H + H + H * H + H + H * 2 * D + 2 * D + D
     rng = np.random.default_rng(2)
     w = rng.normal(size=omlp.count(D, H))
     x = rng.normal(size=D)
@@ -289,10 +289,13 @@ def test_mlp_layout_and_forward_by_hand():
     b2 = w[o + H * H:o + H * H + H]
     o += H * H + H
     W3 = w[o:o + H * 2 * D].reshape(H, 2 * D)
-    b3 = w[o + H * 2 * D:]
+    b3 = w[o + H * 2 * D:o + H * 2 * D + 2 * D]
+    a = w[o + H * 2 * D + 2 * D:]
+    assert a.shape == (D,)
     h1 = [math.tanh(sum(x[i] * W1[i, j] for i in range(D)) + b1[j]) for j in range(H)]
     h2 = [math.tanh(sum(h1[i] * W2[i, j] for i in range(H)) + b2[j]) for j in range(H)]
-    out = [sum(h2[i] * W3[i, j] for i in range(H)) + b3[j] for j in range(2 * D)]
+    out = [sum(h2[i] * W3[i, j] for i in range(H)) + b3[j] + (a[j] * x[j] if j < D else 0.0)
+           for j in range(2 * D)]
     got, _ = omlp.forward(w, x[None, :], D, H)
     assert np.allclose(got[0], out, rtol=1e-14, atol=1e-14)
 
