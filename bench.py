@@ -76,8 +76,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--workload", default="k25_t1e6", choices=["k25_t1e6", "k80_t4m", "batch256", "mcmc_k20"])
     ap.add_argument("--no-mcmc", action="store_true", help="skip the MCMC leg of the default run")
-    ap.add_argument("--mcmc-iterations", type=int, default=8000)
-    ap.add_argument("--mcmc-chains", type=int, default=4)
+    ap.add_argument("--mcmc-iterations", type=int, default=10000)
+    ap.add_argument("--mcmc-chains", type=int, default=8)
     ap.add_argument("--mcmc-lag", type=int, default=5)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
@@ -338,7 +338,7 @@ def bench_batch(args):
     }))
 
 
-def run_mcmc(C=4, burn_rounds=12, adapt_rounds=6, round_len=1000, n_iter=8000, lag=5, train_steps=500,
+def run_mcmc(C=8, burn_rounds=12, adapt_rounds=6, round_len=1000, n_iter=10000, lag=5, train_steps=500,
              lr=1e-4, eps=0.1, seed=1, log=None):
     """MCMC leg: posterior over all D = 480 parameters of the K=20 model given
     the T=500,000 path simulated with seed 4; random-walk MH vs the learned
