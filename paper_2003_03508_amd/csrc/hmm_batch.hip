@@ -70,8 +70,13 @@ void batch_plan_free(BatchPlan *bp)
 
 namespace {
 
-// Segment length of a class: long segments keep the combination tree small;
-// at least ~4 workgroups per CU keep the GPU busy.  A tuned value wins.
+// Segment length of a class.  Workgroups run one per CU, in rounds of 256;
+// a round costs about L steps plus a fixed per-workgroup part (emission
+// setup, the in-workgroup tree) worth kWgOverhead steps.  The length
+// minimises rounds(L) * (L + kWgOverhead) over 128..4096, so that the last
+// round is not left mostly empty.  A tuned value wins.
+constexpr int kWgOverhead = 32;
+
 int64_t class_L(const hmm_ctx *ctx, const BatchPlan &bp, const BatchClass &c, int algo, int W)
 {
     for (int s : c.sets) {
@@ -79,11 +84,22 @@ int64_t class_L(const hmm_ctx *ctx, const BatchPlan &bp, const BatchClass &c, in
         if (it != ctx->tuned_L.end() && it->second > 0) return it->second;
     }
     if (ctx->block_len > 0) return ctx->block_len;
-    int64_t tot = 0;
-    for (int s : c.sets) tot += bp.T[s];
-    int64_t L = tot / (256LL * 4 * W);
-    L = (L / kChunk) * kChunk;
-    return std::max<int64_t>(128, std::min<int64_t>(2048, L));
+    int64_t best = 128;
+    double best_cost = -1.0;
+    for (int64_t L = 128; L <= 4096; ++L) {
+        int64_t wgs = 0;
+        for (int s : c.sets) {
+            const int64_t nseg = (bp.T[s] + L - 1) / L;
+            wgs += (nseg + W - 1) / W;
+        }
+        const int64_t rounds = std::max<int64_t>(1, (wgs + 255) / 256);
+        const double cost = (double)rounds * (double)(L + kWgOverhead);
+        if (best_cost < 0.0 || cost < best_cost) {
+            best_cost = cost;
+            best = L;
+        }
+    }
+    return best;
 }
 
 const void *serial_kernel(int KP)
