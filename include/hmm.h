@@ -208,6 +208,11 @@ int hmm_ctx_profile_read(hmm_ctx *ctx, int64_t *launches, double *total_ms);
  * ------------------------------------------------------------------------ */
 typedef enum { MCMC_RANDOM_WALK = 0, MCMC_LEARNED = 1 } mcmc_proposal;
 
+/* A sampler owns device memory, a private context whose batched plan its
+ * iteration graphs replay, and one captured graph per proposal kind.  Like a
+ * context it is not thread-safe: calls on one sampler must be serialised
+ * (one host thread, one stream). */
+
 typedef struct mcmc_chains mcmc_chains;
 
 /* Device buffers and sizes of a sampler (filled by mcmc_view_get; the
