@@ -351,6 +351,23 @@ int hmm_theta_to_params(hmm_ctx *ctx, int32_t K, int32_t n, const double *theta,
 int hmm_philox(hmm_ctx *ctx, uint64_t seed, uint32_t purpose, uint32_t iter, uint32_t chain,
                int64_t n, int32_t normal, double *out, void *stream);
 
+/* Checkpoints of a sampler, for resuming a run: a host byte image of the
+ * chain states (theta, ln L, log prior), the random-walk scale, acceptance
+ * counts, the Philox seed and iteration counter, the history ring, the prior
+ * box, the network with its standardisation, lag and Adam state.  A sampler
+ * created for the same K, chain count, history length and observations that
+ * loads the image continues bit for bit as the saved one would have (the
+ * observations themselves are not part of the image).
+ *   mcmc_checkpoint_size   *bytes = the image size
+ *   mcmc_checkpoint_save   writes the image into host[bytes] (synchronises
+ *                          the stream); the state must have been set
+ *   mcmc_checkpoint_load   restores from host[bytes]; HMM_E_INVALID_ARG if the
+ *                          image is not a checkpoint of a sampler of this
+ *                          shape (synchronises the stream) */
+int mcmc_checkpoint_size(mcmc_chains *chains, int64_t *bytes);
+int mcmc_checkpoint_save(mcmc_chains *chains, void *host, int64_t bytes, void *stream);
+int mcmc_checkpoint_load(mcmc_chains *chains, const void *host, int64_t bytes, void *stream);
+
 /* Human-readable name of a status code (static storage). */
 const char *hmm_status_string(int status);
 

@@ -67,6 +67,9 @@ _lib.mcmc_reset_proposal.argtypes = [_vp, ctypes.c_uint64, _vp]
 _lib.mlp_forward.argtypes = [_vp, _i32, _vp, _vp, _vp]
 _lib.mlp_loss_grad.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp, _vp]
 _lib.mlp_set_weights.argtypes = [_vp, _vp, _vp, _vp, _vp, _i32, _vp]
+_lib.mcmc_checkpoint_size.argtypes = [_vp, ctypes.POINTER(_i64)]
+_lib.mcmc_checkpoint_save.argtypes = [_vp, _vp, _i64, _vp]
+_lib.mcmc_checkpoint_load.argtypes = [_vp, _vp, _i64, _vp]
 
 
 class McmcView(ctypes.Structure):
@@ -90,7 +93,8 @@ for _f in ("hmm_ctx_create", "hmm_ctx_destroy", "hmm_loglik", "hmm_emission",
            "hmm_theta_to_params", "hmm_philox", "mcmc_create", "mcmc_destroy", "mcmc_set_state",
            "mcmc_set_rw_scale", "mcmc_step", "mcmc_train_proposal", "mcmc_reset_proposal", "mcmc_view_get",
            "mlp_forward",
-           "mlp_loss_grad", "mlp_set_weights"):
+           "mlp_loss_grad", "mlp_set_weights", "mcmc_checkpoint_size", "mcmc_checkpoint_save",
+           "mcmc_checkpoint_load"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 
@@ -412,6 +416,19 @@ class Chains:
                                                    _dev(rows, torch.float32, "row_loss"),
                                                    _dev(grad, torch.float32, "grad"), _stream(stream)))
         return rows, grad
+
+    def checkpoint(self, stream=None):
+        """The sampler's checkpoint image (bytes)."""
+        n = _i64()
+        _check("mcmc_checkpoint_size", _lib.mcmc_checkpoint_size(self._h, ctypes.byref(n)))
+        buf = ctypes.create_string_buffer(n.value)
+        _check("mcmc_checkpoint_save", _lib.mcmc_checkpoint_save(self._h, buf, n.value, _stream(stream)))
+        return buf.raw
+
+    def restore(self, image, stream=None):
+        """Continue from a checkpoint image made by `checkpoint`."""
+        buf = ctypes.create_string_buffer(bytes(image), len(image))
+        _check("mcmc_checkpoint_load", _lib.mcmc_checkpoint_load(self._h, buf, len(image), _stream(stream)))
 
     def set_network(self, weights, center, in_scale, out_scale, lag, stream=None):
         v = self.view()

@@ -747,6 +747,106 @@ int mcmc_step(mcmc_chains *s, int32_t n_iter, int32_t proposal, double eps, void
     return launch_status();
 }
 
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Checkpoints: a host byte image of everything the chains' future depends on.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr uint64_t kCkptMagic = 0x544B43434D4D48ull;  // "HMMCCKT"
+constexpr int64_t kCkptVersion = 1;
+
+struct CkptHeader {
+    uint64_t magic;
+    int64_t version, K, C, D, H, T, P;
+    uint64_t seed;
+    int64_t iter, lag, trained, adam_steps;
+    double box[4];
+};
+
+// (device pointer, bytes) of every array a checkpoint holds, in image order.
+std::vector<std::pair<void *, size_t>> ckpt_arrays(mcmc_chains *s)
+{
+    const size_t CD = (size_t)s->C * s->D, n = (size_t)s->net.P;
+    return {{s->theta, 8 * CD},           {s->ll, 8 * (size_t)s->C},
+            {s->lp, 8 * (size_t)s->C},    {s->rw, 8 * (size_t)s->D},
+            {s->accepts, 8 * (size_t)s->C}, {s->hist, 4 * (size_t)s->H * CD},
+            {s->hist_lpost, 8 * (size_t)s->H * s->C},
+            {s->center, 8 * (size_t)s->D}, {s->in_scale, 8 * (size_t)s->D},
+            {s->out_scale, 8 * (size_t)s->D}, {s->net.w, 4 * n},
+            {s->net.m, 4 * n},            {s->net.v, 4 * n}};
+}
+
+}  // namespace
+
+extern "C" {
+
+int mcmc_checkpoint_size(mcmc_chains *s, int64_t *bytes)
+{
+    if (!s || !bytes) return HMM_E_INVALID_ARG;
+    size_t b = sizeof(CkptHeader);
+    for (auto &a : ckpt_arrays(s)) b += a.second;
+    *bytes = (int64_t)b;
+    return HMM_OK;
+}
+
+int mcmc_checkpoint_save(mcmc_chains *s, void *host, int64_t bytes, void *stream)
+{
+    int64_t need = 0;
+    if (!s || !host || mcmc_checkpoint_size(s, &need) != HMM_OK || bytes < need) return HMM_E_INVALID_ARG;
+    if (!s->ready) return HMM_E_INVALID_ARG;
+    DeviceGuard dg(s->ctx->device);
+    if (!dg.ok) return HMM_E_DEVICE;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    CkptHeader h{kCkptMagic, kCkptVersion, s->K, s->C, s->D, s->H, s->T, s->net.P, s->seed, s->iter, s->lag,
+                 s->trained ? 1 : 0, s->net.steps, {s->box.x0, s->box.x1, s->box.y0, s->box.y1}};
+    char *p = static_cast<char *>(host);
+    std::memcpy(p, &h, sizeof(h));
+    p += sizeof(h);
+    for (auto &a : ckpt_arrays(s)) {
+        if (hipMemcpyAsync(p, a.first, a.second, hipMemcpyDeviceToHost, st) != hipSuccess) return HMM_E_DEVICE;
+        p += a.second;
+    }
+    return hipStreamSynchronize(st) == hipSuccess ? HMM_OK : HMM_E_DEVICE;
+}
+
+int mcmc_checkpoint_load(mcmc_chains *s, const void *host, int64_t bytes, void *stream)
+{
+    int64_t need = 0;
+    if (!s || !host || mcmc_checkpoint_size(s, &need) != HMM_OK || bytes < need) return HMM_E_INVALID_ARG;
+    CkptHeader h;
+    std::memcpy(&h, host, sizeof(h));
+    if (h.magic != kCkptMagic || h.version != kCkptVersion || h.K != s->K || h.C != s->C || h.D != s->D ||
+        h.H != s->H || h.T != s->T || h.P != s->net.P || h.iter < 0 || h.iter > (int64_t)UINT32_MAX)
+        return HMM_E_INVALID_ARG;
+    DeviceGuard dg(s->ctx->device);
+    if (!dg.ok) return HMM_E_DEVICE;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const char *p = static_cast<const char *>(host) + sizeof(h);
+    for (auto &a : ckpt_arrays(s)) {
+        if (hipMemcpyAsync(a.first, p, a.second, hipMemcpyHostToDevice, st) != hipSuccess) return HMM_E_DEVICE;
+        p += a.second;
+    }
+    const uint32_t it32 = (uint32_t)h.iter;
+    if (hipMemcpyAsync(s->iter_dev, &it32, sizeof(it32), hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return HMM_E_DEVICE;
+    drop_graphs(s);  // they carry the seed and the prior box as arguments
+    s->seed = h.seed;
+    s->box = PriorBox{h.box[0], h.box[1], h.box[2], h.box[3]};
+    s->iter = h.iter;
+    s->lag = (int)h.lag;
+    s->trained = h.trained != 0;
+    s->net.steps = (int)h.adam_steps;
+    // build the likelihood plan the iteration graphs replay (scratch outputs only)
+    hipLaunchKernelGGL(k_theta_to_params, dim3(s->C), dim3(256), 0, st, s->K, s->theta, s->params, s->lp_p, s->box);
+    const int rc = loglik_all(s, st);
+    if (rc != HMM_OK) return rc;
+    s->ready = true;
+    return launch_status();
+}
+
 int mcmc_view_get(mcmc_chains *s, mcmc_view *v)
 {
     if (!s || !v) return HMM_E_INVALID_ARG;

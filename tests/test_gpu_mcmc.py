@@ -502,6 +502,44 @@ def test_k1_posterior_means(binding, ctx, learned):
         assert abs(est.mean() - want) < 4 * E.mcse_mean(est), (est.mean(), want, E.mcse_mean(est))
 
 
+def test_checkpoint_resume_is_bit_identical(binding, ctx):
+    """A sampler restored from a checkpoint continues exactly as the saved
+    one: MH steps of both proposals and further training."""
+    K, T, C, H = 3, 2000, 4, 64
+    ch, prm, obs, box, rw, d = _fill_history(binding, ctx, K, T, C, 21, 30, H)
+    ch.train(40, batch=64, lag=2, lr=1e-3)
+    ch.step(5, proposal=binding.MCMC_LEARNED, eps=0.2)
+    image = ch.checkpoint()
+
+    def carry_on(c):
+        c.step(7, proposal=binding.MCMC_LEARNED, eps=0.2)
+        c.train(10, batch=64, lag=2, lr=1e-3)
+        c.step(6, proposal=binding.MCMC_RANDOM_WALK)
+        st = c.state()
+        hist, hlp, it = c.history()
+        net = c.network()
+        return [st["theta"], st["loglik"], st["logprior"], st["accepts"], hist, hlp, net["weights"],
+                net["center"], net["in_scale"], net["out_scale"]], (it, st["iterations"], net["lag"])
+
+    a, a_meta = carry_on(ch)
+    other = binding.Chains(ctx, K, C, d["flag"], d["xy"], (0.0, 1.0, 0.0, 1.0), seed=999, history=H)
+    other.restore(image)
+    b, b_meta = carry_on(other)
+    assert a_meta == b_meta
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+    # images of another shape or damaged ones are refused
+    wrong = binding.Chains(ctx, K, C + 1, d["flag"], d["xy"], box, history=H)
+    with pytest.raises(binding.HMMError):
+        wrong.restore(image)
+    with pytest.raises(binding.HMMError):
+        other.restore(b"\0" * len(image))
+    with pytest.raises(binding.HMMError):
+        other.restore(image[:-1])
+    for c in (ch, other, wrong):
+        c.close()
+
+
 def test_trained_proposal_beats_random_walk():
     """What the trained network gains: on a K=3 posterior (D=21), after the
     same adapted random-walk burn-in, the learned mixture proposal (lag 10,
