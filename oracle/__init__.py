@@ -12,6 +12,8 @@ Contents
   * ``logspace.py`` -- a second, independent forward algorithm in the log
     domain (NumPy, logsumexp), with emissions from SciPy's bivariate normal.
   * ``brute.py``    -- enumeration of every hidden path in exact rationals.
+  * ``loglik_kind`` -- eq. (2) with Poisson-count or 1-D Gaussian emissions
+    (other HMMs differ from the tremor model only in the emission function).
 """
 import ctypes
 import os
@@ -57,6 +59,12 @@ def lib():
         L.oracle_loglik_blocked.restype = ctypes.c_double
         L.oracle_loglik_blocked.argtypes = [ctypes.c_int, dp, dp, dp, dp, dp, ctypes.c_int64,
                                             u8p, dp, ctypes.c_int64]
+        L.oracle_log_emission_kind.restype = ctypes.c_int
+        L.oracle_log_emission_kind.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, ctypes.c_int64, ctypes.c_void_p,
+                                               dp]
+        L.oracle_loglik_kind.restype = ctypes.c_double
+        L.oracle_loglik_kind.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, dp, dp, ctypes.c_int64,
+                                         ctypes.c_void_p]
         L.oracle_loglik_batch.restype = ctypes.c_int
         L.oracle_loglik_batch.argtypes = [ctypes.c_int32, i32p, i64p, i64p, dp, i64p, u8p, dp, dp,
                                           ctypes.c_int32]
@@ -141,3 +149,35 @@ def loglik_batch(K, T, param_off, params, obs_off, flag, xy, nthreads=1):
         obs_off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), fp, xp,
         out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(nthreads))
     return out
+
+
+POISSON, GAUSS1D = 1, 2
+
+
+def _kind_args(kind, e0, e1, obs):
+    e0, p0 = _f64(e0)
+    e1, p1 = _f64(e1 if e1 is not None else np.zeros_like(e0))
+    if kind == POISSON:
+        obs = np.ascontiguousarray(obs, dtype=np.int32)
+    else:
+        obs = np.ascontiguousarray(obs, dtype=np.float64)
+    return e0, p0, e1, p1, obs
+
+
+def log_emission_kind(kind, e0, e1, obs):
+    """ln e_{t,k} (T, K) of the Poisson (kind 1: e0 = lambda, obs = int counts) or
+    1-D Gaussian (kind 2: e0 = mu, e1 = var, obs = values) emission model."""
+    e0, p0, e1, p1, obs = _kind_args(kind, e0, e1, obs)
+    K, T = e0.shape[0], obs.shape[0]
+    out = np.empty((T, K), dtype=np.float64)
+    lib().oracle_log_emission_kind(kind, K, p0, p1, T, obs.ctypes.data,
+                                   out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    return out
+
+
+def loglik_kind(kind, delta, Gamma, e0, e1, obs):
+    """ln L of eq. (2) with the Poisson or 1-D Gaussian emission model (FP64)."""
+    delta, dp_ = _f64(delta)
+    Gamma, gp = _f64(Gamma)
+    e0, p0, e1, p1, obs = _kind_args(kind, e0, e1, obs)
+    return lib().oracle_loglik_kind(kind, delta.shape[0], dp_, gp, p0, p1, obs.shape[0], obs.ctypes.data)

@@ -158,6 +158,65 @@ double oracle_loglik(int K, const double *delta, const double *Gamma, const doub
     return ll;
 }
 
+/* Other emission models.  The paper notes that the method applies to other
+ * HMMs by changing only the emission function (sections "Discussion" and
+ * "Conclusion"); the likelihood is still eq. (2) with P(x) = diag(e_1..e_K).
+ *   kind 1, Poisson counts:  e_k(y) = lambda_k^y exp(-lambda_k) / y!
+ *            e0 = lambda[K] (> 0), obs = int32 counts[T] (>= 0)
+ *   kind 2, 1-D Gaussian:    e_k(x) = N(x; mu_k, var_k)
+ *            e0 = mu[K], e1 = var[K] (> 0), obs = double values[T] (finite)
+ * out[t*K + k] = ln e_{t,k}.  Returns 0, or 1 for invalid parameters or data
+ * (out then holds NaN). */
+int oracle_log_emission_kind(int kind, int K, const double *e0, const double *e1, int64_t T,
+                             const void *obs, double *out)
+{
+    int bad = 0;
+    for (int k = 0; k < K; ++k) {
+        if (kind == 1 && !(isfinite(e0[k]) && e0[k] > 0.0)) bad = 1;
+        if (kind == 2 && !(isfinite(e0[k]) && isfinite(e1[k]) && e1[k] > 0.0)) bad = 1;
+    }
+    if (kind != 1 && kind != 2) bad = 1;
+    for (int64_t t = 0; t < T && !bad; ++t) {
+        for (int k = 0; k < K; ++k) {
+            double v;
+            if (kind == 1) {
+                const int32_t y = ((const int32_t *)obs)[t];
+                if (y < 0) { bad = 1; break; }
+                v = (double)y * log(e0[k]) - e0[k] - lgamma((double)y + 1.0);
+            } else {
+                const double x = ((const double *)obs)[t];
+                if (!isfinite(x)) { bad = 1; break; }
+                const double d = x - e0[k];
+                v = -0.5 * ORACLE_LN_2PI - 0.5 * log(e1[k]) - 0.5 * d * d / e1[k];
+            }
+            out[(size_t)t * K + k] = v;
+        }
+    }
+    if (bad)
+        for (int64_t i = 0; i < T * (int64_t)K; ++i) out[i] = NAN;
+    return bad;
+}
+
+/* ln L of eq. (2) with the emissions of oracle_log_emission_kind. */
+double oracle_loglik_kind(int kind, int K, const double *delta, const double *Gamma, const double *e0,
+                          const double *e1, int64_t T, const void *obs)
+{
+    if (K < 1 || T < 0) return NAN;
+    for (int k = 0; k < K; ++k) {
+        if (!isfinite(delta[k]) || delta[k] < 0.0) return NAN;
+        for (int j = 0; j < K; ++j) {
+            const double g = Gamma[(size_t)k * K + j];
+            if (!isfinite(g) || g < 0.0 || g > 1.0) return NAN;
+        }
+    }
+    double *logE = (double *)malloc(sizeof(double) * (size_t)(T > 0 ? T : 1) * (size_t)K);
+    if (!logE) return NAN;
+    if (oracle_log_emission_kind(kind, K, e0, e1, T, obs, logE) != 0) { free(logE); return NAN; }
+    double ll = oracle_forward_from_logemis(K, delta, Gamma, T, logE);
+    free(logE);
+    return ll;
+}
+
 /* The same quantity in the order of the paper's parallel plan (section "The
  * likelihood algorithm", steps 1-3): the chain Gamma P(x_0) ... Gamma P(x_N)
  * is cut into segments of L factors, each segment's matrix product is formed

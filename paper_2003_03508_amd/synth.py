@@ -158,6 +158,66 @@ def make(K, T, seed):
     return prm, obs
 
 
+@dataclass
+class KindSet:
+    """An HMM with a non-tremor emission model: kind 1 Poisson counts
+    (e0 = lambda, obs = int32 counts), kind 2 1-D Gaussian (e0 = mu, e1 = var,
+    obs = float64 values)."""
+    kind: int
+    delta: np.ndarray
+    Gamma: np.ndarray
+    e0: np.ndarray
+    e1: np.ndarray
+    obs: np.ndarray
+    states: np.ndarray = field(default=None)
+
+    @property
+    def K(self):
+        return int(self.delta.shape[0])
+
+    @property
+    def T(self):
+        return int(self.obs.shape[0])
+
+
+def make_kind(kind, K, T, seed):
+    """Synthetic HMM of another emission family, same transition recipe.
+
+    ``numpy.random.default_rng(seed)``, draws in this order: Gamma rows ~
+    Dirichlet(1 off the diagonal, 50 on it); delta = 1/K; kind 1: lambda_k ~
+    U(0.5, 20); kind 2: mu_k ~ U(0, 100), sd_k ~ U(1, 10); the path as in
+    ``sample_path`` (state uniforms for s_-1..s_{T-1}); then the observations:
+    counts ~ Poisson(lambda_s) (kind 1) or x = mu_s + sd_s z (kind 2)."""
+    rng = np.random.default_rng(seed)
+    alpha = np.full((K, K), 1.0)
+    np.fill_diagonal(alpha, 50.0)
+    Gamma = np.stack([rng.dirichlet(alpha[i]) for i in range(K)])
+    delta = np.full(K, 1.0 / K)
+    if kind == 1:
+        e0 = rng.uniform(0.5, 20.0, size=K)
+        e1 = np.zeros(K)
+    elif kind == 2:
+        e0 = rng.uniform(0.0, 100.0, size=K)
+        e1 = rng.uniform(1.0, 10.0, size=K) ** 2
+    else:
+        raise ValueError("kind must be 1 (Poisson) or 2 (1-D Gaussian)")
+    u_state = rng.random(T + 1)
+    rows = []
+    for i in range(K):
+        c = np.cumsum(Gamma[i])
+        c[-1] = 1.0
+        rows.append(c.tolist())
+    cum_delta = np.cumsum(delta)
+    cum_delta[-1] = 1.0
+    s0 = min(bisect.bisect_right(cum_delta.tolist(), u_state[0]), K - 1)
+    states = _walk_path(rows, s0, u_state[1:])
+    if kind == 1:
+        obs = rng.poisson(e0[states]).astype(np.int32)
+    else:
+        obs = e0[states] + np.sqrt(e1[states]) * rng.standard_normal(T)
+    return KindSet(kind, delta, Gamma, e0, e1, np.ascontiguousarray(obs), states)
+
+
 # Workloads with the shapes the paper's method is benchmarked on.
 WORKLOADS = {
     "k3_t1e4": dict(K=3, T=10_000, seed=0),
