@@ -44,7 +44,12 @@
  *     FP64.  An emission below 2^-222 of its step's largest one loses
  *     precision (FP32 subnormal) and below 2^-245 counts as zero; the FP64
  *     oracle's limit is 2^-1074.  With any transition matrix whose entries
- *     are not tiny this cannot change ln L measurably.
+ *     are not tiny this cannot change ln L measurably.  HMM_SERIAL_F32 scales
+ *     the whole forward vector by one power of two per step, so a state whose
+ *     forward variable falls more than ~2^126 below the largest one is lost;
+ *     that needs a transition matrix that (almost) forbids moving between
+ *     states (e.g. the identity).  The blocked paths keep one exponent per
+ *     start state and are not limited this way.
  */
 #ifndef HMM_MI355X_H
 #define HMM_MI355X_H
@@ -104,6 +109,24 @@ int hmm_loglik(hmm_ctx *ctx, int32_t K, const double *delta, const double *Gamma
                const double *p, const double *mu, const double *Sigma, int64_t T,
                const uint8_t *flag, const double *xy, int32_t algo, void *stream,
                double *out);
+
+/* Other emission models.  The method needs only the emission function of the
+ * model (the matrix chain of eq. 2 is the same), so the same kernels serve
+ * other HMMs:
+ *   HMM_EMIS_POISSON  counts: e_k(y) = lambda_k^y e^(-lambda_k) / y!
+ *                     e0 = lambda[K] (> 0), e1 unused (may be NULL),
+ *                     obs = int32 counts[T] (>= 0)
+ *   HMM_EMIS_GAUSS1D  e_k(x) = N(x; mu_k, var_k)
+ *                     e0 = mu[K], e1 = var[K] (> 0), obs = double values[T]
+ * hmm_loglik_kind returns ln L of eq. (2) with those emissions, with
+ * hmm_loglik's conventions (invalid parameters, a negative count or a
+ * non-finite value give NaN; L = 0 gives -inf; T = 0 gives ln sum delta) and
+ * numerics, for the same algorithms and K limits. */
+typedef enum { HMM_EMIS_POISSON = 1, HMM_EMIS_GAUSS1D = 2 } hmm_emission_kind;
+
+int hmm_loglik_kind(hmm_ctx *ctx, int32_t kind, int32_t K, const double *delta,
+                    const double *Gamma, const double *e0, const double *e1, int64_t T,
+                    const void *obs, int32_t algo, void *stream, double *out);
 
 /* ln L of eq. (2) for n independent parameter sets, each with its own K and
  * observation sequence, in one launch sequence (batched evaluation of MCMC

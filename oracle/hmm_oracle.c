@@ -30,7 +30,11 @@
  *   - L = 0 gives -inf; invalid parameters or data give NaN (see oracle_valid).
  *   - Underflow is avoided as the paper says (logarithm and scaling, section
  *     "Step 3"); the scaling constant here is the per-step sum c_t, which is
- *     mathematically exact and only changes rounding.
+ *     mathematically exact and only changes rounding.  One scale is shared by
+ *     all states, so a state whose forward variable trails the largest by
+ *     more than ~e^-745 at some step underflows to zero; this needs a
+ *     transition matrix that (almost) forbids moving between states (e.g.
+ *     the identity), for which the tests use the closed form instead.
  */
 #include <math.h>
 #include <stdint.h>

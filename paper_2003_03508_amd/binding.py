@@ -23,6 +23,8 @@ SERIAL_F32 = 0
 BLOCKED_F32 = 1
 BLOCKED_BF16 = 2
 BLOCKED_F16 = 3
+EMIS_POISSON = 1
+EMIS_GAUSS1D = 2
 ALGOS = {"serial_f32": SERIAL_F32, "blocked_f32": BLOCKED_F32,
          "blocked_bf16": BLOCKED_BF16, "blocked_f16": BLOCKED_F16}
 
@@ -47,6 +49,7 @@ _lib.hmm_loglik_batched.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp, _i64, _vp, _v
 _lib.hmm_ctx_set_batch_graph.argtypes = [_vp, _i32]
 _lib.hmm_autotune_batched.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _i64, _i32, _vp,
                                       _i32, _vp]
+_lib.hmm_loglik_kind.argtypes = [_vp, _i32, _i32, _vp, _vp, _vp, _vp, _i64, _vp, _i32, _vp, _vp]
 _lib.hmm_theta_to_params.argtypes = [_vp, _i32, _i32, _vp, _vp, _vp, _vp, _vp]
 _lib.hmm_philox.argtypes = [_vp, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, _i64,
                             _i32, _vp, _vp]
@@ -90,7 +93,7 @@ _lib.hmm_status_string.argtypes = [ctypes.c_int]
 for _f in ("hmm_ctx_create", "hmm_ctx_destroy", "hmm_loglik", "hmm_emission",
            "hmm_ctx_set_blocking", "hmm_blocked_plan", "hmm_ctx_profile", "hmm_ctx_profile_read",
            "hmm_loglik_batched", "hmm_ctx_set_batch_graph", "hmm_autotune_batched",
-           "hmm_theta_to_params", "hmm_philox", "mcmc_create", "mcmc_destroy", "mcmc_set_state",
+           "hmm_theta_to_params", "hmm_philox", "hmm_loglik_kind", "mcmc_create", "mcmc_destroy", "mcmc_set_state",
            "mcmc_set_rw_scale", "mcmc_step", "mcmc_train_proposal", "mcmc_reset_proposal", "mcmc_view_get",
            "mlp_forward",
            "mlp_loss_grad", "mlp_set_weights", "mcmc_checkpoint_size", "mcmc_checkpoint_save",
@@ -187,6 +190,22 @@ class Context:
                              _dev(flag, torch.uint8, "flag", T), _dev(xy, torch.float64, "xy", 2 * T),
                              a, _stream(stream), _dev(out, torch.float64, "out", 1))
         _check("hmm_loglik", rc)
+        return out
+
+    def loglik_kind(self, kind, delta, Gamma, e0, e1, obs, algo="blocked_f32", out=None, stream=None):
+        """ln L (eq. 2) with another emission model: kind 1 Poisson (e0 = lambda, obs int32
+        counts), kind 2 1-D Gaussian (e0 = mu, e1 = var, obs float64 values)."""
+        K = int(delta.numel())
+        T = int(obs.numel())
+        if out is None:
+            out = torch.empty(1, dtype=torch.float64, device=delta.device)
+        a = ALGOS[algo] if isinstance(algo, str) else int(algo)
+        obs_t = torch.int32 if int(kind) == EMIS_POISSON else torch.float64
+        rc = _lib.hmm_loglik_kind(self._h, int(kind), K, _dev(delta, torch.float64, "delta", K),
+                                  _dev(Gamma, torch.float64, "Gamma", K * K), _dev(e0, torch.float64, "e0", K),
+                                  _dev(e1, torch.float64, "e1", K) if e1 is not None else None, T,
+                                  _dev(obs, obs_t, "obs", T), a, _stream(stream), _dev(out, torch.float64, "out", 1))
+        _check("hmm_loglik_kind", rc)
         return out
 
     def batch_graph(self, on=True):
@@ -469,3 +488,14 @@ def to_device(prm, obs, device="cuda"):
                 Sigma=torch.as_tensor(prm.Sigma, **f64).contiguous(),
                 flag=torch.as_tensor(obs.flag, dtype=torch.uint8, device=device).contiguous(),
                 xy=torch.as_tensor(obs.xy, **f64).contiguous())
+
+
+def kind_to_device(ks, device="cuda"):
+    """Device tensors for a synth.KindSet (delta, Gamma, e0, e1, obs)."""
+    f64 = dict(dtype=torch.float64, device=device)
+    obs_t = torch.int32 if ks.kind == EMIS_POISSON else torch.float64
+    return dict(delta=torch.as_tensor(ks.delta, **f64).contiguous(),
+                Gamma=torch.as_tensor(ks.Gamma, **f64).contiguous(),
+                e0=torch.as_tensor(ks.e0, **f64).contiguous(),
+                e1=torch.as_tensor(ks.e1, **f64).contiguous(),
+                obs=torch.as_tensor(ks.obs, dtype=obs_t, device=device).contiguous())

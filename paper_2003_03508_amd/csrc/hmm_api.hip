@@ -88,6 +88,90 @@ int launch_status(void)
     return e == hipSuccess ? HMM_OK : HMM_E_DEVICE;
 }
 
+template <bool GEN>
+void launch_serial(int KP, hipStream_t st, int K, int64_t T, const double *delta, const float *gf,
+                   const StateConst *sc, const Obs &obs, int *status, double *out)
+{
+    switch (KP) {
+    case 16: hipLaunchKernelGGL((k_serial<16, GEN>), dim3(1), dim3(64), 0, st, K, T, delta, gf, sc, obs, status, out); break;
+    case 32: hipLaunchKernelGGL((k_serial<32, GEN>), dim3(1), dim3(64), 0, st, K, T, delta, gf, sc, obs, status, out); break;
+    case 64: hipLaunchKernelGGL((k_serial<64, GEN>), dim3(1), dim3(64), 0, st, K, T, delta, gf, sc, obs, status, out); break;
+    case 96: hipLaunchKernelGGL((k_serial<96, GEN>), dim3(1), dim3(64), 0, st, K, T, delta, gf, sc, obs, status, out); break;
+    default: hipLaunchKernelGGL((k_serial<128, GEN>), dim3(1), dim3(64), 0, st, K, T, delta, gf, sc, obs, status, out); break;
+    }
+}
+
+// Blocks of the Poisson log-factorial sum (partials live after the layout).
+constexpr int kFactBlocks = 256;
+
+// ln L of eq. (2) for one set of any emission kind (arguments checked by the
+// caller except delta, Gamma, out and algo).
+int loglik_impl(hmm_ctx *ctx, int kind, int32_t K, const double *delta, const double *Gamma, const double *a,
+                const double *b, const double *c, int64_t T, const Obs &obs, int32_t algo, void *stream,
+                double *out)
+{
+    if (!delta || !Gamma || !out) return HMM_E_INVALID_ARG;
+    if (algo != HMM_SERIAL_F32 && algo != HMM_BLOCKED_F32 && algo != HMM_BLOCKED_BF16 &&
+        algo != HMM_BLOCKED_F16)
+        return HMM_E_INVALID_ARG;
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return HMM_E_DEVICE;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    int rc;
+    if (algo == HMM_SERIAL_F32) {
+        const int KP = serial_kp(K);
+        Layout ly = make_layout(KP, Plan());
+        rc = ensure_ws(ctx, ly.total + sizeof(double) * kFactBlocks);
+        if (rc != HMM_OK) return rc;
+        int *status = at<int>(ctx->ws, ly.status);
+        StateConst *sc = at<StateConst>(ctx->ws, ly.sc);
+        float *gf = at<float>(ctx->ws, ly.gf);
+        hipLaunchKernelGGL(k_prepare, dim3(1), dim3(256), 0, st, kind, K, KP, delta, Gamma, a, b, c, sc, gf, status);
+        if (kind == kEmisTremor)
+            launch_serial<false>(KP, st, K, T, delta, gf, sc, obs, status, out);
+        else
+            launch_serial<true>(KP, st, K, T, delta, gf, sc, obs, status, out);
+        if (kind == kEmisPoisson && T > 0)
+            hipLaunchKernelGGL(k_log_factorials, dim3(kFactBlocks), dim3(256), 0, st, T, obs.cnt,
+                               at<double>(ctx->ws, ly.total));
+        if (kind == kEmisPoisson && T > 0)
+            hipLaunchKernelGGL(k_subtract_sum, dim3(1), dim3(64), 0, st, kFactBlocks, at<double>(ctx->ws, ly.total),
+                               out);
+        return launch_status();
+    }
+    KernelSet ks;
+    if (!select_kernels(algo, K, &ks)) return HMM_E_UNSUPPORTED;
+    const int KP = ks.KP();
+    Plan pl = make_plan(ctx, KP, T);
+    if (pl.n1 > INT_MAX) return HMM_E_UNSUPPORTED;
+    Layout ly = make_layout(KP, pl);
+    rc = ensure_ws(ctx, ly.total + sizeof(double) * kFactBlocks);
+    if (rc != HMM_OK) return rc;
+    int *status = at<int>(ctx->ws, ly.status);
+    StateConst *sc = at<StateConst>(ctx->ws, ly.sc);
+    float *gf = at<float>(ctx->ws, ly.gf);
+    hipLaunchKernelGGL(k_prepare, dim3(1), dim3(256), 0, st, kind, K, KP, delta, Gamma, a, b, c, sc, gf, status);
+    SetDesc d;
+    d.obs = obs;
+    d.sc = sc;
+    d.GF = gf;
+    d.delta = delta;
+    d.status = status;
+    d.out = out;
+    d.T = T;
+    d.L = pl.L;
+    d.K = K;
+    d.pad = 0;
+    rc = run_single(ctx, ks, d, pl, ly, st);
+    if (rc != HMM_OK) return rc;
+    if (kind == kEmisPoisson && T > 0) {
+        hipLaunchKernelGGL(k_log_factorials, dim3(kFactBlocks), dim3(256), 0, st, T, obs.cnt,
+                           at<double>(ctx->ws, ly.total));
+        hipLaunchKernelGGL(k_subtract_sum, dim3(1), dim3(64), 0, st, kFactBlocks, at<double>(ctx->ws, ly.total), out);
+    }
+    return launch_status();
+}
+
 }  // namespace
 
 extern "C" {
@@ -154,64 +238,24 @@ int hmm_loglik(hmm_ctx *ctx, int32_t K, const double *delta, const double *Gamma
                const double *mu, const double *Sigma, int64_t T, const uint8_t *flag,
                const double *xy, int32_t algo, void *stream, double *out)
 {
-    int rc = check_common(ctx, K, p, mu, Sigma, T, flag, xy);
+    const int rc = check_common(ctx, K, p, mu, Sigma, T, flag, xy);
     if (rc != HMM_OK) return rc;
-    if (!delta || !Gamma || !out) return HMM_E_INVALID_ARG;
-    if (algo != HMM_SERIAL_F32 && algo != HMM_BLOCKED_F32 && algo != HMM_BLOCKED_BF16 &&
-        algo != HMM_BLOCKED_F16)
-        return HMM_E_INVALID_ARG;
-    DeviceGuard dg(ctx->device);
-    if (!dg.ok) return HMM_E_DEVICE;
-    hipStream_t st = static_cast<hipStream_t>(stream);
+    return loglik_impl(ctx, kEmisTremor, K, delta, Gamma, p, mu, Sigma, T, Obs{flag, xy, nullptr, kEmisTremor, 0},
+                       algo, stream, out);
+}
 
-    if (algo == HMM_SERIAL_F32) {
-        const int KP = serial_kp(K);
-        Layout ly = make_layout(KP, Plan());
-        rc = ensure_ws(ctx, ly.total);
-        if (rc != HMM_OK) return rc;
-        int *status = at<int>(ctx->ws, ly.status);
-        StateConst *sc = at<StateConst>(ctx->ws, ly.sc);
-        float *gf = at<float>(ctx->ws, ly.gf);
-        hipLaunchKernelGGL(k_prepare, dim3(1), dim3(256), 0, st, K, KP, delta, Gamma, p, mu, Sigma, sc,
-                           gf, status);
-        switch (KP) {
-        case 16: hipLaunchKernelGGL(k_serial<16>, dim3(1), dim3(64), 0, st, K, T, delta, gf, sc, flag, xy, status, out); break;
-        case 32: hipLaunchKernelGGL(k_serial<32>, dim3(1), dim3(64), 0, st, K, T, delta, gf, sc, flag, xy, status, out); break;
-        case 64: hipLaunchKernelGGL(k_serial<64>, dim3(1), dim3(64), 0, st, K, T, delta, gf, sc, flag, xy, status, out); break;
-        case 96: hipLaunchKernelGGL(k_serial<96>, dim3(1), dim3(64), 0, st, K, T, delta, gf, sc, flag, xy, status, out); break;
-        default: hipLaunchKernelGGL(k_serial<128>, dim3(1), dim3(64), 0, st, K, T, delta, gf, sc, flag, xy, status, out); break;
-        }
-        return launch_status();
-    }
-
-    KernelSet ks;
-    if (!select_kernels(algo, K, &ks)) return HMM_E_UNSUPPORTED;
-    const int KP = ks.KP();
-    Plan pl = make_plan(ctx, KP, T);
-    if (pl.n1 > INT_MAX) return HMM_E_UNSUPPORTED;
-    Layout ly = make_layout(KP, pl);
-    rc = ensure_ws(ctx, ly.total);
-    if (rc != HMM_OK) return rc;
-    int *status = at<int>(ctx->ws, ly.status);
-    StateConst *sc = at<StateConst>(ctx->ws, ly.sc);
-    float *gf = at<float>(ctx->ws, ly.gf);
-    hipLaunchKernelGGL(k_prepare, dim3(1), dim3(256), 0, st, K, KP, delta, Gamma, p, mu, Sigma, sc, gf,
-                       status);
-    SetDesc d;
-    d.flag = flag;
-    d.xy = xy;
-    d.sc = sc;
-    d.GF = gf;
-    d.delta = delta;
-    d.status = status;
-    d.out = out;
-    d.T = T;
-    d.L = pl.L;
-    d.K = K;
-    d.pad = 0;
-    rc = run_single(ctx, ks, d, pl, ly, st);
-    if (rc != HMM_OK) return rc;
-    return launch_status();
+int hmm_loglik_kind(hmm_ctx *ctx, int32_t kind, int32_t K, const double *delta, const double *Gamma,
+                    const double *e0, const double *e1, int64_t T, const void *obs, int32_t algo, void *stream,
+                    double *out)
+{
+    if (!ctx || !e0 || K < 1 || K > 128 || T < 0 || T >= kMaxT) return HMM_E_INVALID_ARG;
+    if (kind != HMM_EMIS_POISSON && kind != HMM_EMIS_GAUSS1D) return HMM_E_INVALID_ARG;
+    if (kind == HMM_EMIS_GAUSS1D && !e1) return HMM_E_INVALID_ARG;
+    if (T > 0 && !obs) return HMM_E_INVALID_ARG;
+    const Obs o = kind == HMM_EMIS_POISSON
+                      ? Obs{nullptr, nullptr, static_cast<const int32_t *>(obs), kEmisPoisson, 0}
+                      : Obs{nullptr, static_cast<const double *>(obs), nullptr, kEmisGauss1, 0};
+    return loglik_impl(ctx, o.kind, K, delta, Gamma, e0, e1, nullptr, T, o, algo, stream, out);
 }
 
 int hmm_emission(hmm_ctx *ctx, int32_t K, const double *p, const double *mu, const double *Sigma,
@@ -233,11 +277,11 @@ int hmm_emission(hmm_ctx *ctx, int32_t K, const double *p, const double *mu, con
     const unsigned nchunk = (unsigned)((T + kChunk - 1) / kChunk);
     if (nchunk > 0) {
         switch (KP) {
-        case 16: hipLaunchKernelGGL(k_emission<16>, dim3(nchunk), dim3(64), 0, st, K, T, sc, flag, xy, shift, e_hat, status); break;
-        case 32: hipLaunchKernelGGL(k_emission<32>, dim3(nchunk), dim3(64), 0, st, K, T, sc, flag, xy, shift, e_hat, status); break;
-        case 64: hipLaunchKernelGGL(k_emission<64>, dim3(nchunk), dim3(64), 0, st, K, T, sc, flag, xy, shift, e_hat, status); break;
-        case 96: hipLaunchKernelGGL(k_emission<96>, dim3(nchunk), dim3(64), 0, st, K, T, sc, flag, xy, shift, e_hat, status); break;
-        default: hipLaunchKernelGGL(k_emission<128>, dim3(nchunk), dim3(64), 0, st, K, T, sc, flag, xy, shift, e_hat, status); break;
+        case 16: hipLaunchKernelGGL(k_emission<16>, dim3(nchunk), dim3(64), 0, st, K, T, sc, Obs{flag, xy, nullptr, kEmisTremor, 0}, shift, e_hat, status); break;
+        case 32: hipLaunchKernelGGL(k_emission<32>, dim3(nchunk), dim3(64), 0, st, K, T, sc, Obs{flag, xy, nullptr, kEmisTremor, 0}, shift, e_hat, status); break;
+        case 64: hipLaunchKernelGGL(k_emission<64>, dim3(nchunk), dim3(64), 0, st, K, T, sc, Obs{flag, xy, nullptr, kEmisTremor, 0}, shift, e_hat, status); break;
+        case 96: hipLaunchKernelGGL(k_emission<96>, dim3(nchunk), dim3(64), 0, st, K, T, sc, Obs{flag, xy, nullptr, kEmisTremor, 0}, shift, e_hat, status); break;
+        default: hipLaunchKernelGGL(k_emission<128>, dim3(nchunk), dim3(64), 0, st, K, T, sc, Obs{flag, xy, nullptr, kEmisTremor, 0}, shift, e_hat, status); break;
         }
     }
     return launch_status();

@@ -237,8 +237,7 @@ int build(hmm_ctx *ctx, BatchPlan &bp)
         for (const auto &cc : bp.classes)
             if (cc.ks.seg1 == kss[s].seg1) c = &cc;
         SetDesc &d = hs[s];
-        d.flag = bp.flag + bp.obs_off[s];
-        d.xy = bp.xy + 2 * bp.obs_off[s];
+        d.obs = Obs{bp.flag + bp.obs_off[s], bp.xy + 2 * bp.obs_off[s], nullptr, kEmisTremor, 0};
         d.sc = reinterpret_cast<const StateConst *>(base + o_sc[s]);
         d.GF = reinterpret_cast<const float *>(base + o_gf[s]);
         d.delta = bp.params + bp.param_off[s];

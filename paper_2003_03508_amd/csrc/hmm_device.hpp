@@ -28,8 +28,24 @@ constexpr int kEmisBias = 96;
 // with a1 = log2 p - log2(2 pi) - log2|Sigma|/2, a0 = log2(1 - p) and
 // (cxx, cxy, cyy) = -log2(e)/2 * Sigma^{-1} (off-diagonal doubled).
 // Padding states (k >= K) carry a1 = a0 = -inf so their emission is zero.
+// The other emission kinds use the same fields (see state_log2_emission).
 struct alignas(16) StateConst {
-    double mx, my, cxx, cxy, cyy, a1, a0, pad;
+    double mx, my, cxx, cxy, cyy, a1, a0, lx;
+};
+
+constexpr double kLog2E = 1.4426950408889634073599246810019;
+
+// Emission models: the tremor model of eq. (1), Poisson counts, 1-D Gaussian.
+constexpr int kEmisTremor = 0, kEmisPoisson = 1, kEmisGauss1 = 2;
+
+// The observation sequence of one likelihood, by emission kind:
+//   tremor: flag[t] (uint8) and xy[2t], xy[2t+1];  Poisson: cnt[t] (int32);
+//   1-D Gaussian: xy[t].
+struct Obs {
+    const uint8_t *flag;
+    const double *xy;
+    const int32_t *cnt;
+    int kind, pad;
 };
 
 // ---------------------------------------------------------------------------
@@ -181,37 +197,71 @@ __device__ __forceinline__ double state_log2_emission(const StateConst &s, bool 
     return tremor ? q : s.a0;
 }
 
-template <int ES>
-__device__ __forceinline__ void stage_emissions(int K, int64_t tc, int nst,
-                                                const uint8_t *__restrict__ flag,
-                                                const double *__restrict__ xy,
+// log2 e of one state for every emission kind (FP64), one formula:
+//   q = a1 + lx x + d0 (cxx d0 + cxy d1) + cyy d1^2,  d = (x - mx, y - my)
+//   tremor (eq. 1):  lx = 0; q for a tremor at (x, y), a0 for "no tremor"
+//   1-D Gaussian:    y = my = 0, so d1 = 0: a1 = -log2(2 pi var)/2,
+//                    cxx = -log2(e)/(2 var), mx = mu; always the q branch
+//   Poisson counts:  x = y count, lx = log2(lambda), a1 = -lambda log2(e),
+//                    no quadratic terms; the factor 1/y! is common to all
+//                    states, so it leaves the matrix chain and is added to
+//                    ln L separately (k_log_factorials)
+__device__ __forceinline__ double generic_log2_emission(const StateConst &s, bool q_branch, double x, double y)
+{
+    const double d0 = x - s.mx, d1 = y - s.my;
+    const double q = fma(s.lx, x, s.a1) + d0 * (s.cxx * d0 + s.cxy * d1) + s.cyy * (d1 * d1);
+    return q_branch ? q : s.a0;
+}
+
+// GEN = false: the tremor model only (the likelihood kernels of eq. 1);
+// GEN = true: any emission kind, chosen by o.kind.
+template <int ES, bool GEN>
+__device__ __forceinline__ void stage_emissions(int K, int64_t tc, int nst, const Obs &o,
                                                 const StateConst *__restrict__ sc,
                                                 float *Et, long long &ssum, int &bad, int &shift)
 {
     const int lane = threadIdx.x & (kWave - 1);
     const bool live = lane < nst;
+    const int kind = GEN ? o.kind : kEmisTremor;
     int f = 0;
     double x = 0.0, y = 0.0;
     if (live) {
-        f = flag[tc + lane];
-        if (f == 1) {
-            const double2 p = reinterpret_cast<const double2 *>(xy)[tc + lane];
-            x = p.x;
-            y = p.y;
-            if (!(isfinite(x) && isfinite(y))) bad = 1;
-        } else if (f != 0) {
-            bad = 1;
+        if (kind == kEmisTremor) {
+            f = o.flag[tc + lane];
+            if (f == 1) {
+                const double2 p = reinterpret_cast<const double2 *>(o.xy)[tc + lane];
+                x = p.x;
+                y = p.y;
+                if (!(isfinite(x) && isfinite(y))) bad = 1;
+            } else if (f != 0) {
+                bad = 1;
+            }
+        } else if (kind == kEmisPoisson) {
+            const int32_t n = o.cnt[tc + lane];
+            if (n < 0) bad = 1;
+            x = n < 0 ? 0.0 : (double)n;
+            f = 1;
+        } else {
+            x = o.xy[tc + lane];
+            if (!isfinite(x)) {
+                bad = 1;
+                x = 0.0;
+            }
+            f = 1;
         }
     }
     const bool tremor = (f == 1);
     double m = -INFINITY;
-    for (int k = 0; k < K; ++k) m = fmax(m, state_log2_emission(sc[k], tremor, x, y));
+    auto lam = [&](const StateConst &sk) {
+        return GEN ? generic_log2_emission(sk, tremor, x, y) : state_log2_emission(sk, tremor, x, y);
+    };
+    for (int k = 0; k < K; ++k) m = fmax(m, lam(sc[k]));
     int sh = 0;
     if (m > -1.0e9 && m < 1.0e9) sh = (int)floor(m) - kEmisBias;
     if (live) ssum += sh;
     shift = sh;
     for (int k = 0; k < K; ++k) {
-        const double r = state_log2_emission(sc[k], tremor, x, y) - (double)sh;
+        const double r = lam(sc[k]) - (double)sh;
         float e = 0.f;
         if (live && r > -160.0) {
             const double n = floor(r);

@@ -204,8 +204,10 @@ inline int allow_lds(const void *fn, size_t bytes)
 
 // The kernels of one blocked configuration (operand precision, tile shape,
 // live contraction slots): single-set and batched segment and fold kernels.
+// seg1: single-set segment kernel (tremor model), seg1g: the same for any
+// emission kind, segB: batched (tremor model); fold1 / foldB: combination.
 struct KernelSet {
-    const void *seg1 = nullptr, *segB = nullptr, *fold1 = nullptr, *foldB = nullptr;
+    const void *seg1 = nullptr, *seg1g = nullptr, *segB = nullptr, *fold1 = nullptr, *foldB = nullptr;
     int S = 0, MT = 0, NSL = 0;
     int KP() const { return S * MT; }
 };
@@ -215,6 +217,7 @@ KernelSet kernel_set_f32()
 {
     KernelSet k;
     k.seg1 = reinterpret_cast<const void *>(&k_blocked<S, MT, NSL, false>);
+    k.seg1g = reinterpret_cast<const void *>(&k_blocked<S, MT, NSL, false, true>);
     k.segB = reinterpret_cast<const void *>(&k_blocked<S, MT, NSL, true>);
     k.fold1 = reinterpret_cast<const void *>(&k_fold<S, MT, NSL, false>);
     k.foldB = reinterpret_cast<const void *>(&k_fold<S, MT, NSL, true>);
@@ -229,6 +232,7 @@ KernelSet kernel_set_lp()
 {
     KernelSet k;
     k.seg1 = reinterpret_cast<const void *>(&k_blocked_lp<MT, F16, NSL, false>);
+    k.seg1g = reinterpret_cast<const void *>(&k_blocked_lp<MT, F16, NSL, false, true>);
     k.segB = reinterpret_cast<const void *>(&k_blocked_lp<MT, F16, NSL, true>);
     k.fold1 = reinterpret_cast<const void *>(&k_fold<16, MT, NSL, false>);
     k.foldB = reinterpret_cast<const void *>(&k_fold<16, MT, NSL, true>);
@@ -288,9 +292,10 @@ inline int run_single(hmm_ctx *ctx, const KernelSet &ks, SetDesc d, const Plan &
                       hipStream_t st)
 {
     const int KP = ks.KP();
+    const void *seg = d.obs.kind == kEmisTremor ? ks.seg1 : ks.seg1g;
     void *ws = ctx->ws;
     const size_t rb = (size_t)region_bytes(KP);
-    if (allow_lds(ks.seg1, rb * pl.W) != HMM_OK || allow_lds(ks.fold1, rb * pl.W2) != HMM_OK)
+    if (allow_lds(seg, rb * pl.W) != HMM_OK || allow_lds(ks.fold1, rb * pl.W2) != HMM_OK)
         return HMM_E_DEVICE;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     if (ctx->profile && pl.nb > 0 && ctx->events_used < kMaxTimed) {
@@ -306,7 +311,7 @@ inline int run_single(hmm_ctx *ctx, const KernelSet &ks, SetDesc d, const Plan &
     }
     if (ev0) (void)hipEventRecord(ev0, st);
     if (pl.nb > 0 &&
-        launch_seg(ks.seg1, (unsigned)pl.n1, pl.W, rb * pl.W, st, d, nullptr, nullptr, pl.nb,
+        launch_seg(seg, (unsigned)pl.n1, pl.W, rb * pl.W, st, d, nullptr, nullptr, pl.nb,
                    at<float>(ws, ly.m0), at<long long>(ws, ly.e0), at<long long>(ws, ly.s0)) != hipSuccess)
         return HMM_E_DEVICE;
     if (ev1) (void)hipEventRecord(ev1, st);

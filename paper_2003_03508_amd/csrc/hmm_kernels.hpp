@@ -8,7 +8,6 @@
 
 namespace hmm {
 
-constexpr double kLog2E = 1.4426950408889634073599246810019;
 constexpr double kLn2 = 0.69314718055994530941723212145818;
 constexpr double kLog2TwoPi = 2.6514961294723187980432792951081;  // log2(2 pi)
 
@@ -28,7 +27,7 @@ __device__ __forceinline__ int prepare_state(int k, int K, const double *__restr
 {
     int bad = 0;
     StateConst s;
-    s.pad = 0.0;
+    s.lx = 0.0;
     if (k < K) {
         const double pk = p[k], sxx = Sigma[3 * k], sxy = Sigma[3 * k + 1], syy = Sigma[3 * k + 2];
         const double mx = mu[2 * k], my = mu[2 * k + 1];
@@ -53,7 +52,38 @@ __device__ __forceinline__ int prepare_state(int k, int K, const double *__restr
     return bad;
 }
 
-static __global__ __launch_bounds__(256) void k_prepare(int K, int KP, const double *__restrict__ delta,
+// Constants of the other emission kinds (see state_log2_emission); e0, e1:
+// Poisson lambda[K] (> 0); 1-D Gaussian mu[K], var[K] (> 0).  Observations
+// of these kinds always take the q branch with y = 0, so my = 0 and a0 is
+// unused (-inf for padding states only).
+__device__ __forceinline__ int prepare_state_kind(int kind, int k, int K, const double *__restrict__ e0,
+                                                  const double *__restrict__ e1, StateConst *__restrict__ sc)
+{
+    int bad = 0;
+    StateConst s{0.0, 0.0, 0.0, 0.0, 0.0, -INFINITY, -INFINITY, 0.0};
+    if (k < K) {
+        if (kind == kEmisPoisson) {
+            const double lam = e0[k];
+            if (!(isfinite(lam) && lam > 0.0)) bad = 1;
+            s.lx = log2(lam);
+            s.a1 = -lam * kLog2E;
+            s.a0 = 0.0;
+        } else {
+            const double m = e0[k], v = e1[k];
+            if (!(isfinite(m) && isfinite(v) && v > 0.0)) bad = 1;
+            s.mx = m;
+            s.a1 = -0.5 * (kLog2TwoPi + log2(v));
+            s.cxx = -0.5 * kLog2E / v;
+            s.a0 = 0.0;
+        }
+    }
+    sc[k] = s;
+    return bad;
+}
+
+// kind: kEmisTremor (p, mu, Sigma as in eq. 1) or another kind (p = e0,
+// mu = e1, Sigma unused).
+static __global__ __launch_bounds__(256) void k_prepare(int kind, int K, int KP, const double *__restrict__ delta,
                                                  const double *__restrict__ Gamma,
                                                  const double *__restrict__ p,
                                                  const double *__restrict__ mu,
@@ -66,7 +96,8 @@ static __global__ __launch_bounds__(256) void k_prepare(int K, int KP, const dou
     __syncthreads();
     int mybad = 0;
     for (int k = threadIdx.x; k < KP; k += blockDim.x) {
-        mybad |= prepare_state(k, K, p, mu, Sigma, sc);
+        mybad |= (kind == kEmisTremor) ? prepare_state(k, K, p, mu, Sigma, sc)
+                                       : prepare_state_kind(kind, k, K, p, mu, sc);
         if (k < K && !(isfinite(delta[k]) && delta[k] >= 0.0)) mybad = 1;
     }
     for (int idx = threadIdx.x; idx < KP * KP; idx += blockDim.x) {
@@ -141,13 +172,42 @@ static __global__ __launch_bounds__(256) void k_prepare_states(int K, int KP, co
 }
 
 // ---------------------------------------------------------------------------
+// Poisson counts: sum_t ln(y_t!) in FP64 in a fixed order (thread i of block
+// q sums t = q*256 + i + 256*nblk*j over j, the block adds its 256 partials
+// in order), then one thread subtracts the blocks' sums, in order, from ln L.
+// ---------------------------------------------------------------------------
+static __global__ __launch_bounds__(256) void k_log_factorials(int64_t T, const int32_t *__restrict__ cnt,
+                                                        double *__restrict__ part)
+{
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < T; t += (int64_t)gridDim.x * 256) {
+        const int32_t n = cnt[t];
+        if (n > 1) s += lgamma((double)n + 1.0);
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double b = 0.0;
+        for (int i = 0; i < 256; ++i) b += red[i];
+        part[blockIdx.x] = b;
+    }
+}
+
+static __global__ void k_subtract_sum(int n, const double *__restrict__ part, double *__restrict__ out)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += part[i];
+    *out -= s;
+}
+
+// ---------------------------------------------------------------------------
 // Emission stage alone (hmm_emission): one wavefront per chunk of kChunk
 // observations writes the shifts s_t and the scaled emissions.
 // ---------------------------------------------------------------------------
 template <int KP>
-__global__ __launch_bounds__(64) void k_emission(int K, int64_t T, const StateConst *__restrict__ sc,
-                                                 const uint8_t *__restrict__ flag,
-                                                 const double *__restrict__ xy,
+__global__ __launch_bounds__(64) void k_emission(int K, int64_t T, const StateConst *__restrict__ sc, Obs obs,
                                                  int32_t *__restrict__ shift,
                                                  float *__restrict__ e_hat, int *__restrict__ status)
 {
@@ -157,7 +217,7 @@ __global__ __launch_bounds__(64) void k_emission(int K, int64_t T, const StateCo
     const int nst = (int)min((int64_t)kChunk, T - tc);
     long long ssum = 0;
     int bad = 0, sh = 0;
-    stage_emissions<kChunk>(K, tc, nst, flag, xy, sc, Et, ssum, bad, sh);
+    stage_emissions<kChunk, false>(K, tc, nst, obs, sc, Et, ssum, bad, sh);
     if (lane < nst) shift[tc + lane] = sh;
     for (int idx = lane; idx < nst * K; idx += kWave) {
         const int tl = idx / K, k = idx % K;
@@ -175,13 +235,11 @@ __global__ __launch_bounds__(64) void k_emission(int K, int64_t T, const StateCo
 //   u   = b * 2^-E, E = exponent of max_j b_j, accumulated exactly.
 // The final ln L = ln2 * (sum of exponents + sum of shifts) + ln(sum_j u_j).
 // ---------------------------------------------------------------------------
-template <int KP>
+template <int KP, bool GEN>
 __device__ __forceinline__ void serial_forward(int K, int64_t T, const double *__restrict__ delta,
                                                const float *__restrict__ GF,
-                                               const StateConst *__restrict__ sc,
-                                               const uint8_t *__restrict__ flag,
-                                               const double *__restrict__ xy, int *__restrict__ status,
-                                               double *__restrict__ out)
+                                               const StateConst *__restrict__ sc, const Obs &obs,
+                                               int *__restrict__ status, double *__restrict__ out)
 {
     constexpr int SPL = (KP + kWave - 1) / kWave;
     constexpr int ES = kChunk + 1;  // odd stride: lane j reads row j without bank conflicts
@@ -215,7 +273,7 @@ __device__ __forceinline__ void serial_forward(int K, int64_t T, const double *_
 
     for (int64_t tc = 0; tc < T; tc += kChunk) {
         const int nst = (int)min((int64_t)kChunk, T - tc);
-        stage_emissions<ES>(K, tc, nst, flag, xy, sc, Et, ssum, bad, sh);
+        stage_emissions<ES, GEN>(K, tc, nst, obs, sc, Et, ssum, bad, sh);
         for (int tl = 0; tl < nst; ++tl) {
             float ej[SPL];
 #pragma unroll
@@ -266,15 +324,13 @@ __device__ __forceinline__ void serial_forward(int K, int64_t T, const double *_
     }
 }
 
-template <int KP>
+template <int KP, bool GEN>
 __global__ __launch_bounds__(64) void k_serial(int K, int64_t T, const double *__restrict__ delta,
                                                const float *__restrict__ GF,
-                                               const StateConst *__restrict__ sc,
-                                               const uint8_t *__restrict__ flag,
-                                               const double *__restrict__ xy,
+                                               const StateConst *__restrict__ sc, Obs obs,
                                                int *__restrict__ status, double *__restrict__ out)
 {
-    serial_forward<KP>(K, T, delta, GF, sc, flag, xy, status, out);
+    serial_forward<KP, GEN>(K, T, delta, GF, sc, obs, status, out);
 }
 
 // ===========================================================================
@@ -301,8 +357,7 @@ __global__ __launch_bounds__(64) void k_serial(int K, int64_t T, const double *_
 // One parameter set with its observation sequence, as the segment and fold
 // kernels see it (prepared constants, output and status of that set).
 struct SetDesc {
-    const uint8_t *flag;     // the set's observations
-    const double *xy;
+    Obs obs;                 // the set's observations
     const StateConst *sc;    // prepared per-state constants (KP entries)
     const float *GF;         // Gamma in FP32, KP x KP, zero-padded
     const double *delta;     // initial distribution (FP64)
@@ -587,7 +642,7 @@ __device__ __forceinline__ void workgroup_tree(Prod<S, MT> &P, long long &ssum, 
 // end the workgroup multiplies its W segment products in order (tree in LDS)
 // and writes one product: Mout[q] (KP x KP row-major), Eout[q][KP], Sout[q].
 // ---------------------------------------------------------------------------
-template <int S, int MT, int NSL, bool BATCH>
+template <int S, int MT, int NSL, bool BATCH, bool GEN = false>
 __global__ __launch_bounds__(64 * group_waves(S * MT)) void k_blocked(SetDesc one,
                                                                       const SetDesc *__restrict__ sets,
                                                                       const WgJob *__restrict__ jobs,
@@ -619,8 +674,7 @@ __global__ __launch_bounds__(64 * group_waves(S * MT)) void k_blocked(SetDesc on
     const int64_t T = d.T, L = d.L;
     const float *__restrict__ GF = d.GF;
     const StateConst *__restrict__ sc = d.sc;
-    const uint8_t *__restrict__ flag = d.flag;
-    const double *__restrict__ xy = d.xy;
+    const Obs obs = d.obs;
     const int64_t b = job.seg0 + w;
     float *base = smem + w * region;
     float *Et = Region<KP>::E(base);  // Et[k][t], row stride kChunk
@@ -644,7 +698,7 @@ __global__ __launch_bounds__(64 * group_waves(S * MT)) void k_blocked(SetDesc on
         for (int i = lane; i < KP * kChunk; i += kWave) Et[i] = 0.f;  // rows >= K stay zero
         for (int64_t tc = t0; tc < t1; tc += kChunk) {
             const int nst = (int)min((int64_t)kChunk, t1 - tc);
-            stage_emissions<kChunk>(K, tc, nst, flag, xy, sc, Et, ssum, bad, sh);
+            stage_emissions<kChunk, GEN>(K, tc, nst, obs, sc, Et, ssum, bad, sh);
             for (int tl = 0; tl < nst; tl += kUnroll<S, MT>) {
                 // scaled emissions of the rows this lane holds, kUnroll steps at once
                 float evu[MT][RS][kUnroll<S, MT>];
@@ -736,7 +790,7 @@ template <> struct Lp<true> {
     }
 };
 
-template <int MT, bool F16, int NSL, bool BATCH>
+template <int MT, bool F16, int NSL, bool BATCH, bool GEN = false>
 __global__ __launch_bounds__(64 * group_waves(16 * MT)) void k_blocked_lp(SetDesc one,
                                                                           const SetDesc *__restrict__ sets,
                                                                           const WgJob *__restrict__ jobs,
@@ -771,8 +825,7 @@ __global__ __launch_bounds__(64 * group_waves(16 * MT)) void k_blocked_lp(SetDes
     const int64_t T = d.T, L = d.L;
     const float *__restrict__ GF = d.GF;
     const StateConst *__restrict__ sc = d.sc;
-    const uint8_t *__restrict__ flag = d.flag;
-    const double *__restrict__ xy = d.xy;
+    const Obs obs = d.obs;
     const int64_t b = job.seg0 + w;
     float *base = smem + w * region;
     float *Et = Region<KP>::E(base);
@@ -808,7 +861,7 @@ __global__ __launch_bounds__(64 * group_waves(16 * MT)) void k_blocked_lp(SetDes
         for (int i = lane; i < KP * kChunk; i += kWave) Et[i] = 0.f;
         for (int64_t tc = t0; tc < t1; tc += kChunk) {
             const int nst = (int)min((int64_t)kChunk, t1 - tc);
-            stage_emissions<kChunk>(K, tc, nst, flag, xy, sc, Et, ssum, bad, sh);
+            stage_emissions<kChunk, GEN>(K, tc, nst, obs, sc, Et, ssum, bad, sh);
             for (int tl = 0; tl < nst; tl += 2) {
                 float evu[MT][RS][2];
 #pragma unroll
@@ -979,7 +1032,7 @@ template <int KP>
 __global__ __launch_bounds__(64) void k_serial_batch(const SetDesc *__restrict__ sets, const int *__restrict__ ids)
 {
     const SetDesc d = sets[ids[blockIdx.x]];
-    serial_forward<KP>(d.K, d.T, d.delta, d.GF, d.sc, d.flag, d.xy, d.status, d.out);
+    serial_forward<KP, false>(d.K, d.T, d.delta, d.GF, d.sc, d.obs, d.status, d.out);
 }
 
 }  // namespace hmm

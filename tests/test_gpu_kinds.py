@@ -1,0 +1,130 @@
+"""Other emission models (Poisson counts, 1-D Gaussian) through the same GPU
+kernels, against the FP64 oracle, through the C ABI.
+
+Tolerances as for the tremor model: FP32 paths within 1e-6 * max(|ln L|, 1);
+16-bit operands within the a-priori bound T * eta of the blocked product.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2003_03508_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+REL = 1e-6
+U_OP = {"blocked_bf16": 2.0 ** -8, "blocked_f16": 2.0 ** -11}
+
+
+@pytest.fixture(scope="module")
+def binding():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2003_03508_amd import binding as b
+    return b
+
+
+@pytest.fixture(scope="module")
+def ctx(binding):
+    c = binding.Context(0)
+    yield c
+    c.close()
+
+
+def gpu(binding, ctx, ks, algo, **over):
+    d = binding.kind_to_device(ks)
+    d.update({k: (torch.as_tensor(v, dtype=d[k].dtype, device="cuda").contiguous()) for k, v in over.items()})
+    out = ctx.loglik_kind(ks.kind, d["delta"], d["Gamma"], d["e0"], d["e1"] if ks.kind == 2 else None, d["obs"],
+                          algo=algo)
+    torch.cuda.synchronize()
+    return float(out.item())
+
+
+def ref(ks, **over):
+    a = dict(delta=ks.delta, Gamma=ks.Gamma, e0=ks.e0, e1=ks.e1, obs=ks.obs)
+    a.update(over)
+    return oracle.loglik_kind(ks.kind, a["delta"], a["Gamma"], a["e0"], a["e1"], a["obs"])
+
+
+def close(got, want, what):
+    rel = abs(got - want) / max(abs(want), 1.0)
+    assert rel <= REL, f"{what}: got {got!r} want {want!r} rel {rel:.3e}"
+
+
+@pytest.mark.parametrize("kind", [1, 2])
+@pytest.mark.parametrize("algo", ["serial_f32", "blocked_f32"])
+@pytest.mark.parametrize("K,T", [(1, 500), (3, 37), (3, 5000), (25, 20_001), (33, 3000), (80, 2000)])
+def test_kind_matches_oracle(binding, ctx, kind, algo, K, T):
+    ks = synth.make_kind(kind, K, T, seed=100 * kind + K)
+    close(gpu(binding, ctx, ks, algo), ref(ks), f"kind {kind} {algo} K={K} T={T}")
+
+
+@pytest.mark.parametrize("kind", [1, 2])
+@pytest.mark.parametrize("algo", ["blocked_bf16", "blocked_f16"])
+@pytest.mark.parametrize("K", [3, 25, 80])
+def test_kind_16bit_within_bound(binding, ctx, kind, algo, K):
+    T = 4000
+    ks = synth.make_kind(kind, K, T, seed=200 * kind + K)
+    want = ref(ks)
+    got = gpu(binding, ctx, ks, algo)
+    eta = 2 * U_OP[algo] + (K + 1) * 2.0 ** -24 + (K * 2.0 ** -24 if algo == "blocked_f16" else 0.0)
+    assert abs(got - want) <= T * eta, (got, want, T * eta)
+
+
+@pytest.mark.parametrize("kind", [1, 2])
+def test_kind_full_size(binding, ctx, kind):
+    ks = synth.make_kind(kind, 25, 1_000_000, seed=300 + kind)
+    want = ref(ks)
+    for algo in ("blocked_f32", "serial_f32"):
+        close(gpu(binding, ctx, ks, algo), want, f"kind {kind} {algo} K=25 T=1e6")
+
+
+@pytest.mark.parametrize("kind", [1, 2])
+@pytest.mark.parametrize("algo", ["serial_f32", "blocked_f32"])
+def test_kind_edge_cases(binding, ctx, kind, algo):
+    ks = synth.make_kind(kind, 4, 300, seed=400 + kind)
+    # T = 0: ln(sum delta)
+    empty = synth.KindSet(kind, ks.delta * 0.5, ks.Gamma, ks.e0, ks.e1, ks.obs[:0].copy())
+    assert abs(gpu(binding, ctx, empty, algo) - math.log(0.5)) < 1e-12
+    # Gamma = I with zeros in delta.  Without transitions the states' running
+    # likelihoods drift apart; the plain forward path shares one power-of-two
+    # scale across states, so it needs every state it keeps to stay within
+    # FP32 range of the leader (a short chain); the blocked path keeps one
+    # exponent per start state and takes the whole chain.
+    # The reference is the closed form ln sum_k delta_k prod_t e_{t,k}: the
+    # oracle's scaled recursion also shares one scale per step and loses a
+    # state that trails by more than e^-745 in FP64.
+    from scipy.special import logsumexp
+    dI = np.array([0.0, 0.7, 0.0, 0.3])
+    short = synth.KindSet(kind, ks.delta, ks.Gamma, ks.e0, ks.e1, ks.obs[:40].copy())
+    for case in (short, ks) if algo == "blocked_f32" else (short,):
+        le = oracle.log_emission_kind(kind, case.e0, case.e1, case.obs).sum(axis=0)
+        want = logsumexp(np.log(dI[dI > 0]) + le[dI > 0])
+        close(gpu(binding, ctx, case, algo, delta=dI, Gamma=np.eye(4)), want, f"Gamma=I T={case.T}")
+    # invalid parameters and data give NaN
+    bad0 = ks.e0.copy()
+    if kind == 1:
+        bad0[1] = 0.0                       # lambda must be > 0
+        assert math.isnan(gpu(binding, ctx, ks, algo, e0=bad0))
+        obs = ks.obs.copy()
+        obs[7] = -1                         # negative count
+        assert math.isnan(gpu(binding, ctx, ks, algo, obs=obs))
+    else:
+        bad1 = ks.e1.copy()
+        bad1[2] = -1.0                      # variance must be > 0
+        assert math.isnan(gpu(binding, ctx, ks, algo, e1=bad1))
+        obs = ks.obs.copy()
+        obs[11] = np.nan
+        assert math.isnan(gpu(binding, ctx, ks, algo, obs=obs))
+
+
+def test_kind_host_errors(binding, ctx):
+    ks = synth.make_kind(2, 3, 10, seed=5)
+    d = binding.kind_to_device(ks)
+    with pytest.raises(binding.HMMError):   # 1-D Gaussian needs the variances
+        ctx.loglik_kind(2, d["delta"], d["Gamma"], d["e0"], None, d["obs"])
+    with pytest.raises(binding.HMMError):   # unknown kind
+        ctx.loglik_kind(3, d["delta"], d["Gamma"], d["e0"], d["e1"], d["obs"])
