@@ -20,6 +20,7 @@ Other workloads (one JSON line each, not the headline):
     python bench.py --workload k80_t4m    # K=80, T=4,194,304: FP32, BF16, FP16 operands
     python bench.py --workload batch256   # 256 sets, K in 8..64, T in 1e5..1e6, batched
     python bench.py --workload mcmc_k20   # the MCMC leg on its own
+    python bench.py --workload kinds_k25  # Poisson-count and 1-D Gaussian HMMs, K=25, T=1e6
 """
 import argparse
 import json
@@ -74,7 +75,8 @@ def measured_traffic():
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", default="k25_t1e6", choices=["k25_t1e6", "k80_t4m", "batch256", "mcmc_k20"])
+    ap.add_argument("--workload", default="k25_t1e6",
+                    choices=["k25_t1e6", "k80_t4m", "batch256", "mcmc_k20", "kinds_k25"])
     ap.add_argument("--no-mcmc", action="store_true", help="skip the MCMC leg of the default run")
     ap.add_argument("--mcmc-iterations", type=int, default=10000)
     ap.add_argument("--mcmc-chains", type=int, default=8)
@@ -104,6 +106,8 @@ def main():
         return bench_k80(args)
     if args.workload == "batch256":
         return bench_batch(args)
+    if args.workload == "kinds_k25":
+        return bench_kinds(args)
     if args.workload == "mcmc_k20":
         print(json.dumps(run_mcmc(C=args.mcmc_chains, n_iter=args.mcmc_iterations, lag=args.mcmc_lag,
                                   log=True)))
@@ -336,6 +340,53 @@ def bench_batch(args):
         "oracle_sample_seconds": round(c1 - c0, 2),
         "batched_vs_single_max_rel_diff": float(np.max(np.abs(res_b - res_s) / np.abs(res_s))),
     }))
+
+
+def bench_kinds(args):
+    """Other emission models through the same kernels: Poisson counts and a
+    1-D Gaussian, K=25, T=1e6 (synthetic, seeds 301 / 302): blocked FP32 vs the
+    plain forward recursion vs the FP64 oracle, and the segment kernel's
+    MFMA roofline (2*T*K^3 algorithmic flops)."""
+    import torch
+    from paper_2003_03508_amd import binding, synth
+    import oracle
+    oracle.build(force=False)
+    ctx = binding.Context(0)
+    K, T = 25, 1_000_000
+    res = {}
+    for kind, name, obs_bytes in ((1, "poisson", 4), (2, "gauss1d", 8)):
+        ks = synth.make_kind(kind, K, T, seed=300 + kind)
+        d = binding.kind_to_device(ks)
+        e1 = d["e1"] if kind == 2 else None
+        out = torch.empty(1, dtype=torch.float64, device="cuda")
+
+        def run(algo):
+            ctx.loglik_kind(kind, d["delta"], d["Gamma"], d["e0"], e1, d["obs"], algo=algo, out=out)
+        steps = max(20, args.steps // 2)
+        ctx.profile(True)
+        sec = _timed(lambda: run("blocked_f32"), steps, 3)
+        n, ms = ctx.profile_read()
+        ctx.profile(False)
+        ll = float(out.item())
+        sec_s = _timed(lambda: run("serial_f32"), 2, 1)
+        ll_s = float(out.item())
+        c0 = time.perf_counter()
+        want = oracle.loglik_kind(kind, ks.delta, ks.Gamma, ks.e0, ks.e1, ks.obs)
+        c1 = time.perf_counter()
+        kern = ms / max(n, 1) * 1e-3
+        flops = 2.0 * T * K ** 3
+        res[name] = {"evals_per_s": round(1.0 / sec, 2), "ms_per_eval": round(sec * 1e3, 4),
+                     "plain_forward_evals_per_s": round(1.0 / sec_s, 3),
+                     "speedup_vs_plain_forward": round(sec_s / sec, 1),
+                     "segment_kernel_ms": round(kern * 1e3, 4),
+                     "achieved_tflops": round(flops / kern / 1e12, 2), "peak_tflops": PEAK_FP32_MFMA_TFLOPS,
+                     "frac": round(flops / kern / 1e12 / PEAK_FP32_MFMA_TFLOPS, 4),
+                     "algorithmic_bytes": obs_bytes * T,
+                     "rel_err_blocked": abs(ll - want) / abs(want), "rel_err_serial": abs(ll_s - want) / abs(want),
+                     "oracle_evals_per_s_1_thread": round(1.0 / (c1 - c0), 3)}
+    ctx.close()
+    print(json.dumps({"workload": "kinds_k25: Poisson-count and 1-D Gaussian HMMs, K=25, T=1,000,000",
+                      "unit": "evals/s", "results": res}))
 
 
 def run_mcmc(C=8, burn_rounds=12, adapt_rounds=6, round_len=1000, n_iter=10000, lag=5, train_steps=500,

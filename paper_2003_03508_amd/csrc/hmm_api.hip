@@ -102,7 +102,7 @@ void launch_serial(int KP, hipStream_t st, int K, int64_t T, const double *delta
 }
 
 // Blocks of the Poisson log-factorial sum (partials live after the layout).
-constexpr int kFactBlocks = 256;
+constexpr int kFactBlocks = 1024;
 
 // ln L of eq. (2) for one set of any emission kind (arguments checked by the
 // caller except delta, Gamma, out and algo).
@@ -135,7 +135,7 @@ int loglik_impl(hmm_ctx *ctx, int kind, int32_t K, const double *delta, const do
             hipLaunchKernelGGL(k_log_factorials, dim3(kFactBlocks), dim3(256), 0, st, T, obs.cnt,
                                at<double>(ctx->ws, ly.total));
         if (kind == kEmisPoisson && T > 0)
-            hipLaunchKernelGGL(k_subtract_sum, dim3(1), dim3(64), 0, st, kFactBlocks, at<double>(ctx->ws, ly.total),
+            hipLaunchKernelGGL(k_subtract_sum, dim3(1), dim3(256), 0, st, kFactBlocks, at<double>(ctx->ws, ly.total),
                                out);
         return launch_status();
     }
@@ -167,7 +167,7 @@ int loglik_impl(hmm_ctx *ctx, int kind, int32_t K, const double *delta, const do
     if (kind == kEmisPoisson && T > 0) {
         hipLaunchKernelGGL(k_log_factorials, dim3(kFactBlocks), dim3(256), 0, st, T, obs.cnt,
                            at<double>(ctx->ws, ly.total));
-        hipLaunchKernelGGL(k_subtract_sum, dim3(1), dim3(64), 0, st, kFactBlocks, at<double>(ctx->ws, ly.total), out);
+        hipLaunchKernelGGL(k_subtract_sum, dim3(1), dim3(256), 0, st, kFactBlocks, at<double>(ctx->ws, ly.total), out);
     }
     return launch_status();
 }

@@ -172,9 +172,10 @@ static __global__ __launch_bounds__(256) void k_prepare_states(int K, int KP, co
 }
 
 // ---------------------------------------------------------------------------
-// Poisson counts: sum_t ln(y_t!) in FP64 in a fixed order (thread i of block
-// q sums t = q*256 + i + 256*nblk*j over j, the block adds its 256 partials
-// in order), then one thread subtracts the blocks' sums, in order, from ln L.
+// Poisson counts: sum_t ln(y_t!) in FP64 in a fixed order.  Thread i of
+// block q sums t = q*256 + i + 256*nblk*j over j, the block adds its 256
+// partials in order; then one workgroup adds the nblk block sums (each thread
+// a fixed run of them, then a fixed tree in LDS) and subtracts from ln L.
 // ---------------------------------------------------------------------------
 static __global__ __launch_bounds__(256) void k_log_factorials(int64_t T, const int32_t *__restrict__ cnt,
                                                         double *__restrict__ part)
@@ -194,12 +195,20 @@ static __global__ __launch_bounds__(256) void k_log_factorials(int64_t T, const 
     }
 }
 
-static __global__ void k_subtract_sum(int n, const double *__restrict__ part, double *__restrict__ out)
+static __global__ __launch_bounds__(256) void k_subtract_sum(int n, const double *__restrict__ part,
+                                                      double *__restrict__ out)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    __shared__ double red[256];
+    const int per = (n + 255) / 256;
     double s = 0.0;
-    for (int i = 0; i < n; ++i) s += part[i];
-    *out -= s;
+    for (int i = threadIdx.x * per; i < min(n, (int)(threadIdx.x + 1) * per); ++i) s += part[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out -= red[0];
 }
 
 // ---------------------------------------------------------------------------
