@@ -227,9 +227,9 @@ int hmm_ctx_profile_read(hmm_ctx *ctx, int64_t *launches, double *total_ms);
  * Box-Muller pairs (r cos 2 pi u1, r sin 2 pi u1), r = sqrt(-2 ln u0).
  * Purposes: 1 proposal normals (index = coordinate pair), 2 mixture choice,
  * 3 acceptance uniform, 4 training minibatch rows, 5 weight initialisation,
- * 6 held-out pairs of a training call.
+ * 6 held-out pairs of a training call, 7-9 the t-walk (below).
  * ------------------------------------------------------------------------ */
-typedef enum { MCMC_RANDOM_WALK = 0, MCMC_LEARNED = 1 } mcmc_proposal;
+typedef enum { MCMC_RANDOM_WALK = 0, MCMC_LEARNED = 1, MCMC_TWALK = 2 } mcmc_proposal;
 
 /* A sampler owns device memory, a private context whose batched plan its
  * iteration graphs replay, and one captured graph per proposal kind.  Like a
@@ -257,6 +257,13 @@ typedef struct {
     int32_t net_hidden;        /* width of both hidden layers (256)              */
     double *center, *in_scale, *out_scale; /* [D] network standardisation        */
     int32_t lag, trained;
+    double *theta2;            /* [C*D] t-walk: second point of every chain      */
+    double *loglik2, *logprior2; /* [C] of the second points                     */
+    long long *twalk_counts;   /* [C*8] t-walk: kernel k proposed [2k], accepted [2k+1] */
+    int32_t *twalk_code;       /* [C] last t-walk proposal: bit 0 moved, bit 1 x moved
+                                  (else x'), bits 2-3 kernel (0 traverse, 1 walk,
+                                  2 blow, 3 hop)                                  */
+    int32_t companion;         /* second points set                              */
 } mcmc_view;
 
 /* Create n_chains chains for a K-state model over the observations
@@ -290,6 +297,45 @@ int mcmc_set_rw_scale(mcmc_chains *chains, const double *rw_scale, void *stream)
  * The state after the iteration is written to the history ring.  Enqueued
  * on `stream`. */
 int mcmc_step(mcmc_chains *chains, int32_t n_iter, int32_t proposal, double eps, void *stream);
+
+/* The t-walk (Christen & Fox, "A general purpose sampling algorithm for
+ * continuous distributions (the t-walk)", Bayesian Analysis 2010), the
+ * general-purpose sampler that the paper runs over this posterior (section
+ * "GPUeR-hmmer"), as mcmc_step(..., MCMC_TWALK, ...).  Every chain holds two
+ * points x (theta) and x' (theta2).  Iteration t of chain c:
+ *   (uh, uk) = the uniform pair of purpose 7, index 0: x moves when uh < 1/2
+ *     (h = x, b = x'), else x' (h = x', b = x); uk picks the kernel
+ *     (traverse below p_traverse, walk below p_traverse + p_walk, blow below
+ *     p_traverse + p_walk + p_blow, else hop);
+ *   coordinate j is in the subset phi when u_j < min(D, n1) / D, u_j the
+ *     element j % 2 of the uniform pair of purpose 8, index j / 2;
+ *   on phi (elsewhere y = h):
+ *     traverse  y = b + beta (b - h); (v1, v2) the uniform pair of purpose 9,
+ *               index 0; beta = v2^(1/(a_t+1)) if v1 < (a_t-1)/(2 a_t), else
+ *               v2^(1/(1-a_t)); ln factor = (n_phi - 2) ln beta
+ *     walk      y = h + (h - b) z, z = a_w/(1+a_w) (-1 + 2v + a_w v^2), v the
+ *               uniforms of purpose 9 laid out as for phi; ln factor = 0
+ *     blow      y = b + s z, s = max_phi |h - b|
+ *     hop       y = h + s z, s = max_phi |h - b| / 3
+ *               z the Box-Muller normals of purpose 9 laid out as for phi;
+ *               ln factor = ln g(h | y) - ln g(y | h), g the product over phi
+ *               of the normal densities of the move (centre b for blow, the
+ *               moving point for hop; the scale from the starting point);
+ *               -inf when the reverse scale is 0
+ *   an empty phi (or s = 0) does not move; otherwise y is accepted into the
+ *   moving point when ln u < ln L(y) + ln prior(y) - ln L(h) - ln prior(h) +
+ *   ln factor, u the first uniform of purpose 3, index 0.
+ * The history ring records x.  One likelihood evaluation per chain and
+ * iteration, by the batched FP32 blocked path.
+ *   mcmc_set_companion  sets x' of every chain (theta2: device [C*D]) and
+ *                       evaluates ln L and the log prior there; needs
+ *                       mcmc_set_state first; required before MCMC_TWALK steps
+ *   mcmc_set_twalk      tuning: HOST double[6] = {p_traverse, p_walk, p_blow,
+ *                       a_t, a_w, n1}, hop taking the rest; probabilities >= 0
+ *                       summing to <= 1, a_t > 1, a_w > 0, n1 > 0.  The default
+ *                       is Christen & Fox's {0.4918, 0.4918, 0.0082, 6, 1.5, 4}. */
+int mcmc_set_companion(mcmc_chains *chains, const double *theta2, void *stream);
+int mcmc_set_twalk(mcmc_chains *chains, const double *tuning);
 
 int mcmc_view_get(mcmc_chains *chains, mcmc_view *view);
 
@@ -377,7 +423,8 @@ int hmm_philox(hmm_ctx *ctx, uint64_t seed, uint32_t purpose, uint32_t iter, uin
 /* Checkpoints of a sampler, for resuming a run: a host byte image of the
  * chain states (theta, ln L, log prior), the random-walk scale, acceptance
  * counts, the Philox seed and iteration counter, the history ring, the prior
- * box, the network with its standardisation, lag and Adam state.  A sampler
+ * box, the network with its standardisation, lag and Adam state, and the
+ * t-walk's second points, tuning and kernel counts.  A sampler
  * created for the same K, chain count, history length and observations that
  * loads the image continues bit for bit as the saved one would have (the
  * observations themselves are not part of the image).

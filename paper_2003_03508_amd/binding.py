@@ -73,6 +73,8 @@ _lib.mlp_set_weights.argtypes = [_vp, _vp, _vp, _vp, _vp, _i32, _vp]
 _lib.mcmc_checkpoint_size.argtypes = [_vp, ctypes.POINTER(_i64)]
 _lib.mcmc_checkpoint_save.argtypes = [_vp, _vp, _i64, _vp]
 _lib.mcmc_checkpoint_load.argtypes = [_vp, _vp, _i64, _vp]
+_lib.mcmc_set_companion.argtypes = [_vp, _vp, _vp]
+_lib.mcmc_set_twalk.argtypes = [_vp, _vp]
 
 
 class McmcView(ctypes.Structure):
@@ -84,7 +86,9 @@ class McmcView(ctypes.Structure):
                 ("accepts", _vp), ("history", _vp), ("history_logpost", _vp),
                 ("net_weights", _vp), ("net_count", _i64), ("net_hidden", _i32),
                 ("center", _vp), ("in_scale", _vp), ("out_scale", _vp),
-                ("lag", _i32), ("trained", _i32)]
+                ("lag", _i32), ("trained", _i32),
+                ("theta2", _vp), ("loglik2", _vp), ("logprior2", _vp), ("twalk_counts", _vp),
+                ("twalk_code", _vp), ("companion", _i32)]
 
 
 _lib.mcmc_view_get.argtypes = [_vp, ctypes.POINTER(McmcView)]
@@ -97,7 +101,7 @@ for _f in ("hmm_ctx_create", "hmm_ctx_destroy", "hmm_loglik", "hmm_emission",
            "mcmc_set_rw_scale", "mcmc_step", "mcmc_train_proposal", "mcmc_reset_proposal", "mcmc_view_get",
            "mlp_forward",
            "mlp_loss_grad", "mlp_set_weights", "mcmc_checkpoint_size", "mcmc_checkpoint_save",
-           "mcmc_checkpoint_load"):
+           "mcmc_checkpoint_load", "mcmc_set_companion", "mcmc_set_twalk"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 
@@ -302,6 +306,9 @@ class Context:
 
 MCMC_RANDOM_WALK = 0
 MCMC_LEARNED = 1
+MCMC_TWALK = 2
+# t-walk tuning {p_traverse, p_walk, p_blow, a_t, a_w, n1} (Christen & Fox's defaults)
+TWALK_DEFAULT = (0.4918, 0.4918, 0.0082, 6.0, 1.5, 4.0)
 
 
 class Chains:
@@ -388,6 +395,27 @@ class Chains:
         _check("mcmc_set_state", _lib.mcmc_set_state(self._h, _dev(theta, torch.float64, "theta", self.C * self.D),
                                                      _dev(rw_scale, torch.float64, "rw_scale", self.D),
                                                      _stream(stream)))
+
+    def set_companion(self, theta2, stream=None):
+        """Second t-walk point of every chain (device [C, D] float64)."""
+        theta2 = theta2.reshape(-1)
+        _check("mcmc_set_companion", _lib.mcmc_set_companion(
+            self._h, _dev(theta2, torch.float64, "theta2", self.C * self.D), _stream(stream)))
+
+    def set_twalk(self, tuning=TWALK_DEFAULT):
+        t = (ctypes.c_double * 6)(*[float(v) for v in tuning])
+        _check("mcmc_set_twalk", _lib.mcmc_set_twalk(self._h, t))
+
+    def twalk_state(self):
+        """dict of copies: theta2 [C, D], loglik2 [C], logprior2 [C], counts [C, 4, 2]
+        (proposed, accepted per kernel), code [C] of the last proposal."""
+        v = self.view()
+        return dict(theta2=self._tensor(v.theta2, (self.C, self.D), torch.float64),
+                    loglik2=self._tensor(v.loglik2, (self.C,), torch.float64),
+                    logprior2=self._tensor(v.logprior2, (self.C,), torch.float64),
+                    counts=self._tensor(v.twalk_counts, (self.C, 4, 2), torch.int64),
+                    code=self._tensor(v.twalk_code, (self.C,), torch.int32),
+                    companion=bool(v.companion))
 
     def set_rw_scale(self, rw_scale, stream=None):
         _check("mcmc_set_rw_scale", _lib.mcmc_set_rw_scale(

@@ -102,6 +102,9 @@ constexpr uint32_t kDrawAccept = 3;    // the MH uniform
 constexpr uint32_t kDrawMinibatch = 4; // training minibatch rows
 constexpr uint32_t kDrawInit = 5;      // weight initialisation
 constexpr uint32_t kDrawValidation = 6; // held-out pairs of a training call
+constexpr uint32_t kDrawTwalkChoice = 7;  // t-walk: which point and which kernel
+constexpr uint32_t kDrawTwalkSubset = 8;  // t-walk: coordinate subset
+constexpr uint32_t kDrawTwalkVariate = 9; // t-walk: the kernel's own variates
 
 // ---------------------------------------------------------------------------
 // theta -> packed likelihood block (delta | Gamma | p | mu | Sigma) and the
@@ -123,6 +126,19 @@ __device__ inline double block_sum(double v, double *scratch /* >= blockDim.x/64
     for (int i = 0; i < nw; ++i) s += scratch[i];
     __syncthreads();
     return s;
+}
+
+__device__ inline double block_max(double v, double *scratch /* >= blockDim.x/64 doubles */)
+{
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) scratch[w] = v;
+    __syncthreads();
+    double m = scratch[0];
+    for (int i = 1; i < nw; ++i) m = fmax(m, scratch[i]);
+    __syncthreads();
+    return m;
 }
 
 // Writes the block of one set and returns its log prior (same value on all

@@ -193,6 +193,195 @@ __global__ void k_advance(uint32_t *iter_dev)
     if (threadIdx.x == 0 && blockIdx.x == 0) *iter_dev += 1u;
 }
 
+// ---------------------------------------------------------------------------
+// The t-walk (Christen & Fox, Bayesian Analysis 2010), the general-purpose
+// sampler the paper runs over this posterior (section "GPUeR-hmmer").  Each
+// chain holds two points x, x'; an iteration moves one of them (h, the other
+// being b) on a random coordinate subset phi by one of four kernels:
+//   traverse  y = b + beta (b - h), beta ~ g_t(a_t)   factor beta^(n_phi - 2)
+//   walk      y = h + (h - b) z, z ~ g_w(a_w)          factor 1
+//   blow      y = b + s N(0, 1), s = max_phi |h - b|   Gaussian ratio
+//   hop       y = h + s N(0, 1), s = max_phi |h - b|/3 Gaussian ratio
+// and accepts when ln u < ln pi(y) - ln pi(h) + ln factor.
+// ---------------------------------------------------------------------------
+constexpr int kMaxDim = 80 * 80 + 4 * 80;   // theta_dim(80)
+constexpr int kTraverse = 0, kWalk = 1, kBlow = 2, kHop = 3;
+
+struct TwalkTuning {
+    double p_traverse, p_walk, p_blow, a_t, a_w, n1;   // hop: 1 - p_traverse - p_walk - p_blow
+};
+
+// code of a proposal: bit 0 moved, bit 1 the point x moved (else x'),
+// bits 2-3 the kernel
+__device__ inline int twalk_code(bool moved, bool move_x, int kind)
+{
+    return (moved ? 1 : 0) | (move_x ? 2 : 0) | (kind << 2);
+}
+
+// sum over phi of ln N(v_j; m_j, s^2), without the 2 pi constant
+__device__ inline double twalk_lognormal(int D, const uint8_t *phi, const double *v, const double *m, double s,
+                                         double nphi, double *scratch)
+{
+    double q = 0.0;
+    for (int d = threadIdx.x; d < D; d += blockDim.x)
+        if (phi[d]) {
+            const double e = v[d] - m[d];
+            q += e * e;
+        }
+    q = block_sum(q, scratch);
+    return -nphi * log(s) - q / (2.0 * s * s);
+}
+
+// Proposal of chain c = blockIdx.x at iteration *iter_dev: y into theta_p,
+// its likelihood block and log prior, the log Hastings factor (lq) and the
+// proposal code.  A move that cannot happen (empty subset, zero scale)
+// proposes y = h with code "not moved".
+__global__ __launch_bounds__(256) void k_twalk_propose(int K, uint64_t seed, const uint32_t *__restrict__ iter_dev,
+                                                       TwalkTuning tw, const double *__restrict__ x,
+                                                       const double *__restrict__ x2, double *__restrict__ theta_p,
+                                                       double *__restrict__ params_p, double *__restrict__ lp_p,
+                                                       double *__restrict__ lq, int32_t *__restrict__ code, PriorBox box)
+{
+    __shared__ double scratch[4];
+    __shared__ uint8_t phi[kMaxDim];
+    const int D = theta_dim(K), P = param_block(K);
+    const int c = blockIdx.x;
+    const uint32_t iter = *iter_dev;
+    double uh, uk;
+    philox_uniform2(seed, kDrawTwalkChoice, iter, c, 0, &uh, &uk);
+    const bool move_x = uh < 0.5;
+    const double *h = (move_x ? x : x2) + (int64_t)c * D;
+    const double *b = (move_x ? x2 : x) + (int64_t)c * D;
+    double *y = theta_p + (int64_t)c * D;
+    const int kind = uk < tw.p_traverse                          ? kTraverse
+                     : uk < tw.p_traverse + tw.p_walk             ? kWalk
+                     : uk < tw.p_traverse + tw.p_walk + tw.p_blow ? kBlow
+                                                                  : kHop;
+    // subset and, over it, the largest distance between the two points
+    const double pphi = fmin((double)D, tw.n1) / D;
+    int cnt = 0;
+    double far = 0.0;
+    for (int d2 = threadIdx.x; 2 * d2 < D; d2 += blockDim.x) {
+        double u[2];
+        philox_uniform2(seed, kDrawTwalkSubset, iter, c, d2, &u[0], &u[1]);
+        for (int e = 0; e < 2 && 2 * d2 + e < D; ++e) {
+            const int d = 2 * d2 + e;
+            const bool in = u[e] < pphi;
+            phi[d] = in ? 1 : 0;
+            cnt += in ? 1 : 0;
+            if (in) far = fmax(far, fabs(h[d] - b[d]));
+        }
+    }
+    const double nphi = block_sum((double)cnt, scratch);   // also orders the phi writes
+    far = block_max(far, scratch);
+    const double shrink = kind == kHop ? 1.0 / 3.0 : 1.0;
+    const double s_fwd = shrink * far;
+    bool moved = nphi > 0.0 && (kind == kTraverse || kind == kWalk || s_fwd > 0.0);
+    double factor = 0.0;
+    if (!moved) {
+        for (int d = threadIdx.x; d < D; d += blockDim.x) y[d] = h[d];
+    } else if (kind == kTraverse) {
+        double u1, u2;
+        philox_uniform2(seed, kDrawTwalkVariate, iter, c, 0, &u1, &u2);
+        const double beta = u1 < (tw.a_t - 1.0) / (2.0 * tw.a_t) ? pow(u2, 1.0 / (tw.a_t + 1.0))
+                                                                  : pow(u2, 1.0 / (1.0 - tw.a_t));
+        for (int d = threadIdx.x; d < D; d += blockDim.x) y[d] = phi[d] ? b[d] + beta * (b[d] - h[d]) : h[d];
+        factor = (nphi - 2.0) * log(beta);
+    } else {
+        const double cw = tw.a_w / (1.0 + tw.a_w);
+        for (int d2 = threadIdx.x; 2 * d2 < D; d2 += blockDim.x) {
+            double v[2];
+            if (kind == kWalk)
+                philox_uniform2(seed, kDrawTwalkVariate, iter, c, d2, &v[0], &v[1]);
+            else
+                philox_normal2(seed, kDrawTwalkVariate, iter, c, d2, &v[0], &v[1]);
+            for (int e = 0; e < 2 && 2 * d2 + e < D; ++e) {
+                const int d = 2 * d2 + e;
+                double val = h[d];
+                if (phi[d]) {
+                    if (kind == kWalk) {
+                        const double z = cw * (-1.0 + 2.0 * v[e] + tw.a_w * v[e] * v[e]);
+                        val = h[d] + (h[d] - b[d]) * z;
+                    } else {
+                        val = (kind == kBlow ? b[d] : h[d]) + s_fwd * v[e];
+                    }
+                }
+                y[d] = val;
+            }
+        }
+        if (kind != kWalk) {
+            __threadfence_block();
+            __syncthreads();   // y complete
+            double back = 0.0;
+            for (int d = threadIdx.x; d < D; d += blockDim.x)
+                if (phi[d]) back = fmax(back, fabs(y[d] - b[d]));
+            const double s_rev = shrink * block_max(back, scratch);
+            const double lg_fwd = twalk_lognormal(D, phi, y, kind == kBlow ? b : h, s_fwd, nphi, scratch);
+            const double lg_rev =
+                s_rev > 0.0 ? twalk_lognormal(D, phi, h, kind == kBlow ? b : y, s_rev, nphi, scratch) : -INFINITY;
+            factor = lg_rev - lg_fwd;
+        }
+    }
+    __threadfence_block();
+    __syncthreads();
+    const double lp = theta_to_block(K, y, params_p + (int64_t)c * P, box, scratch);
+    if (threadIdx.x == 0) {
+        lp_p[c] = lp;
+        lq[c] = factor;
+        code[c] = twalk_code(moved, move_x, kind);
+    }
+}
+
+// Accept / reject of chain c at iteration *iter_dev: the moved point takes y
+// when ln u < (ll' + lp') - (ll_h + lp_h) + ln factor (u of purpose 3; a NaN
+// ratio or an unmoved proposal is a rejection).  counts[c][2k] / [2k+1]:
+// proposals / acceptances of kernel k.  The history ring records x.
+__global__ __launch_bounds__(256) void k_twalk_accept(int K, uint64_t seed, const uint32_t *__restrict__ iter_dev,
+                                                      double *__restrict__ x, double *__restrict__ x2,
+                                                      double *__restrict__ ll, double *__restrict__ lp,
+                                                      double *__restrict__ ll2, double *__restrict__ lp2,
+                                                      const double *__restrict__ theta_p,
+                                                      const double *__restrict__ ll_p, const double *__restrict__ lp_p,
+                                                      const double *__restrict__ lq, const int32_t *__restrict__ code,
+                                                      long long *__restrict__ accepts, long long *__restrict__ counts,
+                                                      float *__restrict__ hist, double *__restrict__ hist_lpost,
+                                                      int64_t H, int C)
+{
+    __shared__ int acc_flag;
+    const int D = theta_dim(K);
+    const int c = blockIdx.x;
+    const uint32_t iter = *iter_dev;
+    const int64_t slot = (int64_t)iter % H;
+    const int cd = code[c];
+    const bool moved = cd & 1, move_x = (cd >> 1) & 1;
+    const int kind = cd >> 2;
+    if (threadIdx.x == 0) {
+        double *llh = move_x ? ll : ll2, *lph = move_x ? lp : lp2;
+        const double la = (ll_p[c] + lp_p[c]) - (llh[c] + lph[c]) + lq[c];
+        double u, unused;
+        philox_uniform2(seed, kDrawAccept, iter, c, 0, &u, &unused);
+        const int a = (moved && log(u) < la) ? 1 : 0;
+        acc_flag = a;
+        if (a) {
+            llh[c] = ll_p[c];
+            lph[c] = lp_p[c];
+            accepts[c] += 1;
+        }
+        if (moved) counts[(int64_t)c * 8 + 2 * kind] += 1;
+        counts[(int64_t)c * 8 + 2 * kind + 1] += a;
+        hist_lpost[slot * C + c] = ll[c] + lp[c];
+    }
+    __syncthreads();
+    const int a = acc_flag;
+    const double *yp = theta_p + (int64_t)c * D;
+    double *xc = x + (int64_t)c * D, *tgt = (move_x ? x : x2) + (int64_t)c * D;
+    for (int d = threadIdx.x; d < D; d += blockDim.x) {
+        if (a) tgt[d] = yp[d];
+        const double v = (a && move_x) ? yp[d] : xc[d];
+        hist[(slot * C + c) * (int64_t)D + d] = (float)v;
+    }
+}
+
 // Standardisation of the network and the least-squares start of its linear
 // part, from the history window [t0, t1) (ring of H iterations), one thread
 // per coordinate d:
@@ -447,6 +636,11 @@ struct mcmc_chains {
     double *theta = nullptr, *ll = nullptr, *lp = nullptr, *rw = nullptr;
     double *theta_p = nullptr, *params = nullptr, *ll_p = nullptr, *lp_p = nullptr, *lq = nullptr;
     long long *accepts = nullptr;
+    double *theta2 = nullptr, *ll2 = nullptr, *lp2 = nullptr;  // t-walk: the second point of every chain
+    int32_t *code = nullptr;                                   // t-walk: last proposal's code
+    long long *tw_counts = nullptr;                            // t-walk: [C][4 kernels][proposed, accepted]
+    TwalkTuning tw{0.4918, 0.4918, 0.0082, 6.0, 1.5, 4.0};
+    bool companion = false;    // the second points are set
     float *hist = nullptr;
     double *hist_lpost = nullptr;
     double *center = nullptr, *in_scale = nullptr, *out_scale = nullptr;
@@ -455,7 +649,7 @@ struct mcmc_chains {
     bool ready = false;        // state set: the likelihood plan exists
     uint32_t *iter_dev = nullptr;
     hipStream_t cap = nullptr; // capture stream of the iteration graphs
-    hipGraphExec_t exec[2] = {nullptr, nullptr};  // one MH iteration: random walk, learned
+    hipGraphExec_t exec[3] = {nullptr, nullptr, nullptr};  // one iteration: random walk, learned, t-walk
     double exec_eps = -1.0;
     Net net;
     Acts fwd, rev, train, val;
@@ -539,6 +733,20 @@ void forward_states(mcmc_chains *s, hipStream_t st, const double *theta, Acts &a
     net_forward(st, s->net, s->C, a.X, a.H1, a.H2, a.O);
 }
 
+// One t-walk iteration of every chain, enqueued on st (captured into a graph).
+int enqueue_twalk(mcmc_chains *s, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_twalk_propose, dim3(s->C), dim3(256), 0, st, s->K, s->seed, s->iter_dev, s->tw, s->theta,
+                       s->theta2, s->theta_p, s->params, s->lp_p, s->lq, s->code, s->box);
+    const int rc = loglik_all(s, st);
+    if (rc != HMM_OK) return rc;
+    hipLaunchKernelGGL(k_twalk_accept, dim3(s->C), dim3(256), 0, st, s->K, s->seed, s->iter_dev, s->theta, s->theta2,
+                       s->ll, s->lp, s->ll2, s->lp2, s->theta_p, s->ll_p, s->lp_p, s->lq, s->code, s->accepts,
+                       s->tw_counts, s->hist, s->hist_lpost, s->H, s->C);
+    hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, st, s->iter_dev);
+    return HMM_OK;
+}
+
 // One MH iteration of every chain, enqueued on st (captured into a graph).
 int enqueue_iteration(mcmc_chains *s, hipStream_t st, bool learned, double eps)
 {
@@ -558,7 +766,7 @@ int enqueue_iteration(mcmc_chains *s, hipStream_t st, bool learned, double eps)
 int build_graph(mcmc_chains *s, int mode, double eps)
 {
     if (hipStreamBeginCapture(s->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) return HMM_E_DEVICE;
-    const int rc = enqueue_iteration(s, s->cap, mode == 1, eps);
+    const int rc = mode == 2 ? enqueue_twalk(s, s->cap) : enqueue_iteration(s, s->cap, mode == 1, eps);
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(s->cap, &g);
     if (rc != HMM_OK || e != hipSuccess || !g) {
@@ -633,6 +841,11 @@ int mcmc_create(hmm_ctx *ctx, int32_t K, int32_t n_chains, int64_t T, const uint
     if (rc == HMM_OK) rc = dalloc(s, &s->in_scale, s->D);
     if (rc == HMM_OK) rc = dalloc(s, &s->out_scale, s->D);
     if (rc == HMM_OK) rc = dalloc(s, &s->iter_dev, 1);
+    if (rc == HMM_OK) rc = dalloc(s, &s->theta2, CD);
+    if (rc == HMM_OK) rc = dalloc(s, &s->ll2, s->C);
+    if (rc == HMM_OK) rc = dalloc(s, &s->lp2, s->C);
+    if (rc == HMM_OK) rc = dalloc(s, &s->code, s->C);
+    if (rc == HMM_OK) rc = dalloc(s, &s->tw_counts, (size_t)8 * s->C);
     if (rc == HMM_OK) rc = hmm_ctx_create(&s->own, ctx->device);
     if (rc == HMM_OK) {
         s->own->tuned_L = ctx->tuned_L;
@@ -655,6 +868,9 @@ int mcmc_create(hmm_ctx *ctx, int32_t K, int32_t n_chains, int64_t T, const uint
     bool ok = hipMemset(s->accepts, 0, sizeof(long long) * s->C) == hipSuccess;
     ok = ok && hipMemset(s->iter_dev, 0, sizeof(uint32_t)) == hipSuccess;
     ok = ok && hipMemset(s->theta, 0, sizeof(double) * CD) == hipSuccess;
+    ok = ok && hipMemset(s->theta2, 0, sizeof(double) * CD) == hipSuccess;
+    ok = ok && hipMemset(s->tw_counts, 0, sizeof(long long) * 8 * s->C) == hipSuccess;
+    ok = ok && hipMemset(s->code, 0, sizeof(int32_t) * s->C) == hipSuccess;
     ok = ok && hipMemset(s->hist_lpost, 0, sizeof(double) * s->H * s->C) == hipSuccess;
     ok = ok && hipMemset(n.w, 0, sizeof(float) * n.P) == hipSuccess;
     ok = ok && hipMemset(n.m, 0, sizeof(float) * n.P) == hipSuccess;
@@ -712,17 +928,54 @@ int mcmc_set_rw_scale(mcmc_chains *s, const double *rw_scale, void *stream)
                : HMM_E_DEVICE;
 }
 
+int mcmc_set_companion(mcmc_chains *s, const double *theta2, void *stream)
+{
+    if (!s || !theta2) return HMM_E_INVALID_ARG;
+    if (!s->ready) return HMM_E_INVALID_ARG;   // mcmc_set_state first
+    DeviceGuard dg(s->ctx->device);
+    if (!dg.ok) return HMM_E_DEVICE;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (hipMemcpyAsync(s->theta2, theta2, sizeof(double) * s->C * s->D, hipMemcpyDeviceToDevice, st) != hipSuccess)
+        return HMM_E_DEVICE;
+    hipLaunchKernelGGL(k_theta_to_params, dim3(s->C), dim3(256), 0, st, s->K, s->theta2, s->params, s->lp2, s->box);
+    const int rc = loglik_all(s, st);
+    if (rc != HMM_OK) return rc;
+    if (hipMemcpyAsync(s->ll2, s->ll_p, sizeof(double) * s->C, hipMemcpyDeviceToDevice, st) != hipSuccess)
+        return HMM_E_DEVICE;
+    s->companion = true;
+    return launch_status();
+}
+
+int mcmc_set_twalk(mcmc_chains *s, const double *tuning)
+{
+    if (!s || !tuning) return HMM_E_INVALID_ARG;
+    const TwalkTuning t{tuning[0], tuning[1], tuning[2], tuning[3], tuning[4], tuning[5]};
+    const double hop = 1.0 - (t.p_traverse + t.p_walk + t.p_blow);
+    if (!(t.p_traverse >= 0.0 && t.p_walk >= 0.0 && t.p_blow >= 0.0 && hop >= -1e-12 && t.a_t > 1.0 &&
+          t.a_w > 0.0 && t.n1 > 0.0 && std::isfinite(t.a_t) && std::isfinite(t.a_w) && std::isfinite(t.n1)))
+        return HMM_E_INVALID_ARG;
+    s->tw = t;
+    if (s->exec[2]) {
+        DeviceGuard dg(s->ctx->device);
+        (void)hipGraphExecDestroy(s->exec[2]);
+        s->exec[2] = nullptr;
+    }
+    return HMM_OK;
+}
+
 int mcmc_step(mcmc_chains *s, int32_t n_iter, int32_t proposal, double eps, void *stream)
 {
-    if (!s || n_iter < 0 || (proposal != MCMC_RANDOM_WALK && proposal != MCMC_LEARNED)) return HMM_E_INVALID_ARG;
+    if (!s || n_iter < 0 || (proposal != MCMC_RANDOM_WALK && proposal != MCMC_LEARNED && proposal != MCMC_TWALK))
+        return HMM_E_INVALID_ARG;
     const bool learned = proposal == MCMC_LEARNED;
     if (learned && (!s->trained || !(eps > 0.0 && eps < 1.0))) return HMM_E_INVALID_ARG;
     if (!s->ready) return HMM_E_INVALID_ARG;                                // mcmc_set_state first
+    if (proposal == MCMC_TWALK && !s->companion) return HMM_E_INVALID_ARG;  // mcmc_set_companion first
     if (s->iter + n_iter > (int64_t)UINT32_MAX) return HMM_E_INVALID_ARG;  // Philox iteration word
     DeviceGuard dg(s->ctx->device);
     if (!dg.ok) return HMM_E_DEVICE;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const int mode = learned ? 1 : 0;
+    const int mode = proposal == MCMC_TWALK ? 2 : learned ? 1 : 0;
     if (learned && s->exec[1] && eps != s->exec_eps) {
         (void)hipGraphExecDestroy(s->exec[1]);
         s->exec[1] = nullptr;
@@ -755,7 +1008,7 @@ int mcmc_step(mcmc_chains *s, int32_t n_iter, int32_t proposal, double eps, void
 namespace {
 
 constexpr uint64_t kCkptMagic = 0x544B43434D4D48ull;  // "HMMCCKT"
-constexpr int64_t kCkptVersion = 1;
+constexpr int64_t kCkptVersion = 2;
 
 struct CkptHeader {
     uint64_t magic;
@@ -763,6 +1016,8 @@ struct CkptHeader {
     uint64_t seed;
     int64_t iter, lag, trained, adam_steps;
     double box[4];
+    int64_t companion;   // t-walk second points set
+    double tw[6];        // t-walk tuning
 };
 
 // (device pointer, bytes) of every array a checkpoint holds, in image order.
@@ -775,7 +1030,9 @@ std::vector<std::pair<void *, size_t>> ckpt_arrays(mcmc_chains *s)
             {s->hist_lpost, 8 * (size_t)s->H * s->C},
             {s->center, 8 * (size_t)s->D}, {s->in_scale, 8 * (size_t)s->D},
             {s->out_scale, 8 * (size_t)s->D}, {s->net.w, 4 * n},
-            {s->net.m, 4 * n},            {s->net.v, 4 * n}};
+            {s->net.m, 4 * n},            {s->net.v, 4 * n},
+            {s->theta2, 8 * CD},          {s->ll2, 8 * (size_t)s->C},
+            {s->lp2, 8 * (size_t)s->C},   {s->tw_counts, 64 * (size_t)s->C}};
 }
 
 }  // namespace
@@ -800,7 +1057,8 @@ int mcmc_checkpoint_save(mcmc_chains *s, void *host, int64_t bytes, void *stream
     if (!dg.ok) return HMM_E_DEVICE;
     hipStream_t st = static_cast<hipStream_t>(stream);
     CkptHeader h{kCkptMagic, kCkptVersion, s->K, s->C, s->D, s->H, s->T, s->net.P, s->seed, s->iter, s->lag,
-                 s->trained ? 1 : 0, s->net.steps, {s->box.x0, s->box.x1, s->box.y0, s->box.y1}};
+                 s->trained ? 1 : 0, s->net.steps, {s->box.x0, s->box.x1, s->box.y0, s->box.y1},
+                 s->companion ? 1 : 0, {s->tw.p_traverse, s->tw.p_walk, s->tw.p_blow, s->tw.a_t, s->tw.a_w, s->tw.n1}};
     char *p = static_cast<char *>(host);
     std::memcpy(p, &h, sizeof(h));
     p += sizeof(h);
@@ -839,6 +1097,8 @@ int mcmc_checkpoint_load(mcmc_chains *s, const void *host, int64_t bytes, void *
     s->lag = (int)h.lag;
     s->trained = h.trained != 0;
     s->net.steps = (int)h.adam_steps;
+    s->companion = h.companion != 0;
+    s->tw = TwalkTuning{h.tw[0], h.tw[1], h.tw[2], h.tw[3], h.tw[4], h.tw[5]};
     // build the likelihood plan the iteration graphs replay (scratch outputs only)
     hipLaunchKernelGGL(k_theta_to_params, dim3(s->C), dim3(256), 0, st, s->K, s->theta, s->params, s->lp_p, s->box);
     const int rc = loglik_all(s, st);
@@ -873,6 +1133,12 @@ int mcmc_view_get(mcmc_chains *s, mcmc_view *v)
     v->out_scale = s->out_scale;
     v->lag = s->lag;
     v->trained = s->trained ? 1 : 0;
+    v->theta2 = s->theta2;
+    v->loglik2 = s->ll2;
+    v->logprior2 = s->lp2;
+    v->twalk_counts = s->tw_counts;
+    v->twalk_code = s->code;
+    v->companion = s->companion ? 1 : 0;
     return HMM_OK;
 }
 

@@ -45,6 +45,16 @@ def test_every_declared_symbol_is_exported(lib):
         assert hasattr(lib, name), name
 
 
+def test_binding_declares_every_entry_point():
+    """Every declared function has ctypes argument types in the binding (a
+    missing declaration would pass 64-bit pointers as C ints)."""
+    from paper_2003_03508_amd import binding
+    for name in declared_functions():
+        fn = getattr(binding._lib, name)
+        assert fn.argtypes is not None, name
+        assert fn.restype is not None, name
+
+
 def test_library_carries_gfx950_code_object():
     """The fat binary embedded in our own build targets gfx950 (and only gfx950)."""
     data = open(LIB, "rb").read()
@@ -116,6 +126,12 @@ def test_mcmc_host_argument_checks(lib):
     lib.hmm_philox.argtypes = [vp, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
                                ctypes.c_int64, ctypes.c_int32, vp, vp]
     assert lib.hmm_philox(None, 0, 1, 0, 0, 4, 0, 1, None) == -1
+    lib.mcmc_set_companion.argtypes = [vp, vp, vp]
+    assert lib.mcmc_set_companion(None, 1, None) == -1
+    lib.mcmc_set_twalk.argtypes = [vp, vp]
+    tw = (ctypes.c_double * 6)(0.4918, 0.4918, 0.0082, 6.0, 1.5, 4.0)
+    assert lib.mcmc_set_twalk(None, tw) == -1
+    assert lib.mcmc_step(None, 1, 2, 0.0, None) == -1
 
 
 def test_mcmc_view_layout_matches_binding(tmp_path):
