@@ -21,6 +21,7 @@ Other workloads (one JSON line each, not the headline):
     python bench.py --workload batch256   # 256 sets, K in 8..64, T in 1e5..1e6, batched
     python bench.py --workload mcmc_k20   # the MCMC leg on its own
     python bench.py --workload kinds_k25  # Poisson-count and 1-D Gaussian HMMs, K=25, T=1e6
+    python bench.py --workload twalk_k25  # the t-walk sampler, K=25, T=105,000
 """
 import argparse
 import json
@@ -76,7 +77,8 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--workload", default="k25_t1e6",
-                    choices=["k25_t1e6", "k80_t4m", "batch256", "mcmc_k20", "kinds_k25"])
+                    choices=["k25_t1e6", "k80_t4m", "batch256", "mcmc_k20", "kinds_k25", "twalk_k25"])
+    ap.add_argument("--twalk-chains", type=int, default=64)
     ap.add_argument("--no-mcmc", action="store_true", help="skip the MCMC leg of the default run")
     ap.add_argument("--mcmc-iterations", type=int, default=10000)
     ap.add_argument("--mcmc-chains", type=int, default=8)
@@ -108,6 +110,8 @@ def main():
         return bench_batch(args)
     if args.workload == "kinds_k25":
         return bench_kinds(args)
+    if args.workload == "twalk_k25":
+        return bench_twalk(args)
     if args.workload == "mcmc_k20":
         print(json.dumps(run_mcmc(C=args.mcmc_chains, n_iter=args.mcmc_iterations, lag=args.mcmc_lag,
                                   log=True)))
@@ -387,6 +391,82 @@ def bench_kinds(args):
     ctx.close()
     print(json.dumps({"workload": "kinds_k25: Poisson-count and 1-D Gaussian HMMs, K=25, T=1,000,000",
                       "unit": "evals/s", "results": res}))
+
+
+def bench_twalk(args):
+    """The t-walk over the posterior of a K=25 tremor HMM (D=725 parameters)
+    given T=105,000 observations (the size of the paper's Shikoku record;
+    synthetic, seed 6), one exact FP32 likelihood per chain and iteration.
+    Iterations/s of one chain (the paper's setting) and of many chains
+    batched; the iteration's algorithmic rate (chains * 2*T*K^3 flops per
+    iteration) against the FP32 MFMA peak; the FP64 oracle's t-walk on one
+    host thread."""
+    import numpy as np
+    import torch
+    from paper_2003_03508_amd import binding, synth
+    from paper_2003_03508_amd import mcmc as hm
+    import oracle
+    from oracle import twalk
+    oracle.build(force=False)
+    wl = synth.WORKLOADS["k25_t105k"]
+    K, T = wl["K"], wl["T"]
+    prm, obs = synth.make(**wl)
+    box = hm.box_of(obs.flag, obs.xy)
+    d = binding.to_device(prm, obs)
+    ctx = binding.Context(0)
+    D = hm.dim(K)
+    th0 = hm.theta_from_params(prm.Gamma, prm.p, prm.mu, prm.Sigma)
+    rng = np.random.default_rng(7)
+    f64 = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+    spread = 1e-3 * (np.abs(th0) + 1.0)
+    flops_eval = 2.0 * T * K ** 3
+    res = {}
+    for C, n_iter in ((1, max(500, args.steps * 5)), (args.twalk_chains, max(100, args.steps))):
+        ch = binding.Chains(ctx, K, C, d["flag"], d["xy"], box, seed=11, history=64)
+        ch.set_state(f64(th0 + spread * rng.standard_normal((C, D))), f64(np.full(D, 1e-3)))
+        ch.set_companion(f64(th0 + spread * rng.standard_normal((C, D))))
+        ch.step(max(20, args.warmup), proposal=binding.MCMC_TWALK)
+        a0 = ch.state()["accepts"].cpu().numpy().sum()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ch.step(n_iter, proposal=binding.MCMC_TWALK)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        st, tw = ch.state(), ch.twalk_state()
+        counts = tw["counts"].cpu().numpy().sum(axis=0)
+        it_s = n_iter / dt
+        tfl = C * flops_eval * it_s / 1e12
+        res[f"chains_{C}"] = {
+            "chains": C, "iterations": n_iter, "seconds": round(dt, 3),
+            "iterations_per_s_per_chain": round(it_s, 2), "chain_iterations_per_s": round(C * it_s, 1),
+            "ms_per_iteration": round(dt / n_iter * 1e3, 4),
+            "acceptance": round(float(st["accepts"].cpu().numpy().sum() - a0) / (C * n_iter), 4),
+            "kernel_counts": {n: [int(counts[k, 0]), int(counts[k, 1])] for k, n in enumerate(twalk.NAMES)},
+            "iteration_tflops": round(tfl, 2), "frac_fp32_mfma_peak": round(tfl / PEAK_FP32_MFMA_TFLOPS, 4)}
+        ch.close()
+    ctx.close()
+    # the oracle's t-walk on one host thread (FP64 C likelihood), ~cpu_seconds
+    f = twalk.hmm_logpost(K, obs.flag, obs.xy, box)
+    x, xp = th0 + spread * rng.standard_normal(D), th0 + spread * rng.standard_normal(D)
+    lx, lxp = f(x), f(xp)
+    n = 0
+    c0 = time.perf_counter()
+    while time.perf_counter() - c0 < args.cpu_seconds:
+        x, xp, lx, lxp, _ = twalk.step(x, xp, lx, lxp, f, twalk.philox_draws(11, n, 0, D))
+        n += 1
+    c1 = time.perf_counter()
+    one = res["chains_1"]["iterations_per_s_per_chain"]
+    print(json.dumps({
+        "workload": "twalk_k25: t-walk over all D=725 parameters of a K=25 tremor HMM given "
+                    "T=105,000 synthetic observations (seed 6)",
+        "unit": "iterations/s", "value_one_chain": one,
+        "value_many_chains": res[f"chains_{args.twalk_chains}"]["chain_iterations_per_s"],
+        "results": res,
+        "cpu_baseline": {"value": round(n / (c1 - c0), 3), "unit": "iterations/s", "cores": 1, "kind": "oracle",
+                         "sample": f"{n} t-walk iterations of one chain, FP64 C likelihood, {c1 - c0:.1f} s"},
+        "paper_context": "one chain of 1e6 iterations took about 4 h on a GTX 1080 Ti (about 69 iterations/s, "
+                         "105,000 observations, K up to 30)",
+    }))
 
 
 def run_mcmc(C=8, burn_rounds=12, adapt_rounds=6, round_len=1000, n_iter=10000, lag=5, train_steps=500,

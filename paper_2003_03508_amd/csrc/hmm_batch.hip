@@ -73,8 +73,9 @@ namespace {
 // Segment length of a class.  Workgroups run one per CU, in rounds of 256;
 // a round costs about L steps plus a fixed per-workgroup part (emission
 // setup, the in-workgroup tree) worth kWgOverhead steps.  The length
-// minimises rounds(L) * (L + kWgOverhead) over 128..4096, so that the last
-// round is not left mostly empty.  A tuned value wins.
+// minimises rounds(L) * (L + kWgOverhead) over 32..4096, so that the last
+// round is not left mostly empty (and a set too short to fill the chip in one
+// round at a longer length is cut finer).  A tuned value wins.
 constexpr int kWgOverhead = 32;
 
 int64_t class_L(const hmm_ctx *ctx, const BatchPlan &bp, const BatchClass &c, int algo, int W)
@@ -84,9 +85,9 @@ int64_t class_L(const hmm_ctx *ctx, const BatchPlan &bp, const BatchClass &c, in
         if (it != ctx->tuned_L.end() && it->second > 0) return it->second;
     }
     if (ctx->block_len > 0) return ctx->block_len;
-    int64_t best = 128;
+    int64_t best = 32;
     double best_cost = -1.0;
-    for (int64_t L = 128; L <= 4096; ++L) {
+    for (int64_t L = 32; L <= 4096; ++L) {
         int64_t wgs = 0;
         for (int s : c.sets) {
             const int64_t nseg = (bp.T[s] + L - 1) / L;

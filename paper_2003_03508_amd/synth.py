@@ -224,6 +224,7 @@ WORKLOADS = {
     "k25_t1e6": dict(K=25, T=1_000_000, seed=1),
     "k80_t4m": dict(K=80, T=4_194_304, seed=2),
     "k20_t5e5": dict(K=20, T=500_000, seed=4),
+    "k25_t105k": dict(K=25, T=105_000, seed=6),   # the size of the paper's Shikoku record
 }
 
 
