@@ -14,6 +14,9 @@ Contents
   * ``brute.py``    -- enumeration of every hidden path in exact rationals.
   * ``loglik_kind`` -- eq. (2) with Poisson-count or 1-D Gaussian emissions
     (other HMMs differ from the tremor model only in the emission function).
+  * ``posterior`` / ``viterbi`` -- state posteriors by forward-backward (with
+    expected transition counts and weighted moments) and the most likely path.
+  * ``grad_from_stats`` -- the gradient of ln L from those expectations.
 """
 import ctypes
 import os
@@ -65,6 +68,10 @@ def lib():
         L.oracle_loglik_kind.restype = ctypes.c_double
         L.oracle_loglik_kind.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, dp, dp, ctypes.c_int64,
                                          ctypes.c_void_p]
+        L.oracle_posterior.restype = ctypes.c_double
+        L.oracle_posterior.argtypes = [ctypes.c_int, dp, dp, dp, dp, dp, ctypes.c_int64, u8p, dp, dp, dp, dp, dp]
+        L.oracle_viterbi.restype = ctypes.c_double
+        L.oracle_viterbi.argtypes = [ctypes.c_int, dp, dp, dp, dp, dp, ctypes.c_int64, u8p, dp, i32p, i32p]
         L.oracle_loglik_batch.restype = ctypes.c_int
         L.oracle_loglik_batch.argtypes = [ctypes.c_int32, i32p, i64p, i64p, dp, i64p, u8p, dp, dp,
                                           ctypes.c_int32]
@@ -181,3 +188,81 @@ def loglik_kind(kind, delta, Gamma, e0, e1, obs):
     Gamma, gp = _f64(Gamma)
     e0, p0, e1, p1, obs = _kind_args(kind, e0, e1, obs)
     return lib().oracle_loglik_kind(kind, delta.shape[0], dp_, gp, p0, p1, obs.shape[0], obs.ctypes.data)
+
+
+def posterior(delta, Gamma, p, mu, Sigma, flag, xy):
+    """State posteriors by the scaled forward-backward recursions (FP64).
+
+    Returns dict: loglik, gamma (T, K) = P(s_t = k | x), xi (K, K) = expected
+    transition counts summed over t = 0..T-1 (t = 0 from the state s_-1 before
+    x_0), pre (K,) = P(s_-1 = k | x), mom (K, 7) = per state sum gamma, then
+    over tremor steps sum gamma, gamma x, gamma y, gamma x^2, gamma x y, gamma y^2."""
+    delta, dp_ = _f64(delta)
+    Gamma, gp = _f64(Gamma)
+    p, pp = _f64(p)
+    mu, mup = _f64(mu)
+    Sigma, sp = _f64(Sigma)
+    flag, fp = _u8(flag)
+    xy, xp = _f64(np.asarray(xy).reshape(-1, 2))
+    K, T = delta.shape[0], flag.shape[0]
+    gamma = np.empty((max(T, 1), K))
+    xi = np.empty((K, K))
+    pre = np.empty(K)
+    mom = np.empty((K, 7))
+    P = ctypes.POINTER(ctypes.c_double)
+    ll = lib().oracle_posterior(K, dp_, gp, pp, mup, sp, T, fp, xp, gamma.ctypes.data_as(P),
+                                xi.ctypes.data_as(P), pre.ctypes.data_as(P), mom.ctypes.data_as(P))
+    return dict(loglik=ll, gamma=gamma[:T], xi=xi, pre=pre, mom=mom)
+
+
+def viterbi(delta, Gamma, p, mu, Sigma, flag, xy):
+    """Most likely hidden path: (score = max ln P(path, x), path int32 (T,), s_-1)."""
+    delta, dp_ = _f64(delta)
+    Gamma, gp = _f64(Gamma)
+    p, pp = _f64(p)
+    mu, mup = _f64(mu)
+    Sigma, sp = _f64(Sigma)
+    flag, fp = _u8(flag)
+    xy, xp = _f64(np.asarray(xy).reshape(-1, 2))
+    K, T = delta.shape[0], flag.shape[0]
+    path = np.empty(max(T, 1), dtype=np.int32)
+    first = ctypes.c_int32()
+    score = lib().oracle_viterbi(K, dp_, gp, pp, mup, sp, T, fp, xp,
+                                 path.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), ctypes.byref(first))
+    return score, path[:T], first.value
+
+
+def grad_from_stats(delta, Gamma, p, mu, Sigma, xi, pre, mom):
+    """Gradient of ln L with respect to (delta, Gamma, p, mu, Sigma), every entry
+    a free variable (Sigma as its three entries Sxx, Sxy, Syy), from the
+    posterior expectations (Fisher's identity: grad ln L = E[grad ln P(s, x) | x]):
+      d/d delta_i    = pre_i / delta_i
+      d/d Gamma_ij   = xi_ij / Gamma_ij
+      d/d p_k        = n1_k / p_k - (n_k - n1_k) / (1 - p_k)
+      d/d mu_k       = Sigma_k^-1 (s_k - n1_k mu_k)
+      d/d Sigma_k    = G = (1/2) Sigma^-1 (C_k - n1_k Sigma) Sigma^-1 as a matrix,
+                       C_k = sum gamma f (x - mu)(x - mu)^T; Sxy enters twice: 2 G_xy
+    with n_k = sum gamma, n1_k = sum over tremor steps, s_k = sum gamma f x."""
+    delta = np.asarray(delta, dtype=np.float64)
+    Gamma = np.asarray(Gamma, dtype=np.float64)
+    p = np.asarray(p, dtype=np.float64)
+    mu = np.asarray(mu, dtype=np.float64).reshape(-1, 2)
+    Sigma = np.asarray(Sigma, dtype=np.float64).reshape(-1, 3)
+    K = delta.shape[0]
+    g_delta = pre / delta
+    g_Gamma = xi / Gamma
+    n, n1 = mom[:, 0], mom[:, 1]
+    g_p = n1 / p - (n - n1) / (1.0 - p)
+    g_mu = np.empty((K, 2))
+    g_S = np.empty((K, 3))
+    for k in range(K):
+        S = np.array([[Sigma[k, 0], Sigma[k, 1]], [Sigma[k, 1], Sigma[k, 2]]])
+        Si = np.linalg.inv(S)
+        s = mom[k, 2:4]
+        m = mu[k]
+        g_mu[k] = Si @ (s - n1[k] * m)
+        M2 = np.array([[mom[k, 4], mom[k, 5]], [mom[k, 5], mom[k, 6]]])
+        C = M2 - np.outer(s, m) - np.outer(m, s) + n1[k] * np.outer(m, m)
+        G = 0.5 * Si @ (C - n1[k] * S) @ Si
+        g_S[k] = (G[0, 0], 2.0 * G[0, 1], G[1, 1])
+    return dict(delta=g_delta, Gamma=g_Gamma, p=g_p, mu=g_mu, Sigma=g_S)

@@ -335,3 +335,174 @@ int oracle_loglik_batch(int32_t n, const int32_t *K, const int64_t *T, const int
     for (int32_t i = 0; i < nthreads; ++i) pthread_join(th[i], NULL);
     return 0;
 }
+
+/* State posteriors of eq. (2)'s model by the scaled forward-backward
+ * recursions (the reverse-mode counterpart of Algorithm 1), FP64.
+ * With s_{-1} ~ delta the state before x_0 and e^_{t,k} = exp(ln e_{t,k} - m_t):
+ *   forward   u_{-1} = delta;  a_t = u_{t-1} Gamma;  b_t = a_t o e^_t;
+ *             c_t = sum_k b_t,k;  u_t = b_t / c_t  (stored for every t)
+ *   backward  v_{T-1} = 1;  v_{t-1,i} = sum_j Gamma_ij e^_t,j v_t,j / c_t
+ * so that sum_k u_t,k v_t,k = 1 and
+ *   gamma_t,k = P(s_t = k | x)              = u_t,k v_t,k
+ *   xi_t(i,j) = P(s_{t-1} = i, s_t = j | x) = u_{t-1,i} Gamma_ij e^_t,j v_t,j / c_t
+ * Outputs: gamma[T*K]; xi[K*K] = sum over t = 0..T-1 of xi_t (t = 0 is the
+ * step from s_{-1}); pre[K] = P(s_{-1} = i | x) = sum_j xi_0(i,j);
+ * mom[K*7] per state k: sum_t gamma_t,k, then over tremor steps (flag 1)
+ * sum gamma, sum gamma x, sum gamma y, sum gamma x^2, sum gamma x y,
+ * sum gamma y^2.  Returns ln L (the forward pass's sum of ln c_t + m_t).
+ * Invalid inputs give NaN, L = 0 gives -inf; the outputs are then NaN.
+ * Summations run over ascending indices (xi and the moments over ascending
+ * t within the backward pass, i.e. descending t). */
+double oracle_posterior(int K, const double *delta, const double *Gamma, const double *p,
+                        const double *mu, const double *Sigma, int64_t T, const uint8_t *flag,
+                        const double *xy, double *gamma, double *xi, double *pre, double *mom)
+{
+    const size_t KK = (size_t)K * K, TK = (size_t)(T > 0 ? T : 1) * K;
+    for (size_t i = 0; i < KK; ++i) xi[i] = 0.0;
+    for (int k = 0; k < K; ++k) pre[k] = 0.0;
+    for (int i = 0; i < 7 * K; ++i) mom[i] = 0.0;
+    if (!oracle_params_valid(K, delta, Gamma, p, mu, Sigma) || T < 0) goto invalid;
+    {
+        double *logE = (double *)malloc(sizeof(double) * TK);
+        double *c = (double *)malloc(sizeof(double) * (T > 0 ? T : 1));
+        double *m = (double *)malloc(sizeof(double) * (T > 0 ? T : 1));
+        double *v = (double *)malloc(sizeof(double) * K);
+        double *w = (double *)malloc(sizeof(double) * K);
+        double ll = 0.0;
+        if (oracle_log_emission(K, p, mu, Sigma, T, flag, xy, logE) != 0) {
+            free(logE); free(c); free(m); free(v); free(w);
+            goto invalid;
+        }
+        if (T == 0) {
+            double s = 0.0;
+            for (int k = 0; k < K; ++k) s += delta[k];
+            for (int k = 0; k < K; ++k) pre[k] = delta[k] / s;
+            free(logE); free(c); free(m); free(v); free(w);
+            return log(s);
+        }
+        /* forward: gamma holds u_t */
+        for (int64_t t = 0; t < T; ++t) {
+            const double *u = t == 0 ? delta : gamma + (size_t)(t - 1) * K;
+            double *ut = gamma + (size_t)t * K;
+            const double *le = logE + (size_t)t * K;
+            double mt = -INFINITY;
+            for (int k = 0; k < K; ++k) if (le[k] > mt) mt = le[k];
+            if (mt == -INFINITY) ll = -INFINITY;
+            if (!isfinite(ll)) break;
+            double ct = 0.0;
+            for (int j = 0; j < K; ++j) {
+                double a = 0.0;
+                for (int i = 0; i < K; ++i) a += u[i] * Gamma[(size_t)i * K + j];
+                ut[j] = a * exp(le[j] - mt);
+                ct += ut[j];
+            }
+            if (ct == 0.0) { ll = -INFINITY; break; }
+            for (int j = 0; j < K; ++j) ut[j] /= ct;
+            c[t] = ct;
+            m[t] = mt;
+            ll += log(ct) + mt;
+        }
+        if (!isfinite(ll)) {
+            free(logE); free(c); free(m); free(v); free(w);
+            for (size_t i = 0; i < TK; ++i) gamma[i] = NAN;
+            for (size_t i = 0; i < KK; ++i) xi[i] = NAN;
+            for (int k = 0; k < K; ++k) pre[k] = NAN;
+            for (int i = 0; i < 7 * K; ++i) mom[i] = NAN;
+            return ll;
+        }
+        /* backward: v = v_t; gamma_t = u_t o v_t overwrites u_t once u_t is used */
+        for (int k = 0; k < K; ++k) v[k] = 1.0;
+        for (int64_t t = T - 1; t >= 0; --t) {
+            const double *le = logE + (size_t)t * K;
+            const double *uprev = t == 0 ? delta : gamma + (size_t)(t - 1) * K;
+            double *gt = gamma + (size_t)t * K;
+            /* w_j = e^_t,j v_t,j / c_t */
+            for (int j = 0; j < K; ++j) w[j] = exp(le[j] - m[t]) * v[j] / c[t];
+            for (int i = 0; i < K; ++i)
+                for (int j = 0; j < K; ++j) {
+                    const double x = uprev[i] * Gamma[(size_t)i * K + j] * w[j];
+                    xi[(size_t)i * K + j] += x;
+                    if (t == 0) pre[i] += x;
+                }
+            for (int k = 0; k < K; ++k) {
+                const double g = gt[k] * v[k];
+                gt[k] = g;
+                mom[7 * k] += g;
+                if (flag[t] == 1) {
+                    const double x = xy[2 * t], y = xy[2 * t + 1];
+                    mom[7 * k + 1] += g;
+                    mom[7 * k + 2] += g * x;
+                    mom[7 * k + 3] += g * y;
+                    mom[7 * k + 4] += g * x * x;
+                    mom[7 * k + 5] += g * x * y;
+                    mom[7 * k + 6] += g * y * y;
+                }
+            }
+            /* v_{t-1,i} = sum_j Gamma_ij w_j */
+            for (int i = 0; i < K; ++i) {
+                double s = 0.0;
+                for (int j = 0; j < K; ++j) s += Gamma[(size_t)i * K + j] * w[j];
+                v[i] = s;
+            }
+        }
+        free(logE); free(c); free(m); free(v); free(w);
+        return ll;
+    }
+invalid:
+    for (size_t i = 0; i < TK; ++i) gamma[i] = NAN;
+    for (size_t i = 0; i < KK; ++i) xi[i] = NAN;
+    for (int k = 0; k < K; ++k) pre[k] = NAN;
+    for (int i = 0; i < 7 * K; ++i) mom[i] = NAN;
+    return NAN;
+}
+
+/* Most likely hidden path (Viterbi) of eq. (2)'s model, in the log domain:
+ *   V_{-1,i} = ln delta_i
+ *   V_t,j = max_i (V_{t-1,i} + ln Gamma_ij) + ln e_t,j,  psi_t,j = its argmax
+ * (the smallest i on ties), s_{T-1} = argmax_j V_{T-1,j} (smallest j on ties),
+ * s_{t-1} = psi_t,s_t.  path[t] = s_t for t = 0..T-1, *first = s_{-1}.
+ * Returns max over paths of ln(delta_s-1 prod_t Gamma e) (ln 0 = -inf), NaN
+ * on invalid input (the path is then -1 everywhere). */
+double oracle_viterbi(int K, const double *delta, const double *Gamma, const double *p,
+                      const double *mu, const double *Sigma, int64_t T, const uint8_t *flag,
+                      const double *xy, int32_t *path, int32_t *first)
+{
+    const size_t TK = (size_t)(T > 0 ? T : 1) * K;
+    for (int64_t t = 0; t < T; ++t) path[t] = -1;
+    *first = -1;
+    if (!oracle_params_valid(K, delta, Gamma, p, mu, Sigma) || T < 0) return NAN;
+    double *logE = (double *)malloc(sizeof(double) * TK);
+    int32_t *psi = (int32_t *)malloc(sizeof(int32_t) * (TK + K));
+    double *V = (double *)malloc(sizeof(double) * K);
+    double *Vn = (double *)malloc(sizeof(double) * K);
+    if (oracle_log_emission(K, p, mu, Sigma, T, flag, xy, logE) != 0) {
+        free(logE); free(psi); free(V); free(Vn);
+        return NAN;
+    }
+    for (int i = 0; i < K; ++i) V[i] = log(delta[i]);
+    for (int64_t t = 0; t < T; ++t) {
+        for (int j = 0; j < K; ++j) {
+            double best = -INFINITY;
+            int arg = 0;
+            for (int i = 0; i < K; ++i) {
+                const double s = V[i] + log(Gamma[(size_t)i * K + j]);
+                if (s > best) { best = s; arg = i; }
+            }
+            Vn[j] = best + logE[(size_t)t * K + j];
+            psi[(size_t)t * K + j] = arg;
+        }
+        for (int j = 0; j < K; ++j) V[j] = Vn[j];
+    }
+    double best = -INFINITY;
+    int arg = 0;
+    for (int j = 0; j < K; ++j) if (V[j] > best) { best = V[j]; arg = j; }
+    if (T == 0) {
+        *first = arg;
+    } else {
+        path[T - 1] = arg;
+        for (int64_t t = T - 1; t > 0; --t) path[t - 1] = psi[(size_t)t * K + path[t]];
+        *first = psi[path[0]];
+    }
+    free(logE); free(psi); free(V); free(Vn);
+    return best;
+}
