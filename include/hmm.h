@@ -414,6 +414,47 @@ int mlp_set_weights(mcmc_chains *chains, const float *weights, const double *cen
 int hmm_theta_to_params(hmm_ctx *ctx, int32_t K, int32_t n, const double *theta,
                         const double *box, double *params, double *logprior, void *stream);
 
+/* ------------------------------------------------------------------------
+ * State posteriors and the gradient of ln L (forward-backward) for the tremor
+ * model of eq. (1)-(2), with s_{-1} ~ delta the state before x_0 as in eq. (2).
+ * Computed around the same segment products as the blocked likelihood
+ * (section "The likelihood algorithm"): the products give the forward and
+ * backward messages at segment boundaries, then every segment reruns the
+ * forward and backward recursions over its own observations (FP32 within a
+ * segment, FP64 at the boundaries and in all sums).  1 <= K <= 64.
+ *
+ * hmm_posterior: device outputs
+ *   gamma  float [T*K]: gamma[t*K + k] = P(s_t = k | x_0..x_{T-1})
+ *          (required when T > 0; also used as scratch during the call)
+ *   stats  double [K*K + K + 7K] (may be NULL):
+ *          [0, K*K)     xi[i*K + j] = sum_{t=0..T-1} P(s_{t-1} = i, s_t = j | x)
+ *                       (t = 0 is the step from s_{-1})
+ *          [K*K, +K)    P(s_{-1} = i | x)
+ *          [.., +7K)    per state k: sum_t gamma_t,k, then over tremor steps
+ *                       (flag 1) sum gamma, gamma x, gamma y, gamma x^2,
+ *                       gamma x y, gamma y^2 (x, y in km)
+ *   loglik double [1]: ln L (the same value as hmm_loglik, blocked FP32)
+ * T = 0: stats hold xi = 0, P(s_{-1}) = delta / sum delta, moments 0.
+ * Invalid parameters or data: ln L and stats are NaN, gamma rows NaN.  When
+ * L = 0 (ln L = -inf) the other outputs are NaN or meaningless.
+ *
+ * hmm_loglik_grad: ln L and its gradient with every parameter entry treated
+ *   as a free variable (no row-sum constraint on Gamma or delta), from the
+ *   same expectations (Fisher's identity), device double grad[K + K*K + K +
+ *   2K + 3K] = [d/d delta | d/d Gamma (row-major) | d/d p | d/d mu (x, y per
+ *   state) | d/d Sigma (xx, xy, yy per state; Sxy as one variable that
+ *   enters both off-diagonal positions)].  Needs T*K floats of workspace.
+ * Both enqueue on `stream`; HMM_E_UNSUPPORTED for K > 64.
+ * ------------------------------------------------------------------------ */
+int hmm_posterior(hmm_ctx *ctx, int32_t K, const double *delta, const double *Gamma,
+                  const double *p, const double *mu, const double *Sigma, int64_t T,
+                  const uint8_t *flag, const double *xy, void *stream, float *gamma,
+                  double *stats, double *loglik);
+int hmm_loglik_grad(hmm_ctx *ctx, int32_t K, const double *delta, const double *Gamma,
+                    const double *p, const double *mu, const double *Sigma, int64_t T,
+                    const uint8_t *flag, const double *xy, void *stream, double *loglik,
+                    double *grad);
+
 /* Philox draws of the sampler's streams: for i < n, out[2i], out[2i+1] are
  * the two uniforms (normal = 0) or Box-Muller normals (normal = 1) of counter
  * (i, chain, iter, purpose).  out: device double[2n] (may be NULL when n = 0). */

@@ -74,6 +74,8 @@ _lib.mcmc_checkpoint_size.argtypes = [_vp, ctypes.POINTER(_i64)]
 _lib.mcmc_checkpoint_save.argtypes = [_vp, _vp, _i64, _vp]
 _lib.mcmc_checkpoint_load.argtypes = [_vp, _vp, _i64, _vp]
 _lib.mcmc_set_companion.argtypes = [_vp, _vp, _vp]
+_lib.hmm_posterior.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp]
+_lib.hmm_loglik_grad.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp]
 _lib.mcmc_set_twalk.argtypes = [_vp, _vp]
 
 
@@ -101,7 +103,8 @@ for _f in ("hmm_ctx_create", "hmm_ctx_destroy", "hmm_loglik", "hmm_emission",
            "mcmc_set_rw_scale", "mcmc_step", "mcmc_train_proposal", "mcmc_reset_proposal", "mcmc_view_get",
            "mlp_forward",
            "mlp_loss_grad", "mlp_set_weights", "mcmc_checkpoint_size", "mcmc_checkpoint_save",
-           "mcmc_checkpoint_load", "mcmc_set_companion", "mcmc_set_twalk"):
+           "mcmc_checkpoint_load", "mcmc_set_companion", "mcmc_set_twalk", "hmm_posterior",
+           "hmm_loglik_grad"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 
@@ -211,6 +214,44 @@ class Context:
                                   _dev(obs, obs_t, "obs", T), a, _stream(stream), _dev(out, torch.float64, "out", 1))
         _check("hmm_loglik_kind", rc)
         return out
+
+    def _params(self, delta, Gamma, p, mu, Sigma, flag, xy):
+        K = int(delta.numel())
+        T = int(flag.numel())
+        return K, T, (_dev(delta, torch.float64, "delta", K), _dev(Gamma, torch.float64, "Gamma", K * K),
+                      _dev(p, torch.float64, "p", K), _dev(mu, torch.float64, "mu", 2 * K),
+                      _dev(Sigma, torch.float64, "Sigma", 3 * K), T,
+                      _dev(flag, torch.uint8, "flag", T), _dev(xy, torch.float64, "xy", 2 * T))
+
+    def posterior(self, delta, Gamma, p, mu, Sigma, flag, xy, stats=True, stream=None):
+        """State posteriors: dict gamma (T, K) float32, loglik (1,) float64 and, with
+        stats, xi (K, K), pre (K,), mom (K, 7) float64 (device tensors)."""
+        K, T, args = self._params(delta, Gamma, p, mu, Sigma, flag, xy)
+        dev = delta.device
+        gamma = torch.empty((T, K), dtype=torch.float32, device=dev)
+        st = torch.empty(K * K + 8 * K, dtype=torch.float64, device=dev) if stats else None
+        ll = torch.empty(1, dtype=torch.float64, device=dev)
+        _check("hmm_posterior", _lib.hmm_posterior(self._h, K, *args, _stream(stream),
+                                                   _dev(gamma, torch.float32, "gamma"),
+                                                   _dev(st, torch.float64, "stats") if stats else None,
+                                                   _dev(ll, torch.float64, "loglik", 1)))
+        out = dict(gamma=gamma, loglik=ll)
+        if stats:
+            out.update(xi=st[:K * K].view(K, K), pre=st[K * K:K * K + K], mom=st[K * K + K:].view(K, 7))
+        return out
+
+    def loglik_grad(self, delta, Gamma, p, mu, Sigma, flag, xy, stream=None):
+        """(ln L, dict of gradients delta (K,), Gamma (K, K), p (K,), mu (K, 2), Sigma (K, 3))."""
+        K, T, args = self._params(delta, Gamma, p, mu, Sigma, flag, xy)
+        dev = delta.device
+        g = torch.empty(K + K * K + K + 2 * K + 3 * K, dtype=torch.float64, device=dev)
+        ll = torch.empty(1, dtype=torch.float64, device=dev)
+        _check("hmm_loglik_grad", _lib.hmm_loglik_grad(self._h, K, *args, _stream(stream),
+                                                       _dev(ll, torch.float64, "loglik", 1),
+                                                       _dev(g, torch.float64, "grad")))
+        o = [0, K, K + K * K, 2 * K + K * K, 4 * K + K * K, 7 * K + K * K]
+        return ll, dict(delta=g[o[0]:o[1]], Gamma=g[o[1]:o[2]].view(K, K), p=g[o[2]:o[3]],
+                        mu=g[o[3]:o[4]].view(K, 2), Sigma=g[o[4]:o[5]].view(K, 3))
 
     def batch_graph(self, on=True):
         _check("hmm_ctx_set_batch_graph", _lib.hmm_ctx_set_batch_graph(self._h, 1 if on else 0))

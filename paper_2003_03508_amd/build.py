@@ -11,7 +11,8 @@ LIB = os.path.join(HERE, "libhmm.so")
 UNITS = [(os.path.join(CSRC, "hmm_api.hip"), ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]),
          (os.path.join(CSRC, "hmm_large.hip"), []),
          (os.path.join(CSRC, "hmm_batch.hip"), []),
-         (os.path.join(CSRC, "hmm_sampler.hip"), [])]
+         (os.path.join(CSRC, "hmm_sampler.hip"), []),
+         (os.path.join(CSRC, "hmm_posterior.hip"), [])]
 SOURCES = [u[0] for u in UNITS]
 DEPS = SOURCES + [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hpp")] + [
     os.path.join(os.path.dirname(HERE), "include", "hmm.h")]
