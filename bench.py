@@ -22,6 +22,7 @@ Other workloads (one JSON line each, not the headline):
     python bench.py --workload mcmc_k20   # the MCMC leg on its own
     python bench.py --workload kinds_k25  # Poisson-count and 1-D Gaussian HMMs, K=25, T=1e6
     python bench.py --workload twalk_k25  # the t-walk sampler, K=25, T=105,000
+    python bench.py --workload posterior_k25  # forward-backward and gradient, K=25, T=1e6
 """
 import argparse
 import json
@@ -77,7 +78,8 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--workload", default="k25_t1e6",
-                    choices=["k25_t1e6", "k80_t4m", "batch256", "mcmc_k20", "kinds_k25", "twalk_k25"])
+                    choices=["k25_t1e6", "k80_t4m", "batch256", "mcmc_k20", "kinds_k25", "twalk_k25",
+                             "posterior_k25"])
     ap.add_argument("--twalk-chains", type=int, default=64)
     ap.add_argument("--no-mcmc", action="store_true", help="skip the MCMC leg of the default run")
     ap.add_argument("--mcmc-iterations", type=int, default=10000)
@@ -112,6 +114,8 @@ def main():
         return bench_kinds(args)
     if args.workload == "twalk_k25":
         return bench_twalk(args)
+    if args.workload == "posterior_k25":
+        return bench_posterior(args)
     if args.workload == "mcmc_k20":
         print(json.dumps(run_mcmc(C=args.mcmc_chains, n_iter=args.mcmc_iterations, lag=args.mcmc_lag,
                                   log=True)))
@@ -466,6 +470,66 @@ def bench_twalk(args):
                          "sample": f"{n} t-walk iterations of one chain, FP64 C likelihood, {c1 - c0:.1f} s"},
         "paper_context": "one chain of 1e6 iterations took about 4 h on a GTX 1080 Ti (about 69 iterations/s, "
                          "105,000 observations, K up to 30)",
+    }))
+
+
+def bench_posterior(args):
+    """Forward-backward on the headline data (K=25, T=1e6, seed 1): state
+    posteriors gamma (T x K, FP32), expected transitions and moments; the
+    gradient of ln L; the likelihood alone for comparison; errors against the
+    FP64 oracle's forward-backward, which is also timed on one host thread."""
+    import numpy as np
+    import torch
+    from paper_2003_03508_amd import binding, synth
+    import oracle
+    oracle.build(force=False)
+    wl = synth.WORKLOADS["k25_t1e6"]
+    K, T = wl["K"], wl["T"]
+    prm, obs = synth.make(**wl)
+    d = binding.to_device(prm, obs)
+    ctx = binding.Context(0)
+    steps = max(10, args.steps // 4)
+    res = {}
+    out = {}
+
+    def post():
+        out["p"] = ctx.posterior(**d)
+
+    def grad():
+        out["g"] = ctx.loglik_grad(**d)
+
+    def ll():
+        out["l"] = ctx.loglik(**d)
+    for name, fn in (("loglik", ll), ("posterior", post), ("gradient", grad)):
+        sec = _timed(fn, steps, 3)
+        res[name] = {"ms": round(sec * 1e3, 4), "per_s": round(1.0 / sec, 2)}
+    torch.cuda.synchronize()
+    c0 = time.perf_counter()
+    want = oracle.posterior(prm.delta, prm.Gamma, prm.p, prm.mu, prm.Sigma, obs.flag, obs.xy)
+    c1 = time.perf_counter()
+    g_want = oracle.grad_from_stats(prm.delta, prm.Gamma, prm.p, prm.mu, prm.Sigma, want["xi"], want["pre"],
+                                    want["mom"])
+    p = {k: v.cpu().numpy().astype(np.float64) for k, v in out["p"].items()}
+    gl, gg = out["g"]
+    gerr = max(float(np.abs(gg[n].cpu().numpy().reshape(np.shape(g_want[n])) - g_want[n]).max()
+                     / np.abs(g_want[n]).max()) for n in g_want)
+    ctx.close()
+    # bytes and flops of the per-segment filter / smoothing pass (beyond the
+    # segment products): observations read twice (17 B), u_t written, read
+    # and gamma written (12 K B) per step; 4 K^2 FMAs per step
+    print(json.dumps({
+        "workload": "posterior_k25: forward-backward of the K=25 tremor HMM, T=1,000,000 (seed 1)",
+        "unit": "evaluations/s", "results": res,
+        "posterior_over_loglik": round(res["posterior"]["ms"] / res["loglik"]["ms"], 3),
+        "max_abs_err_gamma": float(np.abs(p["gamma"] - want["gamma"]).max()),
+        "rel_err_xi": float(np.abs(p["xi"] - want["xi"]).max() / np.abs(want["xi"]).max()),
+        "rel_err_moments": float(np.abs(p["mom"] - want["mom"]).max() / np.abs(want["mom"]).max()),
+        "rel_err_gradient_max_block": gerr,
+        "rel_err_loglik": abs(float(p["loglik"][0]) - want["loglik"]) / abs(want["loglik"]),
+        "local_pass_algorithmic_bytes": (34 + 12 * K) * T, "local_pass_algorithmic_flops": 8 * K * K * T,
+        "cpu_baseline": {"value": round(1.0 / (c1 - c0), 4), "unit": "evaluations/s", "cores": 1,
+                         "kind": "oracle", "sample": f"one FP64 forward-backward of the full workload, "
+                                                     f"{c1 - c0:.2f} s"},
     }))
 
 

@@ -26,22 +26,26 @@
 // Pipeline (one set):
 //   1. k_prepare                 FP64 parameters -> state constants, Gamma in FP32
 //   2. k_blocked, one segment per workgroup: every M_b (FP32 + exponents)
-//   3. k_fold, one level, G consecutive segments per workgroup: group products
-//      (kept), then further fold levels down to ln L
-//   4. k_post_scan_groups        FP64 messages at group boundaries (sequential
-//                                over groups; forward and backward in parallel)
-//   5. k_post_scan_segments      FP64 messages at the segment boundaries of each
-//                                group (sequential over its G segments)
-//   6. k_post_local<KB>          one wavefront per segment: forward pass writing
-//                                u_t into the gamma rows, backward pass turning
-//                                them into gamma_t and accumulating xi and the
-//                                per-state moments (FP32 within a segment)
-//   7. k_post_reduce             FP64 sums of the per-segment partials in
-//                                segment order (deterministic)
+//   3. k_fold levels, G consecutive products per workgroup, every level kept,
+//      the last one finishing ln L
+//   4. k_post_scan_level         FP64 messages at product boundaries, from the
+//                                top level of the fold tree down to the
+//                                segments (each level sequential over G
+//                                children, parents in parallel; forward and
+//                                backward messages in parallel)
+//   5. k_post_forward<KB>        one wavefront per segment: the forward filter,
+//                                u_t into the gamma rows (FP32)
+//   6. k_post_backward<KB>       one wavefront per segment: the smoothing pass,
+//                                gamma_t over the u rows, xi and the per-state
+//                                moments (FP32 within a segment)
+//   7. k_colsum_*, k_post_finish FP64 sums of the per-segment partials in a
+//                                fixed order (deterministic)
 //   8. k_post_grad (gradient entry point only)
+#include <algorithm>
 #include <climits>
 #include <cmath>
 #include <cstdint>
+#include <vector>
 
 #include "hmm_host.hpp"
 
@@ -50,21 +54,9 @@ using namespace hmmh;
 
 namespace {
 
-constexpr int kPostWaves = 4;          // segments (wavefronts) per local workgroup
 constexpr int kMoments = 7;            // per-state moments
+constexpr int kMaxKP = 64;             // largest padded K of the posterior path
 constexpr int64_t kPostSegments = 4096; // target segment count of the posterior plan
-
-__device__ __forceinline__ float wsum_f32(float x)
-{
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
-    return x;
-}
-
-__device__ __forceinline__ double wmax_f64(double x)
-{
-    for (int o = 32; o > 0; o >>= 1) x = fmax(x, __shfl_xor(x, o));
-    return x;
-}
 
 __device__ __forceinline__ double wsum_f64(double x)
 {
@@ -81,7 +73,18 @@ __device__ __forceinline__ long long wmax_i64(long long x)
     return x;
 }
 
+// Wavefront-local ordering of LDS accesses only (waits for LDS, not for the
+// wavefront's outstanding global stores).
 __device__ __forceinline__ void wsync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Ordering of global and LDS accesses within the workgroup (the wavefront's
+// global stores become visible to its other lanes).
+__device__ __forceinline__ void gsync()
 {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __builtin_amdgcn_wave_barrier();
@@ -96,69 +99,92 @@ struct PostDesc {
     const double *delta;
     const double *mu;         // [K][2] (the moments are accumulated about mu_k)
     const int *status;
-    const float *Mseg;        // segment products (KP x KP), row exponents, shift sums
-    const long long *Eseg;
-    const float *Mgrp;        // group products
-    const long long *Egrp;
-    double *Agrp, *Cgrp;      // [n1][K] group-boundary messages (C: mantissas)
-    double *Aseg, *Cseg;      // [nb][K] segment-boundary messages (C: mantissas)
-    long long *CgrpE, *CsegE; // exponents of the backward messages
+    const double *Aseg;       // [nb][K] forward message before segment b (normalised)
+    const double *Cseg;       // [nb][K] backward message after segment b: mantissas
+    const long long *CsegE;   //          and per-state exponents
     float *gamma;             // [T][K]
     float *part_xi;           // [nb][K][K]
     float *part_mom;          // [nb][K][kMoments], moments about mu_k
     float *part_pre;          // [K] (segment 0 only)
-    int64_t T, L, nb, n1;
+    int64_t T, L, nb;
+    int K, KP;
+};
+
+// One level of the message scan.  The products of level l (segments at
+// l = 0, then groups of G products of the level below) are children of the
+// products of level l + 1; block q takes parent q's G children in order:
+// wavefront 0 carries the forward message (normalised FP64) left to right,
+// wavefront 1 the backward message (FP64 mantissa + exponent per state)
+// right to left, and both write the message at every child boundary.  The
+// top level has one parent whose messages are delta (normalised) and 1.
+struct ScanLevel {
+    const float *M;           // child products [n][KP][KP], row exponents [n][KP]
+    const long long *E;
+    int64_t n;                // children at this level
+    const double *pA;         // parent messages [P][K] (null: top level)
+    const double *pC;
+    const long long *pCE;
+    double *A, *C;            // child messages [n][K]
+    long long *CE;
+    const double *delta;
     int K, KP, G, pad;
 };
 
-// a <- normalise(a M) for a product M = diag(2^E) M~ (row exponents; the
-// common shift sum drops out).  One wavefront, lane j < K holds a_j; a is
-// also in LDS (sa).  Returns nothing; a (register and LDS) is updated.
-__device__ void msg_forward(const PostDesc &d, const float *M, const long long *E, double &a, double *sa,
-                            double *sf)
+// a <- normalise(a M), M = diag(2^E) M~ in LDS (the common shift drops out).
+// Lane j < K holds a_j; sa is the message's LDS copy, sf and si scratch.  The
+// largest exponent and the sum are read back from LDS by every lane (no
+// cross-lane shuffles).
+__device__ void msg_forward(int K, int KP, const float *M, const long long *E, double &a, double *sa, double *sf,
+                            long long *si)
 {
     const int j = threadIdx.x & 63;
-    const int K = d.K, KP = d.KP;
-    long long e = (j < K && a > 0.0) ? E[j] : LLONG_MIN;
-    const long long emax = wmax_i64(e);
+    si[j] = (j < K && a > 0.0) ? E[j] : LLONG_MIN;
+    wsync();
+    long long emax = LLONG_MIN;
+    for (int i = 0; i < K; ++i) emax = si[i] > emax ? si[i] : emax;
     double f = 0.0;
     if (j < K && a > 0.0) {
         long long sh = E[j] - emax;
-        if (sh < -1000) sh = -1000;
+        if (sh < -1100) sh = -1100;
         f = ldexp(a, (int)sh);
     }
     sf[j] = f;
     wsync();
     double s = 0.0;
     if (j < K)
-        for (int i = 0; i < K; ++i) s += sf[i] * (double)M[(int64_t)i * KP + j];
-    const double tot = wsum_f64(s);
-    a = (tot > 0.0) ? s / tot : (tot == 0.0 ? 0.0 : NAN);
+        for (int i = 0; i < K; ++i) s += sf[i] * (double)M[i * KP + j];
+    wsync();
+    sa[j] = s;
+    wsync();
+    double tot = 0.0;
+    for (int i = 0; i < K; ++i) tot += sa[i];
+    a = (j < K) ? ((tot > 0.0) ? s / tot : (tot == 0.0 ? 0.0 : NAN)) : 0.0;
     wsync();
     sa[j] = a;
     wsync();
 }
 
 // c <- M c for a backward message with one exponent per state,
-// c_i = cm_i 2^ce_i (cm_i in [1/2, 1) or 0), M = diag(2^E) M~:
+// c_i = cm_i 2^ce_i (cm_i in [1/2, 1) or 0), M = diag(2^E) M~ with M~ stored
+// TRANSPOSED in LDS (Mt[j * KP + i] = M~_ij, so that lane i reads row i
+// without bank conflicts):
 //   (M c)_i = 2^(E_i + h_i) sum_j M~_ij cm_j 2^(ce_j - h_i),
 // h_i the largest ce_j over the terms of row i, so each row keeps its own
 // scale.  Lane i < K holds (cm_i, ce_i), mirrored in LDS (sm, se).
-__device__ void msg_backward(const PostDesc &d, const float *M, const long long *E, double &cm, long long &ce,
+__device__ void msg_backward(int K, int KP, const float *Mt, const long long *E, double &cm, long long &ce,
                              double *sm, long long *se)
 {
     const int i = threadIdx.x & 63;
-    const int K = d.K, KP = d.KP;
     double m = 0.0;
     long long e = 0;
     if (i < K) {
         long long h = LLONG_MIN;
         for (int j = 0; j < K; ++j)
-            if (sm[j] > 0.0 && M[(int64_t)i * KP + j] != 0.f && se[j] > h) h = se[j];
+            if (sm[j] > 0.0 && Mt[j * KP + i] != 0.f && se[j] > h) h = se[j];
         if (h != LLONG_MIN) {
             double s = 0.0;
             for (int j = 0; j < K; ++j) {
-                const float mij = M[(int64_t)i * KP + j];
+                const float mij = Mt[j * KP + i];
                 if (sm[j] > 0.0 && mij != 0.f) {
                     long long sh = se[j] - h;
                     if (sh < -1100) sh = -1100;
@@ -178,152 +204,245 @@ __device__ void msg_backward(const PostDesc &d, const float *M, const long long 
     wsync();
 }
 
-// Messages at group boundaries: block 0 forward (Agrp[g] = message before
-// group g), block 1 backward (Cgrp[g] = message after group g).  One wavefront.
-__global__ __launch_bounds__(64) void k_post_scan_groups(PostDesc d)
+// A product held in registers between its load and its LDS store (up to
+// KP = 64: 16 float4 and one exponent per lane).
+struct ProdRegs {
+    float4 m[kMaxKP * kMaxKP / 4 / 64];
+    long long e;
+};
+
+__device__ __forceinline__ void product_load(const float *M, const long long *E, int KP, ProdRegs &r)
 {
-    __shared__ double sv[64], sf[64];
-    const int j = threadIdx.x;
-    const int K = d.K, KP = d.KP;
-    if (blockIdx.x == 0) {
-        double a = 0.0;
-        if (j < K) a = d.delta[j];
-        const double tot = wsum_f64(j < K ? a : 0.0);
-        a = (j < K && tot > 0.0) ? a / tot : 0.0;
-        sv[j] = a;
-        wsync();
-        for (int64_t g = 0; g < d.n1; ++g) {
-            if (j < K) d.Agrp[g * K + j] = a;
-            if (g + 1 < d.n1) msg_forward(d, d.Mgrp + g * KP * KP, d.Egrp + g * KP, a, sv, sf);
-        }
-    } else {
-        __shared__ long long se[64];
-        double cm = (j < K) ? 0.5 : 0.0;   // c = 1: mantissa 1/2, exponent 1
-        long long ce = (j < K) ? 1 : 0;
-        sv[j] = cm;
-        se[j] = ce;
-        wsync();
-        for (int64_t g = d.n1 - 1; g >= 0; --g) {
-            if (j < K) {
-                d.Cgrp[g * K + j] = cm;
-                d.CgrpE[g * K + j] = ce;
-            }
-            if (g > 0) msg_backward(d, d.Mgrp + g * KP * KP, d.Egrp + g * KP, cm, ce, sv, se);
-        }
+    const int lane = threadIdx.x & 63;
+    const float4 *src = reinterpret_cast<const float4 *>(M);
+    const int n4 = KP * KP / 4;
+#pragma unroll
+    for (int q = 0; q < kMaxKP * kMaxKP / 4 / 64; ++q) {
+        const int i = lane + 64 * q;
+        if (i < n4) r.m[q] = src[i];
     }
+    r.e = lane < KP ? E[lane] : 0;
 }
 
-// Messages at the segment boundaries inside group g = blockIdx.x: wavefront 0
-// forward from Agrp[g], wavefront 1 backward from Cgrp[g].
-__global__ __launch_bounds__(128) void k_post_scan_segments(PostDesc d)
+// Into LDS, row-major (transpose = false) or transposed.
+__device__ __forceinline__ void product_store(const ProdRegs &r, int KP, float *lm, long long *le, bool transpose)
 {
-    __shared__ double sv[2][64], sf[64];
-    const int w = threadIdx.x >> 6, j = threadIdx.x & 63;
-    const int K = d.K, KP = d.KP;
-    const int64_t g = blockIdx.x;
-    const int64_t b0 = g * d.G, b1 = min(d.nb, b0 + d.G);
-    if (w == 0) {
-        double a = (j < K) ? d.Agrp[g * K + j] : 0.0;
-        sv[0][j] = a;
-        wsync();
-        for (int64_t b = b0; b < b1; ++b) {
-            if (j < K) d.Aseg[b * K + j] = a;
-            if (b + 1 < b1) msg_forward(d, d.Mseg + b * KP * KP, d.Eseg + b * KP, a, sv[0], sf);
+    const int lane = threadIdx.x & 63;
+    const int n4 = KP * KP / 4;
+    if (!transpose) {
+        float4 *dst = reinterpret_cast<float4 *>(lm);
+#pragma unroll
+        for (int q = 0; q < kMaxKP * kMaxKP / 4 / 64; ++q) {
+            const int i = lane + 64 * q;
+            if (i < n4) dst[i] = r.m[q];
         }
     } else {
-        __shared__ long long se[64];
-        double cm = (j < K) ? d.Cgrp[g * K + j] : 0.0;
-        long long ce = (j < K) ? d.CgrpE[g * K + j] : 0;
+#pragma unroll
+        for (int q = 0; q < kMaxKP * kMaxKP / 4 / 64; ++q) {
+            const int i = lane + 64 * q;
+            if (i < n4) {
+                const int row = (4 * i) / KP, col = (4 * i) % KP;
+                lm[(col + 0) * KP + row] = r.m[q].x;
+                lm[(col + 1) * KP + row] = r.m[q].y;
+                lm[(col + 2) * KP + row] = r.m[q].z;
+                lm[(col + 3) * KP + row] = r.m[q].w;
+            }
+        }
+    }
+    if (lane < KP) le[lane] = r.e;
+    wsync();
+}
+
+__global__ __launch_bounds__(128) void k_post_scan_level(ScanLevel s)
+{
+    __shared__ __attribute__((aligned(16))) float lm[2][kMaxKP * kMaxKP];
+    __shared__ long long le[2][kMaxKP];
+    __shared__ double sv[2][64], sf[64];
+    __shared__ long long se[64], si[64];
+    const int w = threadIdx.x >> 6, j = threadIdx.x & 63;
+    const int K = s.K, KP = s.KP;
+    const int64_t q = blockIdx.x;
+    const int64_t c0 = q * s.G, c1 = min(s.n, c0 + s.G);
+    ProdRegs nx;
+    if (w == 0) {
+        double a = 0.0;
+        if (s.pA) {
+            a = (j < K) ? s.pA[q * K + j] : 0.0;
+        } else {
+            a = (j < K) ? s.delta[j] : 0.0;
+            const double tot = wsum_f64(a);
+            a = (j < K && tot > 0.0) ? a / tot : 0.0;
+        }
+        sv[0][j] = a;
+        wsync();
+        if (c0 + 1 < c1) product_load(s.M + c0 * KP * KP, s.E + c0 * KP, KP, nx);
+        for (int64_t c = c0; c < c1; ++c) {
+            if (j < K) s.A[c * K + j] = a;
+            if (c + 1 < c1) {
+                product_store(nx, KP, lm[0], le[0], false);
+                if (c + 2 < c1) product_load(s.M + (c + 1) * KP * KP, s.E + (c + 1) * KP, KP, nx);
+                msg_forward(K, KP, lm[0], le[0], a, sv[0], sf, si);
+            }
+        }
+    } else {
+        double cm = 0.0;
+        long long ce = 0;
+        if (s.pC) {
+            cm = (j < K) ? s.pC[q * K + j] : 0.0;
+            ce = (j < K) ? s.pCE[q * K + j] : 0;
+        } else {
+            cm = (j < K) ? 0.5 : 0.0;   // c = 1: mantissa 1/2, exponent 1
+            ce = (j < K) ? 1 : 0;
+        }
         sv[1][j] = cm;
         se[j] = ce;
         wsync();
-        for (int64_t b = b1 - 1; b >= b0; --b) {
+        if (c1 - 1 > c0) product_load(s.M + (c1 - 1) * KP * KP, s.E + (c1 - 1) * KP, KP, nx);
+        for (int64_t c = c1 - 1; c >= c0; --c) {
             if (j < K) {
-                d.Cseg[b * K + j] = cm;
-                d.CsegE[b * K + j] = ce;
+                s.C[c * K + j] = cm;
+                s.CE[c * K + j] = ce;
             }
-            if (b > b0) msg_backward(d, d.Mseg + b * KP * KP, d.Eseg + b * KP, cm, ce, sv[1], se);
+            if (c > c0) {
+                product_store(nx, KP, lm[1], le[1], true);
+                if (c - 1 > c0) product_load(s.M + (c - 1) * KP * KP, s.E + (c - 1) * KP, KP, nx);
+                msg_backward(K, KP, lm[1], le[1], cm, ce, sv[1], se);
+            }
         }
     }
 }
 
-// log2 of the emission of observation t for state j (lane); -inf for padding
-// lanes.
-__device__ __forceinline__ double post_log2_emission(const PostDesc &d, const StateConst &s, int64_t t, int j)
+// Waves per workgroup of the local pass (its LDS grows with KB).
+template <int KB> constexpr int post_waves() { return KB <= 32 ? 4 : 2; }
+
+// sum_i x[i] * c[i], x from LDS, c in registers, 4 partial chains.
+template <int KB>
+__device__ __forceinline__ float dot_reg(const float *x, const float (&c)[KB])
 {
-    const int f = d.flag[t];
-    double x = 0.0, y = 0.0;
-    if (f == 1) {
-        const double2 p = reinterpret_cast<const double2 *>(d.xy)[t];
-        x = p.x;
-        y = p.y;
-    }
-    return (j < d.K) ? state_log2_emission(s, f == 1, x, y) : -INFINITY;
+    float p[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int i = 0; i < KB; ++i) p[i & 3] = fmaf(x[i], c[i], p[i & 3]);
+    return (p[0] + p[1]) + (p[2] + p[3]);
 }
 
-// One wavefront per segment: forward then backward pass over its
-// observations.  Lane j is state j; Gamma's column j and row j stay in
-// registers, the shared vectors go through the wavefront's LDS slice.
 template <int KB>
-__global__ __launch_bounds__(64 * kPostWaves) void k_post_local(PostDesc d)
+__device__ __forceinline__ float sum_lds(const float *x)
 {
-    __shared__ float lds[kPostWaves][2][KB];
+    float p[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int i = 0; i < KB; ++i) p[i & 3] += x[i];
+    return (p[0] + p[1]) + (p[2] + p[3]);
+}
+
+// Gamma (gs, row-major) and its transpose (gt) in the workgroup's LDS; lane
+// j reads column j of either, conflict-free.
+template <int KB>
+__device__ __forceinline__ void load_gamma_lds(const PostDesc &d, float *gs, float *gt)
+{
+    for (int idx = threadIdx.x; idx < KB * KB; idx += blockDim.x) {
+        const int r = idx / KB, c = idx % KB;
+        const float v = (r < d.K && c < d.K) ? d.GF[r * d.KP + c] : 0.f;
+        gs[idx] = v;
+        if (gt) gt[c * KB + r] = v;
+    }
+    __syncthreads();
+}
+
+// Forward filter, one wavefront per segment, in chunks of kChunk
+// observations: the chunk's emissions are staged as for the segment products
+// (scaled by 2^-s_t with the same bias, so that a state trailing the best one
+// by up to 2^-256 at one step keeps a normal FP32 value), then
+//   u_t,j = (sum_i u_{t-1,i} Gamma_ij / sum_i u_{t-1,i}) e^_t,j,
+// both sums read from the LDS copy of u_{t-1} (u is never normalised
+// explicitly; every later use is invariant to its scale), stored into the
+// gamma rows.
+template <int KB>
+__global__ __launch_bounds__(64 * post_waves<KB>()) void k_post_forward(PostDesc d)
+{
+    constexpr int NW = post_waves<KB>();
+    __shared__ __attribute__((aligned(16))) float gs[KB * KB];
+    __shared__ __attribute__((aligned(16))) float et[NW][KB * kChunk];
+    __shared__ __attribute__((aligned(16))) float sv[NW][KB];
+    load_gamma_lds<KB>(d, gs, nullptr);
     const int w = threadIdx.x >> 6, j = threadIdx.x & 63;
-    const int64_t b = (int64_t)blockIdx.x * kPostWaves + w;
-    if (b >= d.nb) return;
-    const int K = d.K, KP = d.KP;
+    const int64_t b = (int64_t)blockIdx.x * NW + w;
+    if (b >= d.nb || *d.status != 0) return;
+    const int K = d.K;
     const int64_t t0 = b * d.L, t1 = min(d.T, t0 + d.L);
-    float *su = lds[w][0], *sw = lds[w][1];
+    float *E = et[w], *su = sv[w];
     const bool live = j < K;
+    const int jc = j < KB ? j : 0;
+    const Obs obs{d.flag, d.xy, nullptr, kEmisTremor, 0};
+    float gcol[KB];
+#pragma unroll
+    for (int i = 0; i < KB; ++i) gcol[i] = gs[i * KB + jc];
+    for (int i = j; i < KB * kChunk; i += 64) E[i] = 0.f;   // rows >= K stay zero
+    if (j < KB) su[j] = live ? (float)d.Aseg[b * K + j] : 0.f;
+    wsync();
+    for (int64_t tc = t0; tc < t1; tc += kChunk) {
+        const int nst = (int)min((int64_t)kChunk, t1 - tc);
+        long long ssum = 0;
+        int bad = 0, sh = 0;
+        stage_emissions<kChunk, false>(K, tc, nst, obs, d.sc, E, ssum, bad, sh);
+        for (int tl = 0; tl < nst; ++tl) {
+            const float v = dot_reg<KB>(su, gcol);
+            const float s = sum_lds<KB>(su);
+            const float a = live ? __fdividef(v, s) * E[j * kChunk + tl] : 0.f;
+            if (live) d.gamma[(tc + tl) * K + j] = a;
+            wsync();
+            if (j < KB) su[j] = a;
+            wsync();
+        }
+    }
+}
+
+// Backward pass in the smoothing form, one wavefront per segment, chunks
+// from the end.  Start: gamma at the segment's last step = u o c_b,
+// normalised with the per-state exponents of c_b (FP64).  The chunk's u rows
+// and observations are staged into LDS, and per step
+//   pred_j = sum_i u_{t-1,i} Gamma_ij,  r_j = gamma_t,j / pred_j (0 if pred_j = 0),
+//   xi_t(i,j) = u_{t-1,i} Gamma_ij r_j,  gamma_{t-1,i} = normalise(u_{t-1,i} sum_j Gamma_ij r_j),
+// overwriting the u rows with gamma and accumulating xi (as
+// Gamma_ij sum_t u_{t-1,i} r_t,j) and the moments.
+template <int KB>
+__global__ __launch_bounds__(64 * post_waves<KB>(), KB <= 32 ? 2 : 1) void k_post_backward(PostDesc d)
+{
+    constexpr int NW = post_waves<KB>();
+    __shared__ __attribute__((aligned(16))) float gs[KB * KB], gt[KB * KB];
+    __shared__ __attribute__((aligned(16))) float et[NW][KB * kChunk];   // u rows of a chunk
+    __shared__ __attribute__((aligned(16))) float sv[NW][2][KB];          // r, unnormalised gamma
+    __shared__ double ox[NW][kChunk], oy[NW][kChunk];
+    __shared__ int of[NW][kChunk];
+    load_gamma_lds<KB>(d, gs, gt);
+    const int w = threadIdx.x >> 6, j = threadIdx.x & 63;
+    const int64_t b = (int64_t)blockIdx.x * NW + w;
+    if (b >= d.nb) return;
+    const int K = d.K;
+    const int64_t t0 = b * d.L, t1 = min(d.T, t0 + d.L);
+    float *E = et[w], *sr = sv[w][0], *sg = sv[w][1];
+    const bool live = j < K;
+    const int jc = j < KB ? j : 0;
     if (*d.status != 0) {
         for (int64_t t = t0; t < t1; ++t)
             if (live) d.gamma[t * K + j] = __builtin_nanf("");
         return;
     }
-    float gcol[KB], grow[KB], xi[KB];
+    float xi[KB], gcol[KB], grow[KB];
 #pragma unroll
     for (int i = 0; i < KB; ++i) {
-        gcol[i] = (live && i < K) ? d.GF[i * KP + j] : 0.f;
-        grow[i] = (live && i < K) ? d.GF[j * KP + i] : 0.f;
         xi[i] = 0.f;
+        gcol[i] = gs[i * KB + jc];
+        grow[i] = gt[i * KB + jc];
     }
     float mom[kMoments];
 #pragma unroll
     for (int q = 0; q < kMoments; ++q) mom[q] = 0.f;
-    StateConst scj{};
     double mux = 0.0, muy = 0.0;
     if (live) {
-        scj = d.sc[j];
         mux = d.mu[2 * j];
         muy = d.mu[2 * j + 1];
     }
     const float a_in = live ? (float)d.Aseg[b * K + j] : 0.f;
-    if (j < KB) su[j] = a_in;
-    wsync();
-    // forward: u_t into the gamma rows.  Each step is scaled by the largest
-    // unnormalised component v_j e_j (in log2), not by the largest emission:
-    // an observation that the currently likely states explain 2^-150 times
-    // worse than some unlikely state must not flush the filter to zero.
-    for (int64_t t = t0; t < t1; ++t) {
-        const double lam = post_log2_emission(d, scj, t, j);
-        float v = 0.f;
-#pragma unroll
-        for (int i = 0; i < KB; ++i) v = fmaf(su[i], gcol[i], v);
-        const double lv = (v > 0.f) ? (double)log2f(v) + lam : -INFINITY;
-        const double r = lv - wmax_f64(lv);
-        float a = 0.f;
-        if (r > -160.0) {
-            const double n = floor(r);
-            a = __builtin_amdgcn_ldexpf(exp2f((float)(r - n)), (int)n);
-        }
-        a = a / wsum_f32(a);
-        if (live) d.gamma[t * K + j] = a;
-        wsync();
-        if (j < KB) su[j] = live ? a : 0.f;
-        wsync();
-    }
-    // posterior at the segment's last step: u o c_b, normalised with the
-    // per-state exponents of c_b (FP64)
     float g;
     {
         const double ut = live ? (double)d.gamma[(t1 - 1) * K + j] : 0.0;
@@ -336,104 +455,159 @@ __global__ __launch_bounds__(64 * kPostWaves) void k_post_local(PostDesc d)
         const long long lmax = wmax_i64(lv);
         double v = 0.0;
         if (prod > 0.0) {
-            long long sh = lv - lmax;
-            if (sh < -1100) sh = -1100;
-            v = ldexp(mant, (int)sh);
+            long long shf = lv - lmax;
+            if (shf < -1100) shf = -1100;
+            v = ldexp(mant, (int)shf);
         }
         g = (float)(v / wsum_f64(v));
     }
-    // backward (smoothing form)
-    for (int64_t t = t1 - 1; t >= t0; --t) {
-        if (live) {
-            d.gamma[t * K + j] = g;
-            mom[0] += g;
-            if (d.flag[t] == 1) {
-                const double2 p = reinterpret_cast<const double2 *>(d.xy)[t];
-                const float x = (float)(p.x - mux), y = (float)(p.y - muy);
-                mom[1] += g;
-                mom[2] = fmaf(g, x, mom[2]);
-                mom[3] = fmaf(g, y, mom[3]);
-                mom[4] = fmaf(g * x, x, mom[4]);
-                mom[5] = fmaf(g * x, y, mom[5]);
-                mom[6] = fmaf(g * y, y, mom[6]);
+    const int64_t nch = (t1 - t0 + kChunk - 1) / kChunk;
+    for (int64_t ci = nch - 1; ci >= 0; --ci) {
+        const int64_t tc = t0 + ci * kChunk;
+        const int nst = (int)min((int64_t)kChunk, t1 - tc);
+        wsync();
+        // E row r = u_{tc+r-1} (row stride KB); positions p = r * KB + i, in
+        // batches of 8 loads issued before their LDS stores
+        for (int q0 = 0; q0 < KB; q0 += 8) {
+            float tmp[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int pos = j + 64 * (q0 + q), r = pos / KB, i = pos % KB;
+                const int64_t t = tc + r - 1;
+                tmp[q] = (r < nst && i < K && t >= t0) ? d.gamma[t * K + i] : 0.f;
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int pos = j + 64 * (q0 + q), r = pos / KB;
+                if (r < nst) E[pos] = tmp[q];
             }
         }
-        const float uprev = (t > t0) ? (live ? d.gamma[(t - 1) * K + j] : 0.f) : a_in;
-        wsync();
-        if (j < KB) su[j] = live ? uprev : 0.f;
-        wsync();
-        float pred = 0.f;
-#pragma unroll
-        for (int i = 0; i < KB; ++i) pred = fmaf(su[i], gcol[i], pred);
-        const float r = (live && pred > 0.f) ? g / pred : 0.f;
-        if (j < KB) sw[j] = r;
-        wsync();
-        float back = 0.f;
-#pragma unroll
-        for (int i = 0; i < KB; ++i) {
-            xi[i] = fmaf(su[i] * gcol[i], r, xi[i]);
-            back = fmaf(grow[i], sw[i], back);
+        if (tc == t0 && j < KB) E[j] = a_in;   // u_{t0-1}: the segment's entry message
+        if (j < nst) {
+            const int64_t t = tc + j;
+            const int f = d.flag[t];
+            of[w][j] = f;
+            double x = 0.0, y = 0.0;
+            if (f == 1) {
+                const double2 p = reinterpret_cast<const double2 *>(d.xy)[t];
+                x = p.x;
+                y = p.y;
+            }
+            ox[w][j] = x;
+            oy[w][j] = y;
         }
-        float gp = live ? uprev * back : 0.f;
-        gp = gp / wsum_f32(gp);
-        if (b == 0 && t == 0 && live) d.part_pre[j] = gp;
-        g = gp;
+        wsync();
+        for (int tl = nst - 1; tl >= 0; --tl) {
+            const int64_t t = tc + tl;
+            if (live) {
+                d.gamma[t * K + j] = g;
+                mom[0] += g;
+                if (of[w][tl] == 1) {
+                    const float x = (float)(ox[w][tl] - mux), y = (float)(oy[w][tl] - muy);
+                    mom[1] += g;
+                    mom[2] = fmaf(g, x, mom[2]);
+                    mom[3] = fmaf(g, y, mom[3]);
+                    mom[4] = fmaf(g * x, x, mom[4]);
+                    mom[5] = fmaf(g * x, y, mom[5]);
+                    mom[6] = fmaf(g * y, y, mom[6]);
+                }
+            }
+            const float *up = E + tl * KB;   // u_{t-1}
+            const float pred = dot_reg<KB>(up, gcol);
+            const float r = (live && pred > 0.f) ? __fdividef(g, pred) : 0.f;
+            if (j < KB) sr[j] = r;
+            wsync();
+#pragma unroll
+            for (int i = 0; i < KB; ++i) xi[i] = fmaf(up[i], r, xi[i]);
+            const float back = dot_reg<KB>(sr, grow);
+            const float gp = live ? up[j] * back : 0.f;
+            if (j < KB) sg[j] = gp;
+            wsync();
+            g = __fdividef(gp, sum_lds<KB>(sg));
+            if (b == 0 && t == 0 && live) d.part_pre[j] = g;
+            wsync();
+        }
     }
     if (live) {
+        // xi(i, j) = Gamma_ij sum_t u_{t-1,i} r_t,j
         float *px = d.part_xi + b * K * K;
 #pragma unroll
         for (int i = 0; i < KB; ++i)
-            if (i < K) px[i * K + j] = xi[i];
+            if (i < K) px[i * K + j] = xi[i] * gcol[i];
         float *pm = d.part_mom + (b * K + j) * kMoments;
 #pragma unroll
         for (int q = 0; q < kMoments; ++q) pm[q] = mom[q];
     }
 }
 
-// stats = [xi (K*K) | pre (K) | moments (K*7)], FP64 sums over segments in
-// segment order.  Threads [0, K*K) sum xi; thread K*K + k sums pre_k and the
-// moments of state k, accumulated about mu_k, and turns them into raw
-// moments: with D = sum g f (x - mu), sum g f x = D + n1 mu and
-// sum g f x x' = D_xx' + mu D_x' + mu' D_x + n1 mu mu'.  NaN everywhere when
-// the parameters or data were invalid.
-__global__ __launch_bounds__(256) void k_post_reduce(PostDesc d, double *stats)
+// Column sums of a [rows][n] FP32 array in FP64, two stages with a fixed
+// order (deterministic).  Stage 1: block (x, c) sums columns [64x, 64x + 64)
+// over the rows of chunk c (rows c, c + C, c + 2C, ...; 4 wavefronts, then a
+// fixed tree) into part[c][n].  Stage 2: one thread per column sums the C
+// chunk partials in order.
+constexpr int kSumChunks = 64;
+
+__global__ __launch_bounds__(256) void k_colsum_partial(const float *__restrict__ in, int64_t rows, int64_t n,
+                                                        double *__restrict__ part)
+{
+    __shared__ double red[4][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t col = blockIdx.x * 64 + lane;
+    const int64_t c = blockIdx.y;
+    double s = 0.0;
+    if (col < n)
+        for (int64_t r = c + (int64_t)w * kSumChunks; r < rows; r += 4 * kSumChunks) s += (double)in[r * n + col];
+    red[w][lane] = s;
+    __syncthreads();
+    if (w == 0 && col < n) part[c * n + col] = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
+}
+
+__global__ __launch_bounds__(256) void k_colsum_final(const double *__restrict__ part, int64_t n,
+                                                      double *__restrict__ out)
+{
+    const int64_t col = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (col >= n) return;
+    double s = 0.0;
+    for (int c = 0; c < kSumChunks; ++c) s += part[(int64_t)c * n + col];
+    out[col] = s;
+}
+
+// stats = [xi (K*K) | pre (K) | moments (K*7)] from the column sums of the
+// per-segment partials (xi and the moments about mu_k, already summed into
+// stats[0, K*K) and stats[K*K + K, ...)): pre from segment 0 (or delta when
+// T = 0) and the raw moments: with D = sum g f (x - mu),
+// sum g f x = D + n1 mu and sum g f x x' = D_xx' + mu D_x' + mu' D_x + n1 mu mu'.
+// NaN everywhere when the parameters or data were invalid.
+__global__ __launch_bounds__(64) void k_post_finish(PostDesc d, double *stats)
 {
     const int K = d.K;
-    const int64_t nxi = (int64_t)K * K;
-    const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (idx >= nxi + K) return;
-    const bool bad = *d.status != 0;
-    if (idx < nxi) {
-        double s = 0.0;
-        for (int64_t b = 0; b < d.nb; ++b) s += (double)d.part_xi[b * nxi + idx];
-        stats[idx] = bad ? __builtin_nan("") : s;
+    const int64_t nxi = (int64_t)K * K, n = nxi + K + (int64_t)K * kMoments;
+    if (*d.status != 0) {
+        for (int64_t i = threadIdx.x; i < n; i += blockDim.x) stats[i] = __builtin_nan("");
         return;
     }
-    const int k = (int)(idx - nxi);
-    double *pre = stats + nxi, *mom = stats + nxi + K + (int64_t)k * kMoments;
-    if (bad) {
-        pre[k] = __builtin_nan("");
-        for (int q = 0; q < kMoments; ++q) mom[q] = __builtin_nan("");
-        return;
+    for (int k = threadIdx.x; k < K; k += blockDim.x) {
+        double *pre = stats + nxi, *mom = stats + nxi + K + (int64_t)k * kMoments;
+        if (d.nb > 0) {
+            pre[k] = (double)d.part_pre[k];
+        } else {
+            double tot = 0.0;
+            for (int i = 0; i < K; ++i) tot += d.delta[i];
+            pre[k] = d.delta[k] / tot;
+        }
+        double m[kMoments];
+        for (int q = 0; q < kMoments; ++q) m[q] = d.nb > 0 ? mom[q] : 0.0;
+        const double mx = d.mu[2 * k], my = d.mu[2 * k + 1], n1 = m[1];
+        mom[0] = m[0];
+        mom[1] = n1;
+        mom[2] = m[2] + n1 * mx;
+        mom[3] = m[3] + n1 * my;
+        mom[4] = m[4] + 2.0 * mx * m[2] + n1 * mx * mx;
+        mom[5] = m[5] + mx * m[3] + my * m[2] + n1 * mx * my;
+        mom[6] = m[6] + 2.0 * my * m[3] + n1 * my * my;
     }
-    if (d.nb > 0) {
-        pre[k] = (double)d.part_pre[k];
-    } else {
-        double tot = 0.0;
-        for (int i = 0; i < K; ++i) tot += d.delta[i];
-        pre[k] = d.delta[k] / tot;
-    }
-    double m[kMoments] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int64_t b = 0; b < d.nb; ++b)
-        for (int q = 0; q < kMoments; ++q) m[q] += (double)d.part_mom[(b * K + k) * kMoments + q];
-    const double mx = d.mu[2 * k], my = d.mu[2 * k + 1], n1 = m[1];
-    mom[0] = m[0];
-    mom[1] = n1;
-    mom[2] = m[2] + n1 * mx;
-    mom[3] = m[3] + n1 * my;
-    mom[4] = m[4] + 2.0 * mx * m[2] + n1 * mx * mx;
-    mom[5] = m[5] + mx * m[3] + my * m[2] + n1 * mx * my;
-    mom[6] = m[6] + 2.0 * my * m[3] + n1 * my * my;
+    if (d.nb == 0)
+        for (int64_t i = threadIdx.x; i < nxi; i += blockDim.x) stats[i] = 0.0;
 }
 
 // Gradient of ln L with every parameter entry free (Fisher's identity),
@@ -481,14 +655,18 @@ __global__ __launch_bounds__(256) void k_post_grad(int K, const double *delta, c
 template <int KB>
 void launch_local(const PostDesc &d, hipStream_t st)
 {
-    const unsigned grid = (unsigned)((d.nb + kPostWaves - 1) / kPostWaves);
-    hipLaunchKernelGGL(k_post_local<KB>, dim3(grid), dim3(64 * kPostWaves), 0, st, d);
+    constexpr int NW = post_waves<KB>();
+    const unsigned grid = (unsigned)((d.nb + NW - 1) / NW);
+    hipLaunchKernelGGL(k_post_forward<KB>, dim3(grid), dim3(64 * NW), 0, st, d);
+    hipLaunchKernelGGL(k_post_backward<KB>, dim3(grid), dim3(64 * NW), 0, st, d);
 }
 
-struct PostLayout {
-    size_t status, sc, gf, mseg, eseg, sseg, mgrp, egrp, sgrp, mf1, ef1, sf1, mf2, ef2, sf2, agrp, cgrp, cgrpe, aseg,
-        cseg, csege, pxi, pmom, ppre, gam, stats, total;
-};
+void launch_colsum(const float *in, int64_t rows, int64_t n, double *part, double *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_colsum_partial, dim3((unsigned)((n + 63) / 64), kSumChunks), dim3(256), 0, st, in, rows, n,
+                       part);
+    hipLaunchKernelGGL(k_colsum_final, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, part, n, out);
+}
 
 int posterior_impl(hmm_ctx *ctx, int32_t K, const double *delta, const double *Gamma, const double *p,
                    const double *mu, const double *Sigma, int64_t T, const uint8_t *flag, const double *xy,
@@ -502,56 +680,52 @@ int posterior_impl(hmm_ctx *ctx, int32_t K, const double *delta, const double *G
     if (!select_kernels(HMM_BLOCKED_F32, K, &ks)) return HMM_E_UNSUPPORTED;
     const int KP = ks.KP();
     const int G = group_waves(KP);
-    int64_t L = ctx->block_len > 0 ? ctx->block_len : std::max<int64_t>(32, (T + kPostSegments - 1) / kPostSegments);
+    const int64_t L = ctx->block_len > 0 ? ctx->block_len
+                                         : std::max<int64_t>(32, (T + kPostSegments - 1) / kPostSegments);
     const int64_t nb = T > 0 ? (T + L - 1) / L : 0;
-    const int64_t n1 = (nb + G - 1) / G;
     if (nb > INT_MAX) return HMM_E_UNSUPPORTED;
-    // layout
-    PostLayout ly{};
+    // product levels: 0 = segments, l + 1 = groups of G products of level l,
+    // up to the first level with at most G products
+    std::vector<int64_t> cnt{nb};
+    while (cnt.back() > G) cnt.push_back((cnt.back() + G - 1) / G);
+    const int nlev = (int)cnt.size();
     size_t off = 0;
     auto take = [&](size_t bytes) {
         const size_t o = off;
         off = align_up(off + std::max<size_t>(bytes, 1));
         return o;
     };
-    const size_t P2 = (size_t)KP * KP, nbs = std::max<int64_t>(nb, 1), n1s = std::max<int64_t>(n1, 1);
-    const size_t n2 = (n1s + G - 1) / G, n3 = (n2 + G - 1) / G;
-    ly.status = take(sizeof(int));
-    ly.sc = take(sizeof(StateConst) * KP);
-    ly.gf = take(sizeof(float) * P2);
-    ly.mseg = take(sizeof(float) * P2 * nbs);
-    ly.eseg = take(sizeof(long long) * KP * nbs);
-    ly.sseg = take(sizeof(long long) * nbs);
-    ly.mgrp = take(sizeof(float) * P2 * n1s);
-    ly.egrp = take(sizeof(long long) * KP * n1s);
-    ly.sgrp = take(sizeof(long long) * n1s);
-    ly.mf1 = take(sizeof(float) * P2 * n2);
-    ly.ef1 = take(sizeof(long long) * KP * n2);
-    ly.sf1 = take(sizeof(long long) * n2);
-    ly.mf2 = take(sizeof(float) * P2 * n3);
-    ly.ef2 = take(sizeof(long long) * KP * n3);
-    ly.sf2 = take(sizeof(long long) * n3);
-    ly.agrp = take(sizeof(double) * K * n1s);
-    ly.cgrp = take(sizeof(double) * K * n1s);
-    ly.cgrpe = take(sizeof(long long) * K * n1s);
-    ly.aseg = take(sizeof(double) * K * nbs);
-    ly.cseg = take(sizeof(double) * K * nbs);
-    ly.csege = take(sizeof(long long) * K * nbs);
-    ly.pxi = take(sizeof(float) * K * K * nbs);
-    ly.pmom = take(sizeof(float) * K * kMoments * nbs);
-    ly.ppre = take(sizeof(float) * K);
-    ly.gam = gamma ? 0 : take(sizeof(float) * K * (size_t)std::max<int64_t>(T, 1));
-    ly.stats = need_stats_ws ? take(sizeof(double) * (K * K + K + K * kMoments)) : 0;
-    ly.total = off;
+    const size_t P2 = (size_t)KP * KP;
+    const size_t o_status = take(sizeof(int));
+    const size_t o_sc = take(sizeof(StateConst) * KP);
+    const size_t o_gf = take(sizeof(float) * P2);
+    std::vector<size_t> o_m(nlev), o_e(nlev), o_s(nlev), o_a(nlev), o_c(nlev), o_ce(nlev);
+    for (int l = 0; l < nlev; ++l) {
+        const size_t n = (size_t)std::max<int64_t>(cnt[l], 1);
+        o_m[l] = take(sizeof(float) * P2 * n);
+        o_e[l] = take(sizeof(long long) * KP * n);
+        o_s[l] = take(sizeof(long long) * n);
+        o_a[l] = take(sizeof(double) * K * n);
+        o_c[l] = take(sizeof(double) * K * n);
+        o_ce[l] = take(sizeof(long long) * K * n);
+    }
+    const size_t nbs = (size_t)std::max<int64_t>(nb, 1);
+    const size_t o_pxi = take(sizeof(float) * K * K * nbs);
+    const size_t o_pmom = take(sizeof(float) * K * kMoments * nbs);
+    const size_t o_ppre = take(sizeof(float) * K);
+    const int64_t nstat = (int64_t)K * K + K + (int64_t)K * kMoments;
+    const size_t o_part = take(sizeof(double) * kSumChunks * (size_t)nstat);
+    const size_t o_gam = gamma ? 0 : take(sizeof(float) * K * (size_t)std::max<int64_t>(T, 1));
+    const size_t o_stats = need_stats_ws ? take(sizeof(double) * nstat) : 0;
     DeviceGuard dg(ctx->device);
     if (!dg.ok) return HMM_E_DEVICE;
-    int rc = ensure_ws(ctx, ly.total);
+    int rc = ensure_ws(ctx, off);
     if (rc != HMM_OK) return rc;
     void *ws = ctx->ws;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    int *status = at<int>(ws, ly.status);
-    StateConst *sc = at<StateConst>(ws, ly.sc);
-    float *gf = at<float>(ws, ly.gf);
+    int *status = at<int>(ws, o_status);
+    StateConst *sc = at<StateConst>(ws, o_sc);
+    float *gf = at<float>(ws, o_gf);
     hipLaunchKernelGGL(k_prepare, dim3(1), dim3(256), 0, st, (int)kEmisTremor, K, KP, delta, Gamma, p, mu, Sigma, sc,
                        gf, status);
     SetDesc sd;
@@ -567,40 +741,19 @@ int posterior_impl(hmm_ctx *ctx, int32_t K, const double *delta, const double *G
     sd.pad = 0;
     const size_t rb = (size_t)region_bytes(KP);
     if (allow_lds(ks.seg1, rb) != HMM_OK || allow_lds(ks.fold1, rb * G) != HMM_OK) return HMM_E_DEVICE;
-    float *mseg = at<float>(ws, ly.mseg), *mgrp = at<float>(ws, ly.mgrp);
-    long long *eseg = at<long long>(ws, ly.eseg), *sseg = at<long long>(ws, ly.sseg);
-    long long *egrp = at<long long>(ws, ly.egrp), *sgrp = at<long long>(ws, ly.sgrp);
-    // 2. every segment product (one wavefront per workgroup)
-    if (nb > 0 && launch_seg(ks.seg1, (unsigned)nb, 1, rb, st, sd, nullptr, nullptr, nb, mseg, eseg, sseg) !=
-                      hipSuccess)
+    // segment products (one wavefront per workgroup), group levels, ln L
+    if (nb > 0 && launch_seg(ks.seg1, (unsigned)nb, 1, rb, st, sd, nullptr, nullptr, nb, at<float>(ws, o_m[0]),
+                             at<long long>(ws, o_e[0]), at<long long>(ws, o_s[0])) != hipSuccess)
         return HMM_E_DEVICE;
-    // 3. group products, then fold levels to ln L
-    if (nb > 0 && launch_fold(ks.fold1, (unsigned)n1, G, rb * G, st, sd, nullptr, nullptr, nb, 1, 0, mseg, eseg,
-                              sseg, mgrp, egrp, sgrp) != hipSuccess)
-        return HMM_E_DEVICE;
-    {
-        int64_t n = nb > 0 ? n1 : 0;
-        const float *mi = mgrp;
-        const long long *ei = egrp, *si = sgrp;
-        int which = 1;
-        while (n > G) {
-            const int64_t nout = (n + G - 1) / G;
-            float *mo = at<float>(ws, which == 1 ? ly.mf1 : ly.mf2);
-            long long *eo = at<long long>(ws, which == 1 ? ly.ef1 : ly.ef2);
-            long long *so = at<long long>(ws, which == 1 ? ly.sf1 : ly.sf2);
-            if (launch_fold(ks.fold1, (unsigned)nout, G, rb * G, st, sd, nullptr, nullptr, n, 1, 0, mi, ei, si, mo,
-                            eo, so) != hipSuccess)
-                return HMM_E_DEVICE;
-            mi = mo;
-            ei = eo;
-            si = so;
-            n = nout;
-            which = 3 - which;
-        }
-        if (launch_fold(ks.fold1, 1, G, rb * G, st, sd, nullptr, nullptr, n, 1, 1, mi, ei, si, nullptr, nullptr,
-                        nullptr) != hipSuccess)
+    for (int l = 1; l < nlev; ++l)
+        if (launch_fold(ks.fold1, (unsigned)cnt[l], G, rb * G, st, sd, nullptr, nullptr, cnt[l - 1], 1, 0,
+                        at<float>(ws, o_m[l - 1]), at<long long>(ws, o_e[l - 1]), at<long long>(ws, o_s[l - 1]),
+                        at<float>(ws, o_m[l]), at<long long>(ws, o_e[l]), at<long long>(ws, o_s[l])) != hipSuccess)
             return HMM_E_DEVICE;
-    }
+    if (launch_fold(ks.fold1, 1, G, rb * G, st, sd, nullptr, nullptr, nb > 0 ? cnt[nlev - 1] : 0, 1, 1,
+                    at<float>(ws, o_m[nlev - 1]), at<long long>(ws, o_e[nlev - 1]), at<long long>(ws, o_s[nlev - 1]),
+                    nullptr, nullptr, nullptr) != hipSuccess)
+        return HMM_E_DEVICE;
     PostDesc d;
     d.flag = flag;
     d.xy = xy;
@@ -609,40 +762,54 @@ int posterior_impl(hmm_ctx *ctx, int32_t K, const double *delta, const double *G
     d.delta = delta;
     d.mu = mu;
     d.status = status;
-    d.Mseg = mseg;
-    d.Eseg = eseg;
-    d.Mgrp = mgrp;
-    d.Egrp = egrp;
-    d.Agrp = at<double>(ws, ly.agrp);
-    d.Cgrp = at<double>(ws, ly.cgrp);
-    d.CgrpE = at<long long>(ws, ly.cgrpe);
-    d.Aseg = at<double>(ws, ly.aseg);
-    d.Cseg = at<double>(ws, ly.cseg);
-    d.CsegE = at<long long>(ws, ly.csege);
-    d.gamma = gamma ? gamma : at<float>(ws, ly.gam);
-    d.part_xi = at<float>(ws, ly.pxi);
-    d.part_mom = at<float>(ws, ly.pmom);
-    d.part_pre = at<float>(ws, ly.ppre);
+    d.Aseg = at<double>(ws, o_a[0]);
+    d.Cseg = at<double>(ws, o_c[0]);
+    d.CsegE = at<long long>(ws, o_ce[0]);
+    d.gamma = gamma ? gamma : at<float>(ws, o_gam);
+    d.part_xi = at<float>(ws, o_pxi);
+    d.part_mom = at<float>(ws, o_pmom);
+    d.part_pre = at<float>(ws, o_ppre);
     d.T = T;
     d.L = L;
     d.nb = nb;
-    d.n1 = n1;
     d.K = K;
     d.KP = KP;
-    d.G = G;
-    d.pad = 0;
     if (nb > 0) {
-        hipLaunchKernelGGL(k_post_scan_groups, dim3(2), dim3(64), 0, st, d);
-        hipLaunchKernelGGL(k_post_scan_segments, dim3((unsigned)n1), dim3(128), 0, st, d);
+        // messages, top level down to the segments
+        for (int l = nlev - 1; l >= 0; --l) {
+            ScanLevel sl;
+            sl.M = at<float>(ws, o_m[l]);
+            sl.E = at<long long>(ws, o_e[l]);
+            sl.n = cnt[l];
+            const bool top = (l == nlev - 1);
+            sl.pA = top ? nullptr : at<double>(ws, o_a[l + 1]);
+            sl.pC = top ? nullptr : at<double>(ws, o_c[l + 1]);
+            sl.pCE = top ? nullptr : at<long long>(ws, o_ce[l + 1]);
+            sl.A = at<double>(ws, o_a[l]);
+            sl.C = at<double>(ws, o_c[l]);
+            sl.CE = at<long long>(ws, o_ce[l]);
+            sl.delta = delta;
+            sl.K = K;
+            sl.KP = KP;
+            sl.G = G;
+            sl.pad = 0;
+            const unsigned parents = top ? 1u : (unsigned)cnt[l + 1];
+            hipLaunchKernelGGL(k_post_scan_level, dim3(parents), dim3(128), 0, st, sl);
+        }
         if (K <= 16) launch_local<16>(d, st);
         else if (K <= 32) launch_local<32>(d, st);
         else launch_local<64>(d, st);
     }
-    double *out_stats = need_stats_ws ? at<double>(ws, ly.stats) : stats;
+    double *out_stats = need_stats_ws ? at<double>(ws, o_stats) : stats;
     if (stats_ws) *stats_ws = out_stats;
     if (out_stats) {
-        const int64_t n = (int64_t)K * K + K;
-        hipLaunchKernelGGL(k_post_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, d, out_stats);
+        double *part = at<double>(ws, o_part);
+        if (nb > 0) {
+            launch_colsum(d.part_xi, nb, (int64_t)K * K, part, out_stats, st);
+            launch_colsum(d.part_mom, nb, (int64_t)K * kMoments, part + (size_t)kSumChunks * K * K,
+                          out_stats + K * K + K, st);
+        }
+        hipLaunchKernelGGL(k_post_finish, dim3(1), dim3(64), 0, st, d, out_stats);
     }
     return hipGetLastError() == hipSuccess ? HMM_OK : HMM_E_DEVICE;
 }
