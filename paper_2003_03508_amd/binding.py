@@ -76,6 +76,7 @@ _lib.mcmc_checkpoint_load.argtypes = [_vp, _vp, _i64, _vp]
 _lib.mcmc_set_companion.argtypes = [_vp, _vp, _vp]
 _lib.hmm_posterior.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp]
 _lib.hmm_loglik_grad.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp]
+_lib.hmm_viterbi.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp]
 _lib.mcmc_set_twalk.argtypes = [_vp, _vp]
 
 
@@ -104,7 +105,7 @@ for _f in ("hmm_ctx_create", "hmm_ctx_destroy", "hmm_loglik", "hmm_emission",
            "mlp_forward",
            "mlp_loss_grad", "mlp_set_weights", "mcmc_checkpoint_size", "mcmc_checkpoint_save",
            "mcmc_checkpoint_load", "mcmc_set_companion", "mcmc_set_twalk", "hmm_posterior",
-           "hmm_loglik_grad"):
+           "hmm_loglik_grad", "hmm_viterbi"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 
@@ -252,6 +253,18 @@ class Context:
         o = [0, K, K + K * K, 2 * K + K * K, 4 * K + K * K, 7 * K + K * K]
         return ll, dict(delta=g[o[0]:o[1]], Gamma=g[o[1]:o[2]].view(K, K), p=g[o[2]:o[3]],
                         mu=g[o[3]:o[4]].view(K, 2), Sigma=g[o[4]:o[5]].view(K, 3))
+
+    def viterbi(self, delta, Gamma, p, mu, Sigma, flag, xy, stream=None):
+        """Most likely path: (path int32 (T,), first int32 (1,), score float64 (1,)) on the device."""
+        K, T, args = self._params(delta, Gamma, p, mu, Sigma, flag, xy)
+        dev = delta.device
+        path = torch.empty(max(T, 1), dtype=torch.int32, device=dev)
+        first = torch.empty(1, dtype=torch.int32, device=dev)
+        score = torch.empty(1, dtype=torch.float64, device=dev)
+        _check("hmm_viterbi", _lib.hmm_viterbi(self._h, K, *args, _stream(stream),
+                                               path.data_ptr() if T else None, first.data_ptr(),
+                                               score.data_ptr()))
+        return path[:T], first, score
 
     def batch_graph(self, on=True):
         _check("hmm_ctx_set_batch_graph", _lib.hmm_ctx_set_batch_graph(self._h, 1 if on else 0))

@@ -1,0 +1,458 @@
+// Most likely hidden path (Viterbi) of the tremor HMM of eq. (2), in the
+// max-plus (log2) semiring, parallel over time with the same segment
+// structure as the likelihood (section "The likelihood algorithm").
+//
+// For a segment b of L observations, its max-plus product
+//   V_b[i][j] = max over paths inside the segment from state i (before its
+//               first observation) to state j (at its last) of
+//               sum_t (log2 Gamma + log2 e_t)
+// is formed step by step, V <- (V (x) log2 Gamma) + log2 e_t, renormalised by
+// its largest entry after every step (the subtracted amounts accumulate into
+// an FP64 offset).  Groups of G products are combined level by level (the
+// fold tree).  Decoding runs top-down: the top level starts from log2 delta,
+// picks the best end state and backtracks through its children; every lower
+// parent knows its start state (the end state of its left neighbour) and its
+// end state, so a max-plus recursion over its G children from the one-hot
+// start, with argmax pointers, gives the states at its children's ends.  At
+// the bottom every segment runs the plain Viterbi recursion between its two
+// boundary states with backpointers and writes its part of the path.  Ties
+// go to the smallest state index everywhere, as in the textbook recursion.
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstdint>
+#include <vector>
+
+#include "hmm_host.hpp"
+
+using namespace hmm;
+using namespace hmmh;
+
+namespace {
+
+constexpr int kVitG = 16;                // children per parent
+constexpr int64_t kVitSegments = 4096;   // target segment count
+
+__device__ __forceinline__ void vsync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+__device__ __forceinline__ void vsync_global()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+struct VitDesc {
+    const uint8_t *flag;
+    const double *xy;
+    const StateConst *sc;     // log2 emission constants (k_prepare)
+    const double *Gamma;      // [K][K]
+    const double *delta;      // [K]
+    const int *status;
+    int64_t T, L, nb;
+    int K, pad;
+};
+
+// log2 Gamma (KB x KB, -inf outside K) into LDS.
+template <int KB>
+__device__ __forceinline__ void load_lg(const VitDesc &d, float *lg)
+{
+    for (int idx = threadIdx.x; idx < KB * KB; idx += blockDim.x) {
+        const int r = idx / KB, c = idx % KB;
+        lg[idx] = (r < d.K && c < d.K) ? (float)log2(d.Gamma[r * d.K + c]) : -INFINITY;
+    }
+    __syncthreads();
+}
+
+// log2 e_t,j of one chunk into lam[j * kChunk + tl] (FP64 per observation,
+// rounded once to FP32); lane = step.  -inf for states >= K.
+template <int KB>
+__device__ __forceinline__ void stage_log_emissions(const VitDesc &d, int64_t tc, int nst, float *lam)
+{
+    const int lane = threadIdx.x & 63;
+    int f = 0;
+    double x = 0.0, y = 0.0;
+    if (lane < nst) {
+        f = d.flag[tc + lane];
+        if (f == 1) {
+            const double2 p = reinterpret_cast<const double2 *>(d.xy)[tc + lane];
+            x = p.x;
+            y = p.y;
+        }
+    }
+    for (int k = 0; k < KB; ++k)
+        lam[k * kChunk + lane] = (k < d.K && lane < nst) ? (float)state_log2_emission(d.sc[k], f == 1, x, y)
+                                                           : -INFINITY;
+    vsync();
+}
+
+// Lane layout of a KB x KB max-plus matrix: lane l owns column j = l % KB
+// and rows i = l / KB + (64 / KB) r, r < KB * KB / 64.
+template <int KB> constexpr int vit_rows() { return KB * KB / 64; }
+
+__device__ __forceinline__ float wave_max(float v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+    return v;
+}
+
+// Segment products: one wavefront per segment.  Vout[b] (KB x KB, log2,
+// relative), off[b] (FP64 log2 offset).
+template <int KB>
+__global__ __launch_bounds__(128) void k_vit_segment(VitDesc d, float *Vout, double *off)
+{
+    constexpr int NW = 2, R = vit_rows<KB>(), RS = 64 / KB;
+    __shared__ __attribute__((aligned(16))) float lg[KB * KB];
+    __shared__ __attribute__((aligned(16))) float vb[NW][KB * KB];
+    __shared__ __attribute__((aligned(16))) float lam[NW][KB * kChunk];
+    load_lg<KB>(d, lg);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t b = (int64_t)blockIdx.x * NW + w;
+    if (b >= d.nb || *d.status != 0) return;
+    const int64_t t0 = b * d.L, t1 = min(d.T, t0 + d.L);
+    const int j = lane % KB, ib = lane / KB;
+    float lgc[KB];
+#pragma unroll
+    for (int k = 0; k < KB; ++k) lgc[k] = lg[k * KB + j];
+    float V[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) V[r] = (ib + RS * r == j) ? 0.f : -INFINITY;   // max-plus identity
+    float *M = vb[w], *L2 = lam[w];
+    double acc = 0.0;
+    for (int64_t tc = t0; tc < t1; tc += kChunk) {
+        const int nst = (int)min((int64_t)kChunk, t1 - tc);
+        stage_log_emissions<KB>(d, tc, nst, L2);
+        for (int tl = 0; tl < nst; ++tl) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) M[(ib + RS * r) * KB + j] = V[r];
+            vsync();
+            const float e = L2[j * kChunk + tl];
+            float mx = -INFINITY;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const float *row = M + (ib + RS * r) * KB;
+                float m0 = -INFINITY, m1 = -INFINITY;
+#pragma unroll
+                for (int k = 0; k < KB; k += 2) {
+                    m0 = fmaxf(m0, row[k] + lgc[k]);
+                    m1 = fmaxf(m1, row[k + 1] + lgc[k + 1]);
+                }
+                V[r] = fmaxf(m0, m1) + e;
+                mx = fmaxf(mx, V[r]);
+            }
+            mx = wave_max(mx);
+            if (mx > -INFINITY) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) V[r] -= mx;
+                acc += (double)mx;
+            }
+            vsync();
+        }
+    }
+    float *out = Vout + b * KB * KB;
+#pragma unroll
+    for (int r = 0; r < R; ++r) out[(ib + RS * r) * KB + j] = V[r];
+    if (lane == 0) off[b] = acc;
+}
+
+// Parents of one fold level: block q (one wavefront) multiplies its children
+// [qG, min(qG + G, n)) left to right in max-plus, renormalising by the
+// largest entry; off[q] = sum of the children's offsets + renormalisation.
+template <int KB>
+__global__ __launch_bounds__(64) void k_vit_fold(int64_t n, const float *Vin, const double *offin, float *Vout,
+                                                 double *offout)
+{
+    constexpr int R = vit_rows<KB>(), RS = 64 / KB;
+    __shared__ __attribute__((aligned(16))) float P[KB * KB], Q[KB * KB];
+    const int lane = threadIdx.x, j = lane % KB, ib = lane / KB;
+    const int64_t q = blockIdx.x, c0 = q * kVitG, c1 = min(n, c0 + kVitG);
+    float V[R];
+    const float *src = Vin + c0 * KB * KB;
+#pragma unroll
+    for (int r = 0; r < R; ++r) V[r] = src[(ib + RS * r) * KB + j];
+    double acc = offin[c0];
+    for (int64_t c = c0 + 1; c < c1; ++c) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) P[(ib + RS * r) * KB + j] = V[r];
+        const float *nxt = Vin + c * KB * KB;
+        for (int idx = lane; idx < KB * KB; idx += 64) Q[idx] = nxt[idx];
+        vsync();
+        float mx = -INFINITY;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const float *row = P + (ib + RS * r) * KB;
+            float m = -INFINITY;
+            for (int k = 0; k < KB; ++k) m = fmaxf(m, row[k] + Q[k * KB + j]);
+            V[r] = m;
+            mx = fmaxf(mx, m);
+        }
+        mx = wave_max(mx);
+        if (mx > -INFINITY) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) V[r] -= mx;
+            acc += (double)mx;
+        }
+        acc += offin[c];
+        vsync();
+    }
+    float *out = Vout + q * KB * KB;
+#pragma unroll
+    for (int r = 0; r < R; ++r) out[(ib + RS * r) * KB + j] = V[r];
+    if (lane == 0) offout[q] = acc;
+}
+
+// Decoding of one level.  Block q (one wavefront, lane = state) takes parent
+// q's children [qG, min(qG + G, n)):
+//   top level (start < 0): d = log2 delta (FP64), end state = argmax of the
+//     final d (smallest index on ties); writes the score (log2) and s_-1;
+//   otherwise d starts one-hot at the parent's start state (the end state of
+//     parent q - 1, or s_-1 for q = 0) and the end state is the parent's.
+// d_c[j] = max_i (d_{c-1}[i] + V_c[i][j]) with argmax psi_c[j]; then
+// end(c - 1) = psi_c[end(c)] down to the first child, whose psi gives the
+// start state (checked against the known one).  Child end states go to
+// cend[c].  FP64 accumulation of d over at most G children.
+template <int KB>
+__global__ __launch_bounds__(64) void k_vit_decode(int K, int64_t n, const float *V, const double *off,
+                                                   const int32_t *pend, const int32_t *pfirst, int32_t *cend,
+                                                   int32_t *first, double *score, const double *delta,
+                                                   const int *status)
+{
+    __shared__ double dv[64];
+    __shared__ int32_t psi[kVitG][KB];
+    const int lane = threadIdx.x;
+    const int64_t q = blockIdx.x, c0 = q * kVitG, c1 = min(n, c0 + kVitG);
+    const bool top = (pend == nullptr);
+    int s_in = -1;
+    if (!top) s_in = (q == 0) ? *pfirst : pend[q - 1];
+    if (*status != 0) {   // results are discarded; keep every index in range
+        if (lane == 0) {
+            for (int64_t c = c0; c < c1; ++c) cend[c] = 0;
+            if (top) {
+                *first = 0;
+                *score = 0.0;
+            }
+        }
+        return;
+    }
+    double dj;
+    if (top) dj = (lane < K) ? log2(delta[lane]) : -INFINITY;
+    else dj = (lane == s_in) ? 0.0 : -INFINITY;
+    for (int64_t c = c0; c < c1; ++c) {
+        dv[lane] = dj;
+        vsync();
+        const float *M = V + c * KB * KB;
+        double best = -INFINITY;
+        int arg = 0;
+        if (lane < K)
+            for (int i = 0; i < K; ++i) {
+                const double s = dv[i] + (double)M[i * KB + lane];
+                if (s > best) {
+                    best = s;
+                    arg = i;
+                }
+            }
+        if (lane < KB) psi[c - c0][lane] = arg;
+        dj = (lane < K) ? best + off[c] : -INFINITY;
+        vsync();
+    }
+    dv[lane] = dj;
+    vsync();
+    if (lane == 0) {
+        int e;
+        if (top) {
+            double best = -INFINITY;
+            e = 0;
+            for (int i = 0; i < K; ++i)
+                if (dv[i] > best) {
+                    best = dv[i];
+                    e = i;
+                }
+            *score = best;
+        } else {
+            e = pend[q];
+        }
+        for (int64_t c = c1 - 1; c >= c0; --c) {
+            cend[c] = e;
+            e = psi[c - c0][e];
+        }
+        if (top) *first = e;
+    }
+}
+
+// Bottom: segment b runs the Viterbi recursion from its start state (end of
+// segment b - 1, or s_-1) with backpointers psi[t][j] (uint8, in LDS), then
+// backtracks from its end state and writes path[t0 .. t1).  The running
+// scores are renormalised by their largest value after every step (read back
+// from LDS by every lane).
+constexpr int kVitMaxL = 512;   // longest segment of the plan
+
+template <int KB>
+__global__ __launch_bounds__(128) void k_vit_local(VitDesc d, const int32_t *send, const int32_t *first,
+                                                   int32_t *path)
+{
+    constexpr int NW = 2;
+    __shared__ __attribute__((aligned(16))) float lg[KB * KB];
+    __shared__ __attribute__((aligned(16))) float dv[NW][KB];
+    __shared__ __attribute__((aligned(16))) float lam[NW][KB * kChunk];
+    __shared__ uint8_t psi[NW][kVitMaxL * KB];
+    load_lg<KB>(d, lg);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t b = (int64_t)blockIdx.x * NW + w;
+    if (b >= d.nb) return;
+    const int64_t t0 = b * d.L, t1 = min(d.T, t0 + d.L);
+    if (*d.status != 0) {
+        for (int64_t t = t0 + lane; t < t1; t += 64) path[t] = -1;
+        return;
+    }
+    const int K = d.K;
+    const int jc = lane < KB ? lane : 0;
+    float lgc[KB];
+#pragma unroll
+    for (int k = 0; k < KB; ++k) lgc[k] = lg[k * KB + jc];
+    const int s_in = (b == 0) ? *first : send[b - 1];
+    float *dd = dv[w], *L2 = lam[w];
+    uint8_t *ps = psi[w];
+    if (lane < KB) dd[lane] = (lane == s_in) ? 0.f : -INFINITY;
+    vsync();
+    for (int64_t tc = t0; tc < t1; tc += kChunk) {
+        const int nst = (int)min((int64_t)kChunk, t1 - tc);
+        stage_log_emissions<KB>(d, tc, nst, L2);
+        for (int tl = 0; tl < nst; ++tl) {
+            float best = -INFINITY;
+            int arg = 0;
+#pragma unroll
+            for (int i = 0; i < KB; ++i) {
+                const float s = dd[i] + lgc[i];
+                if (s > best) {
+                    best = s;
+                    arg = i;
+                }
+            }
+            const float v = (lane < K) ? best + L2[jc * kChunk + tl] : -INFINITY;
+            if (lane < KB) ps[(tc + tl - t0) * KB + lane] = (uint8_t)arg;
+            vsync();
+            if (lane < KB) dd[lane] = v;
+            vsync();
+            float mx = -INFINITY;
+#pragma unroll
+            for (int i = 0; i < KB; ++i) mx = fmaxf(mx, dd[i]);
+            vsync();
+            if (lane < KB && mx > -INFINITY) dd[lane] = v - mx;
+            vsync();
+        }
+    }
+    if (lane == 0) {
+        int e = send[b];
+        for (int64_t t = t1 - 1; t >= t0; --t) {
+            path[t] = e;
+            e = ps[(t - t0) * KB + e];
+        }
+    }
+}
+
+// Score in natural log; NaN, s_-1 = -1 for invalid parameters or data.
+__global__ void k_vit_finish(const int *status, double *score, int32_t *first)
+{
+    if (threadIdx.x != 0) return;
+    if (*status != 0) {
+        *score = __builtin_nan("");
+        *first = -1;
+    } else {
+        *score = *score * 0.69314718055994530941723212145818;
+    }
+}
+
+template <int KB>
+int viterbi_impl(hmm_ctx *ctx, int32_t K, const double *delta, const double *Gamma, const double *p,
+                 const double *mu, const double *Sigma, int64_t T, const uint8_t *flag, const double *xy,
+                 hipStream_t st, int32_t *path, int32_t *first, double *score)
+{
+    const int64_t L = ctx->block_len > 0
+                          ? std::min<int64_t>(ctx->block_len, kVitMaxL)
+                          : std::min<int64_t>(kVitMaxL, std::max<int64_t>(32, (T + kVitSegments - 1) / kVitSegments));
+    const int64_t nb = T > 0 ? (T + L - 1) / L : 0;
+    std::vector<int64_t> cnt{nb};
+    while (cnt.back() > kVitG) cnt.push_back((cnt.back() + kVitG - 1) / kVitG);
+    const int nlev = (int)cnt.size();
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align_up(off + std::max<size_t>(bytes, 1));
+        return o;
+    };
+    const size_t o_status = take(sizeof(int));
+    const size_t o_sc = take(sizeof(StateConst) * KB);
+    const size_t o_gf = take(sizeof(float) * KB * KB);
+    std::vector<size_t> o_v(nlev), o_o(nlev), o_e(nlev);
+    for (int l = 0; l < nlev; ++l) {
+        const size_t n = (size_t)std::max<int64_t>(cnt[l], 1);
+        o_v[l] = take(sizeof(float) * KB * KB * n);
+        o_o[l] = take(sizeof(double) * n);
+        o_e[l] = take(sizeof(int32_t) * n);
+    }
+    int rc = ensure_ws(ctx, off);
+    if (rc != HMM_OK) return rc;
+    void *ws = ctx->ws;
+    int *status = at<int>(ws, o_status);
+    StateConst *sc = at<StateConst>(ws, o_sc);
+    hipLaunchKernelGGL(k_prepare, dim3(1), dim3(256), 0, st, (int)kEmisTremor, K, KB, delta, Gamma, p, mu, Sigma, sc,
+                       at<float>(ws, o_gf), status);
+    VitDesc d;
+    d.flag = flag;
+    d.xy = xy;
+    d.sc = sc;
+    d.Gamma = Gamma;
+    d.delta = delta;
+    d.status = status;
+    d.T = T;
+    d.L = L;
+    d.nb = nb;
+    d.K = K;
+    d.pad = 0;
+    if (nb > 0) {
+        hipLaunchKernelGGL(k_vit_segment<KB>, dim3((unsigned)((nb + 1) / 2)), dim3(128), 0, st, d,
+                           at<float>(ws, o_v[0]), at<double>(ws, o_o[0]));
+        for (int l = 1; l < nlev; ++l)
+            hipLaunchKernelGGL(k_vit_fold<KB>, dim3((unsigned)cnt[l]), dim3(64), 0, st, cnt[l - 1],
+                               at<float>(ws, o_v[l - 1]), at<double>(ws, o_o[l - 1]), at<float>(ws, o_v[l]),
+                               at<double>(ws, o_o[l]));
+    }
+    // top level, then every level down to the segments
+    hipLaunchKernelGGL(k_vit_decode<KB>, dim3(1), dim3(64), 0, st, K, nb > 0 ? cnt[nlev - 1] : 0,
+                       at<float>(ws, o_v[nlev - 1]), at<double>(ws, o_o[nlev - 1]), (const int32_t *)nullptr,
+                       (const int32_t *)nullptr, at<int32_t>(ws, o_e[nlev - 1]), first, score, delta, status);
+    for (int l = nlev - 2; l >= 0; --l)
+        hipLaunchKernelGGL(k_vit_decode<KB>, dim3((unsigned)cnt[l + 1]), dim3(64), 0, st, K, cnt[l],
+                           at<float>(ws, o_v[l]), at<double>(ws, o_o[l]), at<int32_t>(ws, o_e[l + 1]),
+                           (const int32_t *)first, at<int32_t>(ws, o_e[l]), first, score, delta, status);
+    if (nb > 0)
+        hipLaunchKernelGGL(k_vit_local<KB>, dim3((unsigned)((nb + 1) / 2)), dim3(128), 0, st, d,
+                           at<int32_t>(ws, o_e[0]), (const int32_t *)first, path);
+    hipLaunchKernelGGL(k_vit_finish, dim3(1), dim3(64), 0, st, status, score, first);
+    return hipGetLastError() == hipSuccess ? HMM_OK : HMM_E_DEVICE;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hmm_viterbi(hmm_ctx *ctx, int32_t K, const double *delta, const double *Gamma, const double *p,
+                const double *mu, const double *Sigma, int64_t T, const uint8_t *flag, const double *xy,
+                void *stream, int32_t *path, int32_t *first, double *score)
+{
+    if (!ctx || !delta || !Gamma || !p || !mu || !Sigma || !first || !score) return HMM_E_INVALID_ARG;
+    if (K < 1 || T < 0 || T >= kMaxT || (T > 0 && (!flag || !xy || !path))) return HMM_E_INVALID_ARG;
+    if (K > 32) return HMM_E_UNSUPPORTED;
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return HMM_E_DEVICE;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (K <= 16) return viterbi_impl<16>(ctx, K, delta, Gamma, p, mu, Sigma, T, flag, xy, st, path, first, score);
+    return viterbi_impl<32>(ctx, K, delta, Gamma, p, mu, Sigma, T, flag, xy, st, path, first, score);
+}
+
+}  // extern "C"
