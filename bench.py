@@ -474,10 +474,11 @@ def bench_twalk(args):
 
 
 def bench_posterior(args):
-    """Forward-backward on the headline data (K=25, T=1e6, seed 1): state
-    posteriors gamma (T x K, FP32), expected transitions and moments; the
-    gradient of ln L; the likelihood alone for comparison; errors against the
-    FP64 oracle's forward-backward, which is also timed on one host thread."""
+    """Forward-backward and Viterbi on the headline data (K=25, T=1e6, seed 1):
+    state posteriors gamma (T x K, FP32), expected transitions and moments; the
+    gradient of ln L; the most likely path; the likelihood alone for
+    comparison; errors against the FP64 oracle's forward-backward and Viterbi,
+    which are also timed on one host thread."""
     import numpy as np
     import torch
     from paper_2003_03508_amd import binding, synth
@@ -500,13 +501,20 @@ def bench_posterior(args):
 
     def ll():
         out["l"] = ctx.loglik(**d)
-    for name, fn in (("loglik", ll), ("posterior", post), ("gradient", grad)):
+
+    def vit():
+        out["v"] = ctx.viterbi(**d)
+    for name, fn in (("loglik", ll), ("posterior", post), ("gradient", grad), ("viterbi", vit)):
         sec = _timed(fn, steps, 3)
         res[name] = {"ms": round(sec * 1e3, 4), "per_s": round(1.0 / sec, 2)}
     torch.cuda.synchronize()
     c0 = time.perf_counter()
     want = oracle.posterior(prm.delta, prm.Gamma, prm.p, prm.mu, prm.Sigma, obs.flag, obs.xy)
     c1 = time.perf_counter()
+    v0 = time.perf_counter()
+    vscore, vpath, vfirst = oracle.viterbi(prm.delta, prm.Gamma, prm.p, prm.mu, prm.Sigma, obs.flag, obs.xy)
+    v1 = time.perf_counter()
+    gpath, gfirst, gscore = (x.cpu().numpy() for x in out["v"])
     g_want = oracle.grad_from_stats(prm.delta, prm.Gamma, prm.p, prm.mu, prm.Sigma, want["xi"], want["pre"],
                                     want["mom"])
     p = {k: v.cpu().numpy().astype(np.float64) for k, v in out["p"].items()}
@@ -526,6 +534,9 @@ def bench_posterior(args):
         "rel_err_moments": float(np.abs(p["mom"] - want["mom"]).max() / np.abs(want["mom"]).max()),
         "rel_err_gradient_max_block": gerr,
         "rel_err_loglik": abs(float(p["loglik"][0]) - want["loglik"]) / abs(want["loglik"]),
+        "viterbi_rel_err_score": abs(float(gscore[0]) - vscore) / abs(vscore),
+        "viterbi_path_positions_differing": int((gpath != vpath).sum()),
+        "viterbi_cpu_oracle_s": round(v1 - v0, 3),
         "local_pass_algorithmic_bytes": (34 + 12 * K) * T, "local_pass_algorithmic_flops": 8 * K * K * T,
         "cpu_baseline": {"value": round(1.0 / (c1 - c0), 4), "unit": "evaluations/s", "cores": 1,
                          "kind": "oracle", "sample": f"one FP64 forward-backward of the full workload, "
