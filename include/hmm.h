@@ -475,6 +475,28 @@ int hmm_viterbi(hmm_ctx *ctx, int32_t K, const double *delta, const double *Gamm
                 const uint8_t *flag, const double *xy, void *stream, int32_t *path,
                 int32_t *first, double *score);
 
+/* Posterior-predictive simulation (section "Forecasting"): for every draw
+ * d < n, a parameter set in the packed layout delta | Gamma | p | mu | Sigma
+ * (params: device double [n][K*(K+7)], delta unused; e.g. the output of
+ * hmm_theta_to_params for posterior samples) and a distribution of the
+ * state before the first simulated step (start: device double [n][K]; for
+ * a forecast after the data, gamma of the last observed step from
+ * hmm_posterior), H steps of eq. (1)-(2):
+ *   s_-1 ~ start_d;  s_t ~ Gamma[s_{t-1}, .];  f_t ~ Bernoulli(p_{s_t});
+ *   x_t = mu + C z (C the lower Cholesky factor of Sigma_{s_t}) if f_t = 1.
+ * A categorical draw with uniform u takes the smallest k with u < w_0 + ...
+ * + w_k (FP64, ascending), the last k with w_k > 0 if rounding leaves u
+ * above the total; all-zero weights end the draw's path (state -1, flag 0,
+ * NaN location from that step on).  Random numbers: Philox with counter
+ * (0, d, t, purpose), purpose 10 the pair (u_state, u_flag) of step t,
+ * 11 the Box-Muller pair (z0, z1) of step t, 12 (first uniform, step 0)
+ * for s_-1.  Outputs (device, step-major): states int32 [H][n],
+ * flags uint8 [H][n], xy double [H][n][2] (NaN when f = 0), first int32 [n]
+ * (s_-1).  Parameters are not validated.  FP64 throughout. */
+int hmm_simulate(hmm_ctx *ctx, int32_t n, int32_t K, const double *params, const double *start,
+                 int32_t H, uint64_t seed, void *stream, int32_t *states, uint8_t *flags,
+                 double *xy, int32_t *first);
+
 /* Philox draws of the sampler's streams: for i < n, out[2i], out[2i+1] are
  * the two uniforms (normal = 0) or Box-Muller normals (normal = 1) of counter
  * (i, chain, iter, purpose).  out: device double[2n] (may be NULL when n = 0). */

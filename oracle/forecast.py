@@ -14,7 +14,8 @@ the model of eq. (1)-(2), Gamma applied before every emission:
 A categorical draw with weights w and uniform u takes the smallest k with
 u < w_0 + ... + w_k (sums in ascending order, FP64); if rounding leaves u
 above the total, the last k with w_k > 0.  A Bernoulli(p) draw is 1 when
-u < p.
+u < p.  A categorical draw over weights that are all zero ends the draw's
+path: that step and every later one get state -1, flag 0 and no location.
 
 Random numbers (Philox, see philox.py), counter (index 0, draw, step, purpose):
     purpose 10, step t: (u_state, u_flag) of step t
@@ -67,12 +68,16 @@ def simulate_one(block, start, K, H, step_fn, u_init):
     G, p, mu, S = unpack(block, K)
     s = categorical(start, u_init)
     first = s
-    states = np.empty(H, dtype=np.int32)
-    flags = np.empty(H, dtype=np.uint8)
+    states = np.full(H, -1, dtype=np.int32)
+    flags = np.zeros(H, dtype=np.uint8)
     xy = np.full((H, 2), np.nan)
     for t in range(H):
+        if s < 0:
+            break
         us, uf, z0, z1 = step_fn(t)
         s = categorical(G[s], us)
+        if s < 0:
+            break
         states[t] = s
         f = 1 if uf < p[s] else 0
         flags[t] = f

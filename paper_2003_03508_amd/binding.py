@@ -77,6 +77,7 @@ _lib.mcmc_set_companion.argtypes = [_vp, _vp, _vp]
 _lib.hmm_posterior.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp]
 _lib.hmm_loglik_grad.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp]
 _lib.hmm_viterbi.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp]
+_lib.hmm_simulate.argtypes = [_vp, _i32, _i32, _vp, _vp, _i32, ctypes.c_uint64, _vp, _vp, _vp, _vp, _vp]
 _lib.mcmc_set_twalk.argtypes = [_vp, _vp]
 
 
@@ -105,7 +106,7 @@ for _f in ("hmm_ctx_create", "hmm_ctx_destroy", "hmm_loglik", "hmm_emission",
            "mlp_forward",
            "mlp_loss_grad", "mlp_set_weights", "mcmc_checkpoint_size", "mcmc_checkpoint_save",
            "mcmc_checkpoint_load", "mcmc_set_companion", "mcmc_set_twalk", "hmm_posterior",
-           "hmm_loglik_grad", "hmm_viterbi"):
+           "hmm_loglik_grad", "hmm_viterbi", "hmm_simulate"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 
@@ -265,6 +266,23 @@ class Context:
                                                path.data_ptr() if T else None, first.data_ptr(),
                                                score.data_ptr()))
         return path[:T], first, score
+
+    def simulate(self, K, params, start, H, seed=0, stream=None):
+        """Posterior-predictive paths of n draws: dict states (H, n) int32, flags (H, n)
+        uint8, xy (H, n, 2) float64, first (n,) int32 (device tensors)."""
+        n = int(start.numel()) // int(K)
+        dev = start.device
+        states = torch.empty((H, n), dtype=torch.int32, device=dev)
+        flags = torch.empty((H, n), dtype=torch.uint8, device=dev)
+        xy = torch.empty((H, n, 2), dtype=torch.float64, device=dev)
+        first = torch.empty(n, dtype=torch.int32, device=dev)
+        nh = n * int(H)
+        _check("hmm_simulate", _lib.hmm_simulate(
+            self._h, n, int(K), _dev(params, torch.float64, "params", n * K * (K + 7)),
+            _dev(start, torch.float64, "start", n * K), int(H), int(seed), _stream(stream),
+            states.data_ptr() if nh else None, flags.data_ptr() if nh else None, xy.data_ptr() if nh else None,
+            first.data_ptr() if n else None))
+        return dict(states=states, flags=flags, xy=xy, first=first)
 
     def batch_graph(self, on=True):
         _check("hmm_ctx_set_batch_graph", _lib.hmm_ctx_set_batch_graph(self._h, 1 if on else 0))

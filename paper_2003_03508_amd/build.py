@@ -13,7 +13,8 @@ UNITS = [(os.path.join(CSRC, "hmm_api.hip"), ["-mllvm", "-amdgpu-mfma-vgpr-form=
          (os.path.join(CSRC, "hmm_batch.hip"), []),
          (os.path.join(CSRC, "hmm_sampler.hip"), []),
          (os.path.join(CSRC, "hmm_posterior.hip"), []),
-         (os.path.join(CSRC, "hmm_viterbi.hip"), [])]
+         (os.path.join(CSRC, "hmm_viterbi.hip"), []),
+         (os.path.join(CSRC, "hmm_forecast.hip"), [])]
 SOURCES = [u[0] for u in UNITS]
 DEPS = SOURCES + [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hpp")] + [
     os.path.join(os.path.dirname(HERE), "include", "hmm.h")]

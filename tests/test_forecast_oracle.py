@@ -83,6 +83,17 @@ def test_start_distribution_and_first_step():
     assert stats.chisquare(np.bincount(s0, minlength=K), want * n).pvalue > 1e-4
 
 
+def test_dead_end_stops_the_path():
+    K = 2
+    prm = _params(K, 5)
+    prm.Gamma = np.array([[0.0, 1.0], [0.0, 0.0]])      # state 1 has no way out
+    step, u0 = _numpy_draws(np.random.default_rng(7), 5)
+    st, fl, xy, first = forecast.simulate_one(synth.HMMParams.packed(prm), np.array([1.0, 0.0]), K, 5, step, u0)
+    assert first == 0 and st[0] == 1 and (st[1:] == -1).all() and not fl[1:].any() and np.isnan(xy[1:]).all()
+    st, fl, xy, first = forecast.simulate_one(synth.HMMParams.packed(prm), np.zeros(2), K, 5, step, u0)
+    assert first == -1 and (st == -1).all()
+
+
 def test_philox_stream_layout():
     step, u0 = forecast.philox_draws(9, 3)
     assert u0 == philox.uniform2(9, 12, 0, 3, 0)[0]
