@@ -23,6 +23,7 @@ Other workloads (one JSON line each, not the headline):
     python bench.py --workload kinds_k25  # Poisson-count and 1-D Gaussian HMMs, K=25, T=1e6
     python bench.py --workload twalk_k25  # the t-walk sampler, K=25, T=105,000
     python bench.py --workload posterior_k25  # forward-backward and gradient, K=25, T=1e6
+    python bench.py --workload forecast_k25   # posterior-predictive paths, K=25, 120 hours
 """
 import argparse
 import json
@@ -79,7 +80,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--workload", default="k25_t1e6",
                     choices=["k25_t1e6", "k80_t4m", "batch256", "mcmc_k20", "kinds_k25", "twalk_k25",
-                             "posterior_k25"])
+                             "posterior_k25", "forecast_k25"])
     ap.add_argument("--twalk-chains", type=int, default=64)
     ap.add_argument("--no-mcmc", action="store_true", help="skip the MCMC leg of the default run")
     ap.add_argument("--mcmc-iterations", type=int, default=10000)
@@ -116,6 +117,8 @@ def main():
         return bench_twalk(args)
     if args.workload == "posterior_k25":
         return bench_posterior(args)
+    if args.workload == "forecast_k25":
+        return bench_forecast(args)
     if args.workload == "mcmc_k20":
         print(json.dumps(run_mcmc(C=args.mcmc_chains, n_iter=args.mcmc_iterations, lag=args.mcmc_lag,
                                   log=True)))
@@ -542,6 +545,50 @@ def bench_posterior(args):
                          "kind": "oracle", "sample": f"one FP64 forward-backward of the full workload, "
                                                      f"{c1 - c0:.2f} s"},
     }))
+
+
+def bench_forecast(args):
+    """Posterior-predictive simulation at K=25, 120 hourly steps: the paper's
+    500 draws, and 100,000 draws for throughput (synthetic parameter draws,
+    seed 3).  Bytes written per draw-step: state 4 + flag 1 + location 16.
+    The oracle simulates a sample of draws on one host thread."""
+    import numpy as np
+    import torch
+    from paper_2003_03508_amd import binding, synth
+    from oracle import forecast
+    K, H = 25, 120
+    rng = np.random.default_rng(3)
+    ctx = binding.Context(0)
+    f64 = dict(dtype=torch.float64, device="cuda")
+    res = {}
+    for n in (500, 100_000):
+        base = [synth.draw_params(rng, K) for _ in range(min(n, 500))]
+        blocks = np.array([base[d % len(base)].packed() for d in range(n)])
+        starts = rng.dirichlet(np.ones(K), size=n)
+        bt, st = torch.as_tensor(blocks, **f64).contiguous(), torch.as_tensor(starts, **f64).contiguous()
+        out = {}
+
+        def run():
+            out["r"] = ctx.simulate(K, bt, st, H, seed=2012)
+        sec = _timed(run, max(5, args.steps // 10), 2)
+        gb = 21.0 * n * H / sec / 1e9
+        res[f"draws_{n}"] = {"ms": round(sec * 1e3, 4), "draw_steps_per_s": round(n * H / sec, 1),
+                             "written_GB_per_s": round(gb, 2), "frac_hbm_peak": round(gb / PEAK_HBM_GBS, 4)}
+        if n == 500:
+            got = {k: v.cpu().numpy() for k, v in out["r"].items()}
+            c0 = time.perf_counter()
+            ok = True
+            for d in range(20):
+                step, u0 = forecast.philox_draws(2012, d)
+                s_, f_, _, f0 = forecast.simulate_one(blocks[d], starts[d], K, H, step, u0)
+                ok = ok and np.array_equal(got["states"][:, d], s_) and np.array_equal(got["flags"][:, d], f_)
+            c1 = time.perf_counter()
+            res["oracle_agrees_on_20_draws"] = bool(ok)
+            cpu = {"value": round(20 / (c1 - c0), 2), "unit": "draws/s", "cores": 1, "kind": "oracle",
+                   "sample": f"20 draws of 120 hours, {c1 - c0:.2f} s"}
+    ctx.close()
+    print(json.dumps({"workload": "forecast_k25: posterior-predictive tremor paths, K=25, 120 hourly steps per draw",
+                      "unit": "draw-steps/s", "results": res, "cpu_baseline": cpu}))
 
 
 def run_mcmc(C=8, burn_rounds=12, adapt_rounds=6, round_len=1000, n_iter=10000, lag=5, train_steps=500,

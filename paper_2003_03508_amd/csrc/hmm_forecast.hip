@@ -21,14 +21,26 @@ constexpr uint32_t kDrawSimInit = 12;    // the state before the first step
 
 // Smallest k with u < w_0 + ... + w_k (ascending FP64 sums); the last k with
 // w_k > 0 if rounding leaves u above the total; -1 if every weight is 0.
+// The weights are read in chunks of 8 whose loads are all issued before the
+// chunk is scanned (the same sums in the same order as a plain scan).
 __device__ __forceinline__ int categorical(const double *w, int K, double u)
 {
     double c = 0.0;
     int last = -1;
-    for (int k = 0; k < K; ++k) {
-        c += w[k];
-        if (w[k] > 0.0) last = k;
-        if (u < c) return k;
+    for (int k0 = 0; k0 < K; k0 += 8) {
+        double v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = (k0 + q < K) ? w[k0 + q] : 0.0;
+        int hit = -1;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            if (k0 + q < K) {
+                c += v[q];
+                if (v[q] > 0.0) last = k0 + q;
+                if (hit < 0 && u < c) hit = k0 + q;
+            }
+        }
+        if (hit >= 0) return hit;
     }
     return last;
 }
