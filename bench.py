@@ -607,9 +607,11 @@ def run_mcmc(C=8, burn_rounds=12, adapt_rounds=6, round_len=1000, n_iter=10000, 
        (lagged pairs, 20% held out; least-squares start of its linear part,
        then Adam steps kept only where the held-out loss improves), timed,
        and frozen.
-    3. n_iter iterations of each method.  ESS per coordinate (multi-chain,
-       Geyer) and of the log posterior; ESS/s = ESS / wall time, the learned
-       method's time including its training.
+    3. n_iter iterations of each method (random walk, learned, and the
+       paper's own sampler, the t-walk, whose second points are the
+       neighbouring chains' burn-in end states).  ESS per coordinate
+       (multi-chain, Geyer) and of the log posterior; ESS/s = ESS / wall time,
+       the learned method's time including its training.
     Agreement of the two runs' posterior means is reported as z-scores
     (difference over the combined Monte Carlo standard error).
     """
@@ -683,8 +685,12 @@ def run_mcmc(C=8, burn_rounds=12, adapt_rounds=6, round_len=1000, n_iter=10000, 
         f"(kept step {tr['best_step']})")
 
     res, draws = {}, {}
-    for name, prop in (("random_walk", binding.MCMC_RANDOM_WALK), ("learned", binding.MCMC_LEARNED)):
+    for name, prop in (("random_walk", binding.MCMC_RANDOM_WALK), ("learned", binding.MCMC_LEARNED),
+                       ("twalk", binding.MCMC_TWALK)):
         ch.set_state(start, f64(rw))
+        if prop == binding.MCMC_TWALK:
+            # second points: the burn-in end states of the neighbouring chains
+            ch.set_companion(torch.roll(start, 1, dims=0).contiguous())
         dt, acc = run(n_iter, prop)
         w, lpost = window(n_iter)
         ess = E.ess_columns(w)
@@ -702,7 +708,7 @@ def run_mcmc(C=8, burn_rounds=12, adapt_rounds=6, round_len=1000, n_iter=10000, 
             f"min {ess.min():.1f}, {dt:.2f} s")
     ch.close()
     ctx.close()
-    a, b = res["random_walk"], res["learned"]
+    a, b, tw = res["random_walk"], res["learned"], res["twalk"]
     z = np.abs(draws["random_walk"][0] - draws["learned"][0]) / np.sqrt(
         draws["random_walk"][1] ** 2 + draws["learned"][1] ** 2)
     gain = lambda k: round(b[k] / a[k], 3) if a[k] > 0 else None
@@ -712,8 +718,14 @@ def run_mcmc(C=8, burn_rounds=12, adapt_rounds=6, round_len=1000, n_iter=10000, 
         "chains": C, "iterations": n_iter, "burn_in": burn, "burn_in_seconds": round(t_burn, 3),
         "train_seconds": round(t_train, 3), "train_steps": train_steps, "kept_adam_step": tr["best_step"],
         "held_out_loss": [round(float(val[0]), 3), round(float(val.min()), 3)],
-        "lag": lag, "mixture_eps": eps, "random_walk": a, "learned": b,
+        "lag": lag, "mixture_eps": eps, "random_walk": a, "learned": b, "twalk": tw,
+        "twalk_note": "the paper's sampler (Christen & Fox defaults: about n1 = 4 of the 480 coordinates move "
+                      "per iteration), second points = neighbouring chains' burn-in end states",
         "ess_per_s_gain_median": gain("ess_per_s_median"),
+        "ess_per_s_gain_vs_twalk_median": round(b["ess_per_s_median"] / tw["ess_per_s_median"], 3)
+        if tw["ess_per_s_median"] > 0 else None,
+        "ess_per_s_gain_vs_twalk_logpost": round(b["ess_per_s_logpost"] / tw["ess_per_s_logpost"], 3)
+        if tw["ess_per_s_logpost"] > 0 else None,
         "ess_per_s_gain_logpost": gain("ess_per_s_logpost"),
         "ess_per_s_gain_min": gain("ess_per_s_min"),
         "mean_agreement_z_median": round(float(np.median(z)), 3),
