@@ -102,8 +102,10 @@ __device__ __forceinline__ float wave_max(float v)
 }
 
 // Segment products: one wavefront per segment.  Vout[b] (KB x KB, log2,
-// relative), off[b] (FP64 log2 offset).
-template <int KB>
+// relative), off[b] (FP64 log2 offset).  KK = K at compile time: the
+// contraction runs over exactly K terms and rows >= K are skipped (their
+// entries stay -inf).
+template <int KB, int KK>
 __global__ __launch_bounds__(128) void k_vit_segment(VitDesc d, float *Vout, double *off)
 {
     constexpr int NW = 2, R = vit_rows<KB>(), RS = 64 / KB;
@@ -121,7 +123,7 @@ __global__ __launch_bounds__(128) void k_vit_segment(VitDesc d, float *Vout, dou
     for (int k = 0; k < KB; ++k) lgc[k] = lg[k * KB + j];
     float V[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) V[r] = (ib + RS * r == j) ? 0.f : -INFINITY;   // max-plus identity
+    for (int r = 0; r < R; ++r) V[r] = (ib + RS * r == j && j < KK) ? 0.f : -INFINITY;   // max-plus identity
     float *M = vb[w], *L2 = lam[w];
     double acc = 0.0;
     for (int64_t tc = t0; tc < t1; tc += kChunk) {
@@ -135,14 +137,16 @@ __global__ __launch_bounds__(128) void k_vit_segment(VitDesc d, float *Vout, dou
             float mx = -INFINITY;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
+                if (RS * r >= KK) break;   // rows ib + RS r >= K for every lane
                 const float *row = M + (ib + RS * r) * KB;
                 float m0 = -INFINITY, m1 = -INFINITY;
 #pragma unroll
-                for (int k = 0; k < KB; k += 2) {
+                for (int k = 0; k + 1 < KK; k += 2) {
                     m0 = fmaxf(m0, row[k] + lgc[k]);
                     m1 = fmaxf(m1, row[k + 1] + lgc[k + 1]);
                 }
-                V[r] = fmaxf(m0, m1) + e;
+                if constexpr (KK % 2 == 1) m0 = fmaxf(m0, row[KK - 1] + lgc[KK - 1]);
+                V[r] = (ib + RS * r < KK) ? fmaxf(m0, m1) + e : -INFINITY;
                 mx = fmaxf(mx, V[r]);
             }
             mx = wave_max(mx);
@@ -291,7 +295,7 @@ __global__ __launch_bounds__(64) void k_vit_decode(int K, int64_t n, const float
 // from LDS by every lane).
 constexpr int kVitMaxL = 512;   // longest segment of the plan
 
-template <int KB>
+template <int KB, int KK>
 __global__ __launch_bounds__(128) void k_vit_local(VitDesc d, const int32_t *send, const int32_t *first,
                                                    int32_t *path)
 {
@@ -326,7 +330,7 @@ __global__ __launch_bounds__(128) void k_vit_local(VitDesc d, const int32_t *sen
             float best = -INFINITY;
             int arg = 0;
 #pragma unroll
-            for (int i = 0; i < KB; ++i) {
+            for (int i = 0; i < KK; ++i) {
                 const float s = dd[i] + lgc[i];
                 if (s > best) {
                     best = s;
@@ -340,7 +344,7 @@ __global__ __launch_bounds__(128) void k_vit_local(VitDesc d, const int32_t *sen
             vsync();
             float mx = -INFINITY;
 #pragma unroll
-            for (int i = 0; i < KB; ++i) mx = fmaxf(mx, dd[i]);
+            for (int i = 0; i < KK; ++i) mx = fmaxf(mx, dd[i]);
             vsync();
             if (lane < KB && mx > -INFINITY) dd[lane] = v - mx;
             vsync();
@@ -365,6 +369,44 @@ __global__ void k_vit_finish(const int *status, double *score, int32_t *first)
     } else {
         *score = *score * 0.69314718055994530941723212145818;
     }
+}
+
+// The segment kernel compiled for exactly K states (KB = 16: K <= 16,
+// KB = 32: 16 < K <= 32).
+template <int KB, int LO, int HI>
+const void *segment_kernel_in(int K)
+{
+    if constexpr (LO > HI) {
+        return nullptr;
+    } else {
+        if (K == LO) return reinterpret_cast<const void *>(&k_vit_segment<KB, LO>);
+        return segment_kernel_in<KB, LO + 1, HI>(K);
+    }
+}
+
+template <int KB>
+const void *segment_kernel(int K)
+{
+    if constexpr (KB == 16) return segment_kernel_in<16, 1, 16>(K);
+    else return segment_kernel_in<32, 17, 32>(K);
+}
+
+template <int KB, int LO, int HI>
+const void *local_kernel_in(int K)
+{
+    if constexpr (LO > HI) {
+        return nullptr;
+    } else {
+        if (K == LO) return reinterpret_cast<const void *>(&k_vit_local<KB, LO>);
+        return local_kernel_in<KB, LO + 1, HI>(K);
+    }
+}
+
+template <int KB>
+const void *local_kernel(int K)
+{
+    if constexpr (KB == 16) return local_kernel_in<16, 1, 16>(K);
+    else return local_kernel_in<32, 17, 32>(K);
 }
 
 template <int KB>
@@ -415,8 +457,13 @@ int viterbi_impl(hmm_ctx *ctx, int32_t K, const double *delta, const double *Gam
     d.K = K;
     d.pad = 0;
     if (nb > 0) {
-        hipLaunchKernelGGL(k_vit_segment<KB>, dim3((unsigned)((nb + 1) / 2)), dim3(128), 0, st, d,
-                           at<float>(ws, o_v[0]), at<double>(ws, o_o[0]));
+        const void *seg = segment_kernel<KB>(K);
+        if (!seg) return HMM_E_UNSUPPORTED;
+        float *v0 = at<float>(ws, o_v[0]);
+        double *f0 = at<double>(ws, o_o[0]);
+        void *args[] = {&d, &v0, &f0};
+        if (hipLaunchKernel(seg, dim3((unsigned)((nb + 1) / 2)), dim3(128), args, 0, st) != hipSuccess)
+            return HMM_E_DEVICE;
         for (int l = 1; l < nlev; ++l)
             hipLaunchKernelGGL(k_vit_fold<KB>, dim3((unsigned)cnt[l]), dim3(64), 0, st, cnt[l - 1],
                                at<float>(ws, o_v[l - 1]), at<double>(ws, o_o[l - 1]), at<float>(ws, o_v[l]),
@@ -430,9 +477,14 @@ int viterbi_impl(hmm_ctx *ctx, int32_t K, const double *delta, const double *Gam
         hipLaunchKernelGGL(k_vit_decode<KB>, dim3((unsigned)cnt[l + 1]), dim3(64), 0, st, K, cnt[l],
                            at<float>(ws, o_v[l]), at<double>(ws, o_o[l]), at<int32_t>(ws, o_e[l + 1]),
                            (const int32_t *)first, at<int32_t>(ws, o_e[l]), first, score, delta, status);
-    if (nb > 0)
-        hipLaunchKernelGGL(k_vit_local<KB>, dim3((unsigned)((nb + 1) / 2)), dim3(128), 0, st, d,
-                           at<int32_t>(ws, o_e[0]), (const int32_t *)first, path);
+    if (nb > 0) {
+        const void *loc = local_kernel<KB>(K);
+        if (!loc) return HMM_E_UNSUPPORTED;
+        int32_t *e0 = at<int32_t>(ws, o_e[0]);
+        void *args[] = {&d, &e0, &first, &path};
+        if (hipLaunchKernel(loc, dim3((unsigned)((nb + 1) / 2)), dim3(128), args, 0, st) != hipSuccess)
+            return HMM_E_DEVICE;
+    }
     hipLaunchKernelGGL(k_vit_finish, dim3(1), dim3(64), 0, st, status, score, first);
     return hipGetLastError() == hipSuccess ? HMM_OK : HMM_E_DEVICE;
 }
