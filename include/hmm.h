@@ -462,14 +462,14 @@ int hmm_loglik_grad(hmm_ctx *ctx, int32_t K, const double *delta, const double *
  * segments (log2, FP32, renormalised every step; FP64 offsets), combined in
  * groups of 16 level by level, decoded top-down, then a Viterbi pass with
  * backpointers inside every segment between its two boundary states.  Ties
- * go to the smallest state index.  1 <= K <= 32.
+ * go to the smallest state index.  1 <= K <= 64.
  *   path   device int32 [T]: s_0 .. s_{T-1} (required when T > 0)
  *   first  device int32 [1]: s_{-1}
  *   score  device double [1]: the maximum (natural log)
  * T = 0: first = argmax delta, score = ln max delta.  Invalid parameters or
  * data: score NaN, first and path -1.  FP32 scores inside segments: a path
  * whose joint log probability is within about 1e-6 relative of the best one
- * may be returned instead of it.  HMM_E_UNSUPPORTED for K > 32. */
+ * may be returned instead of it.  HMM_E_UNSUPPORTED for K > 64. */
 int hmm_viterbi(hmm_ctx *ctx, int32_t K, const double *delta, const double *Gamma,
                 const double *p, const double *mu, const double *Sigma, int64_t T,
                 const uint8_t *flag, const double *xy, void *stream, int32_t *path,

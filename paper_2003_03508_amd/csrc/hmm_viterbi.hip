@@ -95,6 +95,11 @@ __device__ __forceinline__ void stage_log_emissions(const VitDesc &d, int64_t tc
 // and rows i = l / KB + (64 / KB) r, r < KB * KB / 64.
 template <int KB> constexpr int vit_rows() { return KB * KB / 64; }
 
+// Wavefronts per workgroup of the segment and backtracking kernels (their LDS
+// grows with KB), and the longest segment the backtracking kernel holds.
+template <int KB> constexpr int vit_waves() { return KB <= 32 ? 2 : 1; }
+template <int KB> constexpr int vit_max_len() { return KB <= 32 ? 512 : 256; }
+
 __device__ __forceinline__ float wave_max(float v)
 {
     for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
@@ -106,9 +111,9 @@ __device__ __forceinline__ float wave_max(float v)
 // contraction runs over exactly K terms and rows >= K are skipped (their
 // entries stay -inf).
 template <int KB, int KK>
-__global__ __launch_bounds__(128) void k_vit_segment(VitDesc d, float *Vout, double *off)
+__global__ __launch_bounds__(64 * vit_waves<KB>()) void k_vit_segment(VitDesc d, float *Vout, double *off)
 {
-    constexpr int NW = 2, R = vit_rows<KB>(), RS = 64 / KB;
+    constexpr int NW = vit_waves<KB>(), R = vit_rows<KB>(), RS = 64 / KB;
     __shared__ __attribute__((aligned(16))) float lg[KB * KB];
     __shared__ __attribute__((aligned(16))) float vb[NW][KB * KB];
     __shared__ __attribute__((aligned(16))) float lam[NW][KB * kChunk];
@@ -293,17 +298,15 @@ __global__ __launch_bounds__(64) void k_vit_decode(int K, int64_t n, const float
 // backtracks from its end state and writes path[t0 .. t1).  The running
 // scores are renormalised by their largest value after every step (read back
 // from LDS by every lane).
-constexpr int kVitMaxL = 512;   // longest segment of the plan
-
 template <int KB, int KK>
-__global__ __launch_bounds__(128) void k_vit_local(VitDesc d, const int32_t *send, const int32_t *first,
-                                                   int32_t *path)
+__global__ __launch_bounds__(64 * vit_waves<KB>()) void k_vit_local(VitDesc d, const int32_t *send,
+                                                                    const int32_t *first, int32_t *path)
 {
-    constexpr int NW = 2;
+    constexpr int NW = vit_waves<KB>();
     __shared__ __attribute__((aligned(16))) float lg[KB * KB];
     __shared__ __attribute__((aligned(16))) float dv[NW][KB];
     __shared__ __attribute__((aligned(16))) float lam[NW][KB * kChunk];
-    __shared__ uint8_t psi[NW][kVitMaxL * KB];
+    __shared__ uint8_t psi[NW][vit_max_len<KB>() * KB];
     load_lg<KB>(d, lg);
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t b = (int64_t)blockIdx.x * NW + w;
@@ -384,11 +387,13 @@ const void *segment_kernel_in(int K)
     }
 }
 
+// 33 <= K <= 64: one instance padded to 64 states (entries beyond K stay -inf).
 template <int KB>
 const void *segment_kernel(int K)
 {
     if constexpr (KB == 16) return segment_kernel_in<16, 1, 16>(K);
-    else return segment_kernel_in<32, 17, 32>(K);
+    else if constexpr (KB == 32) return segment_kernel_in<32, 17, 32>(K);
+    else return reinterpret_cast<const void *>(&k_vit_segment<64, 64>);
 }
 
 template <int KB, int LO, int HI>
@@ -406,7 +411,8 @@ template <int KB>
 const void *local_kernel(int K)
 {
     if constexpr (KB == 16) return local_kernel_in<16, 1, 16>(K);
-    else return local_kernel_in<32, 17, 32>(K);
+    else if constexpr (KB == 32) return local_kernel_in<32, 17, 32>(K);
+    else return reinterpret_cast<const void *>(&k_vit_local<64, 64>);
 }
 
 template <int KB>
@@ -414,9 +420,10 @@ int viterbi_impl(hmm_ctx *ctx, int32_t K, const double *delta, const double *Gam
                  const double *mu, const double *Sigma, int64_t T, const uint8_t *flag, const double *xy,
                  hipStream_t st, int32_t *path, int32_t *first, double *score)
 {
+    constexpr int64_t maxL = vit_max_len<KB>();
     const int64_t L = ctx->block_len > 0
-                          ? std::min<int64_t>(ctx->block_len, kVitMaxL)
-                          : std::min<int64_t>(kVitMaxL, std::max<int64_t>(32, (T + kVitSegments - 1) / kVitSegments));
+                          ? std::min<int64_t>(ctx->block_len, maxL)
+                          : std::min<int64_t>(maxL, std::max<int64_t>(32, (T + kVitSegments - 1) / kVitSegments));
     const int64_t nb = T > 0 ? (T + L - 1) / L : 0;
     std::vector<int64_t> cnt{nb};
     while (cnt.back() > kVitG) cnt.push_back((cnt.back() + kVitG - 1) / kVitG);
@@ -462,7 +469,8 @@ int viterbi_impl(hmm_ctx *ctx, int32_t K, const double *delta, const double *Gam
         float *v0 = at<float>(ws, o_v[0]);
         double *f0 = at<double>(ws, o_o[0]);
         void *args[] = {&d, &v0, &f0};
-        if (hipLaunchKernel(seg, dim3((unsigned)((nb + 1) / 2)), dim3(128), args, 0, st) != hipSuccess)
+        constexpr int NW = vit_waves<KB>();
+        if (hipLaunchKernel(seg, dim3((unsigned)((nb + NW - 1) / NW)), dim3(64 * NW), args, 0, st) != hipSuccess)
             return HMM_E_DEVICE;
         for (int l = 1; l < nlev; ++l)
             hipLaunchKernelGGL(k_vit_fold<KB>, dim3((unsigned)cnt[l]), dim3(64), 0, st, cnt[l - 1],
@@ -482,7 +490,8 @@ int viterbi_impl(hmm_ctx *ctx, int32_t K, const double *delta, const double *Gam
         if (!loc) return HMM_E_UNSUPPORTED;
         int32_t *e0 = at<int32_t>(ws, o_e[0]);
         void *args[] = {&d, &e0, &first, &path};
-        if (hipLaunchKernel(loc, dim3((unsigned)((nb + 1) / 2)), dim3(128), args, 0, st) != hipSuccess)
+        constexpr int NW = vit_waves<KB>();
+        if (hipLaunchKernel(loc, dim3((unsigned)((nb + NW - 1) / NW)), dim3(64 * NW), args, 0, st) != hipSuccess)
             return HMM_E_DEVICE;
     }
     hipLaunchKernelGGL(k_vit_finish, dim3(1), dim3(64), 0, st, status, score, first);
@@ -499,12 +508,13 @@ int hmm_viterbi(hmm_ctx *ctx, int32_t K, const double *delta, const double *Gamm
 {
     if (!ctx || !delta || !Gamma || !p || !mu || !Sigma || !first || !score) return HMM_E_INVALID_ARG;
     if (K < 1 || T < 0 || T >= kMaxT || (T > 0 && (!flag || !xy || !path))) return HMM_E_INVALID_ARG;
-    if (K > 32) return HMM_E_UNSUPPORTED;
+    if (K > 64) return HMM_E_UNSUPPORTED;
     DeviceGuard dg(ctx->device);
     if (!dg.ok) return HMM_E_DEVICE;
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (K <= 16) return viterbi_impl<16>(ctx, K, delta, Gamma, p, mu, Sigma, T, flag, xy, st, path, first, score);
-    return viterbi_impl<32>(ctx, K, delta, Gamma, p, mu, Sigma, T, flag, xy, st, path, first, score);
+    if (K <= 32) return viterbi_impl<32>(ctx, K, delta, Gamma, p, mu, Sigma, T, flag, xy, st, path, first, score);
+    return viterbi_impl<64>(ctx, K, delta, Gamma, p, mu, Sigma, T, flag, xy, st, path, first, score);
 }
 
 }  // extern "C"

@@ -51,7 +51,8 @@ def _check(binding, ctx, prm, obs, L=0, what=""):
 
 @pytest.mark.parametrize("K,T,L", [(1, 300, 32), (2, 50, 32), (3, 1000, 32), (3, 5003, 0), (8, 2999, 40),
                                    (16, 4000, 33), (17, 3001, 32), (25, 20000, 0), (25, 20000, 32),
-                                   (32, 2500, 32), (5, 1, 0)])
+                                   (32, 2500, 32), (5, 1, 0), (33, 2000, 32), (48, 3001, 40),
+                                   (64, 2500, 0)])
 def test_viterbi_matches_oracle(binding, ctx, K, T, L):
     prm, obs = synth.make(K, T, 300 + K)
     diff = _check(binding, ctx, prm, obs, L, (K, T, L))
@@ -84,7 +85,7 @@ def test_viterbi_edge_cases(binding, ctx):
     bad = synth.HMMParams(**{**prm.__dict__, "p": np.where(np.arange(4) == 0, 1.5, prm.p)})
     path, first, score = _run(binding, ctx, bad, obs)
     assert math.isnan(score) and first == -1 and (path == -1).all()
-    prm, obs = synth.make(33, 100, 9)
+    prm, obs = synth.make(65, 100, 9)
     with pytest.raises(binding.HMMError):
         ctx.viterbi(**binding.to_device(prm, obs))
 
