@@ -23,6 +23,7 @@ struct BatchClass {
     std::vector<int> sets;
     size_t job0 = 0, njobs = 0;   // WgJob table range
     size_t fjob0 = 0, nfjobs = 0; // FoldJob table range (one per set)
+    size_t pjob0 = 0, npjobs = 0; // pre-fold FoldJob table range (sets with many products)
     float *M = nullptr;
     long long *E = nullptr, *S = nullptr;
 };
@@ -43,6 +44,7 @@ struct BatchPlan {
     PrepJob *prep = nullptr;
     WgJob *jobs = nullptr;
     FoldJob *fjobs = nullptr;
+    FoldJob *pjobs = nullptr;
     std::vector<BatchClass> classes;
     // captured launch sequence (classes forked onto parallel branches)
     static constexpr int kBranches = 4;
@@ -77,6 +79,11 @@ namespace {
 // round is not left mostly empty (and a set too short to fill the chip in one
 // round at a longer length is cut finer).  A tuned value wins.
 constexpr int kWgOverhead = 32;
+
+// A set whose final fold would take more than kPrefoldF products per
+// wavefront gets one more fold level first (a lone long set cut into short
+// segments: its final workgroup would otherwise chain many products).
+constexpr int kPrefoldF = 2;
 
 int64_t class_L(const hmm_ctx *ctx, const BatchPlan &bp, const BatchClass &c, int algo, int W)
 {
@@ -147,7 +154,7 @@ int build(hmm_ctx *ctx, BatchPlan &bp)
     }
     // job tables (host)
     std::vector<WgJob> jobs;
-    std::vector<FoldJob> fjobs;
+    std::vector<FoldJob> fjobs, pjobs;
     std::vector<size_t> prods(bp.classes.size(), 0);
     for (size_t ci = 0; ci < bp.classes.size(); ++ci) {
         BatchClass &c = bp.classes[ci];
@@ -155,6 +162,7 @@ int build(hmm_ctx *ctx, BatchPlan &bp)
         c.L = class_L(ctx, bp, c, bp.algo, c.W);
         c.job0 = jobs.size();
         c.fjob0 = fjobs.size();
+        c.pjob0 = pjobs.size();
         int64_t base = 0;
         for (int s : c.sets) {
             const int64_t nb = bp.T[s] > 0 ? (bp.T[s] + c.L - 1) / c.L : 0;
@@ -175,11 +183,32 @@ int build(hmm_ctx *ctx, BatchPlan &bp)
             f.F = (int)std::max<int64_t>(1, (n1 + c.W2 - 1) / c.W2);
             f.final_ = 1;
             f.pad = 0;
-            fjobs.push_back(f);
             base += n1;
+            if (f.F > kPrefoldF) {
+                // a set with many products: one more fold level first, G = W2
+                // products per workgroup, into slots after the segment products
+                const int64_t npre = (n1 + c.W2 - 1) / c.W2;
+                for (int64_t q = 0; q < npre; ++q) {
+                    FoldJob g;
+                    g.in0 = f.in0 + q * c.W2;
+                    g.n_in = std::min<int64_t>(c.W2, n1 - q * c.W2);
+                    g.out = base + q;
+                    g.set = s;
+                    g.F = 1;
+                    g.final_ = 0;
+                    g.pad = 0;
+                    pjobs.push_back(g);
+                }
+                f.in0 = base;
+                f.n_in = npre;
+                f.F = (int)std::max<int64_t>(1, (npre + c.W2 - 1) / c.W2);
+                base += npre;
+            }
+            fjobs.push_back(f);
         }
         c.njobs = jobs.size() - c.job0;
         c.nfjobs = fjobs.size() - c.fjob0;
+        c.npjobs = pjobs.size() - c.pjob0;
         prods[ci] = (size_t)std::max<int64_t>(base, 1);
     }
     // device memory: tables, per-set slots, per-class products
@@ -192,6 +221,7 @@ int build(hmm_ctx *ctx, BatchPlan &bp)
     const size_t o_sets = take(sizeof(SetDesc) * n), o_prep = take(sizeof(PrepJob) * n);
     const size_t o_jobs = take(sizeof(WgJob) * std::max<size_t>(jobs.size(), 1));
     const size_t o_fjobs = take(sizeof(FoldJob) * std::max<size_t>(fjobs.size(), 1));
+    const size_t o_pjobs = take(sizeof(FoldJob) * std::max<size_t>(pjobs.size(), 1));
     const size_t o_status = take(sizeof(int) * n);
     const size_t o_ids = take(sizeof(int) * n);
     std::vector<size_t> o_sc(n), o_gf(n);
@@ -218,6 +248,7 @@ int build(hmm_ctx *ctx, BatchPlan &bp)
     bp.prep = reinterpret_cast<PrepJob *>(base + o_prep);
     bp.jobs = reinterpret_cast<WgJob *>(base + o_jobs);
     bp.fjobs = reinterpret_cast<FoldJob *>(base + o_fjobs);
+    bp.pjobs = reinterpret_cast<FoldJob *>(base + o_pjobs);
     int *status = reinterpret_cast<int *>(base + o_status);
     std::vector<int> ids;
     for (size_t ci = 0; ci < bp.classes.size(); ++ci) {
@@ -262,6 +293,8 @@ int build(hmm_ctx *ctx, BatchPlan &bp)
          hipMemcpy(bp.jobs, jobs.data(), sizeof(WgJob) * jobs.size(), hipMemcpyHostToDevice) != hipSuccess) ||
         (!fjobs.empty() &&
          hipMemcpy(bp.fjobs, fjobs.data(), sizeof(FoldJob) * fjobs.size(), hipMemcpyHostToDevice) != hipSuccess) ||
+        (!pjobs.empty() &&
+         hipMemcpy(bp.pjobs, pjobs.data(), sizeof(FoldJob) * pjobs.size(), hipMemcpyHostToDevice) != hipSuccess) ||
         (!ids.empty() &&
          hipMemcpy(reinterpret_cast<int *>(base + o_ids), ids.data(), sizeof(int) * ids.size(),
                    hipMemcpyHostToDevice) != hipSuccess))
@@ -289,6 +322,10 @@ int enqueue_class(const BatchPlan &bp, const BatchClass &c, hipStream_t st)
     if (c.njobs > 0 &&
         launch_seg(c.ks.segB, (unsigned)c.njobs, c.W, rb * c.W, st, none, bp.sets, bp.jobs + c.job0, 0, c.M, c.E,
                    c.S) != hipSuccess)
+        return HMM_E_DEVICE;
+    if (c.npjobs > 0 &&
+        launch_fold(c.ks.foldB, (unsigned)c.npjobs, c.W2, rb * c.W2, st, none, bp.sets, bp.pjobs + c.pjob0, 0, 1, 0,
+                    c.M, c.E, c.S, c.M, c.E, c.S) != hipSuccess)
         return HMM_E_DEVICE;
     if (launch_fold(c.ks.foldB, (unsigned)c.nfjobs, c.W2, rb * c.W2, st, none, bp.sets, bp.fjobs + c.fjob0, 0, 1,
                     1, c.M, c.E, c.S, nullptr, nullptr, nullptr) != hipSuccess)

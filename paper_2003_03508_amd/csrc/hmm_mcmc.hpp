@@ -150,22 +150,36 @@ __device__ inline double theta_to_block(int K, const double *__restrict__ th, do
     double *delta = blk, *G = blk + K, *p = G + K * K, *mu = p + K, *Sig = mu + 2 * K;
     const double *lg = th, *lp = th + K * (K - 1), *mth = lp + K, *lw = mth + 2 * K;
     double acc = 0.0;
-    // Gamma rows: softmax of (logits j != i, 0 at j = i), stable in FP64
-    for (int i = tid; i < K; i += nt) {
+    // Gamma rows: softmax of (logits j != i, 0 at j = i), stable in FP64, one
+    // wavefront per row (lane j holds entries j and j + 64)
+    const int lane = tid & 63, w = tid >> 6, nw = nt >> 6;
+    for (int i = w; i < K; i += nw) {
         const double *row = lg + (int64_t)i * (K - 1);
-        double mx = 0.0;
-        for (int j = 0; j < K - 1; ++j) mx = fmax(mx, row[j]);
-        double z = exp(-mx);
-        for (int j = 0; j < K - 1; ++j) z += exp(row[j] - mx);
+        double l[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int j = lane + 64 * h;
+            l[h] = (j < K) ? (j == i ? 0.0 : row[j < i ? j : j - 1]) : -INFINITY;
+        }
+        double mx = fmax(l[0], l[1]);
+        for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o));
+        double z = exp(l[0] - mx) + exp(l[1] - mx);
+        for (int o = 32; o > 0; o >>= 1) z += __shfl_xor(z, o);
         const double lz = mx + log(z);
         double slog = 0.0;
-        for (int j = 0, q = 0; j < K; ++j) {
-            const double l = (j == i) ? 0.0 : row[q++];
-            G[(int64_t)i * K + j] = exp(l - lz);
-            slog += l - lz;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int j = lane + 64 * h;
+            if (j < K) {
+                G[(int64_t)i * K + j] = exp(l[h] - lz);
+                slog += l[h] - lz;
+            }
         }
-        acc += kDirichletAlpha * slog;
-        delta[i] = 1.0 / K;
+        for (int o = 32; o > 0; o >>= 1) slog += __shfl_xor(slog, o);
+        if (lane == 0) {
+            acc += kDirichletAlpha * slog;
+            delta[i] = 1.0 / K;
+        }
     }
     for (int k = tid; k < K; k += nt) {
         const double z = lp[k];
