@@ -17,6 +17,7 @@ Contents
   * ``posterior`` / ``viterbi`` -- state posteriors by forward-backward (with
     expected transition counts and weighted moments) and the most likely path.
   * ``grad_from_stats`` -- the gradient of ln L from those expectations.
+  * ``em_mstep`` -- the EM (Baum-Welch) maximisation step from them.
 """
 import ctypes
 import os
@@ -266,3 +267,30 @@ def grad_from_stats(delta, Gamma, p, mu, Sigma, xi, pre, mom):
         G = 0.5 * Si @ (C - n1[k] * S) @ Si
         g_S[k] = (G[0, 0], 2.0 * G[0, 1], G[1, 1])
     return dict(delta=g_delta, Gamma=g_Gamma, p=g_p, mu=g_mu, Sigma=g_S)
+
+
+def em_mstep(xi, pre, mom):
+    """Maximisation step of EM (Baum-Welch) for eq. (2)'s model from the
+    posterior expectations of `posterior`: the complete-data maximum
+    likelihood with counts replaced by their expectations,
+      delta_i   = P(s_-1 = i | x)
+      Gamma_ij  = xi_ij / sum_j xi_ij
+      p_k       = n1_k / n_k            (expected tremor rate of state k)
+      mu_k      = s_k / n1_k            (weighted mean of its tremor locations)
+      Sigma_k   = S2_k / n1_k - mu_k mu_k^T  (weighted covariance)
+    with n_k = sum_t gamma_t,k, n1_k, s_k, S2_k the sums over tremor steps of
+    gamma, gamma x and gamma x x^T.  Returns (delta, Gamma, p, mu, Sigma)."""
+    xi = np.asarray(xi, dtype=np.float64)
+    pre = np.asarray(pre, dtype=np.float64)
+    mom = np.asarray(mom, dtype=np.float64)
+    K = pre.shape[0]
+    delta = pre / pre.sum()
+    Gamma = xi / xi.sum(axis=1, keepdims=True)
+    n, n1 = mom[:, 0], mom[:, 1]
+    p = n1 / n
+    mu = mom[:, 2:4] / n1[:, None]
+    Sigma = np.empty((K, 3))
+    Sigma[:, 0] = mom[:, 4] / n1 - mu[:, 0] ** 2
+    Sigma[:, 1] = mom[:, 5] / n1 - mu[:, 0] * mu[:, 1]
+    Sigma[:, 2] = mom[:, 6] / n1 - mu[:, 1] ** 2
+    return delta, Gamma, p, mu, Sigma
