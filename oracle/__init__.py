@@ -269,7 +269,7 @@ def grad_from_stats(delta, Gamma, p, mu, Sigma, xi, pre, mom):
     return dict(delta=g_delta, Gamma=g_Gamma, p=g_p, mu=g_mu, Sigma=g_S)
 
 
-def em_mstep(xi, pre, mom):
+def em_mstep(xi, pre, mom, prev=None):
     """Maximisation step of EM (Baum-Welch) for eq. (2)'s model from the
     posterior expectations of `posterior`: the complete-data maximum
     likelihood with counts replaced by their expectations,
@@ -279,18 +279,37 @@ def em_mstep(xi, pre, mom):
       mu_k      = s_k / n1_k            (weighted mean of its tremor locations)
       Sigma_k   = S2_k / n1_k - mu_k mu_k^T  (weighted covariance)
     with n_k = sum_t gamma_t,k, n1_k, s_k, S2_k the sums over tremor steps of
-    gamma, gamma x and gamma x x^T.  Returns (delta, Gamma, p, mu, Sigma)."""
+    gamma, gamma x and gamma x x^T.  An expected count of exactly zero leaves
+    its quotient undefined; with `prev` = (delta, Gamma, p, mu, Sigma) such
+    entries keep their previous value (a Gamma row never left, n_k = 0 for
+    p_k, n1_k = 0 for mu_k and Sigma_k), without it they are NaN.
+    Returns (delta, Gamma, p, mu, Sigma)."""
     xi = np.asarray(xi, dtype=np.float64)
     pre = np.asarray(pre, dtype=np.float64)
     mom = np.asarray(mom, dtype=np.float64)
     K = pre.shape[0]
-    delta = pre / pre.sum()
-    Gamma = xi / xi.sum(axis=1, keepdims=True)
     n, n1 = mom[:, 0], mom[:, 1]
-    p = n1 / n
-    mu = mom[:, 2:4] / n1[:, None]
-    Sigma = np.empty((K, 3))
-    Sigma[:, 0] = mom[:, 4] / n1 - mu[:, 0] ** 2
-    Sigma[:, 1] = mom[:, 5] / n1 - mu[:, 0] * mu[:, 1]
-    Sigma[:, 2] = mom[:, 6] / n1 - mu[:, 1] ** 2
+    rows = xi.sum(axis=1)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        delta = pre / pre.sum()
+        Gamma = xi / rows[:, None]
+        p = n1 / n
+        mu = mom[:, 2:4] / n1[:, None]
+        Sigma = np.empty((K, 3))
+        Sigma[:, 0] = mom[:, 4] / n1 - mu[:, 0] ** 2
+        Sigma[:, 1] = mom[:, 5] / n1 - mu[:, 0] * mu[:, 1]
+        Sigma[:, 2] = mom[:, 6] / n1 - mu[:, 1] ** 2
+    if prev is not None:
+        d0, G0, p0, mu0, S0 = (np.asarray(a, dtype=np.float64) for a in prev)
+        if pre.sum() == 0.0:
+            delta = d0.reshape(K).copy()
+        G0 = G0.reshape(K, K)
+        for k in range(K):
+            if rows[k] == 0.0:
+                Gamma[k] = G0[k]
+            if n[k] == 0.0:
+                p[k] = p0.reshape(K)[k]
+            if n1[k] == 0.0:
+                mu[k] = mu0.reshape(K, 2)[k]
+                Sigma[k] = S0.reshape(K, 3)[k]
     return delta, Gamma, p, mu, Sigma

@@ -118,3 +118,24 @@ def test_mstep_is_a_stationary_point_of_q():
     assert Q(d, G, p, mu, S * np.array([1.05, 1.0, 0.97])) < q0
     Gr = G * np.exp(rng.normal(0, 0.05, G.shape))
     assert Q(d, Gr / Gr.sum(axis=1, keepdims=True), p, mu, S) < q0
+
+
+def test_zero_counts_keep_the_previous_values():
+    """A state with p_k = 0 has n1_k = 0 (no tremor hour can be its): mu_k
+    and Sigma_k are left as they were, p_k stays 0.  With T = 0 only delta
+    is renormalised."""
+    prm, obs = synth.make(3, 1500, 11)
+    p = prm.p.copy()
+    p[1] = 0.0
+    r = oracle.posterior(prm.delta, prm.Gamma, p, prm.mu, prm.Sigma, obs.flag, obs.xy)
+    assert r["mom"][1, 1] == 0.0
+    d, G, pn, mu, S = oracle.em_mstep(r["xi"], r["pre"], r["mom"], (prm.delta, prm.Gamma, p, prm.mu, prm.Sigma))
+    assert pn[1] == 0.0 and np.array_equal(mu[1], prm.mu[1]) and np.array_equal(S[1], prm.Sigma[1])
+    assert np.all(np.isfinite(mu)) and np.allclose(G.sum(axis=1), 1.0)
+    _, G2, _, mu2, _ = oracle.em_mstep(r["xi"], r["pre"], r["mom"])
+    assert np.all(np.isnan(mu2[1]))
+    d0 = np.array([0.2, 0.2, 0.4])
+    r = oracle.posterior(d0, prm.Gamma, prm.p, prm.mu, prm.Sigma, obs.flag[:0], obs.xy[:0])
+    d, G, pn, mu, S = oracle.em_mstep(r["xi"], r["pre"], r["mom"], (d0, prm.Gamma, prm.p, prm.mu, prm.Sigma))
+    assert np.allclose(d, d0 / d0.sum()) and np.array_equal(G, prm.Gamma) and np.array_equal(pn, prm.p)
+    assert np.array_equal(mu, prm.mu) and np.array_equal(S, prm.Sigma)
