@@ -479,9 +479,10 @@ def bench_twalk(args):
 def bench_posterior(args):
     """Forward-backward and Viterbi on the headline data (K=25, T=1e6, seed 1):
     state posteriors gamma (T x K, FP32), expected transitions and moments; the
-    gradient of ln L; the most likely path; the likelihood alone for
-    comparison; errors against the FP64 oracle's forward-backward and Viterbi,
-    which are also timed on one host thread."""
+    gradient of ln L; one EM (Baum-Welch) iteration; the most likely path; the
+    likelihood alone for comparison; errors against the FP64 oracle's
+    forward-backward, M-step and Viterbi, which are also timed on one host
+    thread."""
     import numpy as np
     import torch
     from paper_2003_03508_amd import binding, synth
@@ -507,7 +508,11 @@ def bench_posterior(args):
 
     def vit():
         out["v"] = ctx.viterbi(**d)
-    for name, fn in (("loglik", ll), ("posterior", post), ("gradient", grad), ("viterbi", vit)):
+    packed = torch.as_tensor(prm.packed(), dtype=torch.float64, device="cuda").contiguous()
+
+    def em():
+        out["e"] = ctx.em_step(packed, K, d["flag"], d["xy"])
+    for name, fn in (("loglik", ll), ("posterior", post), ("gradient", grad), ("em_step", em), ("viterbi", vit)):
         sec = _timed(fn, steps, 3)
         res[name] = {"ms": round(sec * 1e3, 4), "per_s": round(1.0 / sec, 2)}
     torch.cuda.synchronize()
@@ -522,6 +527,9 @@ def bench_posterior(args):
                                     want["mom"])
     p = {k: v.cpu().numpy().astype(np.float64) for k, v in out["p"].items()}
     gl, gg = out["g"]
+    e_want = oracle.em_mstep(want["xi"], want["pre"], want["mom"], (prm.delta, prm.Gamma, prm.p, prm.mu, prm.Sigma))
+    e_got = out["e"][0].cpu().numpy()
+    e_want = np.concatenate([np.ravel(a) for a in e_want])
     gerr = max(float(np.abs(gg[n].cpu().numpy().reshape(np.shape(g_want[n])) - g_want[n]).max()
                      / np.abs(g_want[n]).max()) for n in g_want)
     ctx.close()
@@ -536,6 +544,7 @@ def bench_posterior(args):
         "rel_err_xi": float(np.abs(p["xi"] - want["xi"]).max() / np.abs(want["xi"]).max()),
         "rel_err_moments": float(np.abs(p["mom"] - want["mom"]).max() / np.abs(want["mom"]).max()),
         "rel_err_gradient_max_block": gerr,
+        "em_step_max_err_params": float((np.abs(e_got - e_want) / np.maximum(1.0, np.abs(e_want))).max()),
         "rel_err_loglik": abs(float(p["loglik"][0]) - want["loglik"]) / abs(want["loglik"]),
         "viterbi_rel_err_score": abs(float(gscore[0]) - vscore) / abs(vscore),
         "viterbi_path_positions_differing": int((gpath != vpath).sum()),

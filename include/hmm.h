@@ -455,6 +455,32 @@ int hmm_loglik_grad(hmm_ctx *ctx, int32_t K, const double *delta, const double *
                     const uint8_t *flag, const double *xy, void *stream, double *loglik,
                     double *grad);
 
+/* One EM (Baum-Welch) iteration for the tremor model of eq. (1)-(2): the
+ * E-step is hmm_posterior's forward-backward expectations, the M-step their
+ * complete-data maximum likelihood, in FP64 on the device:
+ *   delta_i  = P(s_{-1} = i | x)          Gamma_ij = xi_ij / sum_j xi_ij
+ *   p_k      = n1_k / n_k                 mu_k     = s_k / n1_k
+ *   Sigma_k  = S2_k / n1_k - mu_k mu_k^T  (expected covariance of the
+ *                                          tremor locations of state k)
+ * with n_k, n1_k, s_k, S2_k the expected counts and sums of hmm_posterior's
+ * moments.  An entry whose expected count is exactly zero (a Gamma row never
+ * left, n_k = 0, or n1_k = 0 for mu_k and Sigma_k) keeps its input value.
+ *   loglik      device double [1]: ln L of the INPUT parameters
+ *   params_out  device double [K + K*K + K + 2K + 3K]: the new parameters,
+ *               packed [delta | Gamma (row-major) | p | mu | Sigma (xx, xy,
+ *               yy)]; it may be the packed vector the five inputs point into
+ *               (delta = params_out, Gamma = delta + K, ...) for in-place
+ *               iteration, and must not overlap them otherwise.
+ * Invalid parameters or data: ln L and params_out NaN.  EM may drive a state
+ * to a singular Sigma (one tremor location); the next call then reports the
+ * parameters as invalid.  Needs T*K floats of workspace; enqueues on
+ * `stream`; HMM_E_UNSUPPORTED for K > 64.
+ * ------------------------------------------------------------------------ */
+int hmm_em_step(hmm_ctx *ctx, int32_t K, const double *delta, const double *Gamma,
+                const double *p, const double *mu, const double *Sigma, int64_t T,
+                const uint8_t *flag, const double *xy, void *stream, double *loglik,
+                double *params_out);
+
 /* Most likely hidden path (Viterbi) of the tremor model of eq. (1)-(2),
  * with s_{-1} ~ delta the state before x_0:
  *   max over s_{-1}, s_0, ..., s_{T-1} of ln(delta_{s_-1} prod_t Gamma_{s_t-1 s_t} e_t,s_t).

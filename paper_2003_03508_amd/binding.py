@@ -76,6 +76,7 @@ _lib.mcmc_checkpoint_load.argtypes = [_vp, _vp, _i64, _vp]
 _lib.mcmc_set_companion.argtypes = [_vp, _vp, _vp]
 _lib.hmm_posterior.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp]
 _lib.hmm_loglik_grad.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp]
+_lib.hmm_em_step.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp]
 _lib.hmm_viterbi.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp]
 _lib.hmm_simulate.argtypes = [_vp, _i32, _i32, _vp, _vp, _i32, ctypes.c_uint64, _vp, _vp, _vp, _vp, _vp]
 _lib.mcmc_set_twalk.argtypes = [_vp, _vp]
@@ -106,7 +107,7 @@ for _f in ("hmm_ctx_create", "hmm_ctx_destroy", "hmm_loglik", "hmm_emission",
            "mlp_forward",
            "mlp_loss_grad", "mlp_set_weights", "mcmc_checkpoint_size", "mcmc_checkpoint_save",
            "mcmc_checkpoint_load", "mcmc_set_companion", "mcmc_set_twalk", "hmm_posterior",
-           "hmm_loglik_grad", "hmm_viterbi", "hmm_simulate"):
+           "hmm_loglik_grad", "hmm_em_step", "hmm_viterbi", "hmm_simulate"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 
@@ -254,6 +255,26 @@ class Context:
         o = [0, K, K + K * K, 2 * K + K * K, 4 * K + K * K, 7 * K + K * K]
         return ll, dict(delta=g[o[0]:o[1]], Gamma=g[o[1]:o[2]].view(K, K), p=g[o[2]:o[3]],
                         mu=g[o[3]:o[4]].view(K, 2), Sigma=g[o[4]:o[5]].view(K, 3))
+
+    def em_step(self, params, K, flag, xy, out=None, loglik=None, stream=None):
+        """One EM iteration from the packed parameters [delta | Gamma | p | mu |
+        Sigma] (device float64): returns (new packed parameters, ln L of the
+        input).  out=params iterates in place; loglik may be a 1-element view
+        (e.g. one entry of a trace) that receives ln L."""
+        K = int(K)
+        n = K * (K + 7)
+        T = int(flag.numel())
+        prm = _dev(params, torch.float64, "params", n)
+        if out is None:
+            out = torch.empty(n, dtype=torch.float64, device=params.device)
+        if loglik is None:
+            loglik = torch.empty(1, dtype=torch.float64, device=params.device)
+        o = [0, K, K + K * K, 2 * K + K * K, 4 * K + K * K]
+        _check("hmm_em_step", _lib.hmm_em_step(
+            self._h, K, *[prm + 8 * i for i in o], T, _dev(flag, torch.uint8, "flag", T),
+            _dev(xy, torch.float64, "xy", 2 * T), _stream(stream), _dev(loglik, torch.float64, "loglik", 1),
+            _dev(out, torch.float64, "out", n)))
+        return out, loglik
 
     def viterbi(self, delta, Gamma, p, mu, Sigma, flag, xy, stream=None):
         """Most likely path: (path int32 (T,), first int32 (1,), score float64 (1,)) on the device."""

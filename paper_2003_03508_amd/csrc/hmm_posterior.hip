@@ -652,6 +652,53 @@ __global__ __launch_bounds__(256) void k_post_grad(int K, const double *delta, c
     }
 }
 
+// EM (Baum-Welch) maximisation step from the posterior expectations in
+// stats = [xi | pre | raw moments] (layout of k_post_finish), written as the
+// packed vector out = [delta (K) | Gamma (K*K) | p (K) | mu (2K) | Sigma (3K)]:
+//   delta_i  = pre_i / sum pre          Gamma_ij = xi_ij / sum_j xi_ij
+//   p_k      = n1_k / n_k               mu_k     = s_k / n1_k
+//   Sigma_k  = S2_k / n1_k - mu_k mu_k^T
+// An entry whose expected count is exactly zero (a Gamma row never left, a
+// state with no posterior mass, or none on tremor hours) carries no
+// information and keeps its previous value.  NaN statistics (invalid
+// parameters or data) give NaN.  Thread k reads and writes only the entries
+// of state k, so out may be the packed vector the inputs point into.
+__global__ __launch_bounds__(64) void k_em_mstep(int K, const double *delta, const double *Gamma, const double *p,
+                                                 const double *mu, const double *Sigma, const double *stats,
+                                                 double *out)
+{
+    const double *xi = stats, *pre = stats + K * K, *mom = pre + K;
+    double *od = out, *oG = out + K, *op = oG + K * K, *om = op + K, *oS = om + 2 * K;
+    double tot = 0.0;
+    for (int i = 0; i < K; ++i) tot += pre[i];
+    for (int k = threadIdx.x; k < K; k += blockDim.x) {
+        od[k] = tot == 0.0 ? delta[k] : pre[k] / tot;
+        const double *x = xi + k * K;
+        double r = 0.0;
+        for (int j = 0; j < K; ++j) r += x[j];
+        for (int j = 0; j < K; ++j) oG[k * K + j] = r == 0.0 ? Gamma[k * K + j] : x[j] / r;
+        const double *m = mom + k * kMoments;
+        const double n = m[0], n1 = m[1];
+        op[k] = n == 0.0 ? p[k] : n1 / n;
+        if (n1 == 0.0) {
+            const double mx = mu[2 * k], my = mu[2 * k + 1];
+            const double sxx = Sigma[3 * k], sxy = Sigma[3 * k + 1], syy = Sigma[3 * k + 2];
+            om[2 * k] = mx;
+            om[2 * k + 1] = my;
+            oS[3 * k] = sxx;
+            oS[3 * k + 1] = sxy;
+            oS[3 * k + 2] = syy;
+        } else {
+            const double mx = m[2] / n1, my = m[3] / n1;
+            om[2 * k] = mx;
+            om[2 * k + 1] = my;
+            oS[3 * k] = m[4] / n1 - mx * mx;
+            oS[3 * k + 1] = m[5] / n1 - mx * my;
+            oS[3 * k + 2] = m[6] / n1 - my * my;
+        }
+    }
+}
+
 template <int KB>
 void launch_local(const PostDesc &d, hipStream_t st)
 {
@@ -840,5 +887,20 @@ int hmm_loglik_grad(hmm_ctx *ctx, int32_t K, const double *delta, const double *
                        Sigma, st_ws, grad);
     return hipGetLastError() == hipSuccess ? HMM_OK : HMM_E_DEVICE;
 }
+
+int hmm_em_step(hmm_ctx *ctx, int32_t K, const double *delta, const double *Gamma, const double *p,
+                const double *mu, const double *Sigma, int64_t T, const uint8_t *flag, const double *xy,
+                void *stream, double *loglik, double *params_out)
+{
+    if (!params_out) return HMM_E_INVALID_ARG;
+    double *st_ws = nullptr;
+    const int rc = posterior_impl(ctx, K, delta, Gamma, p, mu, Sigma, T, flag, xy, stream, nullptr, nullptr, loglik,
+                                  true, &st_ws);
+    if (rc != HMM_OK) return rc;
+    hipLaunchKernelGGL(k_em_mstep, dim3(1), dim3(64), 0, static_cast<hipStream_t>(stream), K, delta, Gamma, p, mu,
+                       Sigma, st_ws, params_out);
+    return hipGetLastError() == hipSuccess ? HMM_OK : HMM_E_DEVICE;
+}
+
 
 }  // extern "C"
