@@ -91,6 +91,28 @@ typedef enum {
 
 typedef struct hmm_ctx hmm_ctx;
 
+/* Host-side check of one parameter set of eq. (1)-(2) (a debugging aid; the
+ * kernels themselves only reject non-finite or out-of-range entries and
+ * report them as NaN).  All pointers are HOST arrays laid out as for
+ * hmm_loglik.  Checks, in this order: delta and every row of Gamma are
+ * probability vectors (entries finite and >= 0, sum within tol of 1;
+ * tol <= 0 selects 1e-12 * K), p_k in [0, 1], mu finite, Sigma_k symmetric
+ * positive definite (Sxx > 0 and Sxx Syy - Sxy^2 > 0, all finite).  Returns
+ * HMM_OK, or HMM_E_INVALID_ARG at the first failing check with its code in
+ * *what (may be NULL); K < 1 or a null array also give HMM_E_INVALID_ARG
+ * (*what = HMM_PARAMS_OK then).  Touches no device. */
+typedef enum {
+    HMM_PARAMS_OK = 0,
+    HMM_PARAMS_BAD_DELTA = 1,
+    HMM_PARAMS_BAD_GAMMA = 2,
+    HMM_PARAMS_BAD_P = 3,
+    HMM_PARAMS_BAD_MU = 4,
+    HMM_PARAMS_BAD_SIGMA = 5
+} hmm_params_check;
+
+int hmm_validate_params(int32_t K, const double *delta, const double *Gamma, const double *p,
+                        const double *mu, const double *Sigma, double tol, int32_t *what);
+
 /* Create a context on HIP device `device` (makes it current).  *out receives
  * the context.  Returns HMM_E_DEVICE if the device cannot be used. */
 int hmm_ctx_create(hmm_ctx **out, int device);

@@ -7,6 +7,7 @@ compiled library is missing the import fails -- there is no fallback.
 """
 import ctypes
 import os
+import numpy as np
 
 import torch
 
@@ -76,6 +77,7 @@ _lib.mcmc_checkpoint_load.argtypes = [_vp, _vp, _i64, _vp]
 _lib.mcmc_set_companion.argtypes = [_vp, _vp, _vp]
 _lib.hmm_posterior.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp]
 _lib.hmm_loglik_grad.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp]
+_lib.hmm_validate_params.argtypes = [_i32, _vp, _vp, _vp, _vp, _vp, ctypes.c_double, _vp]
 _lib.hmm_em_step.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp]
 _lib.hmm_viterbi.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp]
 _lib.hmm_simulate.argtypes = [_vp, _i32, _i32, _vp, _vp, _i32, ctypes.c_uint64, _vp, _vp, _vp, _vp, _vp]
@@ -107,7 +109,7 @@ for _f in ("hmm_ctx_create", "hmm_ctx_destroy", "hmm_loglik", "hmm_emission",
            "mlp_forward",
            "mlp_loss_grad", "mlp_set_weights", "mcmc_checkpoint_size", "mcmc_checkpoint_save",
            "mcmc_checkpoint_load", "mcmc_set_companion", "mcmc_set_twalk", "hmm_posterior",
-           "hmm_loglik_grad", "hmm_em_step", "hmm_viterbi", "hmm_simulate"):
+           "hmm_loglik_grad", "hmm_em_step", "hmm_viterbi", "hmm_simulate", "hmm_validate_params"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 
@@ -124,6 +126,26 @@ def _check(fn, code):
 
 def lib():
     return _lib
+
+
+PARAM_CHECKS = {0: "ok", 1: "delta", 2: "Gamma", 3: "p", 4: "mu", 5: "Sigma"}
+
+
+def validate_params(delta, Gamma, p, mu, Sigma, tol=0.0):
+    """Host check of one parameter set (hmm_validate_params): returns None when
+    it is valid, else the name of the first failing block."""
+    arrs = [np.ascontiguousarray(np.asarray(a, dtype=np.float64)) for a in (delta, Gamma, p, mu, Sigma)]
+    K = arrs[0].size
+    sizes = (K, K * K, K, 2 * K, 3 * K)
+    if any(a.size != n for a, n in zip(arrs, sizes)):
+        raise ValueError("parameter arrays must have K, K*K, K, 2K and 3K entries")
+    what = ctypes.c_int32(0)
+    rc = _lib.hmm_validate_params(K, *[a.ctypes.data for a in arrs], float(tol), ctypes.byref(what))
+    if rc == HMM_OK:
+        return None
+    if what.value == 0:
+        _check("hmm_validate_params", rc)
+    return PARAM_CHECKS[what.value]
 
 
 def _dev(t, dtype, name, numel=None):

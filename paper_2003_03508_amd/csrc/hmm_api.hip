@@ -5,6 +5,7 @@
 // results kept in ordinary VGPRs, because those kernels read their
 // accumulators with vector ALU code after every step.
 #include <climits>
+#include <cmath>
 #include <cstddef>
 #include <cstdint>
 #include <cstdlib>
@@ -175,6 +176,42 @@ int loglik_impl(hmm_ctx *ctx, int kind, int32_t K, const double *delta, const do
 }  // namespace
 
 extern "C" {
+
+int hmm_validate_params(int32_t K, const double *delta, const double *Gamma, const double *p, const double *mu,
+                        const double *Sigma, double tol, int32_t *what)
+{
+    if (what) *what = HMM_PARAMS_OK;
+    if (K < 1 || !delta || !Gamma || !p || !mu || !Sigma) return HMM_E_INVALID_ARG;
+    if (!(tol > 0.0)) tol = 1e-12 * K;
+    auto fail = [&](int32_t code) {
+        if (what) *what = code;
+        return HMM_E_INVALID_ARG;
+    };
+    // probability vectors: finite, non-negative, summing to 1 within tol
+    auto simplex = [&](const double *v) {
+        double s = 0.0;
+        for (int i = 0; i < K; ++i) {
+            if (!(std::isfinite(v[i]) && v[i] >= 0.0)) return false;
+            s += v[i];
+        }
+        return std::fabs(s - 1.0) <= tol;
+    };
+    if (!simplex(delta)) return fail(HMM_PARAMS_BAD_DELTA);
+    for (int i = 0; i < K; ++i)
+        if (!simplex(Gamma + (size_t)i * K)) return fail(HMM_PARAMS_BAD_GAMMA);
+    for (int k = 0; k < K; ++k)
+        if (!(p[k] >= 0.0 && p[k] <= 1.0)) return fail(HMM_PARAMS_BAD_P);
+    for (int k = 0; k < 2 * K; ++k)
+        if (!std::isfinite(mu[k])) return fail(HMM_PARAMS_BAD_MU);
+    // 2 x 2 symmetric positive definite: Sxx > 0 and det > 0 (finite)
+    for (int k = 0; k < K; ++k) {
+        const double sxx = Sigma[3 * k], sxy = Sigma[3 * k + 1], syy = Sigma[3 * k + 2];
+        const double det = sxx * syy - sxy * sxy;
+        if (!(std::isfinite(sxx) && std::isfinite(sxy) && std::isfinite(syy) && sxx > 0.0 && det > 0.0))
+            return fail(HMM_PARAMS_BAD_SIGMA);
+    }
+    return HMM_OK;
+}
 
 int hmm_ctx_create(hmm_ctx **out, int device)
 {
