@@ -133,15 +133,20 @@ struct ScanLevel {
 // a <- normalise(a M), M = diag(2^E) M~ in LDS (the common shift drops out).
 // Lane j < K holds a_j; sa is the message's LDS copy, sf and si scratch.  The
 // largest exponent and the sum are read back from LDS by every lane (no
-// cross-lane shuffles).
-__device__ void msg_forward(int K, int KP, const float *M, const long long *E, double &a, double *sa, double *sf,
+// cross-lane shuffles).  The loops run over all KP padded states with
+// branch-free bodies, so their LDS reads issue back to back: padded states
+// contribute exact zeros (sf = 0, si = LLONG_MIN, zero rows of M).
+template <int KP>
+__device__ void msg_forward(int K, const float *M, const long long *E, double &a, double *sa, double *sf,
                             long long *si)
 {
     const int j = threadIdx.x & 63;
+    const int jc = j < KP ? j : 0;
     si[j] = (j < K && a > 0.0) ? E[j] : LLONG_MIN;
     wsync();
     long long emax = LLONG_MIN;
-    for (int i = 0; i < K; ++i) emax = si[i] > emax ? si[i] : emax;
+#pragma unroll
+    for (int i = 0; i < KP; ++i) emax = si[i] > emax ? si[i] : emax;
     double f = 0.0;
     if (j < K && a > 0.0) {
         long long sh = E[j] - emax;
@@ -151,13 +156,15 @@ __device__ void msg_forward(int K, int KP, const float *M, const long long *E, d
     sf[j] = f;
     wsync();
     double s = 0.0;
-    if (j < K)
-        for (int i = 0; i < K; ++i) s += sf[i] * (double)M[i * KP + j];
+#pragma unroll
+    for (int i = 0; i < KP; ++i) s += sf[i] * (double)M[i * KP + jc];
+    if (j >= K) s = 0.0;
     wsync();
     sa[j] = s;
     wsync();
     double tot = 0.0;
-    for (int i = 0; i < K; ++i) tot += sa[i];
+#pragma unroll
+    for (int i = 0; i < KP; ++i) tot += sa[i];
     a = (j < K) ? ((tot > 0.0) ? s / tot : (tot == 0.0 ? 0.0 : NAN)) : 0.0;
     wsync();
     sa[j] = a;
@@ -170,31 +177,60 @@ __device__ void msg_forward(int K, int KP, const float *M, const long long *E, d
 // without bank conflicts):
 //   (M c)_i = 2^(E_i + h_i) sum_j M~_ij cm_j 2^(ce_j - h_i),
 // h_i the largest ce_j over the terms of row i, so each row keeps its own
-// scale.  Lane i < K holds (cm_i, ce_i), mirrored in LDS (sm, se).
-__device__ void msg_backward(int K, int KP, const float *Mt, const long long *E, double &cm, long long &ce,
-                             double *sm, long long *se)
+// scale.  Lane i < K holds (cm_i, ce_i), mirrored in LDS (sm, se); lanes of
+// padded states hold 0, so their terms drop out of the branch-free loops.
+template <int KP>
+__device__ void msg_backward(int K, const float *Mt, const long long *E, double &cm, long long &ce, double *sm,
+                             long long *se)
 {
     const int i = threadIdx.x & 63;
+    const int ic = i < KP ? i : 0;
+    // loads first (eight states at a time), then branch-free arithmetic
+    long long h = LLONG_MIN;
+#pragma unroll
+    for (int j0 = 0; j0 < KP; j0 += 8) {
+        double smv[8];
+        long long sev[8];
+        float mv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            smv[u] = sm[j0 + u];
+            sev[u] = se[j0 + u];
+            mv[u] = Mt[(j0 + u) * KP + ic];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const bool live = (smv[u] > 0.0) & (mv[u] != 0.f) & (sev[u] > h);
+            h = live ? sev[u] : h;
+        }
+    }
+    const long long h0 = (h == LLONG_MIN) ? 0 : h;
+    double s = 0.0;
+#pragma unroll
+    for (int j0 = 0; j0 < KP; j0 += 8) {
+        double smv[8];
+        long long sev[8];
+        float mv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            smv[u] = sm[j0 + u];
+            sev[u] = se[j0 + u];
+            mv[u] = Mt[(j0 + u) * KP + ic];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            long long sh = sev[u] - h0;
+            sh = sh < -1100 ? -1100 : (sh > 0 ? 0 : sh);
+            const double term = (double)mv[u] * ldexp(smv[u], (int)sh);
+            s += ((smv[u] > 0.0) & (mv[u] != 0.f)) ? term : 0.0;
+        }
+    }
     double m = 0.0;
     long long e = 0;
-    if (i < K) {
-        long long h = LLONG_MIN;
-        for (int j = 0; j < K; ++j)
-            if (sm[j] > 0.0 && Mt[j * KP + i] != 0.f && se[j] > h) h = se[j];
-        if (h != LLONG_MIN) {
-            double s = 0.0;
-            for (int j = 0; j < K; ++j) {
-                const float mij = Mt[j * KP + i];
-                if (sm[j] > 0.0 && mij != 0.f) {
-                    long long sh = se[j] - h;
-                    if (sh < -1100) sh = -1100;
-                    s += (double)mij * ldexp(sm[j], (int)sh);
-                }
-            }
-            int ex = 0;
-            m = frexp(s, &ex);
-            e = (m > 0.0) ? E[i] + h + ex : 0;
-        }
+    if (i < K && h != LLONG_MIN) {
+        int ex = 0;
+        m = frexp(s, &ex);
+        e = (m > 0.0) ? E[i] + h + ex : 0;
     }
     cm = m;
     ce = e;
@@ -253,6 +289,7 @@ __device__ __forceinline__ void product_store(const ProdRegs &r, int KP, float *
     wsync();
 }
 
+template <int KP>
 __global__ __launch_bounds__(128) void k_post_scan_level(ScanLevel s)
 {
     __shared__ __attribute__((aligned(16))) float lm[2][kMaxKP * kMaxKP];
@@ -260,7 +297,7 @@ __global__ __launch_bounds__(128) void k_post_scan_level(ScanLevel s)
     __shared__ double sv[2][64], sf[64];
     __shared__ long long se[64], si[64];
     const int w = threadIdx.x >> 6, j = threadIdx.x & 63;
-    const int K = s.K, KP = s.KP;
+    const int K = s.K;
     const int64_t q = blockIdx.x;
     const int64_t c0 = q * s.G, c1 = min(s.n, c0 + s.G);
     ProdRegs nx;
@@ -281,7 +318,7 @@ __global__ __launch_bounds__(128) void k_post_scan_level(ScanLevel s)
             if (c + 1 < c1) {
                 product_store(nx, KP, lm[0], le[0], false);
                 if (c + 2 < c1) product_load(s.M + (c + 1) * KP * KP, s.E + (c + 1) * KP, KP, nx);
-                msg_forward(K, KP, lm[0], le[0], a, sv[0], sf, si);
+                msg_forward<KP>(K, lm[0], le[0], a, sv[0], sf, si);
             }
         }
     } else {
@@ -306,7 +343,7 @@ __global__ __launch_bounds__(128) void k_post_scan_level(ScanLevel s)
             if (c > c0) {
                 product_store(nx, KP, lm[1], le[1], true);
                 if (c - 1 > c0) product_load(s.M + (c - 1) * KP * KP, s.E + (c - 1) * KP, KP, nx);
-                msg_backward(K, KP, lm[1], le[1], cm, ce, sv[1], se);
+                msg_backward<KP>(K, lm[1], le[1], cm, ce, sv[1], se);
             }
         }
     }
@@ -841,7 +878,12 @@ int posterior_impl(hmm_ctx *ctx, int32_t K, const double *delta, const double *G
             sl.G = G;
             sl.pad = 0;
             const unsigned parents = top ? 1u : (unsigned)cnt[l + 1];
-            hipLaunchKernelGGL(k_post_scan_level, dim3(parents), dim3(128), 0, st, sl);
+            switch (KP) {
+            case 16: hipLaunchKernelGGL(k_post_scan_level<16>, dim3(parents), dim3(128), 0, st, sl); break;
+            case 32: hipLaunchKernelGGL(k_post_scan_level<32>, dim3(parents), dim3(128), 0, st, sl); break;
+            case 48: hipLaunchKernelGGL(k_post_scan_level<48>, dim3(parents), dim3(128), 0, st, sl); break;
+            default: hipLaunchKernelGGL(k_post_scan_level<64>, dim3(parents), dim3(128), 0, st, sl); break;
+            }
         }
         if (K <= 16) launch_local<16>(d, st);
         else if (K <= 32) launch_local<32>(d, st);
