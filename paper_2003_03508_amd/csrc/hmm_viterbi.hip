@@ -177,7 +177,7 @@ __global__ __launch_bounds__(64) void k_vit_fold(int64_t n, const float *Vin, co
                                                  double *offout)
 {
     constexpr int R = vit_rows<KB>(), RS = 64 / KB;
-    __shared__ __attribute__((aligned(16))) float P[KB * KB], Q[KB * KB];
+    __shared__ __attribute__((aligned(16))) float P[KB * KB];
     const int lane = threadIdx.x, j = lane % KB, ib = lane / KB;
     const int64_t q = blockIdx.x, c0 = q * kVitG, c1 = min(n, c0 + kVitG);
     float V[R];
@@ -185,18 +185,38 @@ __global__ __launch_bounds__(64) void k_vit_fold(int64_t n, const float *Vin, co
 #pragma unroll
     for (int r = 0; r < R; ++r) V[r] = src[(ib + RS * r) * KB + j];
     double acc = offin[c0];
+    // column j of the next child, loaded one product ahead
+    float qn[KB];
+    if (c0 + 1 < c1) {
+        const float *nxt = Vin + (c0 + 1) * KB * KB;
+#pragma unroll
+        for (int k = 0; k < KB; ++k) qn[k] = nxt[k * KB + j];
+    }
     for (int64_t c = c0 + 1; c < c1; ++c) {
+        float qc[KB];
+#pragma unroll
+        for (int k = 0; k < KB; ++k) qc[k] = qn[k];
+        if (c + 1 < c1) {
+            const float *nxt = Vin + (c + 1) * KB * KB;
+#pragma unroll
+            for (int k = 0; k < KB; ++k) qn[k] = nxt[k * KB + j];
+        }
 #pragma unroll
         for (int r = 0; r < R; ++r) P[(ib + RS * r) * KB + j] = V[r];
-        const float *nxt = Vin + c * KB * KB;
-        for (int idx = lane; idx < KB * KB; idx += 64) Q[idx] = nxt[idx];
         vsync();
         float mx = -INFINITY;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const float *row = P + (ib + RS * r) * KB;
+            const float4 *row = reinterpret_cast<const float4 *>(P + (ib + RS * r) * KB);
             float m = -INFINITY;
-            for (int k = 0; k < KB; ++k) m = fmaxf(m, row[k] + Q[k * KB + j]);
+#pragma unroll
+            for (int k4 = 0; k4 < KB / 4; ++k4) {
+                const float4 v = row[k4];
+                m = fmaxf(m, v.x + qc[4 * k4]);
+                m = fmaxf(m, v.y + qc[4 * k4 + 1]);
+                m = fmaxf(m, v.z + qc[4 * k4 + 2]);
+                m = fmaxf(m, v.w + qc[4 * k4 + 3]);
+            }
             V[r] = m;
             mx = fmaxf(mx, m);
         }
