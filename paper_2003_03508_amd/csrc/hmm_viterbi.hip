@@ -106,6 +106,27 @@ __device__ __forceinline__ float wave_max(float v)
     return v;
 }
 
+template <int CTRL>
+__device__ __forceinline__ float dpp_f32(float x)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, true));
+}
+
+// Same with row permutations (DPP) and four lane reads instead of shuffles
+// through LDS; every lane of the wavefront must be active.
+__device__ __forceinline__ float wave_max_dpp(float v)
+{
+    v = fmaxf(v, dpp_f32<0xB1>(v));    // quad_perm [1,0,3,2]
+    v = fmaxf(v, dpp_f32<0x4E>(v));    // quad_perm [2,3,0,1]
+    v = fmaxf(v, dpp_f32<0x141>(v));   // row_half_mirror
+    v = fmaxf(v, dpp_f32<0x140>(v));   // row_mirror: every lane holds its row's max
+    const float a = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
+    const float b = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16));
+    const float c = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
+    const float e = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48));
+    return fmaxf(fmaxf(a, b), fmaxf(c, e));
+}
+
 // Segment products: one wavefront per segment.  Vout[b] (KB x KB, log2,
 // relative), off[b] (FP64 log2 offset).  KK = K at compile time: the
 // contraction runs over exactly K terms and rows >= K are skipped (their
@@ -326,7 +347,7 @@ __global__ __launch_bounds__(64 * vit_waves<KB>()) void k_vit_local(VitDesc d, c
     __shared__ __attribute__((aligned(16))) float lg[KB * KB];
     __shared__ __attribute__((aligned(16))) float dv[NW][KB];
     __shared__ __attribute__((aligned(16))) float lam[NW][KB * kChunk];
-    __shared__ uint8_t psi[NW][vit_max_len<KB>() * KB];
+    extern __shared__ uint8_t psi[];   // NW x (L x KB) backpointers, sized at launch
     load_lg<KB>(d, lg);
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t b = (int64_t)blockIdx.x * NW + w;
@@ -343,7 +364,7 @@ __global__ __launch_bounds__(64 * vit_waves<KB>()) void k_vit_local(VitDesc d, c
     for (int k = 0; k < KB; ++k) lgc[k] = lg[k * KB + jc];
     const int s_in = (b == 0) ? *first : send[b - 1];
     float *dd = dv[w], *L2 = lam[w];
-    uint8_t *ps = psi[w];
+    uint8_t *ps = psi + (size_t)w * d.L * KB;
     if (lane < KB) dd[lane] = (lane == s_in) ? 0.f : -INFINITY;
     vsync();
     for (int64_t tc = t0; tc < t1; tc += kChunk) {
@@ -362,14 +383,9 @@ __global__ __launch_bounds__(64 * vit_waves<KB>()) void k_vit_local(VitDesc d, c
             }
             const float v = (lane < K) ? best + L2[jc * kChunk + tl] : -INFINITY;
             if (lane < KB) ps[(tc + tl - t0) * KB + lane] = (uint8_t)arg;
+            const float mx = wave_max_dpp(v);   // lanes >= K hold -inf
             vsync();
-            if (lane < KB) dd[lane] = v;
-            vsync();
-            float mx = -INFINITY;
-#pragma unroll
-            for (int i = 0; i < KK; ++i) mx = fmaxf(mx, dd[i]);
-            vsync();
-            if (lane < KB && mx > -INFINITY) dd[lane] = v - mx;
+            if (lane < KB) dd[lane] = (mx > -INFINITY) ? v - mx : v;
             vsync();
         }
     }
@@ -511,7 +527,9 @@ int viterbi_impl(hmm_ctx *ctx, int32_t K, const double *delta, const double *Gam
         int32_t *e0 = at<int32_t>(ws, o_e[0]);
         void *args[] = {&d, &e0, &first, &path};
         constexpr int NW = vit_waves<KB>();
-        if (hipLaunchKernel(loc, dim3((unsigned)((nb + NW - 1) / NW)), dim3(64 * NW), args, 0, st) != hipSuccess)
+        const size_t psi_bytes = (size_t)NW * L * KB;   // at most 32 KiB (L <= vit_max_len)
+        if (hipLaunchKernel(loc, dim3((unsigned)((nb + NW - 1) / NW)), dim3(64 * NW), args, psi_bytes, st) !=
+            hipSuccess)
             return HMM_E_DEVICE;
     }
     hipLaunchKernelGGL(k_vit_finish, dim3(1), dim3(64), 0, st, status, score, first);
