@@ -75,10 +75,11 @@ namespace {
 // Segment length of a class.  Workgroups run one per CU, in rounds of 256;
 // a round costs about L steps plus a fixed per-workgroup part (emission
 // setup, the in-workgroup tree) worth kWgOverhead steps.  The length
-// minimises rounds(L) * (L + kWgOverhead) over 32..4096, so that the last
+// minimises rounds(L) * (L + kWgOverhead) over kMinL..4096, so that the last
 // round is not left mostly empty (and a set too short to fill the chip in one
 // round at a longer length is cut finer).  A tuned value wins.
 constexpr int kWgOverhead = 32;
+constexpr int64_t kMinL = 16;   // shortest segment the cost model considers
 
 // A set whose final fold would take more than kPrefoldF products per
 // wavefront gets one more fold level first (a lone long set cut into short
@@ -92,9 +93,9 @@ int64_t class_L(const hmm_ctx *ctx, const BatchPlan &bp, const BatchClass &c, in
         if (it != ctx->tuned_L.end() && it->second > 0) return it->second;
     }
     if (ctx->block_len > 0) return ctx->block_len;
-    int64_t best = 32;
+    int64_t best = kMinL;
     double best_cost = -1.0;
-    for (int64_t L = 32; L <= 4096; ++L) {
+    for (int64_t L = kMinL; L <= 4096; ++L) {
         int64_t wgs = 0;
         for (int s : c.sets) {
             const int64_t nseg = (bp.T[s] + L - 1) / L;
