@@ -69,9 +69,9 @@ __device__ __forceinline__ void load_lg(const VitDesc &d, float *lg)
     __syncthreads();
 }
 
-// log2 e_t,j of one chunk into lam[j * kChunk + tl] (FP64 per observation,
-// rounded once to FP32); lane = step.  -inf for states >= K.
-template <int KB>
+// log2 e_t,j of one chunk of CH <= 64 steps into lam[j * CH + tl] (FP64 per
+// observation, rounded once to FP32); lane = step.  -inf for states >= K.
+template <int KB, int CH = kChunk>
 __device__ __forceinline__ void stage_log_emissions(const VitDesc &d, int64_t tc, int nst, float *lam)
 {
     const int lane = threadIdx.x & 63;
@@ -85,11 +85,17 @@ __device__ __forceinline__ void stage_log_emissions(const VitDesc &d, int64_t tc
             y = p.y;
         }
     }
-    for (int k = 0; k < KB; ++k)
-        lam[k * kChunk + lane] = (k < d.K && lane < nst) ? (float)state_log2_emission(d.sc[k], f == 1, x, y)
-                                                           : -INFINITY;
+    if (lane < CH)
+        for (int k = 0; k < KB; ++k)
+            lam[k * CH + lane] = (k < d.K && lane < nst) ? (float)state_log2_emission(d.sc[k], f == 1, x, y)
+                                                         : -INFINITY;
     vsync();
 }
+
+// Steps per emission chunk of the segment kernel: half the usual chunk keeps
+// its LDS at 20 KiB per two-wave workgroup (KB = 32), so eight workgroups fit
+// per CU and 4,096 segments run in one round.
+constexpr int kVitSegChunk = 32;
 
 // Lane layout of a KB x KB max-plus matrix: lane l owns column j = l % KB
 // and rows i = l / KB + (64 / KB) r, r < KB * KB / 64.
@@ -137,7 +143,7 @@ __global__ __launch_bounds__(64 * vit_waves<KB>()) void k_vit_segment(VitDesc d,
     constexpr int NW = vit_waves<KB>(), R = vit_rows<KB>(), RS = 64 / KB;
     __shared__ __attribute__((aligned(16))) float lg[KB * KB];
     __shared__ __attribute__((aligned(16))) float vb[NW][KB * KB];
-    __shared__ __attribute__((aligned(16))) float lam[NW][KB * kChunk];
+    __shared__ __attribute__((aligned(16))) float lam[NW][KB * kVitSegChunk];
     load_lg<KB>(d, lg);
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t b = (int64_t)blockIdx.x * NW + w;
@@ -152,14 +158,14 @@ __global__ __launch_bounds__(64 * vit_waves<KB>()) void k_vit_segment(VitDesc d,
     for (int r = 0; r < R; ++r) V[r] = (ib + RS * r == j && j < KK) ? 0.f : -INFINITY;   // max-plus identity
     float *M = vb[w], *L2 = lam[w];
     double acc = 0.0;
-    for (int64_t tc = t0; tc < t1; tc += kChunk) {
-        const int nst = (int)min((int64_t)kChunk, t1 - tc);
-        stage_log_emissions<KB>(d, tc, nst, L2);
+    for (int64_t tc = t0; tc < t1; tc += kVitSegChunk) {
+        const int nst = (int)min((int64_t)kVitSegChunk, t1 - tc);
+        stage_log_emissions<KB, kVitSegChunk>(d, tc, nst, L2);
         for (int tl = 0; tl < nst; ++tl) {
 #pragma unroll
             for (int r = 0; r < R; ++r) M[(ib + RS * r) * KB + j] = V[r];
             vsync();
-            const float e = L2[j * kChunk + tl];
+            const float e = L2[j * kVitSegChunk + tl];
             float mx = -INFINITY;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
