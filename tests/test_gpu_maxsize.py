@@ -81,3 +81,97 @@ def test_loglik_beyond_2_pow_32(K):
         d = None
         torch.cuda.empty_cache()
     assert abs(got - want) <= 1e-6 * abs(want), (got, want, abs(got - want) / abs(want))
+
+
+# --- Viterbi -----------------------------------------------------------------
+# The most likely path regroups the same way in the max-plus semiring:
+#   max ln(...) = max_j [ ln delta (x) (V_P)^(x)n (x) V_r ]_j,
+# (x) the max-plus product and V_s[i][j] the best score of s steps of the
+# block from state i (before the block) to state j.  FP64 throughout.
+
+def _mp(A, B):
+    return np.max(A[:, :, None] + B[None, :, :], axis=1)
+
+
+def periodic_viterbi_score(delta, Gamma, logE, n, r):
+    K = Gamma.shape[0]
+    lg = np.log(Gamma)
+    eye = np.full((K, K), -np.inf)
+    np.fill_diagonal(eye, 0.0)
+    V = eye.copy()
+    Vr = eye.copy() if r == 0 else None
+    for t in range(logE.shape[0]):
+        V = np.max(V[:, :, None] + lg[None, :, :], axis=1) + logE[t][None, :]
+        if t + 1 == r:
+            Vr = V.copy()
+    R, B = eye, V
+    while n:
+        if n & 1:
+            R = _mp(R, B)
+        n >>= 1
+        if n:
+            B = _mp(B, B)
+    return float(np.max(np.log(np.asarray(delta))[:, None] + _mp(R, Vr)))
+
+
+@pytest.mark.parametrize("K,P,n,r", [(3, 40, 0, 11), (3, 40, 1, 0), (4, 30, 6, 7), (2, 64, 9, 63)])
+def test_periodic_max_plus_regrouping_matches_the_viterbi_oracle(K, P, n, r):
+    prm, obs = synth.make(K, P, 70 + K)
+    T = n * P + r
+    flag = np.resize(obs.flag, T)
+    xy = np.resize(obs.xy, (T, 2))
+    want, _, _ = oracle.viterbi(prm.delta, prm.Gamma, prm.p, prm.mu, prm.Sigma, flag, xy)
+    le = oracle.log_emission(prm.p, prm.mu, prm.Sigma, obs.flag, obs.xy)
+    got = periodic_viterbi_score(prm.delta, prm.Gamma, le, n, r)
+    assert abs(got - want) <= 1e-10 * max(1.0, abs(want)), (got, want)
+
+
+def _best_between(lg, logE_rows, s_a, s_b):
+    """Best score of the steps after position a up to position b, from state
+    s_a to state s_b (logE_rows: the emissions of those steps)."""
+    d = np.full(lg.shape[0], -np.inf)
+    d[s_a] = 0.0
+    for e in logE_rows:
+        d = np.max(d[:, None] + lg, axis=0) + e
+    return d[s_b]
+
+
+@pytest.mark.gpu
+def test_viterbi_beyond_2_pow_32():
+    """Score against the regrouping; in sampled windows the returned path is a
+    best path between its own end states (any sub-path of a most likely path
+    is one), with FP32's rounding inside segments as the tolerance."""
+    from paper_2003_03508_amd import binding
+    K, P = 25, 100_003
+    T = 2 ** 32 + 4097
+    n, r = divmod(T, P)
+    prm, obs = synth.make(K, P, 90)
+    le = oracle.log_emission(prm.p, prm.mu, prm.Sigma, obs.flag, obs.xy)
+    want = periodic_viterbi_score(prm.delta, prm.Gamma, le, n, r)
+    lg = np.log(prm.Gamma)
+    ctx = binding.Context(0)
+    try:
+        d = binding.to_device(prm, obs)
+        d["flag"] = d["flag"].repeat(n + 1)[:T]
+        d["xy"] = d["xy"].repeat(n + 1, 1)[:T]
+        print(f"K={K} T={T} P={P} n={n} r={r}", flush=True)
+        path, first, score = ctx.viterbi(**d)
+        torch.cuda.synchronize()
+        got = float(score.cpu()[0])
+        windows = []
+        for a in (1000, 2 ** 31 - 777, 2 ** 32 - 1500, T - 1201):
+            w = 1200
+            windows.append((a, path[a:a + w + 1].cpu().numpy().astype(np.int64)))
+        assert 0 <= int(first.cpu()[0]) < K
+    finally:
+        ctx.close()
+        d = path = None
+        torch.cuda.empty_cache()
+    assert abs(got - want) <= 1e-6 * abs(want), (got, want, abs(got - want) / abs(want))
+    for a, s in windows:
+        assert s.min() >= 0 and s.max() < K
+        rows = le[(np.arange(a + 1, a + len(s)) % P)]
+        own = float(sum(lg[s[i - 1], s[i]] + rows[i - 1][s[i]] for i in range(1, len(s))))
+        best = _best_between(lg, rows, s[0], s[-1])
+        assert own <= best + 1e-9 * abs(best)
+        assert best - own <= 1e-5 * abs(best), (a, own, best)
