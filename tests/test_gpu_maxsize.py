@@ -175,3 +175,64 @@ def test_viterbi_beyond_2_pow_32():
         best = _best_between(lg, rows, s[0], s[-1])
         assert own <= best + 1e-9 * abs(best)
         assert best - own <= 1e-5 * abs(best), (a, own, best)
+
+
+@pytest.mark.parametrize("off,T", [(0, 50), (17, 50), (993, 7), (13, 309)])
+def test_rotated_block_windows_match_direct_evaluation(off, T):
+    """The expected values of the batched test below, on a small analogue: a
+    window of the repeated block equals the block rotated by its offset."""
+    K, P, N = 3, 50, 1000
+    prm, obs = synth.make(K, P, 95)
+    le = oracle.log_emission(prm.p, prm.mu, prm.Sigma, obs.flag, obs.xy)
+    flag, xy = np.resize(obs.flag, N), np.resize(obs.xy, (N, 2))
+    direct = oracle.loglik(prm.delta, prm.Gamma, prm.p, prm.mu, prm.Sigma, flag[off:off + T], xy[off:off + T])
+    if T <= P:
+        idx = np.arange(off, off + T) % P
+        w = oracle.loglik(prm.delta, prm.Gamma, prm.p, prm.mu, prm.Sigma, obs.flag[idx], obs.xy[idx])
+    else:
+        n, r = divmod(T, P)
+        w = periodic_loglik(prm.delta, prm.Gamma, np.roll(le, -(off % P), axis=0), n, r)
+    assert abs(direct - w) <= 1e-10 * abs(direct)
+
+
+@pytest.mark.gpu
+def test_batched_offsets_beyond_2_pow_32():
+    """Batched call over packed observations of 2^32 + P steps (the block of P
+    steps repeated): a set at offset 0, a set straddling position 2^32, a set
+    at the very end and a long set of 2^31 + 12,345 steps from offset 1,000.
+    Each set's data is the block rotated by its offset (mod P); short sets
+    against the forward oracle, the long one against the regrouping."""
+    from paper_2003_03508_amd import binding
+    K, P = 8, 100_003
+    N = 2 ** 32 + P
+    prm, obs = synth.make(K, P, 95)
+    le = oracle.log_emission(prm.p, prm.mu, prm.Sigma, obs.flag, obs.xy)
+    sets = [(0, P), (2 ** 32 - 50_000, P), (N - 777, 777), (1000, 2 ** 31 + 12_345)]
+    want = []
+    for off, T in sets:
+        rot = off % P
+        if T <= P:
+            idx = (np.arange(off, off + T)) % P
+            want.append(oracle.loglik(prm.delta, prm.Gamma, prm.p, prm.mu, prm.Sigma, obs.flag[idx], obs.xy[idx]))
+        else:
+            n, r = divmod(T, P)
+            want.append(periodic_loglik(prm.delta, prm.Gamma, np.roll(le, -rot, axis=0), n, r))
+    ctx = binding.Context(0)
+    try:
+        d = binding.to_device(prm, obs)
+        reps = N // P + 1
+        flag = d["flag"].repeat(reps)[:N]
+        xy = d["xy"].repeat(reps, 1)[:N]
+        params = torch.as_tensor(np.concatenate([prm.packed()] * len(sets)), dtype=torch.float64,
+                                 device="cuda").contiguous()
+        blk = prm.packed().shape[0]
+        print(f"K={K} N={N} sets={sets}", flush=True)
+        out = ctx.loglik_batched([K] * len(sets), [T for _, T in sets], [blk * i for i in range(len(sets))],
+                                 params, [off for off, _ in sets], flag, xy)
+        got = out.cpu().numpy()
+    finally:
+        ctx.close()
+        d = flag = xy = None
+        torch.cuda.empty_cache()
+    for g, w, s in zip(got, want, sets):
+        assert abs(g - w) <= 1e-6 * abs(w), (s, g, w)
