@@ -26,10 +26,19 @@
  *   - Layouts: delta[K]; Gamma[K*K] row-major with Gamma[i*K+j] the probability
  *     of moving from state i to state j; p[K]; mu[2K] as (x, y) pairs in km;
  *     Sigma[3K] as (Sxx, Sxy, Syy) triples in km^2; flag[T] uint8 (1 = tremor,
- *     0 = none); xy[2T] as (x, y) pairs, read only where flag is 1.  T counts
- *     observations (the paper's N+1).
+ *     0 = none); xy[2T] as (x, y) pairs, read only where flag is 1, each pair
+ *     loaded as one 16-byte word: xy must be 16-byte aligned (every device
+ *     allocation is; a view starting at an odd double is rejected with
+ *     HMM_E_INVALID_ARG).  T counts observations (the paper's N+1).
  *   - Errors the host can see (null pointers, K or T out of range, unknown
- *     algorithm) are returned as an hmm_status and nothing is enqueued.
+ *     algorithm, a misaligned xy) are returned as an hmm_status and nothing is
+ *     enqueued.  A request whose launches would exceed HIP's 2^32 threads per
+ *     launch returns HMM_E_UNSUPPORTED; with the automatic segment lengths
+ *     that happens only for hmm_emission at T >= 2^32 - 64 and for
+ *     hmm_viterbi above T = 2^35 (K <= 32) or 2^34 (K > 32); a segment length
+ *     set with hmm_ctx_set_blocking lowers the limit of the blocked and
+ *     reverse-direction paths to about 2^26 segments (2^22 workgroups of the
+ *     likelihood's segment kernel).
  *     Problems only the device can see are reported in the result: NaN for
  *     invalid parameters (delta_k < 0, Gamma_ij outside [0,1], p_k outside
  *     [0,1], non-finite mu, Sigma not symmetric positive definite, any

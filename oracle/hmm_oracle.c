@@ -327,12 +327,15 @@ int oracle_loglik_batch(int32_t n, const int32_t *K, const int64_t *T, const int
     if (nthreads > 256) nthreads = 256;
     pthread_t th[256];
     oracle_batch_job jobs[256];
+    int started[256];
     for (int32_t i = 0; i < nthreads; ++i) {
         jobs[i] = (oracle_batch_job){n, nthreads, i, K, T, param_off, params, obs_off, flag, xy, out};
-        if (nthreads == 1) { oracle_batch_worker(&jobs[i]); return 0; }
-        pthread_create(&th[i], NULL, oracle_batch_worker, &jobs[i]);
+        /* a worker that cannot be started runs on this thread instead */
+        started[i] = nthreads > 1 && pthread_create(&th[i], NULL, oracle_batch_worker, &jobs[i]) == 0;
+        if (!started[i]) oracle_batch_worker(&jobs[i]);
     }
-    for (int32_t i = 0; i < nthreads; ++i) pthread_join(th[i], NULL);
+    for (int32_t i = 0; i < nthreads; ++i)
+        if (started[i]) pthread_join(th[i], NULL);
     return 0;
 }
 

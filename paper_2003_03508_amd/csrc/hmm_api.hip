@@ -80,6 +80,7 @@ int check_common(hmm_ctx *ctx, int32_t K, const double *p, const double *mu, con
     if (K < 1 || K > 128) return HMM_E_INVALID_ARG;
     if (T < 0 || T >= kMaxT) return HMM_E_INVALID_ARG;
     if (T > 0 && (!flag || !xy)) return HMM_E_INVALID_ARG;
+    if (T > 0 && !xy_aligned(xy)) return HMM_E_INVALID_ARG;
     return HMM_OK;
 }
 
@@ -144,7 +145,7 @@ int loglik_impl(hmm_ctx *ctx, int kind, int32_t K, const double *delta, const do
     if (!select_kernels(algo, K, &ks)) return HMM_E_UNSUPPORTED;
     const int KP = ks.KP();
     Plan pl = make_plan(ctx, KP, T);
-    if (pl.n1 > INT_MAX) return HMM_E_UNSUPPORTED;
+    if (pl.n1 > INT_MAX || !grid_fits(pl.n1, 64 * pl.W)) return HMM_E_UNSUPPORTED;
     Layout ly = make_layout(KP, pl);
     rc = ensure_ws(ctx, ly.total + sizeof(double) * kFactBlocks);
     if (rc != HMM_OK) return rc;
@@ -163,7 +164,7 @@ int loglik_impl(hmm_ctx *ctx, int kind, int32_t K, const double *delta, const do
     d.L = pl.L;
     d.K = K;
     d.pad = 0;
-    rc = run_single(ctx, ks, d, pl, ly, st);
+    rc = run_single(ctx, ctx->ws, ks, d, pl, ly, st);
     if (rc != HMM_OK) return rc;
     if (kind == kEmisPoisson && T > 0) {
         hipLaunchKernelGGL(k_log_factorials, dim3(kFactBlocks), dim3(256), 0, st, T, obs.cnt,
@@ -302,6 +303,7 @@ int hmm_emission(hmm_ctx *ctx, int32_t K, const double *p, const double *mu, con
     int rc = check_common(ctx, K, p, mu, Sigma, T, flag, xy);
     if (rc != HMM_OK) return rc;
     if (!status || (T > 0 && (!shift || !e_hat))) return HMM_E_INVALID_ARG;
+    if (!grid_fits((T + kChunk - 1) / kChunk, kChunk)) return HMM_E_UNSUPPORTED;
     DeviceGuard dg(ctx->device);
     if (!dg.ok) return HMM_E_DEVICE;
     hipStream_t st = static_cast<hipStream_t>(stream);

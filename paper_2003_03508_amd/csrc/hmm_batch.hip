@@ -210,6 +210,8 @@ int build(hmm_ctx *ctx, BatchPlan &bp)
         c.njobs = jobs.size() - c.job0;
         c.nfjobs = fjobs.size() - c.fjob0;
         c.npjobs = pjobs.size() - c.pjob0;
+        if (!grid_fits((int64_t)c.njobs, 64 * c.W) || !grid_fits((int64_t)c.npjobs, 64 * c.W2))
+            return HMM_E_UNSUPPORTED;
         prods[ci] = (size_t)std::max<int64_t>(base, 1);
     }
     // device memory: tables, per-set slots, per-class products
@@ -457,6 +459,7 @@ int check_batch(hmm_ctx *ctx, int32_t n, const int32_t *K, const int64_t *T, con
         any_obs |= T[s] > 0;
     }
     if (any_obs && (!flag || !xy)) return HMM_E_INVALID_ARG;
+    if (any_obs && !xy_aligned(xy)) return HMM_E_INVALID_ARG;
     return HMM_OK;
 }
 

@@ -48,6 +48,18 @@ constexpr size_t kMaxTimed = 65536;
 
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
+// Locations are read as one 16-byte load per observation, so xy must be
+// 16-byte aligned (any allocation is; a view offset by an odd number of
+// doubles is not).
+inline bool xy_aligned(const double *xy) { return (reinterpret_cast<uintptr_t>(xy) & 15) == 0; }
+
+// A launch of `groups` workgroups of `threads` threads fits HIP's limit of
+// 2^32 - 1 threads in x.
+inline bool grid_fits(int64_t groups, int threads)
+{
+    return groups >= 0 && (uint64_t)groups * (uint64_t)threads <= 0xFFFFFFFFull;
+}
+
 // Keeps the caller's current device and restores it on exit.
 struct DeviceGuard {
     int prev = -1;
@@ -288,17 +300,17 @@ inline hipError_t launch_fold(const void *fn, unsigned grid, int W2, size_t lds,
 
 // Single-set blocked path after parameter preparation: segment kernel, then
 // fold levels (m0 -> m1 -> m2 -> m1 -> ...) until one workgroup finishes ln L.
-inline int run_single(hmm_ctx *ctx, const KernelSet &ks, SetDesc d, const Plan &pl, const Layout &ly,
+// ws holds the layout ly; ctx (may be null) only supplies the timing events.
+inline int run_single(hmm_ctx *ctx, void *ws, const KernelSet &ks, SetDesc d, const Plan &pl, const Layout &ly,
                       hipStream_t st)
 {
     const int KP = ks.KP();
     const void *seg = d.obs.kind == kEmisTremor ? ks.seg1 : ks.seg1g;
-    void *ws = ctx->ws;
     const size_t rb = (size_t)region_bytes(KP);
     if (allow_lds(seg, rb * pl.W) != HMM_OK || allow_lds(ks.fold1, rb * pl.W2) != HMM_OK)
         return HMM_E_DEVICE;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    if (ctx->profile && pl.nb > 0 && ctx->events_used < kMaxTimed) {
+    if (ctx && ctx->profile && pl.nb > 0 && ctx->events_used < kMaxTimed) {
         if (ctx->events_used == ctx->events.size()) {
             hipEvent_t a, b;
             if (hipEventCreate(&a) != hipSuccess) return HMM_E_DEVICE;

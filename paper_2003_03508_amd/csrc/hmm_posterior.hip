@@ -759,6 +759,7 @@ int posterior_impl(hmm_ctx *ctx, int32_t K, const double *delta, const double *G
 {
     if (!ctx || !delta || !Gamma || !p || !mu || !Sigma || !loglik) return HMM_E_INVALID_ARG;
     if (K < 1 || T < 0 || T >= kMaxT || (T > 0 && (!flag || !xy))) return HMM_E_INVALID_ARG;
+    if (T > 0 && !xy_aligned(xy)) return HMM_E_INVALID_ARG;
     if (K > 64) return HMM_E_UNSUPPORTED;
     KernelSet ks;
     if (!select_kernels(HMM_BLOCKED_F32, K, &ks)) return HMM_E_UNSUPPORTED;
@@ -767,7 +768,8 @@ int posterior_impl(hmm_ctx *ctx, int32_t K, const double *delta, const double *G
     const int64_t L = ctx->block_len > 0 ? ctx->block_len
                                          : std::max<int64_t>(32, (T + kPostSegments - 1) / kPostSegments);
     const int64_t nb = T > 0 ? (T + L - 1) / L : 0;
-    if (nb > INT_MAX) return HMM_E_UNSUPPORTED;
+    // one wavefront per segment in the segment and in-segment launches
+    if (nb > INT_MAX || !grid_fits(nb + 64, 64)) return HMM_E_UNSUPPORTED;
     // product levels: 0 = segments, l + 1 = groups of G products of level l,
     // up to the first level with at most G products
     std::vector<int64_t> cnt{nb};

@@ -808,7 +808,7 @@ int mcmc_create(hmm_ctx *ctx, int32_t K, int32_t n_chains, int64_t T, const uint
     if (!ctx || !out || !box || K < 1 || K > 80 || n_chains < 1 || n_chains > 65535 || T < 0 || T >= kMaxT ||
         history < 2)
         return HMM_E_INVALID_ARG;
-    if (T > 0 && (!flag || !xy)) return HMM_E_INVALID_ARG;
+    if (T > 0 && (!flag || !xy || !xy_aligned(xy))) return HMM_E_INVALID_ARG;
     if (!(box[0] <= box[1] && box[2] <= box[3])) return HMM_E_INVALID_ARG;
     DeviceGuard dg(ctx->device);
     if (!dg.ok) return HMM_E_DEVICE;

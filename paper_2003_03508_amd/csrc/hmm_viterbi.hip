@@ -23,6 +23,8 @@
 #include <cstdint>
 #include <vector>
 
+#include <type_traits>
+
 #include "hmm_host.hpp"
 
 using namespace hmm;
@@ -53,7 +55,7 @@ struct VitDesc {
     const StateConst *sc;     // log2 emission constants (k_prepare)
     const double *Gamma;      // [K][K]
     const double *delta;      // [K]
-    const int *status;
+    int *status;              // bit mask: kBadParams (k_prepare), kBadData (k_vit_segment)
     int64_t T, L, nb;
     int K, pad;
 };
@@ -71,11 +73,13 @@ __device__ __forceinline__ void load_lg(const VitDesc &d, float *lg)
 
 // log2 e_t,j of one chunk of CH <= 64 steps into lam[j * CH + tl] (FP64 per
 // observation, rounded once to FP32); lane = step.  -inf for states >= K.
+// Returns 1 on a lane whose observation is invalid (a flag other than 0/1,
+// or a tremor with a non-finite location).
 template <int KB, int CH = kChunk>
-__device__ __forceinline__ void stage_log_emissions(const VitDesc &d, int64_t tc, int nst, float *lam)
+__device__ __forceinline__ int stage_log_emissions(const VitDesc &d, int64_t tc, int nst, float *lam)
 {
     const int lane = threadIdx.x & 63;
-    int f = 0;
+    int f = 0, bad = 0;
     double x = 0.0, y = 0.0;
     if (lane < nst) {
         f = d.flag[tc + lane];
@@ -83,6 +87,9 @@ __device__ __forceinline__ void stage_log_emissions(const VitDesc &d, int64_t tc
             const double2 p = reinterpret_cast<const double2 *>(d.xy)[tc + lane];
             x = p.x;
             y = p.y;
+            if (!(isfinite(x) && isfinite(y))) bad = 1;
+        } else if (f != 0) {
+            bad = 1;
         }
     }
     if (lane < CH)
@@ -90,6 +97,7 @@ __device__ __forceinline__ void stage_log_emissions(const VitDesc &d, int64_t tc
             lam[k * CH + lane] = (k < d.K && lane < nst) ? (float)state_log2_emission(d.sc[k], f == 1, x, y)
                                                          : -INFINITY;
     vsync();
+    return bad;
 }
 
 // Steps per emission chunk of the segment kernel: half the usual chunk keeps
@@ -158,9 +166,10 @@ __global__ __launch_bounds__(64 * vit_waves<KB>()) void k_vit_segment(VitDesc d,
     for (int r = 0; r < R; ++r) V[r] = (ib + RS * r == j && j < KK) ? 0.f : -INFINITY;   // max-plus identity
     float *M = vb[w], *L2 = lam[w];
     double acc = 0.0;
+    int bad = 0;
     for (int64_t tc = t0; tc < t1; tc += kVitSegChunk) {
         const int nst = (int)min((int64_t)kVitSegChunk, t1 - tc);
-        stage_log_emissions<KB, kVitSegChunk>(d, tc, nst, L2);
+        bad |= stage_log_emissions<KB, kVitSegChunk>(d, tc, nst, L2);
         for (int tl = 0; tl < nst; ++tl) {
 #pragma unroll
             for (int r = 0; r < R; ++r) M[(ib + RS * r) * KB + j] = V[r];
@@ -190,6 +199,9 @@ __global__ __launch_bounds__(64 * vit_waves<KB>()) void k_vit_segment(VitDesc d,
             vsync();
         }
     }
+    // the segments cover every observation, so invalid data anywhere is seen
+    // here; the later kernels discard their results when the status is set
+    if (__any(bad) && lane == 0) atomicOr(d.status, kBadData);
     float *out = Vout + b * KB * KB;
 #pragma unroll
     for (int r = 0; r < R; ++r) out[(ib + RS * r) * KB + j] = V[r];
@@ -457,15 +469,38 @@ const void *local_kernel(int K)
     else return reinterpret_cast<const void *>(&k_vit_local<64, 64>);
 }
 
+// Segment length of the Viterbi plan (the same rule as viterbi_impl).
+template <int KB>
+int64_t viterbi_len(const hmm_ctx *ctx, int64_t T)
+{
+    constexpr int64_t maxL = vit_max_len<KB>();
+    return ctx->block_len > 0 ? std::min<int64_t>(ctx->block_len, maxL)
+                              : std::min<int64_t>(maxL, std::max<int64_t>(32, (T + kVitSegments - 1) / kVitSegments));
+}
+
+// The segment and backtracking launches run about one wavefront per
+// segment: with segments of at most vit_max_len steps, T above about
+// 2^26 * that length exceeds HIP's 2^32 threads per launch.
+bool viterbi_grid_fits(const hmm_ctx *ctx, int K, int64_t T)
+{
+    auto fits = [&](auto kb) {
+        constexpr int KB = decltype(kb)::value;
+        const int64_t L = viterbi_len<KB>(ctx, T);
+        const int64_t nb = T > 0 ? (T + L - 1) / L : 0;
+        constexpr int NW = vit_waves<KB>();
+        return grid_fits((nb + NW - 1) / NW, 64 * NW);
+    };
+    if (K <= 16) return fits(std::integral_constant<int, 16>());
+    if (K <= 32) return fits(std::integral_constant<int, 32>());
+    return fits(std::integral_constant<int, 64>());
+}
+
 template <int KB>
 int viterbi_impl(hmm_ctx *ctx, int32_t K, const double *delta, const double *Gamma, const double *p,
                  const double *mu, const double *Sigma, int64_t T, const uint8_t *flag, const double *xy,
                  hipStream_t st, int32_t *path, int32_t *first, double *score)
 {
-    constexpr int64_t maxL = vit_max_len<KB>();
-    const int64_t L = ctx->block_len > 0
-                          ? std::min<int64_t>(ctx->block_len, maxL)
-                          : std::min<int64_t>(maxL, std::max<int64_t>(32, (T + kVitSegments - 1) / kVitSegments));
+    const int64_t L = viterbi_len<KB>(ctx, T);
     const int64_t nb = T > 0 ? (T + L - 1) / L : 0;
     std::vector<int64_t> cnt{nb};
     while (cnt.back() > kVitG) cnt.push_back((cnt.back() + kVitG - 1) / kVitG);
@@ -552,7 +587,9 @@ int hmm_viterbi(hmm_ctx *ctx, int32_t K, const double *delta, const double *Gamm
 {
     if (!ctx || !delta || !Gamma || !p || !mu || !Sigma || !first || !score) return HMM_E_INVALID_ARG;
     if (K < 1 || T < 0 || T >= kMaxT || (T > 0 && (!flag || !xy || !path))) return HMM_E_INVALID_ARG;
+    if (T > 0 && !xy_aligned(xy)) return HMM_E_INVALID_ARG;
     if (K > 64) return HMM_E_UNSUPPORTED;
+    if (!viterbi_grid_fits(ctx, K, T)) return HMM_E_UNSUPPORTED;
     DeviceGuard dg(ctx->device);
     if (!dg.ok) return HMM_E_DEVICE;
     hipStream_t st = static_cast<hipStream_t>(stream);

@@ -241,6 +241,14 @@ def batch(n=256, K_lo=8, K_hi=64, T_lo=100_000, T_hi=1_000_000, seed=3, T_scale=
     return pack(sets), sets
 
 
+def pack_digest(packed):
+    """sha256 of a packed batch (descriptors, parameter blocks, observations)."""
+    h = hashlib.sha256()
+    for key in ("K", "T", "param_off", "obs_off", "params", "flag", "xy"):
+        h.update(np.ascontiguousarray(packed[key]).tobytes())
+    return h.hexdigest()
+
+
 def pack(sets):
     """Pack (params, obs) pairs: returns dict of K, T, param_off, params, obs_off, flag, xy."""
     Ks = np.array([prm.K for prm, _ in sets], dtype=np.int32)

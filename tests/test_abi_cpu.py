@@ -148,3 +148,45 @@ def test_mcmc_view_layout_matches_binding(tmp_path):
     for f in fields:
         assert int(out[f]) == getattr(binding.McmcView, f).offset, f
     assert int(out["size"]) == ctypes.sizeof(binding.McmcView)
+
+
+def test_xy_alignment_and_launch_limits_checked_on_host(lib):
+    """xy is read as 16-byte words: a pointer that is not 16-byte aligned is
+    rejected before anything is enqueued, and so is a request whose
+    launches would exceed HIP's 2^32 threads per launch.  The checks come
+    before the context is used, so a zero-filled stand-in serves as the
+    context here (no device is touched)."""
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    fake = ctypes.create_string_buffer(4096)
+    ctx = ctypes.addressof(fake)
+    dev, flag, good, odd = 0x10000, 0x20000, 0x30000, 0x30008   # never dereferenced
+    f = lib.hmm_loglik
+    f.restype = ctypes.c_int
+    f.argtypes = [vp, i32] + [vp] * 5 + [i64, vp, vp, i32, vp, vp]
+    assert f(ctx, 3, dev, dev, dev, dev, dev, 10, flag, odd, 1, None, dev) == -1
+    e = lib.hmm_emission
+    e.restype = ctypes.c_int
+    e.argtypes = [vp, i32, vp, vp, vp, i64, vp, vp, vp, vp, vp, vp]
+    assert e(ctx, 3, dev, dev, dev, 10, flag, odd, None, dev, dev, dev) == -1
+    # T = 2^32 chunks of 64 observations would need 2^32 + 64 threads
+    assert e(ctx, 3, dev, dev, dev, 2 ** 32, flag, good, None, dev, dev, dev) == -2
+    v = lib.hmm_viterbi
+    v.restype = ctypes.c_int
+    v.argtypes = [vp, i32] + [vp] * 5 + [i64, vp, vp, vp, vp, vp, vp]
+    assert v(ctx, 25, dev, dev, dev, dev, dev, 10, flag, odd, None, dev, dev, dev) == -1
+    # 2^36 steps in segments of at most 512: 2^27 segments of one wavefront each
+    assert v(ctx, 25, dev, dev, dev, dev, dev, 2 ** 36, flag, good, None, dev, dev, dev) == -2
+    assert v(ctx, 50, dev, dev, dev, dev, dev, 2 ** 35, flag, good, None, dev, dev, dev) == -2
+    b = lib.hmm_loglik_batched
+    b.restype = ctypes.c_int
+    b.argtypes = [vp, i32, vp, vp, vp, vp, i64, vp, vp, vp, i64, i32, vp, vp]
+    K = (ctypes.c_int32 * 1)(3)
+    T = (ctypes.c_int64 * 1)(10)
+    zero = (ctypes.c_int64 * 1)(0)
+    assert b(ctx, 1, K, T, zero, dev, 3 * 10, zero, flag, odd, 10, 1, None, dev) == -1
+    m = lib.mcmc_create
+    m.restype = ctypes.c_int
+    m.argtypes = [vp, i32, i32, i64, vp, vp, vp, ctypes.c_uint64, i64, ctypes.POINTER(vp)]
+    box = (ctypes.c_double * 4)(0, 1, 0, 1)
+    h = vp()
+    assert m(ctx, 3, 2, 10, flag, odd, box, 0, 8, ctypes.byref(h)) == -1

@@ -449,6 +449,33 @@ def test_learned_decisions_match_oracle(binding, ctx):
     ch.close()
 
 
+def test_learned_decisions_match_oracle_k20(binding, ctx):
+    """The sampled workload's size: K = 20 (D = 480 parameters), the learned
+    mixture (network trained on the chains' own history, eps = 0.1), each
+    decision against the oracle's MH step from the GPU's pre-state, with a
+    short observation sequence."""
+    K, T, C, seed = 20, 3000, 4, 21
+    ch, prm, obs, box, rw, _ = _fill_history(binding, ctx, K, T, C, seed, 240, 240, c_rw=0.3, data_seed=45)
+    ch.train(150, batch=64, lag=5, lr=1e-3)
+    net = ch.network()
+    w = net["weights"].cpu().numpy().astype(np.float64)
+    center = net["center"].cpu().numpy()
+    ins = net["in_scale"].cpu().numpy()
+    outs = net["out_scale"].cpu().numpy()
+    D = ch.D
+    assert D == 480
+
+    def move(theta):
+        return omlp.move(w, theta, center, ins, outs, D, 256)
+
+    compared, ties = _compare_steps(binding, ch, K, obs, box, seed, rw, 8, net=move, eps=0.1,
+                                    theta_tol=1e-5, lq_tol=2e-2)
+    assert ties <= 2 and compared >= 8 * C - 2
+    acc = ch.state()["accepts"].cpu().numpy()
+    print(f"K=20 learned mixture: {compared} decisions compared, {ties} near ties, accepts {acc.tolist()}")
+    ch.close()
+
+
 # --------------------------------------------------------------------------- posterior checks
 def _k1_exact(obs):
     from scipy import integrate

@@ -289,6 +289,30 @@ def test_batched_matches_oracle_uneven_sets(binding, ctx):
     assert_close(float(out[6].item()), ref(p2, obs0), "batched after in-place parameter update")
 
 
+def test_batched_full_size_256_sets(binding, ctx):
+    """The 256-set workload at full size (K in 8..64, T in 1e5..1e6, seed 3,
+    1.4e8 observations): tuned plan, captured graph, replayed; every set's
+    ln L against the stored oracle value (FP64 oracle, all host cores)."""
+    import json
+    import os
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "oracle_values.json")))["batch256"]
+    print("generating the 256 sets", flush=True)
+    packed, sets = synth.batch()
+    del sets
+    assert synth.pack_digest(packed) == g["inputs_sha256"], "generator output changed: rerun make_oracle_values.py"
+    d = binding.batch_to_device(packed)
+    want = np.asarray(g["loglik"])
+    print("autotuning", flush=True)
+    ctx.autotune_batched(**d, reps=1)
+    for rep in range(3):   # first call builds and captures the plan, later ones replay it
+        out = ctx.loglik_batched(**d)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()
+        rel = np.abs(got - want) / np.maximum(np.abs(want), 1.0)
+        print(f"rep {rep}: max rel err {rel.max():.3e} (set {int(np.argmax(rel))})", flush=True)
+        assert rel.max() <= REL, (rep, int(np.argmax(rel)), float(rel.max()))
+
+
 @pytest.mark.parametrize("algo", ["blocked_bf16", "blocked_f16"])
 def test_batched_16bit(binding, ctx, algo):
     sets = [synth.make(K, T, seed=400 + K) for K, T in [(3, 2000), (25, 3000), (40, 2500), (64, 1500), (80, 1200)]]

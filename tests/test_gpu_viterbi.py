@@ -85,9 +85,26 @@ def test_viterbi_edge_cases(binding, ctx):
     bad = synth.HMMParams(**{**prm.__dict__, "p": np.where(np.arange(4) == 0, 1.5, prm.p)})
     path, first, score = _run(binding, ctx, bad, obs)
     assert math.isnan(score) and first == -1 and (path == -1).all()
-    prm, obs = synth.make(65, 100, 9)
-    with pytest.raises(binding.HMMError):
-        ctx.viterbi(**binding.to_device(prm, obs))
+
+@pytest.mark.parametrize("what", ["flag 2", "nan location", "inf location"])
+def test_viterbi_invalid_data(binding, ctx, what):
+    """Invalid observations (a flag other than 0/1, a tremor with a
+    non-finite location) anywhere in the sequence give a NaN score and -1
+    for s_-1 and the whole path, as invalid parameters do."""
+    prm, obs = synth.make(5, 3000, 13)
+    flag, xy = obs.flag.copy(), obs.xy.copy()
+    t = 2222
+    if what == "flag 2":
+        flag[t] = 2
+    else:
+        flag[t] = 1
+        xy[t] = (np.nan, 1.0) if what == "nan location" else (1.0, np.inf)
+    bad = synth.Observations(flag=flag, xy=xy)
+    assert math.isnan(oracle.loglik(prm.delta, prm.Gamma, prm.p, prm.mu, prm.Sigma, flag, xy))
+    path, first, score = _run(binding, ctx, prm, bad, 64)
+    assert math.isnan(score) and first == -1 and (path == -1).all()
+    # the same context then gives the valid answer again
+    _check(binding, ctx, prm, obs, 64, "after invalid data")
 
 
 def test_viterbi_identity_transitions(binding, ctx):

@@ -258,3 +258,55 @@ def test_stored_oracle_values_are_current(oracle_mod):
     assert obs.digest() == g["inputs_sha256"]
     got = oracle_mod.loglik(prm.delta, prm.Gamma, prm.p, prm.mu, prm.Sigma, obs.flag, obs.xy)
     assert got == g["loglik"]
+
+
+@pytest.mark.parametrize("nthreads", [1, 4])
+def test_batch_driver_unpacks_like_single_sets(oracle_mod, nthreads):
+    """The batch driver (the checker of the many-set workload) against one
+    call per set: packed parameter blocks delta[K] | Gamma[K*K] | p[K] |
+    mu[2K] | Sigma[3K], written here block by block with gaps and in a
+    shuffled order, uneven K from 1 to 80, T of 0, 1 and ragged lengths,
+    and two sets reading the same observations (shared offset).  A wrong
+    block order or offset changes the result; equality is bit-for-bit
+    because both paths run the same recursion on the same numbers."""
+    rng = np.random.default_rng(77)
+    Ks = [1, 80, 3, 25, 2, 64, 7, 13, 1, 40, 5]
+    Ts = [0, 1, 333, 1000, 64, 129, 1, 517, 2048, 0, 65]
+    sets = [synth.make(K, T, seed=500 + i) for i, (K, T) in enumerate(zip(Ks, Ts))]
+    # observations: each set's own run, plus set 11 reading set 3's run
+    flag_parts, xy_parts, obs_off, pos = [], [], [], 0
+    for _, obs in sets:
+        obs_off.append(pos)
+        flag_parts.append(obs.flag)
+        xy_parts.append(obs.xy)
+        pos += obs.T
+    Ks.append(25)
+    prm_shared = synth.make(25, 1000, seed=9000)[0]   # other parameters, set 3's data
+    obs_off.append(obs_off[3])
+    Ts.append(Ts[3])
+    flag = np.concatenate(flag_parts)
+    xy = np.concatenate(xy_parts)
+    prms = [prm for prm, _ in sets] + [prm_shared]
+    # parameter blocks in a shuffled order with a gap of 3 doubles between blocks
+    order = rng.permutation(len(prms))
+    chunks, param_off, pos = [], np.zeros(len(prms), np.int64), 0
+    for s in order:
+        prm = prms[s]
+        block = np.concatenate([prm.delta, prm.Gamma.ravel(), prm.p, prm.mu.ravel(),
+                                prm.Sigma.ravel()])
+        param_off[s] = pos
+        chunks.append(block)
+        chunks.append(np.full(3, np.nan))
+        pos += block.shape[0] + 3
+    params = np.concatenate(chunks)
+    got = oracle_mod.loglik_batch(np.array(Ks), np.array(Ts), param_off, params,
+                                  np.array(obs_off, np.int64), flag, xy, nthreads=nthreads)
+    for s, prm in enumerate(prms):
+        o, T = obs_off[s], Ts[s]
+        want = oracle_mod.loglik(prm.delta, prm.Gamma, prm.p, prm.mu, prm.Sigma,
+                                 flag[o:o + T], xy[o:o + T])
+        assert got[s] == want or (math.isnan(got[s]) and math.isnan(want)), (s, got[s], want)
+        assert math.isfinite(want), s
+    # an empty batch leaves nothing to do
+    assert oracle_mod.loglik_batch(np.zeros(0), np.zeros(0), np.zeros(0), params,
+                                   np.zeros(0), flag, xy, nthreads=nthreads).shape == (0,)
