@@ -75,6 +75,50 @@ def measured_traffic():
     return int(round(fetch + write))
 
 
+def issued_mfma_flops(K, T, n_blocks):
+    """Flops the FP32 segment kernel issues on the matrix cores for one
+    evaluation: per observation MT^2 output tiles x NSL live contraction slots
+    x the flops of one MFMA (32x32x2: 4096, 16x16x4: 2048), plus the W - 1
+    products of each workgroup's tree.  Mirrors the library's tile choice
+    (side S, MT tiles per side, W wavefronts per workgroup)."""
+    if K <= 16:
+        S, MT = 16, 1
+    elif K <= 32:
+        S, MT = 32, 1
+    elif K <= 48:
+        S, MT = 16, 3
+    elif K <= 64:
+        S, MT = 32, 2
+    else:
+        S, MT = 16, 5
+    KP = S * MT
+    W = 16 if KP <= 32 else (12 if KP <= 48 else (8 if KP <= 64 else 4))
+    RS = S * S // 64
+    nsl = 0
+    for j in range(MT * RS):
+        r = j % RS
+        row = S * (j // RS) + (r if S == 16 else 8 * (r >> 2) + (r & 3))
+        if row < K:
+            nsl = j + 1
+    per_mfma = 2 * S * S * (64 // S)
+    per_product = MT * MT * nsl * per_mfma
+    n_wg = -(-n_blocks // W)
+    return float(T * per_product + n_wg * (W - 1) * per_product), {"S": S, "MT": MT, "NSL": nsl}
+
+
+def host_cpu():
+    """Host cores and CPU model (from /proc/cpuinfo)."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return os.cpu_count(), model
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -146,14 +190,22 @@ def main():
         ctx.loglik(**d, algo="blocked_f32", out=out)
     torch.cuda.synchronize()
     ctx.profile(True)
+    # one HIP event pair per step on the stream the library launches on
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for i in range(args.steps):
+        ev[i][0].record(stream)
         ctx.loglik(**d, algo="blocked_f32", out=out)
+        ev[i][1].record(stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     launches, kern_ms = ctx.profile_read()
     ctx.profile(False)
+    step_ms = sorted(a.elapsed_time(b) for a, b in ev)
+    step_median_ms = step_ms[len(step_ms) // 2] if len(step_ms) % 2 else 0.5 * (
+        step_ms[len(step_ms) // 2 - 1] + step_ms[len(step_ms) // 2])
     ll_blocked = float(out.item())
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     evals_per_s = args.steps / (t1 - t0)
@@ -174,14 +226,19 @@ def main():
 
     # ---- roofline of the dominant kernel (segment products)
     flops = 2.0 * T * K ** 3                 # algorithmic, unpadded
+    issued, tile = issued_mfma_flops(K, T, plan["n_blocks"])
     achieved_tflops = flops / (kern_avg_ms * 1e-3) / 1e12
     roofline = {"bound": "mfma", "achieved": round(achieved_tflops, 3),
                 "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved_tflops / PEAK_FP32_MFMA_TFLOPS, 4),
                 "traffic": measured_traffic(), "traffic_unit": "bytes/launch",
                 "algorithmic_bytes": 17 * T,
-                "kernel": "k_blocked<32,1>", "kernel_avg_ms": round(kern_avg_ms, 5),
-                "launches_timed": launches, "flops_per_launch": flops}
+                "kernel": "k_blocked<%d,%d,%d>" % (tile["S"], tile["MT"], tile["NSL"]),
+                "kernel_avg_ms": round(kern_avg_ms, 5),
+                "launches_timed": launches, "flops_per_launch": flops,
+                "issued_flops_per_launch": issued,
+                "issued_over_algorithmic": round(issued / flops, 4),
+                "frac_issued": round(issued / (kern_avg_ms * 1e-3) / 1e12 / PEAK_FP32_MFMA_TFLOPS, 4)}
 
     # ---- CPU oracle on the host (reference value and baseline throughput)
     cpu = None
@@ -197,9 +254,11 @@ def main():
             if time.perf_counter() - c0 >= args.cpu_seconds:
                 break
         c1 = time.perf_counter()
+        nproc, model = host_cpu()
         cpu = {"value": round(n / (c1 - c0), 4), "unit": "evals/s", "cores": 1, "kind": "oracle",
                "sample": f"{n} full evaluations of the same K=25, T=1e6 workload, single thread, "
-                         f"FP64 C oracle, {c1 - c0:.1f} s"}
+                         f"FP64 C oracle, {c1 - c0:.1f} s",
+               "host_nproc": nproc, "host_cpu_model": model}
 
     def rel(x):
         return None if (ll_oracle is None or x is None) else abs(x - ll_oracle) / abs(ll_oracle)
@@ -212,6 +271,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms_per_step, 5),
+        "step_ms_hip_event_median": round(step_median_ms, 5),
+        "evals_per_s_at_median": round(1e3 / step_median_ms, 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
