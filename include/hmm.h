@@ -141,6 +141,24 @@ int hmm_loglik(hmm_ctx *ctx, int32_t K, const double *delta, const double *Gamma
                const uint8_t *flag, const double *xy, int32_t algo, void *stream,
                double *out);
 
+/* hmm_loglik without a context and without any device allocation, for
+ * callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc).  Same arguments,
+ * algorithms, conventions and results as hmm_loglik with the automatic
+ * segment lengths (bit-identical output), on the CURRENT HIP device.
+ * Scratch: a fixed 16 MiB device array inside the library, one copy per
+ * GPU, held until the process ends; its device address is looked up once
+ * per device on the first call there.  Every K <= 80 (blocked) and K <= 128
+ * (serial) fits at any T; a request that would need more scratch returns
+ * HMM_E_UNSUPPORTED and enqueues nothing.  All calls on one GPU share that
+ * array: calls that overlap in time on one GPU (two streams, two threads)
+ * race and give undefined results, so serialise them.  Nothing from an
+ * earlier call is read: each call rewrites every scratch word it reads. */
+int hmm_loglik_noalloc(int32_t K, const double *delta, const double *Gamma,
+                       const double *p, const double *mu, const double *Sigma, int64_t T,
+                       const uint8_t *flag, const double *xy, int32_t algo, void *stream,
+                       double *out);
+
 /* Other emission models.  The method needs only the emission function of the
  * model (the matrix chain of eq. 2 is the same), so the same kernels serve
  * other HMMs:

@@ -40,6 +40,7 @@ _i32, _i64 = ctypes.c_int32, ctypes.c_int64
 _lib.hmm_ctx_create.argtypes = [ctypes.POINTER(_vp), ctypes.c_int]
 _lib.hmm_ctx_destroy.argtypes = [_vp]
 _lib.hmm_loglik.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _i32, _vp, _vp]
+_lib.hmm_loglik_noalloc.argtypes = [_i32, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _i32, _vp, _vp]
 _lib.hmm_emission.argtypes = [_vp, _i32, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp]
 _lib.hmm_ctx_set_blocking.argtypes = [_vp, _i64, _i32]
 _lib.hmm_blocked_plan.argtypes = [_vp, _i32, _i64, ctypes.POINTER(_i64), ctypes.POINTER(_i64),
@@ -101,7 +102,7 @@ class McmcView(ctypes.Structure):
 _lib.mcmc_view_get.argtypes = [_vp, ctypes.POINTER(McmcView)]
 _lib.hmm_status_string.restype = ctypes.c_char_p
 _lib.hmm_status_string.argtypes = [ctypes.c_int]
-for _f in ("hmm_ctx_create", "hmm_ctx_destroy", "hmm_loglik", "hmm_emission",
+for _f in ("hmm_ctx_create", "hmm_ctx_destroy", "hmm_loglik", "hmm_loglik_noalloc", "hmm_emission",
            "hmm_ctx_set_blocking", "hmm_blocked_plan", "hmm_ctx_profile", "hmm_ctx_profile_read",
            "hmm_loglik_batched", "hmm_ctx_set_batch_graph", "hmm_autotune_batched",
            "hmm_theta_to_params", "hmm_philox", "hmm_loglik_kind", "mcmc_create", "mcmc_destroy", "mcmc_set_state",
@@ -166,6 +167,25 @@ def _stream(stream):
     if stream is None:
         stream = torch.cuda.current_stream()
     return stream.cuda_stream
+
+
+def loglik_noalloc(delta, Gamma, p, mu, Sigma, flag, xy, algo="blocked_f32", out=None, stream=None):
+    """ln L (eq. 2) through hmm_loglik_noalloc (no context, no device allocation
+    by the library; the tensors' device must be the current one).  `out` must
+    be given where the caller cannot allocate either."""
+    K = int(delta.numel())
+    T = int(flag.numel())
+    if out is None:
+        out = torch.empty(1, dtype=torch.float64, device=delta.device)
+    a = ALGOS[algo] if isinstance(algo, str) else int(algo)
+    rc = _lib.hmm_loglik_noalloc(K, _dev(delta, torch.float64, "delta", K),
+                                 _dev(Gamma, torch.float64, "Gamma", K * K),
+                                 _dev(p, torch.float64, "p", K), _dev(mu, torch.float64, "mu", 2 * K),
+                                 _dev(Sigma, torch.float64, "Sigma", 3 * K), T,
+                                 _dev(flag, torch.uint8, "flag", T), _dev(xy, torch.float64, "xy", 2 * T),
+                                 a, _stream(stream), _dev(out, torch.float64, "out", 1))
+    _check("hmm_loglik_noalloc", rc)
+    return out
 
 
 class Context:

@@ -9,6 +9,7 @@
 #include <cstddef>
 #include <cstdint>
 #include <cstdlib>
+#include <mutex>
 #include <new>
 #include <utility>
 #include <vector>
@@ -174,6 +175,53 @@ int loglik_impl(hmm_ctx *ctx, int kind, int32_t K, const double *delta, const do
     return launch_status();
 }
 
+// ---------------------------------------------------------------------------
+// Fixed scratch of hmm_loglik_noalloc.  Every GPU the library runs on holds
+// one copy of this array (at its own address) until the process ends; the
+// host never passes the array's name to a kernel, only the device address
+// that hipGetSymbolAddress returns for the current device.
+// ---------------------------------------------------------------------------
+constexpr size_t kNoAllocScratchBytes = size_t(16) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's copy of `scratch` (looked up once
+// per device, with that device current).
+int noalloc_scratch(int dev, void **ptr)
+{
+    if (dev < 0 || dev >= kMaxDevices) return HMM_E_DEVICE;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return HMM_E_DEVICE;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    *ptr = g_scratch_ptr[dev];
+    return HMM_OK;
+}
+
+// Bytes of scratch one tremor-model likelihood needs (default segment
+// lengths), or 0 if the request is not supported.
+size_t loglik_scratch_bytes(int32_t K, int64_t T, int32_t algo, KernelSet *ks, Plan *pl, Layout *ly)
+{
+    const hmm_ctx defaults;
+    if (algo == HMM_SERIAL_F32) {
+        *ly = make_layout(serial_kp(K), Plan());
+        return ly->total;
+    }
+    if (!select_kernels(algo, K, ks)) return 0;
+    *pl = make_plan(&defaults, ks->KP(), T);
+    if (pl->n1 > INT_MAX || !grid_fits(pl->n1, 64 * pl->W)) return 0;
+    *ly = make_layout(ks->KP(), *pl);
+    return ly->total;
+}
+
 }  // namespace
 
 extern "C" {
@@ -280,6 +328,60 @@ int hmm_loglik(hmm_ctx *ctx, int32_t K, const double *delta, const double *Gamma
     if (rc != HMM_OK) return rc;
     return loglik_impl(ctx, kEmisTremor, K, delta, Gamma, p, mu, Sigma, T, Obs{flag, xy, nullptr, kEmisTremor, 0},
                        algo, stream, out);
+}
+
+int hmm_loglik_noalloc(int32_t K, const double *delta, const double *Gamma, const double *p,
+                       const double *mu, const double *Sigma, int64_t T, const uint8_t *flag,
+                       const double *xy, int32_t algo, void *stream, double *out)
+{
+    if (!delta || !Gamma || !p || !mu || !Sigma || !out) return HMM_E_INVALID_ARG;
+    if (K < 1 || K > 128 || T < 0 || T >= kMaxT) return HMM_E_INVALID_ARG;
+    if (T > 0 && (!flag || !xy || !xy_aligned(xy))) return HMM_E_INVALID_ARG;
+    if (algo != HMM_SERIAL_F32 && algo != HMM_BLOCKED_F32 && algo != HMM_BLOCKED_BF16 &&
+        algo != HMM_BLOCKED_F16)
+        return HMM_E_INVALID_ARG;
+    KernelSet ks;
+    Plan pl;
+    Layout ly;
+    const size_t need = loglik_scratch_bytes(K, T, algo, &ks, &pl, &ly);
+    if (need == 0) return HMM_E_UNSUPPORTED;
+    if (need > kNoAllocScratchBytes) return HMM_E_UNSUPPORTED;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return HMM_E_DEVICE;
+    void *ws = nullptr;
+    int rc = noalloc_scratch(dev, &ws);
+    if (rc != HMM_OK) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const Obs obs{flag, xy, nullptr, kEmisTremor, 0};
+    // k_prepare rewrites the status word, the state constants and Gamma;
+    // every product slot the later kernels read is written first in the same
+    // call, so nothing left by an earlier call is read.
+    int *status = at<int>(ws, ly.status);
+    StateConst *sc = at<StateConst>(ws, ly.sc);
+    float *gf = at<float>(ws, ly.gf);
+    if (algo == HMM_SERIAL_F32) {
+        const int KP = serial_kp(K);
+        hipLaunchKernelGGL(k_prepare, dim3(1), dim3(256), 0, st, kEmisTremor, K, KP, delta, Gamma, p, mu, Sigma,
+                           sc, gf, status);
+        launch_serial<false>(KP, st, K, T, delta, gf, sc, obs, status, out);
+        return launch_status();
+    }
+    hipLaunchKernelGGL(k_prepare, dim3(1), dim3(256), 0, st, kEmisTremor, K, ks.KP(), delta, Gamma, p, mu, Sigma,
+                       sc, gf, status);
+    SetDesc d;
+    d.obs = obs;
+    d.sc = sc;
+    d.GF = gf;
+    d.delta = delta;
+    d.status = status;
+    d.out = out;
+    d.T = T;
+    d.L = pl.L;
+    d.K = K;
+    d.pad = 0;
+    rc = run_single(nullptr, ws, ks, d, pl, ly, st);
+    if (rc != HMM_OK) return rc;
+    return launch_status();
 }
 
 int hmm_loglik_kind(hmm_ctx *ctx, int32_t kind, int32_t K, const double *delta, const double *Gamma,
