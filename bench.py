@@ -24,6 +24,8 @@ Other workloads (one JSON line each, not the headline):
     python bench.py --workload twalk_k25  # the t-walk sampler, K=25, T=105,000
     python bench.py --workload posterior_k25  # forward-backward and gradient, K=25, T=1e6
     python bench.py --workload forecast_k25   # posterior-predictive paths, K=25, 120 hours
+    python bench.py --workload chains   # 8 x (K=20, T=5e5) and 64 x (K=25, T=105,000), batched vs sequential
+    python bench.py --workload mcmc_ablation --mcmc-iterations 40000   # random walk / linear start / Adam arms
 """
 import argparse
 import json
@@ -93,13 +95,8 @@ def issued_mfma_flops(K, T, n_blocks):
         S, MT = 16, 5
     KP = S * MT
     W = 16 if KP <= 32 else (12 if KP <= 48 else (8 if KP <= 64 else 4))
-    RS = S * S // 64
-    nsl = 0
-    for j in range(MT * RS):
-        r = j % RS
-        row = S * (j // RS) + (r if S == 16 else 8 * (r >> 2) + (r & 3))
-        if row < K:
-            nsl = j + 1
+    RS, G = S * S // 64, 64 // S
+    nsl = min(MT * RS, -(-K // G))   # slot-major state order: ceil(K / G) live slots
     per_mfma = 2 * S * S * (64 // S)
     per_product = MT * MT * nsl * per_mfma
     n_wg = -(-n_blocks // W)
@@ -124,7 +121,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--workload", default="k25_t1e6",
                     choices=["k25_t1e6", "k80_t4m", "batch256", "mcmc_k20", "kinds_k25", "twalk_k25",
-                             "posterior_k25", "forecast_k25"])
+                             "posterior_k25", "forecast_k25", "chains", "mcmc_ablation"])
     ap.add_argument("--twalk-chains", type=int, default=64)
     ap.add_argument("--no-mcmc", action="store_true", help="skip the MCMC leg of the default run")
     ap.add_argument("--mcmc-iterations", type=int, default=10000)
@@ -157,12 +154,18 @@ def main():
         return bench_batch(args)
     if args.workload == "kinds_k25":
         return bench_kinds(args)
+    if args.workload == "chains":
+        return bench_chains(args)
     if args.workload == "twalk_k25":
         return bench_twalk(args)
     if args.workload == "posterior_k25":
         return bench_posterior(args)
     if args.workload == "forecast_k25":
         return bench_forecast(args)
+    if args.workload == "mcmc_ablation":
+        print(json.dumps(run_ablation(C=args.mcmc_chains, n_iter=args.mcmc_iterations, lag=args.mcmc_lag,
+                                      log=True)))
+        return
     if args.workload == "mcmc_k20":
         print(json.dumps(run_mcmc(C=args.mcmc_chains, n_iter=args.mcmc_iterations, lag=args.mcmc_lag,
                                   log=True)))
@@ -336,8 +339,11 @@ def bench_k80(args):
     out = torch.empty(1, dtype=torch.float64, device="cuda")
     flops = 2.0 * T * K ** 3
     res = {}
+    # the *_split forms carry the transition matrix as two 16-bit parts (twice
+    # the matrix-core work); their flops are still counted once (algorithmic)
     for algo, peak in (("blocked_f32", PEAK_FP32_MFMA_TFLOPS), ("blocked_bf16", PEAK_16BIT_MFMA_TFLOPS),
-                       ("blocked_f16", PEAK_16BIT_MFMA_TFLOPS)):
+                       ("blocked_f16", PEAK_16BIT_MFMA_TFLOPS), ("blocked_bf16_split", PEAK_16BIT_MFMA_TFLOPS),
+                       ("blocked_f16_split", PEAK_16BIT_MFMA_TFLOPS)):
         steps = max(3, args.steps // 20)
         ctx.profile(True)
         sec = _timed(lambda: ctx.loglik(**d, algo=algo, out=out), steps, 2)
@@ -385,6 +391,13 @@ def bench_batch(args):
     # plain forward recursion for all sets at once (one wavefront per set)
     out_p = torch.empty(n, dtype=torch.float64, device="cuda")
     sec_p = _timed(lambda: ctx.loglik_batched(**d, algo="serial_f32", out=out_p), 1, 1)
+    # the plain forward recursion as 256 sequential single-set launches (once)
+    outs_p = torch.empty(n, dtype=torch.float64, device="cuda")
+
+    def seq_plain():
+        for i in range(n):
+            ctx.loglik(**singles[i], algo="serial_f32", out=outs_p[i:i + 1])
+    sec_sp = _timed(seq_plain, 1, 0)
     # oracle on a sample of sets (host, one thread per set)
     import oracle
     oracle.build(force=False)
@@ -408,10 +421,80 @@ def bench_batch(args):
                                   "max_rel_diff_vs_blocked": float(np.max(np.abs(out_p.cpu().numpy() - res_b)
                                                                           / np.abs(res_b)))},
         "speedup_batched_vs_plain_forward": round(sec_p / sec_b, 3),
+        "sequential_plain_calls": {"sets_per_s": round(n / sec_sp, 3), "ms_per_batch": round(sec_sp * 1e3, 1),
+                                   "max_rel_diff_vs_blocked": float(np.max(np.abs(outs_p.cpu().numpy() - res_b)
+                                                                           / np.abs(res_b)))},
+        "speedup_batched_vs_sequential_plain": round(sec_sp / sec_b, 2),
         "max_rel_err_vs_oracle_sample": max(rel), "oracle_sample_sets": len(sample),
         "oracle_sample_seconds": round(c1 - c0, 2),
         "batched_vs_single_max_rel_diff": float(np.max(np.abs(res_b - res_s) / np.abs(res_s))),
     }))
+
+
+def bench_chains(args):
+    """Where batching matters: many parameter sets (MCMC chains or proposals)
+    over one shared observation sequence.  (a) the MH step's likelihood of the
+    K=20 posterior: 8 sets over the T=500,000 observations (seed 4); (b) 64
+    sets of K=25 over T=105,000 observations (seed 6, the size of the paper's
+    Shikoku record).  One batched call (captured graph) vs the same sets as
+    sequential single-set calls; per-call HIP-event medians; algorithmic
+    rate n * 2*T*K^3 flops against the FP32 MFMA peak."""
+    import numpy as np
+    import torch
+    from paper_2003_03508_amd import binding, synth
+    ctx = binding.Context(0)
+    stream = torch.cuda.current_stream()
+    res = {}
+    for name, wl, n in (("k20_t5e5_x8", "k20_t5e5", 8), ("k25_t105k_x64", "k25_t105k", 64)):
+        w = synth.WORKLOADS[wl]
+        K, T = w["K"], w["T"]
+        prm0, obs = synth.make(**w)
+        rng = np.random.default_rng(77)
+        prms = [prm0] + [synth.draw_params(rng, K) for _ in range(n - 1)]
+        blocks = [p.packed() for p in prms]
+        blk = blocks[0].shape[0]
+        dv = dict(K=np.full(n, K, np.int32), T=np.full(n, T, np.int64),
+                  param_off=np.arange(n, dtype=np.int64) * blk, obs_off=np.zeros(n, np.int64),
+                  params=torch.as_tensor(np.concatenate(blocks), dtype=torch.float64, device="cuda"),
+                  flag=torch.as_tensor(obs.flag, dtype=torch.uint8, device="cuda"),
+                  xy=torch.as_tensor(obs.xy, dtype=torch.float64, device="cuda").contiguous())
+        out = torch.empty(n, dtype=torch.float64, device="cuda")
+        singles = [binding.to_device(p, obs) for p in prms]
+        outs = torch.empty(n, dtype=torch.float64, device="cuda")
+
+        def batched():
+            ctx.loglik_batched(**dv, out=out)
+
+        def sequential():
+            for i in range(n):
+                ctx.loglik(**singles[i], out=outs[i:i + 1])
+
+        def median_ms(fn, steps, warm):
+            for _ in range(warm):
+                fn()
+            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                  for _ in range(steps)]
+            for a, b in ev:
+                a.record(stream)
+                fn()
+                b.record(stream)
+            torch.cuda.synchronize()
+            return float(np.median([a.elapsed_time(b) for a, b in ev]))
+        steps = max(20, args.steps // 4)
+        mb = median_ms(batched, steps, 3)
+        ms = median_ms(sequential, steps, 2)
+        flops = n * 2.0 * T * K ** 3
+        rb, rs = out.cpu().numpy(), outs.cpu().numpy()
+        res[name] = {"sets": n, "K": K, "T": T,
+                     "batched_ms": round(mb, 4), "sequential_ms": round(ms, 4),
+                     "speedup_batched_vs_sequential": round(ms / mb, 3),
+                     "batched_sets_per_s": round(n / mb * 1e3, 1),
+                     "batched_tflops_algorithmic": round(flops / (mb * 1e-3) / 1e12, 2),
+                     "batched_frac_fp32_peak": round(flops / (mb * 1e-3) / 1e12 / PEAK_FP32_MFMA_TFLOPS, 4),
+                     "max_rel_diff_batched_vs_single": float(np.max(np.abs(rb - rs) / np.abs(rs)))}
+    ctx.close()
+    print(json.dumps({"workload": "chains: many parameter sets over one observation sequence (MCMC shape)",
+                      "unit": "ms", "results": res}))
 
 
 def bench_kinds(args):
@@ -659,6 +742,163 @@ def bench_forecast(args):
     ctx.close()
     print(json.dumps({"workload": "forecast_k25: posterior-predictive tremor paths, K=25, 120 hourly steps per draw",
                       "unit": "draw-steps/s", "results": res, "cpu_baseline": cpu}))
+
+
+def run_ablation(C=8, burn_rounds=12, adapt_rounds=6, round_len=1000, n_iter=40000, lag=5, train_steps=500,
+                 lr=1e-4, eps=0.1, seed=1, log=None):
+    """Ablation of the learned proposal on the K=20, T=500,000 posterior
+    (D = 480), C chains, the exact FP32 likelihood in every MH step.
+
+    After the same burn-in as the MCMC leg (random walk with adapted scales),
+    four samplers run n_iter iterations each from the burn-in's end state:
+      random_walk   the adapted random walk;
+      linear_start  the proposal network with only its least-squares linear
+                    part (0 Adam steps: the hidden layers' output weights are 0);
+      adam_selected linear start + Adam steps, keeping the step with the best
+                    held-out loss (the MCMC leg's training);
+      adam_final    linear start + Adam steps, keeping the last step (no
+                    held-out selection: what the trained hidden layers do).
+    Training uses the second half of the burn-in and is counted in the
+    method's time.  For each: acceptance, ESS (min / median / log posterior)
+    and ESS/s.  Posterior accuracy: each method's posterior means against
+    the pooled draws of the other three methods (z = difference over the
+    combined Monte Carlo standard error; the fraction with |z| < 2), and
+    against the generating parameters (|mean - truth| / posterior sd).
+    States are matched to the generating states by the Hungarian method on
+    the posterior means of the locations; the matching is reported."""
+    import numpy as np
+    import torch
+    from scipy.optimize import linear_sum_assignment
+    from paper_2003_03508_amd import binding, synth
+    from paper_2003_03508_amd import ess as E
+    from paper_2003_03508_amd import mcmc as hm
+
+    def say(*a):
+        if log:
+            print(*a, file=sys.stderr, flush=True)
+
+    wl = synth.WORKLOADS["k20_t5e5"]
+    K, T = wl["K"], wl["T"]
+    prm, obs = synth.make(**wl)
+    box = hm.box_of(obs.flag, obs.xy)
+    d = binding.to_device(prm, obs)
+    ctx = binding.Context(0)
+    D = hm.dim(K)
+    burn = burn_rounds * round_len
+    arms = ("random_walk", "linear_start", "adam_selected", "adam_final")
+    H = burn + len(arms) * n_iter
+    f64 = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+    sl = hm.block_slices(K)
+    nk = T / K
+    rw = np.empty(D)
+    rw[sl["gamma"]] = 0.1
+    rw[sl["p"]] = 1.0 / np.sqrt(nk * prm.p * (1 - prm.p))
+    rw[sl["mu"]] = (np.sqrt(prm.Sigma[:, [0, 2]]) / np.sqrt(nk * prm.p)[:, None]).ravel()
+    rw[sl["logsigma"]] = np.repeat(np.sqrt(2.0 / (nk * prm.p)), 2)
+    rw *= 2.38 / math.sqrt(D)
+    th0 = hm.theta_from_params(prm.Gamma, prm.p, prm.mu, prm.Sigma)
+    ch = binding.Chains(ctx, K, C, d["flag"], d["xy"], box, seed=seed, history=H)
+    ch.set_state(f64(np.tile(th0, (C, 1))), f64(rw))
+
+    def window(n):
+        hist, hlp, it = ch.history()
+        idx = [(it - n + i) % H for i in range(n)]
+        return (hist[idx].cpu().numpy().transpose(1, 0, 2).astype(np.float64), hlp[idx].cpu().numpy().T)
+
+    def run(n, proposal):
+        a0 = int(ch.state()["accepts"].sum())
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(0, n, round_len):
+            ch.step(min(round_len, n - k), proposal=proposal, eps=eps)
+            torch.cuda.synchronize()
+            if (k // round_len) % 10 == 9:
+                say(f"  {k + round_len} iterations, {time.perf_counter() - t0:.1f} s")
+        dt = time.perf_counter() - t0
+        return dt, (int(ch.state()["accepts"].sum()) - a0) / (n * C)
+
+    scale = 1.0
+    for r in range(burn_rounds):
+        dt, acc = run(round_len, binding.MCMC_RANDOM_WALK)
+        if r < adapt_rounds:
+            spread = window(round_len)[0][:, round_len // 3:].reshape(-1, D).std(axis=0)
+            scale *= math.exp(3.0 * (acc - 0.234))
+            rw = scale * 2.38 / math.sqrt(D) * np.maximum(spread, 1e-12)
+            ch.set_rw_scale(f64(rw))
+        say(f"burn-in round {r}: acceptance {acc:.3f}, {dt / round_len * 1e3:.2f} ms/iteration")
+    start = ch.state()["theta"].clone()
+    rw_t = f64(rw)
+
+    def train(steps, holdout):
+        ch.reset_proposal(seed=11)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tr = ch.train(steps, batch=256, lag=lag, lr=lr, window=burn // 2, window_end=burn, holdout=holdout,
+                      val_every=25, val_batch=1024)
+        torch.cuda.synchronize()
+        out = {"train_seconds": round(time.perf_counter() - t0, 3), "adam_steps": steps}
+        if holdout > 0:
+            val = tr["val"].cpu().numpy()
+            out.update(kept_adam_step=int(tr["best_step"]), held_out_loss_start=round(float(val[0]), 3),
+                       held_out_loss_best=round(float(val.min()), 3))
+        return out
+
+    res, draws = {}, {}
+    for name in arms:
+        info = {}
+        if name == "linear_start":
+            info = train(0, 0.2)
+        elif name == "adam_selected":
+            info = train(train_steps, 0.2)
+        elif name == "adam_final":
+            info = train(train_steps, 0.0)
+        prop = binding.MCMC_RANDOM_WALK if name == "random_walk" else binding.MCMC_LEARNED
+        ch.set_state(start, rw_t)
+        say(f"{name}: {n_iter} iterations")
+        dt, acc = run(n_iter, prop)
+        w, lpost = window(n_iter)
+        ess = E.ess_columns(w)
+        ess_lp = E.ess(lpost)
+        cost = dt + info.get("train_seconds", 0.0)
+        res[name] = dict(info, seconds=round(dt, 3), ms_per_iteration=round(dt / n_iter * 1e3, 4),
+                         acceptance=round(acc, 4), ess_min=round(float(ess.min()), 2),
+                         ess_median=round(float(np.median(ess)), 2), ess_logpost=round(float(ess_lp), 2),
+                         ess_per_s_median=round(float(np.median(ess)) / cost, 4),
+                         ess_per_s_logpost=round(float(ess_lp) / cost, 4),
+                         ess_per_s_min=round(float(ess.min()) / cost, 4))
+        flat = w.reshape(-1, D)
+        draws[name] = (flat.mean(axis=0), np.array([E.mcse_mean(w[:, :, j]) for j in range(D)]),
+                       flat.std(axis=0))
+        del w, flat
+        say(f"{name}: acceptance {acc:.3f}, ESS median {np.median(ess):.1f}, log posterior {ess_lp:.1f}, "
+            f"min {ess.min():.1f}, {dt:.2f} s")
+    ch.close()
+    ctx.close()
+    # state matching on the location means (x, y of state k at theta[mu slice])
+    mu_sl = sl["mu"]
+    true_mu = th0[mu_sl].reshape(K, 2)
+    for name in arms:
+        est = draws[name][0][mu_sl].reshape(K, 2)
+        cost_m = ((est[:, None, :] - true_mu[None, :, :]) ** 2).sum(axis=2)
+        rows, cols = linear_sum_assignment(cost_m)
+        res[name]["state_matching_is_identity"] = bool((cols == np.arange(K)).all())
+    # accuracy: against the pooled other methods, and against the truth
+    for name in arms:
+        # the pooled draws of the other methods (equal sizes): the mean of their means
+        m_ref = np.mean([draws[o][0] for o in arms if o != name], axis=0)
+        se_ref = np.sqrt(sum(draws[o][1] ** 2 for o in arms if o != name)) / (len(arms) - 1)
+        z = np.abs(draws[name][0] - m_ref) / np.sqrt(draws[name][1] ** 2 + se_ref ** 2)
+        zt = np.abs(draws[name][0] - th0) / np.maximum(draws[name][2], 1e-300)
+        res[name]["vs_pooled_others_z_median"] = round(float(np.median(z)), 3)
+        res[name]["vs_pooled_others_frac_z_below_2"] = round(float(np.mean(z < 2.0)), 4)
+        res[name]["vs_truth_abs_err_over_sd_median"] = round(float(np.median(zt)), 3)
+    rwm = res["random_walk"]
+    gains = {name: {k: (round(res[name][k] / rwm[k], 3) if rwm[k] > 0 else None)
+                    for k in ("ess_per_s_median", "ess_per_s_logpost", "ess_per_s_min")} for name in arms[1:]}
+    return {"workload": "k20_t5e5: posterior over all D=480 parameters of a K=20 tremor HMM given "
+                        "T=500,000 observations simulated with seed 4",
+            "chains": C, "iterations_per_method": n_iter, "burn_in": burn, "lag": lag, "mixture_eps": eps,
+            "methods": res, "ess_per_s_gain_vs_random_walk": gains}
 
 
 def run_mcmc(C=8, burn_rounds=12, adapt_rounds=6, round_len=1000, n_iter=10000, lag=5, train_steps=500,

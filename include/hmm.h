@@ -95,7 +95,17 @@ typedef enum {
      * two.  Error grows with T (about T * 2^-8 resp. T * 2^-11 relative per
      * step at worst); the FP32 path is the reference.  K <= 80. */
     HMM_BLOCKED_BF16 = 2,
-    HMM_BLOCKED_F16 = 3
+    HMM_BLOCKED_F16 = 3,
+    /* BF16 / FP16 operands with the transition matrix split in two 16-bit
+     * parts, hi = round(Gamma) and lo = round(Gamma - hi), both multiplied
+     * into the same FP32 accumulator: twice the matrix-core work, and the
+     * transition matrix then carries about twice the operand precision.
+     * Rounding Gamma once (HMM_BLOCKED_BF16 / _F16) makes an error that is
+     * the same at every step and grows in proportion to T; the split removes
+     * most of it, leaving the per-step rounding of the running product.
+     * hmm_loglik only (tremor model, one set); K <= 80. */
+    HMM_BLOCKED_BF16_SPLIT = 4,
+    HMM_BLOCKED_F16_SPLIT = 5
 } hmm_algo;
 
 typedef struct hmm_ctx hmm_ctx;
@@ -205,10 +215,19 @@ int hmm_loglik_batched(hmm_ctx *ctx, int32_t n, const int32_t *K, const int64_t 
 /* Use (on != 0, default) or bypass HIP graph capture for batched calls. */
 int hmm_ctx_set_batch_graph(hmm_ctx *ctx, int32_t on);
 
-/* Segment-length autotuner of the batched path: for every class of sets that
- * share a kernel, times the class's launches (reps repetitions after one
- * warm-up) for segment lengths 256..4096 on the caller's own inputs and keeps
- * the fastest in the context (used by later batched calls).  Synchronous;
+/* Work distribution of the batched segment kernels.  on != 0 (default): one
+ * persistent launch per kernel class, about as many workgroups as the GPU
+ * holds at once, each pulling (set, segment-group) jobs from an atomic
+ * counter in decreasing order of their work; on == 0: one workgroup per job.
+ * Both give the same result bit for bit (the jobs and their products are the
+ * same; only the order in which workgroups take them differs). */
+int hmm_ctx_set_batch_persistent(hmm_ctx *ctx, int32_t on);
+
+/* Autotuner of the batched path: for every class of sets that share a
+ * kernel, times the class's launches (reps repetitions after one warm-up)
+ * for segment lengths 256..4096 and for the segment kernel's full and half
+ * wavefront count per workgroup, on the caller's own inputs, and keeps the
+ * fastest pair in the context (used by later batched calls).  Synchronous;
  * writes out[] as a side effect.  chosen_L (host, n entries, may be NULL)
  * receives the length chosen for each set. */
 int hmm_autotune_batched(hmm_ctx *ctx, int32_t n, const int32_t *K, const int64_t *T,

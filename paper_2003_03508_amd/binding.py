@@ -24,10 +24,13 @@ SERIAL_F32 = 0
 BLOCKED_F32 = 1
 BLOCKED_BF16 = 2
 BLOCKED_F16 = 3
+BLOCKED_BF16_SPLIT = 4
+BLOCKED_F16_SPLIT = 5
 EMIS_POISSON = 1
 EMIS_GAUSS1D = 2
 ALGOS = {"serial_f32": SERIAL_F32, "blocked_f32": BLOCKED_F32,
-         "blocked_bf16": BLOCKED_BF16, "blocked_f16": BLOCKED_F16}
+         "blocked_bf16": BLOCKED_BF16, "blocked_f16": BLOCKED_F16,
+         "blocked_bf16_split": BLOCKED_BF16_SPLIT, "blocked_f16_split": BLOCKED_F16_SPLIT}
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with "
@@ -49,6 +52,7 @@ _lib.hmm_ctx_profile.argtypes = [_vp, _i32]
 _lib.hmm_ctx_profile_read.argtypes = [_vp, ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_double)]
 _lib.hmm_loglik_batched.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _i64, _i32, _vp, _vp]
 _lib.hmm_ctx_set_batch_graph.argtypes = [_vp, _i32]
+_lib.hmm_ctx_set_batch_persistent.argtypes = [_vp, _i32]
 _lib.hmm_autotune_batched.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _i64, _i32, _vp,
                                       _i32, _vp]
 _lib.hmm_loglik_kind.argtypes = [_vp, _i32, _i32, _vp, _vp, _vp, _vp, _i64, _vp, _i32, _vp, _vp]
@@ -104,7 +108,8 @@ _lib.hmm_status_string.restype = ctypes.c_char_p
 _lib.hmm_status_string.argtypes = [ctypes.c_int]
 for _f in ("hmm_ctx_create", "hmm_ctx_destroy", "hmm_loglik", "hmm_loglik_noalloc", "hmm_emission",
            "hmm_ctx_set_blocking", "hmm_blocked_plan", "hmm_ctx_profile", "hmm_ctx_profile_read",
-           "hmm_loglik_batched", "hmm_ctx_set_batch_graph", "hmm_autotune_batched",
+           "hmm_loglik_batched", "hmm_ctx_set_batch_graph", "hmm_ctx_set_batch_persistent",
+           "hmm_autotune_batched",
            "hmm_theta_to_params", "hmm_philox", "hmm_loglik_kind", "mcmc_create", "mcmc_destroy", "mcmc_set_state",
            "mcmc_set_rw_scale", "mcmc_step", "mcmc_train_proposal", "mcmc_reset_proposal", "mcmc_view_get",
            "mlp_forward",
@@ -349,6 +354,11 @@ class Context:
 
     def batch_graph(self, on=True):
         _check("hmm_ctx_set_batch_graph", _lib.hmm_ctx_set_batch_graph(self._h, 1 if on else 0))
+
+    def set_batch_persistent(self, on=True):
+        """Persistent batched segment launches with an atomic job queue (default) or one
+        workgroup per job."""
+        _check("hmm_ctx_set_batch_persistent", _lib.hmm_ctx_set_batch_persistent(self._h, 1 if on else 0))
 
     @staticmethod
     def _desc(K, T, param_off, obs_off):

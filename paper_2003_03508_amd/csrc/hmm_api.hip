@@ -38,17 +38,29 @@ bool pick_f32(int nsl, KernelSet *ks)
     }
 }
 
-template <int MT, bool F16, int LO, int HI>
+template <int MT, bool F16, int LO, int HI, bool SPLIT = false>
 bool pick_lp(int nsl, KernelSet *ks)
 {
     if constexpr (LO > HI) {
         return false;
     } else {
         if (nsl == LO) {
-            *ks = kernel_set_lp<MT, F16, LO>();
+            *ks = kernel_set_lp<MT, F16, LO, SPLIT>();
             return true;
         }
-        return pick_lp<MT, F16, LO + 1, HI>(nsl, ks);
+        return pick_lp<MT, F16, LO + 1, HI, SPLIT>(nsl, ks);
+    }
+}
+
+template <int MT, int LO, int HI>
+bool pick_lp_algo(int algo, int nsl, KernelSet *ks)
+{
+    switch (algo) {
+    case HMM_BLOCKED_BF16: return pick_lp<MT, false, LO, HI>(nsl, ks);
+    case HMM_BLOCKED_F16: return pick_lp<MT, true, LO, HI>(nsl, ks);
+    case HMM_BLOCKED_BF16_SPLIT: return pick_lp<MT, false, LO, HI, true>(nsl, ks);
+    case HMM_BLOCKED_F16_SPLIT: return pick_lp<MT, true, LO, HI, true>(nsl, ks);
+    default: return false;
     }
 }
 
@@ -62,11 +74,10 @@ bool kernels_small(int algo, int S, int MT, int NSL, KernelSet *ks)
         if (S == 16 && MT == 3) return pick_f32<16, 3, 9, 12>(NSL, ks);
         return false;
     }
-    const bool f16 = (algo == HMM_BLOCKED_F16);
     if (S != 16) return false;
-    if (MT == 1) return f16 ? pick_lp<1, true, 1, 4>(NSL, ks) : pick_lp<1, false, 1, 4>(NSL, ks);
-    if (MT == 2) return f16 ? pick_lp<2, true, 5, 8>(NSL, ks) : pick_lp<2, false, 5, 8>(NSL, ks);
-    if (MT == 3) return f16 ? pick_lp<3, true, 9, 12>(NSL, ks) : pick_lp<3, false, 9, 12>(NSL, ks);
+    if (MT == 1) return pick_lp_algo<1, 1, 4>(algo, NSL, ks);
+    if (MT == 2) return pick_lp_algo<2, 5, 8>(algo, NSL, ks);
+    if (MT == 3) return pick_lp_algo<3, 9, 12>(algo, NSL, ks);
     return false;
 }
 
@@ -115,7 +126,7 @@ int loglik_impl(hmm_ctx *ctx, int kind, int32_t K, const double *delta, const do
 {
     if (!delta || !Gamma || !out) return HMM_E_INVALID_ARG;
     if (algo != HMM_SERIAL_F32 && algo != HMM_BLOCKED_F32 && algo != HMM_BLOCKED_BF16 &&
-        algo != HMM_BLOCKED_F16)
+        algo != HMM_BLOCKED_F16 && algo != HMM_BLOCKED_BF16_SPLIT && algo != HMM_BLOCKED_F16_SPLIT)
         return HMM_E_INVALID_ARG;
     DeviceGuard dg(ctx->device);
     if (!dg.ok) return HMM_E_DEVICE;
@@ -144,6 +155,7 @@ int loglik_impl(hmm_ctx *ctx, int kind, int32_t K, const double *delta, const do
     }
     KernelSet ks;
     if (!select_kernels(algo, K, &ks)) return HMM_E_UNSUPPORTED;
+    if (!(kind == kEmisTremor ? ks.seg1 : ks.seg1g)) return HMM_E_UNSUPPORTED;   // split: tremor model only
     const int KP = ks.KP();
     Plan pl = make_plan(ctx, KP, T);
     if (pl.n1 > INT_MAX || !grid_fits(pl.n1, 64 * pl.W)) return HMM_E_UNSUPPORTED;
@@ -338,7 +350,7 @@ int hmm_loglik_noalloc(int32_t K, const double *delta, const double *Gamma, cons
     if (K < 1 || K > 128 || T < 0 || T >= kMaxT) return HMM_E_INVALID_ARG;
     if (T > 0 && (!flag || !xy || !xy_aligned(xy))) return HMM_E_INVALID_ARG;
     if (algo != HMM_SERIAL_F32 && algo != HMM_BLOCKED_F32 && algo != HMM_BLOCKED_BF16 &&
-        algo != HMM_BLOCKED_F16)
+        algo != HMM_BLOCKED_F16 && algo != HMM_BLOCKED_BF16_SPLIT && algo != HMM_BLOCKED_F16_SPLIT)
         return HMM_E_INVALID_ARG;
     KernelSet ks;
     Plan pl;

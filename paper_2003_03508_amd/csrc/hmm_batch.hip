@@ -20,6 +20,10 @@ struct BatchClass {
     int *ids = nullptr;    // plain-forward path: the class's set ids (device)
     int W = 1, W2 = 1;
     int64_t L = 0;
+    int grid = 0;          // workgroups of the persistent segment launch (0: one per job)
+    int *queue = nullptr;  // its atomic job counter (device)
+    double cost = 0.0;     // sum over jobs of observations * KP^3 (class order)
+    size_t nprod = 0;      // product slots (segment products and pre-fold outputs)
     std::vector<int> sets;
     size_t job0 = 0, njobs = 0;   // WgJob table range
     size_t fjob0 = 0, nfjobs = 0; // FoldJob table range (one per set)
@@ -38,6 +42,8 @@ struct BatchPlan {
     const double *xy = nullptr;
     double *out = nullptr;
     std::map<std::pair<int, int>, int64_t> tuned;
+    std::map<std::pair<int, int>, int> tunedW;
+    bool persistent = true;
     // device memory
     void *mem = nullptr;
     SetDesc *sets = nullptr;
@@ -45,6 +51,7 @@ struct BatchPlan {
     WgJob *jobs = nullptr;
     FoldJob *fjobs = nullptr;
     FoldJob *pjobs = nullptr;
+    int *queues = nullptr;   // one job counter per class, zeroed at the start of every launch sequence
     std::vector<BatchClass> classes;
     // captured launch sequence (classes forked onto parallel branches)
     static constexpr int kBranches = 4;
@@ -111,6 +118,26 @@ int64_t class_L(const hmm_ctx *ctx, const BatchPlan &bp, const BatchClass &c, in
     return best;
 }
 
+// Segment-kernel waves per workgroup of a class: a tuned value (1..the
+// kernel's maximum) wins, else the maximum.
+int class_W(const hmm_ctx *ctx, const BatchPlan &bp, const BatchClass &c, int algo)
+{
+    const int wmax = group_waves(c.KP);
+    for (int s : c.sets) {
+        auto it = ctx->tuned_W.find({bp.K[s], algo});
+        if (it != ctx->tuned_W.end() && it->second > 0) return std::min(it->second, wmax);
+    }
+    return wmax;
+}
+
+// Fill kernel for the queue counters (a kernel, not a memset node, so that
+// the captured graph replays it reliably).
+__global__ void k_zero_i32(int *p, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
 const void *serial_kernel(int KP)
 {
     switch (KP) {
@@ -156,10 +183,10 @@ int build(hmm_ctx *ctx, BatchPlan &bp)
     // job tables (host)
     std::vector<WgJob> jobs;
     std::vector<FoldJob> fjobs, pjobs;
-    std::vector<size_t> prods(bp.classes.size(), 0);
     for (size_t ci = 0; ci < bp.classes.size(); ++ci) {
         BatchClass &c = bp.classes[ci];
         if (c.serial) continue;
+        c.W = class_W(ctx, bp, c, bp.algo);
         c.L = class_L(ctx, bp, c, bp.algo, c.W);
         c.job0 = jobs.size();
         c.fjob0 = fjobs.size();
@@ -210,10 +237,24 @@ int build(hmm_ctx *ctx, BatchPlan &bp)
         c.njobs = jobs.size() - c.job0;
         c.nfjobs = fjobs.size() - c.fjob0;
         c.npjobs = pjobs.size() - c.pjob0;
+        // queue order: decreasing work per job (observations of its
+        // segments), so the longest jobs start first; slots stay as assigned
+        auto job_obs = [&](const WgJob &j) {
+            const int64_t T = bp.T[j.set];
+            const int64_t a = j.seg0 * c.L, e = std::min<int64_t>(T, (j.seg0 + j.nseg) * c.L);
+            return e - a;
+        };
+        std::stable_sort(jobs.begin() + c.job0, jobs.end(),
+                         [&](const WgJob &x, const WgJob &y) { return job_obs(x) > job_obs(y); });
+        for (size_t q = c.job0; q < jobs.size(); ++q)
+            c.cost += (double)job_obs(jobs[q]) * c.KP * c.KP * c.KP;
         if (!grid_fits((int64_t)c.njobs, 64 * c.W) || !grid_fits((int64_t)c.npjobs, 64 * c.W2))
             return HMM_E_UNSUPPORTED;
-        prods[ci] = (size_t)std::max<int64_t>(base, 1);
+        c.nprod = (size_t)std::max<int64_t>(base, 1);
     }
+    // the most expensive classes first (they start first on the branches)
+    std::stable_sort(bp.classes.begin(), bp.classes.end(),
+                     [](const BatchClass &x, const BatchClass &y) { return x.cost > y.cost; });
     // device memory: tables, per-set slots, per-class products
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -227,6 +268,7 @@ int build(hmm_ctx *ctx, BatchPlan &bp)
     const size_t o_pjobs = take(sizeof(FoldJob) * std::max<size_t>(pjobs.size(), 1));
     const size_t o_status = take(sizeof(int) * n);
     const size_t o_ids = take(sizeof(int) * n);
+    const size_t o_queues = take(sizeof(int) * std::max<size_t>(bp.classes.size(), 1));
     std::vector<size_t> o_sc(n), o_gf(n);
     for (int s = 0; s < n; ++s) {
         const int KP = kp[s];
@@ -237,9 +279,10 @@ int build(hmm_ctx *ctx, BatchPlan &bp)
     for (size_t ci = 0; ci < bp.classes.size(); ++ci) {
         const int KP = bp.classes[ci].KP;
         if (bp.classes[ci].serial) continue;
-        o_m[ci] = take(sizeof(float) * KP * KP * prods[ci]);
-        o_e[ci] = take(sizeof(long long) * KP * prods[ci]);
-        o_s[ci] = take(sizeof(long long) * prods[ci]);
+        const size_t np = bp.classes[ci].nprod;
+        o_m[ci] = take(sizeof(float) * KP * KP * np);
+        o_e[ci] = take(sizeof(long long) * KP * np);
+        o_s[ci] = take(sizeof(long long) * np);
     }
     if (hipMalloc(&bp.mem, off) != hipSuccess) {
         (void)hipGetLastError();
@@ -253,9 +296,17 @@ int build(hmm_ctx *ctx, BatchPlan &bp)
     bp.fjobs = reinterpret_cast<FoldJob *>(base + o_fjobs);
     bp.pjobs = reinterpret_cast<FoldJob *>(base + o_pjobs);
     int *status = reinterpret_cast<int *>(base + o_status);
+    bp.queues = reinterpret_cast<int *>(base + o_queues);
+    int n_cu = 0;
+    if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess ||
+        n_cu < 1) {
+        (void)hipGetLastError();
+        n_cu = 256;
+    }
     std::vector<int> ids;
     for (size_t ci = 0; ci < bp.classes.size(); ++ci) {
         BatchClass &c = bp.classes[ci];
+        c.queue = bp.queues + ci;
         if (c.serial) {
             c.ids = reinterpret_cast<int *>(base + o_ids) + ids.size();
             ids.insert(ids.end(), c.sets.begin(), c.sets.end());
@@ -302,11 +353,22 @@ int build(hmm_ctx *ctx, BatchPlan &bp)
          hipMemcpy(reinterpret_cast<int *>(base + o_ids), ids.data(), sizeof(int) * ids.size(),
                    hipMemcpyHostToDevice) != hipSuccess))
         return HMM_E_DEVICE;
-    for (const auto &c : bp.classes) {
+    for (auto &c : bp.classes) {
         if (c.serial) continue;
         const size_t rb = (size_t)region_bytes(c.ks.KP());
         if (allow_lds(c.ks.segB, rb * c.W) != HMM_OK || allow_lds(c.ks.foldB, rb * c.W2) != HMM_OK)
             return HMM_E_DEVICE;
+        // persistent launch: as many workgroups as are resident at once
+        c.grid = 0;
+        if (bp.persistent) {
+            int per_cu = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, c.ks.segB, 64 * c.W, rb * c.W) != hipSuccess ||
+                per_cu < 1) {
+                (void)hipGetLastError();
+                per_cu = 1;
+            }
+            c.grid = (int)std::min<int64_t>((int64_t)c.njobs, (int64_t)per_cu * n_cu);
+        }
     }
     return HMM_OK;
 }
@@ -323,8 +385,8 @@ int enqueue_class(const BatchPlan &bp, const BatchClass &c, hipStream_t st)
     std::memset(&none, 0, sizeof(none));
     const size_t rb = (size_t)region_bytes(c.ks.KP());
     if (c.njobs > 0 &&
-        launch_seg(c.ks.segB, (unsigned)c.njobs, c.W, rb * c.W, st, none, bp.sets, bp.jobs + c.job0, 0, c.M, c.E,
-                   c.S) != hipSuccess)
+        launch_seg(c.ks.segB, (unsigned)(c.grid > 0 ? c.grid : (int64_t)c.njobs), c.W, rb * c.W, st, none, bp.sets,
+                   bp.jobs + c.job0, (int64_t)c.njobs, c.M, c.E, c.S, c.grid > 0 ? c.queue : nullptr) != hipSuccess)
         return HMM_E_DEVICE;
     if (c.npjobs > 0 &&
         launch_fold(c.ks.foldB, (unsigned)c.npjobs, c.W2, rb * c.W2, st, none, bp.sets, bp.pjobs + c.pjob0, 0, 1, 0,
@@ -343,6 +405,10 @@ int enqueue_class(const BatchPlan &bp, const BatchClass &c, hipStream_t st)
 int enqueue(const BatchPlan &bp, hipStream_t st, const BatchClass *only = nullptr, bool branches = false)
 {
     if (!only) hipLaunchKernelGGL(k_prepare_batch, dim3(bp.n), dim3(256), 0, st, bp.prep);
+    // job counters of the persistent launches start at zero on every run
+    if (bp.persistent && !bp.classes.empty() && bp.queues)
+        hipLaunchKernelGGL(k_zero_i32, dim3((unsigned)((bp.classes.size() + 255) / 256)), dim3(256), 0, st,
+                           bp.queues, (int)bp.classes.size());
     if (!branches) {
         for (const auto &c : bp.classes) {
             if (only && &c != only) continue;
@@ -400,7 +466,8 @@ bool same_plan(const BatchPlan &bp, const hmm_ctx *ctx, int n, const int32_t *K,
 {
     if (bp.n != n || bp.algo != algo || bp.params != params || bp.flag != flag || bp.xy != xy || bp.out != out)
         return false;
-    if (bp.tuned != ctx->tuned_L) return false;
+    if (bp.tuned != ctx->tuned_L || bp.tunedW != ctx->tuned_W || bp.persistent != ctx->batch_persistent)
+        return false;
     return std::equal(K, K + n, bp.K.begin()) && std::equal(T, T + n, bp.T.begin()) &&
            std::equal(param_off, param_off + n, bp.param_off.begin()) &&
            std::equal(obs_off, obs_off + n, bp.obs_off.begin());
@@ -431,6 +498,8 @@ int get_plan(hmm_ctx *ctx, int n, const int32_t *K, const int64_t *T, const int6
     bp->xy = xy;
     bp->out = out;
     bp->tuned = ctx->tuned_L;
+    bp->tunedW = ctx->tuned_W;
+    bp->persistent = ctx->batch_persistent;
     int rc = build(ctx, *bp);
     if (rc == HMM_OK && ctx->batch_graph) rc = capture(*bp);
     if (rc != HMM_OK) {
@@ -508,6 +577,19 @@ int hmm_ctx_set_batch_graph(hmm_ctx *ctx, int32_t on)
     return HMM_OK;
 }
 
+int hmm_ctx_set_batch_persistent(hmm_ctx *ctx, int32_t on)
+{
+    if (!ctx) return HMM_E_INVALID_ARG;
+    ctx->batch_persistent = on != 0;
+    if (ctx->batch) {
+        DeviceGuard dg(ctx->device);
+        if (hipDeviceSynchronize() != hipSuccess) return HMM_E_DEVICE;
+        batch_plan_free(ctx->batch);
+        ctx->batch = nullptr;
+    }
+    return HMM_OK;
+}
+
 int hmm_autotune_batched(hmm_ctx *ctx, int32_t n, const int32_t *K, const int64_t *T, const int64_t *param_off,
                          const double *params, int64_t params_len, const int64_t *obs_off, const uint8_t *flag,
                          const double *xy, int64_t obs_len, int32_t algo, double *out, int32_t reps,
@@ -519,7 +601,10 @@ int hmm_autotune_batched(hmm_ctx *ctx, int32_t n, const int32_t *K, const int64_
     if (reps < 1) reps = 3;
     DeviceGuard dg(ctx->device);
     if (!dg.ok) return HMM_E_DEVICE;
-    const int64_t cands[] = {256, 512, 1024, 2048, 4096};
+    // candidates: segment length x segment-kernel waves per workgroup (the
+    // kernel's maximum, half of it); W = 0 stands for the maximum
+    const int64_t candL[] = {256, 512, 1024, 2048, 4096};
+    const int candW[] = {0, 2};   // 0: maximum; 2: half the maximum (divisor)
     // distinct K values of the batch, tuned one class at a time
     std::vector<int> ks(K, K + n);
     std::sort(ks.begin(), ks.end());
@@ -531,31 +616,47 @@ int hmm_autotune_batched(hmm_ctx *ctx, int32_t n, const int32_t *K, const int64_
     (void)hipEventCreate(&e1);
     const bool graph_was = ctx->batch_graph;
     ctx->batch_graph = false;
-    for (int k : ks) ctx->tuned_L.erase({k, algo});
+    for (int k : ks) {
+        ctx->tuned_L.erase({k, algo});
+        ctx->tuned_W.erase({k, algo});
+    }
     // classes are independent: time each class's launches under each candidate
-    std::map<const void *, std::pair<double, int64_t>> best;  // class seg kernel -> (ms, L)
-    for (int64_t L : cands) {
-        for (int k : ks) ctx->tuned_L[{k, algo}] = L;
-        BatchPlan *bp = nullptr;
-        rc = get_plan(ctx, n, K, T, param_off, params, obs_off, flag, xy, algo, out, &bp);
-        if (rc != HMM_OK) break;
-        hipLaunchKernelGGL(k_prepare_batch, dim3(bp->n), dim3(256), 0, st, bp->prep);
-        for (const auto &c : bp->classes) {
-            if (c.serial) continue;
-            float tot = 0.f;
-            for (int r = 0; r <= reps; ++r) {
-                (void)hipEventRecord(e0, st);
-                rc = enqueue(*bp, st, &c);
-                (void)hipEventRecord(e1, st);
-                if (rc != HMM_OK) break;
-                (void)hipEventSynchronize(e1);
-                float ms = 0.f;
-                (void)hipEventElapsedTime(&ms, e0, e1);
-                if (r > 0) tot += ms;  // first run warms up
+    struct Best {
+        double ms;
+        int64_t L;
+        int W;
+    };
+    std::map<const void *, Best> best;  // class segment kernel -> fastest (ms, L, W)
+    for (int wdiv : candW) {
+        for (int64_t L : candL) {
+            for (int k : ks) {
+                KernelSet kset;
+                const int wmax = select_kernels(algo, k, &kset) ? group_waves(kset.KP()) : 1;
+                ctx->tuned_L[{k, algo}] = L;
+                ctx->tuned_W[{k, algo}] = wdiv ? std::max(1, wmax / wdiv) : wmax;
             }
-            const double avg = tot / reps;
-            auto it = best.find(c.ks.seg1);
-            if (it == best.end() || avg < it->second.first) best[c.ks.seg1] = {avg, L};
+            BatchPlan *bp = nullptr;
+            rc = get_plan(ctx, n, K, T, param_off, params, obs_off, flag, xy, algo, out, &bp);
+            if (rc != HMM_OK) break;
+            hipLaunchKernelGGL(k_prepare_batch, dim3(bp->n), dim3(256), 0, st, bp->prep);
+            for (const auto &c : bp->classes) {
+                if (c.serial) continue;
+                float tot = 0.f;
+                for (int r = 0; r <= reps; ++r) {
+                    (void)hipEventRecord(e0, st);
+                    rc = enqueue(*bp, st, &c);
+                    (void)hipEventRecord(e1, st);
+                    if (rc != HMM_OK) break;
+                    (void)hipEventSynchronize(e1);
+                    float ms = 0.f;
+                    (void)hipEventElapsedTime(&ms, e0, e1);
+                    if (r > 0) tot += ms;  // first run warms up
+                }
+                const double avg = tot / reps;
+                auto it = best.find(c.ks.seg1);
+                if (it == best.end() || avg < it->second.ms) best[c.ks.seg1] = Best{avg, L, c.W};
+            }
+            if (rc != HMM_OK) break;
         }
         if (rc != HMM_OK) break;
     }
@@ -565,7 +666,8 @@ int hmm_autotune_batched(hmm_ctx *ctx, int32_t n, const int32_t *K, const int64_
             KernelSet kset;
             if (!select_kernels(algo, k, &kset)) continue;
             auto it = best.find(kset.seg1);
-            ctx->tuned_L[{k, algo}] = (it != best.end()) ? it->second.second : 0;
+            ctx->tuned_L[{k, algo}] = (it != best.end()) ? it->second.L : 0;
+            ctx->tuned_W[{k, algo}] = (it != best.end()) ? it->second.W : 0;
         }
         if (chosen_L)
             for (int s = 0; s < n; ++s) chosen_L[s] = ctx->tuned_L[{K[s], algo}];

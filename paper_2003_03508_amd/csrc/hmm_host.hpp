@@ -34,8 +34,12 @@ struct hmm_ctx {
     // batched path: the last plan (descriptor tables, scratch, captured graph)
     hmmh::BatchPlan *batch = nullptr;
     bool batch_graph = true;
-    // tuned segment length per (K, algo) for the batched path (0 = heuristic)
+    // tuned segment length and segment-kernel waves per workgroup per
+    // (K, algo) for the batched path (absent or 0 = heuristic / default)
     std::map<std::pair<int, int>, int64_t> tuned_L;
+    std::map<std::pair<int, int>, int> tuned_W;
+    // batched segment kernels run persistent with an atomic job queue
+    bool batch_persistent = true;
 };
 
 namespace hmmh {
@@ -239,13 +243,19 @@ KernelSet kernel_set_f32()
     return k;
 }
 
-template <int MT, bool F16, int NSL>
+// SPLIT: the hi/lo-split transition matrix (single set, tremor model only:
+// no batched or other-kind kernel, seg1g and segB are null).
+template <int MT, bool F16, int NSL, bool SPLIT = false>
 KernelSet kernel_set_lp()
 {
     KernelSet k;
-    k.seg1 = reinterpret_cast<const void *>(&k_blocked_lp<MT, F16, NSL, false>);
-    k.seg1g = reinterpret_cast<const void *>(&k_blocked_lp<MT, F16, NSL, false, true>);
-    k.segB = reinterpret_cast<const void *>(&k_blocked_lp<MT, F16, NSL, true>);
+    if constexpr (SPLIT) {
+        k.seg1 = reinterpret_cast<const void *>(&k_blocked_lp<MT, F16, NSL, false, false, true>);
+    } else {
+        k.seg1 = reinterpret_cast<const void *>(&k_blocked_lp<MT, F16, NSL, false>);
+        k.seg1g = reinterpret_cast<const void *>(&k_blocked_lp<MT, F16, NSL, false, true>);
+        k.segB = reinterpret_cast<const void *>(&k_blocked_lp<MT, F16, NSL, true>);
+    }
     k.fold1 = reinterpret_cast<const void *>(&k_fold<16, MT, NSL, false>);
     k.foldB = reinterpret_cast<const void *>(&k_fold<16, MT, NSL, true>);
     k.S = 16;
@@ -254,17 +264,13 @@ KernelSet kernel_set_lp()
     return k;
 }
 
-// Runtime number of live contraction slots (same rule as needed_slots<S, MT>).
+// Runtime number of live contraction slots (same rule as needed_slots<S, MT>):
+// in the slot-major state order K states fill ceil(K / G) slots, G = 64 / S.
 inline int live_slots(int S, int MT, int K)
 {
-    const int RS = S * S / 64;
-    int n = 0;
-    for (int j = 0; j < MT * RS; ++j) {
-        const int r = j % RS;
-        const int row = S * (j / RS) + (S == 16 ? r : 8 * (r >> 2) + (r & 3));
-        if (row < K) n = j + 1;
-    }
-    return n;
+    const int G = 64 / S, RS = S * S / 64;
+    const int n = (K + G - 1) / G;
+    return n < MT * RS ? n : MT * RS;
 }
 
 // Kernel sets compiled in hmm_api.hip (FP32 tiles with KP <= 48, 16-bit with
@@ -276,16 +282,21 @@ inline bool select_kernels(int algo, int K, KernelSet *ks)
 {
     Shape sh;
     if (!blocked_shape(K, &sh)) return false;
-    if (algo == HMM_BLOCKED_BF16 || algo == HMM_BLOCKED_F16) sh = Shape{16, (K + 15) / 16};
+    if (algo == HMM_BLOCKED_BF16 || algo == HMM_BLOCKED_F16 || algo == HMM_BLOCKED_BF16_SPLIT ||
+        algo == HMM_BLOCKED_F16_SPLIT)
+        sh = Shape{16, (K + 15) / 16};
     const int nsl = live_slots(sh.S, sh.MT, K);
     return kernels_small(algo, sh.S, sh.MT, nsl, ks) || kernels_large(algo, sh.S, sh.MT, nsl, ks);
 }
 
+// Segment kernel launch.  nb: segments (single set) or job-table entries
+// (batched); queue: atomic job counter of a persistent batched launch (null:
+// one workgroup per job or per W segments).
 inline hipError_t launch_seg(const void *fn, unsigned grid, int W, size_t lds, hipStream_t st, SetDesc one,
                              const SetDesc *sets, const WgJob *jobs, int64_t nb, float *M, long long *E,
-                             long long *Ssum)
+                             long long *Ssum, int *queue = nullptr)
 {
-    void *args[] = {&one, &sets, &jobs, &nb, &M, &E, &Ssum};
+    void *args[] = {&one, &sets, &jobs, &nb, &queue, &M, &E, &Ssum};
     return hipLaunchKernel(fn, dim3(grid), dim3(64 * W), args, lds, st);
 }
 

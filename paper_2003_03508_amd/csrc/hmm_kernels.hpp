@@ -394,15 +394,48 @@ __host__ __device__ constexpr int rit(int g, int r)
     return S == 16 ? 4 * g + r : 8 * (r >> 2) + 4 * g + (r & 3);
 }
 
-// Number of contraction slots (prefix) that touch one of the first K states.
+// Slot-major state order.  Physical row p of a padded KP x KP product
+// (tile p / S, row i = p % S of the tile) is held by lane group g, register
+// r with rit(g, r) = i, and is contracted in slot j = (p / S) * RS + r of the
+// permuted MFMA order.  States are assigned slot by slot,
+//     state(p) = j * G + g,  G = 64 / S lane groups,
+// so K states occupy exactly the first ceil(K / G) slots: only those slots
+// are issued, and registers of later slots hold padding rows only.  The
+// order is a permutation P of the KP padded states; every product is kept
+// as P M P^T (the same order for rows and columns), which leaves the chain
+// of eq. (2) unchanged up to the final delta^T ... 1, where delta is read
+// through the same order.
+template <int S, int MT>
+__host__ __device__ constexpr int phys_state(int p)
+{
+    constexpr int RS = S * S / 64, G = 64 / S;
+    const int m = p / S, i = p % S;
+    const int g = S == 16 ? (i >> 2) : ((i >> 2) & 1);
+    const int r = S == 16 ? (i & 3) : (((i >> 3) << 2) | (i & 3));
+    return (m * RS + r) * G + g;
+}
+
+// State held in register r of tile row m by lane group g.
+template <int S>
+__host__ __device__ constexpr int reg_state(int m, int g, int r)
+{
+    return (m * (S * S / 64) + r) * (64 / S) + g;
+}
+
+// Number of contraction slots that hold one of the first K states.
 template <int S, int MT>
 __host__ __device__ constexpr int needed_slots(int K)
 {
-    constexpr int RS = S * S / 64;
-    int n = 0;
-    for (int j = 0; j < MT * RS; ++j)
-        if (S * (j / RS) + rit<S>(0, j % RS) < K) n = j + 1;
-    return n;
+    constexpr int RS = S * S / 64, G = 64 / S;
+    const int n = (K + G - 1) / G;
+    return n < MT * RS ? n : MT * RS;
+}
+
+// Register (m, r) holds a state of a live slot.
+template <int S, int NSL>
+__host__ __device__ constexpr bool live_reg(int m, int r)
+{
+    return m * (S * S / 64) + r < NSL;
 }
 
 template <int S, int MT>
@@ -412,17 +445,20 @@ struct Prod {
     long long ex[MT];
 };
 
-template <int S, int MT>
-__device__ __forceinline__ void prod_identity(Prod<S, MT> &P)
+// The identity (in the physical order the identity stays the identity);
+// registers of dead slots are zero and are never written again.
+template <int S, int MT, int NSL>
+__device__ __forceinline__ void prod_identity(Prod<S, MT> &P, int lane)
 {
     constexpr int RS = Tile<S>::RS;
-    const int lane = threadIdx.x & 63, c = lane % S, g = lane / S;
+    const int c = lane % S, g = lane / S;
 #pragma unroll
     for (int m = 0; m < MT; ++m)
 #pragma unroll
         for (int n = 0; n < MT; ++n)
 #pragma unroll
-            for (int r = 0; r < RS; ++r) P.B[m][n][r] = (S * m + rit<S>(g, r) == S * n + c) ? 1.f : 0.f;
+            for (int r = 0; r < RS; ++r)
+                P.B[m][n][r] = (live_reg<S, NSL>(m, r) && S * m + rit<S>(g, r) == S * n + c) ? 1.f : 0.f;
 #pragma unroll
     for (int n = 0; n < MT; ++n) P.ex[n] = 0;
 }
@@ -442,7 +478,9 @@ __device__ __forceinline__ long long column_max_i64(long long x)
 
 // Divide every column of C (times an optional per-row factor) by the power of
 // two of its largest entry and store it as the new product; exponents add up.
-template <int S, int MT, bool SCALE>
+// Only registers of the NSL live slots are read and written (the others hold
+// padding rows, zero in C and in P).
+template <int S, int MT, int NSL, bool SCALE>
 __device__ __forceinline__ void renorm_columns(const typename Tile<S>::acc_t (&C)[MT][MT],
                                                const float (&ev)[MT][Tile<S>::RS], Prod<S, MT> &P)
 {
@@ -455,6 +493,7 @@ __device__ __forceinline__ void renorm_columns(const typename Tile<S>::acc_t (&C
         for (int m = 0; m < MT; ++m)
 #pragma unroll
             for (int r = 0; r < RS; ++r) {
+                if (!live_reg<S, NSL>(m, r)) continue;
                 v[m][r] = SCALE ? C[m][n][r] * ev[m][r] : C[m][n][r];
                 mx = fmaxf(mx, v[m][r]);
             }
@@ -463,7 +502,8 @@ __device__ __forceinline__ void renorm_columns(const typename Tile<S>::acc_t (&C
 #pragma unroll
         for (int m = 0; m < MT; ++m)
 #pragma unroll
-            for (int r = 0; r < RS; ++r) P.B[m][n][r] = __builtin_amdgcn_ldexpf(v[m][r], -e);
+            for (int r = 0; r < RS; ++r)
+                if (live_reg<S, NSL>(m, r)) P.B[m][n][r] = __builtin_amdgcn_ldexpf(v[m][r], -e);
         P.ex[n] += e;
     }
 }
@@ -586,6 +626,7 @@ __device__ __forceinline__ void combine_from_lds(Prod<S, MT> &P, long long &ssum
         for (int m = 0; m < MT; ++m)
 #pragma unroll
             for (int r = 0; r < RS; ++r) {
+                if (!live_reg<S, NSL>(m, r)) continue;
                 const float v = P.B[m][n][r];
                 const long long t = QE[S * m + rit<S>(g, r)] + fexp(v);
                 if (v > 0.f && t > beta) beta = t;
@@ -596,6 +637,7 @@ __device__ __forceinline__ void combine_from_lds(Prod<S, MT> &P, long long &ssum
             for (int m = 0; m < MT; ++m)
 #pragma unroll
                 for (int r = 0; r < RS; ++r) {
+                    if (!live_reg<S, NSL>(m, r)) continue;
                     long long d = QE[S * m + rit<S>(g, r)] - beta;
                     if (d < -400) d = -400;
                     P.B[m][n][r] = __builtin_amdgcn_ldexpf(P.B[m][n][r], (int)d);
@@ -619,7 +661,7 @@ __device__ __forceinline__ void combine_from_lds(Prod<S, MT> &P, long long &ssum
             C[m][n] = acc;
         }
     const float dummy[MT][RS] = {};
-    renorm_columns<S, MT, false>(C, dummy, P);
+    renorm_columns<S, MT, NSL, false>(C, dummy, P);
     ssum += *Region<KP>::QS(base);
 }
 
@@ -651,34 +693,22 @@ __device__ __forceinline__ void workgroup_tree(Prod<S, MT> &P, long long &ssum, 
 // end the workgroup multiplies its W segment products in order (tree in LDS)
 // and writes one product: Mout[q] (KP x KP row-major), Eout[q][KP], Sout[q].
 // ---------------------------------------------------------------------------
-template <int S, int MT, int NSL, bool BATCH, bool GEN = false>
-__global__ __launch_bounds__(64 * group_waves(S * MT)) void k_blocked(SetDesc one,
-                                                                      const SetDesc *__restrict__ sets,
-                                                                      const WgJob *__restrict__ jobs,
-                                                                      int64_t nb, float *__restrict__ Mout,
-                                                                      long long *__restrict__ Eout,
-                                                                      long long *__restrict__ Sout)
+// salt: 0 at run time.  In a persistent launch it comes from the job index,
+// so that nothing derived from the lane index is hoisted out of the job loop
+// and held in registers across jobs.
+template <int S, int MT, int NSL, bool GEN>
+__device__ __forceinline__ void blocked_job(const SetDesc &d, const WgJob &job, float *__restrict__ Mout,
+                                            long long *__restrict__ Eout, long long *__restrict__ Sout,
+                                            int salt = 0)
 {
     constexpr int KP = S * MT, RS = Tile<S>::RS;
     typedef typename Tile<S>::acc_t acc_t;
     extern __shared__ __attribute__((aligned(16))) float smem[];
     constexpr int region = Region<KP>::floats;
 
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int tid = (int)threadIdx.x + salt;
+    const int lane = tid & 63, w = tid >> 6;
     const int c = lane % S, g = lane / S;
-    const int W = blockDim.x >> 6;
-    WgJob job;
-    SetDesc d;
-    if constexpr (BATCH) {
-        job = jobs[blockIdx.x];
-        d = sets[job.set];
-    } else {
-        d = one;
-        job.seg0 = (int64_t)blockIdx.x * W;
-        job.nseg = (int)min((int64_t)W, nb - job.seg0);
-        job.out = blockIdx.x;
-        job.set = 0;
-    }
     const int K = d.K;
     const int64_t T = d.T, L = d.L;
     const float *__restrict__ GF = d.GF;
@@ -689,21 +719,21 @@ __global__ __launch_bounds__(64 * group_waves(S * MT)) void k_blocked(SetDesc on
     float *Et = Region<KP>::E(base);  // Et[k][t], row stride kChunk
 
     Prod<S, MT> P;
-    prod_identity<S, MT>(P);
+    prod_identity<S, MT, NSL>(P, lane);
     long long ssum = 0;
     int bad = 0, sh = 0;
 
     if (w < job.nseg) {
         const int64_t t0 = b * L;
         const int64_t t1 = min(T, t0 + L);
+        // A = Gamma^T in the slot-major order: row = output state of lane c,
+        // contraction index = the state of slot j on lane group g
         float A[MT][NSL];
 #pragma unroll
         for (int m = 0; m < MT; ++m)
 #pragma unroll
-            for (int j = 0; j < NSL; ++j) {
-                const int rho = S * (j / RS) + rit<S>(g, j % RS);
-                A[m][j] = GF[rho * KP + S * m + c];
-            }
+            for (int j = 0; j < NSL; ++j)
+                A[m][j] = GF[(j * (64 / S) + g) * KP + phys_state<S, MT>(S * m + c)];
         for (int i = lane; i < KP * kChunk; i += kWave) Et[i] = 0.f;  // rows >= K stay zero
         for (int64_t tc = t0; tc < t1; tc += kChunk) {
             const int nst = (int)min((int64_t)kChunk, t1 - tc);
@@ -715,7 +745,8 @@ __global__ __launch_bounds__(64 * group_waves(S * MT)) void k_blocked(SetDesc on
                 for (int m = 0; m < MT; ++m)
 #pragma unroll
                     for (int r = 0; r < RS; ++r) {
-                        const float *src = &Et[(S * m + rit<S>(g, r)) * kChunk + tl];
+                        if (!live_reg<S, NSL>(m, r)) continue;
+                        const float *src = &Et[reg_state<S>(m, g, r) * kChunk + tl];
                         if constexpr (kUnroll<S, MT> == 4) {
                             const float4 q = *reinterpret_cast<const float4 *>(src);
                             evu[m][r][0] = q.x;
@@ -735,7 +766,7 @@ __global__ __launch_bounds__(64 * group_waves(S * MT)) void k_blocked(SetDesc on
 #pragma unroll
                     for (int m = 0; m < MT; ++m)
 #pragma unroll
-                        for (int r = 0; r < RS; ++r) ev[m][r] = evu[m][r][u];
+                        for (int r = 0; r < RS; ++r) ev[m][r] = live_reg<S, NSL>(m, r) ? evu[m][r][u] : 0.f;
                     acc_t C[MT][MT];
 #pragma unroll
                     for (int m = 0; m < MT; ++m)
@@ -748,7 +779,7 @@ __global__ __launch_bounds__(64 * group_waves(S * MT)) void k_blocked(SetDesc on
                             for (int j = 0; j < NSL; ++j) acc = mfma<S>(A[m][j], P.B[j / RS][n][j % RS], acc);
                             C[m][n] = acc;
                         }
-                    renorm_columns<S, MT, true>(C, ev, P);
+                    renorm_columns<S, MT, NSL, true>(C, ev, P);
                 }
             }
             wave_sync_lds();
@@ -760,6 +791,60 @@ __global__ __launch_bounds__(64 * group_waves(S * MT)) void k_blocked(SetDesc on
     workgroup_tree<S, MT, NSL>(P, ssum, smem, region);
     if (w == 0)
         prod_to_global<S, MT>(P, ssum, Mout + job.out * KP * KP, Eout + job.out * KP, Sout + job.out);
+}
+
+// Work distribution of the segment kernels.  Single set (BATCH = false):
+// workgroup q takes segments [q W, q W + W).  Batched: with queue == null
+// workgroup q takes job q of the table; otherwise the launch is persistent
+// (about one wave of resident workgroups) and every workgroup pulls job
+// indices from the atomic counter *queue (zeroed before the launch) until
+// they run past the n_jobs entries.  The table is ordered by decreasing cost,
+// so the longest jobs start first and the short ones fill the tail.
+template <typename Job>
+__device__ __forceinline__ void run_jobs(const WgJob *__restrict__ jobs, int64_t n_jobs, int *queue, Job &&job)
+{
+    __shared__ int next;
+    // index of the next job: blockIdx.x without a queue, else from the counter
+    auto fetch = [&]() -> int64_t {
+        __syncthreads();   // every wavefront is done with the previous job and with `next`
+        if (threadIdx.x == 0) next = atomicAdd(queue, 1);
+        __syncthreads();
+        // the same value on every lane: make it a scalar, so that the job and
+        // set descriptors are read with scalar loads into scalar registers
+        return (int64_t)__builtin_amdgcn_readfirstlane(next);
+    };
+    int64_t q = queue ? fetch() : (int64_t)blockIdx.x;
+    while (q < n_jobs) {
+        const WgJob jb = jobs[q];
+        job(jb, (int)(q >> 40));   // q < 2^31: the salt is 0
+        if (!queue) break;
+        q = fetch();
+    }
+}
+
+template <int S, int MT, int NSL, bool BATCH, bool GEN = false>
+__global__ __launch_bounds__(64 * group_waves(S * MT)) void k_blocked(SetDesc one,
+                                                                      const SetDesc *__restrict__ sets,
+                                                                      const WgJob *__restrict__ jobs,
+                                                                      int64_t nb, int *queue,
+                                                                      float *__restrict__ Mout,
+                                                                      long long *__restrict__ Eout,
+                                                                      long long *__restrict__ Sout)
+{
+    if constexpr (BATCH) {
+        run_jobs(jobs, nb, queue, [&](const WgJob &job, int salt) {
+            const SetDesc d = sets[job.set];
+            blocked_job<S, MT, NSL, GEN>(d, job, Mout, Eout, Sout, salt);
+        });
+    } else {
+        const int W = blockDim.x >> 6;
+        WgJob job;
+        job.seg0 = (int64_t)blockIdx.x * W;
+        job.nseg = (int)min((int64_t)W, nb - job.seg0);
+        job.out = blockIdx.x;
+        job.set = 0;
+        blocked_job<S, MT, NSL, GEN>(one, job, Mout, Eout, Sout);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -799,13 +884,16 @@ template <> struct Lp<true> {
     }
 };
 
-template <int MT, bool F16, int NSL, bool BATCH, bool GEN = false>
-__global__ __launch_bounds__(64 * group_waves(16 * MT)) void k_blocked_lp(SetDesc one,
-                                                                          const SetDesc *__restrict__ sets,
-                                                                          const WgJob *__restrict__ jobs,
-                                                                          int64_t nb, float *__restrict__ Mout,
-                                                                          long long *__restrict__ Eout,
-                                                                          long long *__restrict__ Sout)
+// SPLIT: Gamma^T enters as two 16-bit operands, hi = round(G) and
+// lo = round(G - hi), both multiplied with the same B operand into the same
+// FP32 accumulator (same opcode), so the transition matrix carries about
+// twice the operand precision (the product N is still rounded once per
+// step).  Rounding Gamma once gives an error that is the same at every step
+// and so grows in proportion to T; the split removes most of it.
+template <int MT, bool F16, int NSL, bool GEN, bool SPLIT = false>
+__device__ __forceinline__ void blocked_lp_job(const SetDesc &d, const WgJob &job, float *__restrict__ Mout,
+                                               long long *__restrict__ Eout, long long *__restrict__ Sout,
+                                               int salt = 0)
 {
     constexpr int S = 16, KP = 16 * MT, RS = 4, NP = MT / 2, ODD = MT % 2;
     typedef typename Tile<S>::acc_t acc_t;
@@ -815,21 +903,9 @@ __global__ __launch_bounds__(64 * group_waves(16 * MT)) void k_blocked_lp(SetDes
     extern __shared__ __attribute__((aligned(16))) float smem[];
     constexpr int region = Region<KP>::floats;
 
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int tid = (int)threadIdx.x + salt;
+    const int lane = tid & 63, w = tid >> 6;
     const int c = lane % S, g = lane / S;
-    const int W = blockDim.x >> 6;
-    WgJob job;
-    SetDesc d;
-    if constexpr (BATCH) {
-        job = jobs[blockIdx.x];
-        d = sets[job.set];
-    } else {
-        d = one;
-        job.seg0 = (int64_t)blockIdx.x * W;
-        job.nseg = (int)min((int64_t)W, nb - job.seg0);
-        job.out = blockIdx.x;
-        job.set = 0;
-    }
     const int K = d.K;
     const int64_t T = d.T, L = d.L;
     const float *__restrict__ GF = d.GF;
@@ -840,7 +916,7 @@ __global__ __launch_bounds__(64 * group_waves(16 * MT)) void k_blocked_lp(SetDes
     float *Et = Region<KP>::E(base);
 
     Prod<S, MT> P;
-    prod_identity<S, MT>(P);
+    prod_identity<S, MT, NSL>(P, lane);
     long long ssum = 0;
     int bad = 0, sh = 0;
 
@@ -850,20 +926,27 @@ __global__ __launch_bounds__(64 * group_waves(16 * MT)) void k_blocked_lp(SetDes
         const float gscale = (float)(1 << lp::shift);
         v8 Ap[MT][NP > 0 ? NP : 1];
         v8 Ao[MT];
+        v8 Apl[SPLIT ? MT : 1][NP > 0 && SPLIT ? NP : 1];   // low parts (SPLIT only)
+        v8 Aol[SPLIT ? MT : 1];
 #pragma unroll
         for (int m = 0; m < MT; ++m) {
 #pragma unroll
             for (int p2 = 0; p2 < NP; ++p2)
 #pragma unroll
                 for (int e = 0; e < 8; ++e) {
-                    const int rho = 16 * (2 * p2 + e / 4) + 4 * g + (e % 4);
-                    Ap[m][p2][e] = (e_t)(GF[rho * KP + 16 * m + c] * gscale);
+                    // contraction row: register e % 4 of tile row 2 p2 + e / 4 on lane group g
+                    const int rho = reg_state<16>(2 * p2 + e / 4, g, e % 4);
+                    const float gv = GF[rho * KP + phys_state<16, MT>(16 * m + c)] * gscale;
+                    Ap[m][p2][e] = (e_t)gv;
+                    if constexpr (SPLIT) Apl[m][p2][e] = (e_t)(gv - (float)Ap[m][p2][e]);
                 }
             if constexpr (ODD) {
 #pragma unroll
                 for (int e = 0; e < 8; ++e) {
-                    const int rho = 16 * (MT - 1) + 4 * g + e;
-                    Ao[m][e] = (e < 4) ? (e_t)(GF[rho * KP + 16 * m + c] * gscale) : (e_t)0.f;
+                    const int rho = reg_state<16>(MT - 1, g, e % 4);
+                    const float gv = (e < 4) ? GF[rho * KP + phys_state<16, MT>(16 * m + c)] * gscale : 0.f;
+                    Ao[m][e] = (e_t)gv;
+                    if constexpr (SPLIT) Aol[m][e] = (e_t)(gv - (float)Ao[m][e]);
                 }
             }
         }
@@ -877,7 +960,11 @@ __global__ __launch_bounds__(64 * group_waves(16 * MT)) void k_blocked_lp(SetDes
                 for (int m = 0; m < MT; ++m)
 #pragma unroll
                     for (int r = 0; r < RS; ++r) {
-                        const float2 q = *reinterpret_cast<const float2 *>(&Et[(S * m + rit<S>(g, r)) * kChunk + tl]);
+                        if (!live_reg<S, NSL>(m, r)) {
+                            evu[m][r][0] = evu[m][r][1] = 0.f;
+                            continue;
+                        }
+                        const float2 q = *reinterpret_cast<const float2 *>(&Et[reg_state<S>(m, g, r) * kChunk + tl]);
                         evu[m][r][0] = q.x;
                         evu[m][r][1] = q.y;
                     }
@@ -910,11 +997,17 @@ __global__ __launch_bounds__(64 * group_waves(16 * MT)) void k_blocked_lp(SetDes
                         for (int n = 0; n < MT; ++n) {
                             acc_t acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-                            for (int p2 = 0; p2 < NP; ++p2) acc = lp::mma32(Ap[m][p2], Bp[p2][n], acc);
-                            if constexpr (ODD) acc = lp::mma32(Ao[m], Bo[n], acc);
+                            for (int p2 = 0; p2 < NP; ++p2) {
+                                if constexpr (SPLIT) acc = lp::mma32(Apl[m][p2], Bp[p2][n], acc);
+                                acc = lp::mma32(Ap[m][p2], Bp[p2][n], acc);
+                            }
+                            if constexpr (ODD) {
+                                if constexpr (SPLIT) acc = lp::mma32(Aol[m], Bo[n], acc);
+                                acc = lp::mma32(Ao[m], Bo[n], acc);
+                            }
                             C[m][n] = acc;
                         }
-                    renorm_columns<S, MT, true>(C, ev, P);
+                    renorm_columns<S, MT, NSL, true>(C, ev, P);
                 }
             }
             wave_sync_lds();
@@ -927,6 +1020,31 @@ __global__ __launch_bounds__(64 * group_waves(16 * MT)) void k_blocked_lp(SetDes
     workgroup_tree<S, MT, NSL>(P, ssum, smem, region);
     if (w == 0)
         prod_to_global<S, MT>(P, ssum, Mout + job.out * KP * KP, Eout + job.out * KP, Sout + job.out);
+}
+
+template <int MT, bool F16, int NSL, bool BATCH, bool GEN = false, bool SPLIT = false>
+__global__ __launch_bounds__(64 * group_waves(16 * MT)) void k_blocked_lp(SetDesc one,
+                                                                          const SetDesc *__restrict__ sets,
+                                                                          const WgJob *__restrict__ jobs,
+                                                                          int64_t nb, int *queue,
+                                                                          float *__restrict__ Mout,
+                                                                          long long *__restrict__ Eout,
+                                                                          long long *__restrict__ Sout)
+{
+    if constexpr (BATCH) {
+        run_jobs(jobs, nb, queue, [&](const WgJob &job, int salt) {
+            const SetDesc d = sets[job.set];
+            blocked_lp_job<MT, F16, NSL, GEN, SPLIT>(d, job, Mout, Eout, Sout, salt);
+        });
+    } else {
+        const int W = blockDim.x >> 6;
+        WgJob job;
+        job.seg0 = (int64_t)blockIdx.x * W;
+        job.nseg = (int)min((int64_t)W, nb - job.seg0);
+        job.out = blockIdx.x;
+        job.set = 0;
+        blocked_lp_job<MT, F16, NSL, GEN, SPLIT>(one, job, Mout, Eout, Sout);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -988,7 +1106,7 @@ __global__ __launch_bounds__(64 * group_waves(S * MT)) void k_fold(SetDesc one, 
             wave_sync_lds();
         }
     } else {
-        prod_identity<S, MT>(P);
+        prod_identity<S, MT, NSL>(P, lane);
     }
     workgroup_tree<S, MT, NSL>(P, ssum, smem, region);
     if (w != 0) return;
@@ -1008,8 +1126,8 @@ __global__ __launch_bounds__(64 * group_waves(S * MT)) void k_fold(SetDesc one, 
             for (int r = 0; r < RS; ++r) rs += (double)P.B[m][n][r];
         rs += __shfl_xor(rs, 32);
         if constexpr (S == 16) rs += __shfl_xor(rs, 16);
-        const int row = S * n + c;
-        term[n] = (row < K && g == 0) ? delta[row] * rs : 0.0;
+        const int st = phys_state<S, MT>(S * n + c);   // the row's state
+        term[n] = (st < K && g == 0) ? delta[st] * rs : 0.0;
         if (term[n] > 0.0 && P.ex[n] > emax) emax = P.ex[n];
     }
     emax = wave_max_i64(emax);

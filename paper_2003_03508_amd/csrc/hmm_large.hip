@@ -21,17 +21,29 @@ bool pick_f32(int nsl, KernelSet *ks)
     }
 }
 
-template <int MT, bool F16, int LO, int HI>
+template <int MT, bool F16, int LO, int HI, bool SPLIT = false>
 bool pick_lp(int nsl, KernelSet *ks)
 {
     if constexpr (LO > HI) {
         return false;
     } else {
         if (nsl == LO) {
-            *ks = kernel_set_lp<MT, F16, LO>();
+            *ks = kernel_set_lp<MT, F16, LO, SPLIT>();
             return true;
         }
-        return pick_lp<MT, F16, LO + 1, HI>(nsl, ks);
+        return pick_lp<MT, F16, LO + 1, HI, SPLIT>(nsl, ks);
+    }
+}
+
+template <int MT, int LO, int HI>
+bool pick_lp_algo(int algo, int nsl, KernelSet *ks)
+{
+    switch (algo) {
+    case HMM_BLOCKED_BF16: return pick_lp<MT, false, LO, HI>(nsl, ks);
+    case HMM_BLOCKED_F16: return pick_lp<MT, true, LO, HI>(nsl, ks);
+    case HMM_BLOCKED_BF16_SPLIT: return pick_lp<MT, false, LO, HI, true>(nsl, ks);
+    case HMM_BLOCKED_F16_SPLIT: return pick_lp<MT, true, LO, HI, true>(nsl, ks);
+    default: return false;
     }
 }
 
@@ -44,10 +56,9 @@ bool kernels_large(int algo, int S, int MT, int NSL, KernelSet *ks)
         if (S == 16 && MT == 5) return pick_f32<16, 5, 17, 20>(NSL, ks);
         return false;
     }
-    const bool f16 = (algo == HMM_BLOCKED_F16);
     if (S != 16) return false;
-    if (MT == 4) return f16 ? pick_lp<4, true, 13, 16>(NSL, ks) : pick_lp<4, false, 13, 16>(NSL, ks);
-    if (MT == 5) return f16 ? pick_lp<5, true, 17, 20>(NSL, ks) : pick_lp<5, false, 17, 20>(NSL, ks);
+    if (MT == 4) return pick_lp_algo<4, 13, 16>(algo, NSL, ks);
+    if (MT == 5) return pick_lp_algo<5, 17, 20>(algo, NSL, ks);
     return false;
 }
 

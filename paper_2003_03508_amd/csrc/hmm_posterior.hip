@@ -260,32 +260,37 @@ __device__ __forceinline__ void product_load(const float *M, const long long *E,
     r.e = lane < KP ? E[lane] : 0;
 }
 
-// Into LDS, row-major (transpose = false) or transposed.
+// State of physical row p of a blocked-path product (the slot-major order of
+// the segment and fold kernels; the tile side S follows from KP).
+__device__ __forceinline__ int prow_state(int KP, int p)
+{
+    const bool s32 = (KP == 32 || KP == 64);
+    const int i = s32 ? (p & 31) : (p & 15), m = s32 ? (p >> 5) : (p >> 4);
+    const int g = s32 ? ((i >> 2) & 1) : (i >> 2);
+    const int r = s32 ? (((i >> 3) << 2) | (i & 3)) : (i & 3);
+    return s32 ? (m * 16 + r) * 2 + g : (m * 4 + r) * 4 + g;
+}
+
+// Into LDS in state order, row-major (transpose = false) or transposed: the
+// products come in the kernels' slot-major order and are reordered here.
 __device__ __forceinline__ void product_store(const ProdRegs &r, int KP, float *lm, long long *le, bool transpose)
 {
     const int lane = threadIdx.x & 63;
     const int n4 = KP * KP / 4;
-    if (!transpose) {
-        float4 *dst = reinterpret_cast<float4 *>(lm);
 #pragma unroll
-        for (int q = 0; q < kMaxKP * kMaxKP / 4 / 64; ++q) {
-            const int i = lane + 64 * q;
-            if (i < n4) dst[i] = r.m[q];
-        }
-    } else {
+    for (int q = 0; q < kMaxKP * kMaxKP / 4 / 64; ++q) {
+        const int i = lane + 64 * q;
+        if (i < n4) {
+            const int row = prow_state(KP, (4 * i) / KP), col = (4 * i) % KP;
+            const float v[4] = {r.m[q].x, r.m[q].y, r.m[q].z, r.m[q].w};
 #pragma unroll
-        for (int q = 0; q < kMaxKP * kMaxKP / 4 / 64; ++q) {
-            const int i = lane + 64 * q;
-            if (i < n4) {
-                const int row = (4 * i) / KP, col = (4 * i) % KP;
-                lm[(col + 0) * KP + row] = r.m[q].x;
-                lm[(col + 1) * KP + row] = r.m[q].y;
-                lm[(col + 2) * KP + row] = r.m[q].z;
-                lm[(col + 3) * KP + row] = r.m[q].w;
+            for (int k = 0; k < 4; ++k) {
+                const int sc = prow_state(KP, col + k);
+                lm[transpose ? sc * KP + row : row * KP + sc] = v[k];
             }
         }
     }
-    if (lane < KP) le[lane] = r.e;
+    if (lane < KP) le[prow_state(KP, lane)] = r.e;
     wsync();
 }
 

@@ -849,6 +849,7 @@ int mcmc_create(hmm_ctx *ctx, int32_t K, int32_t n_chains, int64_t T, const uint
     if (rc == HMM_OK) rc = hmm_ctx_create(&s->own, ctx->device);
     if (rc == HMM_OK) {
         s->own->tuned_L = ctx->tuned_L;
+        s->own->tuned_W = ctx->tuned_W;
         s->own->batch_graph = false;
         if (hipStreamCreateWithFlags(&s->cap, hipStreamNonBlocking) != hipSuccess) rc = HMM_E_DEVICE;
     }

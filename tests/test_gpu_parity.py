@@ -210,13 +210,14 @@ def lowp_bound(algo, K, T):
     factors are nonnegative, so each step adds at most 2*u_op (operand rounding
     of Gamma and N) + (K+1)*2^-24 (FP32 accumulation) relative error, plus
     K*2^-24 for FP16 subnormal flushes of N's small entries."""
-    eta = 2 * U_OP[algo] + (K + 1) * 2.0 ** -24
-    if algo == "blocked_f16":
+    base = algo.replace("_split", "")
+    eta = 2 * U_OP[base] + (K + 1) * 2.0 ** -24
+    if base == "blocked_f16":
         eta += K * 2.0 ** -24
     return T * eta
 
 
-@pytest.mark.parametrize("algo", ["blocked_bf16", "blocked_f16"])
+@pytest.mark.parametrize("algo", ["blocked_bf16", "blocked_f16", "blocked_bf16_split", "blocked_f16_split"])
 @pytest.mark.parametrize("K", [3, 16, 25, 40, 64, 80])
 def test_blocked_16bit_within_bound(binding, ctx, algo, K):
     T = 4000 + 37 * K
@@ -245,12 +246,31 @@ def test_full_size_k80_t4m_all_precisions(binding, ctx):
     prm, obs, want = golden("k80_t4m")
     got = gpu(binding, ctx, prm, obs, "blocked_f32")
     assert_close(got, want, "blocked_f32 k80_t4m")
-    for algo in ("blocked_bf16", "blocked_f16"):
+    errs = {}
+    for algo in ("blocked_bf16", "blocked_f16", "blocked_bf16_split", "blocked_f16_split"):
         got = gpu(binding, ctx, prm, obs, algo)
         err = abs(got - want)
+        errs[algo] = err
         bound = lowp_bound(algo, 80, obs.T)
         print(f"{algo} k80_t4m: |d ln L| = {err:.3e} nats, rel {err / abs(want):.2e} (bound {bound:.3e})")
         assert err <= bound
+    # the split removes the error that rounding Gamma once makes at every step
+    assert errs["blocked_bf16_split"] < errs["blocked_bf16"]
+
+
+def test_split_is_tremor_single_set_only(binding, ctx):
+    """The split algorithms serve hmm_loglik; the batched call and the other
+    emission kinds reject them."""
+    sets = [synth.make(5, 100, seed=990 + i) for i in range(2)]
+    d = binding.batch_to_device(synth.pack(sets))
+    with pytest.raises(binding.HMMError) as e:
+        ctx.loglik_batched(**d, algo="blocked_bf16_split")
+    assert e.value.code == binding.HMM_E_INVALID_ARG
+    ks = synth.make_kind(1, 5, 200, seed=991)
+    kd = binding.kind_to_device(ks)
+    with pytest.raises(binding.HMMError) as e:
+        ctx.loglik_kind(1, kd["delta"], kd["Gamma"], kd["e0"], None, kd["obs"], algo="blocked_f16_split")
+    assert e.value.code == binding.HMM_E_UNSUPPORTED
 
 
 # ---------------------------------------------------------------- batched evaluation
@@ -379,3 +399,58 @@ def test_batched_serial_and_graph_modes(binding, ctx):
     finally:
         ctx.batch_graph(True)
     assert (g0 == g1).all()  # same kernels, same order: identical with or without the graph
+
+
+def test_batched_persistent_queue_many_rounds(binding, ctx):
+    """Many more jobs than resident workgroups (short segments force several
+    rounds): the persistent launches (atomic job queue, reset on every graph
+    replay) give the same bits as one workgroup per job, and match the
+    oracle.  Parameters change between replays, so a queue counter left from
+    the previous replay (jobs skipped, stale products) would show."""
+    sets = [synth.make(K, T, seed=900 + i) for i, (K, T) in
+            enumerate([(25, 20_000)] * 24 + [(9, 15_000)] * 8 + [(40, 9_000)] * 6 + [(64, 5_000)] * 3)]
+    packed = synth.pack(sets)
+    d = binding.batch_to_device(packed)
+    ctx = binding.Context(0)   # no tuned lengths: the 48-step segments apply
+    ctx.set_blocking(48, 0)
+    try:
+        res = {}
+        for mode in (True, False):
+            ctx.set_batch_persistent(mode)
+            d["params"].copy_(torch.as_tensor(packed["params"], dtype=torch.float64, device="cuda"))
+            outs = []
+            for rep in range(3):
+                if rep == 2:   # change set 0's parameters in place before the third replay
+                    prm0 = sets[0][0]
+                    blk = synth.HMMParams(prm0.delta, prm0.Gamma, prm0.p * 0.7, prm0.mu, prm0.Sigma).packed()
+                    d["params"][0:blk.size].copy_(torch.as_tensor(blk, dtype=torch.float64, device="cuda"))
+                outs.append(ctx.loglik_batched(**d).cpu().numpy())
+            res[mode] = outs
+        for rep in range(3):
+            assert (res[True][rep] == res[False][rep]).all(), rep
+        assert (res[True][0] == res[True][1]).all()
+        for i in range(0, len(sets), 5):
+            assert_close(float(res[True][1][i]), ref(*sets[i]), f"persistent set {i}")
+        prm0, obs0 = sets[0]
+        p2 = synth.HMMParams(prm0.delta, prm0.Gamma, prm0.p * 0.7, prm0.mu, prm0.Sigma)
+        assert_close(float(res[True][2][0]), ref(p2, obs0), "after in-place update")
+        assert (res[True][2][1:] == res[True][1][1:]).all()
+    finally:
+        ctx.close()
+
+
+def test_autotune_batched_waves(binding, ctx):
+    """The tuner's (segment length, waves per workgroup) choice keeps the
+    results within the FP32 tolerance for every class, with and without the
+    persistent queue."""
+    sets = [synth.make(K, 30_000, seed=950 + K) for K in (6, 20, 30, 44, 60, 77)]
+    packed = synth.pack(sets)
+    d = binding.batch_to_device(packed)
+    chosen = ctx.autotune_batched(**d, reps=1)
+    assert all(L in (256, 512, 1024, 2048, 4096) for L in chosen)
+    for mode in (True, False):
+        ctx.set_batch_persistent(mode)
+        out = ctx.loglik_batched(**d).cpu().numpy()
+        for i, (prm, obs) in enumerate(sets):
+            assert_close(float(out[i]), ref(prm, obs), f"tuned set {i} K={prm.K} persistent={mode}")
+    ctx.set_batch_persistent(True)
