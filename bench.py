@@ -99,6 +99,16 @@ def issued_mfma_flops(K, T, n_blocks):
     nsl = min(MT * RS, -(-K // G))   # slot-major state order: ceil(K / G) live slots
     per_mfma = 2 * S * S * (64 // S)
     per_product = MT * MT * nsl * per_mfma
+    if 16 < K <= 28:
+        # packed: G = 128 // K segments per wavefront share NT = 4 column
+        # tiles; every wavefront runs L steps of NT * NSL MFMAs, then folds its
+        # G products, and 8 wavefronts per workgroup meet in the tree
+        G, NT, waves_per_wg = 128 // K, 4, 8
+        L = -(-T // n_blocks) if n_blocks else 0
+        waves = -(-n_blocks // G)
+        n_wg = -(-waves // waves_per_wg)
+        issued = waves * L * NT * per_product + waves * G * per_product + n_wg * (waves_per_wg - 1) * per_product
+        return float(issued), {"S": S, "MT": MT, "NSL": nsl, "packed_segments_per_wave": G, "packed_tiles": NT}
     n_wg = -(-n_blocks // W)
     return float(T * per_product + n_wg * (W - 1) * per_product), {"S": S, "MT": MT, "NSL": nsl}
 
@@ -236,7 +246,9 @@ def main():
                 "frac": round(achieved_tflops / PEAK_FP32_MFMA_TFLOPS, 4),
                 "traffic": measured_traffic(), "traffic_unit": "bytes/launch",
                 "algorithmic_bytes": 17 * T,
-                "kernel": "k_blocked<%d,%d,%d>" % (tile["S"], tile["MT"], tile["NSL"]),
+                "kernel": ("k_blocked_packed<%d,%d,%d>" % (tile["packed_tiles"], tile["packed_segments_per_wave"],
+                                                             tile["NSL"]) if "packed_tiles" in tile
+                           else "k_blocked<%d,%d,%d>" % (tile["S"], tile["MT"], tile["NSL"])),
                 "kernel_avg_ms": round(kern_avg_ms, 5),
                 "launches_timed": launches, "flops_per_launch": flops,
                 "issued_flops_per_launch": issued,

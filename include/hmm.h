@@ -223,6 +223,17 @@ int hmm_ctx_set_batch_graph(hmm_ctx *ctx, int32_t on);
  * same; only the order in which workgroups take them differs). */
 int hmm_ctx_set_batch_persistent(hmm_ctx *ctx, int32_t on);
 
+/* Column packing of the FP32 blocked path (default on): for 16 < K <= 28 one
+ * wavefront advances floor(128 / K) segments at once, their start-state
+ * columns side by side in four 32-column MFMA tiles, so that one step costs
+ * 4 ceil(K / 2) MFMAs for all of them instead of ceil(K / 2) per segment.
+ * Single-set calls pack when the segment length is automatic
+ * (hmm_ctx_set_blocking with block_len 0); batched calls pack every class
+ * with such a K.  Off: one segment per wavefront as for other K.  The
+ * products are the same up to FP32 rounding order.  HMM_E_INVALID_ARG for a
+ * null context. */
+int hmm_ctx_set_packing(hmm_ctx *ctx, int32_t on);
+
 /* Autotuner of the batched path: for every class of sets that share a
  * kernel, times the class's launches (reps repetitions after one warm-up)
  * for segment lengths 256..4096 and for the segment kernel's full and half
@@ -489,7 +500,7 @@ int hmm_theta_to_params(hmm_ctx *ctx, int32_t K, int32_t n, const double *theta,
  * (section "The likelihood algorithm"): the products give the forward and
  * backward messages at segment boundaries, then every segment reruns the
  * forward and backward recursions over its own observations (FP32 within a
- * segment, FP64 at the boundaries and in all sums).  1 <= K <= 64.
+ * segment, FP64 at the boundaries and in all sums).  1 <= K <= 80.
  *
  * hmm_posterior: device outputs
  *   gamma  float [T*K]: gamma[t*K + k] = P(s_t = k | x_0..x_{T-1})
@@ -512,7 +523,7 @@ int hmm_theta_to_params(hmm_ctx *ctx, int32_t K, int32_t n, const double *theta,
  *   2K + 3K] = [d/d delta | d/d Gamma (row-major) | d/d p | d/d mu (x, y per
  *   state) | d/d Sigma (xx, xy, yy per state; Sxy as one variable that
  *   enters both off-diagonal positions)].  Needs T*K floats of workspace.
- * Both enqueue on `stream`; HMM_E_UNSUPPORTED for K > 64.
+ * Both enqueue on `stream`; HMM_E_UNSUPPORTED for K > 80.
  * ------------------------------------------------------------------------ */
 int hmm_posterior(hmm_ctx *ctx, int32_t K, const double *delta, const double *Gamma,
                   const double *p, const double *mu, const double *Sigma, int64_t T,
@@ -542,7 +553,7 @@ int hmm_loglik_grad(hmm_ctx *ctx, int32_t K, const double *delta, const double *
  * Invalid parameters or data: ln L and params_out NaN.  EM may drive a state
  * to a singular Sigma (one tremor location); the next call then reports the
  * parameters as invalid.  Needs T*K floats of workspace; enqueues on
- * `stream`; HMM_E_UNSUPPORTED for K > 64.
+ * `stream`; HMM_E_UNSUPPORTED for K > 80.
  * ------------------------------------------------------------------------ */
 int hmm_em_step(hmm_ctx *ctx, int32_t K, const double *delta, const double *Gamma,
                 const double *p, const double *mu, const double *Sigma, int64_t T,
@@ -556,14 +567,15 @@ int hmm_em_step(hmm_ctx *ctx, int32_t K, const double *delta, const double *Gamm
  * segments (log2, FP32, renormalised every step; FP64 offsets), combined in
  * groups of 16 level by level, decoded top-down, then a Viterbi pass with
  * backpointers inside every segment between its two boundary states.  Ties
- * go to the smallest state index.  1 <= K <= 64.
+ * go to the smallest state index.  1 <= K <= 80 (64 < K: two wavefronts per
+ * segment, the matrix exchanged through LDS).
  *   path   device int32 [T]: s_0 .. s_{T-1} (required when T > 0)
  *   first  device int32 [1]: s_{-1}
  *   score  device double [1]: the maximum (natural log)
  * T = 0: first = argmax delta, score = ln max delta.  Invalid parameters or
  * data: score NaN, first and path -1.  FP32 scores inside segments: a path
  * whose joint log probability is within about 1e-6 relative of the best one
- * may be returned instead of it.  HMM_E_UNSUPPORTED for K > 64. */
+ * may be returned instead of it.  HMM_E_UNSUPPORTED for K > 80. */
 int hmm_viterbi(hmm_ctx *ctx, int32_t K, const double *delta, const double *Gamma,
                 const double *p, const double *mu, const double *Sigma, int64_t T,
                 const uint8_t *flag, const double *xy, void *stream, int32_t *path,

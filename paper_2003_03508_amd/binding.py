@@ -53,6 +53,7 @@ _lib.hmm_ctx_profile_read.argtypes = [_vp, ctypes.POINTER(_i64), ctypes.POINTER(
 _lib.hmm_loglik_batched.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _i64, _i32, _vp, _vp]
 _lib.hmm_ctx_set_batch_graph.argtypes = [_vp, _i32]
 _lib.hmm_ctx_set_batch_persistent.argtypes = [_vp, _i32]
+_lib.hmm_ctx_set_packing.argtypes = [_vp, _i32]
 _lib.hmm_autotune_batched.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _i64, _i32, _vp,
                                       _i32, _vp]
 _lib.hmm_loglik_kind.argtypes = [_vp, _i32, _i32, _vp, _vp, _vp, _vp, _i64, _vp, _i32, _vp, _vp]
@@ -109,7 +110,7 @@ _lib.hmm_status_string.argtypes = [ctypes.c_int]
 for _f in ("hmm_ctx_create", "hmm_ctx_destroy", "hmm_loglik", "hmm_loglik_noalloc", "hmm_emission",
            "hmm_ctx_set_blocking", "hmm_blocked_plan", "hmm_ctx_profile", "hmm_ctx_profile_read",
            "hmm_loglik_batched", "hmm_ctx_set_batch_graph", "hmm_ctx_set_batch_persistent",
-           "hmm_autotune_batched",
+           "hmm_ctx_set_packing", "hmm_autotune_batched",
            "hmm_theta_to_params", "hmm_philox", "hmm_loglik_kind", "mcmc_create", "mcmc_destroy", "mcmc_set_state",
            "mcmc_set_rw_scale", "mcmc_step", "mcmc_train_proposal", "mcmc_reset_proposal", "mcmc_view_get",
            "mlp_forward",
@@ -359,6 +360,10 @@ class Context:
         """Persistent batched segment launches with an atomic job queue (default) or one
         workgroup per job."""
         _check("hmm_ctx_set_batch_persistent", _lib.hmm_ctx_set_batch_persistent(self._h, 1 if on else 0))
+
+    def set_packing(self, on=True):
+        """Several segments per wavefront for FP32 with 16 < K <= 28 (default) or one."""
+        _check("hmm_ctx_set_packing", _lib.hmm_ctx_set_packing(self._h, 1 if on else 0))
 
     @staticmethod
     def _desc(K, T, param_off, obs_off):

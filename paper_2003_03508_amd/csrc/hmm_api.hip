@@ -81,6 +81,39 @@ bool kernels_small(int algo, int S, int MT, int NSL, KernelSet *ks)
     return false;
 }
 
+namespace {
+
+template <int K>
+void set_packed(KernelSet *ks)
+{
+    constexpr int NT = 4, G = 128 / K, NSL = (K + 1) / 2;
+    ks->segP = reinterpret_cast<const void *>(&k_blocked_packed<NT, G, NSL, false>);
+    ks->segPB = reinterpret_cast<const void *>(&k_blocked_packed<NT, G, NSL, true>);
+    ks->packNT = NT;
+    ks->packG = G;
+}
+
+template <int LO, int HI>
+bool pick_packed(int K, KernelSet *ks)
+{
+    if constexpr (LO > HI) {
+        return false;
+    } else {
+        if (K == LO) {
+            set_packed<LO>(ks);
+            return true;
+        }
+        return pick_packed<LO + 1, HI>(K, ks);
+    }
+}
+
+}  // namespace
+
+bool packed_kernel(int K, KernelSet *ks)
+{
+    return pick_packed<17, 28>(K, ks);
+}
+
 }  // namespace hmmh
 
 namespace {
@@ -157,8 +190,8 @@ int loglik_impl(hmm_ctx *ctx, int kind, int32_t K, const double *delta, const do
     if (!select_kernels(algo, K, &ks)) return HMM_E_UNSUPPORTED;
     if (!(kind == kEmisTremor ? ks.seg1 : ks.seg1g)) return HMM_E_UNSUPPORTED;   // split: tremor model only
     const int KP = ks.KP();
-    Plan pl = make_plan(ctx, KP, T);
-    if (pl.n1 > INT_MAX || !grid_fits(pl.n1, 64 * pl.W)) return HMM_E_UNSUPPORTED;
+    Plan pl = make_plan(ctx, KP, T, (kind == kEmisTremor && ks.segP) ? ks.packG : 0);
+    if (pl.n1 > INT_MAX || !grid_fits(pl.n1, 64 * pl.waves)) return HMM_E_UNSUPPORTED;
     Layout ly = make_layout(KP, pl);
     rc = ensure_ws(ctx, ly.total + sizeof(double) * kFactBlocks);
     if (rc != HMM_OK) return rc;
@@ -228,8 +261,8 @@ size_t loglik_scratch_bytes(int32_t K, int64_t T, int32_t algo, KernelSet *ks, P
         return ly->total;
     }
     if (!select_kernels(algo, K, ks)) return 0;
-    *pl = make_plan(&defaults, ks->KP(), T);
-    if (pl->n1 > INT_MAX || !grid_fits(pl->n1, 64 * pl->W)) return 0;
+    *pl = make_plan(&defaults, ks->KP(), T, ks->segP ? ks->packG : 0);
+    if (pl->n1 > INT_MAX || !grid_fits(pl->n1, 64 * pl->waves)) return 0;
     *ly = make_layout(ks->KP(), *pl);
     return ly->total;
 }
@@ -322,10 +355,10 @@ int hmm_blocked_plan(hmm_ctx *ctx, int32_t K, int64_t T, int64_t *block_len, int
                      int32_t *levels)
 {
     if (!block_len || !n_blocks || !levels || T < 0 || T >= kMaxT || K < 1) return HMM_E_INVALID_ARG;
-    Shape sh;
-    if (!blocked_shape(K, &sh)) return HMM_E_UNSUPPORTED;
+    KernelSet ks;
+    if (!select_kernels(HMM_BLOCKED_F32, K, &ks)) return HMM_E_UNSUPPORTED;
     const hmm_ctx defaults;
-    Plan pl = make_plan(ctx ? ctx : &defaults, sh.KP(), T);
+    Plan pl = make_plan(ctx ? ctx : &defaults, ks.KP(), T, ks.segP ? ks.packG : 0);
     *block_len = pl.L;
     *n_blocks = pl.nb;
     *levels = pl.levels;

@@ -18,7 +18,12 @@ struct BatchClass {
     const void *serial = nullptr;  // plain-forward path: k_serial_batch<KP>
     int KP = 0;
     int *ids = nullptr;    // plain-forward path: the class's set ids (device)
-    int W = 1, W2 = 1;
+    // batched segment kernel (k_blocked or, with G > 1 segments per
+    // wavefront, k_blocked_packed), its wavefronts per workgroup and LDS
+    const void *seg = nullptr;
+    int G = 1, waves = 1;
+    size_t seg_lds = 0;
+    int W = 1, W2 = 1;     // segments per segment job, wavefronts of a fold workgroup
     int64_t L = 0;
     int grid = 0;          // workgroups of the persistent segment launch (0: one per job)
     int *queue = nullptr;  // its atomic job counter (device)
@@ -43,7 +48,7 @@ struct BatchPlan {
     double *out = nullptr;
     std::map<std::pair<int, int>, int64_t> tuned;
     std::map<std::pair<int, int>, int> tunedW;
-    bool persistent = true;
+    bool persistent = true, packing = true;
     // device memory
     void *mem = nullptr;
     SetDesc *sets = nullptr;
@@ -118,16 +123,28 @@ int64_t class_L(const hmm_ctx *ctx, const BatchPlan &bp, const BatchClass &c, in
     return best;
 }
 
+// Most wavefronts per workgroup of a class's segment kernel.
+int max_waves(const BatchClass &c) { return c.G > 1 ? kPackWaves : group_waves(c.KP); }
+
 // Segment-kernel waves per workgroup of a class: a tuned value (1..the
 // kernel's maximum) wins, else the maximum.
-int class_W(const hmm_ctx *ctx, const BatchPlan &bp, const BatchClass &c, int algo)
+int class_waves(const hmm_ctx *ctx, const BatchPlan &bp, const BatchClass &c, int algo)
 {
-    const int wmax = group_waves(c.KP);
+    const int wmax = max_waves(c);
     for (int s : c.sets) {
         auto it = ctx->tuned_W.find({bp.K[s], algo});
         if (it != ctx->tuned_W.end() && it->second > 0) return std::min(it->second, wmax);
     }
     return wmax;
+}
+
+// The kernel that identifies a class: the batched segment kernel (the packed
+// one where there is one for K, FP32 with 16 < K <= 28, and packing is on),
+// or the plain-forward kernel.
+const void *class_key(const KernelSet &ks, bool serial, bool packing)
+{
+    if (serial) return ks.seg1;
+    return (packing && ks.segPB) ? ks.segPB : ks.segB;
 }
 
 // Fill kernel for the queue counters (a kernel, not a memset node, so that
@@ -166,13 +183,16 @@ int build(hmm_ctx *ctx, BatchPlan &bp)
         }
     }
     for (int s = 0; s < n; ++s) {
+        const void *key = class_key(kss[s], serial, bp.packing);
         auto it = std::find_if(bp.classes.begin(), bp.classes.end(),
-                               [&](const BatchClass &c) { return c.ks.seg1 == kss[s].seg1; });
+                               [&](const BatchClass &c) { return c.seg == key; });
         if (it == bp.classes.end()) {
             BatchClass c;
             c.ks = kss[s];
             c.KP = kp[s];
+            c.seg = key;
             if (serial) c.serial = kss[s].seg1;
+            c.G = (!serial && key == kss[s].segPB) ? kss[s].packG : 1;
             c.W = group_waves(c.KP);
             c.W2 = c.W;
             bp.classes.push_back(c);
@@ -186,7 +206,10 @@ int build(hmm_ctx *ctx, BatchPlan &bp)
     for (size_t ci = 0; ci < bp.classes.size(); ++ci) {
         BatchClass &c = bp.classes[ci];
         if (c.serial) continue;
-        c.W = class_W(ctx, bp, c, bp.algo);
+        c.waves = class_waves(ctx, bp, c, bp.algo);
+        c.W = c.waves * c.G;
+        c.seg_lds = c.G > 1 ? (size_t)packed_region_bytes(c.ks.packNT, c.G) * c.waves
+                            : (size_t)region_bytes(c.KP) * c.waves;
         c.L = class_L(ctx, bp, c, bp.algo, c.W);
         c.job0 = jobs.size();
         c.fjob0 = fjobs.size();
@@ -248,7 +271,7 @@ int build(hmm_ctx *ctx, BatchPlan &bp)
                          [&](const WgJob &x, const WgJob &y) { return job_obs(x) > job_obs(y); });
         for (size_t q = c.job0; q < jobs.size(); ++q)
             c.cost += (double)job_obs(jobs[q]) * c.KP * c.KP * c.KP;
-        if (!grid_fits((int64_t)c.njobs, 64 * c.W) || !grid_fits((int64_t)c.npjobs, 64 * c.W2))
+        if (!grid_fits((int64_t)c.njobs, 64 * c.waves) || !grid_fits((int64_t)c.npjobs, 64 * c.W2))
             return HMM_E_UNSUPPORTED;
         c.nprod = (size_t)std::max<int64_t>(base, 1);
     }
@@ -320,8 +343,9 @@ int build(hmm_ctx *ctx, BatchPlan &bp)
     std::vector<PrepJob> hp(n);
     for (int s = 0; s < n; ++s) {
         const BatchClass *c = nullptr;
+        const void *key = class_key(kss[s], serial, bp.packing);
         for (const auto &cc : bp.classes)
-            if (cc.ks.seg1 == kss[s].seg1) c = &cc;
+            if (cc.seg == key) c = &cc;
         SetDesc &d = hs[s];
         d.obs = Obs{bp.flag + bp.obs_off[s], bp.xy + 2 * bp.obs_off[s], nullptr, kEmisTremor, 0};
         d.sc = reinterpret_cast<const StateConst *>(base + o_sc[s]);
@@ -356,13 +380,13 @@ int build(hmm_ctx *ctx, BatchPlan &bp)
     for (auto &c : bp.classes) {
         if (c.serial) continue;
         const size_t rb = (size_t)region_bytes(c.ks.KP());
-        if (allow_lds(c.ks.segB, rb * c.W) != HMM_OK || allow_lds(c.ks.foldB, rb * c.W2) != HMM_OK)
+        if (allow_lds(c.seg, c.seg_lds) != HMM_OK || allow_lds(c.ks.foldB, rb * c.W2) != HMM_OK)
             return HMM_E_DEVICE;
         // persistent launch: as many workgroups as are resident at once
         c.grid = 0;
         if (bp.persistent) {
             int per_cu = 0;
-            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, c.ks.segB, 64 * c.W, rb * c.W) != hipSuccess ||
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, c.seg, 64 * c.waves, c.seg_lds) != hipSuccess ||
                 per_cu < 1) {
                 (void)hipGetLastError();
                 per_cu = 1;
@@ -385,7 +409,7 @@ int enqueue_class(const BatchPlan &bp, const BatchClass &c, hipStream_t st)
     std::memset(&none, 0, sizeof(none));
     const size_t rb = (size_t)region_bytes(c.ks.KP());
     if (c.njobs > 0 &&
-        launch_seg(c.ks.segB, (unsigned)(c.grid > 0 ? c.grid : (int64_t)c.njobs), c.W, rb * c.W, st, none, bp.sets,
+        launch_seg(c.seg, (unsigned)(c.grid > 0 ? c.grid : (int64_t)c.njobs), c.waves, c.seg_lds, st, none, bp.sets,
                    bp.jobs + c.job0, (int64_t)c.njobs, c.M, c.E, c.S, c.grid > 0 ? c.queue : nullptr) != hipSuccess)
         return HMM_E_DEVICE;
     if (c.npjobs > 0 &&
@@ -466,7 +490,8 @@ bool same_plan(const BatchPlan &bp, const hmm_ctx *ctx, int n, const int32_t *K,
 {
     if (bp.n != n || bp.algo != algo || bp.params != params || bp.flag != flag || bp.xy != xy || bp.out != out)
         return false;
-    if (bp.tuned != ctx->tuned_L || bp.tunedW != ctx->tuned_W || bp.persistent != ctx->batch_persistent)
+    if (bp.tuned != ctx->tuned_L || bp.tunedW != ctx->tuned_W || bp.persistent != ctx->batch_persistent ||
+        bp.packing != ctx->packing)
         return false;
     return std::equal(K, K + n, bp.K.begin()) && std::equal(T, T + n, bp.T.begin()) &&
            std::equal(param_off, param_off + n, bp.param_off.begin()) &&
@@ -500,6 +525,7 @@ int get_plan(hmm_ctx *ctx, int n, const int32_t *K, const int64_t *T, const int6
     bp->tuned = ctx->tuned_L;
     bp->tunedW = ctx->tuned_W;
     bp->persistent = ctx->batch_persistent;
+    bp->packing = ctx->packing;
     int rc = build(ctx, *bp);
     if (rc == HMM_OK && ctx->batch_graph) rc = capture(*bp);
     if (rc != HMM_OK) {
@@ -590,6 +616,19 @@ int hmm_ctx_set_batch_persistent(hmm_ctx *ctx, int32_t on)
     return HMM_OK;
 }
 
+int hmm_ctx_set_packing(hmm_ctx *ctx, int32_t on)
+{
+    if (!ctx) return HMM_E_INVALID_ARG;
+    ctx->packing = on != 0;
+    if (ctx->batch) {
+        DeviceGuard dg(ctx->device);
+        if (hipDeviceSynchronize() != hipSuccess) return HMM_E_DEVICE;
+        batch_plan_free(ctx->batch);
+        ctx->batch = nullptr;
+    }
+    return HMM_OK;
+}
+
 int hmm_autotune_batched(hmm_ctx *ctx, int32_t n, const int32_t *K, const int64_t *T, const int64_t *param_off,
                          const double *params, int64_t params_len, const int64_t *obs_off, const uint8_t *flag,
                          const double *xy, int64_t obs_len, int32_t algo, double *out, int32_t reps,
@@ -626,12 +665,14 @@ int hmm_autotune_batched(hmm_ctx *ctx, int32_t n, const int32_t *K, const int64_
         int64_t L;
         int W;
     };
-    std::map<const void *, Best> best;  // class segment kernel -> fastest (ms, L, W)
+    std::map<const void *, Best> best;  // class segment kernel -> fastest (ms, L, waves)
     for (int wdiv : candW) {
         for (int64_t L : candL) {
             for (int k : ks) {
                 KernelSet kset;
-                const int wmax = select_kernels(algo, k, &kset) ? group_waves(kset.KP()) : 1;
+                int wmax = 1;
+                if (select_kernels(algo, k, &kset))
+                    wmax = (ctx->packing && kset.segPB) ? kPackWaves : group_waves(kset.KP());
                 ctx->tuned_L[{k, algo}] = L;
                 ctx->tuned_W[{k, algo}] = wdiv ? std::max(1, wmax / wdiv) : wmax;
             }
@@ -653,8 +694,8 @@ int hmm_autotune_batched(hmm_ctx *ctx, int32_t n, const int32_t *K, const int64_
                     if (r > 0) tot += ms;  // first run warms up
                 }
                 const double avg = tot / reps;
-                auto it = best.find(c.ks.seg1);
-                if (it == best.end() || avg < it->second.ms) best[c.ks.seg1] = Best{avg, L, c.W};
+                auto it = best.find(c.seg);
+                if (it == best.end() || avg < it->second.ms) best[c.seg] = Best{avg, L, c.waves};
             }
             if (rc != HMM_OK) break;
         }
@@ -665,7 +706,7 @@ int hmm_autotune_batched(hmm_ctx *ctx, int32_t n, const int32_t *K, const int64_
         for (int k : ks) {
             KernelSet kset;
             if (!select_kernels(algo, k, &kset)) continue;
-            auto it = best.find(kset.seg1);
+            auto it = best.find(class_key(kset, false, ctx->packing));
             ctx->tuned_L[{k, algo}] = (it != best.end()) ? it->second.L : 0;
             ctx->tuned_W[{k, algo}] = (it != best.end()) ? it->second.W : 0;
         }

@@ -40,6 +40,8 @@ struct hmm_ctx {
     std::map<std::pair<int, int>, int> tuned_W;
     // batched segment kernels run persistent with an atomic job queue
     bool batch_persistent = true;
+    // FP32 paths with 16 < K <= 28 pack several segments per wavefront
+    bool packing = true;
 };
 
 namespace hmmh {
@@ -127,17 +129,40 @@ inline int serial_kp(int K)
 struct Plan {
     int64_t L = 0;      // observations per segment
     int64_t nb = 0;     // segments
-    int W = 1;          // segments (wavefronts) per workgroup of the segment kernel
+    int W = 1;          // segments per workgroup of the segment kernel
     int64_t n1 = 0;     // products written by the segment kernel
     int W2 = 1, F = 1;  // fold: wavefronts per workgroup, inputs folded per wavefront
     int levels = 0;     // fold launches (the last one finishes ln L)
+    int waves = 1;      // wavefronts per workgroup of the segment kernel
+    bool packed = false;  // k_blocked_packed: G segments per wavefront
 };
 
-inline Plan make_plan(const hmm_ctx *ctx, int KP, int64_t T)
+inline Plan make_plan(const hmm_ctx *ctx, int KP, int64_t T, int packG = 0)
 {
     Plan p;
     p.W = group_waves(KP);
     p.W2 = group_waves(KP);
+    p.waves = p.W;
+    if (packG > 0 && ctx->packing && ctx->block_len == 0) {
+        // packed: kPackWaves wavefronts of packG segments per workgroup, one
+        // workgroup per CU (256), segments of at least 16 observations
+        p.packed = true;
+        p.waves = kPackWaves;
+        p.W = kPackWaves * packG;
+        const int64_t target = 256 * (int64_t)p.W;
+        p.L = std::max<int64_t>(16, (T + target - 1) / target);
+        p.nb = T > 0 ? (T + p.L - 1) / p.L : 0;
+        p.n1 = (p.nb + p.W - 1) / p.W;
+        p.F = ctx->fold > 0 ? ctx->fold : 1;
+        const int64_t per_wg = (int64_t)p.F * p.W2;
+        int64_t n = p.n1;
+        p.levels = 1;
+        while (n > per_wg) {
+            n = (n + per_wg - 1) / per_wg;
+            ++p.levels;
+        }
+        return p;
+    }
     // One workgroup of W segments per CU (256 CUs), segments of at least 32
     // observations.
     if (ctx->block_len > 0) {
@@ -225,6 +250,11 @@ inline int allow_lds(const void *fn, size_t bytes)
 struct KernelSet {
     const void *seg1 = nullptr, *seg1g = nullptr, *segB = nullptr, *fold1 = nullptr, *foldB = nullptr;
     int S = 0, MT = 0, NSL = 0;
+    // FP32 segment kernels with G segments per wavefront packed into NT
+    // column tiles (k_blocked_packed), if there are for this K: single set
+    // (segP) and batched (segPB)
+    const void *segP = nullptr, *segPB = nullptr;
+    int packNT = 0, packG = 0;
     int KP() const { return S * MT; }
 };
 
@@ -278,6 +308,18 @@ inline int live_slots(int S, int MT, int K)
 bool kernels_small(int algo, int S, int MT, int NSL, KernelSet *ks);
 bool kernels_large(int algo, int S, int MT, int NSL, KernelSet *ks);
 
+// LDS bytes per wavefront of k_blocked_packed (pack_region_floats at run time).
+inline int packed_region_bytes(int NT, int G)
+{
+    (void)NT;
+    const int ch = ((64 / G) / 4) * 4, et = G * 32 * ch, q = Region<32>::floats;
+    return 4 * ((et > q ? et : q) + 128);
+}
+
+// k_blocked_packed for 16 < K <= 28 (NT = 4 tiles, G = floor(128 / K)
+// segments); compiled in hmm_api.hip.  False when there is none for K.
+bool packed_kernel(int K, KernelSet *ks);
+
 inline bool select_kernels(int algo, int K, KernelSet *ks)
 {
     Shape sh;
@@ -286,7 +328,9 @@ inline bool select_kernels(int algo, int K, KernelSet *ks)
         algo == HMM_BLOCKED_F16_SPLIT)
         sh = Shape{16, (K + 15) / 16};
     const int nsl = live_slots(sh.S, sh.MT, K);
-    return kernels_small(algo, sh.S, sh.MT, nsl, ks) || kernels_large(algo, sh.S, sh.MT, nsl, ks);
+    if (!(kernels_small(algo, sh.S, sh.MT, nsl, ks) || kernels_large(algo, sh.S, sh.MT, nsl, ks))) return false;
+    if (algo == HMM_BLOCKED_F32) packed_kernel(K, ks);
+    return true;
 }
 
 // Segment kernel launch.  nb: segments (single set) or job-table entries
@@ -316,9 +360,12 @@ inline int run_single(hmm_ctx *ctx, void *ws, const KernelSet &ks, SetDesc d, co
                       hipStream_t st)
 {
     const int KP = ks.KP();
-    const void *seg = d.obs.kind == kEmisTremor ? ks.seg1 : ks.seg1g;
+    const bool packed = pl.packed;
+    if (packed && !(ks.segP && d.obs.kind == kEmisTremor)) return HMM_E_UNSUPPORTED;   // plan made for another kernel
+    const void *seg = packed ? ks.segP : (d.obs.kind == kEmisTremor ? ks.seg1 : ks.seg1g);
     const size_t rb = (size_t)region_bytes(KP);
-    if (allow_lds(seg, rb * pl.W) != HMM_OK || allow_lds(ks.fold1, rb * pl.W2) != HMM_OK)
+    const size_t seg_lds = packed ? (size_t)packed_region_bytes(ks.packNT, ks.packG) * pl.waves : rb * pl.W;
+    if (allow_lds(seg, seg_lds) != HMM_OK || allow_lds(ks.fold1, rb * pl.W2) != HMM_OK)
         return HMM_E_DEVICE;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     if (ctx && ctx->profile && pl.nb > 0 && ctx->events_used < kMaxTimed) {
@@ -333,10 +380,11 @@ inline int run_single(hmm_ctx *ctx, void *ws, const KernelSet &ks, SetDesc d, co
         ++ctx->events_used;
     }
     if (ev0) (void)hipEventRecord(ev0, st);
-    if (pl.nb > 0 &&
-        launch_seg(seg, (unsigned)pl.n1, pl.W, rb * pl.W, st, d, nullptr, nullptr, pl.nb,
-                   at<float>(ws, ly.m0), at<long long>(ws, ly.e0), at<long long>(ws, ly.s0)) != hipSuccess)
-        return HMM_E_DEVICE;
+    if (pl.nb > 0) {
+        if (launch_seg(seg, (unsigned)pl.n1, pl.waves, seg_lds, st, d, nullptr, nullptr, pl.nb,
+                       at<float>(ws, ly.m0), at<long long>(ws, ly.e0), at<long long>(ws, ly.s0)) != hipSuccess)
+            return HMM_E_DEVICE;
+    }
     if (ev1) (void)hipEventRecord(ev1, st);
     int64_t n = pl.n1;
     const float *mi = at<float>(ws, ly.m0);

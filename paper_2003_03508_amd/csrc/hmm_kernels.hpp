@@ -3,6 +3,7 @@
 #pragma once
 
 #include <climits>
+#include <type_traits>
 
 #include "hmm_device.hpp"
 
@@ -844,6 +845,252 @@ __global__ __launch_bounds__(64 * group_waves(S * MT)) void k_blocked(SetDesc on
         job.out = blockIdx.x;
         job.set = 0;
         blocked_job<S, MT, NSL, GEN>(one, job, Mout, Eout, Sout);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Several segments per wavefront (FP32, one 32-row tile, 16 < K <= 32).  The
+// start-state columns of G consecutive segments are packed side by side in
+// NT tiles of 32 columns: column 32 n + c holds start state (32 n + c) % K of
+// the wavefront's segment (32 n + c) / K (no segment for columns >= G K).
+// The A operand (Gamma^T) does not depend on the segment, so one step of all
+// G segments costs NT * NSL MFMAs instead of G * NSL, and the per-column
+// renormalisation touches NT tiles instead of G: at K = 25, 5 segments in 4
+// tiles (125 of 128 columns live) instead of 25 of 32 per segment.  Each
+// column is scaled by the emissions of its own segment at the same relative
+// step (all segments of a plan have length L; the last segment of the
+// sequence may be shorter, and its columns then keep their value once it has
+// ended).  At the end the wavefront multiplies its segments' products in
+// order (each staged through LDS in the layout of the other kernels), and the
+// workgroup tree combines the wavefronts as in k_blocked.
+// ---------------------------------------------------------------------------
+template <int G>
+__host__ __device__ constexpr int pack_chunk()
+{
+    // observations per segment per staging pass: G * CH <= 64 lanes, CH a
+    // multiple of 4 (float4 reads of four steps)
+    return ((64 / G) / 4) * 4;
+}
+
+template <int NT, int G>
+__host__ __device__ constexpr int pack_region_floats()
+{
+    constexpr int et = G * 32 * pack_chunk<G>(), q = Region<32>::floats;
+    return (et > q ? et : q) + 64 * 2;   // + per-lane shift sums (int64)
+}
+
+constexpr int kPackWaves = 8;   // wavefronts per workgroup (two per SIMD)
+
+// One workgroup job: segments [job.seg0, job.seg0 + job.nseg) of the set, G
+// per wavefront in order, product to slot job.out.
+template <int NT, int G, int NSL>
+__device__ __forceinline__ void packed_job(const SetDesc &d, const WgJob &job, float *__restrict__ Mout,
+                                           long long *__restrict__ Eout, long long *__restrict__ Sout,
+                                           int salt = 0)
+{
+    constexpr int S = 32, KP = 32, RS = 16, CH = pack_chunk<G>();
+    constexpr int region = pack_region_floats<NT, G>();
+    typedef typename Tile<S>::acc_t acc_t;
+    extern __shared__ __attribute__((aligned(16))) float smem[];
+    const int tid = (int)threadIdx.x + salt;   // salt: as in blocked_job
+    const int lane = tid & 63, w = tid >> 6;
+    const int c = lane % S, g = lane / S;
+    const int K = d.K;
+    const int64_t T = d.T, L = d.L;
+    float *base = smem + w * region;
+    float *Et = base;                                                   // [G][KP][CH]
+    long long *lsum = reinterpret_cast<long long *>(base + (region - 128));   // per-lane shift sums
+    const int64_t b0 = job.seg0 + (int64_t)w * G;                        // first segment of this wavefront
+    const int64_t nb = job.seg0 + job.nseg;                              // end of the job's segments
+
+    // the columns of this lane: segment and start state per tile
+    int segn[NT], stn[NT];
+    bool liven[NT];
+    int64_t lenn[NT];
+#pragma unroll
+    for (int n = 0; n < NT; ++n) {
+        const int col = S * n + c;
+        segn[n] = col / K;
+        stn[n] = col % K;
+        const int64_t b = b0 + segn[n];
+        liven[n] = segn[n] < G && b < nb;
+        lenn[n] = liven[n] ? min(L, T - b * L) : 0;
+        if (!liven[n]) segn[n] = 0;
+    }
+    // A = Gamma^T in the slot-major order (as k_blocked)
+    float A[NSL];
+#pragma unroll
+    for (int j = 0; j < NSL; ++j) A[j] = d.GF[(j * 2 + g) * KP + phys_state<S, 1>(c)];
+    // identity per live column: state stn at the register holding it
+    typename Tile<S>::acc_t B[NT];
+    long long ex[NT];
+#pragma unroll
+    for (int n = 0; n < NT; ++n) {
+#pragma unroll
+        for (int r = 0; r < RS; ++r) B[n][r] = (liven[n] && r < NSL && reg_state<S>(0, g, r) == stn[n]) ? 1.f : 0.f;
+        ex[n] = 0;
+    }
+    for (int i = lane; i < G * KP * CH; i += kWave) Et[i] = 0.f;   // rows >= K stay zero
+    long long ssum = 0;   // shifts of the observations this lane stages (its segment lane / CH)
+    int bad = 0;
+    // staging lane: segment sl, step tl0 within the chunk
+    const int sl = lane / CH, tl0 = lane % CH;
+    const int64_t bl = b0 + sl;
+    const bool stager = sl < G && bl < nb;
+    const int64_t t0l = bl * L, t1l = stager ? min(T, t0l + L) : 0;
+    // do all live segments of the wavefront run the full L steps?
+    bool full = true;
+#pragma unroll
+    for (int n = 0; n < NT; ++n) full &= (!liven[n] || lenn[n] == L);
+    full = __all(full);
+    const int64_t Lw = [&] {
+        int64_t m = 0;
+#pragma unroll
+        for (int n = 0; n < NT; ++n) m = lenn[n] > m ? lenn[n] : m;
+        return m;
+    }();
+    int64_t steps = Lw;
+    for (int o = 32; o > 0; o >>= 1) {
+        const int64_t y = __shfl_xor(steps, o);
+        steps = y > steps ? y : steps;
+    }
+    for (int64_t tc = 0; tc < steps; tc += CH) {
+        const int nst = (int)min((int64_t)CH, steps - tc);
+        // stage: lane (sl, tl0) evaluates observation t0l + tc + tl0 of its segment
+        {
+            const int64_t t = t0l + tc + tl0;
+            const bool live = stager && tl0 < nst && t < t1l;
+            int f = 0;
+            double x = 0.0, y = 0.0;
+            if (live) {
+                f = d.obs.flag[t];
+                if (f == 1) {
+                    const double2 p = reinterpret_cast<const double2 *>(d.obs.xy)[t];
+                    x = p.x;
+                    y = p.y;
+                    if (!(isfinite(x) && isfinite(y))) bad = 1;
+                } else if (f != 0) {
+                    bad = 1;
+                }
+            }
+            const bool tremor = (f == 1);
+            double m = -INFINITY;
+            for (int k = 0; k < K; ++k) m = fmax(m, state_log2_emission(d.sc[k], tremor, x, y));
+            int sh = 0;
+            if (m > -1.0e9 && m < 1.0e9) sh = (int)floor(m) - kEmisBias;
+            if (live) ssum += sh;
+            if (sl < G) {
+                float *row = Et + sl * (KP * CH) + tl0;
+                for (int k = 0; k < K; ++k) {
+                    const double r = state_log2_emission(d.sc[k], tremor, x, y) - (double)sh;
+                    float e = 0.f;
+                    if (live && r > -160.0) {
+                        const double nn = floor(r);
+                        e = __builtin_amdgcn_ldexpf(exp2f((float)(r - nn)), (int)nn);
+                    }
+                    row[k * CH] = e;
+                }
+            }
+            wave_sync_lds();
+        }
+        auto steps_of = [&](auto masked) {
+            constexpr bool MASK = decltype(masked)::value;
+            for (int tl = 0; tl < nst; ++tl) {
+                acc_t C[NT];
+#pragma unroll
+                for (int n = 0; n < NT; ++n) {
+                    acc_t acc;
+#pragma unroll
+                    for (int r = 0; r < RS; ++r) acc[r] = 0.f;
+#pragma unroll
+                    for (int j = 0; j < NSL; ++j) acc = mfma<S>(A[j], B[n][j], acc);
+                    C[n] = acc;
+                }
+#pragma unroll
+                for (int n = 0; n < NT; ++n) {
+                    const float *ev = Et + segn[n] * (KP * CH) + tl;
+                    const bool act = !MASK || (tc + tl < lenn[n]);
+                    float v[RS];
+                    float mx = 0.f;
+#pragma unroll
+                    for (int r = 0; r < RS; ++r) {
+                        if (r >= NSL) continue;
+                        v[r] = act ? C[n][r] * ev[reg_state<S>(0, g, r) * CH] : B[n][r];
+                        mx = fmaxf(mx, v[r]);
+                    }
+                    mx = column_max<S>(mx);
+                    const int e = (mx > 0.f) ? fexp(mx) : 0;
+#pragma unroll
+                    for (int r = 0; r < RS; ++r)
+                        if (r < NSL) B[n][r] = __builtin_amdgcn_ldexpf(v[r], -e);
+                    ex[n] += e;
+                }
+            }
+        };
+        if (full) steps_of(std::integral_constant<bool, false>());
+        else steps_of(std::integral_constant<bool, true>());
+        wave_sync_lds();
+    }
+    if (__any(bad) && lane == 0) atomicOr(d.status, kBadData);
+    // shift sum of each segment: lanes [s CH, (s + 1) CH) staged segment s
+    lsum[lane] = ssum;
+    wave_sync_lds();
+    // multiply the segments' products in order into P (the layout of k_blocked)
+    Prod<S, 1> P;
+    prod_identity<S, 1, NSL>(P, lane);
+    long long ptot = 0;
+    float *Q = Region<KP>::E(base);
+    for (int s = 0; s < G; ++s) {
+        if (b0 + s >= nb) break;
+        long long ss = 0;
+        for (int i = 0; i < CH; ++i) ss += lsum[s * CH + i];   // every lane reads the same values
+        wave_sync_lds();
+        // rows of padding states are zero; the live rows come from the columns of segment s
+        for (int i = lane; i < KP * KP; i += kWave) Q[i] = 0.f;
+        if (lane < KP) Region<KP>::QE(base)[lane] = 0;
+        wave_sync_lds();
+#pragma unroll
+        for (int n = 0; n < NT; ++n) {
+            if (!(liven[n] && segn[n] == s)) continue;
+            // physical row of start state stn[n]: the row whose state is stn[n]
+            const int st = stn[n];
+            const int prow = 8 * ((st >> 1) >> 2) + 4 * (st & 1) + ((st >> 1) & 3);
+#pragma unroll
+            for (int r = 0; r < RS; ++r) Q[prow * KP + rit<S>(g, r)] = B[n][r];
+            if (g == 0) Region<KP>::QE(base)[prow] = ex[n];
+        }
+        if (lane == 0) *Region<KP>::QS(base) = ss;
+        wave_sync_lds();
+        combine_from_lds<S, 1, NSL>(P, ptot, base);
+        wave_sync_lds();
+    }
+    workgroup_tree<S, 1, NSL>(P, ptot, smem, region);
+    if (w == 0)
+        prod_to_global<S, 1>(P, ptot, Mout + job.out * KP * KP, Eout + job.out * KP, Sout + job.out);
+}
+
+// Single set (BATCH false): workgroup q takes segments [q W, q W + W), W =
+// G per wavefront.  Batched: jobs from the table (persistent with a queue).
+template <int NT, int G, int NSL, bool BATCH>
+__global__ __launch_bounds__(64 * kPackWaves) void k_blocked_packed(SetDesc one, const SetDesc *__restrict__ sets,
+                                                                    const WgJob *__restrict__ jobs, int64_t nb,
+                                                                    int *queue, float *__restrict__ Mout,
+                                                                    long long *__restrict__ Eout,
+                                                                    long long *__restrict__ Sout)
+{
+    if constexpr (BATCH) {
+        run_jobs(jobs, nb, queue, [&](const WgJob &job, int salt) {
+            const SetDesc d = sets[job.set];
+            packed_job<NT, G, NSL>(d, job, Mout, Eout, Sout, salt);
+        });
+    } else {
+        const int W = (blockDim.x >> 6) * G;
+        WgJob job;
+        job.seg0 = (int64_t)blockIdx.x * W;
+        job.nseg = (int)min((int64_t)W, nb - job.seg0);
+        job.out = blockIdx.x;
+        job.set = 0;
+        packed_job<NT, G, NSL>(one, job, Mout, Eout, Sout);
     }
 }
 

@@ -55,7 +55,7 @@ using namespace hmmh;
 namespace {
 
 constexpr int kMoments = 7;            // per-state moments
-constexpr int kMaxKP = 64;             // largest padded K of the posterior path
+constexpr int kMaxKP = 80;             // largest padded K of the posterior path
 constexpr int64_t kPostSegments = 4096; // target segment count of the posterior plan
 
 __device__ __forceinline__ double wsum_f64(double x)
@@ -130,44 +130,68 @@ struct ScanLevel {
     int K, KP, G, pad;
 };
 
+// States per lane of the message passes: lane j holds states j + 64 q,
+// q < NS (two for the padded K = 80).
+template <int KP> constexpr int msg_ns() { return (KP + 63) / 64; }
+
 // a <- normalise(a M), M = diag(2^E) M~ in LDS (the common shift drops out).
-// Lane j < K holds a_j; sa is the message's LDS copy, sf and si scratch.  The
-// largest exponent and the sum are read back from LDS by every lane (no
-// cross-lane shuffles).  The loops run over all KP padded states with
-// branch-free bodies, so their LDS reads issue back to back: padded states
-// contribute exact zeros (sf = 0, si = LLONG_MIN, zero rows of M).
+// Lane j holds a_s for its states s = j + 64 q < K; sa is the message's LDS
+// copy, sf and si scratch (NS * 64 entries each).  The largest exponent and
+// the sum are read back from LDS by every lane (no cross-lane shuffles).  The
+// loops run over all KP padded states with branch-free bodies, so their LDS
+// reads issue back to back: padded states contribute exact zeros (sf = 0,
+// si = LLONG_MIN, zero rows of M).
 template <int KP>
-__device__ void msg_forward(int K, const float *M, const long long *E, double &a, double *sa, double *sf,
-                            long long *si)
+__device__ void msg_forward(int K, const float *M, const long long *E, double (&a)[msg_ns<KP>()], double *sa,
+                            double *sf, long long *si)
 {
+    constexpr int NS = msg_ns<KP>();
     const int j = threadIdx.x & 63;
-    const int jc = j < KP ? j : 0;
-    si[j] = (j < K && a > 0.0) ? E[j] : LLONG_MIN;
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+        const int js = j + 64 * q;
+        si[js] = (js < K && a[q] > 0.0) ? E[js < KP ? js : 0] : LLONG_MIN;
+    }
     wsync();
     long long emax = LLONG_MIN;
 #pragma unroll
     for (int i = 0; i < KP; ++i) emax = si[i] > emax ? si[i] : emax;
-    double f = 0.0;
-    if (j < K && a > 0.0) {
-        long long sh = E[j] - emax;
-        if (sh < -1100) sh = -1100;
-        f = ldexp(a, (int)sh);
-    }
-    sf[j] = f;
-    wsync();
-    double s = 0.0;
 #pragma unroll
-    for (int i = 0; i < KP; ++i) s += sf[i] * (double)M[i * KP + jc];
-    if (j >= K) s = 0.0;
+    for (int q = 0; q < NS; ++q) {
+        const int js = j + 64 * q;
+        double f = 0.0;
+        if (js < K && a[q] > 0.0) {
+            long long sh = E[js] - emax;
+            if (sh < -1100) sh = -1100;
+            f = ldexp(a[q], (int)sh);
+        }
+        sf[js] = f;
+    }
     wsync();
-    sa[j] = s;
+    double s[NS];
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+        const int js = j + 64 * q, jc = js < KP ? js : 0;
+        double t = 0.0;
+#pragma unroll
+        for (int i = 0; i < KP; ++i) t += sf[i] * (double)M[i * KP + jc];
+        s[q] = js < K ? t : 0.0;
+    }
+    wsync();
+#pragma unroll
+    for (int q = 0; q < NS; ++q) sa[j + 64 * q] = s[q];
     wsync();
     double tot = 0.0;
 #pragma unroll
     for (int i = 0; i < KP; ++i) tot += sa[i];
-    a = (j < K) ? ((tot > 0.0) ? s / tot : (tot == 0.0 ? 0.0 : NAN)) : 0.0;
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+        const int js = j + 64 * q;
+        a[q] = (js < K) ? ((tot > 0.0) ? s[q] / tot : (tot == 0.0 ? 0.0 : NAN)) : 0.0;
+    }
     wsync();
-    sa[j] = a;
+#pragma unroll
+    for (int q = 0; q < NS; ++q) sa[j + 64 * q] = a[q];
     wsync();
 }
 
@@ -180,84 +204,100 @@ __device__ void msg_forward(int K, const float *M, const long long *E, double &a
 // scale.  Lane i < K holds (cm_i, ce_i), mirrored in LDS (sm, se); lanes of
 // padded states hold 0, so their terms drop out of the branch-free loops.
 template <int KP>
-__device__ void msg_backward(int K, const float *Mt, const long long *E, double &cm, long long &ce, double *sm,
-                             long long *se)
+__device__ void msg_backward(int K, const float *Mt, const long long *E, double (&cm)[msg_ns<KP>()],
+                             long long (&ce)[msg_ns<KP>()], double *sm, long long *se)
 {
-    const int i = threadIdx.x & 63;
-    const int ic = i < KP ? i : 0;
-    // loads first (eight states at a time), then branch-free arithmetic
-    long long h = LLONG_MIN;
+    constexpr int NS = msg_ns<KP>();
+    const int j = threadIdx.x & 63;
+    double mres[NS];
+    long long eres[NS];
 #pragma unroll
-    for (int j0 = 0; j0 < KP; j0 += 8) {
-        double smv[8];
-        long long sev[8];
-        float mv[8];
+    for (int q = 0; q < NS; ++q) {
+        const int i = j + 64 * q;
+        const int ic = i < KP ? i : 0;
+        // loads first (eight states at a time), then branch-free arithmetic
+        long long h = LLONG_MIN;
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            smv[u] = sm[j0 + u];
-            sev[u] = se[j0 + u];
-            mv[u] = Mt[(j0 + u) * KP + ic];
+        for (int j0 = 0; j0 < KP; j0 += 8) {
+            double smv[8];
+            long long sev[8];
+            float mv[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                smv[u] = sm[j0 + u];
+                sev[u] = se[j0 + u];
+                mv[u] = Mt[(j0 + u) * KP + ic];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const bool live = (smv[u] > 0.0) & (mv[u] != 0.f) & (sev[u] > h);
+                h = live ? sev[u] : h;
+            }
         }
+        const long long h0 = (h == LLONG_MIN) ? 0 : h;
+        double sum = 0.0;
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const bool live = (smv[u] > 0.0) & (mv[u] != 0.f) & (sev[u] > h);
-            h = live ? sev[u] : h;
+        for (int j0 = 0; j0 < KP; j0 += 8) {
+            double smv[8];
+            long long sev[8];
+            float mv[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                smv[u] = sm[j0 + u];
+                sev[u] = se[j0 + u];
+                mv[u] = Mt[(j0 + u) * KP + ic];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                long long sh = sev[u] - h0;
+                sh = sh < -1100 ? -1100 : (sh > 0 ? 0 : sh);
+                const double term = (double)mv[u] * ldexp(smv[u], (int)sh);
+                sum += ((smv[u] > 0.0) & (mv[u] != 0.f)) ? term : 0.0;
+            }
         }
+        double m = 0.0;
+        long long e = 0;
+        if (i < K && h != LLONG_MIN) {
+            int ex = 0;
+            m = frexp(sum, &ex);
+            e = (m > 0.0) ? E[i] + h + ex : 0;
+        }
+        mres[q] = m;
+        eres[q] = e;
     }
-    const long long h0 = (h == LLONG_MIN) ? 0 : h;
-    double s = 0.0;
-#pragma unroll
-    for (int j0 = 0; j0 < KP; j0 += 8) {
-        double smv[8];
-        long long sev[8];
-        float mv[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            smv[u] = sm[j0 + u];
-            sev[u] = se[j0 + u];
-            mv[u] = Mt[(j0 + u) * KP + ic];
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            long long sh = sev[u] - h0;
-            sh = sh < -1100 ? -1100 : (sh > 0 ? 0 : sh);
-            const double term = (double)mv[u] * ldexp(smv[u], (int)sh);
-            s += ((smv[u] > 0.0) & (mv[u] != 0.f)) ? term : 0.0;
-        }
-    }
-    double m = 0.0;
-    long long e = 0;
-    if (i < K && h != LLONG_MIN) {
-        int ex = 0;
-        m = frexp(s, &ex);
-        e = (m > 0.0) ? E[i] + h + ex : 0;
-    }
-    cm = m;
-    ce = e;
     wsync();
-    sm[i] = m;
-    se[i] = e;
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+        cm[q] = mres[q];
+        ce[q] = eres[q];
+        sm[j + 64 * q] = mres[q];
+        se[j + 64 * q] = eres[q];
+    }
     wsync();
 }
 
-// A product held in registers between its load and its LDS store (up to
-// KP = 64: 16 float4 and one exponent per lane).
+// A product held in registers between its load and its LDS store (KP x KP
+// floats spread over the wavefront as float4, one exponent per state).
+template <int KP>
 struct ProdRegs {
-    float4 m[kMaxKP * kMaxKP / 4 / 64];
-    long long e;
+    static constexpr int N4 = (KP * KP / 4 + 63) / 64;
+    float4 m[N4];
+    long long e[msg_ns<KP>()];
 };
 
-__device__ __forceinline__ void product_load(const float *M, const long long *E, int KP, ProdRegs &r)
+template <int KP>
+__device__ __forceinline__ void product_load(const float *M, const long long *E, ProdRegs<KP> &r)
 {
     const int lane = threadIdx.x & 63;
     const float4 *src = reinterpret_cast<const float4 *>(M);
-    const int n4 = KP * KP / 4;
+    constexpr int n4 = KP * KP / 4;
 #pragma unroll
-    for (int q = 0; q < kMaxKP * kMaxKP / 4 / 64; ++q) {
+    for (int q = 0; q < ProdRegs<KP>::N4; ++q) {
         const int i = lane + 64 * q;
         if (i < n4) r.m[q] = src[i];
     }
-    r.e = lane < KP ? E[lane] : 0;
+#pragma unroll
+    for (int q = 0; q < msg_ns<KP>(); ++q) r.e[q] = lane + 64 * q < KP ? E[lane + 64 * q] : 0;
 }
 
 // State of physical row p of a blocked-path product (the slot-major order of
@@ -273,12 +313,13 @@ __device__ __forceinline__ int prow_state(int KP, int p)
 
 // Into LDS in state order, row-major (transpose = false) or transposed: the
 // products come in the kernels' slot-major order and are reordered here.
-__device__ __forceinline__ void product_store(const ProdRegs &r, int KP, float *lm, long long *le, bool transpose)
+template <int KP>
+__device__ __forceinline__ void product_store(const ProdRegs<KP> &r, float *lm, long long *le, bool transpose)
 {
     const int lane = threadIdx.x & 63;
-    const int n4 = KP * KP / 4;
+    constexpr int n4 = KP * KP / 4;
 #pragma unroll
-    for (int q = 0; q < kMaxKP * kMaxKP / 4 / 64; ++q) {
+    for (int q = 0; q < ProdRegs<KP>::N4; ++q) {
         const int i = lane + 64 * q;
         if (i < n4) {
             const int row = prow_state(KP, (4 * i) / KP), col = (4 * i) % KP;
@@ -290,64 +331,83 @@ __device__ __forceinline__ void product_store(const ProdRegs &r, int KP, float *
             }
         }
     }
-    if (lane < KP) le[prow_state(KP, lane)] = r.e;
+#pragma unroll
+    for (int q = 0; q < msg_ns<KP>(); ++q)
+        if (lane + 64 * q < KP) le[prow_state(KP, lane + 64 * q)] = r.e[q];
     wsync();
 }
 
 template <int KP>
 __global__ __launch_bounds__(128) void k_post_scan_level(ScanLevel s)
 {
-    __shared__ __attribute__((aligned(16))) float lm[2][kMaxKP * kMaxKP];
-    __shared__ long long le[2][kMaxKP];
-    __shared__ double sv[2][64], sf[64];
-    __shared__ long long se[64], si[64];
+    constexpr int NS = msg_ns<KP>();
+    __shared__ __attribute__((aligned(16))) float lm[2][KP * KP];
+    __shared__ long long le[2][KP];
+    __shared__ double sv[2][64 * NS], sf[64 * NS];
+    __shared__ long long se[64 * NS], si[64 * NS];
     const int w = threadIdx.x >> 6, j = threadIdx.x & 63;
     const int K = s.K;
     const int64_t q = blockIdx.x;
     const int64_t c0 = q * s.G, c1 = min(s.n, c0 + s.G);
-    ProdRegs nx;
+    ProdRegs<KP> nx;
     if (w == 0) {
-        double a = 0.0;
-        if (s.pA) {
-            a = (j < K) ? s.pA[q * K + j] : 0.0;
-        } else {
-            a = (j < K) ? s.delta[j] : 0.0;
-            const double tot = wsum_f64(a);
-            a = (j < K && tot > 0.0) ? a / tot : 0.0;
+        double a[NS];
+        double part = 0.0;
+#pragma unroll
+        for (int u = 0; u < NS; ++u) {
+            const int js = j + 64 * u;
+            a[u] = (js < K) ? (s.pA ? s.pA[q * K + js] : s.delta[js]) : 0.0;
+            part += a[u];
         }
-        sv[0][j] = a;
+        if (!s.pA) {
+            const double tot = wsum_f64(part);
+#pragma unroll
+            for (int u = 0; u < NS; ++u) a[u] = (j + 64 * u < K && tot > 0.0) ? a[u] / tot : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < NS; ++u) sv[0][j + 64 * u] = a[u];
         wsync();
-        if (c0 + 1 < c1) product_load(s.M + c0 * KP * KP, s.E + c0 * KP, KP, nx);
+        if (c0 + 1 < c1) product_load<KP>(s.M + c0 * KP * KP, s.E + c0 * KP, nx);
         for (int64_t c = c0; c < c1; ++c) {
-            if (j < K) s.A[c * K + j] = a;
+#pragma unroll
+            for (int u = 0; u < NS; ++u)
+                if (j + 64 * u < K) s.A[c * K + j + 64 * u] = a[u];
             if (c + 1 < c1) {
-                product_store(nx, KP, lm[0], le[0], false);
-                if (c + 2 < c1) product_load(s.M + (c + 1) * KP * KP, s.E + (c + 1) * KP, KP, nx);
+                product_store<KP>(nx, lm[0], le[0], false);
+                if (c + 2 < c1) product_load<KP>(s.M + (c + 1) * KP * KP, s.E + (c + 1) * KP, nx);
                 msg_forward<KP>(K, lm[0], le[0], a, sv[0], sf, si);
             }
         }
     } else {
-        double cm = 0.0;
-        long long ce = 0;
-        if (s.pC) {
-            cm = (j < K) ? s.pC[q * K + j] : 0.0;
-            ce = (j < K) ? s.pCE[q * K + j] : 0;
-        } else {
-            cm = (j < K) ? 0.5 : 0.0;   // c = 1: mantissa 1/2, exponent 1
-            ce = (j < K) ? 1 : 0;
+        double cm[NS];
+        long long ce[NS];
+#pragma unroll
+        for (int u = 0; u < NS; ++u) {
+            const int js = j + 64 * u;
+            if (s.pC) {
+                cm[u] = (js < K) ? s.pC[q * K + js] : 0.0;
+                ce[u] = (js < K) ? s.pCE[q * K + js] : 0;
+            } else {
+                cm[u] = (js < K) ? 0.5 : 0.0;   // c = 1: mantissa 1/2, exponent 1
+                ce[u] = (js < K) ? 1 : 0;
+            }
+            sv[1][js] = cm[u];
+            se[js] = ce[u];
         }
-        sv[1][j] = cm;
-        se[j] = ce;
         wsync();
-        if (c1 - 1 > c0) product_load(s.M + (c1 - 1) * KP * KP, s.E + (c1 - 1) * KP, KP, nx);
+        if (c1 - 1 > c0) product_load<KP>(s.M + (c1 - 1) * KP * KP, s.E + (c1 - 1) * KP, nx);
         for (int64_t c = c1 - 1; c >= c0; --c) {
-            if (j < K) {
-                s.C[c * K + j] = cm;
-                s.CE[c * K + j] = ce;
+#pragma unroll
+            for (int u = 0; u < NS; ++u) {
+                const int js = j + 64 * u;
+                if (js < K) {
+                    s.C[c * K + js] = cm[u];
+                    s.CE[c * K + js] = ce[u];
+                }
             }
             if (c > c0) {
-                product_store(nx, KP, lm[1], le[1], true);
-                if (c - 1 > c0) product_load(s.M + (c - 1) * KP * KP, s.E + (c - 1) * KP, KP, nx);
+                product_store<KP>(nx, lm[1], le[1], true);
+                if (c - 1 > c0) product_load<KP>(s.M + (c - 1) * KP * KP, s.E + (c - 1) * KP, nx);
                 msg_backward<KP>(K, lm[1], le[1], cm, ce, sv[1], se);
             }
         }
@@ -582,6 +642,234 @@ __global__ __launch_bounds__(64 * post_waves<KB>(), KB <= 32 ? 2 : 1) void k_pos
     }
 }
 
+// The local passes for 64 < K <= KB = 80: lane j holds states j and j + 64
+// (the second one for j < KB - 64); Gamma and its transpose are read from
+// LDS instead of registers (two columns per lane would not fit), otherwise
+// the same recursions as k_post_forward / k_post_backward.
+template <int KB>
+__global__ __launch_bounds__(64 * post_waves<KB>()) void k_post_forward_wide(PostDesc d)
+{
+    constexpr int NW = post_waves<KB>(), NS = 2;
+    __shared__ __attribute__((aligned(16))) float gs[KB * KB];
+    __shared__ __attribute__((aligned(16))) float et[NW][KB * kChunk];
+    __shared__ __attribute__((aligned(16))) float sv[NW][64 * NS];
+    load_gamma_lds<KB>(d, gs, nullptr);
+    const int w = threadIdx.x >> 6, j = threadIdx.x & 63;
+    const int64_t b = (int64_t)blockIdx.x * NW + w;
+    if (b >= d.nb || *d.status != 0) return;
+    const int K = d.K;
+    const int64_t t0 = b * d.L, t1 = min(d.T, t0 + d.L);
+    float *E = et[w], *su = sv[w];
+    const Obs obs{d.flag, d.xy, nullptr, kEmisTremor, 0};
+    for (int i = j; i < KB * kChunk; i += 64) E[i] = 0.f;   // rows >= K stay zero
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+        const int js = j + 64 * q;
+        su[js] = js < K ? (float)d.Aseg[b * K + js] : 0.f;
+    }
+    wsync();
+    for (int64_t tc = t0; tc < t1; tc += kChunk) {
+        const int nst = (int)min((int64_t)kChunk, t1 - tc);
+        long long ssum = 0;
+        int bad = 0, sh = 0;
+        stage_emissions<kChunk, false>(K, tc, nst, obs, d.sc, E, ssum, bad, sh);
+        for (int tl = 0; tl < nst; ++tl) {
+            const float s = sum_lds<KB>(su);
+            float a[NS];
+#pragma unroll
+            for (int q = 0; q < NS; ++q) {
+                const int js = j + 64 * q, jc = js < KB ? js : 0;
+                float p4[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int i = 0; i < KB; ++i) p4[i & 3] = fmaf(su[i], gs[i * KB + jc], p4[i & 3]);
+                const float v = (p4[0] + p4[1]) + (p4[2] + p4[3]);
+                a[q] = js < K ? __fdividef(v, s) * E[jc * kChunk + tl] : 0.f;
+                if (js < K) d.gamma[(tc + tl) * K + js] = a[q];
+            }
+            wsync();
+#pragma unroll
+            for (int q = 0; q < NS; ++q) su[j + 64 * q] = a[q];
+            wsync();
+        }
+    }
+}
+
+template <int KB>
+__global__ __launch_bounds__(64 * post_waves<KB>()) void k_post_backward_wide(PostDesc d)
+{
+    constexpr int NW = post_waves<KB>(), NS = 2;
+    __shared__ __attribute__((aligned(16))) float gs[KB * KB], gt[KB * KB];
+    __shared__ __attribute__((aligned(16))) float et[NW][KB * kChunk];   // u rows of a chunk
+    __shared__ __attribute__((aligned(16))) float sv[NW][2][64 * NS];    // r, unnormalised gamma
+    __shared__ double ox[NW][kChunk], oy[NW][kChunk];
+    __shared__ int of[NW][kChunk];
+    load_gamma_lds<KB>(d, gs, gt);
+    const int w = threadIdx.x >> 6, j = threadIdx.x & 63;
+    const int64_t b = (int64_t)blockIdx.x * NW + w;
+    if (b >= d.nb) return;
+    const int K = d.K;
+    const int64_t t0 = b * d.L, t1 = min(d.T, t0 + d.L);
+    float *E = et[w], *sr = sv[w][0], *sg = sv[w][1];
+    if (*d.status != 0) {
+        for (int64_t t = t0; t < t1; ++t)
+#pragma unroll
+            for (int q = 0; q < NS; ++q)
+                if (j + 64 * q < K) d.gamma[t * K + j + 64 * q] = __builtin_nanf("");
+        return;
+    }
+    float xi[NS][KB];
+    float mom[NS][kMoments];
+    double mux[NS], muy[NS];
+    float a_in[NS], g[NS];
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+        const int js = j + 64 * q;
+#pragma unroll
+        for (int i = 0; i < KB; ++i) xi[q][i] = 0.f;
+#pragma unroll
+        for (int m = 0; m < kMoments; ++m) mom[q][m] = 0.f;
+        mux[q] = js < K ? d.mu[2 * js] : 0.0;
+        muy[q] = js < K ? d.mu[2 * js + 1] : 0.0;
+        a_in[q] = js < K ? (float)d.Aseg[b * K + js] : 0.f;
+    }
+    {
+        double mant[NS];
+        long long lv[NS];
+        long long lmax = LLONG_MIN;
+#pragma unroll
+        for (int q = 0; q < NS; ++q) {
+            const int js = j + 64 * q;
+            const double ut = js < K ? (double)d.gamma[(t1 - 1) * K + js] : 0.0;
+            const double cm = js < K ? d.Cseg[b * K + js] : 0.0;
+            const long long ce = js < K ? d.CsegE[b * K + js] : 0;
+            const double prod = ut * cm;
+            int ex = 0;
+            mant[q] = frexp(prod, &ex);
+            lv[q] = (prod > 0.0) ? ce + ex : LLONG_MIN;
+            lmax = lv[q] > lmax ? lv[q] : lmax;
+        }
+        lmax = wmax_i64(lmax);
+        double v[NS], part = 0.0;
+#pragma unroll
+        for (int q = 0; q < NS; ++q) {
+            v[q] = 0.0;
+            if (lv[q] != LLONG_MIN) {
+                long long shf = lv[q] - lmax;
+                if (shf < -1100) shf = -1100;
+                v[q] = ldexp(mant[q], (int)shf);
+            }
+            part += v[q];
+        }
+        const double tot = wsum_f64(part);
+#pragma unroll
+        for (int q = 0; q < NS; ++q) g[q] = (float)(v[q] / tot);
+    }
+    const int64_t nch = (t1 - t0 + kChunk - 1) / kChunk;
+    for (int64_t ci = nch - 1; ci >= 0; --ci) {
+        const int64_t tc = t0 + ci * kChunk;
+        const int nst = (int)min((int64_t)kChunk, t1 - tc);
+        wsync();
+        // E row r = u_{tc+r-1} (row stride KB)
+        for (int q0 = 0; q0 < KB; q0 += 8) {
+            float tmp[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int pos = j + 64 * (q0 + u), r = pos / KB, i = pos % KB;
+                const int64_t t = tc + r - 1;
+                tmp[u] = (r < nst && i < K && t >= t0) ? d.gamma[t * K + i] : 0.f;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int pos = j + 64 * (q0 + u), r = pos / KB;
+                if (r < nst) E[pos] = tmp[u];
+            }
+        }
+        if (tc == t0) {
+#pragma unroll
+            for (int q = 0; q < NS; ++q)
+                if (j + 64 * q < KB) E[j + 64 * q] = a_in[q];   // u_{t0-1}: the segment's entry message
+        }
+        if (j < nst) {
+            const int64_t t = tc + j;
+            const int f = d.flag[t];
+            of[w][j] = f;
+            double x = 0.0, y = 0.0;
+            if (f == 1) {
+                const double2 pp = reinterpret_cast<const double2 *>(d.xy)[t];
+                x = pp.x;
+                y = pp.y;
+            }
+            ox[w][j] = x;
+            oy[w][j] = y;
+        }
+        wsync();
+        for (int tl = nst - 1; tl >= 0; --tl) {
+            const int64_t t = tc + tl;
+            const float *up = E + tl * KB;   // u_{t-1}
+            float r[NS];
+#pragma unroll
+            for (int q = 0; q < NS; ++q) {
+                const int js = j + 64 * q, jc = js < KB ? js : 0;
+                const bool live = js < K;
+                if (live) {
+                    d.gamma[t * K + js] = g[q];
+                    mom[q][0] += g[q];
+                    if (of[w][tl] == 1) {
+                        const float x = (float)(ox[w][tl] - mux[q]), y = (float)(oy[w][tl] - muy[q]);
+                        mom[q][1] += g[q];
+                        mom[q][2] = fmaf(g[q], x, mom[q][2]);
+                        mom[q][3] = fmaf(g[q], y, mom[q][3]);
+                        mom[q][4] = fmaf(g[q] * x, x, mom[q][4]);
+                        mom[q][5] = fmaf(g[q] * x, y, mom[q][5]);
+                        mom[q][6] = fmaf(g[q] * y, y, mom[q][6]);
+                    }
+                }
+                float p4[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int i = 0; i < KB; ++i) p4[i & 3] = fmaf(up[i], gs[i * KB + jc], p4[i & 3]);
+                const float pred = (p4[0] + p4[1]) + (p4[2] + p4[3]);
+                r[q] = (live && pred > 0.f) ? __fdividef(g[q], pred) : 0.f;
+                sr[j + 64 * q] = r[q];
+            }
+            wsync();
+            float gp[NS];
+#pragma unroll
+            for (int q = 0; q < NS; ++q) {
+                const int js = j + 64 * q, jc = js < KB ? js : 0;
+#pragma unroll
+                for (int i = 0; i < KB; ++i) xi[q][i] = fmaf(up[i], r[q], xi[q][i]);
+                float p4[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int i = 0; i < KB; ++i) p4[i & 3] = fmaf(sr[i], gt[i * KB + jc], p4[i & 3]);
+                const float back = (p4[0] + p4[1]) + (p4[2] + p4[3]);
+                gp[q] = js < K ? up[jc] * back : 0.f;
+                sg[j + 64 * q] = gp[q];
+            }
+            wsync();
+            const float tot = sum_lds<KB>(sg);
+#pragma unroll
+            for (int q = 0; q < NS; ++q) {
+                g[q] = __fdividef(gp[q], tot);
+                if (b == 0 && t == 0 && j + 64 * q < K) d.part_pre[j + 64 * q] = g[q];
+            }
+            wsync();
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+        const int js = j + 64 * q;
+        if (js >= K) continue;
+        // xi(i, j) = Gamma_ij sum_t u_{t-1,i} r_t,j
+        float *px = d.part_xi + b * K * K;
+#pragma unroll
+        for (int i = 0; i < KB; ++i)
+            if (i < K) px[i * K + js] = xi[q][i] * gs[i * KB + js];
+        float *pm = d.part_mom + (b * K + js) * kMoments;
+#pragma unroll
+        for (int m = 0; m < kMoments; ++m) pm[m] = mom[q][m];
+    }
+}
+
 // Column sums of a [rows][n] FP32 array in FP64, two stages with a fixed
 // order (deterministic).  Stage 1: block (x, c) sums columns [64x, 64x + 64)
 // over the rows of chunk c (rows c, c + C, c + 2C, ...; 4 wavefronts, then a
@@ -746,8 +1034,39 @@ void launch_local(const PostDesc &d, hipStream_t st)
 {
     constexpr int NW = post_waves<KB>();
     const unsigned grid = (unsigned)((d.nb + NW - 1) / NW);
-    hipLaunchKernelGGL(k_post_forward<KB>, dim3(grid), dim3(64 * NW), 0, st, d);
-    hipLaunchKernelGGL(k_post_backward<KB>, dim3(grid), dim3(64 * NW), 0, st, d);
+    if constexpr (KB <= 64) {
+        hipLaunchKernelGGL(k_post_forward<KB>, dim3(grid), dim3(64 * NW), 0, st, d);
+        hipLaunchKernelGGL(k_post_backward<KB>, dim3(grid), dim3(64 * NW), 0, st, d);
+    } else {
+        hipLaunchKernelGGL(k_post_forward_wide<KB>, dim3(grid), dim3(64 * NW), 0, st, d);
+        hipLaunchKernelGGL(k_post_backward_wide<KB>, dim3(grid), dim3(64 * NW), 0, st, d);
+    }
+}
+
+// LDS of one workgroup (one wavefront) of the posterior plan's segment
+// launch: its region, but at least 1/16 of the CU's 160 KiB, so that at most
+// 16 such workgroups (4 per SIMD) share a CU and the segments spread evenly
+// over the SIMDs (a fifth wavefront on some SIMDs would make them the tail).
+size_t post_seg_lds(const KernelSet &ks)
+{
+    return std::max<size_t>((size_t)region_bytes(ks.KP()), (size_t)(160 * 1024) / 16);
+}
+
+// Segments of the posterior plan: one wavefront (workgroup) each, as many as
+// the GPU holds at once (resident workgroups of the segment launch per CU x
+// CUs), so that every CU gets the same number of segments in one round;
+// kPostSegments if the occupancy cannot be queried.
+int64_t post_segments(const hmm_ctx *ctx, const KernelSet &ks)
+{
+    int per_cu = 0, n_cu = 0;
+    const size_t rb = post_seg_lds(ks);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ks.seg1, 64, rb) != hipSuccess || per_cu < 1 ||
+        hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess ||
+        n_cu < 1) {
+        (void)hipGetLastError();
+        return kPostSegments;
+    }
+    return (int64_t)per_cu * n_cu;
 }
 
 void launch_colsum(const float *in, int64_t rows, int64_t n, double *part, double *out, hipStream_t st)
@@ -765,13 +1084,13 @@ int posterior_impl(hmm_ctx *ctx, int32_t K, const double *delta, const double *G
     if (!ctx || !delta || !Gamma || !p || !mu || !Sigma || !loglik) return HMM_E_INVALID_ARG;
     if (K < 1 || T < 0 || T >= kMaxT || (T > 0 && (!flag || !xy))) return HMM_E_INVALID_ARG;
     if (T > 0 && !xy_aligned(xy)) return HMM_E_INVALID_ARG;
-    if (K > 64) return HMM_E_UNSUPPORTED;
+    if (K > 80) return HMM_E_UNSUPPORTED;
     KernelSet ks;
     if (!select_kernels(HMM_BLOCKED_F32, K, &ks)) return HMM_E_UNSUPPORTED;
     const int KP = ks.KP();
     const int G = group_waves(KP);
-    const int64_t L = ctx->block_len > 0 ? ctx->block_len
-                                         : std::max<int64_t>(32, (T + kPostSegments - 1) / kPostSegments);
+    const int64_t nseg = ctx->block_len > 0 ? 0 : post_segments(ctx, ks);
+    const int64_t L = ctx->block_len > 0 ? ctx->block_len : std::max<int64_t>(32, (T + nseg - 1) / nseg);
     const int64_t nb = T > 0 ? (T + L - 1) / L : 0;
     // one wavefront per segment in the segment and in-segment launches
     if (nb > INT_MAX || !grid_fits(nb + 64, 64)) return HMM_E_UNSUPPORTED;
@@ -830,10 +1149,10 @@ int posterior_impl(hmm_ctx *ctx, int32_t K, const double *delta, const double *G
     sd.L = L;
     sd.K = K;
     sd.pad = 0;
-    const size_t rb = (size_t)region_bytes(KP);
-    if (allow_lds(ks.seg1, rb) != HMM_OK || allow_lds(ks.fold1, rb * G) != HMM_OK) return HMM_E_DEVICE;
+    const size_t rb = (size_t)region_bytes(KP), rb_seg = post_seg_lds(ks);
+    if (allow_lds(ks.seg1, rb_seg) != HMM_OK || allow_lds(ks.fold1, rb * G) != HMM_OK) return HMM_E_DEVICE;
     // segment products (one wavefront per workgroup), group levels, ln L
-    if (nb > 0 && launch_seg(ks.seg1, (unsigned)nb, 1, rb, st, sd, nullptr, nullptr, nb, at<float>(ws, o_m[0]),
+    if (nb > 0 && launch_seg(ks.seg1, (unsigned)nb, 1, rb_seg, st, sd, nullptr, nullptr, nb, at<float>(ws, o_m[0]),
                              at<long long>(ws, o_e[0]), at<long long>(ws, o_s[0])) != hipSuccess)
         return HMM_E_DEVICE;
     for (int l = 1; l < nlev; ++l)
@@ -889,12 +1208,14 @@ int posterior_impl(hmm_ctx *ctx, int32_t K, const double *delta, const double *G
             case 16: hipLaunchKernelGGL(k_post_scan_level<16>, dim3(parents), dim3(128), 0, st, sl); break;
             case 32: hipLaunchKernelGGL(k_post_scan_level<32>, dim3(parents), dim3(128), 0, st, sl); break;
             case 48: hipLaunchKernelGGL(k_post_scan_level<48>, dim3(parents), dim3(128), 0, st, sl); break;
-            default: hipLaunchKernelGGL(k_post_scan_level<64>, dim3(parents), dim3(128), 0, st, sl); break;
+            case 64: hipLaunchKernelGGL(k_post_scan_level<64>, dim3(parents), dim3(128), 0, st, sl); break;
+            default: hipLaunchKernelGGL(k_post_scan_level<80>, dim3(parents), dim3(128), 0, st, sl); break;
             }
         }
         if (K <= 16) launch_local<16>(d, st);
         else if (K <= 32) launch_local<32>(d, st);
-        else launch_local<64>(d, st);
+        else if (K <= 64) launch_local<64>(d, st);
+        else launch_local<80>(d, st);
     }
     double *out_stats = need_stats_ws ? at<double>(ws, o_stats) : stats;
     if (stats_ws) *stats_ws = out_stats;

@@ -416,6 +416,289 @@ __global__ __launch_bounds__(64 * vit_waves<KB>()) void k_vit_local(VitDesc d, c
     }
 }
 
+// ---------------------------------------------------------------------------
+// 64 < K <= 80: the same plan with two wavefronts per segment (block) and
+// thread = column / state: KW = 80 padded states, threads 80..127 hold
+// padding (-inf) columns.  Cross-wave steps synchronise with barriers and
+// take maxima through LDS.
+// ---------------------------------------------------------------------------
+constexpr int kVitWide = 80;       // padded state count of the wide kernels
+constexpr int kVitWideThreads = 128;
+
+// Largest value over the block (two wavefronts); every thread gets it.
+__device__ __forceinline__ float block_max2(float v, float *red)
+{
+    v = wave_max(v);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    const float m = fmaxf(red[0], red[1]);
+    __syncthreads();
+    return m;
+}
+
+// Segment products: thread j computes column j of the KW x KW max-plus matrix;
+// the matrix lives in LDS (two buffers, read one, write the other).  The
+// renormalisation by the step's largest entry mx is folded into the next
+// step (subtracting a constant commutes with the max-plus product), so no
+// pass over the matrix is needed for it; the offset of the stored matrix is
+// the last mx, removed when the product is written out.
+__global__ __launch_bounds__(kVitWideThreads) void k_vit_segment_wide(VitDesc d, float *Vout, double *off)
+{
+    constexpr int KW = kVitWide;
+    __shared__ __attribute__((aligned(16))) float lg[KW * KW];
+    __shared__ __attribute__((aligned(16))) float vb[2][KW * KW];
+    __shared__ __attribute__((aligned(16))) float lam[KW * kVitSegChunk];
+    __shared__ float red[2];
+    __shared__ int badw;
+    load_lg<KW>(d, lg);
+    const int64_t b = blockIdx.x;
+    if (b >= d.nb || *d.status != 0) return;
+    const int K = d.K, j = threadIdx.x, w = threadIdx.x >> 6;
+    const int jc = j < KW ? j : 0;
+    const int64_t t0 = b * d.L, t1 = min(d.T, t0 + d.L);
+    float lgc[KW];
+#pragma unroll
+    for (int k = 0; k < KW; ++k) lgc[k] = lg[k * KW + jc];
+    if (j < KW)
+        for (int i = 0; i < KW; ++i) vb[0][i * KW + j] = (i == j && j < K) ? 0.f : -INFINITY;   // identity
+    if (threadIdx.x == 0) badw = 0;
+    double acc = 0.0;
+    float po = 0.f;   // offset of the stored matrix (its largest entry)
+    int cur = 0;
+    for (int64_t tc = t0; tc < t1; tc += kVitSegChunk) {
+        const int nst = (int)min((int64_t)kVitSegChunk, t1 - tc);
+        __syncthreads();
+        if (w == 0) {
+            const int bad = stage_log_emissions<KW, kVitSegChunk>(d, tc, nst, lam);
+            if (__any(bad) && (threadIdx.x & 63) == 0) badw = 1;
+        }
+        __syncthreads();
+        for (int tl = 0; tl < nst; ++tl) {
+            const float e = (j < K) ? lam[jc * kVitSegChunk + tl] - po : -INFINITY;
+            const float *A = vb[cur];
+            float *B = vb[cur ^ 1];
+            float mx = -INFINITY;
+            for (int i = 0; i < KW; ++i) {
+                const float4 *row = reinterpret_cast<const float4 *>(A + i * KW);
+                float m0 = -INFINITY, m1 = -INFINITY;
+#pragma unroll
+                for (int k4 = 0; k4 < KW / 4; ++k4) {
+                    const float4 v = row[k4];
+                    m0 = fmaxf(m0, v.x + lgc[4 * k4]);
+                    m1 = fmaxf(m1, v.y + lgc[4 * k4 + 1]);
+                    m0 = fmaxf(m0, v.z + lgc[4 * k4 + 2]);
+                    m1 = fmaxf(m1, v.w + lgc[4 * k4 + 3]);
+                }
+                const float v = (i < K) ? fmaxf(m0, m1) + e : -INFINITY;
+                if (j < KW) B[i * KW + j] = v;
+                mx = fmaxf(mx, v);
+            }
+            mx = block_max2(mx, red);   // its barriers also order B's writes before the next step's reads
+            if (mx > -INFINITY) {
+                po = mx;
+                acc += (double)mx;
+            } else {
+                po = 0.f;
+            }
+            cur ^= 1;
+        }
+    }
+    __syncthreads();
+    if (badw && threadIdx.x == 0) atomicOr(d.status, kBadData);
+    float *out = Vout + b * KW * KW;
+    if (j < KW)
+        for (int i = 0; i < KW; ++i) out[i * KW + j] = vb[cur][i * KW + j] - po;
+    if (threadIdx.x == 0) off[b] = acc;
+}
+
+// One fold level: block q multiplies its children left to right (max-plus)
+// with the running product in LDS (two buffers), thread j computing column j;
+// renormalisation folded into the next product as in k_vit_segment_wide.
+__global__ __launch_bounds__(kVitWideThreads) void k_vit_fold_wide(int64_t n, const float *Vin, const double *offin,
+                                                                   float *Vout, double *offout)
+{
+    constexpr int KW = kVitWide;
+    __shared__ __attribute__((aligned(16))) float P[2][KW * KW];
+    __shared__ float red[2];
+    const int j = threadIdx.x, jc = j < KW ? j : 0;
+    const int64_t q = blockIdx.x, c0 = q * kVitG, c1 = min(n, c0 + kVitG);
+    const float *src = Vin + c0 * KW * KW;
+    if (j < KW)
+        for (int i = 0; i < KW; ++i) P[0][i * KW + j] = src[i * KW + j];
+    double acc = offin[c0];
+    float po = 0.f;
+    int cur = 0;
+    for (int64_t c = c0 + 1; c < c1; ++c) {
+        float qc[KW];
+        const float *nxt = Vin + c * KW * KW;
+#pragma unroll
+        for (int k = 0; k < KW; ++k) qc[k] = nxt[k * KW + jc] - po;
+        __syncthreads();
+        const float *A = P[cur];
+        float *B = P[cur ^ 1];
+        float mx = -INFINITY;
+        for (int i = 0; i < KW; ++i) {
+            const float4 *row = reinterpret_cast<const float4 *>(A + i * KW);
+            float m0 = -INFINITY, m1 = -INFINITY;
+#pragma unroll
+            for (int k4 = 0; k4 < KW / 4; ++k4) {
+                const float4 v = row[k4];
+                m0 = fmaxf(m0, v.x + qc[4 * k4]);
+                m1 = fmaxf(m1, v.y + qc[4 * k4 + 1]);
+                m0 = fmaxf(m0, v.z + qc[4 * k4 + 2]);
+                m1 = fmaxf(m1, v.w + qc[4 * k4 + 3]);
+            }
+            const float v = j < KW ? fmaxf(m0, m1) : -INFINITY;
+            if (j < KW) B[i * KW + j] = v;
+            mx = fmaxf(mx, v);
+        }
+        mx = block_max2(mx, red);
+        if (mx > -INFINITY) {
+            po = mx;
+            acc += (double)mx;
+        } else {
+            po = 0.f;
+        }
+        acc += offin[c];
+        cur ^= 1;
+    }
+    __syncthreads();
+    float *out = Vout + q * KW * KW;
+    if (j < KW)
+        for (int i = 0; i < KW; ++i) out[i * KW + j] = P[cur][i * KW + j] - po;
+    if (threadIdx.x == 0) offout[q] = acc;
+}
+
+// Decoding of one level (as k_vit_decode), thread = state over two wavefronts.
+__global__ __launch_bounds__(kVitWideThreads) void k_vit_decode_wide(int K, int64_t n, const float *V,
+                                                                     const double *off, const int32_t *pend,
+                                                                     const int32_t *pfirst, int32_t *cend,
+                                                                     int32_t *first, double *score,
+                                                                     const double *delta, const int *status)
+{
+    constexpr int KW = kVitWide;
+    __shared__ double dv[kVitWideThreads];
+    __shared__ int32_t psi[kVitG][KW];
+    const int lane = threadIdx.x;
+    const int64_t q = blockIdx.x, c0 = q * kVitG, c1 = min(n, c0 + kVitG);
+    const bool top = (pend == nullptr);
+    int s_in = -1;
+    if (!top) s_in = (q == 0) ? *pfirst : pend[q - 1];
+    if (*status != 0) {   // results are discarded; keep every index in range
+        if (lane == 0) {
+            for (int64_t c = c0; c < c1; ++c) cend[c] = 0;
+            if (top) {
+                *first = 0;
+                *score = 0.0;
+            }
+        }
+        return;
+    }
+    double dj;
+    if (top) dj = (lane < K) ? log2(delta[lane]) : -INFINITY;
+    else dj = (lane == s_in) ? 0.0 : -INFINITY;
+    for (int64_t c = c0; c < c1; ++c) {
+        dv[lane] = dj;
+        __syncthreads();
+        const float *M = V + c * KW * KW;
+        double best = -INFINITY;
+        int arg = 0;
+        if (lane < K)
+            for (int i = 0; i < K; ++i) {
+                const double s = dv[i] + (double)M[i * KW + lane];
+                if (s > best) {
+                    best = s;
+                    arg = i;
+                }
+            }
+        if (lane < KW) psi[c - c0][lane] = arg;
+        dj = (lane < K) ? best + off[c] : -INFINITY;
+        __syncthreads();
+    }
+    dv[lane] = dj;
+    __syncthreads();
+    if (lane == 0) {
+        int e;
+        if (top) {
+            double best = -INFINITY;
+            e = 0;
+            for (int i = 0; i < K; ++i)
+                if (dv[i] > best) {
+                    best = dv[i];
+                    e = i;
+                }
+            *score = best;
+        } else {
+            e = pend[q];
+        }
+        for (int64_t c = c1 - 1; c >= c0; --c) {
+            cend[c] = e;
+            e = psi[c - c0][e];
+        }
+        if (top) *first = e;
+    }
+}
+
+// Bottom (as k_vit_local): one block of two wavefronts per segment, thread =
+// state; backpointers psi[t][j] (uint8) in dynamic LDS (L x KW bytes).
+__global__ __launch_bounds__(kVitWideThreads) void k_vit_local_wide(VitDesc d, const int32_t *send,
+                                                                    const int32_t *first, int32_t *path)
+{
+    constexpr int KW = kVitWide;
+    __shared__ __attribute__((aligned(16))) float lg[KW * KW];
+    __shared__ __attribute__((aligned(16))) float dd[kVitWideThreads];
+    __shared__ __attribute__((aligned(16))) float lam[KW * kChunk];
+    __shared__ float red[2];
+    extern __shared__ uint8_t psi[];
+    load_lg<KW>(d, lg);
+    const int64_t b = blockIdx.x;
+    if (b >= d.nb) return;
+    const int64_t t0 = b * d.L, t1 = min(d.T, t0 + d.L);
+    const int lane = threadIdx.x, w = threadIdx.x >> 6;
+    if (*d.status != 0) {
+        for (int64_t t = t0 + lane; t < t1; t += kVitWideThreads) path[t] = -1;
+        return;
+    }
+    const int K = d.K;
+    const int jc = lane < KW ? lane : 0;
+    float lgc[KW];
+#pragma unroll
+    for (int k = 0; k < KW; ++k) lgc[k] = lg[k * KW + jc];
+    const int s_in = (b == 0) ? *first : send[b - 1];
+    dd[lane] = (lane == s_in) ? 0.f : -INFINITY;
+    for (int64_t tc = t0; tc < t1; tc += kChunk) {
+        const int nst = (int)min((int64_t)kChunk, t1 - tc);
+        __syncthreads();
+        if (w == 0) stage_log_emissions<KW>(d, tc, nst, lam);
+        __syncthreads();
+        for (int tl = 0; tl < nst; ++tl) {
+            // states >= K hold -inf in dd and lgc, so the loop runs over all KW
+            float best = -INFINITY;
+            int arg = 0;
+#pragma unroll
+            for (int i = 0; i < KW; ++i) {
+                const float s = dd[i] + lgc[i];
+                if (s > best) {
+                    best = s;
+                    arg = i;
+                }
+            }
+            const float v = (lane < K) ? best + lam[jc * kChunk + tl] : -INFINITY;
+            if (lane < KW) psi[(tc + tl - t0) * KW + lane] = (uint8_t)arg;
+            const float mx = block_max2(v, red);   // also orders the reads of dd before its update
+            dd[lane] = (mx > -INFINITY) ? v - mx : v;
+            __syncthreads();
+        }
+    }
+    if (lane == 0) {
+        int e = send[b];
+        for (int64_t t = t1 - 1; t >= t0; --t) {
+            path[t] = e;
+            e = psi[(t - t0) * KW + e];
+        }
+    }
+}
+
 // Score in natural log; NaN, s_-1 = -1 for invalid parameters or data.
 __global__ void k_vit_finish(const int *status, double *score, int32_t *first)
 {
@@ -441,13 +724,15 @@ const void *segment_kernel_in(int K)
     }
 }
 
-// 33 <= K <= 64: one instance padded to 64 states (entries beyond K stay -inf).
+// 33 <= K <= 64: one instance padded to 64 states (entries beyond K stay -inf);
+// 64 < K <= 80: the two-wavefront kernels.
 template <int KB>
 const void *segment_kernel(int K)
 {
     if constexpr (KB == 16) return segment_kernel_in<16, 1, 16>(K);
     else if constexpr (KB == 32) return segment_kernel_in<32, 17, 32>(K);
-    else return reinterpret_cast<const void *>(&k_vit_segment<64, 64>);
+    else if constexpr (KB == 64) return reinterpret_cast<const void *>(&k_vit_segment<64, 64>);
+    else return reinterpret_cast<const void *>(&k_vit_segment_wide);
 }
 
 template <int KB, int LO, int HI>
@@ -466,8 +751,14 @@ const void *local_kernel(int K)
 {
     if constexpr (KB == 16) return local_kernel_in<16, 1, 16>(K);
     else if constexpr (KB == 32) return local_kernel_in<32, 17, 32>(K);
-    else return reinterpret_cast<const void *>(&k_vit_local<64, 64>);
+    else if constexpr (KB == 64) return reinterpret_cast<const void *>(&k_vit_local<64, 64>);
+    else return reinterpret_cast<const void *>(&k_vit_local_wide);
 }
+
+// Launch shape of the segment and backtracking kernels: segments per block
+// and threads per block (the wide kernels take one segment per 128 threads).
+template <int KB> constexpr int vit_seg_per_block() { return KB == kVitWide ? 1 : vit_waves<KB>(); }
+template <int KB> constexpr int vit_block_threads() { return KB == kVitWide ? kVitWideThreads : 64 * vit_waves<KB>(); }
 
 // Segment length of the Viterbi plan (the same rule as viterbi_impl).
 template <int KB>
@@ -487,12 +778,13 @@ bool viterbi_grid_fits(const hmm_ctx *ctx, int K, int64_t T)
         constexpr int KB = decltype(kb)::value;
         const int64_t L = viterbi_len<KB>(ctx, T);
         const int64_t nb = T > 0 ? (T + L - 1) / L : 0;
-        constexpr int NW = vit_waves<KB>();
-        return grid_fits((nb + NW - 1) / NW, 64 * NW);
+        constexpr int NW = vit_seg_per_block<KB>();
+        return grid_fits((nb + NW - 1) / NW, vit_block_threads<KB>());
     };
     if (K <= 16) return fits(std::integral_constant<int, 16>());
     if (K <= 32) return fits(std::integral_constant<int, 32>());
-    return fits(std::integral_constant<int, 64>());
+    if (K <= 64) return fits(std::integral_constant<int, 64>());
+    return fits(std::integral_constant<int, kVitWide>());
 }
 
 template <int KB>
@@ -546,31 +838,46 @@ int viterbi_impl(hmm_ctx *ctx, int32_t K, const double *delta, const double *Gam
         float *v0 = at<float>(ws, o_v[0]);
         double *f0 = at<double>(ws, o_o[0]);
         void *args[] = {&d, &v0, &f0};
-        constexpr int NW = vit_waves<KB>();
-        if (hipLaunchKernel(seg, dim3((unsigned)((nb + NW - 1) / NW)), dim3(64 * NW), args, 0, st) != hipSuccess)
+        constexpr int NW = vit_seg_per_block<KB>();
+        if (hipLaunchKernel(seg, dim3((unsigned)((nb + NW - 1) / NW)), dim3(vit_block_threads<KB>()), args, 0, st) !=
+            hipSuccess)
             return HMM_E_DEVICE;
-        for (int l = 1; l < nlev; ++l)
-            hipLaunchKernelGGL(k_vit_fold<KB>, dim3((unsigned)cnt[l]), dim3(64), 0, st, cnt[l - 1],
-                               at<float>(ws, o_v[l - 1]), at<double>(ws, o_o[l - 1]), at<float>(ws, o_v[l]),
-                               at<double>(ws, o_o[l]));
+        for (int l = 1; l < nlev; ++l) {
+            if constexpr (KB == kVitWide)
+                hipLaunchKernelGGL(k_vit_fold_wide, dim3((unsigned)cnt[l]), dim3(kVitWideThreads), 0, st, cnt[l - 1],
+                                   at<float>(ws, o_v[l - 1]), at<double>(ws, o_o[l - 1]), at<float>(ws, o_v[l]),
+                                   at<double>(ws, o_o[l]));
+            else
+                hipLaunchKernelGGL(k_vit_fold<KB>, dim3((unsigned)cnt[l]), dim3(64), 0, st, cnt[l - 1],
+                                   at<float>(ws, o_v[l - 1]), at<double>(ws, o_o[l - 1]), at<float>(ws, o_v[l]),
+                                   at<double>(ws, o_o[l]));
+        }
     }
     // top level, then every level down to the segments
-    hipLaunchKernelGGL(k_vit_decode<KB>, dim3(1), dim3(64), 0, st, K, nb > 0 ? cnt[nlev - 1] : 0,
-                       at<float>(ws, o_v[nlev - 1]), at<double>(ws, o_o[nlev - 1]), (const int32_t *)nullptr,
-                       (const int32_t *)nullptr, at<int32_t>(ws, o_e[nlev - 1]), first, score, delta, status);
+    const void *dec = KB == kVitWide ? reinterpret_cast<const void *>(&k_vit_decode_wide)
+                                     : reinterpret_cast<const void *>(&k_vit_decode<KB == kVitWide ? 64 : KB>);
+    const unsigned dec_threads = KB == kVitWide ? kVitWideThreads : 64;
+    auto decode = [&](unsigned grid, int64_t n, const float *V, const double *offs, const int32_t *pend,
+                      const int32_t *pfirst, int32_t *cend) {
+        void *args[] = {&K, &n, &V, &offs, &pend, &pfirst, &cend, &first, &score, (void *)&delta, &status};
+        return hipLaunchKernel(dec, dim3(grid), dim3(dec_threads), args, 0, st) == hipSuccess;
+    };
+    if (!decode(1, nb > 0 ? cnt[nlev - 1] : 0, at<float>(ws, o_v[nlev - 1]), at<double>(ws, o_o[nlev - 1]), nullptr,
+                nullptr, at<int32_t>(ws, o_e[nlev - 1])))
+        return HMM_E_DEVICE;
     for (int l = nlev - 2; l >= 0; --l)
-        hipLaunchKernelGGL(k_vit_decode<KB>, dim3((unsigned)cnt[l + 1]), dim3(64), 0, st, K, cnt[l],
-                           at<float>(ws, o_v[l]), at<double>(ws, o_o[l]), at<int32_t>(ws, o_e[l + 1]),
-                           (const int32_t *)first, at<int32_t>(ws, o_e[l]), first, score, delta, status);
+        if (!decode((unsigned)cnt[l + 1], cnt[l], at<float>(ws, o_v[l]), at<double>(ws, o_o[l]),
+                    at<int32_t>(ws, o_e[l + 1]), first, at<int32_t>(ws, o_e[l])))
+            return HMM_E_DEVICE;
     if (nb > 0) {
         const void *loc = local_kernel<KB>(K);
         if (!loc) return HMM_E_UNSUPPORTED;
         int32_t *e0 = at<int32_t>(ws, o_e[0]);
         void *args[] = {&d, &e0, &first, &path};
-        constexpr int NW = vit_waves<KB>();
+        constexpr int NW = vit_seg_per_block<KB>();
         const size_t psi_bytes = (size_t)NW * L * KB;   // at most 32 KiB (L <= vit_max_len)
-        if (hipLaunchKernel(loc, dim3((unsigned)((nb + NW - 1) / NW)), dim3(64 * NW), args, psi_bytes, st) !=
-            hipSuccess)
+        if (hipLaunchKernel(loc, dim3((unsigned)((nb + NW - 1) / NW)), dim3(vit_block_threads<KB>()), args, psi_bytes,
+                            st) != hipSuccess)
             return HMM_E_DEVICE;
     }
     hipLaunchKernelGGL(k_vit_finish, dim3(1), dim3(64), 0, st, status, score, first);
@@ -588,14 +895,15 @@ int hmm_viterbi(hmm_ctx *ctx, int32_t K, const double *delta, const double *Gamm
     if (!ctx || !delta || !Gamma || !p || !mu || !Sigma || !first || !score) return HMM_E_INVALID_ARG;
     if (K < 1 || T < 0 || T >= kMaxT || (T > 0 && (!flag || !xy || !path))) return HMM_E_INVALID_ARG;
     if (T > 0 && !xy_aligned(xy)) return HMM_E_INVALID_ARG;
-    if (K > 64) return HMM_E_UNSUPPORTED;
+    if (K > kVitWide) return HMM_E_UNSUPPORTED;
     if (!viterbi_grid_fits(ctx, K, T)) return HMM_E_UNSUPPORTED;
     DeviceGuard dg(ctx->device);
     if (!dg.ok) return HMM_E_DEVICE;
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (K <= 16) return viterbi_impl<16>(ctx, K, delta, Gamma, p, mu, Sigma, T, flag, xy, st, path, first, score);
     if (K <= 32) return viterbi_impl<32>(ctx, K, delta, Gamma, p, mu, Sigma, T, flag, xy, st, path, first, score);
-    return viterbi_impl<64>(ctx, K, delta, Gamma, p, mu, Sigma, T, flag, xy, st, path, first, score);
+    if (K <= 64) return viterbi_impl<64>(ctx, K, delta, Gamma, p, mu, Sigma, T, flag, xy, st, path, first, score);
+    return viterbi_impl<kVitWide>(ctx, K, delta, Gamma, p, mu, Sigma, T, flag, xy, st, path, first, score);
 }
 
 }  // extern "C"

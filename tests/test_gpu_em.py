@@ -10,7 +10,7 @@ two such sums are then good to a few 1e-6 relative:
   Sigma               1e-4 relative to sqrt(Sxx Syy)
   ln L                1e-6 relative (the blocked FP32 likelihood's bound).
 Sizes: one to many segments and fold groups, ragged tails, each K padding of
-the local pass (16, 32, 64), and the full K = 25, T = 1e6 workload."""
+the local pass (16, 32, 64, 80), and the full K = 25, T = 1e6 workload."""
 import math
 
 import numpy as np
@@ -66,7 +66,7 @@ def _step(ctx, prm, obs, block_len=0):
 
 
 @pytest.mark.parametrize("K,T,L", [(1, 300, 32), (3, 1000, 32), (3, 5003, 0), (8, 2999, 40), (20, 4000, 33),
-                                   (25, 20000, 0), (33, 3001, 32), (64, 2500, 32)])
+                                   (25, 20000, 0), (33, 3001, 32), (64, 2500, 32), (70, 2500, 32), (80, 3000, 0)])
 def test_em_step_matches_oracle(binding, ctx, K, T, L):
     prm, obs = synth.make(K, T, 200 + K)
     ll0, want = _want(prm, obs)
@@ -138,11 +138,11 @@ def test_em_zero_counts_and_edge_cases(binding, ctx):
 
 
 def test_em_argument_errors(binding, ctx):
-    prm, obs = synth.make(65, 100, 12)
+    prm, obs = synth.make(81, 100, 12)
     f = torch.as_tensor(obs.flag, dtype=torch.uint8, device="cuda").contiguous()
     xy = torch.as_tensor(obs.xy, dtype=torch.float64, device="cuda").contiguous()
     with pytest.raises(binding.HMMError):
-        ctx.em_step(_packed(prm), 65, f, xy)
+        ctx.em_step(_packed(prm), 81, f, xy)
     prm, obs = synth.make(3, 100, 12)
     v = _packed(prm)
     f = torch.as_tensor(obs.flag, dtype=torch.uint8, device="cuda").contiguous()

@@ -9,7 +9,8 @@ Tolerances (FP32 recursions inside segments, FP64 messages and sums):
   gradient           relative 1e-4 of each block's scale (built in FP64 from
                      the expectations above).
 Sizes span one to many segments and groups, ragged tails, every K padding of
-the local pass (16, 32, 64), and the full K = 25, T = 1e6 workload."""
+the local pass (16, 32, 64, and 80 with two states per lane), and the full
+K = 25, T = 1e6 workload."""
 import math
 
 import numpy as np
@@ -46,7 +47,8 @@ def _check(got, want, T, what):
 
 
 @pytest.mark.parametrize("K,T,L", [(1, 200, 32), (3, 1000, 32), (3, 5003, 0), (8, 2999, 40), (20, 4000, 33),
-                                   (25, 20000, 0), (33, 3001, 32), (48, 2000, 64), (64, 2500, 32)])
+                                   (25, 20000, 0), (33, 3001, 32), (48, 2000, 64), (64, 2500, 32),
+                                   (65, 2100, 32), (72, 3001, 0), (80, 2600, 40)])
 def test_posterior_matches_oracle(binding, ctx, K, T, L):
     prm, obs = synth.make(K, T, 100 + K)
     want = oracle.posterior(prm.delta, prm.Gamma, prm.p, prm.mu, prm.Sigma, obs.flag, obs.xy)
@@ -70,7 +72,7 @@ def test_full_size_k25_t1e6(binding, ctx):
     assert np.allclose(got["gamma"].sum(axis=1), 1.0, atol=1e-5)
 
 
-@pytest.mark.parametrize("K,T,L", [(3, 2000, 32), (20, 20000, 0), (25, 100000, 0)])
+@pytest.mark.parametrize("K,T,L", [(3, 2000, 32), (20, 20000, 0), (25, 100000, 0), (80, 6000, 0)])
 def test_gradient_matches_oracle(binding, ctx, K, T, L):
     prm, obs = synth.make(K, T, 200 + K)
     prm.Sigma[:, 1] = 0.2 * np.sqrt(prm.Sigma[:, 0] * prm.Sigma[:, 2])
@@ -133,7 +135,7 @@ def test_identity_transitions_closed_form(binding, ctx):
 
 def test_argument_errors(binding, ctx):
     import ctypes
-    prm, obs = synth.make(65, 100, 12)
+    prm, obs = synth.make(81, 100, 12)
     with pytest.raises(binding.HMMError):
         ctx.posterior(**binding.to_device(prm, obs))
     prm, obs = synth.make(3, 100, 12)

@@ -52,7 +52,7 @@ def _check(binding, ctx, prm, obs, L=0, what=""):
 @pytest.mark.parametrize("K,T,L", [(1, 300, 32), (2, 50, 32), (3, 1000, 32), (3, 5003, 0), (8, 2999, 40),
                                    (16, 4000, 33), (17, 3001, 32), (25, 20000, 0), (25, 20000, 32),
                                    (32, 2500, 32), (5, 1, 0), (33, 2000, 32), (48, 3001, 40),
-                                   (64, 2500, 0)])
+                                   (64, 2500, 0), (65, 2100, 32), (72, 3001, 0), (80, 2600, 40), (80, 700, 0)])
 def test_viterbi_matches_oracle(binding, ctx, K, T, L):
     prm, obs = synth.make(K, T, 300 + K)
     diff = _check(binding, ctx, prm, obs, L, (K, T, L))
