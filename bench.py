@@ -99,15 +99,20 @@ def issued_mfma_flops(K, T, n_blocks):
     nsl = min(MT * RS, -(-K // G))   # slot-major state order: ceil(K / G) live slots
     per_mfma = 2 * S * S * (64 // S)
     per_product = MT * MT * nsl * per_mfma
-    if 16 < K <= 28:
-        # packed: G = 128 // K segments per wavefront share NT = 4 column
-        # tiles; every wavefront runs L steps of NT * NSL MFMAs, then folds its
-        # G products, and 8 wavefronts per workgroup meet in the tree
-        G, NT, waves_per_wg = 128 // K, 4, 8
-        L = -(-T // n_blocks) if n_blocks else 0
+    if 16 < K <= 25:
+        # packed (the default per-K table of a single set): G = 32 NT // K
+        # segments per wavefront share NT column tiles (NT = 2 for K 19..21,
+        # else 4); every wavefront runs ceil(T / n_blocks) steps (balanced
+        # segment lengths) of NT * NSL MFMAs, then folds its G products, and the
+        # wavefronts of a workgroup (16 for NT = 2, else 8) meet in the tree
+        NT = 2 if 19 <= K <= 21 else 4
+        waves_per_wg = 16 if NT == 2 else 8
+        G = 32 * NT // K
+        steps = -(-T // n_blocks) if n_blocks else 0
         waves = -(-n_blocks // G)
         n_wg = -(-waves // waves_per_wg)
-        issued = waves * L * NT * per_product + waves * G * per_product + n_wg * (waves_per_wg - 1) * per_product
+        issued = (waves * steps * NT * per_product + n_blocks * per_product
+                  + n_wg * (waves_per_wg - 1) * per_product)
         return float(issued), {"S": S, "MT": MT, "NSL": nsl, "packed_segments_per_wave": G, "packed_tiles": NT}
     n_wg = -(-n_blocks // W)
     return float(T * per_product + n_wg * (W - 1) * per_product), {"S": S, "MT": MT, "NSL": nsl}

@@ -223,16 +223,23 @@ int hmm_ctx_set_batch_graph(hmm_ctx *ctx, int32_t on);
  * same; only the order in which workgroups take them differs). */
 int hmm_ctx_set_batch_persistent(hmm_ctx *ctx, int32_t on);
 
-/* Column packing of the FP32 blocked path (default on): for 16 < K <= 28 one
- * wavefront advances floor(128 / K) segments at once, their start-state
- * columns side by side in four 32-column MFMA tiles, so that one step costs
- * 4 ceil(K / 2) MFMAs for all of them instead of ceil(K / 2) per segment.
- * Single-set calls pack when the segment length is automatic
- * (hmm_ctx_set_blocking with block_len 0); batched calls pack every class
- * with such a K.  Off: one segment per wavefront as for other K.  The
+/* Column packing of the FP32 blocked path.  A wavefront advances
+ * G = floor(32 NT / K) segments at once, their start-state columns side by
+ * side in NT 32-column MFMA tiles that share the Gamma^T operand, so one step
+ * costs NT ceil(K / 2) MFMAs for all G instead of ceil(K / 2) per segment.
+ * NT = 4 gives floor(128 / K) segments and 8 wavefronts per workgroup (two
+ * per SIMD), NT = 2 three segments and 16 wavefronts (four per SIMD).
+ * mode 1 (default, from measurements): NT = 4 for 17 <= K <= 25, except
+ * NT = 2 for single-set calls with 19 <= K <= 21; other K not packed.
+ * mode 2: NT = 2 for 17 <= K <= 21.  mode 4: NT = 4 for 17 <= K <= 28.
+ * Other K are not packed under modes 2 and 4.  mode 0: no packing.  Packed
+ * segments have balanced lengths, floor or ceil of T over their number.
+ * Single-set calls
+ * pack when the segment length is automatic (hmm_ctx_set_blocking with
+ * block_len 0); batched calls pack every class whose K the mode covers.  The
  * products are the same up to FP32 rounding order.  HMM_E_INVALID_ARG for a
- * null context. */
-int hmm_ctx_set_packing(hmm_ctx *ctx, int32_t on);
+ * null context or another mode. */
+int hmm_ctx_set_packing(hmm_ctx *ctx, int32_t mode);
 
 /* Autotuner of the batched path: for every class of sets that share a
  * kernel, times the class's launches (reps repetitions after one warm-up)

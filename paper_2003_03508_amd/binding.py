@@ -361,9 +361,10 @@ class Context:
         workgroup per job."""
         _check("hmm_ctx_set_batch_persistent", _lib.hmm_ctx_set_batch_persistent(self._h, 1 if on else 0))
 
-    def set_packing(self, on=True):
-        """Several segments per wavefront for FP32 with 16 < K <= 28 (default) or one."""
-        _check("hmm_ctx_set_packing", _lib.hmm_ctx_set_packing(self._h, 1 if on else 0))
+    def set_packing(self, mode=1):
+        """Segments per wavefront of the FP32 path for 16 < K <= 28: 1 (or True) the
+        per-K default, 0 (or False) one segment per wavefront, 2 or 4 column tiles."""
+        _check("hmm_ctx_set_packing", _lib.hmm_ctx_set_packing(self._h, int(mode)))
 
     @staticmethod
     def _desc(K, T, param_off, obs_off):

@@ -83,35 +83,38 @@ bool kernels_small(int algo, int S, int MT, int NSL, KernelSet *ks)
 
 namespace {
 
-template <int K>
+template <int K, int NT>
 void set_packed(KernelSet *ks)
 {
-    constexpr int NT = 4, G = 128 / K, NSL = (K + 1) / 2;
+    constexpr int G = 32 * NT / K, NSL = (K + 1) / 2;
     ks->segP = reinterpret_cast<const void *>(&k_blocked_packed<NT, G, NSL, false>);
     ks->segPB = reinterpret_cast<const void *>(&k_blocked_packed<NT, G, NSL, true>);
     ks->packNT = NT;
     ks->packG = G;
+    ks->packWaves = pack_waves<NT>();
 }
 
-template <int LO, int HI>
+template <int NT, int LO, int HI>
 bool pick_packed(int K, KernelSet *ks)
 {
     if constexpr (LO > HI) {
         return false;
     } else {
         if (K == LO) {
-            set_packed<LO>(ks);
+            set_packed<LO, NT>(ks);
             return true;
         }
-        return pick_packed<LO + 1, HI>(K, ks);
+        return pick_packed<NT, LO + 1, HI>(K, ks);
     }
 }
 
 }  // namespace
 
-bool packed_kernel(int K, KernelSet *ks)
+bool packed_kernel(int K, int NT, KernelSet *ks)
 {
-    return pick_packed<17, 28>(K, ks);
+    if (NT == 4) return pick_packed<4, 17, 28>(K, ks);
+    if (NT == 2) return pick_packed<2, 17, 21>(K, ks);
+    return false;
 }
 
 }  // namespace hmmh
@@ -187,10 +190,10 @@ int loglik_impl(hmm_ctx *ctx, int kind, int32_t K, const double *delta, const do
         return launch_status();
     }
     KernelSet ks;
-    if (!select_kernels(algo, K, &ks)) return HMM_E_UNSUPPORTED;
+    if (!select_kernels(algo, K, &ks, ctx->packing)) return HMM_E_UNSUPPORTED;
     if (!(kind == kEmisTremor ? ks.seg1 : ks.seg1g)) return HMM_E_UNSUPPORTED;   // split: tremor model only
     const int KP = ks.KP();
-    Plan pl = make_plan(ctx, KP, T, (kind == kEmisTremor && ks.segP) ? ks.packG : 0);
+    Plan pl = kind == kEmisTremor ? make_plan(ctx, KP, T, ks.packG, ks.packWaves) : make_plan(ctx, KP, T);
     if (pl.n1 > INT_MAX || !grid_fits(pl.n1, 64 * pl.waves)) return HMM_E_UNSUPPORTED;
     Layout ly = make_layout(KP, pl);
     rc = ensure_ws(ctx, ly.total + sizeof(double) * kFactBlocks);
@@ -260,8 +263,8 @@ size_t loglik_scratch_bytes(int32_t K, int64_t T, int32_t algo, KernelSet *ks, P
         *ly = make_layout(serial_kp(K), Plan());
         return ly->total;
     }
-    if (!select_kernels(algo, K, ks)) return 0;
-    *pl = make_plan(&defaults, ks->KP(), T, ks->segP ? ks->packG : 0);
+    if (!select_kernels(algo, K, ks, defaults.packing)) return 0;
+    *pl = make_plan(&defaults, ks->KP(), T, ks->packG, ks->packWaves);
     if (pl->n1 > INT_MAX || !grid_fits(pl->n1, 64 * pl->waves)) return 0;
     *ly = make_layout(ks->KP(), *pl);
     return ly->total;
@@ -356,9 +359,10 @@ int hmm_blocked_plan(hmm_ctx *ctx, int32_t K, int64_t T, int64_t *block_len, int
 {
     if (!block_len || !n_blocks || !levels || T < 0 || T >= kMaxT || K < 1) return HMM_E_INVALID_ARG;
     KernelSet ks;
-    if (!select_kernels(HMM_BLOCKED_F32, K, &ks)) return HMM_E_UNSUPPORTED;
     const hmm_ctx defaults;
-    Plan pl = make_plan(ctx ? ctx : &defaults, ks.KP(), T, ks.segP ? ks.packG : 0);
+    const hmm_ctx *c = ctx ? ctx : &defaults;
+    if (!select_kernels(HMM_BLOCKED_F32, K, &ks, c->packing)) return HMM_E_UNSUPPORTED;
+    Plan pl = make_plan(c, ks.KP(), T, ks.packG, ks.packWaves);
     *block_len = pl.L;
     *n_blocks = pl.nb;
     *levels = pl.levels;

@@ -48,7 +48,8 @@ struct BatchPlan {
     double *out = nullptr;
     std::map<std::pair<int, int>, int64_t> tuned;
     std::map<std::pair<int, int>, int> tunedW;
-    bool persistent = true, packing = true;
+    bool persistent = true;
+    int packing = 1;
     // device memory
     void *mem = nullptr;
     SetDesc *sets = nullptr;
@@ -124,7 +125,7 @@ int64_t class_L(const hmm_ctx *ctx, const BatchPlan &bp, const BatchClass &c, in
 }
 
 // Most wavefronts per workgroup of a class's segment kernel.
-int max_waves(const BatchClass &c) { return c.G > 1 ? kPackWaves : group_waves(c.KP); }
+int max_waves(const BatchClass &c) { return c.G > 1 ? c.ks.packWaves : group_waves(c.KP); }
 
 // Segment-kernel waves per workgroup of a class: a tuned value (1..the
 // kernel's maximum) wins, else the maximum.
@@ -139,12 +140,11 @@ int class_waves(const hmm_ctx *ctx, const BatchPlan &bp, const BatchClass &c, in
 }
 
 // The kernel that identifies a class: the batched segment kernel (the packed
-// one where there is one for K, FP32 with 16 < K <= 28, and packing is on),
-// or the plain-forward kernel.
-const void *class_key(const KernelSet &ks, bool serial, bool packing)
+// one where the packing mode gives one for K), or the plain-forward kernel.
+const void *class_key(const KernelSet &ks, bool serial)
 {
     if (serial) return ks.seg1;
-    return (packing && ks.segPB) ? ks.segPB : ks.segB;
+    return ks.segPB ? ks.segPB : ks.segB;
 }
 
 // Fill kernel for the queue counters (a kernel, not a memset node, so that
@@ -178,12 +178,12 @@ int build(hmm_ctx *ctx, BatchPlan &bp)
             kp[s] = serial_kp(bp.K[s]);
             kss[s].seg1 = serial_kernel(kp[s]);
         } else {
-            if (!select_kernels(bp.algo, bp.K[s], &kss[s])) return HMM_E_UNSUPPORTED;
+            if (!select_kernels(bp.algo, bp.K[s], &kss[s], bp.packing, true)) return HMM_E_UNSUPPORTED;
             kp[s] = kss[s].KP();
         }
     }
     for (int s = 0; s < n; ++s) {
-        const void *key = class_key(kss[s], serial, bp.packing);
+        const void *key = class_key(kss[s], serial);
         auto it = std::find_if(bp.classes.begin(), bp.classes.end(),
                                [&](const BatchClass &c) { return c.seg == key; });
         if (it == bp.classes.end()) {
@@ -343,7 +343,7 @@ int build(hmm_ctx *ctx, BatchPlan &bp)
     std::vector<PrepJob> hp(n);
     for (int s = 0; s < n; ++s) {
         const BatchClass *c = nullptr;
-        const void *key = class_key(kss[s], serial, bp.packing);
+        const void *key = class_key(kss[s], serial);
         for (const auto &cc : bp.classes)
             if (cc.seg == key) c = &cc;
         SetDesc &d = hs[s];
@@ -616,10 +616,11 @@ int hmm_ctx_set_batch_persistent(hmm_ctx *ctx, int32_t on)
     return HMM_OK;
 }
 
-int hmm_ctx_set_packing(hmm_ctx *ctx, int32_t on)
+int hmm_ctx_set_packing(hmm_ctx *ctx, int32_t mode)
 {
     if (!ctx) return HMM_E_INVALID_ARG;
-    ctx->packing = on != 0;
+    if (mode != 0 && mode != 1 && mode != 2 && mode != 4) return HMM_E_INVALID_ARG;
+    ctx->packing = mode;
     if (ctx->batch) {
         DeviceGuard dg(ctx->device);
         if (hipDeviceSynchronize() != hipSuccess) return HMM_E_DEVICE;
@@ -671,8 +672,8 @@ int hmm_autotune_batched(hmm_ctx *ctx, int32_t n, const int32_t *K, const int64_
             for (int k : ks) {
                 KernelSet kset;
                 int wmax = 1;
-                if (select_kernels(algo, k, &kset))
-                    wmax = (ctx->packing && kset.segPB) ? kPackWaves : group_waves(kset.KP());
+                if (select_kernels(algo, k, &kset, ctx->packing, true))
+                    wmax = kset.segPB ? kset.packWaves : group_waves(kset.KP());
                 ctx->tuned_L[{k, algo}] = L;
                 ctx->tuned_W[{k, algo}] = wdiv ? std::max(1, wmax / wdiv) : wmax;
             }
@@ -705,8 +706,8 @@ int hmm_autotune_batched(hmm_ctx *ctx, int32_t n, const int32_t *K, const int64_
     if (rc == HMM_OK) {
         for (int k : ks) {
             KernelSet kset;
-            if (!select_kernels(algo, k, &kset)) continue;
-            auto it = best.find(class_key(kset, false, ctx->packing));
+            if (!select_kernels(algo, k, &kset, ctx->packing, true)) continue;
+            auto it = best.find(class_key(kset, false));
             ctx->tuned_L[{k, algo}] = (it != best.end()) ? it->second.L : 0;
             ctx->tuned_W[{k, algo}] = (it != best.end()) ? it->second.W : 0;
         }

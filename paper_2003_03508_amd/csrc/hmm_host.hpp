@@ -40,8 +40,9 @@ struct hmm_ctx {
     std::map<std::pair<int, int>, int> tuned_W;
     // batched segment kernels run persistent with an atomic job queue
     bool batch_persistent = true;
-    // FP32 paths with 16 < K <= 28 pack several segments per wavefront
-    bool packing = true;
+    // FP32 paths with 16 < K <= 28: segments per wavefront packed into column
+    // tiles (0 off, 1 the per-K default, 2 or 4 tiles where built)
+    int packing = 1;
 };
 
 namespace hmmh {
@@ -137,18 +138,18 @@ struct Plan {
     bool packed = false;  // k_blocked_packed: G segments per wavefront
 };
 
-inline Plan make_plan(const hmm_ctx *ctx, int KP, int64_t T, int packG = 0)
+inline Plan make_plan(const hmm_ctx *ctx, int KP, int64_t T, int packG = 0, int packWaves = 0)
 {
     Plan p;
     p.W = group_waves(KP);
     p.W2 = group_waves(KP);
     p.waves = p.W;
-    if (packG > 0 && ctx->packing && ctx->block_len == 0) {
-        // packed: kPackWaves wavefronts of packG segments per workgroup, one
+    if (packG > 0 && packWaves > 0 && ctx->block_len == 0) {
+        // packed: packWaves wavefronts of packG segments per workgroup, one
         // workgroup per CU (256), segments of at least 16 observations
         p.packed = true;
-        p.waves = kPackWaves;
-        p.W = kPackWaves * packG;
+        p.waves = packWaves;
+        p.W = packWaves * packG;
         const int64_t target = 256 * (int64_t)p.W;
         p.L = std::max<int64_t>(16, (T + target - 1) / target);
         p.nb = T > 0 ? (T + p.L - 1) / p.L : 0;
@@ -254,7 +255,7 @@ struct KernelSet {
     // column tiles (k_blocked_packed), if there are for this K: single set
     // (segP) and batched (segPB)
     const void *segP = nullptr, *segPB = nullptr;
-    int packNT = 0, packG = 0;
+    int packNT = 0, packG = 0, packWaves = 0;
     int KP() const { return S * MT; }
 };
 
@@ -316,11 +317,33 @@ inline int packed_region_bytes(int NT, int G)
     return 4 * ((et > q ? et : q) + 128);
 }
 
-// k_blocked_packed for 16 < K <= 28 (NT = 4 tiles, G = floor(128 / K)
-// segments); compiled in hmm_api.hip.  False when there is none for K.
-bool packed_kernel(int K, KernelSet *ks);
+// k_blocked_packed with NT tiles (G = floor(32 NT / K) segments) for K;
+// compiled in hmm_api.hip for NT = 4, 16 < K <= 28 and NT = 2, 16 < K <= 21.
+// False (and ks unchanged) when there is none.
+bool packed_kernel(int K, int NT, KernelSet *ks);
 
-inline bool select_kernels(int algo, int K, KernelSet *ks)
+// Column tiles per wavefront of the default packing for K (0: no packing),
+// from measurements of every choice at T = 10^6 (single set) and of 8 and 64
+// sets (batched): four tiles (floor(128 / K) segments, two wavefronts per
+// SIMD) for 17 <= K <= 25, except two tiles (three segments, four wavefronts
+// per SIMD) for a single set with 19 <= K <= 21.  Above 25 four tiles hold
+// only four segments and one segment per wavefront is faster.
+inline int default_pack_tiles(int K, bool batched)
+{
+    if (K < 17 || K > 25) return 0;
+    return (!batched && K >= 19 && K <= 21) ? 2 : 4;
+}
+
+// Sets the packed kernels of ks for the packing mode (see hmm_ctx::packing).
+inline void choose_packing(int mode, int K, bool batched, KernelSet *ks)
+{
+    ks->segP = ks->segPB = nullptr;
+    ks->packNT = ks->packG = ks->packWaves = 0;
+    const int nt = mode == 1 ? default_pack_tiles(K, batched) : ((mode == 2 || mode == 4) ? mode : 0);
+    if (nt > 0) packed_kernel(K, nt, ks);
+}
+
+inline bool select_kernels(int algo, int K, KernelSet *ks, int packing = 1, bool batched = false)
 {
     Shape sh;
     if (!blocked_shape(K, &sh)) return false;
@@ -329,7 +352,7 @@ inline bool select_kernels(int algo, int K, KernelSet *ks)
         sh = Shape{16, (K + 15) / 16};
     const int nsl = live_slots(sh.S, sh.MT, K);
     if (!(kernels_small(algo, sh.S, sh.MT, nsl, ks) || kernels_large(algo, sh.S, sh.MT, nsl, ks))) return false;
-    if (algo == HMM_BLOCKED_F32) packed_kernel(K, ks);
+    if (algo == HMM_BLOCKED_F32) choose_packing(packing, K, batched, ks);
     return true;
 }
 

@@ -858,12 +858,22 @@ __global__ __launch_bounds__(64 * group_waves(S * MT)) void k_blocked(SetDesc on
 // renormalisation touches NT tiles instead of G: at K = 25, 5 segments in 4
 // tiles (125 of 128 columns live) instead of 25 of 32 per segment.  Each
 // column is scaled by the emissions of its own segment at the same relative
-// step (all segments of a plan have length L; the last segment of the
-// sequence may be shorter, and its columns then keep their value once it has
-// ended).  At the end the wavefront multiplies its segments' products in
-// order (each staged through LDS in the layout of the other kernels), and the
-// workgroup tree combines the wavefronts as in k_blocked.
+// step.  The segments have balanced lengths (packed_seg_start): a wavefront's
+// segments differ by at most one step, and the steps past the shortest one
+// (at most one) run a masked variant in which ended columns keep their value.
+// At the end the wavefront multiplies its segments' products in order (each
+// staged through LDS in the layout of the other kernels), and the workgroup
+// tree combines the wavefronts as in k_blocked.
 // ---------------------------------------------------------------------------
+// Segments of a packed launch: the set's nb = ceil(T / L) segments with
+// balanced lengths, q + 1 for the first T mod nb and q = floor(T / nb) for the
+// rest (q <= L), so that the segments of a wavefront differ in length by at
+// most one observation and only their last step can be masked.
+__host__ __device__ inline int64_t packed_seg_start(int64_t b, int64_t q, int64_t r)
+{
+    return b * q + (b < r ? b : r);
+}
+
 template <int G>
 __host__ __device__ constexpr int pack_chunk()
 {
@@ -879,7 +889,15 @@ __host__ __device__ constexpr int pack_region_floats()
     return (et > q ? et : q) + 64 * 2;   // + per-lane shift sums (int64)
 }
 
-constexpr int kPackWaves = 8;   // wavefronts per workgroup (two per SIMD)
+// Wavefronts per workgroup: with NT = 4 tiles a wavefront needs the whole
+// register file of two wavefronts per SIMD (8 per CU); with NT = 2 it fits
+// in half of it, and 16 wavefronts (four per SIMD) hide each other's
+// latencies.
+template <int NT>
+__host__ __device__ constexpr int pack_waves()
+{
+    return NT <= 2 ? 16 : 8;
+}
 
 // One workgroup job: segments [job.seg0, job.seg0 + job.nseg) of the set, G
 // per wavefront in order, product to slot job.out.
@@ -902,6 +920,9 @@ __device__ __forceinline__ void packed_job(const SetDesc &d, const WgJob &job, f
     long long *lsum = reinterpret_cast<long long *>(base + (region - 128));   // per-lane shift sums
     const int64_t b0 = job.seg0 + (int64_t)w * G;                        // first segment of this wavefront
     const int64_t nb = job.seg0 + job.nseg;                              // end of the job's segments
+    // balanced segment lengths over the set's ceil(T / L) segments
+    const int64_t nbs = L > 0 ? (T + L - 1) / L : 0;
+    const int64_t q = nbs > 0 ? T / nbs : 0, qr = nbs > 0 ? T % nbs : 0;
 
     // the columns of this lane: segment and start state per tile
     int segn[NT], stn[NT];
@@ -914,7 +935,7 @@ __device__ __forceinline__ void packed_job(const SetDesc &d, const WgJob &job, f
         stn[n] = col % K;
         const int64_t b = b0 + segn[n];
         liven[n] = segn[n] < G && b < nb;
-        lenn[n] = liven[n] ? min(L, T - b * L) : 0;
+        lenn[n] = liven[n] ? q + (b < qr ? 1 : 0) : 0;
         if (!liven[n]) segn[n] = 0;
     }
     // A = Gamma^T in the slot-major order (as k_blocked)
@@ -937,22 +958,19 @@ __device__ __forceinline__ void packed_job(const SetDesc &d, const WgJob &job, f
     const int sl = lane / CH, tl0 = lane % CH;
     const int64_t bl = b0 + sl;
     const bool stager = sl < G && bl < nb;
-    const int64_t t0l = bl * L, t1l = stager ? min(T, t0l + L) : 0;
-    // do all live segments of the wavefront run the full L steps?
-    bool full = true;
+    const int64_t t0l = stager ? packed_seg_start(bl, q, qr) : 0;
+    const int64_t t1l = stager ? t0l + q + (bl < qr ? 1 : 0) : 0;
+    // steps of the longest and of the shortest live segment of the wavefront
+    int64_t steps = 0, lmin = INT64_MAX;
 #pragma unroll
-    for (int n = 0; n < NT; ++n) full &= (!liven[n] || lenn[n] == L);
-    full = __all(full);
-    const int64_t Lw = [&] {
-        int64_t m = 0;
-#pragma unroll
-        for (int n = 0; n < NT; ++n) m = lenn[n] > m ? lenn[n] : m;
-        return m;
-    }();
-    int64_t steps = Lw;
+    for (int n = 0; n < NT; ++n) {
+        steps = lenn[n] > steps ? lenn[n] : steps;
+        if (liven[n]) lmin = lenn[n] < lmin ? lenn[n] : lmin;
+    }
     for (int o = 32; o > 0; o >>= 1) {
-        const int64_t y = __shfl_xor(steps, o);
+        const int64_t y = __shfl_xor(steps, o), z = __shfl_xor(lmin, o);
         steps = y > steps ? y : steps;
+        lmin = z < lmin ? z : lmin;
     }
     for (int64_t tc = 0; tc < steps; tc += CH) {
         const int nst = (int)min((int64_t)CH, steps - tc);
@@ -1027,7 +1045,7 @@ __device__ __forceinline__ void packed_job(const SetDesc &d, const WgJob &job, f
                 }
             }
         };
-        if (full) steps_of(std::integral_constant<bool, false>());
+        if (tc + nst <= lmin) steps_of(std::integral_constant<bool, false>());
         else steps_of(std::integral_constant<bool, true>());
         wave_sync_lds();
     }
@@ -1072,7 +1090,7 @@ __device__ __forceinline__ void packed_job(const SetDesc &d, const WgJob &job, f
 // Single set (BATCH false): workgroup q takes segments [q W, q W + W), W =
 // G per wavefront.  Batched: jobs from the table (persistent with a queue).
 template <int NT, int G, int NSL, bool BATCH>
-__global__ __launch_bounds__(64 * kPackWaves) void k_blocked_packed(SetDesc one, const SetDesc *__restrict__ sets,
+__global__ __launch_bounds__(64 * pack_waves<NT>()) void k_blocked_packed(SetDesc one, const SetDesc *__restrict__ sets,
                                                                     const WgJob *__restrict__ jobs, int64_t nb,
                                                                     int *queue, float *__restrict__ Mout,
                                                                     long long *__restrict__ Eout,

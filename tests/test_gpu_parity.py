@@ -104,28 +104,52 @@ def test_blocked_matches_oracle_all_tile_shapes(binding, ctx, K):
                      f"blocked K={K} T={T} L={L} G={G}")
 
 
-@pytest.mark.parametrize("K", [17, 18, 21, 22, 25, 26, 28])
-def test_blocked_several_segments_per_wavefront(binding, ctx, K):
-    """16 < K <= 28 in the default plan packs floor(128 / K) segments into one
-    wavefront's four column tiles.  Lengths: none, one observation, fewer
-    observations than one wavefront's segments, the 16-observation minimum
-    segment with a ragged last segment and a partly filled last workgroup, and
-    a plan with L > 16 whose last segment is short (masked steps)."""
-    G = 128 // K
-    W = 8 * G
-    for T, seed in [(0, 1), (1, 2), (G * 16 - 5, 3), (W * 16 * 3 + 7, 4), (256 * W * 16 + 1234, 5)]:
-        prm, obs = synth.make(K, T, seed=200 + 10 * K + seed)
-        plan = ctx.plan(K, T)
-        if T == 256 * W * 16 + 1234:
-            assert plan["block_len"] > 16 and plan["n_blocks"] * plan["block_len"] > T
-        assert_close(gpu(binding, ctx, prm, obs, "blocked_f32"), ref(prm, obs), f"packed K={K} T={T}")
-    # invalid observations in a packed segment other than the wavefront's first -> NaN
-    prm, obs = synth.make(K, W * 16 * 3 + 7, seed=200 + 10 * K)
-    for i, (f, xy) in enumerate([(3, (0.0, 0.0)), (1, (np.nan, 1.0))]):
-        fl, xyv = obs.flag.copy(), obs.xy.copy()
-        t = 16 * (G - 1) + 5 + i
-        fl[t], xyv[t] = f, xy
-        assert math.isnan(gpu(binding, ctx, prm, synth.Observations(fl, xyv), "blocked_f32")), (K, f)
+def pack_tiles(K, mode):
+    """Column tiles per wavefront of the single-set packed FP32 kernel for a
+    packing mode (0: none): mode 1 is the default table (4 tiles for K 17..25
+    but 2 for K 19..21), 2 and 4 force that many tiles where built (K <= 21 /
+    K <= 28)."""
+    if mode == 1:
+        return 0 if not 16 < K <= 25 else (2 if 19 <= K <= 21 else 4)
+    if mode == 2:
+        return 2 if 16 < K <= 21 else 0
+    if mode == 4:
+        return 4 if 16 < K <= 28 else 0
+    return 0
+
+
+@pytest.mark.parametrize("K,mode", [(17, 2), (19, 2), (21, 2), (17, 4), (18, 4), (21, 4), (22, 4), (25, 4),
+                                    (26, 4), (28, 4), (20, 1), (25, 1)])
+def test_blocked_several_segments_per_wavefront(binding, K, mode):
+    """16 < K <= 28: G = floor(32 NT / K) segments share a wavefront's NT
+    column tiles.  Lengths: none, one observation, fewer observations than
+    one wavefront's segments, the 16-observation minimum segment with a ragged
+    last segment and a partly filled last workgroup, and a plan with L > 16
+    whose last segment is short (masked steps); invalid observations in a
+    segment other than the wavefront's first give NaN."""
+    NT = pack_tiles(K, mode)
+    assert NT > 0
+    G = 32 * NT // K
+    W = (16 if NT == 2 else 8) * G
+    c = binding.Context(0)
+    c.set_packing(mode)
+    try:
+        for T, seed in [(0, 1), (1, 2), (G * 16 - 5, 3), (W * 16 * 3 + 7, 4), (256 * W * 16 + 1234, 5)]:
+            prm, obs = synth.make(K, T, seed=200 + 10 * K + seed)
+            plan = c.plan(K, T)
+            if T == W * 16 * 3 + 7:
+                assert plan["block_len"] == 16   # the packed plan applies
+            if T == 256 * W * 16 + 1234:
+                assert plan["block_len"] > 16 and plan["n_blocks"] * plan["block_len"] > T
+            assert_close(gpu(binding, c, prm, obs, "blocked_f32"), ref(prm, obs), f"packed K={K} NT={NT} T={T}")
+        prm, obs = synth.make(K, W * 16 * 3 + 7, seed=200 + 10 * K)
+        for i, (f, xy) in enumerate([(3, (0.0, 0.0)), (1, (np.nan, 1.0))]):
+            fl, xyv = obs.flag.copy(), obs.xy.copy()
+            t = 16 * (G - 1) + 5 + i
+            fl[t], xyv[t] = f, xy
+            assert math.isnan(gpu(binding, c, prm, synth.Observations(fl, xyv), "blocked_f32")), (K, f)
+    finally:
+        c.close()
 
 
 def test_blocked_config0_k3_t1e4(binding, ctx):
@@ -481,23 +505,26 @@ def test_autotune_batched_waves(binding, ctx):
 
 
 def test_packing_switch_single_and_batched(binding, ctx):
-    """Packed (several segments per wavefront) and unpacked FP32 paths for
-    16 < K <= 28, single set and batched: both within the tolerance of the
-    oracle.  K = 25 and 26 share a k_blocked instantiation but not a packed
-    one (5 vs 4 segments per wavefront): separate batch classes."""
-    specs = [(17, 9_000), (20, 31_000), (25, 12_345), (26, 12_346), (28, 7_000), (20, 1), (25, 0), (29, 5_000)]
+    """Every packing mode (none, default table, two tiles, four tiles) for
+    16 < K <= 28 and neighbours, single set and batched: within the tolerance
+    of the oracle.  K = 25 and 26 share a k_blocked instantiation but not a
+    packed one: separate batch classes under mode 4."""
+    specs = [(17, 9_000), (20, 31_000), (21, 4_000), (25, 12_345), (26, 12_346), (28, 7_000), (20, 1), (25, 0),
+             (29, 5_000), (16, 3_000)]
     sets = [synth.make(K, T, seed=1000 + i) for i, (K, T) in enumerate(specs)]
     want = [ref(prm, obs) for prm, obs in sets]
     packed = synth.pack(sets)
     d = binding.batch_to_device(packed)
     c2 = binding.Context(0)
     try:
-        for on in (True, False, True):
-            c2.set_packing(on)
+        with pytest.raises(binding.HMMError):
+            c2.set_packing(3)
+        for mode in (1, 0, 2, 4, 1):
+            c2.set_packing(mode)
             out = c2.loglik_batched(**d).cpu().numpy()
             for i, (prm, obs) in enumerate(sets):
-                assert_close(float(out[i]), want[i], f"batched K={prm.K} T={obs.T} packing={on}")
+                assert_close(float(out[i]), want[i], f"batched K={prm.K} T={obs.T} packing={mode}")
                 got = float(c2.loglik(**binding.to_device(prm, obs)).item())
-                assert_close(got, want[i], f"single K={prm.K} T={obs.T} packing={on}")
+                assert_close(got, want[i], f"single K={prm.K} T={obs.T} packing={mode}")
     finally:
         c2.close()
