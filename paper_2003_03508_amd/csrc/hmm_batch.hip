@@ -127,14 +127,16 @@ int64_t class_L(const hmm_ctx *ctx, const BatchPlan &bp, const BatchClass &c, in
 // Most wavefronts per workgroup of a class's segment kernel.
 int max_waves(const BatchClass &c) { return c.G > 1 ? c.ks.packWaves : group_waves(c.KP); }
 
-// Segment-kernel waves per workgroup of a class: a tuned value (1..the
-// kernel's maximum) wins, else the maximum.
+// Segment-kernel waves per workgroup of a class: a tuned value wins (w > 0:
+// w waves, at most the kernel's maximum; w < 0: the maximum divided by -w,
+// the autotuner's candidates), else the maximum.
 int class_waves(const hmm_ctx *ctx, const BatchPlan &bp, const BatchClass &c, int algo)
 {
     const int wmax = max_waves(c);
     for (int s : c.sets) {
         auto it = ctx->tuned_W.find({bp.K[s], algo});
-        if (it != ctx->tuned_W.end() && it->second > 0) return std::min(it->second, wmax);
+        if (it == ctx->tuned_W.end() || it->second == 0) continue;
+        return it->second > 0 ? std::min(it->second, wmax) : std::max(1, wmax / -it->second);
     }
     return wmax;
 }
@@ -181,6 +183,20 @@ int build(hmm_ctx *ctx, BatchPlan &bp)
             if (!select_kernels(bp.algo, bp.K[s], &kss[s], bp.packing, true)) return HMM_E_UNSUPPORTED;
             kp[s] = kss[s].KP();
         }
+    }
+    // packed kernels only for the K whose sets give at least one workgroup
+    // per CU at the shortest segments (a few short sequences fill the chip
+    // better with one segment per wavefront)
+    if (!serial) {
+        std::map<const void *, int64_t> jobs_min;   // packed kernel -> jobs at kMinL
+        for (int s = 0; s < n; ++s) {
+            if (!kss[s].segPB) continue;
+            const int64_t W = (int64_t)kss[s].packWaves * kss[s].packG;
+            const int64_t nb = (bp.T[s] + kMinL - 1) / kMinL;
+            jobs_min[kss[s].segPB] += (nb + W - 1) / W;
+        }
+        for (int s = 0; s < n; ++s)
+            if (kss[s].segPB && jobs_min[kss[s].segPB] < 256) choose_packing(0, bp.K[s], true, &kss[s]);
     }
     for (int s = 0; s < n; ++s) {
         const void *key = class_key(kss[s], serial);
@@ -667,15 +683,12 @@ int hmm_autotune_batched(hmm_ctx *ctx, int32_t n, const int32_t *K, const int64_
         int W;
     };
     std::map<const void *, Best> best;  // class segment kernel -> fastest (ms, L, waves)
+    std::map<int, const void *> kseg;   // K -> its class's segment kernel
     for (int wdiv : candW) {
         for (int64_t L : candL) {
             for (int k : ks) {
-                KernelSet kset;
-                int wmax = 1;
-                if (select_kernels(algo, k, &kset, ctx->packing, true))
-                    wmax = kset.segPB ? kset.packWaves : group_waves(kset.KP());
                 ctx->tuned_L[{k, algo}] = L;
-                ctx->tuned_W[{k, algo}] = wdiv ? std::max(1, wmax / wdiv) : wmax;
+                ctx->tuned_W[{k, algo}] = wdiv ? -wdiv : 0;
             }
             BatchPlan *bp = nullptr;
             rc = get_plan(ctx, n, K, T, param_off, params, obs_off, flag, xy, algo, out, &bp);
@@ -697,6 +710,7 @@ int hmm_autotune_batched(hmm_ctx *ctx, int32_t n, const int32_t *K, const int64_
                 const double avg = tot / reps;
                 auto it = best.find(c.seg);
                 if (it == best.end() || avg < it->second.ms) best[c.seg] = Best{avg, L, c.waves};
+                for (int s : c.sets) kseg[bp->K[s]] = c.seg;
             }
             if (rc != HMM_OK) break;
         }
@@ -705,9 +719,8 @@ int hmm_autotune_batched(hmm_ctx *ctx, int32_t n, const int32_t *K, const int64_
     // record the winner for every K of each class
     if (rc == HMM_OK) {
         for (int k : ks) {
-            KernelSet kset;
-            if (!select_kernels(algo, k, &kset, ctx->packing, true)) continue;
-            auto it = best.find(class_key(kset, false));
+            auto ks_it = kseg.find(k);
+            auto it = ks_it != kseg.end() ? best.find(ks_it->second) : best.end();
             ctx->tuned_L[{k, algo}] = (it != best.end()) ? it->second.L : 0;
             ctx->tuned_W[{k, algo}] = (it != best.end()) ? it->second.W : 0;
         }

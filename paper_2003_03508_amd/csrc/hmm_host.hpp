@@ -144,13 +144,16 @@ inline Plan make_plan(const hmm_ctx *ctx, int KP, int64_t T, int packG = 0, int 
     p.W = group_waves(KP);
     p.W2 = group_waves(KP);
     p.waves = p.W;
-    if (packG > 0 && packWaves > 0 && ctx->block_len == 0) {
-        // packed: packWaves wavefronts of packG segments per workgroup, one
-        // workgroup per CU (256), segments of at least 16 observations
+    // packed: packWaves wavefronts of packG segments per workgroup, one
+    // workgroup per CU (256), segments of at least 16 observations; only when
+    // that fills every CU (a shorter sequence is cut finer with one segment
+    // per wavefront)
+    const int64_t packW = (int64_t)packWaves * packG;
+    if (packW > 0 && ctx->block_len == 0 && T >= 16 * 256 * packW) {
         p.packed = true;
         p.waves = packWaves;
-        p.W = packWaves * packG;
-        const int64_t target = 256 * (int64_t)p.W;
+        p.W = (int)packW;
+        const int64_t target = 256 * packW;
         p.L = std::max<int64_t>(16, (T + target - 1) / target);
         p.nb = T > 0 ? (T + p.L - 1) / p.L : 0;
         p.n1 = (p.nb + p.W - 1) / p.W;
@@ -313,8 +316,7 @@ bool kernels_large(int algo, int S, int MT, int NSL, KernelSet *ks);
 inline int packed_region_bytes(int NT, int G)
 {
     (void)NT;
-    const int ch = ((64 / G) / 4) * 4, et = G * 32 * ch, q = Region<32>::floats;
-    return 4 * ((et > q ? et : q) + 128);
+    return 4 * pack_region_floats_of(G);
 }
 
 // k_blocked_packed with NT tiles (G = floor(32 NT / K) segments) for K;

@@ -874,19 +874,31 @@ __host__ __device__ inline int64_t packed_seg_start(int64_t b, int64_t q, int64_
     return b * q + (b < r ? b : r);
 }
 
+// Observations per segment per staging pass (one lane each, G * CH <= 64),
+// and the LDS floats of one wavefront: the staged emissions [G][32][CH] or
+// the product staging of the final combination, whichever is larger, then
+// the per-lane shift sums (int64).
+__host__ __device__ constexpr int pack_chunk_of(int G)
+{
+    return 64 / G;
+}
+
+__host__ __device__ constexpr int pack_region_floats_of(int G)
+{
+    return (G * 32 * pack_chunk_of(G) > Region<32>::floats ? G * 32 * pack_chunk_of(G) : Region<32>::floats) +
+           64 * 2;
+}
+
 template <int G>
 __host__ __device__ constexpr int pack_chunk()
 {
-    // observations per segment per staging pass: G * CH <= 64 lanes, CH a
-    // multiple of 4 (float4 reads of four steps)
-    return ((64 / G) / 4) * 4;
+    return pack_chunk_of(G);
 }
 
 template <int NT, int G>
 __host__ __device__ constexpr int pack_region_floats()
 {
-    constexpr int et = G * 32 * pack_chunk<G>(), q = Region<32>::floats;
-    return (et > q ? et : q) + 64 * 2;   // + per-lane shift sums (int64)
+    return pack_region_floats_of(G);
 }
 
 // Wavefronts per workgroup: with NT = 4 tiles a wavefront needs the whole

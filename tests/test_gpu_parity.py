@@ -122,11 +122,12 @@ def pack_tiles(K, mode):
                                     (26, 4), (28, 4), (20, 1), (25, 1)])
 def test_blocked_several_segments_per_wavefront(binding, K, mode):
     """16 < K <= 28: G = floor(32 NT / K) segments share a wavefront's NT
-    column tiles.  Lengths: none, one observation, fewer observations than
-    one wavefront's segments, the 16-observation minimum segment with a ragged
-    last segment and a partly filled last workgroup, and a plan with L > 16
-    whose last segment is short (masked steps); invalid observations in a
-    segment other than the wavefront's first give NaN."""
+    column tiles.  Single set (packed once the sequence fills every CU at
+    16-step segments): balanced lengths with a masked last step, invalid
+    observations in a segment other than the wavefront's first.  Batched:
+    300 short sets (none, one observation, fewer observations than one
+    wavefront's segments, a partly filled last workgroup), packed because
+    together they fill the chip."""
     NT = pack_tiles(K, mode)
     assert NT > 0
     G = 32 * NT // K
@@ -134,20 +135,25 @@ def test_blocked_several_segments_per_wavefront(binding, K, mode):
     c = binding.Context(0)
     c.set_packing(mode)
     try:
-        for T, seed in [(0, 1), (1, 2), (G * 16 - 5, 3), (W * 16 * 3 + 7, 4), (256 * W * 16 + 1234, 5)]:
+        for T, seed in [(256 * W * 16 + 1234, 5), (256 * W * 16 * 3 + 7, 6)]:
             prm, obs = synth.make(K, T, seed=200 + 10 * K + seed)
             plan = c.plan(K, T)
-            if T == W * 16 * 3 + 7:
-                assert plan["block_len"] == 16   # the packed plan applies
-            if T == 256 * W * 16 + 1234:
-                assert plan["block_len"] > 16 and plan["n_blocks"] * plan["block_len"] > T
+            assert plan["block_len"] == -(-T // (256 * W))   # the packed plan applies
+            assert plan["n_blocks"] * plan["block_len"] > T    # unequal lengths: masked last step
             assert_close(gpu(binding, c, prm, obs, "blocked_f32"), ref(prm, obs), f"packed K={K} NT={NT} T={T}")
-        prm, obs = synth.make(K, W * 16 * 3 + 7, seed=200 + 10 * K)
+        # below 16 * 256 * W observations one segment per wavefront fills the chip better
+        assert c.plan(K, 16 * 256 * W - 1)["block_len"] == max(32, -(-(16 * 256 * W - 1) // 4096))
+        prm, obs = synth.make(K, 256 * W * 16 + 1234, seed=200 + 10 * K)
         for i, (f, xy) in enumerate([(3, (0.0, 0.0)), (1, (np.nan, 1.0))]):
             fl, xyv = obs.flag.copy(), obs.xy.copy()
-            t = 16 * (G - 1) + 5 + i
+            t = 17 * (G - 1) + 5 + i
             fl[t], xyv[t] = f, xy
             assert math.isnan(gpu(binding, c, prm, synth.Observations(fl, xyv), "blocked_f32")), (K, f)
+        Ts = [1, G * 16 - 5, W * 16 + 7, 3 * W * 16 + 5, 0] * 60
+        sets = [synth.make(K, T, seed=5000 + i) for i, T in enumerate(Ts)]
+        out = c.loglik_batched(**binding.batch_to_device(synth.pack(sets))).cpu().numpy()
+        for i, (prm, obs) in enumerate(sets):
+            assert_close(float(out[i]), ref(prm, obs), f"batched packed K={K} NT={NT} set {i} T={obs.T}")
     finally:
         c.close()
 
