@@ -1004,22 +1004,41 @@ __device__ __forceinline__ void packed_job(const SetDesc &d, const WgJob &job, f
                 }
             }
             const bool tremor = (f == 1);
-            double m = -INFINITY;
-            for (int k = 0; k < K; ++k) m = fmax(m, state_log2_emission(d.sc[k], tremor, x, y));
-            int sh = 0;
-            if (m > -1.0e9 && m < 1.0e9) sh = (int)floor(m) - kEmisBias;
-            if (live) ssum += sh;
-            if (sl < G) {
-                float *row = Et + sl * (KP * CH) + tl0;
-                for (int k = 0; k < K; ++k) {
-                    const double r = state_log2_emission(d.sc[k], tremor, x, y) - (double)sh;
-                    float e = 0.f;
-                    if (live && r > -160.0) {
-                        const double nn = floor(r);
-                        e = __builtin_amdgcn_ldexpf(exp2f((float)(r - nn)), (int)nn);
-                    }
-                    row[k * CH] = e;
+            float *row = Et + (sl < G ? sl : 0) * (KP * CH) + tl0;
+            auto store = [&](int k, double lam, int sh) {
+                const double r = lam - (double)sh;
+                float e = 0.f;
+                if (live && r > -160.0) {
+                    const double nn = floor(r);
+                    e = __builtin_amdgcn_ldexpf(exp2f((float)(r - nn)), (int)nn);
                 }
+                row[k * CH] = e;
+            };
+            auto shift_of = [](double m) { return (m > -1.0e9 && m < 1.0e9) ? (int)floor(m) - kEmisBias : 0; };
+            if constexpr (NT >= 4) {
+                // the accumulators are free while staging: keep log2 e of the
+                // K <= 2 NSL states in registers, one FP64 evaluation each
+                double lam[2 * NSL];
+                double m = -INFINITY;
+#pragma unroll
+                for (int k = 0; k < 2 * NSL; ++k) {
+                    lam[k] = k < K ? state_log2_emission(d.sc[k], tremor, x, y) : -INFINITY;
+                    m = fmax(m, lam[k]);
+                }
+                const int sh = shift_of(m);
+                if (live) ssum += sh;
+                if (sl < G) {
+#pragma unroll
+                    for (int k = 0; k < 2 * NSL; ++k)
+                        if (k < K) store(k, lam[k], sh);
+                }
+            } else {
+                double m = -INFINITY;
+                for (int k = 0; k < K; ++k) m = fmax(m, state_log2_emission(d.sc[k], tremor, x, y));
+                const int sh = shift_of(m);
+                if (live) ssum += sh;
+                if (sl < G)
+                    for (int k = 0; k < K; ++k) store(k, state_log2_emission(d.sc[k], tremor, x, y), sh);
             }
             wave_sync_lds();
         }
