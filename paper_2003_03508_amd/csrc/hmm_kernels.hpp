@@ -1018,6 +1018,8 @@ __device__ __forceinline__ void packed_job(const SetDesc &d, const WgJob &job, f
             if constexpr (NT >= 4) {
                 // the accumulators are free while staging: keep log2 e of the
                 // K <= 2 NSL states in registers, one FP64 evaluation each
+                // (with two tiles the register file is half as large, and the
+                // same caching spilled and was slower)
                 double lam[2 * NSL];
                 double m = -INFINITY;
 #pragma unroll
