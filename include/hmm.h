@@ -234,11 +234,14 @@ int hmm_ctx_set_batch_persistent(hmm_ctx *ctx, int32_t on);
  * mode 2: NT = 2 for 17 <= K <= 21.  mode 4: NT = 4 for 17 <= K <= 28.
  * Other K are not packed under modes 2 and 4.  mode 0: no packing.  Packed
  * segments have balanced lengths, floor or ceil of T over their number.
- * Single-set calls
- * pack when the segment length is automatic (hmm_ctx_set_blocking with
- * block_len 0); batched calls pack every class whose K the mode covers.  The
- * products are the same up to FP32 rounding order.  HMM_E_INVALID_ARG for a
- * null context or another mode. */
+ * A single-set call packs when the segment length is automatic
+ * (hmm_ctx_set_blocking with block_len 0) and T >= 16 * 256 * W, W = G times
+ * the wavefronts per workgroup (the packed plan then gives every CU a
+ * workgroup of segments of at least 16 observations); a batched call packs the
+ * sets of a K the mode covers when together they give at least 256 such
+ * workgroups.  Otherwise one segment per wavefront, which fills the chip
+ * better.  The products are the same up to FP32 rounding order.
+ * HMM_E_INVALID_ARG for a null context or another mode. */
 int hmm_ctx_set_packing(hmm_ctx *ctx, int32_t mode);
 
 /* Autotuner of the batched path: for every class of sets that share a
