@@ -99,16 +99,16 @@ def issued_mfma_flops(K, T, n_blocks):
     nsl = min(MT * RS, -(-K // G))   # slot-major state order: ceil(K / G) live slots
     per_mfma = 2 * S * S * (64 // S)
     per_product = MT * MT * nsl * per_mfma
-    NT = 2 if 19 <= K <= 21 else 4
+    NT = {19: 5, 20: 5, 22: 5, 21: 2}.get(K, 4)
     waves_per_wg = 16 if NT == 2 else 8
     G = 32 * NT // K
     if 16 < K <= 25 and T >= 16 * 256 * waves_per_wg * G:
         # packed (the default per-K table of a single set, for a sequence that
         # fills every CU at 16-step segments): G = 32 NT // K segments per
-        # wavefront share NT column tiles (NT = 2 for K 19..21, else 4); every
-        # wavefront runs ceil(T / n_blocks) steps (balanced segment lengths) of
-        # NT * NSL MFMAs, then folds its G products, and the wavefronts of a
-        # workgroup (16 for NT = 2, else 8) meet in the tree
+        # wavefront share NT column tiles (5 for K 19, 20, 22, 2 for K 21,
+        # else 4); every wavefront runs ceil(T / n_blocks) steps (balanced
+        # segment lengths) of NT * NSL MFMAs, then folds its G products, and the
+        # wavefronts of a workgroup (16 for NT = 2, else 8) meet in the tree
         steps = -(-T // n_blocks) if n_blocks else 0
         waves = -(-n_blocks // G)
         n_wg = -(-waves // waves_per_wg)

@@ -227,12 +227,15 @@ int hmm_ctx_set_batch_persistent(hmm_ctx *ctx, int32_t on);
  * G = floor(32 NT / K) segments at once, their start-state columns side by
  * side in NT 32-column MFMA tiles that share the Gamma^T operand, so one step
  * costs NT ceil(K / 2) MFMAs for all G instead of ceil(K / 2) per segment.
- * NT = 4 gives floor(128 / K) segments and 8 wavefronts per workgroup (two
- * per SIMD), NT = 2 three segments and 16 wavefronts (four per SIMD).
- * mode 1 (default, from measurements): NT = 4 for 17 <= K <= 25, except
- * NT = 2 for single-set calls with 19 <= K <= 21; other K not packed.
+ * NT = 4 or 5 gives floor(32 NT / K) segments and 8 wavefronts per workgroup
+ * (two per SIMD), NT = 2 three segments and 16 wavefronts (four per SIMD).
+ * mode 1 (default, from measurements): NT = 5 for K = 19, 20, 22 (and 17 in
+ * batched calls), NT = 2 for single-set calls with K = 21, NT = 4 for the
+ * other 17 <= K <= 25; other K not packed.
  * mode 2: NT = 2 for 17 <= K <= 21.  mode 4: NT = 4 for 17 <= K <= 28.
- * Other K are not packed under modes 2 and 4.  mode 0: no packing.  Packed
+ * mode 5: NT = 5 (8 wavefronts per workgroup) for K in {17, 19, 20, 22},
+ * where five tiles hold more live columns than four.  Other K are not packed
+ * under modes 2, 4 and 5.  mode 0: no packing.  Packed
  * segments have balanced lengths, floor or ceil of T over their number.
  * A single-set call packs when the segment length is automatic
  * (hmm_ctx_set_blocking with block_len 0) and T >= 16 * 256 * W, W = G times

@@ -363,7 +363,7 @@ class Context:
 
     def set_packing(self, mode=1):
         """Segments per wavefront of the FP32 path for 16 < K <= 28: 1 (or True) the
-        per-K default, 0 (or False) one segment per wavefront, 2 or 4 column tiles."""
+        per-K default, 0 (or False) one segment per wavefront, 2, 4 or 5 column tiles."""
         _check("hmm_ctx_set_packing", _lib.hmm_ctx_set_packing(self._h, int(mode)))
 
     @staticmethod

@@ -114,6 +114,16 @@ bool packed_kernel(int K, int NT, KernelSet *ks)
 {
     if (NT == 4) return pick_packed<4, 17, 28>(K, ks);
     if (NT == 2) return pick_packed<2, 17, 21>(K, ks);
+    if (NT == 5) {
+        // five tiles only where they hold more live columns than four
+        switch (K) {
+        case 17: set_packed<17, 5>(ks); return true;
+        case 19: set_packed<19, 5>(ks); return true;
+        case 20: set_packed<20, 5>(ks); return true;
+        case 22: set_packed<22, 5>(ks); return true;
+        default: return false;
+        }
+    }
     return false;
 }
 

@@ -635,7 +635,7 @@ int hmm_ctx_set_batch_persistent(hmm_ctx *ctx, int32_t on)
 int hmm_ctx_set_packing(hmm_ctx *ctx, int32_t mode)
 {
     if (!ctx) return HMM_E_INVALID_ARG;
-    if (mode != 0 && mode != 1 && mode != 2 && mode != 4) return HMM_E_INVALID_ARG;
+    if (mode != 0 && mode != 1 && mode != 2 && mode != 4 && mode != 5) return HMM_E_INVALID_ARG;
     ctx->packing = mode;
     if (ctx->batch) {
         DeviceGuard dg(ctx->device);

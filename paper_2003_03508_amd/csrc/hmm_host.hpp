@@ -320,20 +320,30 @@ inline int packed_region_bytes(int NT, int G)
 }
 
 // k_blocked_packed with NT tiles (G = floor(32 NT / K) segments) for K;
-// compiled in hmm_api.hip for NT = 4, 16 < K <= 28 and NT = 2, 16 < K <= 21.
-// False (and ks unchanged) when there is none.
+// compiled in hmm_api.hip for NT = 4, 16 < K <= 28, NT = 2, 16 < K <= 21 and
+// NT = 5, K in {17, 19, 20, 22}.  False (and ks unchanged) when there is none.
 bool packed_kernel(int K, int NT, KernelSet *ks);
 
 // Column tiles per wavefront of the default packing for K (0: no packing),
 // from measurements of every choice at T = 10^6 (single set) and of 8 and 64
-// sets (batched): four tiles (floor(128 / K) segments, two wavefronts per
-// SIMD) for 17 <= K <= 25, except two tiles (three segments, four wavefronts
-// per SIMD) for a single set with 19 <= K <= 21.  Above 25 four tiles hold
-// only four segments and one segment per wavefront is faster.
+// sets (batched).  Five tiles where they hold more live columns than four
+// (K = 19, 20, 22, and K = 17 batched), two tiles for a single set at K = 21,
+// four tiles for the other 17 <= K <= 25.  Above 25 four tiles hold only four
+// segments and one segment per wavefront is faster.
 inline int default_pack_tiles(int K, bool batched)
 {
-    if (K < 17 || K > 25) return 0;
-    return (!batched && K >= 19 && K <= 21) ? 2 : 4;
+    switch (K) {
+    case 17: return batched ? 5 : 4;
+    case 19:
+    case 20:
+    case 22: return 5;
+    case 21: return batched ? 4 : 2;
+    case 18:
+    case 23:
+    case 24:
+    case 25: return 4;
+    default: return 0;
+    }
 }
 
 // Sets the packed kernels of ks for the packing mode (see hmm_ctx::packing).
@@ -341,7 +351,7 @@ inline void choose_packing(int mode, int K, bool batched, KernelSet *ks)
 {
     ks->segP = ks->segPB = nullptr;
     ks->packNT = ks->packG = ks->packWaves = 0;
-    const int nt = mode == 1 ? default_pack_tiles(K, batched) : ((mode == 2 || mode == 4) ? mode : 0);
+    const int nt = mode == 1 ? default_pack_tiles(K, batched) : ((mode == 2 || mode == 4 || mode == 5) ? mode : 0);
     if (nt > 0) packed_kernel(K, nt, ks);
 }
 

@@ -106,20 +106,22 @@ def test_blocked_matches_oracle_all_tile_shapes(binding, ctx, K):
 
 def pack_tiles(K, mode):
     """Column tiles per wavefront of the single-set packed FP32 kernel for a
-    packing mode (0: none): mode 1 is the default table (4 tiles for K 17..25
-    but 2 for K 19..21), 2 and 4 force that many tiles where built (K <= 21 /
-    K <= 28)."""
+    packing mode (0: none): mode 1 is the default table (5 tiles for K 19, 20
+    and 22, 2 for K 21, 4 for the other K 17..25), 2, 4 and 5 force that many
+    tiles where built (K <= 21 / K <= 28 / K in 17, 19, 20, 22)."""
     if mode == 1:
-        return 0 if not 16 < K <= 25 else (2 if 19 <= K <= 21 else 4)
+        return {19: 5, 20: 5, 22: 5, 21: 2}.get(K, 4 if 16 < K <= 25 else 0)
     if mode == 2:
         return 2 if 16 < K <= 21 else 0
     if mode == 4:
         return 4 if 16 < K <= 28 else 0
+    if mode == 5:
+        return 5 if K in (17, 19, 20, 22) else 0
     return 0
 
 
 @pytest.mark.parametrize("K,mode", [(17, 2), (19, 2), (21, 2), (17, 4), (18, 4), (21, 4), (22, 4), (25, 4),
-                                    (26, 4), (28, 4), (20, 1), (25, 1)])
+                                    (26, 4), (28, 4), (17, 5), (20, 5), (22, 5), (20, 1), (25, 1)])
 def test_blocked_several_segments_per_wavefront(binding, K, mode):
     """16 < K <= 28: G = floor(32 NT / K) segments share a wavefront's NT
     column tiles.  Single set (packed once the sequence fills every CU at
@@ -525,7 +527,7 @@ def test_packing_switch_single_and_batched(binding, ctx):
     try:
         with pytest.raises(binding.HMMError):
             c2.set_packing(3)
-        for mode in (1, 0, 2, 4, 1):
+        for mode in (1, 0, 2, 4, 5, 1):
             c2.set_packing(mode)
             out = c2.loglik_batched(**d).cpu().numpy()
             for i, (prm, obs) in enumerate(sets):
