@@ -41,7 +41,7 @@ struct hmm_ctx {
     // batched segment kernels run persistent with an atomic job queue
     bool batch_persistent = true;
     // FP32 paths with 16 < K <= 28: segments per wavefront packed into column
-    // tiles (0 off, 1 the per-K default, 2 or 4 tiles where built)
+    // tiles (0 off, 1 the per-K default, 2, 4 or 5 tiles where built)
     int packing = 1;
 };
 
