@@ -154,7 +154,7 @@ def main():
                          "a counter profile of this command holds a copy of known size")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for {args.gpus}); this build has no "
+        print(f"bench.py measures one GPU only (asked for {args.gpus}); the library has no "
               "multi-GPU path.", file=sys.stderr)
         sys.exit(2)
 

@@ -72,7 +72,7 @@ extern "C" {
 typedef enum {
     HMM_OK = 0,
     HMM_E_INVALID_ARG = -1,  /* null pointer, K/T/n out of range, bad option      */
-    HMM_E_UNSUPPORTED = -2,  /* valid request this build does not implement      */
+    HMM_E_UNSUPPORTED = -2,  /* valid request the library does not implement     */
     HMM_E_DEVICE = -3,       /* a HIP call failed (launch, allocation of scratch) */
     HMM_E_NOMEM = -4         /* scratch memory could not be allocated            */
 } hmm_status;
