@@ -71,6 +71,16 @@ __device__ __forceinline__ void load_lg(const VitDesc &d, float *lg)
     __syncthreads();
 }
 
+// Column j of log2 Gamma (KB entries, -inf outside K) straight into
+// registers: the segment kernels keep it for the whole segment, so staging
+// the matrix through LDS would only cost occupancy.
+template <int KB>
+__device__ __forceinline__ void load_lg_column(const VitDesc &d, int j, float (&lgc)[KB])
+{
+#pragma unroll
+    for (int k = 0; k < KB; ++k) lgc[k] = (k < d.K && j < d.K) ? (float)log2(d.Gamma[k * d.K + j]) : -INFINITY;
+}
+
 // log2 e_t,j of one chunk of CH <= 64 steps into lam[j * CH + tl] (FP64 per
 // observation, rounded once to FP32); lane = step.  -inf for states >= K.
 // Returns 1 on a lane whose observation is invalid (a flag other than 0/1,
@@ -149,18 +159,15 @@ template <int KB, int KK>
 __global__ __launch_bounds__(64 * vit_waves<KB>()) void k_vit_segment(VitDesc d, float *Vout, double *off)
 {
     constexpr int NW = vit_waves<KB>(), R = vit_rows<KB>(), RS = 64 / KB;
-    __shared__ __attribute__((aligned(16))) float lg[KB * KB];
     __shared__ __attribute__((aligned(16))) float vb[NW][KB * KB];
     __shared__ __attribute__((aligned(16))) float lam[NW][KB * kVitSegChunk];
-    load_lg<KB>(d, lg);
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t b = (int64_t)blockIdx.x * NW + w;
     if (b >= d.nb || *d.status != 0) return;
     const int64_t t0 = b * d.L, t1 = min(d.T, t0 + d.L);
     const int j = lane % KB, ib = lane / KB;
     float lgc[KB];
-#pragma unroll
-    for (int k = 0; k < KB; ++k) lgc[k] = lg[k * KB + j];
+    load_lg_column<KB>(d, j, lgc);
     float V[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) V[r] = (ib + RS * r == j && j < KK) ? 0.f : -INFINITY;   // max-plus identity
@@ -424,6 +431,10 @@ __global__ __launch_bounds__(64 * vit_waves<KB>()) void k_vit_local(VitDesc d, c
 // ---------------------------------------------------------------------------
 constexpr int kVitWide = 80;       // padded state count of the wide kernels
 constexpr int kVitWideThreads = 128;
+// Steps per emission chunk of the wide segment kernel: its two product
+// buffers take 51 KB of LDS, and a 6-step chunk keeps the block under a third
+// of the CU's 160 KB, so three blocks (six wavefronts) share a CU.
+constexpr int kVitWideChunk = 6;
 
 // Largest value over the block (two wavefronts); every thread gets it.
 __device__ __forceinline__ float block_max2(float v, float *red)
@@ -444,37 +455,34 @@ __device__ __forceinline__ float block_max2(float v, float *red)
 // the last mx, removed when the product is written out.
 __global__ __launch_bounds__(kVitWideThreads) void k_vit_segment_wide(VitDesc d, float *Vout, double *off)
 {
-    constexpr int KW = kVitWide;
-    __shared__ __attribute__((aligned(16))) float lg[KW * KW];
+    constexpr int KW = kVitWide, CH = kVitWideChunk;
     __shared__ __attribute__((aligned(16))) float vb[2][KW * KW];
-    __shared__ __attribute__((aligned(16))) float lam[KW * kVitSegChunk];
+    __shared__ __attribute__((aligned(16))) float lam[KW * CH];
     __shared__ float red[2];
     __shared__ int badw;
-    load_lg<KW>(d, lg);
     const int64_t b = blockIdx.x;
     if (b >= d.nb || *d.status != 0) return;
     const int K = d.K, j = threadIdx.x, w = threadIdx.x >> 6;
     const int jc = j < KW ? j : 0;
     const int64_t t0 = b * d.L, t1 = min(d.T, t0 + d.L);
     float lgc[KW];
-#pragma unroll
-    for (int k = 0; k < KW; ++k) lgc[k] = lg[k * KW + jc];
+    load_lg_column<KW>(d, j, lgc);   // -inf for the padding threads j >= KW
     if (j < KW)
         for (int i = 0; i < KW; ++i) vb[0][i * KW + j] = (i == j && j < K) ? 0.f : -INFINITY;   // identity
     if (threadIdx.x == 0) badw = 0;
     double acc = 0.0;
     float po = 0.f;   // offset of the stored matrix (its largest entry)
     int cur = 0;
-    for (int64_t tc = t0; tc < t1; tc += kVitSegChunk) {
-        const int nst = (int)min((int64_t)kVitSegChunk, t1 - tc);
+    for (int64_t tc = t0; tc < t1; tc += CH) {
+        const int nst = (int)min((int64_t)CH, t1 - tc);
         __syncthreads();
         if (w == 0) {
-            const int bad = stage_log_emissions<KW, kVitSegChunk>(d, tc, nst, lam);
+            const int bad = stage_log_emissions<KW, CH>(d, tc, nst, lam);
             if (__any(bad) && (threadIdx.x & 63) == 0) badw = 1;
         }
         __syncthreads();
         for (int tl = 0; tl < nst; ++tl) {
-            const float e = (j < K) ? lam[jc * kVitSegChunk + tl] - po : -INFINITY;
+            const float e = (j < K) ? lam[jc * CH + tl] - po : -INFINITY;
             const float *A = vb[cur];
             float *B = vb[cur ^ 1];
             float mx = -INFINITY;
