@@ -435,6 +435,7 @@ constexpr int kVitWideThreads = 128;
 // buffers take 51 KB of LDS, and a 6-step chunk keeps the block under a third
 // of the CU's 160 KB, so three blocks (six wavefronts) share a CU.
 constexpr int kVitWideChunk = 6;
+constexpr int kVitWideSegThreads = 192;   // segment kernel: 160 threads = (column, half of the rows)
 
 // Largest value over the block (two wavefronts); every thread gets it.
 __device__ __forceinline__ float block_max2(float v, float *red)
@@ -447,29 +448,45 @@ __device__ __forceinline__ float block_max2(float v, float *red)
     return m;
 }
 
-// Segment products: thread j computes column j of the KW x KW max-plus matrix;
+// Largest value over the block (blockDim.x / 64 wavefronts, at most four);
+// every thread gets it.
+__device__ __forceinline__ float block_max_waves(float v, float *red)
+{
+    v = wave_max(v);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    float m = red[0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = fmaxf(m, red[w]);
+    __syncthreads();
+    return m;
+}
+
+// Segment products: thread t < 2 KW computes column j = t % KW of half h =
+// t / KW of the rows (row i of the next matrix depends only on row i of the
+// current one), so 160 of the block's 192 threads work instead of 80 of 128;
 // the matrix lives in LDS (two buffers, read one, write the other).  The
 // renormalisation by the step's largest entry mx is folded into the next
 // step (subtracting a constant commutes with the max-plus product), so no
 // pass over the matrix is needed for it; the offset of the stored matrix is
 // the last mx, removed when the product is written out.
-__global__ __launch_bounds__(kVitWideThreads) void k_vit_segment_wide(VitDesc d, float *Vout, double *off)
+__global__ __launch_bounds__(kVitWideSegThreads) void k_vit_segment_wide(VitDesc d, float *Vout, double *off)
 {
-    constexpr int KW = kVitWide, CH = kVitWideChunk;
+    constexpr int KW = kVitWide, CH = kVitWideChunk, HR = KW / 2;
     __shared__ __attribute__((aligned(16))) float vb[2][KW * KW];
     __shared__ __attribute__((aligned(16))) float lam[KW * CH];
-    __shared__ float red[2];
+    __shared__ float red[kVitWideSegThreads / 64];
     __shared__ int badw;
     const int64_t b = blockIdx.x;
     if (b >= d.nb || *d.status != 0) return;
-    const int K = d.K, j = threadIdx.x, w = threadIdx.x >> 6;
-    const int jc = j < KW ? j : 0;
+    const int K = d.K, t = threadIdx.x, w = t >> 6;
+    const bool live = t < 2 * KW;
+    const int j = live ? t % KW : KW, i0 = live ? (t / KW) * HR : 0;
     const int64_t t0 = b * d.L, t1 = min(d.T, t0 + d.L);
     float lgc[KW];
-    load_lg_column<KW>(d, j, lgc);   // -inf for the padding threads j >= KW
-    if (j < KW)
-        for (int i = 0; i < KW; ++i) vb[0][i * KW + j] = (i == j && j < K) ? 0.f : -INFINITY;   // identity
-    if (threadIdx.x == 0) badw = 0;
+    load_lg_column<KW>(d, j, lgc);   // -inf for the idle threads (j = KW)
+    if (live)
+        for (int r = 0; r < HR; ++r) vb[0][(i0 + r) * KW + j] = (i0 + r == j && j < K) ? 0.f : -INFINITY;   // identity
+    if (t == 0) badw = 0;
     double acc = 0.0;
     float po = 0.f;   // offset of the stored matrix (its largest entry)
     int cur = 0;
@@ -478,30 +495,33 @@ __global__ __launch_bounds__(kVitWideThreads) void k_vit_segment_wide(VitDesc d,
         __syncthreads();
         if (w == 0) {
             const int bad = stage_log_emissions<KW, CH>(d, tc, nst, lam);
-            if (__any(bad) && (threadIdx.x & 63) == 0) badw = 1;
+            if (__any(bad) && (t & 63) == 0) badw = 1;
         }
         __syncthreads();
         for (int tl = 0; tl < nst; ++tl) {
-            const float e = (j < K) ? lam[jc * CH + tl] - po : -INFINITY;
             const float *A = vb[cur];
             float *B = vb[cur ^ 1];
             float mx = -INFINITY;
-            for (int i = 0; i < KW; ++i) {
-                const float4 *row = reinterpret_cast<const float4 *>(A + i * KW);
-                float m0 = -INFINITY, m1 = -INFINITY;
+            if (live) {
+                const float e = (j < K) ? lam[j * CH + tl] - po : -INFINITY;
+                for (int r = 0; r < HR; ++r) {
+                    const int i = i0 + r;
+                    const float4 *row = reinterpret_cast<const float4 *>(A + i * KW);
+                    float m0 = -INFINITY, m1 = -INFINITY;
 #pragma unroll
-                for (int k4 = 0; k4 < KW / 4; ++k4) {
-                    const float4 v = row[k4];
-                    m0 = fmaxf(m0, v.x + lgc[4 * k4]);
-                    m1 = fmaxf(m1, v.y + lgc[4 * k4 + 1]);
-                    m0 = fmaxf(m0, v.z + lgc[4 * k4 + 2]);
-                    m1 = fmaxf(m1, v.w + lgc[4 * k4 + 3]);
+                    for (int k4 = 0; k4 < KW / 4; ++k4) {
+                        const float4 v = row[k4];
+                        m0 = fmaxf(m0, v.x + lgc[4 * k4]);
+                        m1 = fmaxf(m1, v.y + lgc[4 * k4 + 1]);
+                        m0 = fmaxf(m0, v.z + lgc[4 * k4 + 2]);
+                        m1 = fmaxf(m1, v.w + lgc[4 * k4 + 3]);
+                    }
+                    const float v = (i < K) ? fmaxf(m0, m1) + e : -INFINITY;
+                    B[i * KW + j] = v;
+                    mx = fmaxf(mx, v);
                 }
-                const float v = (i < K) ? fmaxf(m0, m1) + e : -INFINITY;
-                if (j < KW) B[i * KW + j] = v;
-                mx = fmaxf(mx, v);
             }
-            mx = block_max2(mx, red);   // its barriers also order B's writes before the next step's reads
+            mx = block_max_waves(mx, red);   // its barriers also order B's writes before the next step's reads
             if (mx > -INFINITY) {
                 po = mx;
                 acc += (double)mx;
@@ -512,11 +532,11 @@ __global__ __launch_bounds__(kVitWideThreads) void k_vit_segment_wide(VitDesc d,
         }
     }
     __syncthreads();
-    if (badw && threadIdx.x == 0) atomicOr(d.status, kBadData);
+    if (badw && t == 0) atomicOr(d.status, kBadData);
     float *out = Vout + b * KW * KW;
-    if (j < KW)
-        for (int i = 0; i < KW; ++i) out[i * KW + j] = vb[cur][i * KW + j] - po;
-    if (threadIdx.x == 0) off[b] = acc;
+    if (live)
+        for (int r = 0; r < HR; ++r) out[(i0 + r) * KW + j] = vb[cur][(i0 + r) * KW + j] - po;
+    if (t == 0) off[b] = acc;
 }
 
 // One fold level: block q multiplies its children left to right (max-plus)
@@ -787,7 +807,7 @@ bool viterbi_grid_fits(const hmm_ctx *ctx, int K, int64_t T)
         const int64_t L = viterbi_len<KB>(ctx, T);
         const int64_t nb = T > 0 ? (T + L - 1) / L : 0;
         constexpr int NW = vit_seg_per_block<KB>();
-        return grid_fits((nb + NW - 1) / NW, vit_block_threads<KB>());
+        return grid_fits((nb + NW - 1) / NW, KB == kVitWide ? kVitWideSegThreads : vit_block_threads<KB>());
     };
     if (K <= 16) return fits(std::integral_constant<int, 16>());
     if (K <= 32) return fits(std::integral_constant<int, 32>());
@@ -847,8 +867,8 @@ int viterbi_impl(hmm_ctx *ctx, int32_t K, const double *delta, const double *Gam
         double *f0 = at<double>(ws, o_o[0]);
         void *args[] = {&d, &v0, &f0};
         constexpr int NW = vit_seg_per_block<KB>();
-        if (hipLaunchKernel(seg, dim3((unsigned)((nb + NW - 1) / NW)), dim3(vit_block_threads<KB>()), args, 0, st) !=
-            hipSuccess)
+        const unsigned seg_threads = KB == kVitWide ? kVitWideSegThreads : vit_block_threads<KB>();
+        if (hipLaunchKernel(seg, dim3((unsigned)((nb + NW - 1) / NW)), dim3(seg_threads), args, 0, st) != hipSuccess)
             return HMM_E_DEVICE;
         for (int l = 1; l < nlev; ++l) {
             if constexpr (KB == kVitWide)
