@@ -435,7 +435,6 @@ constexpr int kVitWideThreads = 128;
 // buffers take 51 KB of LDS, and a 6-step chunk keeps the block under a third
 // of the CU's 160 KB, so three blocks (six wavefronts) share a CU.
 constexpr int kVitWideChunk = 6;
-constexpr int kVitWideSegThreads = 192;   // segment kernel: 160 threads = (column, half of the rows)
 
 // Largest value over the block (two wavefronts); every thread gets it.
 __device__ __forceinline__ float block_max2(float v, float *red)
@@ -463,18 +462,28 @@ __device__ __forceinline__ float block_max_waves(float v, float *red)
 
 // Segment products: thread t < 2 KW computes column j = t % KW of half h =
 // t / KW of the rows (row i of the next matrix depends only on row i of the
-// current one), so 160 of the block's 192 threads work instead of 80 of 128;
+// current one; at KW = 80, 160 of the block's 192 threads work instead of
+// 80 of 128 with one thread per column);
 // the matrix lives in LDS (two buffers, read one, write the other).  The
 // renormalisation by the step's largest entry mx is folded into the next
 // step (subtracting a constant commutes with the max-plus product), so no
 // pass over the matrix is needed for it; the offset of the stored matrix is
 // the last mx, removed when the product is written out.
-__global__ __launch_bounds__(kVitWideSegThreads) void k_vit_segment_wide(VitDesc d, float *Vout, double *off)
+// Used for KW = 80 (64 < K <= 80; 6-step emission chunks keep three blocks
+// per CU) and KW = 64 (32 < K <= 64: 128 threads, all busy; 24-step chunks
+// keep four blocks per CU).
+template <int KW>
+constexpr int vit_rows_threads() { return (2 * KW + 63) / 64 * 64; }
+template <int KW>
+constexpr int vit_rows_chunk() { return KW == kVitWide ? kVitWideChunk : 24; }
+
+template <int KW>
+__global__ __launch_bounds__(vit_rows_threads<KW>()) void k_vit_segment_rows(VitDesc d, float *Vout, double *off)
 {
-    constexpr int KW = kVitWide, CH = kVitWideChunk, HR = KW / 2;
+    constexpr int CH = vit_rows_chunk<KW>(), HR = KW / 2;
     __shared__ __attribute__((aligned(16))) float vb[2][KW * KW];
     __shared__ __attribute__((aligned(16))) float lam[KW * CH];
-    __shared__ float red[kVitWideSegThreads / 64];
+    __shared__ float red[vit_rows_threads<KW>() / 64];
     __shared__ int badw;
     const int64_t b = blockIdx.x;
     if (b >= d.nb || *d.status != 0) return;
@@ -541,7 +550,7 @@ __global__ __launch_bounds__(kVitWideSegThreads) void k_vit_segment_wide(VitDesc
 
 // One fold level: block q multiplies its children left to right (max-plus)
 // with the running product in LDS (two buffers), thread j computing column j;
-// renormalisation folded into the next product as in k_vit_segment_wide.
+// renormalisation folded into the next product as in k_vit_segment_rows.
 __global__ __launch_bounds__(kVitWideThreads) void k_vit_fold_wide(int64_t n, const float *Vin, const double *offin,
                                                                    float *Vout, double *offout)
 {
@@ -759,8 +768,8 @@ const void *segment_kernel(int K)
 {
     if constexpr (KB == 16) return segment_kernel_in<16, 1, 16>(K);
     else if constexpr (KB == 32) return segment_kernel_in<32, 17, 32>(K);
-    else if constexpr (KB == 64) return reinterpret_cast<const void *>(&k_vit_segment<64, 64>);
-    else return reinterpret_cast<const void *>(&k_vit_segment_wide);
+    else if constexpr (KB == 64) return reinterpret_cast<const void *>(&k_vit_segment_rows<64>);
+    else return reinterpret_cast<const void *>(&k_vit_segment_rows<kVitWide>);
 }
 
 template <int KB, int LO, int HI>
@@ -807,7 +816,7 @@ bool viterbi_grid_fits(const hmm_ctx *ctx, int K, int64_t T)
         const int64_t L = viterbi_len<KB>(ctx, T);
         const int64_t nb = T > 0 ? (T + L - 1) / L : 0;
         constexpr int NW = vit_seg_per_block<KB>();
-        return grid_fits((nb + NW - 1) / NW, KB == kVitWide ? kVitWideSegThreads : vit_block_threads<KB>());
+        return grid_fits((nb + NW - 1) / NW, KB >= 64 ? vit_rows_threads<KB>() : vit_block_threads<KB>());
     };
     if (K <= 16) return fits(std::integral_constant<int, 16>());
     if (K <= 32) return fits(std::integral_constant<int, 32>());
@@ -867,7 +876,7 @@ int viterbi_impl(hmm_ctx *ctx, int32_t K, const double *delta, const double *Gam
         double *f0 = at<double>(ws, o_o[0]);
         void *args[] = {&d, &v0, &f0};
         constexpr int NW = vit_seg_per_block<KB>();
-        const unsigned seg_threads = KB == kVitWide ? kVitWideSegThreads : vit_block_threads<KB>();
+        const unsigned seg_threads = KB >= 64 ? vit_rows_threads<KB>() : vit_block_threads<KB>();
         if (hipLaunchKernel(seg, dim3((unsigned)((nb + NW - 1) / NW)), dim3(seg_threads), args, 0, st) != hipSuccess)
             return HMM_E_DEVICE;
         for (int l = 1; l < nlev; ++l) {
