@@ -460,10 +460,10 @@ __device__ __forceinline__ float block_max_waves(float v, float *red)
     return m;
 }
 
-// Segment products: thread t < 2 KW computes column j = t % KW of half h =
+// Segment products: thread t < NP KW computes column j = t % KW of part
 // t / KW of the rows (row i of the next matrix depends only on row i of the
-// current one; at KW = 80, 160 of the block's 192 threads work instead of
-// 80 of 128 with one thread per column);
+// current one), NP = 4 parts of 20 rows at KW = 80 (320 threads, all busy),
+// 2 of 32 at KW = 64 (128 threads);
 // the matrix lives in LDS (two buffers, read one, write the other).  The
 // renormalisation by the step's largest entry mx is folded into the next
 // step (subtracting a constant commutes with the max-plus product), so no
@@ -473,14 +473,16 @@ __device__ __forceinline__ float block_max_waves(float v, float *red)
 // per CU) and KW = 64 (32 < K <= 64: 128 threads, all busy; 24-step chunks
 // keep four blocks per CU).
 template <int KW>
-constexpr int vit_rows_threads() { return (2 * KW + 63) / 64 * 64; }
+constexpr int vit_rows_parts() { return KW == kVitWide ? 4 : 2; }   // threads per column
+template <int KW>
+constexpr int vit_rows_threads() { return (vit_rows_parts<KW>() * KW + 63) / 64 * 64; }
 template <int KW>
 constexpr int vit_rows_chunk() { return KW == kVitWide ? kVitWideChunk : 24; }
 
 template <int KW>
 __global__ __launch_bounds__(vit_rows_threads<KW>()) void k_vit_segment_rows(VitDesc d, float *Vout, double *off)
 {
-    constexpr int CH = vit_rows_chunk<KW>(), HR = KW / 2;
+    constexpr int CH = vit_rows_chunk<KW>(), NP = vit_rows_parts<KW>(), HR = KW / NP;
     __shared__ __attribute__((aligned(16))) float vb[2][KW * KW];
     __shared__ __attribute__((aligned(16))) float lam[KW * CH];
     __shared__ float red[vit_rows_threads<KW>() / 64];
@@ -488,7 +490,7 @@ __global__ __launch_bounds__(vit_rows_threads<KW>()) void k_vit_segment_rows(Vit
     const int64_t b = blockIdx.x;
     if (b >= d.nb || *d.status != 0) return;
     const int K = d.K, t = threadIdx.x, w = t >> 6;
-    const bool live = t < 2 * KW;
+    const bool live = t < NP * KW;
     const int j = live ? t % KW : KW, i0 = live ? (t / KW) * HR : 0;
     const int64_t t0 = b * d.L, t1 = min(d.T, t0 + d.L);
     float lgc[KW];
