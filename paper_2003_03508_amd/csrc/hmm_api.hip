@@ -203,7 +203,8 @@ int loglik_impl(hmm_ctx *ctx, int kind, int32_t K, const double *delta, const do
     if (!select_kernels(algo, K, &ks, ctx->packing)) return HMM_E_UNSUPPORTED;
     if (!(kind == kEmisTremor ? ks.seg1 : ks.seg1g)) return HMM_E_UNSUPPORTED;   // split: tremor model only
     const int KP = ks.KP();
-    Plan pl = kind == kEmisTremor ? make_plan(ctx, KP, T, ks.packG, ks.packWaves) : make_plan(ctx, KP, T);
+    Plan pl = kind == kEmisTremor ? make_plan(ctx, KP, T, ks.packG, ks.packWaves, ks.seg_waves())
+                                  : make_plan(ctx, KP, T, 0, 0, ks.seg_waves());
     if (pl.n1 > INT_MAX || !grid_fits(pl.n1, 64 * pl.waves)) return HMM_E_UNSUPPORTED;
     Layout ly = make_layout(KP, pl);
     rc = ensure_ws(ctx, ly.total + sizeof(double) * kFactBlocks);
@@ -274,7 +275,7 @@ size_t loglik_scratch_bytes(int32_t K, int64_t T, int32_t algo, KernelSet *ks, P
         return ly->total;
     }
     if (!select_kernels(algo, K, ks, defaults.packing)) return 0;
-    *pl = make_plan(&defaults, ks->KP(), T, ks->packG, ks->packWaves);
+    *pl = make_plan(&defaults, ks->KP(), T, ks->packG, ks->packWaves, ks->seg_waves());
     if (pl->n1 > INT_MAX || !grid_fits(pl->n1, 64 * pl->waves)) return 0;
     *ly = make_layout(ks->KP(), *pl);
     return ly->total;
@@ -372,7 +373,7 @@ int hmm_blocked_plan(hmm_ctx *ctx, int32_t K, int64_t T, int64_t *block_len, int
     const hmm_ctx defaults;
     const hmm_ctx *c = ctx ? ctx : &defaults;
     if (!select_kernels(HMM_BLOCKED_F32, K, &ks, c->packing)) return HMM_E_UNSUPPORTED;
-    Plan pl = make_plan(c, ks.KP(), T, ks.packG, ks.packWaves);
+    Plan pl = make_plan(c, ks.KP(), T, ks.packG, ks.packWaves, ks.seg_waves());
     *block_len = pl.L;
     *n_blocks = pl.nb;
     *levels = pl.levels;

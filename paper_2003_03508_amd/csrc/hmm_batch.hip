@@ -125,7 +125,7 @@ int64_t class_L(const hmm_ctx *ctx, const BatchPlan &bp, const BatchClass &c, in
 }
 
 // Most wavefronts per workgroup of a class's segment kernel.
-int max_waves(const BatchClass &c) { return c.G > 1 ? c.ks.packWaves : group_waves(c.KP); }
+int max_waves(const BatchClass &c) { return c.G > 1 ? c.ks.packWaves : c.ks.seg_waves(); }
 
 // Segment-kernel waves per workgroup of a class: a tuned value wins (w > 0:
 // w waves, at most the kernel's maximum; w < 0: the maximum divided by -w,
@@ -209,8 +209,8 @@ int build(hmm_ctx *ctx, BatchPlan &bp)
             c.seg = key;
             if (serial) c.serial = kss[s].seg1;
             c.G = (!serial && key == kss[s].segPB) ? kss[s].packG : 1;
-            c.W = group_waves(c.KP);
-            c.W2 = c.W;
+            c.W = c.ks.seg_waves();
+            c.W2 = group_waves(c.KP);
             bp.classes.push_back(c);
             it = bp.classes.end() - 1;
         }
@@ -225,7 +225,7 @@ int build(hmm_ctx *ctx, BatchPlan &bp)
         c.waves = class_waves(ctx, bp, c, bp.algo);
         c.W = c.waves * c.G;
         c.seg_lds = c.G > 1 ? (size_t)packed_region_bytes(c.ks.packNT, c.G) * c.waves
-                            : (size_t)region_bytes(c.KP) * c.waves;
+                            : c.ks.seg_region() * c.waves;
         c.L = class_L(ctx, bp, c, bp.algo, c.W);
         c.job0 = jobs.size();
         c.fjob0 = fjobs.size();

@@ -159,8 +159,8 @@ __device__ __forceinline__ long long wave_max_i64(long long x)
 __device__ __forceinline__ int fexp(float x) { return __builtin_amdgcn_frexp_expf(x); }
 
 // ---------------------------------------------------------------------------
-// Fused emission stage (eq. 1) for one chunk of up to kChunk observations.
-// Lane t of the wavefront owns observation tc + t:
+// Fused emission stage (eq. 1) for one chunk of up to min(ES, kChunk)
+// observations.  Lane t of the wavefront owns observation tc + t:
 //
 //  1. its flag and location are read with coalesced loads (one observation
 //     per lane: 1 byte and 16 bytes);
@@ -174,8 +174,9 @@ __device__ __forceinline__ int fexp(float x) { return __builtin_amdgcn_frexp_exp
 //     rounded to FP32, so the relative error of the scaled emission does not
 //     grow with |lam|.
 //
-// Et is stored transposed, row k (state) of stride ES >= kChunk floats, so
-// that the writes of one state are contiguous across lanes.  Rows k >= K
+// Et is stored transposed, row k (state) of stride ES floats, so that the
+// writes of one state are contiguous across lanes (lanes t >= ES write
+// nothing).  Rows k >= K
 // are not written (the caller keeps them zero).  The shift of the lane's
 // observation is returned in `shift` and added to `ssum`; `bad` is set for
 // invalid data (flag not 0/1, tremor with a non-finite location).
@@ -267,7 +268,7 @@ __device__ __forceinline__ void stage_emissions(int K, int64_t tc, int nst, cons
             const double n = floor(r);
             e = __builtin_amdgcn_ldexpf(exp2f((float)(r - n)), (int)n);
         }
-        Et[k * ES + lane] = e;
+        if (ES >= kWave || lane < ES) Et[k * ES + lane] = e;
     }
     wave_sync_lds();
 }

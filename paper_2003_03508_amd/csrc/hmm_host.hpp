@@ -138,10 +138,10 @@ struct Plan {
     bool packed = false;  // k_blocked_packed: G segments per wavefront
 };
 
-inline Plan make_plan(const hmm_ctx *ctx, int KP, int64_t T, int packG = 0, int packWaves = 0)
+inline Plan make_plan(const hmm_ctx *ctx, int KP, int64_t T, int packG = 0, int packWaves = 0, int segWaves = 0)
 {
     Plan p;
-    p.W = group_waves(KP);
+    p.W = segWaves > 0 ? segWaves : group_waves(KP);
     p.W2 = group_waves(KP);
     p.waves = p.W;
     // packed: packWaves wavefronts of packG segments per workgroup, one
@@ -259,7 +259,12 @@ struct KernelSet {
     // (segP) and batched (segPB)
     const void *segP = nullptr, *segPB = nullptr;
     int packNT = 0, packG = 0, packWaves = 0;
+    // wavefronts per workgroup and LDS bytes per wavefront of the unpacked
+    // segment kernels (seg1, seg1g, segB); 0: as the fold kernels
+    int segWaves = 0, segRegion = 0;
     int KP() const { return S * MT; }
+    int seg_waves() const { return segWaves > 0 ? segWaves : group_waves(KP()); }
+    size_t seg_region() const { return segRegion > 0 ? (size_t)segRegion : (size_t)region_bytes(KP()); }
 };
 
 template <int S, int MT, int NSL>
@@ -295,6 +300,8 @@ KernelSet kernel_set_lp()
     k.S = 16;
     k.MT = MT;
     k.NSL = NSL;
+    k.segWaves = lp_waves<MT>();
+    k.segRegion = 4 * lp_region_floats<MT>();
     return k;
 }
 
@@ -399,7 +406,7 @@ inline int run_single(hmm_ctx *ctx, void *ws, const KernelSet &ks, SetDesc d, co
     if (packed && !(ks.segP && d.obs.kind == kEmisTremor)) return HMM_E_UNSUPPORTED;   // plan made for another kernel
     const void *seg = packed ? ks.segP : (d.obs.kind == kEmisTremor ? ks.seg1 : ks.seg1g);
     const size_t rb = (size_t)region_bytes(KP);
-    const size_t seg_lds = packed ? (size_t)packed_region_bytes(ks.packNT, ks.packG) * pl.waves : rb * pl.W;
+    const size_t seg_lds = packed ? (size_t)packed_region_bytes(ks.packNT, ks.packG) * pl.waves : ks.seg_region() * pl.W;
     if (allow_lds(seg, seg_lds) != HMM_OK || allow_lds(ks.fold1, rb * pl.W2) != HMM_OK)
         return HMM_E_DEVICE;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;

@@ -668,16 +668,22 @@ __device__ __forceinline__ void combine_from_lds(Prod<S, MT> &P, long long &ssum
 
 // Binary tree over the W wavefronts of a workgroup: wave w ends up holding
 // the ordered product of the waves [w, w + 2^k) after round k.  Every wave
-// takes part in every barrier.
-template <int S, int MT, int NSL>
+// takes part in every barrier.  SHARED: the per-wave regions are smaller
+// than one exchanged product, and the writer w of a round uses regions w - 1
+// and w (free by then: wave w - 1 is the reader or was a writer of an
+// earlier round), after a first barrier that ends every wave's use of its
+// own region.
+template <int S, int MT, int NSL, bool SHARED = false>
 __device__ __forceinline__ void workgroup_tree(Prod<S, MT> &P, long long &ssum, float *smem, int region)
 {
     const int W = blockDim.x >> 6, w = threadIdx.x >> 6;
+    if constexpr (SHARED) __syncthreads();
     for (int stride = 1; stride < W; stride <<= 1) {
         const int pos = w % (2 * stride);
-        if (pos == stride) prod_to_lds<S, MT>(P, ssum, smem + w * region);
+        if (pos == stride) prod_to_lds<S, MT>(P, ssum, smem + (SHARED ? w - 1 : w) * region);
         __syncthreads();
-        if (pos == 0 && w + stride < W) combine_from_lds<S, MT, NSL>(P, ssum, smem + (w + stride) * region);
+        if (pos == 0 && w + stride < W)
+            combine_from_lds<S, MT, NSL>(P, ssum, smem + (SHARED ? w + stride - 1 : w + stride) * region);
         __syncthreads();
     }
 }
@@ -1146,15 +1152,21 @@ __global__ __launch_bounds__(64 * pack_waves<NT>()) void k_blocked_packed(SetDes
 }
 
 // ---------------------------------------------------------------------------
-// Segment products with BF16 or FP16 MFMA operands and FP32 accumulation.
-// Same structure as k_blocked with 16x16 tiles: the running product N is kept
-// and renormalised in FP32 (accumulator layout); each step packs it to 16-bit
-// as the B operand.  v_mfma_f32_16x16x32_{bf16,f16} contracts 32 rows: lane
-// group g supplies 8 of them, the rows it holds of two row tiles (2p, 2p+1):
-// element e of its operand is contraction row 16*(2p + e/4) + 4g + e%4.  An
+// Segment products with BF16 or FP16 MFMA operands and FP32 accumulation, on
+// 16x16 tiles.  The running product N is held only as the 16-bit B operand
+// of v_mfma_f32_16x16x32_{bf16,f16}, which contracts 32 rows: lane group g
+// supplies 8 of them, the rows it holds of two row tiles (2p, 2p+1), so
+// element e of its operand is contraction row 16*(2p + e/4) + 4g + e%4 and
+// the lane that computes an output row also supplies it as an input row.  An
 // odd last row tile uses the same instruction with elements 4..7 zero, so
 // that every accumulation chain uses one opcode (a 16x16x32 result fed as
 // the accumulator of a 16x16x16 instruction gave wrong sums on gfx950).
+// Columns of N (start states) are independent chains, so a step runs column
+// tile by column tile: the MFMAs of column tile n, then its emission product,
+// column maxima and power-of-two rescale in FP32, written straight back into
+// tile n's 16-bit operand.  Only one column tile's FP32 results are live at a
+// time.  The last step of a segment keeps its result in FP32 (the product the
+// segment hands on).
 // Gamma^T is converted once per segment; for FP16 it is pre-scaled by
 // 2^kF16GammaShift to keep small transition probabilities out of FP16's
 // subnormal range, and each step's extra factor is removed from the shift
@@ -1182,6 +1194,106 @@ template <> struct Lp<true> {
     }
 };
 
+// Wavefronts per workgroup, observations per emission chunk and LDS floats
+// per wavefront of k_blocked_lp.  With five row tiles (K_p = 80) the kernel
+// fits in 256 registers, and eight wavefronts (two per SIMD, so that one's
+// VALU work runs beside the other's MFMAs) fit in the CU's LDS with
+// 48-observation chunks and an exchange of the workgroup tree that spans the
+// writer's region and the one before it.  Otherwise as k_blocked.
+template <int MT>
+__host__ __device__ constexpr bool lp_shared_exchange()
+{
+    return MT == 5;
+}
+template <int MT>
+__host__ __device__ constexpr int lp_waves()
+{
+    return lp_shared_exchange<MT>() ? 8 : group_waves(16 * MT);
+}
+template <int MT>
+__host__ __device__ constexpr int lp_chunk()
+{
+    return lp_shared_exchange<MT>() ? 48 : kChunk;
+}
+template <int MT>
+__host__ __device__ constexpr int lp_region_floats()
+{
+    constexpr int KP = 16 * MT, et = lp_chunk<MT>() * KP, half = (Region<KP>::floats / 2 + 3) / 4 * 4;
+    return !lp_shared_exchange<MT>() ? Region<KP>::floats : (et > half ? et : half);
+}
+
+// Operands of one wavefront: Gamma^T (A, per row tile m) and N (B, per column
+// tile n), both in the contraction order above.
+template <int MT, bool F16, bool SPLIT>
+struct LpOps {
+    typedef typename Lp<F16>::v8 v8;
+    static constexpr int NP = MT / 2;
+    v8 Ap[MT][NP > 0 ? NP : 1];
+    v8 Ao[MT];
+    v8 Apl[SPLIT ? MT : 1][NP > 0 && SPLIT ? NP : 1];   // low parts (SPLIT only)
+    v8 Aol[SPLIT ? MT : 1];
+    v8 Bp[NP > 0 ? NP : 1][MT];
+    v8 Bo[MT];
+};
+
+// One observation step: N <- diag(e_hat_t) Gamma^T N, column tile by column
+// tile, each column divided by the power of two of its largest entry (the
+// exponent added to ex).  LAST: the result goes to the FP32 product P
+// instead of N's operand.  Registers of dead slots stay zero.
+template <int MT, bool F16, int NSL, bool SPLIT, bool LAST>
+__device__ __forceinline__ void lp_step(LpOps<MT, F16, SPLIT> &o, const float (&ev)[MT][4], long long (&ex)[MT],
+                                        Prod<16, MT> &P)
+{
+    constexpr int NP = MT / 2, ODD = MT % 2;
+    typedef Lp<F16> lp;
+    typedef typename lp::e_t e_t;
+    typedef typename Tile<16>::acc_t acc_t;
+#pragma unroll
+    for (int n = 0; n < MT; ++n) {
+        acc_t C[MT];
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+            acc_t acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int p2 = 0; p2 < NP; ++p2) {
+                if constexpr (SPLIT) acc = lp::mma32(o.Apl[m][p2], o.Bp[p2][n], acc);
+                acc = lp::mma32(o.Ap[m][p2], o.Bp[p2][n], acc);
+            }
+            if constexpr (ODD) {
+                if constexpr (SPLIT) acc = lp::mma32(o.Aol[m], o.Bo[n], acc);
+                acc = lp::mma32(o.Ao[m], o.Bo[n], acc);
+            }
+            C[m] = acc;
+        }
+        float v[MT][4];
+        float mx = 0.f;
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                if (!live_reg<16, NSL>(m, r)) continue;
+                v[m][r] = C[m][r] * ev[m][r];
+                mx = fmaxf(mx, v[m][r]);
+            }
+        mx = column_max<16>(mx);
+        const int e = (mx > 0.f) ? fexp(mx) : 0;
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                if (!live_reg<16, NSL>(m, r)) {
+                    if constexpr (LAST) P.B[m][n][r] = 0.f;
+                    continue;
+                }
+                const float x = __builtin_amdgcn_ldexpf(v[m][r], -e);
+                if constexpr (LAST) P.B[m][n][r] = x;
+                else if (m < 2 * NP) o.Bp[m / 2][n][(m % 2) * 4 + r] = (e_t)x;
+                else o.Bo[n][r] = (e_t)x;
+            }
+        ex[n] += e;
+    }
+}
+
 // SPLIT: Gamma^T enters as two 16-bit operands, hi = round(G) and
 // lo = round(G - hi), both multiplied with the same B operand into the same
 // FP32 accumulator (same opcode), so the transition matrix carries about
@@ -1193,13 +1305,11 @@ __device__ __forceinline__ void blocked_lp_job(const SetDesc &d, const WgJob &jo
                                                long long *__restrict__ Eout, long long *__restrict__ Sout,
                                                int salt = 0)
 {
-    constexpr int S = 16, KP = 16 * MT, RS = 4, NP = MT / 2, ODD = MT % 2;
-    typedef typename Tile<S>::acc_t acc_t;
+    constexpr int S = 16, KP = 16 * MT, NP = MT / 2, ODD = MT % 2;
+    constexpr int CH = lp_chunk<MT>(), region = lp_region_floats<MT>();
     typedef Lp<F16> lp;
     typedef typename lp::e_t e_t;
-    typedef typename lp::v8 v8;
     extern __shared__ __attribute__((aligned(16))) float smem[];
-    constexpr int region = Region<KP>::floats;
 
     const int tid = (int)threadIdx.x + salt;
     const int lane = tid & 63, w = tid >> 6;
@@ -1210,11 +1320,9 @@ __device__ __forceinline__ void blocked_lp_job(const SetDesc &d, const WgJob &jo
     const StateConst *__restrict__ sc = d.sc;
     const Obs obs = d.obs;
     const int64_t b = job.seg0 + w;
-    float *base = smem + w * region;
-    float *Et = Region<KP>::E(base);
+    float *Et = smem + w * region;   // Et[k][t], row stride CH
 
     Prod<S, MT> P;
-    prod_identity<S, MT, NSL>(P, lane);
     long long ssum = 0;
     int bad = 0, sh = 0;
 
@@ -1222,10 +1330,8 @@ __device__ __forceinline__ void blocked_lp_job(const SetDesc &d, const WgJob &jo
         const int64_t t0 = b * L;
         const int64_t t1 = min(T, t0 + L);
         const float gscale = (float)(1 << lp::shift);
-        v8 Ap[MT][NP > 0 ? NP : 1];
-        v8 Ao[MT];
-        v8 Apl[SPLIT ? MT : 1][NP > 0 && SPLIT ? NP : 1];   // low parts (SPLIT only)
-        v8 Aol[SPLIT ? MT : 1];
+        LpOps<MT, F16, SPLIT> o;
+        long long ex[MT];
 #pragma unroll
         for (int m = 0; m < MT; ++m) {
 #pragma unroll
@@ -1235,99 +1341,83 @@ __device__ __forceinline__ void blocked_lp_job(const SetDesc &d, const WgJob &jo
                     // contraction row: register e % 4 of tile row 2 p2 + e / 4 on lane group g
                     const int rho = reg_state<16>(2 * p2 + e / 4, g, e % 4);
                     const float gv = GF[rho * KP + phys_state<16, MT>(16 * m + c)] * gscale;
-                    Ap[m][p2][e] = (e_t)gv;
-                    if constexpr (SPLIT) Apl[m][p2][e] = (e_t)(gv - (float)Ap[m][p2][e]);
+                    o.Ap[m][p2][e] = (e_t)gv;
+                    if constexpr (SPLIT) o.Apl[m][p2][e] = (e_t)(gv - (float)o.Ap[m][p2][e]);
                 }
             if constexpr (ODD) {
 #pragma unroll
                 for (int e = 0; e < 8; ++e) {
                     const int rho = reg_state<16>(MT - 1, g, e % 4);
                     const float gv = (e < 4) ? GF[rho * KP + phys_state<16, MT>(16 * m + c)] * gscale : 0.f;
-                    Ao[m][e] = (e_t)gv;
-                    if constexpr (SPLIT) Aol[m][e] = (e_t)(gv - (float)Ao[m][e]);
+                    o.Ao[m][e] = (e_t)gv;
+                    if constexpr (SPLIT) o.Aol[m][e] = (e_t)(gv - (float)o.Ao[m][e]);
                 }
             }
         }
-        for (int i = lane; i < KP * kChunk; i += kWave) Et[i] = 0.f;
-        for (int64_t tc = t0; tc < t1; tc += kChunk) {
-            const int nst = (int)min((int64_t)kChunk, t1 - tc);
-            stage_emissions<kChunk, GEN>(K, tc, nst, obs, sc, Et, ssum, bad, sh);
-            for (int tl = 0; tl < nst; tl += 2) {
-                float evu[MT][RS][2];
+        // N = identity (in the physical order); registers of dead slots zero
 #pragma unroll
-                for (int m = 0; m < MT; ++m)
+        for (int n = 0; n < MT; ++n) {
+            auto id = [&](int m, int r) -> e_t {
+                return (e_t)((live_reg<S, NSL>(m, r) && S * m + rit<S>(g, r) == S * n + c) ? 1.f : 0.f);
+            };
 #pragma unroll
-                    for (int r = 0; r < RS; ++r) {
-                        if (!live_reg<S, NSL>(m, r)) {
-                            evu[m][r][0] = evu[m][r][1] = 0.f;
-                            continue;
-                        }
-                        const float2 q = *reinterpret_cast<const float2 *>(&Et[reg_state<S>(m, g, r) * kChunk + tl]);
-                        evu[m][r][0] = q.x;
-                        evu[m][r][1] = q.y;
-                    }
+            for (int p2 = 0; p2 < NP; ++p2)
 #pragma unroll
-                for (int u = 0; u < 2; ++u) {
-                    if (tl + u >= nst) break;
-                    float ev[MT][RS];
+                for (int e = 0; e < 8; ++e) o.Bp[p2][n][e] = id(2 * p2 + e / 4, e % 4);
+            if constexpr (ODD) {
 #pragma unroll
-                    for (int m = 0; m < MT; ++m)
-#pragma unroll
-                        for (int r = 0; r < RS; ++r) ev[m][r] = evu[m][r][u];
-                    // pack N (columns of every tile) to 16-bit B operands
-                    v8 Bp[NP > 0 ? NP : 1][MT];
-                    v8 Bo[MT];
-#pragma unroll
-                    for (int n = 0; n < MT; ++n) {
-#pragma unroll
-                        for (int p2 = 0; p2 < NP; ++p2)
-#pragma unroll
-                            for (int e = 0; e < 8; ++e) Bp[p2][n][e] = (e_t)P.B[2 * p2 + e / 4][n][e % 4];
-                        if constexpr (ODD) {
-#pragma unroll
-                            for (int e = 0; e < 8; ++e) Bo[n][e] = (e < 4) ? (e_t)P.B[MT - 1][n][e] : (e_t)0.f;
-                        }
-                    }
-                    acc_t C[MT][MT];
-#pragma unroll
-                    for (int m = 0; m < MT; ++m)
-#pragma unroll
-                        for (int n = 0; n < MT; ++n) {
-                            acc_t acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                            for (int p2 = 0; p2 < NP; ++p2) {
-                                if constexpr (SPLIT) acc = lp::mma32(Apl[m][p2], Bp[p2][n], acc);
-                                acc = lp::mma32(Ap[m][p2], Bp[p2][n], acc);
-                            }
-                            if constexpr (ODD) {
-                                if constexpr (SPLIT) acc = lp::mma32(Aol[m], Bo[n], acc);
-                                acc = lp::mma32(Ao[m], Bo[n], acc);
-                            }
-                            C[m][n] = acc;
-                        }
-                    renorm_columns<S, MT, NSL, true>(C, ev, P);
-                }
+                for (int e = 0; e < 8; ++e) o.Bo[n][e] = (e < 4) ? id(MT - 1, e) : (e_t)0.f;
             }
+            ex[n] = 0;
+        }
+        auto read_ev = [&](int tl, float (&ev)[MT][4]) {
+#pragma unroll
+            for (int m = 0; m < MT; ++m)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    ev[m][r] = live_reg<S, NSL>(m, r) ? Et[reg_state<S>(m, g, r) * CH + tl] : 0.f;
+        };
+        for (int i = lane; i < KP * CH; i += kWave) Et[i] = 0.f;
+        // every step but the segment's last one
+        for (int64_t tc = t0; tc < t1; tc += CH) {
+            const int nst = (int)min((int64_t)CH, t1 - tc);
+            stage_emissions<CH, GEN>(K, tc, nst, obs, sc, Et, ssum, bad, sh);
+            const bool last_chunk = tc + nst >= t1;
+            const int nrun = last_chunk ? nst - 1 : nst;
+            for (int tl = 0; tl < nrun; ++tl) {
+                float ev[MT][4];
+                read_ev(tl, ev);
+                lp_step<MT, F16, NSL, SPLIT, false>(o, ev, ex, P);
+            }
+            if (!last_chunk) wave_sync_lds();
+        }
+        // the last step (its emissions are still staged) ends in FP32
+        {
+            float ev[MT][4];
+            read_ev((int)((t1 - 1 - t0) % CH), ev);
+            lp_step<MT, F16, NSL, SPLIT, true>(o, ev, ex, P);
             wave_sync_lds();
         }
+#pragma unroll
+        for (int n = 0; n < MT; ++n) P.ex[n] = ex[n];
         // remove the Gamma pre-scale: one factor 2^shift per observation
         if (lane == 0) ssum -= (long long)lp::shift * (t1 - t0);
+    } else {
+        prod_identity<S, MT, NSL>(P, lane);
     }
     if (__any(bad) && lane == 0) atomicOr(d.status, kBadData);
     ssum = wave_sum_i64(ssum);
-    workgroup_tree<S, MT, NSL>(P, ssum, smem, region);
+    workgroup_tree<S, MT, NSL, lp_shared_exchange<MT>()>(P, ssum, smem, region);
     if (w == 0)
         prod_to_global<S, MT>(P, ssum, Mout + job.out * KP * KP, Eout + job.out * KP, Sout + job.out);
 }
 
 template <int MT, bool F16, int NSL, bool BATCH, bool GEN = false, bool SPLIT = false>
-__global__ __launch_bounds__(64 * group_waves(16 * MT)) void k_blocked_lp(SetDesc one,
-                                                                          const SetDesc *__restrict__ sets,
-                                                                          const WgJob *__restrict__ jobs,
-                                                                          int64_t nb, int *queue,
-                                                                          float *__restrict__ Mout,
-                                                                          long long *__restrict__ Eout,
-                                                                          long long *__restrict__ Sout)
+__global__ __launch_bounds__(64 * lp_waves<MT>()) void k_blocked_lp(SetDesc one, const SetDesc *__restrict__ sets,
+                                                                    const WgJob *__restrict__ jobs, int64_t nb,
+                                                                    int *queue, float *__restrict__ Mout,
+                                                                    long long *__restrict__ Eout,
+                                                                    long long *__restrict__ Sout)
 {
     if constexpr (BATCH) {
         run_jobs(jobs, nb, queue, [&](const WgJob &job, int salt) {
