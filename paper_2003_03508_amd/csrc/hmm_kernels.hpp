@@ -1197,9 +1197,12 @@ template <> struct Lp<true> {
 // Wavefronts per workgroup, observations per emission chunk and LDS floats
 // per wavefront of k_blocked_lp.  With five row tiles (K_p = 80) the kernel
 // fits in 256 registers, and eight wavefronts (two per SIMD, so that one's
-// VALU work runs beside the other's MFMAs) fit in the CU's LDS with
-// 48-observation chunks and an exchange of the workgroup tree that spans the
-// writer's region and the one before it.  Otherwise as k_blocked.
+// VALU work runs beside the other's MFMAs) fit in the CU's 160 KiB of LDS
+// with 63-observation chunks (8 x 80 x 63 floats, which leaves room for the
+// batched kernel's job index; the odd row stride also keeps the four lane
+// groups' emission reads in different banks) and an exchange of the
+// workgroup tree that spans the writer's region and the one before it.
+// Otherwise as k_blocked.
 template <int MT>
 __host__ __device__ constexpr bool lp_shared_exchange()
 {
@@ -1213,7 +1216,7 @@ __host__ __device__ constexpr int lp_waves()
 template <int MT>
 __host__ __device__ constexpr int lp_chunk()
 {
-    return lp_shared_exchange<MT>() ? 48 : kChunk;
+    return lp_shared_exchange<MT>() ? kChunk - 1 : kChunk;
 }
 template <int MT>
 __host__ __device__ constexpr int lp_region_floats()
@@ -1221,6 +1224,9 @@ __host__ __device__ constexpr int lp_region_floats()
     constexpr int KP = 16 * MT, et = lp_chunk<MT>() * KP, half = (Region<KP>::floats / 2 + 3) / 4 * 4;
     return !lp_shared_exchange<MT>() ? Region<KP>::floats : (et > half ? et : half);
 }
+static_assert(8 * lp_region_floats<5>() * 4 + 256 <= 160 * 1024, "eight K_p = 80 regions exceed the CU's LDS");
+static_assert(lp_region_floats<5>() % 4 == 0, "regions hold float4 exchanges");
+static_assert(2 * lp_region_floats<5>() >= Region<80>::floats, "the tree's exchange spans two regions");
 
 // Operands of one wavefront: Gamma^T (A, per row tile m) and N (B, per column
 // tile n), both in the contraction order above.

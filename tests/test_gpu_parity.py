@@ -291,15 +291,15 @@ def test_blocked_16bit_within_bound(binding, ctx, algo, K):
 @pytest.mark.parametrize("algo", ["blocked_bf16", "blocked_f16", "blocked_bf16_split"])
 @pytest.mark.parametrize("K", [65, 72, 80])
 def test_blocked_16bit_five_row_tiles(binding, ctx, algo, K):
-    """K_p = 80 (eight wavefronts per workgroup, 48-observation emission chunks,
-    the tree's exchange across two regions): segments of one step, of one
-    chunk, one step short of and past a chunk, of two chunks, the default plan,
-    and a ragged last segment; dead slots for K < 80."""
+    """K_p = 80 (eight wavefronts per workgroup, the tree's exchange across two
+    regions): segments of one step, of one emission chunk (63 observations),
+    one step short of and past a chunk, of two chunks, the default plan, and a
+    ragged last segment; dead slots for K < 80."""
     T = 3000 + 7 * K
     prm, obs = synth.make(K, T, seed=260 + K)
     want = ref(prm, obs)
     bound = lowp_bound(algo, K, T)
-    for L in (1, 47, 48, 49, 96, 0, T - 1):
+    for L in (1, 62, 63, 64, 126, 0, T - 1):
         got = gpu(binding, ctx, prm, obs, algo, L, 0)
         err = abs(got - want)
         print(f"{algo} K={K} T={T} L={L}: |d ln L| = {err:.3e} nats (bound {bound:.3e})", flush=True)
