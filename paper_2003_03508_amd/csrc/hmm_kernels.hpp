@@ -1053,7 +1053,16 @@ __device__ __forceinline__ void packed_job(const SetDesc &d, const WgJob &job, f
         auto steps_of = [&](auto masked) {
             constexpr bool MASK = decltype(masked)::value;
             for (int tl = 0; tl < nst; ++tl) {
-                acc_t C[NT];
+                // the step's emissions for every tile, read before its MFMAs
+                float evs[NT][NSL];
+#pragma unroll
+                for (int n = 0; n < NT; ++n) {
+                    const float *ev = Et + segn[n] * (KP * CH) + tl;
+#pragma unroll
+                    for (int r = 0; r < NSL; ++r) evs[n][r] = ev[reg_state<S>(0, g, r) * CH];
+                }
+                // column tiles are independent chains: each tile's MFMAs, then
+                // its renormalisation (the next tile's MFMAs can run meanwhile)
 #pragma unroll
                 for (int n = 0; n < NT; ++n) {
                     acc_t acc;
@@ -1061,18 +1070,13 @@ __device__ __forceinline__ void packed_job(const SetDesc &d, const WgJob &job, f
                     for (int r = 0; r < RS; ++r) acc[r] = 0.f;
 #pragma unroll
                     for (int j = 0; j < NSL; ++j) acc = mfma<S>(A[j], B[n][j], acc);
-                    C[n] = acc;
-                }
-#pragma unroll
-                for (int n = 0; n < NT; ++n) {
-                    const float *ev = Et + segn[n] * (KP * CH) + tl;
                     const bool act = !MASK || (tc + tl < lenn[n]);
                     float v[RS];
                     float mx = 0.f;
 #pragma unroll
                     for (int r = 0; r < RS; ++r) {
                         if (r >= NSL) continue;
-                        v[r] = act ? C[n][r] * ev[reg_state<S>(0, g, r) * CH] : B[n][r];
+                        v[r] = act ? acc[r] * evs[n][r] : B[n][r];
                         mx = fmaxf(mx, v[r]);
                     }
                     mx = column_max<S>(mx);
