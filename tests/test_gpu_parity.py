@@ -418,6 +418,31 @@ def test_batched_16bit(binding, ctx, algo):
         assert err <= lowp_bound(algo, prm.K, obs.T), (algo, i, err)
 
 
+@pytest.mark.parametrize("algo", ["blocked_bf16", "blocked_f16"])
+def test_batched_16bit_five_row_tiles_tuned(binding, ctx, algo):
+    """K_p = 80 sets in a batch, before and after autotuning (which also tries
+    half the wavefronts per workgroup, i.e. the two-region tree exchange with
+    four wavefronts), with the persistent queue and with one workgroup per
+    job, twice in a row: every set within its bound each time."""
+    sets = [synth.make(K, T, seed=700 + i) for i, (K, T) in
+            enumerate([(80, 9000), (72, 7001), (65, 5003), (80, 1), (70, 12000), (40, 3000)])]
+    d = binding.batch_to_device(synth.pack(sets))
+    want = [ref(prm, obs) for prm, obs in sets]
+    try:
+        for stage in ("default", "tuned", "one workgroup per job"):
+            if stage == "tuned":
+                ctx.autotune_batched(**d, algo=algo, reps=1)
+            if stage == "one workgroup per job":
+                ctx.set_batch_persistent(False)
+            for rep in range(2):
+                out = ctx.loglik_batched(**d, algo=algo).cpu().numpy()
+                for i, (prm, obs) in enumerate(sets):
+                    err = abs(out[i] - want[i])
+                    assert err <= lowp_bound(algo, prm.K, obs.T) + 1e-9, (stage, rep, i, err)
+    finally:
+        ctx.set_batch_persistent(True)
+
+
 def test_batched_invalid_set_is_isolated(binding, ctx):
     sets = [synth.make(5, 1000, seed=500 + i) for i in range(3)]
     sets[1][0].p[2] = 1.5  # invalid parameter in set 1 only
