@@ -243,7 +243,9 @@ int hmm_ctx_set_batch_persistent(hmm_ctx *ctx, int32_t on);
  * workgroup of segments of at least 16 observations); a batched call packs the
  * sets of a K the mode covers when together they give at least 256 such
  * workgroups.  Otherwise one segment per wavefront, which fills the chip
- * better.  The products are the same up to FP32 rounding order.
+ * better.  Single-set calls of the other emission kinds (hmm_loglik_kind)
+ * pack by the same rules.  The products are the same up to FP32 rounding
+ * order.
  * HMM_E_INVALID_ARG for a null context or another mode. */
 int hmm_ctx_set_packing(hmm_ctx *ctx, int32_t mode);
 

@@ -88,6 +88,7 @@ void set_packed(KernelSet *ks)
 {
     constexpr int G = 32 * NT / K, NSL = (K + 1) / 2;
     ks->segP = reinterpret_cast<const void *>(&k_blocked_packed<NT, G, NSL, false>);
+    ks->segPg = reinterpret_cast<const void *>(&k_blocked_packed_kind<NT, G, NSL>);
     ks->segPB = reinterpret_cast<const void *>(&k_blocked_packed<NT, G, NSL, true>);
     ks->packNT = NT;
     ks->packG = G;
@@ -203,8 +204,7 @@ int loglik_impl(hmm_ctx *ctx, int kind, int32_t K, const double *delta, const do
     if (!select_kernels(algo, K, &ks, ctx->packing)) return HMM_E_UNSUPPORTED;
     if (!(kind == kEmisTremor ? ks.seg1 : ks.seg1g)) return HMM_E_UNSUPPORTED;   // split: tremor model only
     const int KP = ks.KP();
-    Plan pl = kind == kEmisTremor ? make_plan(ctx, KP, T, ks.packG, ks.packWaves, ks.seg_waves())
-                                  : make_plan(ctx, KP, T, 0, 0, ks.seg_waves());
+    Plan pl = make_plan(ctx, KP, T, ks.packG, ks.packWaves, ks.seg_waves());
     if (pl.n1 > INT_MAX || !grid_fits(pl.n1, 64 * pl.waves)) return HMM_E_UNSUPPORTED;
     Layout ly = make_layout(KP, pl);
     rc = ensure_ws(ctx, ly.total + sizeof(double) * kFactBlocks);

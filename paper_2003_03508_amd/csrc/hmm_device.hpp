@@ -216,6 +216,44 @@ __device__ __forceinline__ double generic_log2_emission(const StateConst &s, boo
 
 // GEN = false: the tremor model only (the likelihood kernels of eq. 1);
 // GEN = true: any emission kind, chosen by o.kind.
+// Observation t for a live lane: the tremor flag and location (read only for
+// a tremor), a Poisson count or a 1-D value (GEN: o.kind decides; otherwise
+// the tremor model).  f = 1 selects the state's density branch; bad is set
+// for invalid data.
+template <bool GEN>
+__device__ __forceinline__ void load_observation(const Obs &o, int64_t t, bool live, int &f, double &x, double &y,
+                                                 int &bad)
+{
+    const int kind = GEN ? o.kind : kEmisTremor;
+    f = 0;
+    x = 0.0;
+    y = 0.0;
+    if (!live) return;
+    if (kind == kEmisTremor) {
+        f = o.flag[t];
+        if (f == 1) {
+            const double2 p = reinterpret_cast<const double2 *>(o.xy)[t];
+            x = p.x;
+            y = p.y;
+            if (!(isfinite(x) && isfinite(y))) bad = 1;
+        } else if (f != 0) {
+            bad = 1;
+        }
+    } else if (kind == kEmisPoisson) {
+        const int32_t n = o.cnt[t];
+        if (n < 0) bad = 1;
+        x = n < 0 ? 0.0 : (double)n;
+        f = 1;
+    } else {
+        x = o.xy[t];
+        if (!isfinite(x)) {
+            bad = 1;
+            x = 0.0;
+        }
+        f = 1;
+    }
+}
+
 template <int ES, bool GEN>
 __device__ __forceinline__ void stage_emissions(int K, int64_t tc, int nst, const Obs &o,
                                                 const StateConst *__restrict__ sc,
@@ -223,34 +261,9 @@ __device__ __forceinline__ void stage_emissions(int K, int64_t tc, int nst, cons
 {
     const int lane = threadIdx.x & (kWave - 1);
     const bool live = lane < nst;
-    const int kind = GEN ? o.kind : kEmisTremor;
-    int f = 0;
-    double x = 0.0, y = 0.0;
-    if (live) {
-        if (kind == kEmisTremor) {
-            f = o.flag[tc + lane];
-            if (f == 1) {
-                const double2 p = reinterpret_cast<const double2 *>(o.xy)[tc + lane];
-                x = p.x;
-                y = p.y;
-                if (!(isfinite(x) && isfinite(y))) bad = 1;
-            } else if (f != 0) {
-                bad = 1;
-            }
-        } else if (kind == kEmisPoisson) {
-            const int32_t n = o.cnt[tc + lane];
-            if (n < 0) bad = 1;
-            x = n < 0 ? 0.0 : (double)n;
-            f = 1;
-        } else {
-            x = o.xy[tc + lane];
-            if (!isfinite(x)) {
-                bad = 1;
-                x = 0.0;
-            }
-            f = 1;
-        }
-    }
+    int f;
+    double x, y;
+    load_observation<GEN>(o, tc + lane, live, f, x, y, bad);
     const bool tremor = (f == 1);
     double m = -INFINITY;
     auto lam = [&](const StateConst &sk) {

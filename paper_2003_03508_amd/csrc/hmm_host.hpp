@@ -256,8 +256,8 @@ struct KernelSet {
     int S = 0, MT = 0, NSL = 0;
     // FP32 segment kernels with G segments per wavefront packed into NT
     // column tiles (k_blocked_packed), if there are for this K: single set
-    // (segP) and batched (segPB)
-    const void *segP = nullptr, *segPB = nullptr;
+    // (segP), single set of any emission kind (segPg) and batched (segPB)
+    const void *segP = nullptr, *segPg = nullptr, *segPB = nullptr;
     int packNT = 0, packG = 0, packWaves = 0;
     // wavefronts per workgroup and LDS bytes per wavefront of the unpacked
     // segment kernels (seg1, seg1g, segB); 0: as the fold kernels
@@ -356,7 +356,7 @@ inline int default_pack_tiles(int K, bool batched)
 // Sets the packed kernels of ks for the packing mode (see hmm_ctx::packing).
 inline void choose_packing(int mode, int K, bool batched, KernelSet *ks)
 {
-    ks->segP = ks->segPB = nullptr;
+    ks->segP = ks->segPg = ks->segPB = nullptr;
     ks->packNT = ks->packG = ks->packWaves = 0;
     const int nt = mode == 1 ? default_pack_tiles(K, batched) : ((mode == 2 || mode == 4 || mode == 5) ? mode : 0);
     if (nt > 0) packed_kernel(K, nt, ks);
@@ -403,8 +403,9 @@ inline int run_single(hmm_ctx *ctx, void *ws, const KernelSet &ks, SetDesc d, co
 {
     const int KP = ks.KP();
     const bool packed = pl.packed;
-    if (packed && !(ks.segP && d.obs.kind == kEmisTremor)) return HMM_E_UNSUPPORTED;   // plan made for another kernel
-    const void *seg = packed ? ks.segP : (d.obs.kind == kEmisTremor ? ks.seg1 : ks.seg1g);
+    const bool tremor = d.obs.kind == kEmisTremor;
+    const void *seg = packed ? (tremor ? ks.segP : ks.segPg) : (tremor ? ks.seg1 : ks.seg1g);
+    if (!seg) return HMM_E_UNSUPPORTED;   // plan made for another kernel
     const size_t rb = (size_t)region_bytes(KP);
     const size_t seg_lds = packed ? (size_t)packed_region_bytes(ks.packNT, ks.packG) * pl.waves : ks.seg_region() * pl.W;
     if (allow_lds(seg, seg_lds) != HMM_OK || allow_lds(ks.fold1, rb * pl.W2) != HMM_OK)

@@ -919,7 +919,8 @@ __host__ __device__ constexpr int pack_waves()
 
 // One workgroup job: segments [job.seg0, job.seg0 + job.nseg) of the set, G
 // per wavefront in order, product to slot job.out.
-template <int NT, int G, int NSL>
+// GEN: any emission kind (o.kind), as stage_emissions<ES, true>.
+template <int NT, int G, int NSL, bool GEN = false>
 __device__ __forceinline__ void packed_job(const SetDesc &d, const WgJob &job, float *__restrict__ Mout,
                                            long long *__restrict__ Eout, long long *__restrict__ Sout,
                                            int salt = 0)
@@ -996,20 +997,13 @@ __device__ __forceinline__ void packed_job(const SetDesc &d, const WgJob &job, f
         {
             const int64_t t = t0l + tc + tl0;
             const bool live = stager && tl0 < nst && t < t1l;
-            int f = 0;
-            double x = 0.0, y = 0.0;
-            if (live) {
-                f = d.obs.flag[t];
-                if (f == 1) {
-                    const double2 p = reinterpret_cast<const double2 *>(d.obs.xy)[t];
-                    x = p.x;
-                    y = p.y;
-                    if (!(isfinite(x) && isfinite(y))) bad = 1;
-                } else if (f != 0) {
-                    bad = 1;
-                }
-            }
+            int f;
+            double x, y;
+            load_observation<GEN>(d.obs, t, live, f, x, y, bad);
             const bool tremor = (f == 1);
+            auto lam_of = [&](const StateConst &sk) {
+                return GEN ? generic_log2_emission(sk, tremor, x, y) : state_log2_emission(sk, tremor, x, y);
+            };
             float *row = Et + (sl < G ? sl : 0) * (KP * CH) + tl0;
             auto store = [&](int k, double lam, int sh) {
                 const double r = lam - (double)sh;
@@ -1030,7 +1024,7 @@ __device__ __forceinline__ void packed_job(const SetDesc &d, const WgJob &job, f
                 double m = -INFINITY;
 #pragma unroll
                 for (int k = 0; k < 2 * NSL; ++k) {
-                    lam[k] = k < K ? state_log2_emission(d.sc[k], tremor, x, y) : -INFINITY;
+                    lam[k] = k < K ? lam_of(d.sc[k]) : -INFINITY;
                     m = fmax(m, lam[k]);
                 }
                 const int sh = shift_of(m);
@@ -1042,11 +1036,11 @@ __device__ __forceinline__ void packed_job(const SetDesc &d, const WgJob &job, f
                 }
             } else {
                 double m = -INFINITY;
-                for (int k = 0; k < K; ++k) m = fmax(m, state_log2_emission(d.sc[k], tremor, x, y));
+                for (int k = 0; k < K; ++k) m = fmax(m, lam_of(d.sc[k]));
                 const int sh = shift_of(m);
                 if (live) ssum += sh;
                 if (sl < G)
-                    for (int k = 0; k < K; ++k) store(k, state_log2_emission(d.sc[k], tremor, x, y), sh);
+                    for (int k = 0; k < K; ++k) store(k, lam_of(d.sc[k]), sh);
             }
             wave_sync_lds();
         }
@@ -1153,6 +1147,28 @@ __global__ __launch_bounds__(64 * pack_waves<NT>()) void k_blocked_packed(SetDes
         job.set = 0;
         packed_job<NT, G, NSL>(one, job, Mout, Eout, Sout);
     }
+}
+
+// The same for a single set of any emission kind (Poisson counts, 1-D
+// Gaussian, or the tremor model through the generic formula).
+template <int NT, int G, int NSL>
+__global__ __launch_bounds__(64 * pack_waves<NT>()) void k_blocked_packed_kind(SetDesc one,
+                                                                         const SetDesc *__restrict__ sets,
+                                                                         const WgJob *__restrict__ jobs, int64_t nb,
+                                                                         int *queue, float *__restrict__ Mout,
+                                                                         long long *__restrict__ Eout,
+                                                                         long long *__restrict__ Sout)
+{
+    (void)sets;
+    (void)jobs;
+    (void)queue;
+    const int W = (blockDim.x >> 6) * G;
+    WgJob job;
+    job.seg0 = (int64_t)blockIdx.x * W;
+    job.nseg = (int)min((int64_t)W, nb - job.seg0);
+    job.out = blockIdx.x;
+    job.set = 0;
+    packed_job<NT, G, NSL, true>(one, job, Mout, Eout, Sout);
 }
 
 // ---------------------------------------------------------------------------

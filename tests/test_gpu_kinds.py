@@ -83,6 +83,33 @@ def test_kind_full_size(binding, ctx, kind):
 
 
 @pytest.mark.parametrize("kind", [1, 2])
+@pytest.mark.parametrize("K", [17, 18, 21, 22, 25])
+def test_kind_packed_segments(binding, ctx, kind, K):
+    """Several segments per wavefront (17 <= K <= 25, long enough to pack):
+    the default table (five, four and two column tiles), forced four tiles,
+    no packing, a ragged length, and an invalid observation inside a packed
+    segment."""
+    T = 300_007
+    ks = synth.make_kind(kind, K, T, seed=500 * kind + K)
+    want = ref(ks)
+    try:
+        for mode in (1, 4, 0):
+            ctx.set_packing(mode)
+            close(gpu(binding, ctx, ks, "blocked_f32"), want, f"kind {kind} K={K} packing {mode}")
+        ctx.set_packing(1)
+        short = synth.KindSet(kind, ks.delta, ks.Gamma, ks.e0, ks.e1, ks.obs[:T - 5000].copy())
+        close(gpu(binding, ctx, short, "blocked_f32"), ref(short), f"kind {kind} K={K} T={T - 5000}")
+        obs = ks.obs.copy()
+        if kind == 1:
+            obs[T // 2 + 3] = -1
+        else:
+            obs[T // 2 + 3] = np.inf
+        assert math.isnan(gpu(binding, ctx, ks, "blocked_f32", obs=obs))
+    finally:
+        ctx.set_packing(1)
+
+
+@pytest.mark.parametrize("kind", [1, 2])
 @pytest.mark.parametrize("algo", ["serial_f32", "blocked_f32"])
 def test_kind_edge_cases(binding, ctx, kind, algo):
     ks = synth.make_kind(kind, 4, 300, seed=400 + kind)
